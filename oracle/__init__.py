@@ -1,0 +1,208 @@
+"""ctypes front end of the FP64 brute-force oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import this
+package.  The product library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+AUTO, DOUBLE_LAYER, DIRECT, SINGLE_LAYER = 0, 1, 2, 3
+PROG_CONST, PROG_LINEAR, PROG_QUAD, PROG_INVDIST = 0, 1, 2, 3
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_verts", C.c_int64), ("n_prims", C.c_int64),
+                ("verts", C.c_void_p), ("prims", C.c_void_p), ("kind", C.c_void_p),
+                ("alpha", C.c_void_p)]
+
+
+class _BC(C.Structure):
+    _fields_ = [("domain", C.c_int), ("formulation", C.c_int), ("program", C.c_int),
+                ("params", C.c_double * 8), ("self_threshold", C.c_uint32), ("self_p", C.c_double)]
+
+
+class _TraceOut(C.Structure):
+    _fields_ = [("value", C.c_void_p), ("abs_sum", C.c_void_p), ("graze", C.c_void_p),
+                ("vtx_prim", C.c_void_p), ("vtx_m", C.c_void_p), ("vtx_pos", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            _build.build()
+        _lib = C.CDLL(LIB_PATH)
+        _lib.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        vp = C.c_void_p
+        _lib.orc_trace.restype = C.c_int
+        _lib.orc_trace.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32,
+                                   C.c_int64, vp, vp, vp, C.c_int]
+        _lib.orc_solve.restype = C.c_int
+        _lib.orc_solve.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int, C.c_int, C.c_uint64,
+                                   C.c_uint32, vp, vp, C.c_int]
+        _lib.orc_intersect_all.restype = C.c_int
+        _lib.orc_intersect_all.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int, vp, vp, vp, vp,
+                                           vp, C.c_int]
+        _lib.orc_self_panel.restype = C.c_double
+        _lib.orc_self_panel.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_double,
+                                        C.c_double, C.c_void_p]
+        _lib.orc_boundary_datum.restype = C.c_double
+        _lib.orc_boundary_datum.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        _lib.orc_program_value.restype = C.c_double
+        _lib.orc_program_value.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.orc_resolve_formulation.restype = C.c_int
+        _lib.orc_resolve_formulation.argtypes = [C.c_void_p, C.c_int]
+        _lib.orc_lines_per_path.restype = C.c_int
+        _lib.orc_lines_per_path.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
+        _lib.orc_prim_normal.argtypes = [C.c_void_p, C.c_int64, C.c_void_p]
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class OracleMesh:
+    """Holds contiguous float64 / int32 copies of a mesh and the C view of them."""
+
+    def __init__(self, mesh):
+        self.dim = int(mesh.dim)
+        self.verts = np.ascontiguousarray(mesh.verts, dtype=np.float64)
+        self.prims = np.ascontiguousarray(mesh.prims, dtype=np.int32)
+        self.kind = None if mesh.kind is None else np.ascontiguousarray(mesh.kind, dtype=np.uint8)
+        self.alpha = None if mesh.alpha is None else np.ascontiguousarray(mesh.alpha, dtype=np.float64)
+        self.c = _Mesh(self.dim, self.verts.shape[0], self.prims.shape[0], _ptr(self.verts),
+                       _ptr(self.prims), _ptr(self.kind), _ptr(self.alpha))
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+    def normals(self) -> np.ndarray:
+        out = np.zeros((self.prims.shape[0], 3))
+        for j in range(self.prims.shape[0]):
+            lib().orc_prim_normal(self.ref, j, out[j].ctypes.data)
+        return out[:, : self.dim]
+
+
+def self_threshold(p: float) -> int:
+    return int(np.floor(p * 2.0 ** 24))
+
+
+def make_bc(domain: int = 1, formulation: int = AUTO, program: int = PROG_CONST,
+            params=(), self_p: float = 1.0 / 16.0) -> _BC:
+    b = _BC()
+    b.domain = int(domain)
+    b.formulation = int(formulation)
+    b.program = int(program)
+    for i, v in enumerate(params):
+        b.params[i] = float(v)
+    b.self_threshold = self_threshold(self_p)
+    b.self_p = b.self_threshold / 2.0 ** 24
+    return b
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    o = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data, k.ctypes.data, o.ctypes.data)
+    return o
+
+
+def resolve_formulation(mesh: OracleMesh, formulation: int) -> int:
+    return lib().orc_resolve_formulation(mesh.ref, int(formulation))
+
+
+def lines_per_path(mesh: OracleMesh, bc: _BC, walk_len: int) -> int:
+    return lib().orc_lines_per_path(mesh.ref, C.byref(bc), int(walk_len))
+
+
+def trace(mesh: OracleMesh, points: np.ndarray, point_prim: Optional[np.ndarray], bc: _BC,
+          walk_len: int, seed: int, item_point: np.ndarray, item_path: np.ndarray,
+          problem: int = 0, n_threads: int = 0, want_pos: bool = True) -> dict:
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    pp = None if point_prim is None else np.ascontiguousarray(point_prim, dtype=np.int32)
+    ip = np.ascontiguousarray(item_point, dtype=np.int64)
+    ik = np.ascontiguousarray(item_path, dtype=np.int64)
+    n = ip.shape[0]
+    L = lines_per_path(mesh, bc, walk_len)
+    out = {"value": np.zeros(n), "abs_sum": np.zeros(n), "graze": np.zeros(n),
+           "vtx_prim": np.zeros((n, L), dtype=np.int32), "vtx_m": np.zeros((n, L), dtype=np.int32)}
+    if want_pos:
+        out["vtx_pos"] = np.zeros((n, L, mesh.dim))
+    t = _TraceOut(_ptr(out["value"]), _ptr(out["abs_sum"]), _ptr(out["graze"]),
+                  _ptr(out["vtx_prim"]), _ptr(out["vtx_m"]), _ptr(out.get("vtx_pos")))
+    rc = lib().orc_trace(mesh.ref, _ptr(pts), _ptr(pp), C.c_int64(pts.shape[0]), C.byref(bc),
+                         C.c_int(walk_len), C.c_uint64(seed), C.c_uint32(problem), C.c_int64(n),
+                         _ptr(ip), _ptr(ik), C.byref(t), C.c_int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_trace rejected its arguments")
+    return out
+
+
+def solve(mesh: OracleMesh, points: np.ndarray, point_prim: Optional[np.ndarray], bc: _BC,
+          samples: int, walk_len: int, seed: int, problem: int = 0, n_threads: int = 0):
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    pp = None if point_prim is None else np.ascontiguousarray(point_prim, dtype=np.int32)
+    P = pts.shape[0]
+    mean = np.zeros(P)
+    var = np.zeros(P)
+    rc = lib().orc_solve(mesh.ref, _ptr(pts), _ptr(pp), C.c_int64(P), C.byref(bc),
+                         C.c_int(samples), C.c_int(walk_len), C.c_uint64(seed),
+                         C.c_uint32(problem), _ptr(mean), _ptr(var), C.c_int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_solve rejected its arguments")
+    return mean, var
+
+
+def intersect_all(mesh: OracleMesh, orig: np.ndarray, dirs: np.ndarray,
+                  exclude: Optional[np.ndarray] = None, max_hits: int = 64, n_threads: int = 0):
+    o = np.ascontiguousarray(orig, dtype=np.float64)
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    ex = None if exclude is None else np.ascontiguousarray(exclude, dtype=np.int32)
+    n = o.shape[0]
+    nh = np.zeros(n, dtype=np.int32)
+    hp = np.full((n, max_hits), -1, dtype=np.int32)
+    ht = np.zeros((n, max_hits))
+    hm = np.zeros((n, max_hits))
+    lg = np.zeros(n)
+    rc = lib().orc_intersect_all(mesh.ref, _ptr(o), _ptr(d), _ptr(ex), C.c_int64(n),
+                                 C.c_int(max_hits), _ptr(nh), _ptr(hp), _ptr(ht), _ptr(hm),
+                                 _ptr(lg), C.c_int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_intersect_all rejected its arguments")
+    return {"n_hits": nh, "prim": hp, "t": ht, "margin": hm, "graze": lg}
+
+
+def self_panel(mesh: OracleMesh, prim: int, x: np.ndarray, u0: float, u1: float):
+    xx = np.zeros(3)
+    xx[: mesh.dim] = x
+    y = np.zeros(3)
+    gp = lib().orc_self_panel(mesh.ref, int(prim), xx.ctypes.data, float(u0), float(u1), y.ctypes.data)
+    return gp, y[: mesh.dim]
+
+
+def boundary_datum(mesh: OracleMesh, bc: _BC, prim: int, y: np.ndarray) -> float:
+    yy = np.zeros(3)
+    yy[: mesh.dim] = y
+    return lib().orc_boundary_datum(mesh.ref, C.byref(bc), int(prim), yy.ctypes.data)
+
+
+def program_value(mesh: OracleMesh, bc: _BC, y: np.ndarray) -> float:
+    yy = np.zeros(3)
+    yy[: mesh.dim] = y
+    return lib().orc_program_value(mesh.ref, C.byref(bc), yy.ctypes.data)

@@ -1,0 +1,681 @@
+/*
+ * oracle.c - FP64 brute-force walk-on-boundary reference estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain, slow and literal on
+ * purpose: every line query tests every primitive, every weight is formed as
+ * "kernel / pdf" from the fundamental solution of Appendix A and the
+ * line-sampling density of Sec. 4.4.1, and all arithmetic is double precision.
+ *
+ * Random-number streams (Philox4x32-10, key = (seed low 32 bits, seed high 32
+ * bits)); counter words for path k of point p, problem q, line i:
+ *     ctr = (k, p, (q << 24) | (i << 8) | block, w)
+ *   block 0, w = 0     : word0, word1 -> line direction, word2 -> mixture branch
+ *   block 1, w = 0     : word0, word1 -> in-plane self-panel sample
+ *   block 2, w = prim  : word0 -> selection key of primitive `prim` on line i
+ * Uniform variates: u = ((word >> 9) + 0.5) / 2^23, exact in binary32 and
+ * binary64.  A branch with probability p is taken when (word >> 8) < floor(p 2^24).
+ *
+ * Hit selection (Sec. 4.4.1 picks one of the m hits uniformly at random):
+ * the hit with the smallest (key, primitive id) is taken.  With independent
+ * keys this is a uniform choice among the m hits and does not depend on the
+ * order in which hits are found.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies, with a   */
+/* Weyl key schedule between rounds.                                          */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void draw(uint64_t seed, uint32_t path, uint32_t point, uint32_t problem,
+                 uint32_t line, uint32_t block, uint32_t w, uint32_t out[4]) {
+  uint32_t ctr[4] = {path, point, (problem << 24) | (line << 8) | block, w};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+static double uniform(uint32_t word) {
+  return ((double)(word >> 9) + 0.5) / 8388608.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Small vector helpers (dimension 2 or 3; unused components are zero).       */
+/* ------------------------------------------------------------------------- */
+static double dot(const double* a, const double* b, int dim) {
+  double s = 0.0;
+  for (int k = 0; k < dim; ++k) s += a[k] * b[k];
+  return s;
+}
+static void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double cross2(const double* a, const double* b) { return a[0] * b[1] - a[1] * b[0]; }
+
+static void prim_vertex(const orc_mesh* m, int64_t prim, int corner, double* v) {
+  int64_t vi = m->prims[prim * m->dim + corner];
+  v[2] = 0.0;
+  for (int a = 0; a < m->dim; ++a) v[a] = m->verts[vi * m->dim + a];
+}
+
+void orc_prim_normal(const orc_mesh* m, int64_t prim, double* n) {
+  double v0[3] = {0.0, 0.0, 0.0}, v1[3] = {0.0, 0.0, 0.0}, v2[3] = {0.0, 0.0, 0.0};
+  n[0] = n[1] = n[2] = 0.0;
+  prim_vertex(m, prim, 0, v0);
+  prim_vertex(m, prim, 1, v1);
+  if (m->dim == 3) {
+    prim_vertex(m, prim, 2, v2);
+    double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+    double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+    cross3(e1, e2, n);
+    double l = sqrt(dot(n, n, 3));
+    for (int a = 0; a < 3; ++a) n[a] /= l;
+  } else {
+    /* counter-clockwise boundary: the outward normal is the tangent turned by -90 deg */
+    double e[2] = {v1[0] - v0[0], v1[1] - v0[1]};
+    double l = sqrt(e[0] * e[0] + e[1] * e[1]);
+    n[0] = e[1] / l;
+    n[1] = -e[0] / l;
+  }
+}
+
+static int prim_kind(const orc_mesh* m, int64_t prim) {
+  return m->kind ? (int)m->kind[prim] : ORC_DIRICHLET;
+}
+static double prim_alpha(const orc_mesh* m, int64_t prim) {
+  return m->alpha ? m->alpha[prim] : 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fundamental solution and its derivatives, Appendix A (r = y - x).          */
+/* ------------------------------------------------------------------------- */
+static double G(const double* x, const double* y, int dim) {
+  double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+  double rn = sqrt(dot(r, r, dim));
+  return dim == 3 ? 1.0 / (4.0 * ORC_PI * rn) : -log(rn) / (2.0 * ORC_PI);
+}
+static double dG_dny(const double* x, const double* y, const double* ny, int dim) {
+  double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+  double rn = sqrt(dot(r, r, dim));
+  double rdn = dot(r, ny, dim);
+  return dim == 3 ? -rdn / (4.0 * ORC_PI * rn * rn * rn) : -rdn / (2.0 * ORC_PI * rn * rn);
+}
+static double dG_dnx(const double* x, const double* y, const double* nx, int dim) {
+  double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+  double rn = sqrt(dot(r, r, dim));
+  double rdn = dot(r, nx, dim);
+  return dim == 3 ? rdn / (4.0 * ORC_PI * rn * rn * rn) : rdn / (2.0 * ORC_PI * rn * rn);
+}
+
+/* Area density of the point y reached by a uniformly random line through x
+ * that is one of m hits picked uniformly: the line direction is uniform on the
+ * sphere (circle) and covers +d and -d, so the density per unit solid angle is
+ * 2/(4 pi) (per radian 2/(2 pi)); converting solid angle to area gives
+ * |cos theta_y| / r^2 (2D: / r).  Sec. 4.4.1: picking one of m multiplies by 1/m. */
+static double line_pdf(const double* x, const double* y, const double* ny, int m, int dim) {
+  double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+  double rn = sqrt(dot(r, r, dim));
+  double c = fabs(dot(r, ny, dim)) / rn;
+  if (dim == 3) return (2.0 / (4.0 * ORC_PI)) * c / (rn * rn) / (double)m;
+  return (2.0 / (2.0 * ORC_PI)) * c / rn / (double)m;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Harmonic programs u(x) and the boundary datum derived from them.           */
+/* ------------------------------------------------------------------------- */
+static void program_eval(const orc_mesh* m, const orc_bc* bc, const double* y, double* u,
+                         double* grad) {
+  const double* p = bc->params;
+  int dim = m->dim;
+  grad[0] = grad[1] = grad[2] = 0.0;
+  switch (bc->program) {
+    case ORC_PROG_CONST:
+      *u = p[0];
+      break;
+    case ORC_PROG_LINEAR:
+      *u = p[0] * y[0] + p[1] * y[1] + (dim == 3 ? p[2] * y[2] : 0.0) + p[3];
+      grad[0] = p[0];
+      grad[1] = p[1];
+      grad[2] = dim == 3 ? p[2] : 0.0;
+      break;
+    case ORC_PROG_QUAD:
+      *u = y[0] * y[0] - y[1] * y[1];
+      grad[0] = 2.0 * y[0];
+      grad[1] = -2.0 * y[1];
+      break;
+    case ORC_PROG_INVDIST: {
+      double r[3] = {y[0] - p[0], y[1] - p[1], dim == 3 ? y[2] - p[2] : 0.0};
+      double rr = dot(r, r, dim);
+      if (dim == 3) {
+        double rn = sqrt(rr);
+        *u = 1.0 / rn;
+        for (int a = 0; a < 3; ++a) grad[a] = -r[a] / (rr * rn);
+      } else {
+        *u = 0.5 * log(rr);
+        for (int a = 0; a < 2; ++a) grad[a] = r[a] / rr;
+      }
+      break;
+    }
+    default:
+      *u = NAN;
+  }
+}
+
+double orc_program_value(const orc_mesh* m, const orc_bc* bc, const double* y) {
+  double u, g[3];
+  program_eval(m, bc, y, &u, g);
+  return u;
+}
+
+/* eq. PoissonBC: Dirichlet value u, Neumann flux du/dn, Robin du/dn + alpha u. */
+double orc_boundary_datum(const orc_mesh* m, const orc_bc* bc, int64_t prim, const double* y) {
+  double u, g[3], n[3];
+  program_eval(m, bc, y, &u, g);
+  int kind = prim_kind(m, prim);
+  if (kind == ORC_DIRICHLET) return u;
+  orc_prim_normal(m, prim, n);
+  double q = dot(n, g, m->dim);
+  if (kind == ORC_NEUMANN) return q;
+  return q + prim_alpha(m, prim) * u;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Line / primitive intersection (line x + t d, t real).                      */
+/* Returns 1 on a hit.  *margin is the signed smallest barycentric coordinate  */
+/* (negative outside), *cosv = |d . n| of the primitive.                       */
+/* ------------------------------------------------------------------------- */
+static int line_prim(const orc_mesh* m, int64_t j, const double* x, const double* d,
+                     double* t, double* y, double* margin, double* cosv) {
+  double v0[3] = {0.0, 0.0, 0.0}, v1[3] = {0.0, 0.0, 0.0}, v2[3] = {0.0, 0.0, 0.0};
+  prim_vertex(m, j, 0, v0);
+  prim_vertex(m, j, 1, v1);
+  if (m->dim == 3) {
+    /* Moeller-Trumbore in double precision, inclusive edges */
+    prim_vertex(m, j, 2, v2);
+    double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+    double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+    double pv[3], qv[3], nn[3];
+    cross3(d, e2, pv);
+    double det = dot(e1, pv, 3);
+    cross3(e1, e2, nn);
+    double nl = sqrt(dot(nn, nn, 3));
+    *cosv = fabs(dot(d, nn, 3)) / nl;
+    if (det == 0.0) {
+      *margin = 0.0;
+      return 0;
+    }
+    double s[3] = {x[0] - v0[0], x[1] - v0[1], x[2] - v0[2]};
+    double u = dot(s, pv, 3) / det;
+    cross3(s, e1, qv);
+    double v = dot(d, qv, 3) / det;
+    *t = dot(e2, qv, 3) / det;
+    double w = 1.0 - u - v;
+    double mg = u < v ? u : v;
+    mg = mg < w ? mg : w;
+    *margin = mg;
+    for (int a = 0; a < 3; ++a) y[a] = v0[a] + u * e1[a] + v * e2[a];
+    return mg >= 0.0;
+  } else {
+    double e[2] = {v1[0] - v0[0], v1[1] - v0[1]};
+    double det = cross2(d, e);
+    double el = sqrt(e[0] * e[0] + e[1] * e[1]);
+    *cosv = fabs(cross2(d, e)) / el; /* |d . n| with n the unit normal of e */
+    if (det == 0.0) {
+      *margin = 0.0;
+      return 0;
+    }
+    double xa[2] = {x[0] - v0[0], x[1] - v0[1]};
+    double ax[2] = {v0[0] - x[0], v0[1] - x[1]};
+    double s = cross2(xa, d) / cross2(e, d);
+    *t = cross2(ax, e) / det;
+    double mg = s < 1.0 - s ? s : 1.0 - s;
+    *margin = mg;
+    y[0] = v0[0] + s * e[0];
+    y[1] = v0[1] + s * e[1];
+    y[2] = 0.0;
+    return mg >= 0.0;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* In-plane sample on the primitive that contains x ("self panel").  A line   */
+/* through x never meets the primitive it starts on (its plane contains the  */
+/* line only with probability zero), yet G does not vanish there; this term  */
+/* covers that part of every single-layer integral.                           */
+/*  3D: theta uniform in [0, 2 pi), radius uniform in [0, R(theta)], where     */
+/*      R(theta) is the distance from x to the triangle's boundary; the area   */
+/*      density is 1 / (2 pi R(theta) rho).                                    */
+/*  2D: y uniform along the segment; density 1 / length.                       */
+/* Returns G(x, y) / p(y).                                                     */
+/* ------------------------------------------------------------------------- */
+double orc_self_panel(const orc_mesh* m, int64_t prim, const double* x, double u0, double u1,
+                      double* y) {
+  double v[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  for (int c = 0; c < m->dim; ++c) prim_vertex(m, prim, c, v[c]);
+  if (m->dim == 3) {
+    double n[3], t1[3], t2[3];
+    orc_prim_normal(m, prim, n);
+    double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+    double l1 = sqrt(dot(e1, e1, 3));
+    for (int a = 0; a < 3; ++a) t1[a] = e1[a] / l1;
+    cross3(n, t1, t2);
+    double loc[3][2];
+    for (int c = 0; c < 3; ++c) {
+      double r[3] = {v[c][0] - x[0], v[c][1] - x[1], v[c][2] - x[2]};
+      loc[c][0] = dot(r, t1, 3);
+      loc[c][1] = dot(r, t2, 3);
+    }
+    double theta = 2.0 * ORC_PI * u0;
+    double dir[2] = {cos(theta), sin(theta)};
+    double R = INFINITY;
+    for (int c = 0; c < 3; ++c) {
+      const double* a = loc[c];
+      const double* b = loc[(c + 1) % 3];
+      double e[2] = {b[0] - a[0], b[1] - a[1]};
+      double den = cross2(dir, e);
+      if (den != 0.0) {
+        double s = cross2(a, e) / den;
+        if (s > 0.0 && s < R) R = s;
+      }
+    }
+    if (!(R < INFINITY)) R = 0.0;
+    double rho = u1 * R;
+    for (int a = 0; a < 3; ++a) y[a] = x[a] + rho * (dir[0] * t1[a] + dir[1] * t2[a]);
+    if (rho <= 0.0) return 0.0;
+    double pdf = 1.0 / (2.0 * ORC_PI * R * rho);
+    return G(x, y, 3) / pdf;
+  } else {
+    double e[2] = {v[1][0] - v[0][0], v[1][1] - v[0][1]};
+    double len = sqrt(e[0] * e[0] + e[1] * e[1]);
+    y[0] = v[0][0] + u0 * e[0];
+    y[1] = v[0][1] + u0 * e[1];
+    y[2] = 0.0;
+    double pdf = 1.0 / len;
+    return G(x, y, 2) / pdf;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Formulation mapping, Table 1: Dirichlet -> double layer, Neumann -> direct,*/
+/* Robin or Neumann/Robin mixtures -> single layer.  Mixtures containing      */
+/* Dirichlet parts (first-kind rows) are not handled here.                    */
+/* ------------------------------------------------------------------------- */
+int orc_resolve_formulation(const orc_mesh* m, int formulation) {
+  int nd = 0, nn = 0, nr = 0;
+  for (int64_t j = 0; j < m->n_prims; ++j) {
+    int k = prim_kind(m, j);
+    nd += k == ORC_DIRICHLET;
+    nn += k == ORC_NEUMANN;
+    nr += k == ORC_ROBIN;
+  }
+  if (formulation == ORC_AUTO) {
+    if (nn == 0 && nr == 0) return ORC_DOUBLE_LAYER;
+    if (nd == 0 && nr == 0) return ORC_DIRECT;
+    if (nd == 0) return ORC_SINGLE_LAYER;
+    return -1;
+  }
+  if (formulation == ORC_DOUBLE_LAYER) return (nn == 0 && nr == 0) ? formulation : -1;
+  if (formulation == ORC_DIRECT) return (nd == 0 && nr == 0) ? formulation : -1;
+  if (formulation == ORC_SINGLE_LAYER) return nd == 0 ? formulation : -1;
+  return -1;
+}
+
+int orc_lines_per_path(const orc_mesh* m, const orc_bc* bc, int walk_len) {
+  int f = orc_resolve_formulation(m, bc->formulation);
+  return f == ORC_DIRECT ? walk_len + 1 : walk_len;
+}
+
+/* ------------------------------------------------------------------------- */
+/* All hits of one line, brute force.                                         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int m;                 /* number of hits */
+  int64_t sel;           /* selected primitive (smallest key, then id), -1 if none */
+  uint32_t sel_key;
+  double sel_y[3];
+  double src;            /* sum over hits of G(x,y) q(y) / p_all(y) (direct Neumann) */
+  double graze;          /* min over primitives of |margin| * cos */
+} line_hits;
+
+static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc, int want_src,
+                     int want_sel, const double* x, const double* d, int64_t exclude,
+                     uint64_t seed, uint32_t path, uint32_t point, uint32_t problem,
+                     uint32_t line, line_hits* h) {
+  h->m = 0;
+  h->sel = -1;
+  h->sel_key = 0xffffffffu;
+  h->src = 0.0;
+  h->graze = INFINITY;
+  for (int64_t j = 0; j < m->n_prims; ++j) {
+    if (j == exclude) continue;
+    double t, y[3], margin, cosv;
+    int hit = line_prim(m, j, x, d, &t, y, &margin, &cosv);
+    double g = fabs(margin) * cosv;
+    if (g < h->graze) h->graze = g;
+    if (!hit) continue;
+    h->m += 1;
+    if (want_sel) {
+      uint32_t r[4];
+      draw(seed, path, point, problem, line, 2u, (uint32_t)j, r);
+      if (h->sel < 0 || r[0] < h->sel_key || (r[0] == h->sel_key && j < h->sel)) {
+        h->sel = j;
+        h->sel_key = r[0];
+        memcpy(h->sel_y, y, sizeof(h->sel_y));
+      }
+    }
+    if (want_src) {
+      /* all-hits estimate of the integral of G q along this line: each hit is
+         weighted by 1 / p_all with p_all the density without the 1/m factor */
+      const double* ny = normals + 3 * j;
+      double q = orc_boundary_datum(m, bc, j, y);
+      h->src += G(x, y, m->dim) * q / line_pdf(x, y, ny, 1, m->dim);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* One path (point p, path k).                                                */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double value, abs_sum, graze;
+} path_result;
+
+static path_result one_path(const orc_mesh* m, const double* normals, const orc_bc* bc,
+                            int form, const double* x0, int64_t prim0, int M, uint64_t seed,
+                            uint32_t problem, uint32_t point, uint32_t path, int32_t* vprim,
+                            int32_t* vm, double* vpos) {
+  const int dim = m->dim;
+  const double phi = (double)bc->domain;
+  const int L = form == ORC_DIRECT ? M + 1 : M;
+  path_result res = {0.0, 0.0, INFINITY};
+  for (int i = 0; i < L; ++i) {
+    if (vprim) vprim[i] = -1;
+    if (vm) vm[i] = 0;
+    if (vpos)
+      for (int a = 0; a < dim; ++a) vpos[i * dim + a] = NAN;
+  }
+
+  /* Table 1, Dirichlet: on the boundary the solution is the given value. */
+  if (form == ORC_DOUBLE_LAYER && prim0 >= 0) {
+    res.value = orc_boundary_datum(m, bc, prim0, x0);
+    res.abs_sum = fabs(res.value);
+    return res;
+  }
+
+  double x[3] = {x0[0], x0[1], dim == 3 ? x0[2] : 0.0};
+  int64_t cur = prim0;
+  double W = 1.0, acc = 0.0, abs_sum = 0.0;
+
+  for (int i = 0; i < L; ++i) {
+    const int on_gamma = cur >= 0;
+    uint32_t r0[4];
+    draw(seed, path, point, problem, (uint32_t)i, 0u, 0u, r0);
+    double d[3] = {0.0, 0.0, 0.0};
+    if (dim == 3) {
+      double z = 1.0 - 2.0 * uniform(r0[0]);
+      double s = sqrt(fmax(0.0, 1.0 - z * z));
+      double ph = 2.0 * ORC_PI * uniform(r0[1]);
+      d[0] = s * cos(ph);
+      d[1] = s * sin(ph);
+      d[2] = z;
+    } else {
+      double th = 2.0 * ORC_PI * uniform(r0[0]);
+      d[0] = cos(th);
+      d[1] = sin(th);
+    }
+
+    /* single layer: where G acts on the own primitive (the first step from a
+       boundary point, and the alpha G part at Robin vertices) mix the line
+       sample with an in-plane self-panel sample */
+    int mixture = form == ORC_SINGLE_LAYER && on_gamma &&
+                  (i == 0 || prim_kind(m, cur) == ORC_ROBIN);
+    int use_self = mixture && (r0[2] >> 8) < bc->self_threshold;
+
+    double y[3] = {0.0, 0.0, 0.0};
+    int64_t next = -1;
+    double w;
+    if (use_self) {
+      uint32_t r1[4];
+      draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
+      double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), y);
+      if (i == 0)
+        w = gp / bc->self_p; /* u = int G mu */
+      else
+        w = -2.0 * phi * prim_alpha(m, cur) * gp / bc->self_p; /* -2 phi alpha G */
+      next = cur;
+      if (vprim) vprim[i] = (int32_t)(-2 - cur);
+      if (vm) vm[i] = 0;
+    } else {
+      line_hits h;
+      const int src_line = form == ORC_DIRECT;
+      const int last = i == L - 1;
+      all_hits(m, normals, bc, src_line, !(src_line && last), x, d, cur, seed, path, point,
+               problem, (uint32_t)i, &h);
+      if (h.graze < res.graze) res.graze = h.graze;
+      if (vm) vm[i] = h.m;
+      if (vprim) vprim[i] = (int32_t)h.sel;
+      if (form == ORC_DIRECT) {
+        /* source integral of the direct BIE: phi int G q off the boundary,
+           2 phi int G q on it (Table 1, Neumann rows) */
+        double S;
+        if (on_gamma) {
+          uint32_t r1[4];
+          double ys[3];
+          draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
+          double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), ys);
+          double own = gp * orc_boundary_datum(m, bc, cur, ys);
+          S = 2.0 * phi * (h.src + own);
+        } else {
+          S = phi * h.src;
+        }
+        double term = W * S * (last ? 0.5 : 1.0);
+        acc += term;
+        abs_sum += fabs(term);
+        if (last) break;
+      }
+      if (h.m == 0) break;
+      memcpy(y, h.sel_y, sizeof(y));
+      next = h.sel;
+      const double* ny = normals + 3 * next;
+      double p = line_pdf(x, y, ny, h.m, dim);
+      double kern;
+      if (form == ORC_DOUBLE_LAYER) {
+        kern = (i == 0 && !on_gamma) ? -dG_dny(x, y, ny, dim)          /* u = -int dG/dny nu */
+                                     : 2.0 * phi * dG_dny(x, y, ny, dim); /* nu = 2 phi int dG/dny nu + ... */
+      } else if (form == ORC_DIRECT) {
+        kern = on_gamma ? -2.0 * phi * dG_dny(x, y, ny, dim) /* boundary row */
+                        : -phi * dG_dny(x, y, ny, dim);      /* interior / exterior row */
+      } else {
+        if (i == 0) {
+          kern = G(x, y, dim); /* u = int G mu */
+        } else {
+          const double* nx = normals + 3 * cur;
+          kern = -2.0 * phi * (dG_dnx(x, y, nx, dim) + prim_alpha(m, cur) * G(x, y, dim));
+        }
+      }
+      w = kern / p;
+      if (mixture) w /= (1.0 - bc->self_p);
+    }
+
+    W *= w;
+    memcpy(x, y, sizeof(x));
+    cur = next;
+    if (vpos)
+      for (int a = 0; a < dim; ++a) vpos[i * dim + a] = x[a];
+
+    if (form != ORC_DIRECT) {
+      /* emission 2 phi s at x_{i+1}; the last vertex gets half of it
+         (Sec. 4.1.2, modified Neumann series) */
+      double s = orc_boundary_datum(m, bc, cur, x);
+      double e = (i + 1 < M ? 2.0 : 1.0) * phi * s;
+      double term = W * e;
+      acc += term;
+      abs_sum += fabs(term);
+    }
+  }
+  res.value = acc;
+  res.abs_sum = abs_sum;
+  return res;
+}
+
+static double* make_normals(const orc_mesh* m) {
+  double* n = (double*)malloc(sizeof(double) * 3 * (size_t)(m->n_prims > 0 ? m->n_prims : 1));
+  for (int64_t j = 0; j < m->n_prims; ++j) orc_prim_normal(m, j, n + 3 * j);
+  return n;
+}
+
+static int check_args(const orc_mesh* m, const orc_bc* bc, int walk_len) {
+  if (!m || !bc) return 1;
+  if (m->dim != 2 && m->dim != 3) return 1;
+  if (m->n_prims <= 0 || !m->verts || !m->prims) return 1;
+  if (walk_len < 1) return 1;
+  if (bc->domain != 1 && bc->domain != -1) return 1;
+  if (orc_resolve_formulation(m, bc->formulation) < 0) return 1;
+  return 0;
+}
+
+int orc_trace(const orc_mesh* m, const double* points, const int32_t* point_prim,
+              int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed, uint32_t problem,
+              int64_t n_items, const int64_t* item_point, const int64_t* item_path,
+              orc_trace_out* out, int n_threads) {
+  if (check_args(m, bc, walk_len)) return 1;
+  const int form = orc_resolve_formulation(m, bc->formulation);
+  const int L = form == ORC_DIRECT ? walk_len + 1 : walk_len;
+  double* normals = make_normals(m);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+  for (int64_t it = 0; it < n_items; ++it) {
+    int64_t p = item_point[it];
+    if (p < 0 || p >= n_points) continue;
+    double x0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
+    int64_t prim0 = point_prim ? point_prim[p] : -1;
+    path_result r = one_path(m, normals, bc, form, x0, prim0, walk_len, seed, problem,
+                             (uint32_t)p, (uint32_t)item_path[it],
+                             out->vtx_prim ? out->vtx_prim + it * L : NULL,
+                             out->vtx_m ? out->vtx_m + it * L : NULL,
+                             out->vtx_pos ? out->vtx_pos + it * L * m->dim : NULL);
+    if (out->value) out->value[it] = r.value;
+    if (out->abs_sum) out->abs_sum[it] = r.abs_sum;
+    if (out->graze) out->graze[it] = r.graze;
+  }
+  free(normals);
+  return 0;
+}
+
+int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim,
+              int64_t n_points, const orc_bc* bc, int samples, int walk_len, uint64_t seed,
+              uint32_t problem, double* mean_out, double* var_out, int n_threads) {
+  if (check_args(m, bc, walk_len) || samples < 1) return 1;
+  const int form = orc_resolve_formulation(m, bc->formulation);
+  double* normals = make_normals(m);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t p = 0; p < n_points; ++p) {
+    double x0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
+    int64_t prim0 = point_prim ? point_prim[p] : -1;
+    double* v = (double*)malloc(sizeof(double) * (size_t)samples);
+    double sum = 0.0;
+    for (int k = 0; k < samples; ++k) {
+      v[k] = one_path(m, normals, bc, form, x0, prim0, walk_len, seed, problem, (uint32_t)p,
+                      (uint32_t)k, NULL, NULL, NULL)
+                 .value;
+      sum += v[k];
+    }
+    double mean = sum / samples;
+    double ss = 0.0;
+    for (int k = 0; k < samples; ++k) ss += (v[k] - mean) * (v[k] - mean);
+    mean_out[p] = mean;
+    if (var_out) var_out[p] = samples > 1 ? ss / (samples - 1) : 0.0;
+    free(v);
+  }
+  free(normals);
+  return 0;
+}
+
+int orc_intersect_all(const orc_mesh* m, const double* orig, const double* dir,
+                      const int32_t* exclude, int64_t n_lines, int max_hits, int32_t* n_hits,
+                      int32_t* hit_prim, double* hit_t, double* hit_margin, double* line_graze,
+                      int n_threads) {
+  if (!m || (m->dim != 2 && m->dim != 3) || max_hits < 0) return 1;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t l = 0; l < n_lines; ++l) {
+    double x[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < m->dim; ++a) {
+      x[a] = orig[l * m->dim + a];
+      d[a] = dir[l * m->dim + a];
+    }
+    int64_t ex = exclude ? exclude[l] : -1;
+    int cnt = 0;
+    double graze = INFINITY;
+    for (int64_t j = 0; j < m->n_prims; ++j) {
+      if (j == ex) continue;
+      double t, y[3], margin, cosv;
+      int hit = line_prim(m, j, x, d, &t, y, &margin, &cosv);
+      double g = fabs(margin) * cosv;
+      if (g < graze) graze = g;
+      if (!hit) continue;
+      if (cnt < max_hits) {
+        /* insertion in (t, prim) order */
+        int pos = cnt;
+        int32_t* hp = hit_prim + l * max_hits;
+        double* ht = hit_t + l * max_hits;
+        double* hm = hit_margin ? hit_margin + l * max_hits : NULL;
+        while (pos > 0 && (ht[pos - 1] > t || (ht[pos - 1] == t && hp[pos - 1] > j))) {
+          hp[pos] = hp[pos - 1];
+          ht[pos] = ht[pos - 1];
+          if (hm) hm[pos] = hm[pos - 1];
+          --pos;
+        }
+        hp[pos] = (int32_t)j;
+        ht[pos] = t;
+        if (hm) hm[pos] = fabs(margin) * cosv;
+      }
+      ++cnt;
+    }
+    n_hits[l] = cnt;
+    if (line_graze) line_graze[l] = graze;
+  }
+  return 0;
+}

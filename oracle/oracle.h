@@ -1,0 +1,119 @@
+/*
+ * oracle.h - FP64 brute-force walk-on-boundary (WoB) reference estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the independent checker for the HIP
+ * library: it shares no source with it and is never called by the product
+ * path.  Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load it.
+ *
+ * What it computes (Sugimoto et al., "A Practical Walk-on-Boundary Method for
+ * Boundary Value Problems"):
+ *   - Dirichlet problems, double-layer indirect BIE (Sec. 4.1, Table 1 rows
+ *     "Dirichlet"), recursive estimator of eq. indirect_double_boundary_reordered2
+ *     and eq. mc_dirichlet_interior_sol, truncated with the halved last term
+ *     (Sec. 4.1.2 "Path truncation").
+ *   - Neumann problems, direct BIE (Sec. 4.2, eq. cbie_neumann, eq.
+ *     mc_cbie_neumann, eq. mc_cbie_neumann2, Table 1 rows "Neumann").
+ *   - Neumann / Robin problems, single-layer indirect BIE (Sec. 4.3, Table 1
+ *     rows "Mixed or degenerate problem", Neumann and Robin boundary rows).
+ *   - Interior (phi = +1) and exterior (phi = -1) domains (Sec. 4.5.1).
+ *   - Line sampling with all hits, one hit picked uniformly, pdf times 1/m
+ *     (Sec. 4.4.1 "Ray sampling").
+ *   Kernels G, dG/dn_y, dG/dn_x are taken verbatim from Appendix A.
+ *
+ * Every intersection query loops over EVERY primitive (no acceleration
+ * structure).  All arithmetic is double precision.  Random numbers come from
+ * Philox4x32-10 (Salmon et al., SC'11), implemented here from its published
+ * definition; the stream layout is documented in oracle.c.
+ */
+#ifndef WOB_ORACLE_H
+#define WOB_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* primitive boundary-condition kinds (eq. PoissonBC) */
+enum { ORC_DIRICHLET = 0, ORC_NEUMANN = 1, ORC_ROBIN = 2 };
+/* formulations (Table 1) */
+enum { ORC_AUTO = 0, ORC_DOUBLE_LAYER = 1, ORC_DIRECT = 2, ORC_SINGLE_LAYER = 3 };
+/* analytic harmonic functions u from which boundary data are derived */
+enum { ORC_PROG_CONST = 0, ORC_PROG_LINEAR = 1, ORC_PROG_QUAD = 2, ORC_PROG_INVDIST = 3 };
+
+typedef struct {
+  int dim;                 /* 2 (segments) or 3 (triangles) */
+  int64_t n_verts;
+  int64_t n_prims;
+  const double* verts;     /* n_verts * dim */
+  const int32_t* prims;    /* n_prims * dim, oriented so the normal points out of Omega */
+  const uint8_t* kind;     /* n_prims, or NULL = all Dirichlet */
+  const double* alpha;     /* n_prims Robin coefficients, or NULL = 0 */
+} orc_mesh;
+
+typedef struct {
+  int domain;              /* +1 interior (phi = +1), -1 exterior (phi = -1) */
+  int formulation;         /* ORC_* formulation, ORC_AUTO = Table 1 mapping */
+  int program;             /* ORC_PROG_* */
+  double params[8];        /* program parameters */
+  uint32_t self_threshold; /* self-panel mixture probability as floor(p_s * 2^24) */
+  double self_p;           /* the same probability as a real number, floor(p_s*2^24)/2^24 */
+} orc_bc;
+
+/* Per (point, path) record produced by orc_trace. Arrays may be NULL. */
+typedef struct {
+  double* value;           /* [n_items] per-path estimate u_hat */
+  double* abs_sum;         /* [n_items] sum of |terms| (scale for relative tolerances) */
+  double* graze;           /* [n_items] min over lines of |barycentric margin|*|cos| */
+  int32_t* vtx_prim;       /* [n_items * L] selected primitive per line, -1 none, -2-p self-panel */
+  int32_t* vtx_m;          /* [n_items * L] number of hits per line */
+  double* vtx_pos;         /* [n_items * L * dim] vertex reached by each line */
+} orc_trace_out;
+
+/* Philox4x32-10 block: out = Philox(ctr, key). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Lines per path for a formulation: M (double / single layer) or M + 1 (direct). */
+int orc_lines_per_path(const orc_mesh* mesh, const orc_bc* bc, int walk_len);
+
+/* Resolve ORC_AUTO with Table 1's mapping; returns the formulation or -1. */
+int orc_resolve_formulation(const orc_mesh* mesh, int formulation);
+
+/* Per-path estimates for an explicit list of (point index, path index) items.
+ * points: [n_points * dim]; point_prim: [n_points] or NULL (-1 = off boundary).
+ * Returns 0 on success, nonzero on bad arguments. */
+int orc_trace(const orc_mesh* mesh, const double* points, const int32_t* point_prim,
+              int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed,
+              uint32_t problem, int64_t n_items, const int64_t* item_point,
+              const int64_t* item_path, orc_trace_out* out, int n_threads);
+
+/* Mean and unbiased variance over paths 0..N-1 for every point (two-pass). */
+int orc_solve(const orc_mesh* mesh, const double* points, const int32_t* point_prim,
+              int64_t n_points, const orc_bc* bc, int samples, int walk_len,
+              uint64_t seed, uint32_t problem, double* mean_out, double* var_out,
+              int n_threads);
+
+/* All hits of the lines orig + t*dir (t real), excluding primitive exclude[i].
+ * n_hits[i] is the full count; at most max_hits (prim, t, margin) are stored,
+ * in increasing (t, prim) order. margin = |barycentric margin| * |cos|. */
+int orc_intersect_all(const orc_mesh* mesh, const double* orig, const double* dir,
+                      const int32_t* exclude, int64_t n_lines, int max_hits,
+                      int32_t* n_hits, int32_t* hit_prim, double* hit_t,
+                      double* hit_margin, double* line_graze, int n_threads);
+
+/* Harmonic program value and boundary datum s(y) on primitive `prim`. */
+double orc_program_value(const orc_mesh* mesh, const orc_bc* bc, const double* y);
+double orc_boundary_datum(const orc_mesh* mesh, const orc_bc* bc, int64_t prim, const double* y);
+
+/* Self-panel estimate of the single-layer integral over the own primitive:
+ * returns G(x, y)/p(y) for the sample drawn from uniforms (u0, u1) and writes y. */
+double orc_self_panel(const orc_mesh* mesh, int64_t prim, const double* x, double u0,
+                      double u1, double* y_out);
+
+/* Unit outward normal of a primitive. */
+void orc_prim_normal(const orc_mesh* mesh, int64_t prim, double* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

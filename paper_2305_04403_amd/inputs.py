@@ -1,0 +1,313 @@
+"""Seeded synthetic inputs: boundary meshes, evaluation points, boundary-kind maps.
+
+This module only builds geometry and point sets.  It holds none of the
+walk-on-boundary arithmetic, so both the HIP path and the CPU oracle can be fed
+from it.  All randomness comes from ``numpy.random.default_rng(seed)``.
+
+Workloads (the paper's own shapes and 3D models are not available, so these
+synthetic ones stand in for them):
+
+* ``circle_polygon``      - regular n-gon on the unit circle (2D, segments).
+* ``icosphere``           - geodesic icosphere with 20 f^2 triangles, optionally
+                            radially perturbed r = 1 + a sin(k1 theta) sin(k2 phi).
+* ``torus_union``         - boundary of the union of three tori (R, r) with random
+                            rotations, meshed by marching tetrahedra.
+* point sets              - uniform disk / ball / shell / box samples, a z-slice
+                            grid, and area-uniform samples on a mesh.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Mesh:
+    """Boundary mesh. ``prims`` rows are oriented so that the normal points out of
+    the interior domain Omega (2D: counter-clockwise boundary; 3D: (v1-v0)x(v2-v0)
+    points outward)."""
+
+    dim: int
+    verts: np.ndarray            # (V, dim) float64 (values representable in float32 when built so)
+    prims: np.ndarray            # (T, dim) int32
+    kind: Optional[np.ndarray] = None   # (T,) uint8 boundary kind, None = all Dirichlet
+    alpha: Optional[np.ndarray] = None  # (T,) Robin coefficient, None = 0
+
+    @property
+    def n_prims(self) -> int:
+        return int(self.prims.shape[0])
+
+    @property
+    def n_verts(self) -> int:
+        return int(self.verts.shape[0])
+
+    def as_float32_geometry(self) -> "Mesh":
+        """Round vertices to float32 (both implementations then see identical geometry)."""
+        return dataclasses.replace(self, verts=self.verts.astype(np.float32).astype(np.float64))
+
+
+# ----------------------------------------------------------------------------- meshes
+
+def circle_polygon(n: int = 256, radius: float = 1.0) -> Mesh:
+    ang = 2.0 * np.pi * np.arange(n) / n
+    verts = np.stack([radius * np.cos(ang), radius * np.sin(ang)], axis=1)
+    prims = np.stack([np.arange(n), (np.arange(n) + 1) % n], axis=1).astype(np.int32)
+    return Mesh(2, verts, prims)
+
+
+_GOLD = (1.0 + math.sqrt(5.0)) / 2.0
+_ICO_V = np.array([[-1, _GOLD, 0], [1, _GOLD, 0], [-1, -_GOLD, 0], [1, -_GOLD, 0],
+                   [0, -1, _GOLD], [0, 1, _GOLD], [0, -1, -_GOLD], [0, 1, -_GOLD],
+                   [_GOLD, 0, -1], [_GOLD, 0, 1], [-_GOLD, 0, -1], [-_GOLD, 0, 1]], dtype=np.float64)
+_ICO_F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+          (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8),
+          (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+
+
+def icosphere(freq: int) -> Mesh:
+    """Geodesic sphere: each icosahedron face split into freq^2 triangles, vertices
+    projected to the unit sphere. Shared vertices are merged exactly through their
+    integer barycentric keys, so the mesh is watertight."""
+    base = _ICO_V / np.linalg.norm(_ICO_V, axis=1, keepdims=True)
+    faces = []
+    for a, b, c in _ICO_F:
+        n = np.cross(base[b] - base[a], base[c] - base[a])
+        faces.append((a, b, c) if np.dot(n, base[a]) > 0 else (a, c, b))
+    f = int(freq)
+    index: Dict[tuple, int] = {}
+    pos: List[np.ndarray] = []
+
+    def vid(wts: Tuple[Tuple[int, int], ...]) -> int:
+        key = tuple(sorted((v, w) for v, w in wts if w > 0))
+        got = index.get(key)
+        if got is None:
+            p = sum(w * base[v] for v, w in key) / f
+            pos.append(p / np.linalg.norm(p))
+            got = len(pos) - 1
+            index[key] = got
+        return got
+
+    tris = []
+    for a, b, c in faces:
+        grid = {}
+        for i in range(f + 1):
+            for j in range(f + 1 - i):
+                grid[(i, j)] = vid(((a, f - i - j), (b, i), (c, j)))
+        for i in range(f):
+            for j in range(f - i):
+                tris.append((grid[(i, j)], grid[(i + 1, j)], grid[(i, j + 1)]))
+                if i + j + 1 < f:
+                    tris.append((grid[(i + 1, j)], grid[(i + 1, j + 1)], grid[(i, j + 1)]))
+    return Mesh(3, np.array(pos), np.array(tris, dtype=np.int32))
+
+
+def perturb_radial(mesh: Mesh, amp: float = 0.1, k_theta: int = 3, k_phi: int = 4) -> Mesh:
+    """Move every vertex of a unit-sphere mesh to radius 1 + amp sin(k_theta theta) sin(k_phi phi),
+    theta the polar angle from +z, phi the azimuth from +x."""
+    v = mesh.verts
+    u = v / np.linalg.norm(v, axis=1, keepdims=True)
+    theta = np.arccos(np.clip(u[:, 2], -1.0, 1.0))
+    phi = np.arctan2(u[:, 1], u[:, 0])
+    r = 1.0 + amp * np.sin(k_theta * theta) * np.sin(k_phi * phi)
+    return dataclasses.replace(mesh, verts=u * r[:, None])
+
+
+def radial_surface(amp: float, k_theta: int, k_phi: int, dirs: np.ndarray) -> np.ndarray:
+    """Radius of the smooth perturbed sphere along unit directions ``dirs``."""
+    theta = np.arccos(np.clip(dirs[:, 2], -1.0, 1.0))
+    phi = np.arctan2(dirs[:, 1], dirs[:, 0])
+    return 1.0 + amp * np.sin(k_theta * theta) * np.sin(k_phi * phi)
+
+
+def random_rotations(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Uniform random rotations (QR of a Gaussian matrix with sign fix)."""
+    out = []
+    for _ in range(n):
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q @ np.diag(np.sign(np.diag(r)))
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        out.append(q)
+    return np.array(out)
+
+
+def torus_union_sdf(p: np.ndarray, rots: np.ndarray, R: float, r: float) -> np.ndarray:
+    """Signed distance (exact per torus, min over tori) of the union; negative inside."""
+    best = None
+    for Q in rots:
+        q = p @ Q  # rotate the point into the torus frame: q = Q^T p
+        rho = np.sqrt(q[..., 0] ** 2 + q[..., 1] ** 2)
+        d = np.sqrt((rho - R) ** 2 + q[..., 2] ** 2) - r
+        best = d if best is None else np.minimum(best, d)
+    return best
+
+
+# six tetrahedra sharing the cube diagonal 0-7 (corner index = x + 2y + 4z)
+_CUBE_TETS = np.array([[0, 1, 3, 7], [0, 3, 2, 7], [0, 2, 6, 7],
+                       [0, 6, 4, 7], [0, 4, 5, 7], [0, 5, 1, 7]], dtype=np.int64)
+_CUBE_OFF = np.array([[(c >> 0) & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], dtype=np.int64)
+
+
+def marching_tetrahedra(sdf, lo: float, hi: float, n: int) -> Mesh:
+    """Watertight, outward-oriented triangle mesh of {sdf < 0} on an n^3 grid of
+    cubes over [lo, hi]^3.  Each cube is split into six tetrahedra; surface
+    vertices sit on grid edges and are shared through the edge id."""
+    g = np.linspace(lo, hi, n + 1)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    P = np.stack([X, Y, Z], axis=-1)
+    F = sdf(P)
+    F = np.where(F == 0.0, 1e-12, F)  # no zero exactly on a grid vertex
+    inside = F < 0
+    N1 = n + 1
+
+    def flat(ix, iy, iz):
+        return (ix * N1 + iy) * N1 + iz
+
+    # candidate cubes: corners not all of one sign
+    c = np.stack([inside[_CUBE_OFF[k, 0]:n + _CUBE_OFF[k, 0], _CUBE_OFF[k, 1]:n + _CUBE_OFF[k, 1],
+                         _CUBE_OFF[k, 2]:n + _CUBE_OFF[k, 2]] for k in range(8)], axis=-1)
+    mixed = np.any(c, axis=-1) & ~np.all(c, axis=-1)
+    cx, cy, cz = np.nonzero(mixed)
+    corner_ids = np.stack([flat(cx + _CUBE_OFF[k, 0], cy + _CUBE_OFF[k, 1], cz + _CUBE_OFF[k, 2])
+                           for k in range(8)], axis=1)  # (C, 8)
+    tet = corner_ids[:, _CUBE_TETS].reshape(-1, 4)        # (6C, 4) global vertex ids
+    Ff = F.reshape(-1)
+    Pf = P.reshape(-1, 3)
+    ins = Ff[tet] < 0
+    cnt = ins.sum(axis=1)
+    tris: List[np.ndarray] = []
+    toward: List[np.ndarray] = []  # per triangle: a direction from inside to outside
+
+    def edge_key(a, b):
+        lo_ = np.minimum(a, b)
+        hi_ = np.maximum(a, b)
+        return lo_ * (N1 ** 3) + hi_
+
+    # case: one vertex on one side, three on the other -> one triangle
+    for single_inside in (True, False):
+        sel = cnt == (1 if single_inside else 3)
+        T = tet[sel]
+        I = ins[sel]
+        r = np.arange(len(T))
+        lone = np.argmax(I if single_inside else ~I, axis=1)
+        others = np.array([[k for k in range(4) if k != l] for l in range(4)])[lone]
+        a = T[r, lone]
+        bs = T[r[:, None], others]
+        tris.append(np.stack([edge_key(a, bs[:, k]) for k in range(3)], axis=1))
+        away = Pf[bs].mean(axis=1) - Pf[a]
+        toward.append(away if single_inside else -away)
+    # case: two and two -> quad split into two triangles
+    sel = cnt == 2
+    T = tet[sel]
+    I = ins[sel]
+    r = np.arange(len(T))
+    order = np.argsort(~I, axis=1, kind="stable")  # inside vertices first
+    a0, a1 = T[r, order[:, 0]], T[r, order[:, 1]]
+    b0, b1 = T[r, order[:, 2]], T[r, order[:, 3]]
+    k00, k01, k11, k10 = edge_key(a0, b0), edge_key(a0, b1), edge_key(a1, b1), edge_key(a1, b0)
+    out_dir = 0.5 * (Pf[b0] + Pf[b1]) - 0.5 * (Pf[a0] + Pf[a1])
+    tris.append(np.stack([k00, k01, k11], axis=1))
+    toward.append(out_dir)
+    tris.append(np.stack([k00, k11, k10], axis=1))
+    toward.append(out_dir)
+    K = np.concatenate(tris, axis=0)
+    D = np.concatenate(toward, axis=0)
+    uniq, inv = np.unique(K.reshape(-1), return_inverse=True)
+    va = uniq // (N1 ** 3)
+    vb = uniq % (N1 ** 3)
+    fa, fb = Ff[va], Ff[vb]
+    t = fa / (fa - fb)
+    verts = Pf[va] + t[:, None] * (Pf[vb] - Pf[va])
+    prims = inv.reshape(-1, 3).astype(np.int64)
+    # orient each triangle so its normal points from the tetrahedron's inside
+    # vertices toward its outside vertices
+    v0, v1, v2 = verts[prims[:, 0]], verts[prims[:, 1]], verts[prims[:, 2]]
+    nrm = np.cross(v1 - v0, v2 - v0)
+    flip = np.einsum("ij,ij->i", nrm, D) < 0
+    prims[flip] = prims[flip][:, [0, 2, 1]]
+    area = 0.5 * np.linalg.norm(nrm, axis=1)
+    keep = area > 1e-14
+    prims = prims[keep]
+    used = np.unique(prims)
+    remap = np.full(len(verts), -1, dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    return Mesh(3, verts[used], remap[prims].astype(np.int32))
+
+
+def torus_union(grid_n: int = 150, R: float = 1.0, r: float = 0.3, seed: int = 0):
+    """Union of three tori (major radius R, minor radius r) centred at the origin with
+    seeded random rotations.  Returns (mesh, rotations)."""
+    rng = np.random.default_rng(seed)
+    rots = random_rotations(3, rng)
+    ext = R + r + 0.1
+    mesh = marching_tetrahedra(lambda p: torus_union_sdf(p, rots, R, r), -ext, ext, grid_n)
+    return mesh, rots
+
+
+# ----------------------------------------------------------------------------- points
+
+def disk_points(n: int, r_max: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    r = r_max * np.sqrt(rng.random(n))
+    th = 2.0 * np.pi * rng.random(n)
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
+def ball_points(n: int, r_max: float, seed: int, r_min: float = 0.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    u = rng.random(n)
+    r = (r_min ** 3 + u * (r_max ** 3 - r_min ** 3)) ** (1.0 / 3.0)
+    return d * r[:, None]
+
+
+def slice_grid_inside(res: int, extent: float, amp: float, k_theta: int, k_phi: int,
+                      margin: float) -> np.ndarray:
+    """Cell centres of a res x res grid on z = 0 over [-extent, extent]^2 that lie
+    inside the perturbed sphere by at least ``margin`` (radially)."""
+    c = -extent + (np.arange(res) + 0.5) * (2.0 * extent / res)
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    p = np.stack([X.ravel(), Y.ravel(), np.zeros(res * res)], axis=1)
+    rad = np.linalg.norm(p, axis=1)
+    dirs = p / np.maximum(rad, 1e-300)[:, None]
+    dirs[rad == 0] = np.array([1.0, 0.0, 0.0])
+    keep = rad < radial_surface(amp, k_theta, k_phi, dirs) - margin
+    return p[keep]
+
+
+def mesh_surface_points(mesh: Mesh, n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Area-uniform points on a triangle mesh; returns (points, primitive ids)."""
+    rng = np.random.default_rng(seed)
+    v = mesh.verts
+    t = mesh.prims
+    area = 0.5 * np.linalg.norm(np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]]), axis=1)
+    prim = rng.choice(len(t), size=n, p=area / area.sum())
+    a, b = rng.random(n), rng.random(n)
+    flip = a + b > 1.0
+    a[flip], b[flip] = 1.0 - a[flip], 1.0 - b[flip]
+    v0, v1, v2 = v[t[prim, 0]], v[t[prim, 1]], v[t[prim, 2]]
+    pts = v0 + a[:, None] * (v1 - v0) + b[:, None] * (v2 - v0)
+    return pts, prim.astype(np.int32)
+
+
+def box_points_outside(n: int, lo: float, hi: float, sdf, margin: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    out = []
+    have = 0
+    while have < n:
+        p = lo + (hi - lo) * rng.random((2 * n, 3))
+        p = p[sdf(p) > margin]
+        out.append(p)
+        have += len(p)
+    return np.concatenate(out)[:n]
+
+
+def assign_kinds(n_prims: int, kinds: Tuple[int, ...], seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.asarray(kinds, dtype=np.uint8)[rng.integers(0, len(kinds), n_prims)]
