@@ -1,0 +1,141 @@
+"""Walk-on-boundary throughput on one MI355X.
+
+Workload: 3D interior Dirichlet problem on a 20,480-triangle icosphere radially
+perturbed to r = 1 + 0.1 sin(3 theta) sin(4 phi), data g = 1/|x - x0| with
+x0 = (2, 0.5, 0), evaluated at the cells of a 512 x 512 slice z = 0 that lie
+inside (167,604 points), 256 paths per point, path length 6, FP32.
+
+One step = one wob_solve over every point (direction sampling, all-hits BVH
+traversal, hit selection, weights, emission and the per-point mean / variance
+reduction, all in one kernel).  The scene (BVH) is built once before timing, as
+a model's weights would be; inputs are resident in device memory.
+
+Prints one JSON line: path samples/s (value), lines/s, the roofline record of
+the walk kernel and the FP64 oracle timed on a bounded sample on host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes: a node is its box (6 x 4 B) plus two links; a tested
+# triangle is v0, e1, e2 (9 x 4 B); a hit also reads id, kind and alpha (12 B)
+NODE_BYTES, TRI_BYTES, HIT_BYTES = 32, 36, 12
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--cpu-sample-points", type=int, default=96)
+    p.add_argument("--skip-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def cpu_baseline(w, n_points):
+    import oracle
+    om = oracle.OracleMesh(w.mesh)
+    bc = oracle.make_bc(w.bc["domain"], w.bc["formulation"], w.bc["program"], w.bc["params"])
+    idx = np.linspace(0, w.points.shape[0] - 1, n_points).astype(np.int64)
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    oracle.solve(om, w.points[idx], None, bc, w.samples, w.walk_len, w.seed, n_threads=threads)
+    dt = time.perf_counter() - t0
+    paths = n_points * w.samples
+    return {"value": paths / dt, "unit": "path samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_points} evenly spaced points of the same workload x {w.samples} paths x "
+                      f"{w.walk_len} lines, brute force over all {w.mesh.n_prims} triangles, FP64; "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2305_04403_amd import inputs as I
+    from paper_2305_04403_amd import wob
+
+    torch.cuda.set_device(0)
+    w = I.config_icosphere_slice()
+    scene = wob.Scene(w.mesh, wob.F32)
+    info = scene.info()
+    bc = wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"]))
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device="cuda")
+    P, N, M = pts.shape[0], w.samples, w.walk_len
+    mean = torch.empty(P, dtype=torch.float32, device="cuda")
+    var = torch.empty(P, dtype=torch.float32, device="cuda")
+
+    # work counters of exactly the timed solve (same seed, same paths)
+    cnt = wob.count_work(scene, pts, bc, N, M, w.seed)
+
+    for _ in range(args.warmup):
+        wob.solve(scene, pts, bc, N, M, w.seed, out=(mean, var))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[2 * k].record(stream)
+        wob.solve(scene, pts, bc, N, M, w.seed, out=(mean, var))
+        ev[2 * k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]
+    ms_step = 1e3 * wall / args.steps
+    avg_kern_s = 1e-3 * float(np.mean(kern_ms))
+
+    paths = P * N
+    value = paths * args.steps / wall
+    lines = cnt["lines"]
+    alg_bytes = cnt["nodes"] * NODE_BYTES + cnt["prims"] * TRI_BYTES + cnt["hits"] * HIT_BYTES
+    achieved = alg_bytes / avg_kern_s / 1e9
+    m = mean.double().cpu().numpy()
+    se = np.sqrt(var.double().cpu().numpy() / N)
+    rmse = float(np.sqrt(np.mean((m - w.exact) ** 2)))
+
+    rec = {
+        "metric": "WoB path samples/s at 1 GPU",
+        "value": value,
+        "unit": "path samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "points": P, "paths_per_point": N, "walk_len": M,
+                   "triangles": w.mesh.n_prims, "formulation": "double layer (interior Dirichlet)",
+                   "parallelism": "none (1 GPU)"},
+        "lines_per_s": lines * args.steps / wall,
+        "work_per_line": {"nodes": cnt["nodes"] / lines, "triangles": cnt["prims"] / lines,
+                          "hits": cnt["hits"] / lines},
+        "kernel_ms": float(np.mean(kern_ms)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "rmse_vs_analytic": rmse,
+        "mean_se": float(np.mean(se)),
+        "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")},
+    }
+    if not args.skip_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_points)
+    scene.close()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * wob.h - C ABI of the MI355X (gfx950) walk-on-boundary library.
+ *
+ * Walk-on-boundary (WoB) Monte Carlo estimation of harmonic functions from
+ * boundary integral equations (Sugimoto, Chen, Jiang, Batty, Hachisuka, "A
+ * Practical Walk-on-Boundary Method for Boundary Value Problems"):
+ *   - Dirichlet problems: indirect double-layer BIE (Sec. 4.1; Table 1,
+ *     "Dirichlet" rows; estimator eq. indirect_double_boundary_reordered2 and
+ *     eq. mc_dirichlet_interior_sol).
+ *   - Neumann problems: direct BIE (Sec. 4.2; eq. cbie_neumann,
+ *     eq. mc_cbie_neumann, eq. mc_cbie_neumann2; Table 1, "Neumann" rows).
+ *   - Robin and Neumann/Robin mixtures: indirect single-layer BIE (Sec. 4.3;
+ *     Table 1, "Mixed or degenerate problem" rows for Neumann and Robin parts).
+ *   - Interior and exterior domains (Sec. 4.5.1; sign phi of Table 1).
+ *   - Line sampling with all hits and a uniform pick among them (Sec. 4.4.1),
+ *     truncated after M boundary vertices with the last emission halved
+ *     (Sec. 4.1.2).
+ *
+ * Conventions
+ *   - Every call returns a wob_status; no exception crosses the ABI.
+ *   - Arrays passed to wob_solve / wob_trace / wob_intersect_all / wob_count_work
+ *     are DEVICE pointers owned by the caller.  Their element type follows the
+ *     scene's precision: float for WOB_F32 scenes, double for WOB_F64 scenes.
+ *     The library never allocates or frees caller outputs.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *     void*, NULL = default stream).  Argument errors are detected on the host
+ *     before anything is enqueued; a WOB_E_DEVICE return means the HIP runtime
+ *     reported an error for the launch.
+ *   - A scene is immutable after wob_build_bvh and may be used by any number
+ *     of concurrent calls on any streams of the device it was built on.
+ *   - Random numbers: Philox4x32-10 with key (seed & 0xffffffff, seed >> 32)
+ *     and counter (path k, point p, (problem << 24) | (line << 8) | block, w);
+ *     block 0 draws the line direction and the mixture branch, block 1 the
+ *     in-plane self-panel sample, block 2 with w = primitive id the key that
+ *     selects a hit (the hit with the smallest (key, id) is taken, a uniform
+ *     choice among the hits).  Results are bit-reproducible for a given seed.
+ */
+#ifndef WOB_H
+#define WOB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wob_scene_s* wob_scene;
+
+typedef enum {
+  WOB_OK = 0,
+  WOB_E_ARG = 1,         /* invalid argument: NULL where required, bad size, bad enum */
+  WOB_E_ALLOC = 2,       /* device or host allocation failed */
+  WOB_E_DEVICE = 3,      /* HIP runtime error (no device, launch failure, copy failure) */
+  WOB_E_MESH = 4,        /* index out of range, zero-length / zero-area primitive, non-finite vertex */
+  WOB_E_UNSUPPORTED = 5  /* a combination this library does not implement */
+} wob_status;
+
+/* Boundary-condition kind per primitive (eq. PoissonBC). */
+enum { WOB_BC_DIRICHLET = 0, WOB_BC_NEUMANN = 1, WOB_BC_ROBIN = 2 };
+
+/* BIE formulation (Table 1).  AUTO: all Dirichlet -> double layer, all Neumann
+ * -> direct, Robin or Neumann/Robin mixture -> single layer.  Mixtures with
+ * Dirichlet parts return WOB_E_UNSUPPORTED. */
+enum { WOB_F_AUTO = 0, WOB_F_DOUBLE_LAYER = 1, WOB_F_DIRECT = 2, WOB_F_SINGLE_LAYER = 3 };
+
+/* Harmonic function u whose boundary traces give the data: Dirichlet u,
+ * Neumann du/dn, Robin du/dn + alpha u (n = the primitive's unit normal).
+ *   CONST    u = params[0]
+ *   LINEAR   u = params[0] x + params[1] y + params[2] z + params[3]   (2D: no z term)
+ *   QUAD     u = x^2 - y^2
+ *   INVDIST  3D: u = 1 / |x - c|;  2D: u = ln |x - c|;  c = params[0..2] */
+enum { WOB_PROG_CONST = 0, WOB_PROG_LINEAR = 1, WOB_PROG_QUAD = 2, WOB_PROG_INVDIST = 3 };
+
+/* Scene precision: geometry, arithmetic of the walk and element type of arrays. */
+enum { WOB_F32 = 0, WOB_F64 = 1 };
+
+typedef struct {
+  int32_t domain;       /* +1 interior (phi = +1), -1 exterior (phi = -1) */
+  int32_t formulation;  /* WOB_F_* */
+  int32_t program;      /* WOB_PROG_* */
+  int32_t reserved;     /* must be 0 */
+  double params[8];     /* program parameters */
+  double self_panel_p;  /* single layer: probability of the in-plane sample on the own
+                           primitive where G acts on it (0 selects 1/16); in (0, 1) */
+} wob_bc;
+
+typedef struct {
+  int32_t dim;          /* 2 or 3 */
+  int32_t precision;    /* WOB_F32 / WOB_F64 */
+  int64_t n_prims;
+  int64_t n_nodes;
+  int64_t n_leaves;
+  int32_t depth;        /* longest root-to-leaf path */
+  int32_t max_leaf;     /* most primitives in one leaf */
+  int64_t device_bytes; /* bytes of device memory the scene holds */
+  int64_t node_bytes;   /* size of one node record */
+  int64_t prim_bytes;   /* size of one primitive record */
+  int32_t n_dirichlet, n_neumann, n_robin, reserved;
+} wob_scene_info;
+
+/* Build the line-query acceleration structure for a boundary mesh and upload it
+ * to the current HIP device (the geometry query that Sec. 4.4.1's all-hits
+ * sampling needs; the structure itself is this library's design).
+ *   dim        2 (line segments) or 3 (triangles)
+ *   precision  WOB_F32 or WOB_F64; vertices are rounded to that precision
+ *   verts      HOST array, n_verts * dim doubles
+ *   prims      HOST array, n_prims * dim vertex indices; orientation such that
+ *              (v1 - v0) x (v2 - v0) (3D) or the tangent turned by -90 degrees
+ *              (2D, counter-clockwise boundary) points OUT of the interior Omega
+ *              (Sec. 4.5.1: normals stay outward from Omega for exterior problems)
+ *   kind       HOST array, n_prims WOB_BC_* codes, or NULL (all Dirichlet)
+ *   alpha      HOST array, n_prims Robin coefficients, or NULL (all 0)
+ *   out        receives the scene handle; released with wob_free
+ * Synchronous.  Errors: WOB_E_ARG, WOB_E_MESH, WOB_E_ALLOC, WOB_E_DEVICE. */
+wob_status wob_build_bvh(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
+                         const int32_t* prims, int64_t n_prims, const uint8_t* kind,
+                         const double* alpha, wob_scene* out);
+
+/* Release a scene (waits for nothing: the caller must not free a scene that
+ * enqueued work still uses).  NULL is ignored. */
+void wob_free(wob_scene scene);
+
+wob_status wob_get_scene_info(wob_scene scene, wob_scene_info* info);
+
+/* Number of lines traced per path: walk_len for the double and single layer,
+ * walk_len + 1 for the direct BIE (the last vertex traces one more line for its
+ * source integral).  Returns -1 on bad arguments. */
+int32_t wob_lines_per_path(wob_scene scene, const wob_bc* bc, int32_t walk_len);
+
+/* Solve: for every evaluation point p, average N independent WoB paths of
+ * walk_len boundary vertices (Algorithm 1's EstimateSolution generalised to
+ * Table 1's estimators).
+ *   points      DEVICE, n_points * dim (float / double by scene precision)
+ *   point_prim  DEVICE, n_points primitive ids, -1 for points off the boundary;
+ *               NULL = all off the boundary.  A point with an id must lie on
+ *               that primitive: it is then estimated with the boundary rows of
+ *               Table 1 (Dirichlet: the given value; direct and single layer:
+ *               the boundary equations).
+ *   samples     N >= 1 (N >= 2 when var_out is not NULL)
+ *   walk_len    M >= 1, M < 65536
+ *   seed        Philox key
+ *   mean_out    DEVICE, n_points: (1/N) sum of path values
+ *   var_out     DEVICE, n_points: unbiased sample variance of the path values, or NULL
+ * Errors: WOB_E_ARG, WOB_E_UNSUPPORTED, WOB_E_DEVICE. */
+wob_status wob_solve(wob_scene scene, const void* points, const int32_t* point_prim,
+                     int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                     uint64_t seed, void* mean_out, void* var_out, void* stream);
+
+/* Per-path values (parity and debugging); the same paths as wob_solve.
+ *   point_ids  DEVICE, n_points uint32 point indices used in the random-number
+ *              counter, or NULL (point i uses index i).  With ids, a subset of a
+ *              larger solve's points reproduces that solve's paths exactly.
+ *   path_out   DEVICE, n_points * samples, path k of point p at p * samples + k
+ *   vtx_prim   DEVICE, n_points * samples * L int32 (L = wob_lines_per_path) or NULL:
+ *              primitive id picked by each line, -1 if the line met nothing (or was
+ *              the source-only last line of the direct BIE), -2 - id for an in-plane
+ *              self-panel sample on primitive id; entries after a path ended are -1
+ *   vtx_m      DEVICE, same shape, number of hits of each line, or NULL */
+wob_status wob_trace(wob_scene scene, const void* points, const int32_t* point_prim,
+                     int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                     uint64_t seed, const uint32_t* point_ids, void* path_out, int32_t* vtx_prim,
+                     int32_t* vtx_m, void* stream);
+
+/* Every intersection of the lines orig + t dir, t real (Sec. 4.4.1 "all-hits").
+ *   orig, dir    DEVICE, n_lines * dim
+ *   exclude      DEVICE, n_lines primitive ids to skip (-1 none), or NULL
+ *   n_hits       DEVICE, n_lines: total number of hits of each line
+ *   hit_prim     DEVICE, n_lines * max_hits primitive ids, in traversal order;
+ *                only the first max_hits hits of a line are stored
+ *   hit_t        DEVICE, n_lines * max_hits line parameters (float / double), or NULL */
+wob_status wob_intersect_all(wob_scene scene, const void* orig, const void* dir,
+                             const int32_t* exclude, int64_t n_lines, int32_t max_hits,
+                             int32_t* n_hits, int32_t* hit_prim, void* hit_t, void* stream);
+
+/* Work counters for the same walk as wob_solve (measurement only).
+ *   counters  DEVICE, 4 uint64: lines traced, nodes visited, primitives tested,
+ *             hits found; accumulated (the caller zeroes them). */
+wob_status wob_count_work(wob_scene scene, const void* points, const int32_t* point_prim,
+                          int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                          uint64_t seed, uint64_t* counters, void* stream);
+
+const char* wob_status_string(wob_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WOB_H */

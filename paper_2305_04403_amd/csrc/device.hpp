@@ -1,0 +1,418 @@
+// Device-side building blocks of the walk-on-boundary path kernels (gfx950).
+//
+// Everything here runs per lane: one lane owns one Monte Carlo path.  The walk
+// is not a contraction, so there is no MFMA in it; the cost is the all-hits
+// line traversal, which is bound by gathers from the cache level that holds
+// the scene.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wob {
+
+enum Formulation { F_DL = 1, F_DIRECT = 2, F_SL = 3 };
+enum Kind { K_DIRICHLET = 0, K_NEUMANN = 1, K_ROBIN = 2 };
+enum Program { P_CONST = 0, P_LINEAR = 1, P_QUAD = 2, P_INVDIST = 3 };
+
+// --------------------------------------------------------------------------
+// Scene records.  Primitives are stored in BVH leaf order.  idkind packs the
+// caller's primitive id (bits 0..28) and its boundary kind (bits 29..30).
+// --------------------------------------------------------------------------
+template <typename R> struct alignas(16) Node3 { R lo[3]; int32_t skip; R hi[3]; int32_t child; };
+template <typename R> struct alignas(16) Node2 { R lo[2]; R hi[2]; int32_t skip; int32_t child; };
+template <typename R> struct alignas(16) Prim3 { R v0[3]; int32_t idkind; R e1[3]; R alpha; R e2[3]; int32_t pad; };
+template <typename R> struct alignas(16) Prim2 { R v0[2]; R e[2]; R alpha; int32_t idkind; };
+
+template <typename R, int D> struct Rec;
+template <typename R> struct Rec<R, 3> { using Node = Node3<R>; using Prim = Prim3<R>; };
+template <typename R> struct Rec<R, 2> { using Node = Node2<R>; using Prim = Prim2<R>; };
+
+constexpr int kIdBits = 29;
+constexpr int32_t kIdMask = (1 << kIdBits) - 1;
+
+template <typename R, int D>
+struct SceneView {
+  const typename Rec<R, D>::Node* nodes;
+  const typename Rec<R, D>::Prim* prims;
+  const int32_t* leaf_of_id;  // caller id -> leaf-order index
+  int32_t n_nodes;
+  int32_t n_prims;
+};
+
+template <typename R>
+struct ProgramView {
+  int32_t type;
+  R p[8];
+};
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// --------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                      uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// u = ((w >> 9) + 1/2) 2^-23: exact in binary32 and binary64, never 0 or 1.
+template <typename R>
+__device__ __forceinline__ R unit(uint32_t w) {
+  return ((R)(w >> 9) + (R)0.5) * (R)(1.0 / 8388608.0);
+}
+
+template <typename R> __device__ __forceinline__ void sincospi_(R x, R* s, R* c);
+template <> __device__ __forceinline__ void sincospi_<float>(float x, float* s, float* c) { sincospif(x, s, c); }
+template <> __device__ __forceinline__ void sincospi_<double>(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// Uniform direction on the sphere (3D) or circle (2D); the line covers +d and -d.
+template <typename R, int D>
+__device__ __forceinline__ void direction(uint32_t w0, uint32_t w1, R d[3]) {
+  if constexpr (D == 3) {
+    const R z = (R)1 - (R)2 * unit<R>(w0);
+    const R s = sqrt(fmax((R)0, (R)1 - z * z));
+    R sn, cs;
+    sincospi_<R>((R)2 * unit<R>(w1), &sn, &cs);
+    d[0] = s * cs;
+    d[1] = s * sn;
+    d[2] = z;
+  } else {
+    R sn, cs;
+    sincospi_<R>((R)2 * unit<R>(w0), &sn, &cs);
+    d[0] = cs;
+    d[1] = sn;
+    d[2] = 0;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Small vector helpers
+// --------------------------------------------------------------------------
+template <typename R> __device__ __forceinline__ R dot3(const R a[3], const R b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+template <typename R> __device__ __forceinline__ void cross3(const R a[3], const R b[3], R c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+template <typename R> __device__ __forceinline__ R rsqrt_(R v);
+template <> __device__ __forceinline__ float rsqrt_<float>(float v) { return rsqrtf(v); }
+template <> __device__ __forceinline__ double rsqrt_<double>(double v) { return 1.0 / sqrt(v); }
+
+// Geometry of one primitive in a uniform 3-component form (z = 0 in 2D).
+template <typename R>
+struct PrimGeo {
+  R v0[3], e1[3], e2[3];  // 2D: e1 = segment vector, e2 unused
+  R alpha;
+  int32_t id, kind;
+};
+
+template <typename R, int D>
+__device__ __forceinline__ PrimGeo<R> load_prim(const SceneView<R, D>& s, int32_t idx) {
+  PrimGeo<R> g;
+  const auto& p = s.prims[idx];
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      g.v0[a] = p.v0[a];
+      g.e1[a] = p.e1[a];
+      g.e2[a] = p.e2[a];
+    }
+  } else {
+    g.v0[0] = p.v0[0]; g.v0[1] = p.v0[1]; g.v0[2] = 0;
+    g.e1[0] = p.e[0]; g.e1[1] = p.e[1]; g.e1[2] = 0;
+    g.e2[0] = g.e2[1] = g.e2[2] = 0;
+  }
+  g.alpha = p.alpha;
+  g.id = p.idkind & kIdMask;
+  g.kind = (p.idkind >> kIdBits) & 3;
+  return g;
+}
+
+// Unit normal pointing out of Omega.
+template <typename R, int D>
+__device__ __forceinline__ void prim_normal(const PrimGeo<R>& g, R n[3]) {
+  if constexpr (D == 3) {
+    cross3(g.e1, g.e2, n);
+    const R il = rsqrt_<R>(dot3(n, n));
+    n[0] *= il; n[1] *= il; n[2] *= il;
+  } else {
+    const R il = rsqrt_<R>(g.e1[0] * g.e1[0] + g.e1[1] * g.e1[1]);
+    n[0] = g.e1[1] * il;
+    n[1] = -g.e1[0] * il;
+    n[2] = 0;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Harmonic program and boundary datum (eq. PoissonBC)
+// --------------------------------------------------------------------------
+template <typename R, int D>
+__device__ __forceinline__ void program_eval(const ProgramView<R>& g, const R y[3], R& u, R grad[3]) {
+  grad[0] = grad[1] = grad[2] = 0;
+  switch (g.type) {
+    case P_CONST:
+      u = g.p[0];
+      break;
+    case P_LINEAR:
+      u = g.p[0] * y[0] + g.p[1] * y[1] + (D == 3 ? g.p[2] * y[2] : (R)0) + g.p[3];
+      grad[0] = g.p[0];
+      grad[1] = g.p[1];
+      grad[2] = D == 3 ? g.p[2] : (R)0;
+      break;
+    case P_QUAD:
+      u = y[0] * y[0] - y[1] * y[1];
+      grad[0] = (R)2 * y[0];
+      grad[1] = (R)-2 * y[1];
+      break;
+    default: {  // P_INVDIST
+      const R r0 = y[0] - g.p[0], r1 = y[1] - g.p[1], r2 = D == 3 ? y[2] - g.p[2] : (R)0;
+      const R rr = r0 * r0 + r1 * r1 + r2 * r2;
+      if constexpr (D == 3) {
+        const R il = rsqrt_<R>(rr);
+        u = il;
+        const R il3 = il * il * il;
+        grad[0] = -r0 * il3;
+        grad[1] = -r1 * il3;
+        grad[2] = -r2 * il3;
+      } else {
+        u = (R)0.5 * log(rr);
+        const R ir = (R)1 / rr;
+        grad[0] = r0 * ir;
+        grad[1] = r1 * ir;
+      }
+    }
+  }
+}
+
+template <typename R, int D>
+__device__ __forceinline__ R boundary_datum(const ProgramView<R>& prog, const PrimGeo<R>& g, const R y[3]) {
+  R u, grad[3];
+  program_eval<R, D>(prog, y, u, grad);
+  if (g.kind == K_DIRICHLET) return u;
+  R n[3];
+  prim_normal<R, D>(g, n);
+  const R q = dot3(n, grad);
+  return g.kind == K_NEUMANN ? q : q + g.alpha * u;
+}
+
+// --------------------------------------------------------------------------
+// In-plane sample on the primitive that contains x.  Returns G(x, y) / p(y):
+// 3D, theta uniform and radius uniform in [0, R(theta)]: G/p = R(theta) / 2;
+// 2D, y uniform on the segment: G/p = -L ln|y - x| / (2 pi).
+// --------------------------------------------------------------------------
+template <typename R, int D>
+__device__ __forceinline__ R self_panel(const PrimGeo<R>& g, const R x[3], R u0, R u1, R y[3]) {
+  if constexpr (D == 3) {
+    R n[3], t1[3], t2[3];
+    prim_normal<R, D>(g, n);
+    const R il = rsqrt_<R>(dot3(g.e1, g.e1));
+    t1[0] = g.e1[0] * il; t1[1] = g.e1[1] * il; t1[2] = g.e1[2] * il;
+    cross3(n, t1, t2);
+    const R b[3] = {g.v0[0] - x[0], g.v0[1] - x[1], g.v0[2] - x[2]};
+    R a[3][2];
+    a[0][0] = dot3(b, t1);
+    a[0][1] = dot3(b, t2);
+    a[1][0] = a[0][0] + dot3(g.e1, t1);
+    a[1][1] = a[0][1] + dot3(g.e1, t2);
+    a[2][0] = a[0][0] + dot3(g.e2, t1);
+    a[2][1] = a[0][1] + dot3(g.e2, t2);
+    R sn, cs;
+    sincospi_<R>((R)2 * u0, &sn, &cs);
+    R Rt = (R)3.0e38;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int c1 = c == 2 ? 0 : c + 1;
+      const R ex = a[c1][0] - a[c][0], ey = a[c1][1] - a[c][1];
+      const R den = cs * ey - sn * ex;
+      if (den != (R)0) {
+        const R s = (a[c][0] * ey - a[c][1] * ex) / den;
+        if (s > (R)0 && s < Rt) Rt = s;
+      }
+    }
+    if (!(Rt < (R)3.0e38)) Rt = 0;
+    const R rho = u1 * Rt;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y[k] = x[k] + rho * (cs * t1[k] + sn * t2[k]);
+    return (R)0.5 * Rt;
+  } else {
+    y[0] = g.v0[0] + u0 * g.e1[0];
+    y[1] = g.v0[1] + u0 * g.e1[1];
+    y[2] = 0;
+    const R L = sqrt(g.e1[0] * g.e1[0] + g.e1[1] * g.e1[1]);
+    const R dx = y[0] - x[0], dy = y[1] - x[1];
+    const R rho = sqrt(dx * dx + dy * dy);
+    return -L * log(rho) * (R)(0.5 / 3.14159265358979323846);
+  }
+}
+
+// --------------------------------------------------------------------------
+// All-hits line traversal
+// --------------------------------------------------------------------------
+struct WorkCount {
+  uint64_t lines, nodes, prims, hits;
+};
+
+template <typename R>
+struct HitAcc {
+  int32_t m;
+  uint32_t key;
+  int32_t id, idx;
+  R u, v;     // barycentric coordinates of the selected hit
+  R src;      // direct BIE: sum over hits of G q / p_all
+};
+
+// Test one primitive against the line x + t d (t real, inclusive edges).
+// On a hit returns true and writes t and the barycentrics.
+template <typename R, int D>
+__device__ __forceinline__ bool hit_prim(const PrimGeo<R>& g, const R x[3], const R d[3], R& t, R& u, R& v) {
+  if constexpr (D == 3) {
+    R pv[3], qv[3];
+    cross3(d, g.e2, pv);
+    const R det = dot3(g.e1, pv);
+    if (det == (R)0) return false;
+    const R inv = (R)1 / det;
+    const R sv[3] = {x[0] - g.v0[0], x[1] - g.v0[1], x[2] - g.v0[2]};
+    u = dot3(sv, pv) * inv;
+    if (u < (R)0 || u > (R)1) return false;
+    cross3(sv, g.e1, qv);
+    v = dot3(d, qv) * inv;
+    if (v < (R)0 || u + v > (R)1) return false;
+    t = dot3(g.e2, qv) * inv;
+    return true;
+  } else {
+    const R det = d[0] * g.e1[1] - d[1] * g.e1[0];
+    if (det == (R)0) return false;
+    const R inv = (R)1 / det;
+    const R sx = x[0] - g.v0[0], sy = x[1] - g.v0[1];
+    // s = cross(x - v0, d) / cross(e, d) = -cross(x - v0, d) / det
+    u = -(sx * d[1] - sy * d[0]) * inv;
+    if (u < (R)0 || u > (R)1) return false;
+    v = 0;
+    // t = cross(v0 - x, e) / det
+    t = (-sx * g.e1[1] + sy * g.e1[0]) * inv;
+    return true;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void hit_point(const PrimGeo<R>& g, R u, R v, R y[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) y[k] = g.v0[k] + u * g.e1[k] + v * g.e2[k];
+}
+
+// Slab test of a line against a box; inv = 1 / d (finite), ox = -x * inv.
+template <typename R, int D>
+__device__ __forceinline__ bool line_box(const typename Rec<R, D>::Node& n, const R inv[3], const R ox[3]) {
+  R tmin, tmax;
+  {
+    const R a = fma(n.lo[0], inv[0], ox[0]), b = fma(n.hi[0], inv[0], ox[0]);
+    tmin = fmin(a, b);
+    tmax = fmax(a, b);
+  }
+  {
+    const R a = fma(n.lo[1], inv[1], ox[1]), b = fma(n.hi[1], inv[1], ox[1]);
+    tmin = fmax(tmin, fmin(a, b));
+    tmax = fmin(tmax, fmax(a, b));
+  }
+  if constexpr (D == 3) {
+    const R a = fma(n.lo[2], inv[2], ox[2]), b = fma(n.hi[2], inv[2], ox[2]);
+    tmin = fmax(tmin, fmin(a, b));
+    tmax = fmin(tmax, fmax(a, b));
+  }
+  return tmin <= tmax;
+}
+
+template <typename R> __device__ __forceinline__ R safe_inv(R d) {
+  const R big = sizeof(R) == 4 ? (R)1e30 : (R)1e300;
+  return d == (R)0 ? big : (R)1 / d;
+}
+
+// Visit every hit of the line through x with direction d, skipping primitive
+// `exclude` (leaf-order index).  Per hit: count it; with `select`, draw its
+// key (Philox block 2, w = caller id) and keep the smallest (key, id); with
+// `source`, add G q / p_all for the direct BIE's source integral.
+template <typename R, int D, bool COUNT>
+__device__ __forceinline__ void trace_line(const SceneView<R, D>& s, const ProgramView<R>& prog,
+                                           const R x[3], const R d[3], int32_t exclude, bool select,
+                                           bool source, uint32_t kc0, uint32_t kc1, uint32_t kc2,
+                                           uint32_t k0, uint32_t k1, HitAcc<R>& h, WorkCount& wc) {
+  R inv[3], ox[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    inv[a] = safe_inv(d[a]);
+    ox[a] = -x[a] * inv[a];
+  }
+  h.m = 0;
+  h.key = 0xffffffffu;
+  h.id = 0x7fffffff;
+  h.idx = -1;
+  h.u = h.v = 0;
+  h.src = 0;
+  if (COUNT) wc.lines += 1;
+  int32_t i = 0;
+  const int32_t end = s.n_nodes;
+  while (i < end) {
+    const typename Rec<R, D>::Node node = s.nodes[i];
+    if (COUNT) wc.nodes += 1;
+    if (line_box<R, D>(node, inv, ox)) {
+      if (node.child >= 0) {
+        i = node.child;
+        continue;
+      }
+      const int32_t code = -1 - node.child;
+      const int32_t first = code >> 3, count = (code & 7) + 1;
+      for (int32_t j = first; j < first + count; ++j) {
+        if (j == exclude) continue;
+        if (COUNT) wc.prims += 1;
+        const PrimGeo<R> g = load_prim<R, D>(s, j);
+        R t, u, v;
+        if (!hit_prim<R, D>(g, x, d, t, u, v)) continue;
+        if (COUNT) wc.hits += 1;
+        h.m += 1;
+        if (select) {
+          const uint32_t key = philox(kc0, kc1, kc2, (uint32_t)g.id, k0, k1).x;
+          if (key < h.key || (key == h.key && g.id < h.id)) {
+            h.key = key;
+            h.id = g.id;
+            h.idx = j;
+            h.u = u;
+            h.v = v;
+          }
+        }
+        if (source) {
+          R y[3], n[3];
+          hit_point(g, u, v, y);
+          prim_normal<R, D>(g, n);
+          R uu, grad[3];
+          program_eval<R, D>(prog, y, uu, grad);
+          const R q = dot3(n, grad);
+          const R r[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+          const R rho = sqrt(dot3(r, r));
+          const R ac = fabs(dot3(r, n)) / rho;  // |cos theta_y|
+          // G q / p_all: 3D rho q / (2 |c|); 2D -rho ln(rho) q / (2 |c|)
+          const R gp = D == 3 ? rho / ((R)2 * ac) : -rho * log(rho) / ((R)2 * ac);
+          h.src += gp * q;
+        }
+      }
+    }
+    i = node.skip;
+  }
+}
+
+}  // namespace wob

@@ -1,0 +1,293 @@
+// The fused walk-on-boundary path kernel: one lane = one path, all vertices of
+// the path in registers, per-point mean / variance reduced in the same launch.
+#pragma once
+
+#include "device.hpp"
+
+namespace wob {
+
+template <typename R, int D>
+struct WalkArgs {
+  SceneView<R, D> scene;
+  ProgramView<R> prog;
+  const R* points;
+  const int32_t* point_prim;  // caller ids, -1 off the boundary; may be null
+  const uint32_t* point_ids;  // random-number point index per point; null = position
+  int64_t n_points;
+  int32_t N, M, L;            // paths per point, boundary vertices, lines per path
+  R phi;                      // +1 interior, -1 exterior
+  uint32_t self_thr;          // mixture branch threshold floor(p_s 2^24)
+  R self_p;                   // floor(p_s 2^24) / 2^24
+  uint32_t k0, k1;            // Philox key
+  uint32_t problem;           // problem index (counter word 2, bits 24..31)
+  int32_t lpp_shift;          // log2 of lanes per point (6, 7 or 8)
+  R* mean_out;
+  R* var_out;
+  R* path_out;
+  int32_t* vtx_prim;
+  int32_t* vtx_m;
+  unsigned long long* counters;
+};
+
+// One path.  Returns the path value u_hat(x_0).
+//
+// Double layer (Table 1, Dirichlet; eq. mc_dirichlet_interior_sol and
+// eq. indirect_double_boundary_reordered2):  first weight -dG/dn_y / p, then
+// 2 phi dG/dn_y / p; emission 2 phi g at x_1..x_{M-1} and phi g at x_M.
+// With line sampling these weights are (m/2) sgn(cos) and -phi m sgn(cos).
+//
+// Direct BIE (Table 1, Neumann; eq. mc_cbie_neumann2, eq. mc_cbie_neumann):
+// first weight -phi dG/dn_y / p = phi (m/2) sgn(cos), then
+// -2 phi dG/dn_y / p = phi m sgn(cos).  Source phi int G q (off the boundary)
+// or 2 phi int G q (on it), estimated from all hits of the same line plus the
+// in-plane sample of the own primitive; the source of x_M (its own line) is
+// halved.
+//
+// Single layer (Table 1, Neumann / Robin rows): first weight G / p =
+// m rho / (2 |cos|) (3D), then -2 phi (dG/dn_x + alpha G) / p =
+// -phi m (cos_x + alpha rho) / |cos_y| (3D); where G acts on the own primitive
+// (boundary x_0, Robin vertices) the line sample is mixed with the in-plane
+// sample with probability p_s.  Emission 2 phi s, halved at x_M.
+template <typename R, int D, int FORM, bool TRACE, bool COUNT>
+__device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, uint32_t path,
+                                      const R x0[3], int32_t prim0, int32_t* vprim, int32_t* vm,
+                                      WorkCount& wc) {
+  const R phi = a.phi;
+  if (TRACE) {
+    for (int i = 0; i < a.L; ++i) {
+      if (vprim) vprim[i] = -1;
+      if (vm) vm[i] = 0;
+    }
+  }
+  // a primitive id outside [-1, n_prims) is a caller error: the path is NaN
+  if (prim0 < -1 || prim0 >= a.scene.n_prims) return (R)NAN;
+  int32_t cur_idx = prim0 >= 0 ? a.scene.leaf_of_id[prim0] : -1;
+  R x[3] = {x0[0], x0[1], x0[2]};
+  if (FORM == F_DL && cur_idx >= 0) {
+    // Table 1: on the boundary the Dirichlet solution is the given value
+    const PrimGeo<R> g = load_prim<R, D>(a.scene, cur_idx);
+    return boundary_datum<R, D>(a.prog, g, x);
+  }
+  R W = 1, acc = 0;
+  const uint32_t zbase = a.problem << 24;
+  for (int i = 0; i < a.L; ++i) {
+    const bool on_gamma = cur_idx >= 0;
+    const uint32_t z = zbase | ((uint32_t)i << 8);
+    const U4 r0 = philox(path, point, z, 0u, a.k0, a.k1);
+    R d[3];
+    direction<R, D>(r0.x, r0.y, d);
+    PrimGeo<R> gc;
+    if (on_gamma && (FORM != F_DL)) gc = load_prim<R, D>(a.scene, cur_idx);
+    bool mixture = false, use_self = false;
+    if constexpr (FORM == F_SL) {
+      mixture = on_gamma && (i == 0 || gc.kind == K_ROBIN);
+      use_self = mixture && (r0.z >> 8) < a.self_thr;
+    }
+    R y[3], w;
+    int32_t next_idx;
+    if (use_self) {
+      const U4 r1 = philox(path, point, z | 1u, 0u, a.k0, a.k1);
+      const R gp = self_panel<R, D>(gc, x, unit<R>(r1.x), unit<R>(r1.y), y);
+      w = (i == 0 ? gp : (R)-2 * phi * gc.alpha * gp) / a.self_p;
+      next_idx = cur_idx;
+      if (TRACE && vprim) vprim[i] = -2 - gc.id;
+    } else {
+      const bool last = i == a.L - 1;
+      const bool src_line = FORM == F_DIRECT;
+      const bool select = !(src_line && last);
+      HitAcc<R> h;
+      trace_line<R, D, COUNT>(a.scene, a.prog, x, d, cur_idx, select, src_line, path, point, z | 2u,
+                              a.k0, a.k1, h, wc);
+      if (TRACE) {
+        if (vm) vm[i] = h.m;
+        if (vprim) vprim[i] = (select && h.m > 0) ? h.id : -1;
+      }
+      if constexpr (FORM == F_DIRECT) {
+        R S;
+        if (on_gamma) {
+          const U4 r1 = philox(path, point, z | 1u, 0u, a.k0, a.k1);
+          R ys[3];
+          const R gp = self_panel<R, D>(gc, x, unit<R>(r1.x), unit<R>(r1.y), ys);
+          S = (R)2 * phi * (h.src + gp * boundary_datum<R, D>(a.prog, gc, ys));
+        } else {
+          S = phi * h.src;
+        }
+        acc += W * S * (last ? (R)0.5 : (R)1);
+        if (last) break;
+      }
+      if (h.m == 0) break;
+      const PrimGeo<R> gy = load_prim<R, D>(a.scene, h.idx);
+      hit_point(gy, h.u, h.v, y);
+      R ny[3];
+      prim_normal<R, D>(gy, ny);
+      const R r[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+      const R mm = (R)h.m;
+      if constexpr (FORM == F_DL) {
+        const R sg = dot3(r, ny) > (R)0 ? (R)1 : (R)-1;
+        w = (i == 0 && !on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
+      } else if constexpr (FORM == F_DIRECT) {
+        const R sg = dot3(r, ny) > (R)0 ? (R)1 : (R)-1;
+        w = on_gamma ? phi * mm * sg : (R)0.5 * phi * mm * sg;
+      } else {
+        const R rho = sqrt(dot3(r, r));
+        const R acy = fabs(dot3(r, ny)) / rho;
+        if (i == 0) {
+          // G / p
+          w = D == 3 ? mm * rho / ((R)2 * acy) : -mm * rho * log(rho) / ((R)2 * acy);
+        } else {
+          R nx[3];
+          prim_normal<R, D>(gc, nx);
+          const R cx = dot3(r, nx) / rho;
+          w = D == 3 ? -phi * mm * (cx + gc.alpha * rho) / acy
+                     : -phi * mm * (cx - gc.alpha * rho * log(rho)) / acy;
+        }
+        if (mixture) w /= ((R)1 - a.self_p);
+      }
+      next_idx = h.idx;
+    }
+    W *= w;
+    x[0] = y[0];
+    x[1] = y[1];
+    x[2] = y[2];
+    cur_idx = next_idx;
+    if constexpr (FORM != F_DIRECT) {
+      const PrimGeo<R> gn = load_prim<R, D>(a.scene, cur_idx);
+      const R s = boundary_datum<R, D>(a.prog, gn, x);
+      acc += W * ((i + 1 < a.M) ? (R)2 * phi : phi) * s;
+    }
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, double nb,
+                                           double meanb, double m2b) {
+  if (nb == 0.0) return;
+  if (n == 0.0) {
+    n = nb;
+    mean = meanb;
+    m2 = m2b;
+    return;
+  }
+  const double nn = n + nb;
+  const double delta = meanb - mean;
+  mean += delta * (nb / nn);
+  m2 += m2b + delta * delta * (n * nb / nn);
+  n = nn;
+}
+
+template <typename R, int D, int FORM, bool TRACE, bool COUNT>
+__global__ void __launch_bounds__(256) walk_kernel(WalkArgs<R, D> a) {
+  const int tid = threadIdx.x;
+  const int lpp = 1 << a.lpp_shift;
+  const int64_t point = (int64_t)blockIdx.x * (256 >> a.lpp_shift) + (tid >> a.lpp_shift);
+  const int lane_in_point = tid & (lpp - 1);
+  double n = 0.0, mean = 0.0, m2 = 0.0;
+  WorkCount wc = {0, 0, 0, 0};
+  if (point < a.n_points) {
+    R x0[3];
+    x0[0] = a.points[point * D + 0];
+    x0[1] = a.points[point * D + 1];
+    x0[2] = D == 3 ? a.points[point * D + 2] : (R)0;
+    const int32_t prim0 = a.point_prim ? a.point_prim[point] : -1;
+    for (int k = lane_in_point; k < a.N; k += lpp) {
+      const int64_t item = point * (int64_t)a.N + k;
+      int32_t* vp = (TRACE && a.vtx_prim) ? a.vtx_prim + item * a.L : nullptr;
+      int32_t* vm = (TRACE && a.vtx_m) ? a.vtx_m + item * a.L : nullptr;
+      const uint32_t pid = a.point_ids ? a.point_ids[point] : (uint32_t)point;
+      const R v = run_path<R, D, FORM, TRACE, COUNT>(a, pid, (uint32_t)k, x0, prim0, vp, vm, wc);
+      if (TRACE) a.path_out[item] = v;
+      n += 1.0;
+      const double dv = (double)v - mean;
+      mean += dv / n;
+      m2 += dv * ((double)v - mean);
+    }
+  }
+  if (COUNT) {
+    unsigned long long c[4] = {wc.lines, wc.nodes, wc.prims, wc.hits};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
+      if ((tid & 63) == 0) atomicAdd(a.counters + k, c[k]);
+    }
+    return;
+  }
+  if (TRACE) return;
+
+  // per-point reduction: within the wavefront, then across the point's wavefronts
+  for (int off = 32; off > 0; off >>= 1) {
+    const double nb = __shfl_xor(n, off, 64);
+    const double mb = __shfl_xor(mean, off, 64);
+    const double sb = __shfl_xor(m2, off, 64);
+    if (((tid & 63) & off) == 0) {
+      chan_merge(n, mean, m2, nb, mb, sb);
+    } else {
+      double n2 = nb, mean2 = mb, m22 = sb;
+      chan_merge(n2, mean2, m22, n, mean, m2);
+      n = n2;
+      mean = mean2;
+      m2 = m22;
+    }
+  }
+  __shared__ double red[4][3];
+  const int wave = tid >> 6;
+  if ((tid & 63) == 0) {
+    red[wave][0] = n;
+    red[wave][1] = mean;
+    red[wave][2] = m2;
+  }
+  __syncthreads();
+  if (lane_in_point == 0 && point < a.n_points) {
+    const int waves = lpp >> 6;
+    double tn = red[wave][0], tm = red[wave][1], ts = red[wave][2];
+    for (int w = 1; w < waves; ++w) chan_merge(tn, tm, ts, red[wave + w][0], red[wave + w][1], red[wave + w][2]);
+    a.mean_out[point] = (R)tm;
+    if (a.var_out) a.var_out[point] = (R)(tn > 1.0 ? ts / (tn - 1.0) : 0.0);
+  }
+}
+
+// Every hit of each line, in traversal order (parity / debugging).
+template <typename R, int D>
+__global__ void __launch_bounds__(256) intersect_kernel(SceneView<R, D> s, const R* orig, const R* dir,
+                                                        const int32_t* exclude, int64_t n_lines,
+                                                        int32_t max_hits, int32_t* n_hits,
+                                                        int32_t* hit_ids, R* hit_t) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_lines) return;
+  R x[3], d[3], inv[3], ox[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = a < D ? orig[l * D + a] : (R)0;
+    d[a] = a < D ? dir[l * D + a] : (R)0;
+    inv[a] = safe_inv(d[a]);
+    ox[a] = -x[a] * inv[a];
+  }
+  const int32_t ex_id = exclude ? exclude[l] : -1;
+  const int32_t ex = (ex_id >= 0 && ex_id < s.n_prims) ? s.leaf_of_id[ex_id] : -1;
+  int32_t cnt = 0;
+  int32_t i = 0;
+  while (i < s.n_nodes) {
+    const typename Rec<R, D>::Node node = s.nodes[i];
+    if (line_box<R, D>(node, inv, ox)) {
+      if (node.child >= 0) {
+        i = node.child;
+        continue;
+      }
+      const int32_t code = -1 - node.child;
+      const int32_t first = code >> 3, count = (code & 7) + 1;
+      for (int32_t j = first; j < first + count; ++j) {
+        if (j == ex) continue;
+        const PrimGeo<R> g = load_prim<R, D>(s, j);
+        R t, u, v;
+        if (!hit_prim<R, D>(g, x, d, t, u, v)) continue;
+        if (cnt < max_hits) {
+          hit_ids[l * max_hits + cnt] = g.id;
+          if (hit_t) hit_t[l * max_hits + cnt] = t;
+        }
+        ++cnt;
+      }
+    }
+    i = node.skip;
+  }
+  n_hits[l] = cnt;
+}
+
+}  // namespace wob

@@ -1,0 +1,456 @@
+// C ABI of the walk-on-boundary library: argument validation, scene upload and
+// kernel dispatch.  The kernels themselves live in walk.hpp / device.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/wob.h"
+#include "bvh_build.hpp"
+#include "walk.hpp"
+
+struct wob_scene_s {
+  int32_t dim = 0, precision = 0, device = 0;
+  int64_t n_prims = 0, n_nodes = 0, n_leaves = 0;
+  int32_t depth = 0, max_leaf = 0;
+  void* d_nodes = nullptr;
+  void* d_prims = nullptr;
+  int32_t* d_leaf_of_id = nullptr;
+  int64_t node_bytes = 0, prim_bytes = 0, device_bytes = 0;
+  int32_t n_dirichlet = 0, n_neumann = 0, n_robin = 0;
+};
+
+namespace {
+
+constexpr int kMaxLeaf = 4;
+
+// Round a double to float toward -inf / +inf so boxes stay conservative.
+float down_f(double v) {
+  float f = (float)v;
+  if ((double)f > v) f = std::nextafter(f, -INFINITY);
+  return f;
+}
+float up_f(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+template <typename R> R round_to(double v) { return (R)v; }
+
+// Pad a box so that the FMA slab test in R precision never misses a primitive
+// that the exact test would hit.
+template <typename R>
+void padded_box(const wobhost::Box& b, int dim, R lo[3], R hi[3]) {
+  double mag = 0.0;
+  for (int a = 0; a < dim; ++a) mag = std::fmax(mag, std::fmax(std::fabs(b.lo[a]), std::fabs(b.hi[a])));
+  const double pad = (sizeof(R) == 4 ? 0x1p-19 : 0x1p-45) * (mag + 1e-30);
+  for (int a = 0; a < dim; ++a) {
+    if (sizeof(R) == 4) {
+      lo[a] = (R)down_f(b.lo[a] - pad);
+      hi[a] = (R)up_f(b.hi[a] + pad);
+    } else {
+      lo[a] = (R)(b.lo[a] - pad);
+      hi[a] = (R)(b.hi[a] + pad);
+    }
+  }
+}
+
+template <typename R, int D>
+wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int32_t* prims,
+                        const uint8_t* kind, const double* alpha, const wobhost::Bvh& bvh) {
+  using Node = typename wob::Rec<R, D>::Node;
+  using Prim = typename wob::Rec<R, D>::Prim;
+  const int64_t T = sc->n_prims;
+  std::vector<Node> nodes(bvh.nodes.size());
+  for (size_t i = 0; i < bvh.nodes.size(); ++i) {
+    const auto& fn = bvh.nodes[i];
+    Node& n = nodes[i];
+    std::memset(&n, 0, sizeof(Node));
+    R lo[3], hi[3];
+    padded_box<R>(fn.box, D, lo, hi);
+    for (int a = 0; a < D; ++a) {
+      n.lo[a] = lo[a];
+      n.hi[a] = hi[a];
+    }
+    n.skip = fn.skip;
+    n.child = fn.child;
+  }
+  std::vector<Prim> recs((size_t)T);
+  std::vector<int32_t> leaf_of_id((size_t)T);
+  for (int64_t j = 0; j < T; ++j) {
+    const int32_t id = bvh.order[j];
+    leaf_of_id[id] = (int32_t)j;
+    Prim& p = recs[j];
+    std::memset(&p, 0, sizeof(Prim));
+    const int32_t* ix = prims + (int64_t)id * D;
+    const int k = kind ? kind[id] : 0;
+    p.idkind = id | (k << wob::kIdBits);
+    p.alpha = alpha ? (R)alpha[id] : (R)0;
+    if constexpr (D == 3) {
+      for (int a = 0; a < 3; ++a) {
+        const double v0 = v[(int64_t)ix[0] * 3 + a], v1 = v[(int64_t)ix[1] * 3 + a],
+                     v2 = v[(int64_t)ix[2] * 3 + a];
+        p.v0[a] = (R)v0;
+        p.e1[a] = (R)(v1 - v0);
+        p.e2[a] = (R)(v2 - v0);
+      }
+    } else {
+      for (int a = 0; a < 2; ++a) {
+        const double v0 = v[(int64_t)ix[0] * 2 + a], v1 = v[(int64_t)ix[1] * 2 + a];
+        p.v0[a] = (R)v0;
+        p.e[a] = (R)(v1 - v0);
+      }
+    }
+  }
+  sc->node_bytes = sizeof(Node);
+  sc->prim_bytes = sizeof(Prim);
+  const size_t nb = nodes.size() * sizeof(Node), pb = recs.size() * sizeof(Prim),
+               lb = leaf_of_id.size() * sizeof(int32_t);
+  if (hipMalloc(&sc->d_nodes, nb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc(&sc->d_prims, pb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc((void**)&sc->d_leaf_of_id, lb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMemcpy(sc->d_nodes, nodes.data(), nb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
+  if (hipMemcpy(sc->d_prims, recs.data(), pb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
+  if (hipMemcpy(sc->d_leaf_of_id, leaf_of_id.data(), lb, hipMemcpyHostToDevice) != hipSuccess)
+    return WOB_E_DEVICE;
+  sc->device_bytes = (int64_t)(nb + pb + lb);
+  return WOB_OK;
+}
+
+template <typename R, int D>
+wob::SceneView<R, D> view(const wob_scene_s* sc) {
+  wob::SceneView<R, D> s;
+  s.nodes = (const typename wob::Rec<R, D>::Node*)sc->d_nodes;
+  s.prims = (const typename wob::Rec<R, D>::Prim*)sc->d_prims;
+  s.leaf_of_id = sc->d_leaf_of_id;
+  s.n_nodes = (int32_t)sc->n_nodes;
+  s.n_prims = (int32_t)sc->n_prims;
+  return s;
+}
+
+int resolve_formulation(const wob_scene_s* sc, int f) {
+  const bool d = sc->n_dirichlet > 0, n = sc->n_neumann > 0, r = sc->n_robin > 0;
+  if (f == WOB_F_AUTO) {
+    if (!n && !r) return WOB_F_DOUBLE_LAYER;
+    if (!d && !r) return WOB_F_DIRECT;
+    if (!d) return WOB_F_SINGLE_LAYER;
+    return -1;
+  }
+  if (f == WOB_F_DOUBLE_LAYER) return (!n && !r) ? f : -1;
+  if (f == WOB_F_DIRECT) return (!d && !r) ? f : -1;
+  if (f == WOB_F_SINGLE_LAYER) return !d ? f : -1;
+  return -2;
+}
+
+struct Plan {
+  int form;
+  int32_t L;
+  uint32_t self_thr;
+  double self_p;
+};
+
+wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                     Plan* p) {
+  if (!sc || !bc) return WOB_E_ARG;
+  if (bc->domain != 1 && bc->domain != -1) return WOB_E_ARG;
+  if (bc->program < WOB_PROG_CONST || bc->program > WOB_PROG_INVDIST) return WOB_E_ARG;
+  if (bc->reserved != 0) return WOB_E_ARG;
+  if (samples < 1 || walk_len < 1 || walk_len >= 65535) return WOB_E_ARG;
+  const int f = resolve_formulation(sc, bc->formulation);
+  if (f == -2) return WOB_E_ARG;
+  if (f < 0) return WOB_E_UNSUPPORTED;
+  double ps = bc->self_panel_p == 0.0 ? 1.0 / 16.0 : bc->self_panel_p;
+  if (!(ps > 0.0 && ps < 1.0)) return WOB_E_ARG;
+  p->form = f;
+  p->L = f == WOB_F_DIRECT ? walk_len + 1 : walk_len;
+  p->self_thr = (uint32_t)std::floor(ps * 16777216.0);
+  if (p->self_thr == 0) return WOB_E_ARG;
+  p->self_p = p->self_thr / 16777216.0;
+  return WOB_OK;
+}
+
+template <typename R, int D>
+wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void* points,
+                              const int32_t* point_prim, int64_t n_points, const wob_bc* bc,
+                              int32_t samples, int32_t walk_len, uint64_t seed) {
+  wob::WalkArgs<R, D> a;
+  std::memset(&a, 0, sizeof(a));
+  a.scene = view<R, D>(sc);
+  a.prog.type = bc->program;
+  for (int k = 0; k < 8; ++k) a.prog.p[k] = (R)bc->params[k];
+  a.points = (const R*)points;
+  a.point_prim = point_prim;
+  a.n_points = n_points;
+  a.N = samples;
+  a.M = walk_len;
+  a.L = pl.L;
+  a.phi = (R)bc->domain;
+  a.self_thr = pl.self_thr;
+  a.self_p = (R)pl.self_p;
+  a.k0 = (uint32_t)(seed & 0xffffffffu);
+  a.k1 = (uint32_t)(seed >> 32);
+  a.problem = 0;
+  a.lpp_shift = samples <= 64 ? 6 : (samples <= 128 ? 7 : 8);
+  return a;
+}
+
+enum Mode { MODE_SOLVE = 0, MODE_TRACE = 1, MODE_COUNT = 2 };
+
+template <typename R, int D, int FORM>
+void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
+  const int ppb = 256 >> a.lpp_shift;
+  const dim3 grid((unsigned)((a.n_points + ppb - 1) / ppb)), block(256);
+  if (mode == MODE_SOLVE)
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false>), grid, block, 0, st, a);
+  else if (mode == MODE_TRACE)
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false>), grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true>), grid, block, 0, st, a);
+}
+
+template <typename R, int D>
+void launch_walk(const wob::WalkArgs<R, D>& a, int form, int mode, hipStream_t st) {
+  if (form == WOB_F_DOUBLE_LAYER) launch_form<R, D, wob::F_DL>(a, mode, st);
+  else if (form == WOB_F_DIRECT) launch_form<R, D, wob::F_DIRECT>(a, mode, st);
+  else launch_form<R, D, wob::F_SL>(a, mode, st);
+}
+
+wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim, int64_t n_points,
+                    const wob_bc* bc, int32_t samples, int32_t walk_len, uint64_t seed,
+                    const uint32_t* point_ids, void* mean_out, void* var_out, void* path_out,
+                    int32_t* vtx_prim, int32_t* vtx_m, uint64_t* counters, int mode,
+                    void* stream) {
+  Plan pl;
+  wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
+  if (s != WOB_OK) return s;
+  if (n_points < 0 || (n_points > 0 && !points)) return WOB_E_ARG;
+  if (n_points >= (int64_t)1 << 32) return WOB_E_ARG;  // point index is a 32-bit counter word
+  if (mode == MODE_SOLVE && n_points > 0 && !mean_out) return WOB_E_ARG;
+  if (mode == MODE_SOLVE && var_out && samples < 2) return WOB_E_ARG;
+  if (mode == MODE_TRACE && n_points > 0 && !path_out) return WOB_E_ARG;
+  if (mode == MODE_COUNT && !counters) return WOB_E_ARG;
+  if (n_points == 0) return WOB_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (sc->precision == WOB_F32) {
+    if (sc->dim == 3) {
+      auto a = make_args<float, 3>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
+      a.mean_out = (float*)mean_out; a.var_out = (float*)var_out; a.path_out = (float*)path_out;
+      a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
+      a.point_ids = point_ids;
+      launch_walk<float, 3>(a, pl.form, mode, st);
+    } else {
+      auto a = make_args<float, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
+      a.mean_out = (float*)mean_out; a.var_out = (float*)var_out; a.path_out = (float*)path_out;
+      a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
+      a.point_ids = point_ids;
+      launch_walk<float, 2>(a, pl.form, mode, st);
+    }
+  } else {
+    if (sc->dim == 3) {
+      auto a = make_args<double, 3>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
+      a.mean_out = (double*)mean_out; a.var_out = (double*)var_out; a.path_out = (double*)path_out;
+      a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
+      a.point_ids = point_ids;
+      launch_walk<double, 3>(a, pl.form, mode, st);
+    } else {
+      auto a = make_args<double, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
+      a.mean_out = (double*)mean_out; a.var_out = (double*)var_out; a.path_out = (double*)path_out;
+      a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
+      a.point_ids = point_ids;
+      launch_walk<double, 2>(a, pl.form, mode, st);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wob_status_string(wob_status s) {
+  switch (s) {
+    case WOB_OK: return "ok";
+    case WOB_E_ARG: return "invalid argument";
+    case WOB_E_ALLOC: return "allocation failed";
+    case WOB_E_DEVICE: return "HIP runtime error";
+    case WOB_E_MESH: return "invalid mesh";
+    case WOB_E_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+wob_status wob_build_bvh(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
+                         const int32_t* prims, int64_t n_prims, const uint8_t* kind,
+                         const double* alpha, wob_scene* out) {
+  if (!out) return WOB_E_ARG;
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return WOB_E_ARG;
+  if (precision != WOB_F32 && precision != WOB_F64) return WOB_E_ARG;
+  if (!verts || !prims || n_verts <= 0 || n_prims <= 0) return WOB_E_ARG;
+  if (n_prims > wob::kIdMask) return WOB_E_ARG;
+  // vertices rounded to the scene precision: both the walk and any external
+  // checker then see the same geometry
+  std::vector<double> v((size_t)(n_verts * dim));
+  for (int64_t i = 0; i < n_verts * dim; ++i) {
+    const double x = verts[i];
+    if (!std::isfinite(x)) return WOB_E_MESH;
+    v[i] = precision == WOB_F32 ? (double)(float)x : x;
+    if (!std::isfinite(v[i])) return WOB_E_MESH;
+  }
+  std::vector<wobhost::Box> boxes((size_t)n_prims);
+  int32_t nd = 0, nn = 0, nr = 0;
+  for (int64_t j = 0; j < n_prims; ++j) {
+    wobhost::Box b;
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = INFINITY;
+      b.hi[a] = -INFINITY;
+    }
+    double p[3][3] = {{0}};
+    for (int c = 0; c < dim; ++c) {
+      const int32_t ix = prims[j * dim + c];
+      if (ix < 0 || ix >= n_verts) return WOB_E_MESH;
+      for (int a = 0; a < dim; ++a) {
+        p[c][a] = v[(int64_t)ix * dim + a];
+        b.lo[a] = std::fmin(b.lo[a], p[c][a]);
+        b.hi[a] = std::fmax(b.hi[a], p[c][a]);
+      }
+    }
+    for (int a = dim; a < 3; ++a) b.lo[a] = b.hi[a] = 0.0;
+    // zero-length segment / zero-area triangle
+    if (dim == 2) {
+      if (p[0][0] == p[1][0] && p[0][1] == p[1][1]) return WOB_E_MESH;
+    } else {
+      const double e1[3] = {p[1][0] - p[0][0], p[1][1] - p[0][1], p[1][2] - p[0][2]};
+      const double e2[3] = {p[2][0] - p[0][0], p[2][1] - p[0][1], p[2][2] - p[0][2]};
+      const double c0 = e1[1] * e2[2] - e1[2] * e2[1], c1 = e1[2] * e2[0] - e1[0] * e2[2],
+                   c2 = e1[0] * e2[1] - e1[1] * e2[0];
+      if (c0 == 0.0 && c1 == 0.0 && c2 == 0.0) return WOB_E_MESH;
+    }
+    boxes[j] = b;
+    const int k = kind ? kind[j] : WOB_BC_DIRICHLET;
+    if (k == WOB_BC_DIRICHLET) ++nd;
+    else if (k == WOB_BC_NEUMANN) ++nn;
+    else if (k == WOB_BC_ROBIN) ++nr;
+    else return WOB_E_ARG;
+    if (alpha && !std::isfinite(alpha[j])) return WOB_E_ARG;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WOB_E_DEVICE;
+  wobhost::Bvh bvh = wobhost::build_bvh(dim, boxes, kMaxLeaf);
+  wob_scene_s* sc = new (std::nothrow) wob_scene_s();
+  if (!sc) return WOB_E_ALLOC;
+  sc->dim = dim;
+  sc->precision = precision;
+  sc->device = dev;
+  sc->n_prims = n_prims;
+  sc->n_nodes = (int64_t)bvh.nodes.size();
+  sc->n_leaves = bvh.n_leaves;
+  sc->depth = bvh.depth;
+  sc->max_leaf = bvh.max_leaf;
+  sc->n_dirichlet = nd;
+  sc->n_neumann = nn;
+  sc->n_robin = nr;
+  wob_status s;
+  if (precision == WOB_F32)
+    s = dim == 3 ? upload_scene<float, 3>(sc, v, prims, kind, alpha, bvh)
+                 : upload_scene<float, 2>(sc, v, prims, kind, alpha, bvh);
+  else
+    s = dim == 3 ? upload_scene<double, 3>(sc, v, prims, kind, alpha, bvh)
+                 : upload_scene<double, 2>(sc, v, prims, kind, alpha, bvh);
+  if (s != WOB_OK) {
+    wob_free(sc);
+    return s;
+  }
+  *out = sc;
+  return WOB_OK;
+}
+
+void wob_free(wob_scene sc) {
+  if (!sc) return;
+  if (sc->d_nodes) (void)hipFree(sc->d_nodes);
+  if (sc->d_prims) (void)hipFree(sc->d_prims);
+  if (sc->d_leaf_of_id) (void)hipFree(sc->d_leaf_of_id);
+  delete sc;
+}
+
+wob_status wob_get_scene_info(wob_scene sc, wob_scene_info* info) {
+  if (!sc || !info) return WOB_E_ARG;
+  std::memset(info, 0, sizeof(*info));
+  info->dim = sc->dim;
+  info->precision = sc->precision;
+  info->n_prims = sc->n_prims;
+  info->n_nodes = sc->n_nodes;
+  info->n_leaves = sc->n_leaves;
+  info->depth = sc->depth;
+  info->max_leaf = sc->max_leaf;
+  info->device_bytes = sc->device_bytes;
+  info->node_bytes = sc->node_bytes;
+  info->prim_bytes = sc->prim_bytes;
+  info->n_dirichlet = sc->n_dirichlet;
+  info->n_neumann = sc->n_neumann;
+  info->n_robin = sc->n_robin;
+  return WOB_OK;
+}
+
+int32_t wob_lines_per_path(wob_scene sc, const wob_bc* bc, int32_t walk_len) {
+  Plan pl;
+  if (plan_walk(sc, bc, 1, walk_len, &pl) != WOB_OK) return -1;
+  return pl.L;
+}
+
+wob_status wob_solve(wob_scene sc, const void* points, const int32_t* point_prim, int64_t n_points,
+                     const wob_bc* bc, int32_t samples, int32_t walk_len, uint64_t seed,
+                     void* mean_out, void* var_out, void* stream) {
+  return run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, nullptr, mean_out,
+                  var_out, nullptr, nullptr, nullptr, nullptr, MODE_SOLVE, stream);
+}
+
+wob_status wob_trace(wob_scene sc, const void* points, const int32_t* point_prim, int64_t n_points,
+                     const wob_bc* bc, int32_t samples, int32_t walk_len, uint64_t seed,
+                     const uint32_t* point_ids, void* path_out, int32_t* vtx_prim, int32_t* vtx_m,
+                     void* stream) {
+  return run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, point_ids, nullptr,
+                  nullptr, path_out, vtx_prim, vtx_m, nullptr, MODE_TRACE, stream);
+}
+
+wob_status wob_count_work(wob_scene sc, const void* points, const int32_t* point_prim,
+                          int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                          uint64_t seed, uint64_t* counters, void* stream) {
+  return run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, nullptr, nullptr,
+                  nullptr, nullptr, nullptr, nullptr, counters, MODE_COUNT, stream);
+}
+
+wob_status wob_intersect_all(wob_scene sc, const void* orig, const void* dir,
+                             const int32_t* exclude, int64_t n_lines, int32_t max_hits,
+                             int32_t* n_hits, int32_t* hit_prim, void* hit_t, void* stream) {
+  if (!sc || n_lines < 0 || max_hits < 0) return WOB_E_ARG;
+  if (n_lines == 0) return WOB_OK;
+  if (!orig || !dir || !n_hits || (max_hits > 0 && !hit_prim)) return WOB_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const dim3 grid((unsigned)((n_lines + 255) / 256)), block(256);
+  if (sc->precision == WOB_F32) {
+    if (sc->dim == 3)
+      hipLaunchKernelGGL((wob::intersect_kernel<float, 3>), grid, block, 0, st, view<float, 3>(sc),
+                         (const float*)orig, (const float*)dir, exclude, n_lines, max_hits, n_hits,
+                         hit_prim, (float*)hit_t);
+    else
+      hipLaunchKernelGGL((wob::intersect_kernel<float, 2>), grid, block, 0, st, view<float, 2>(sc),
+                         (const float*)orig, (const float*)dir, exclude, n_lines, max_hits, n_hits,
+                         hit_prim, (float*)hit_t);
+  } else {
+    if (sc->dim == 3)
+      hipLaunchKernelGGL((wob::intersect_kernel<double, 3>), grid, block, 0, st, view<double, 3>(sc),
+                         (const double*)orig, (const double*)dir, exclude, n_lines, max_hits, n_hits,
+                         hit_prim, (double*)hit_t);
+    else
+      hipLaunchKernelGGL((wob::intersect_kernel<double, 2>), grid, block, 0, st, view<double, 2>(sc),
+                         (const double*)orig, (const double*)dir, exclude, n_lines, max_hits, n_hits,
+                         hit_prim, (double*)hit_t);
+  }
+  return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
+}
+
+}  // extern "C"

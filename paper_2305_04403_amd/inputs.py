@@ -311,3 +311,82 @@ def box_points_outside(n: int, lo: float, hi: float, sdf, margin: float, seed: i
 def assign_kinds(n_prims: int, kinds: Tuple[int, ...], seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.asarray(kinds, dtype=np.uint8)[rng.integers(0, len(kinds), n_prims)]
+
+
+# ----------------------------------------------------------------------------- workloads
+
+@dataclasses.dataclass
+class Workload:
+    """One boundary value problem instance: geometry, points, data and run sizes.
+    ``bc`` holds plain values (domain, formulation, program, params) so either
+    implementation can build its own boundary-condition record from it."""
+
+    name: str
+    mesh: Mesh
+    points: np.ndarray
+    point_prim: Optional[np.ndarray]
+    bc: dict
+    samples: int
+    walk_len: int
+    precision: str            # "f32" or "f64"
+    seed: int = 0
+    exact: Optional[np.ndarray] = None   # analytic solution at the points, if known
+
+
+def _round(mesh: Mesh, points: np.ndarray, precision: str):
+    if precision == "f32":
+        return mesh.as_float32_geometry(), points.astype(np.float32).astype(np.float64)
+    return mesh, points
+
+
+def config_circle(n_points: int = 1024, samples: int = 64, walk_len: int = 4) -> Workload:
+    """2D interior Dirichlet on the unit circle as 256 segments, g = x^2 - y^2;
+    points uniform in the disk r <= 0.9; FP64."""
+    mesh = circle_polygon(256)
+    pts = disk_points(n_points, 0.9, 0)
+    return Workload("circle256-dirichlet-f64", mesh, pts, None,
+                    dict(domain=1, formulation=1, program=2, params=()), samples, walk_len, "f64",
+                    exact=pts[:, 0] ** 2 - pts[:, 1] ** 2)
+
+
+def config_icosphere_slice(res: int = 512, samples: int = 256, walk_len: int = 6,
+                           freq: int = 32) -> Workload:
+    """3D interior Dirichlet on a 20 freq^2-triangle icosphere perturbed to
+    r = 1 + 0.1 sin(3 theta) sin(4 phi); g = 1/|x - x0|, x0 = (2, 0.5, 0); the
+    cell centres of a res x res grid on z = 0 over [-1.1, 1.1]^2 that lie at
+    least 0.01 inside the smooth surface; FP32."""
+    mesh = perturb_radial(icosphere(freq), 0.1, 3, 4)
+    pts = slice_grid_inside(res, 1.1, 0.1, 3, 4, 0.01)
+    mesh, pts = _round(mesh, pts, "f32")
+    x0 = (2.0, 0.5, 0.0)
+    exact = 1.0 / np.linalg.norm(pts - np.array(x0), axis=1)
+    return Workload(f"icosphere{20 * freq * freq}-slice{res}-dirichlet-f32", mesh, pts, None,
+                    dict(domain=1, formulation=1, program=3, params=x0), samples, walk_len, "f32",
+                    exact=exact)
+
+
+def config_tori(grid_n: int = 87, n_points: int = 1_000_000, boundary_frac: float = 0.1,
+                samples: int = 512, walk_len: int = 4, alpha: float = 1.0, seed: int = 0) -> Workload:
+    """3D exterior mixed Neumann / Robin (Robin alpha) on the boundary of the union
+    of three tori (R = 1, r = 0.3, random rotations); each triangle is Neumann
+    or Robin with probability 1/2; data from the point source u = 1/|x - xs|
+    with xs on torus 0's core circle (inside Omega); evaluation points uniform in
+    [-2, 2]^3 at least 0.02 outside, plus a fraction area-uniform on the mesh."""
+    rng = np.random.default_rng(seed)
+    mesh, rots = torus_union(grid_n=grid_n, seed=seed)
+    kind = assign_kinds(mesh.n_prims, (NEUMANN, ROBIN), seed + 1)
+    mesh = dataclasses.replace(mesh, kind=kind, alpha=np.where(kind == ROBIN, alpha, 0.0))
+    xs = rots[0] @ np.array([1.0, 0.0, 0.0])
+    n_b = int(round(boundary_frac * n_points))
+    sdf = lambda p: torus_union_sdf(p, rots, 1.0, 0.3)
+    off = box_points_outside(n_points - n_b, -2.0, 2.0, sdf, 0.02, seed + 2)
+    mesh = mesh.as_float32_geometry()
+    on, on_prim = mesh_surface_points(mesh, n_b, seed + 3)
+    pts = np.concatenate([off, on]).astype(np.float32).astype(np.float64)
+    pp = np.concatenate([np.full(len(off), -1, np.int32), on_prim]).astype(np.int32)
+    perm = rng.permutation(len(pts))
+    pts, pp = pts[perm], pp[perm]
+    exact = 1.0 / np.linalg.norm(pts - xs, axis=1)
+    return Workload(f"tori{mesh.n_prims}-exterior-neumann-robin-f32", mesh, pts, pp,
+                    dict(domain=-1, formulation=3, program=3, params=tuple(xs)), samples, walk_len,
+                    "f32", exact=exact)

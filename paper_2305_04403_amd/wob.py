@@ -1,0 +1,230 @@
+"""Thin Python binding of libwob.so (argument marshalling only).
+
+Every step of the walk runs in the HIP kernels of ``libwob.so``; this module
+only turns torch device tensors into raw device pointers, passes torch's
+current HIP stream, and checks status codes.  It raises if the library is
+missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwob.so")
+
+F32, F64 = 0, 1
+AUTO, DOUBLE_LAYER, DIRECT, SINGLE_LAYER = 0, 1, 2, 3
+PROG_CONST, PROG_LINEAR, PROG_QUAD, PROG_INVDIST = 0, 1, 2, 3
+DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
+
+EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_path", "wob_solve",
+            "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string")
+
+
+class WobError(RuntimeError):
+    pass
+
+
+class _BC(C.Structure):
+    _fields_ = [("domain", C.c_int32), ("formulation", C.c_int32), ("program", C.c_int32),
+                ("reserved", C.c_int32), ("params", C.c_double * 8), ("self_panel_p", C.c_double)]
+
+
+class _SceneInfo(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("n_prims", C.c_int64),
+                ("n_nodes", C.c_int64), ("n_leaves", C.c_int64), ("depth", C.c_int32),
+                ("max_leaf", C.c_int32), ("device_bytes", C.c_int64), ("node_bytes", C.c_int64),
+                ("prim_bytes", C.c_int64), ("n_dirichlet", C.c_int32), ("n_neumann", C.c_int32),
+                ("n_robin", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libwob.so (built by ``python -m paper_2305_04403_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise WobError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_04403_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    L.wob_build_bvh.argtypes = [i32, i32, vp, i64, vp, i64, vp, vp, C.POINTER(vp)]
+    L.wob_free.argtypes = [vp]
+    L.wob_free.restype = None
+    L.wob_get_scene_info.argtypes = [vp, C.POINTER(_SceneInfo)]
+    L.wob_lines_per_path.argtypes = [vp, C.POINTER(_BC), i32]
+    L.wob_lines_per_path.restype = i32
+    L.wob_solve.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
+    L.wob_trace.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
+    L.wob_count_work.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp]
+    L.wob_intersect_all.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
+    L.wob_status_string.argtypes = [C.c_int]
+    L.wob_status_string.restype = C.c_char_p
+    for name in ("wob_build_bvh", "wob_get_scene_info", "wob_solve", "wob_trace",
+                 "wob_count_work", "wob_intersect_all"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = lib().wob_status_string(status).decode()
+        raise WobError(f"{what}: {msg} (status {status})")
+
+
+@dataclasses.dataclass
+class BC:
+    """Boundary data and formulation (mirrors ``wob_bc``)."""
+    domain: int = 1               # +1 interior, -1 exterior
+    formulation: int = AUTO
+    program: int = PROG_CONST
+    params: Sequence[float] = ()
+    self_panel_p: float = 1.0 / 16.0
+
+    def c(self) -> _BC:
+        b = _BC()
+        b.domain, b.formulation, b.program, b.reserved = self.domain, self.formulation, self.program, 0
+        for i, v in enumerate(self.params):
+            b.params[i] = float(v)
+        b.self_panel_p = float(self.self_panel_p)
+        return b
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise WobError("expected a device tensor")
+    if not t.is_contiguous():
+        raise WobError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> Optional[int]:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Scene:
+    """A boundary mesh uploaded to the current device with its line-query BVH."""
+
+    def __init__(self, mesh, precision: int = F32):
+        verts = np.ascontiguousarray(mesh.verts, dtype=np.float64)
+        prims = np.ascontiguousarray(mesh.prims, dtype=np.int32)
+        kind = None if mesh.kind is None else np.ascontiguousarray(mesh.kind, dtype=np.uint8)
+        alpha = None if mesh.alpha is None else np.ascontiguousarray(mesh.alpha, dtype=np.float64)
+        h = C.c_void_p()
+        st = lib().wob_build_bvh(int(mesh.dim), int(precision), verts.ctypes.data, verts.shape[0],
+                                 prims.ctypes.data, prims.shape[0],
+                                 None if kind is None else kind.ctypes.data,
+                                 None if alpha is None else alpha.ctypes.data, C.byref(h))
+        _check(st, "wob_build_bvh")
+        self.handle = h
+        self.dim = int(mesh.dim)
+        self.precision = int(precision)
+
+    @property
+    def dtype(self):
+        torch = _torch()
+        return torch.float32 if self.precision == F32 else torch.float64
+
+    def info(self) -> dict:
+        i = _SceneInfo()
+        _check(lib().wob_get_scene_info(self.handle, C.byref(i)), "wob_get_scene_info")
+        return {f: getattr(i, f) for f, _ in _SceneInfo._fields_ if f != "reserved"}
+
+    def lines_per_path(self, bc: BC, walk_len: int) -> int:
+        b = bc.c()
+        n = lib().wob_lines_per_path(self.handle, C.byref(b), int(walk_len))
+        if n < 0:
+            raise WobError("wob_lines_per_path: invalid arguments")
+        return n
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().wob_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
+          point_prim=None, want_var: bool = True, stream=None, out=None):
+    """Per-point mean (and variance) of ``samples`` WoB paths.  ``points`` is a
+    contiguous (P, dim) device tensor of the scene's dtype."""
+    torch = _torch()
+    P = points.shape[0]
+    if out is None:
+        mean = torch.empty(P, dtype=scene.dtype, device=points.device)
+        var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
+    else:
+        mean, var = out
+    b = bc.c()
+    st = lib().wob_solve(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
+                         int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(mean),
+                         _dev_ptr(var), _stream(stream))
+    _check(st, "wob_solve")
+    return mean, var
+
+
+def trace(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
+          point_prim=None, want_vertices: bool = True, point_ids=None, stream=None):
+    """Per-path values (P, samples) plus, optionally, the primitive picked and the
+    hit count of every line.  ``point_ids`` (uint32 stored in an int32 tensor)
+    replaces the point index used in the random-number counter."""
+    torch = _torch()
+    P = points.shape[0]
+    L = scene.lines_per_path(bc, walk_len)
+    path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
+    vp = torch.empty((P, samples, L), dtype=torch.int32, device=points.device) if want_vertices else None
+    vm = torch.empty((P, samples, L), dtype=torch.int32, device=points.device) if want_vertices else None
+    b = bc.c()
+    st = lib().wob_trace(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
+                         int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(point_ids),
+                         _dev_ptr(path), _dev_ptr(vp), _dev_ptr(vm), _stream(stream))
+    _check(st, "wob_trace")
+    return path, vp, vm
+
+
+def count_work(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
+               point_prim=None, stream=None):
+    torch = _torch()
+    c = torch.zeros(4, dtype=torch.int64, device=points.device)
+    b = bc.c()
+    st = lib().wob_count_work(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), points.shape[0],
+                              C.byref(b), int(samples), int(walk_len), C.c_uint64(seed),
+                              _dev_ptr(c), _stream(stream))
+    _check(st, "wob_count_work")
+    v = c.cpu().numpy()
+    return {"lines": int(v[0]), "nodes": int(v[1]), "prims": int(v[2]), "hits": int(v[3])}
+
+
+def intersect_all(scene: Scene, orig, dirs, exclude=None, max_hits: int = 64, stream=None):
+    torch = _torch()
+    n = orig.shape[0]
+    nh = torch.empty(n, dtype=torch.int32, device=orig.device)
+    hp = torch.full((n, max_hits), -1, dtype=torch.int32, device=orig.device)
+    ht = torch.zeros((n, max_hits), dtype=scene.dtype, device=orig.device)
+    st = lib().wob_intersect_all(scene.handle, _dev_ptr(orig), _dev_ptr(dirs), _dev_ptr(exclude), n,
+                                 int(max_hits), _dev_ptr(nh), _dev_ptr(hp), _dev_ptr(ht),
+                                 _stream(stream))
+    _check(st, "wob_intersect_all")
+    return nh, hp, ht

@@ -1,0 +1,79 @@
+"""The C-ABI library loads, exports every entry point its header declares, and
+rejects bad arguments on the host before touching a device (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2305_04403_amd import wob
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "wob.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wob_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = wob.lib()
+    names = declared()
+    assert "wob_solve" in names and "wob_build_bvh" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(wob.EXPORTED) <= set(names)
+
+
+def test_status_strings():
+    L = wob.lib()
+    assert L.wob_status_string(0) == b"ok"
+    assert L.wob_status_string(1) == b"invalid argument"
+    assert L.wob_status_string(99) == b"unknown status"
+
+
+def _build(dim, prec, verts, prims, kind=None, alpha=None):
+    L = wob.lib()
+    v = np.ascontiguousarray(verts, np.float64)
+    p = np.ascontiguousarray(prims, np.int32)
+    k = None if kind is None else np.ascontiguousarray(kind, np.uint8)
+    a = None if alpha is None else np.ascontiguousarray(alpha, np.float64)
+    h = C.c_void_p()
+    st = L.wob_build_bvh(dim, prec, v.ctypes.data, v.shape[0], p.ctypes.data, p.shape[0],
+                         None if k is None else k.ctypes.data, None if a is None else a.ctypes.data,
+                         C.byref(h))
+    return st, h
+
+
+def test_build_rejects_bad_meshes_on_host():
+    tri = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0.0]])
+    assert _build(4, 0, tri, [[0, 1, 2]])[0] == 1          # dim
+    assert _build(3, 7, tri, [[0, 1, 2]])[0] == 1          # precision
+    assert _build(3, 0, tri, [[0, 1, 3]])[0] == 4          # index out of range
+    assert _build(3, 0, tri, [[0, 1, 1]])[0] == 4          # zero area
+    assert _build(3, 0, np.array([[0, 0, 0], [1, 0, np.nan], [0, 1, 0.0]]), [[0, 1, 2]])[0] == 4
+    assert _build(2, 0, np.array([[0, 0], [0, 0.0]]), [[0, 1]])[0] == 4  # zero length
+    assert _build(3, 0, tri, [[0, 1, 2]], kind=[5])[0] == 1  # unknown kind
+    # float32 rounding can make a tiny triangle degenerate
+    tiny = np.array([[0, 0, 0], [1e-12, 0, 0], [0, 1e-12, 0.0]]) + 1.0
+    assert _build(3, 0, tiny, [[0, 1, 2]])[0] == 4
+
+
+def test_entry_points_reject_null_scene():
+    L = wob.lib()
+    bc = wob.BC().c()
+    assert L.wob_lines_per_path(None, C.byref(bc), 4) == -1
+    assert L.wob_solve(None, None, None, 0, C.byref(bc), 4, 4, 0, None, None, None) == 1
+    assert L.wob_trace(None, None, None, 0, C.byref(bc), 4, 4, 0, None, None, None, None, None) == 1
+    assert L.wob_intersect_all(None, None, None, None, 1, 4, None, None, None, None) == 1
+    assert L.wob_get_scene_info(None, None) == 1
+    L.wob_free(None)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(wob, "_lib", None)
+    monkeypatch.setattr(wob, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(wob.WobError):
+        wob.lib()

@@ -1,0 +1,287 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Per-path values and the primitive picked by every line must agree for every
+non-grazing path (see tests/parity.py for the grazing class and tolerances);
+hit lists of single lines must agree as sets.  Inputs are seeded and synthetic.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_04403_amd import inputs as I
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def W():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_04403_amd import wob
+    wob.lib()
+    return wob
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def obc(bc: dict, self_p=1.0 / 16.0):
+    return oracle.make_bc(bc["domain"], bc["formulation"], bc["program"], bc["params"], self_p)
+
+
+def wbc(W, bc: dict, self_p=1.0 / 16.0):
+    return W.BC(bc["domain"], bc["formulation"], bc["program"], tuple(bc["params"]), self_p)
+
+
+def run_trace_parity(W, mesh, pts, pp, bc, N, M, seed, precision, max_vertex_mismatch_frac=0.0):
+    scene = W.Scene(mesh, W.F32 if precision == "f32" else W.F64)
+    dt = torch.float32 if precision == "f32" else torch.float64
+    tp = dev(pts, dt)
+    tpp = None if pp is None else dev(pp, torch.int32)
+    val, vprim, vm = W.trace(scene, tp, wbc(W, bc), N, M, seed, point_prim=tpp)
+    torch.cuda.synchronize()
+    om = oracle.OracleMesh(mesh)
+    orc = PT.oracle_all_paths(om, pts, pp, obc(bc), N, M, seed)
+    L = orc["vtx_prim"].shape[1]
+    res = PT.compare_paths(orc, val.cpu().double().numpy().reshape(-1),
+                           vprim.cpu().numpy().reshape(-1, L), vm.cpu().numpy().reshape(-1, L),
+                           PT.RTOL_F32 if precision == "f32" else PT.RTOL_F64)
+    print(res.summary(), flush=True)
+    assert res.n_graze <= 0.01 * res.n
+    assert res.n_vertex_mismatch <= max_vertex_mismatch_frac * res.n_checked
+    assert res.n_value_mismatch <= max_vertex_mismatch_frac * res.n_checked
+    scene.close()
+    return res
+
+
+# ------------------------------------------------------------------- hit lists
+
+@pytest.mark.parametrize("shape", ["sphere-f32", "tori-f32", "circle-f64"])
+def test_intersect_all_matches_brute_force(W, shape):
+    rng = np.random.default_rng(3)
+    if shape == "sphere-f32":
+        mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(10), 0.1, 3, 4))
+        prec, dt = W.F32, torch.float32
+    elif shape == "tori-f32":
+        mesh = PT.f32_mesh(I.torus_union(grid_n=24, seed=2)[0])
+        prec, dt = W.F32, torch.float32
+    else:
+        mesh = I.circle_polygon(256)
+        prec, dt = W.F64, torch.float64
+    dim = mesh.dim
+    n = 3000
+    orig = rng.uniform(-1.5, 1.5, (n, dim))
+    # a third of the lines start on the boundary and exclude their own primitive
+    bp = rng.integers(0, mesh.n_prims, n // 3)
+    v = mesh.verts[mesh.prims[bp]]
+    w = rng.dirichlet(np.ones(dim), n // 3)
+    orig[: n // 3] = np.einsum("nk,nkd->nd", w, v)
+    excl = np.full(n, -1, np.int32)
+    excl[: n // 3] = bp
+    d = rng.standard_normal((n, dim))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    if prec == W.F32:
+        orig, d = PT.f32(orig), PT.f32(d)
+    scene = W.Scene(mesh, prec)
+    nh, hp, ht = W.intersect_all(scene, dev(orig, dt), dev(d, dt), dev(excl, torch.int32), max_hits=32)
+    torch.cuda.synchronize()
+    nh, hp, ht = nh.cpu().numpy(), hp.cpu().numpy(), ht.cpu().double().numpy()
+    om = oracle.OracleMesh(mesh)
+    o = oracle.intersect_all(om, orig, d, excl, max_hits=32)
+    ok = o["graze"] >= PT.GRAZE
+    assert ok.mean() > 0.99
+    assert np.all(o["n_hits"] <= 32)
+    np.testing.assert_array_equal(nh[ok], o["n_hits"][ok])
+    for l in np.nonzero(ok)[0]:
+        k = nh[l]
+        gi = np.argsort(hp[l, :k])
+        oi = np.argsort(o["prim"][l, :k])
+        assert np.array_equal(hp[l, :k][gi], o["prim"][l, :k][oi]), l
+        tol = 1e-5 * (1 + np.abs(o["t"][l, :k][oi])) if prec == W.F32 else 1e-12
+        assert np.all(np.abs(ht[l, :k][gi] - o["t"][l, :k][oi]) <= tol * 10), l
+    scene.close()
+
+
+# ------------------------------------------------------------------- per-path parity
+
+def test_trace_parity_circle_fp64_full_config(W):
+    """2D interior Dirichlet on the 256-gon, FP64, at its full size
+    (1024 points x 64 paths, M = 4)."""
+    w = I.config_circle()
+    res = run_trace_parity(W, w.mesh, w.points, None, w.bc, w.samples, w.walk_len, 0, "f64")
+    assert res.n_checked == res.n - res.n_graze
+
+
+def test_trace_parity_dirichlet_3d_f32(W):
+    """3D interior Dirichlet, perturbed icosphere, FP32, M = 6, ragged sizes
+    (P not a multiple of the points per block, N = 100 not a multiple of 64)."""
+    mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(12), 0.1, 3, 4))
+    pts = PT.f32(I.ball_points(77, 0.8, 5))
+    bc = dict(domain=1, formulation=1, program=3, params=(2.0, 0.5, 0.0))
+    run_trace_parity(W, mesh, pts, None, bc, 100, 6, 11, "f32", max_vertex_mismatch_frac=0.002)
+
+
+def test_trace_parity_direct_neumann_exterior(W):
+    """3D exterior Neumann, direct BIE (M + 1 lines, all-hits source), with
+    points both off and on the boundary."""
+    s = I.icosphere(8)
+    mesh = PT.f32_mesh(I.Mesh(3, s.verts, s.prims, np.full(s.n_prims, 1, np.uint8), None))
+    off = I.ball_points(40, 2.5, 1, r_min=1.2)
+    on, onp = I.mesh_surface_points(mesh, 24, 2)
+    pts = PT.f32(np.concatenate([off, on]))
+    pp = np.concatenate([np.full(40, -1), onp]).astype(np.int32)
+    bc = dict(domain=-1, formulation=2, program=3, params=(0.2, -0.1, 0.1))
+    run_trace_parity(W, mesh, pts, pp, bc, 64, 4, 3, "f32", max_vertex_mismatch_frac=0.002)
+
+
+def test_trace_parity_single_layer_mixed_tori(W):
+    """3D exterior Neumann / Robin (alpha = 1) single layer on the tori union,
+    with boundary points (self-panel mixture at step 0 and at Robin vertices)."""
+    w = I.config_tori(grid_n=24, n_points=96, samples=64, walk_len=4)
+    run_trace_parity(W, w.mesh, w.points, w.point_prim, w.bc, 64, 4, 5, "f32",
+                     max_vertex_mismatch_frac=0.002)
+
+
+def test_trace_parity_interior_single_layer_2d_f64(W):
+    """2D interior Robin single layer in FP64 (segment self-panel, log kernels)."""
+    m = I.circle_polygon(96)
+    mesh = I.Mesh(2, m.verts, m.prims, np.full(96, 2, np.uint8), np.full(96, 0.5))
+    pts = I.disk_points(40, 0.8, 9)
+    s = np.random.default_rng(1).random(10)
+    bp = np.arange(10, dtype=np.int32) * 7
+    on = m.verts[m.prims[bp, 0]] + s[:, None] * (m.verts[m.prims[bp, 1]] - m.verts[m.prims[bp, 0]])
+    pts = np.concatenate([pts, on])
+    pp = np.concatenate([np.full(40, -1), bp]).astype(np.int32)
+    bc = dict(domain=1, formulation=3, program=2, params=())
+    run_trace_parity(W, mesh, pts, pp, bc, 64, 3, 2, "f64")
+
+
+# ------------------------------------------------------------------- solve
+
+def test_solve_mean_var_equal_trace_statistics(W):
+    mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(8), 0.1, 3, 4))
+    pts = PT.f32(I.ball_points(133, 0.8, 5))
+    bc = dict(domain=1, formulation=1, program=3, params=(2.0, 0.5, 0.0))
+    scene = W.Scene(mesh, W.F32)
+    tp = dev(pts, torch.float32)
+    for N in (1, 63, 64, 100, 256, 300):
+        mean, var = W.solve(scene, tp, wbc(W, bc), N, 5, 7, want_var=N > 1)
+        val, _, _ = W.trace(scene, tp, wbc(W, bc), N, 5, 7, want_vertices=False)
+        torch.cuda.synchronize()
+        v = val.cpu().double().numpy()
+        np.testing.assert_allclose(mean.cpu().numpy(), v.mean(axis=1), rtol=2e-6, atol=2e-6)
+        if N > 1:
+            np.testing.assert_allclose(var.cpu().numpy(), v.var(axis=1, ddof=1), rtol=2e-5, atol=1e-6)
+    scene.close()
+
+
+def test_solve_matches_oracle_mean(W):
+    w = I.config_circle(n_points=128, samples=256)
+    scene = W.Scene(w.mesh, W.F64)
+    mean, var = W.solve(scene, dev(w.points, torch.float64), wbc(W, w.bc), 256, 4, 0)
+    torch.cuda.synchronize()
+    om = oracle.OracleMesh(w.mesh)
+    m_o, v_o = oracle.solve(om, w.points, None, obc(w.bc), 256, 4, 0)
+    np.testing.assert_allclose(mean.cpu().numpy(), m_o, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(var.cpu().numpy(), v_o, rtol=1e-9, atol=1e-11)
+    scene.close()
+
+
+def test_full_size_icosphere_slice_sampled(W):
+    """The full 3D Dirichlet workload (20,480 triangles, ~168k slice points,
+    256 paths, M = 6) in the benchmark's launch configuration; at 12 sampled
+    points the paths are re-traced with their original random-number indices
+    and compared path by path with the oracle, and the solve's mean there must
+    equal the traced paths' mean."""
+    w = I.config_icosphere_slice()
+    scene = W.Scene(w.mesh, W.F32)
+    tp = dev(w.points, torch.float32)
+    mean, var = W.solve(scene, tp, wbc(W, w.bc), w.samples, w.walk_len, w.seed)
+    torch.cuda.synchronize()
+    assert torch.isfinite(mean).all() and torch.isfinite(var).all()
+    rng = np.random.default_rng(0)
+    ids = np.sort(rng.choice(w.points.shape[0], 12, replace=False)).astype(np.int64)
+    sub = w.points[ids]
+    val, vprim, vm = W.trace(scene, dev(sub, torch.float32), wbc(W, w.bc), w.samples, w.walk_len,
+                             w.seed, point_ids=dev(ids.astype(np.int32), torch.int32))
+    torch.cuda.synchronize()
+    v = val.cpu().double().numpy()
+    np.testing.assert_allclose(mean.cpu().numpy()[ids], v.mean(axis=1), rtol=2e-6, atol=2e-6)
+    om = oracle.OracleMesh(w.mesh)
+    orc = PT.oracle_all_paths(om, sub, None, obc(w.bc), w.samples, w.walk_len, w.seed, point_ids=ids)
+    L = orc["vtx_prim"].shape[1]
+    res = PT.compare_paths(orc, v.reshape(-1), vprim.cpu().numpy().reshape(-1, L),
+                           vm.cpu().numpy().reshape(-1, L), PT.RTOL_F32)
+    print(res.summary(), flush=True)
+    assert res.n_graze <= 0.01 * res.n
+    assert res.n_vertex_mismatch <= 0.002 * res.n_checked
+    assert res.n_value_mismatch <= 0.002 * res.n_checked
+    # and the estimate itself: within 5 SE + 1% of the analytic solution on average
+    se = np.sqrt(var.cpu().double().numpy() / w.samples)
+    z = (mean.cpu().double().numpy() - w.exact) / np.maximum(se, 1e-12)
+    assert abs(np.mean(z)) < 0.2
+    scene.close()
+
+
+# ------------------------------------------------------------------- edge cases
+
+def test_edge_cases(W):
+    mesh = PT.f32_mesh(I.icosphere(4))
+    scene = W.Scene(mesh, W.F32)
+    bc = W.BC(1, W.AUTO, W.PROG_CONST, (1.0,))
+    empty = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    m, v = W.solve(scene, empty, bc, 8, 3)
+    assert m.numel() == 0
+    pts = dev(PT.f32(I.ball_points(5, 0.5, 1)), torch.float32)
+    # constant data: the double layer reproduces it exactly on every path (lambda_0 = -1)
+    for M in (1, 2, 3, 7):
+        m, v = W.solve(scene, pts, bc, 64, M)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(m.cpu().numpy(), 1.0, atol=1e-5)
+        np.testing.assert_allclose(v.cpu().numpy(), 0.0, atol=1e-8)
+    # variance with one sample is an argument error
+    with pytest.raises(W.WobError):
+        W.solve(scene, pts, bc, 1, 3)
+    # out-of-range boundary ids give NaN, not a fault
+    bad = dev(np.array([0, -1, 10 ** 6, -5, 3], np.int32), torch.int32)
+    m, _ = W.solve(scene, pts, bc, 8, 2, point_prim=bad, want_var=False)
+    torch.cuda.synchronize()
+    mm = m.cpu().numpy()
+    assert np.isnan(mm[2]) and np.isnan(mm[3]) and np.isfinite(mm[1])
+    # Dirichlet mixed with Neumann is not supported
+    mixed = I.Mesh(3, mesh.verts, mesh.prims, np.array([0, 1] * (mesh.n_prims // 2), np.uint8))
+    s2 = W.Scene(mixed, W.F32)
+    with pytest.raises(W.WobError):
+        W.solve(s2, pts, bc, 8, 2)
+    s2.close()
+    scene.close()
+
+
+def test_deterministic_and_seeded(W):
+    mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(6), 0.1, 3, 4))
+    scene = W.Scene(mesh, W.F32)
+    pts = dev(PT.f32(I.ball_points(64, 0.7, 3)), torch.float32)
+    bc = W.BC(1, W.AUTO, W.PROG_LINEAR, (1.0, 0.0, 0.0, 0.0))
+    a = W.solve(scene, pts, bc, 128, 4, seed=5)[0].cpu()
+    b = W.solve(scene, pts, bc, 128, 4, seed=5)[0].cpu()
+    c = W.solve(scene, pts, bc, 128, 4, seed=6)[0].cpu()
+    assert torch.equal(a, b)
+    assert not torch.equal(a, c)
+    scene.close()
+
+
+def test_work_counters(W):
+    mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(8), 0.1, 3, 4))
+    scene = W.Scene(mesh, W.F32)
+    pts = dev(PT.f32(I.ball_points(50, 0.7, 3)), torch.float32)
+    bc = W.BC(1, W.AUTO, W.PROG_CONST, (1.0,))
+    c = W.count_work(scene, pts, bc, 64, 4)
+    # a closed surface meets every line through an interior or boundary point
+    assert c["lines"] == 50 * 64 * 4
+    assert c["hits"] >= c["lines"]
+    assert c["nodes"] > c["lines"] and c["prims"] >= c["hits"]
+    scene.close()
