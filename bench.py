@@ -35,7 +35,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--cpu-sample-points", type=int, default=96)
+    p.add_argument("--cpu-sample-points", type=int, default=640)
     p.add_argument("--skip-cpu-baseline", action="store_true")
     return p.parse_args()
 

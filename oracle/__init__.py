@@ -33,7 +33,8 @@ class _BC(C.Structure):
 
 class _TraceOut(C.Structure):
     _fields_ = [("value", C.c_void_p), ("abs_sum", C.c_void_p), ("graze", C.c_void_p),
-                ("vtx_prim", C.c_void_p), ("vtx_m", C.c_void_p), ("vtx_pos", C.c_void_p)]
+                ("cond_cos", C.c_void_p), ("vtx_prim", C.c_void_p), ("vtx_m", C.c_void_p),
+                ("vtx_pos", C.c_void_p)]
 
 
 _lib = None
@@ -140,12 +141,13 @@ def trace(mesh: OracleMesh, points: np.ndarray, point_prim: Optional[np.ndarray]
     ik = np.ascontiguousarray(item_path, dtype=np.int64)
     n = ip.shape[0]
     L = lines_per_path(mesh, bc, walk_len)
-    out = {"value": np.zeros(n), "abs_sum": np.zeros(n), "graze": np.zeros(n),
+    out = {"value": np.zeros(n), "abs_sum": np.zeros(n), "graze": np.zeros(n), "cond_cos": np.zeros(n),
            "vtx_prim": np.zeros((n, L), dtype=np.int32), "vtx_m": np.zeros((n, L), dtype=np.int32)}
     if want_pos:
         out["vtx_pos"] = np.zeros((n, L, mesh.dim))
     t = _TraceOut(_ptr(out["value"]), _ptr(out["abs_sum"]), _ptr(out["graze"]),
-                  _ptr(out["vtx_prim"]), _ptr(out["vtx_m"]), _ptr(out.get("vtx_pos")))
+                  _ptr(out["cond_cos"]), _ptr(out["vtx_prim"]), _ptr(out["vtx_m"]),
+                  _ptr(out.get("vtx_pos")))
     rc = lib().orc_trace(mesh.ref, _ptr(pts), _ptr(pp), C.c_int64(pts.shape[0]), C.byref(bc),
                          C.c_int(walk_len), C.c_uint64(seed), C.c_uint32(problem), C.c_int64(n),
                          _ptr(ip), _ptr(ik), C.byref(t), C.c_int(n_threads))

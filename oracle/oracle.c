@@ -367,6 +367,8 @@ typedef struct {
   uint32_t sel_key;
   double sel_y[3];
   double src;            /* sum over hits of G(x,y) q(y) / p_all(y) (direct Neumann) */
+  double src_abs;        /* sum over hits of |G(x,y) q(y) / p_all(y)| */
+  double src_cos;        /* smallest |cos theta_y| among the source hits */
   double graze;          /* min over primitives of |margin| * cos */
 } line_hits;
 
@@ -378,6 +380,8 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
   h->sel = -1;
   h->sel_key = 0xffffffffu;
   h->src = 0.0;
+  h->src_abs = 0.0;
+  h->src_cos = INFINITY;
   h->graze = INFINITY;
   for (int64_t j = 0; j < m->n_prims; ++j) {
     if (j == exclude) continue;
@@ -401,7 +405,10 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
          weighted by 1 / p_all with p_all the density without the 1/m factor */
       const double* ny = normals + 3 * j;
       double q = orc_boundary_datum(m, bc, j, y);
-      h->src += G(x, y, m->dim) * q / line_pdf(x, y, ny, 1, m->dim);
+      double term = G(x, y, m->dim) * q / line_pdf(x, y, ny, 1, m->dim);
+      h->src += term;
+      h->src_abs += fabs(term);
+      if (cosv < h->src_cos) h->src_cos = cosv;
     }
   }
 }
@@ -410,7 +417,7 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
 /* One path (point p, path k).                                                */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-  double value, abs_sum, graze;
+  double value, abs_sum, graze, cond_cos;
 } path_result;
 
 static path_result one_path(const orc_mesh* m, const double* normals, const orc_bc* bc,
@@ -420,7 +427,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
   const int dim = m->dim;
   const double phi = (double)bc->domain;
   const int L = form == ORC_DIRECT ? M + 1 : M;
-  path_result res = {0.0, 0.0, INFINITY};
+  path_result res = {0.0, 0.0, INFINITY, INFINITY};
   for (int i = 0; i < L; ++i) {
     if (vprim) vprim[i] = -1;
     if (vm) vm[i] = 0;
@@ -437,7 +444,9 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
 
   double x[3] = {x0[0], x0[1], dim == 3 ? x0[2] : 0.0};
   int64_t cur = prim0;
-  double W = 1.0, acc = 0.0, abs_sum = 0.0;
+  /* abs_sum: the same sum with every factor and summand replaced by its
+     magnitude (the scale of the rounding error of the sum) */
+  double W = 1.0, acc = 0.0, abs_sum = 0.0, Wabs = 1.0;
 
   for (int i = 0; i < L; ++i) {
     const int on_gamma = cur >= 0;
@@ -466,7 +475,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
 
     double y[3] = {0.0, 0.0, 0.0};
     int64_t next = -1;
-    double w;
+    double w, wabs;
     if (use_self) {
       uint32_t r1[4];
       draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
@@ -475,6 +484,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
         w = gp / bc->self_p; /* u = int G mu */
       else
         w = -2.0 * phi * prim_alpha(m, cur) * gp / bc->self_p; /* -2 phi alpha G */
+      wabs = fabs(w);
       next = cur;
       if (vprim) vprim[i] = (int32_t)(-2 - cur);
       if (vm) vm[i] = 0;
@@ -490,7 +500,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
       if (form == ORC_DIRECT) {
         /* source integral of the direct BIE: phi int G q off the boundary,
            2 phi int G q on it (Table 1, Neumann rows) */
-        double S;
+        double S, Sabs;
         if (on_gamma) {
           uint32_t r1[4];
           double ys[3];
@@ -498,12 +508,15 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
           double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), ys);
           double own = gp * orc_boundary_datum(m, bc, cur, ys);
           S = 2.0 * phi * (h.src + own);
+          Sabs = 2.0 * (h.src_abs + fabs(own));
         } else {
           S = phi * h.src;
+          Sabs = h.src_abs;
         }
+        if (h.src_cos < res.cond_cos) res.cond_cos = h.src_cos;
         double term = W * S * (last ? 0.5 : 1.0);
         acc += term;
-        abs_sum += fabs(term);
+        abs_sum += Wabs * Sabs * (last ? 0.5 : 1.0);
         if (last) break;
       }
       if (h.m == 0) break;
@@ -511,26 +524,41 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
       next = h.sel;
       const double* ny = normals + 3 * next;
       double p = line_pdf(x, y, ny, h.m, dim);
-      double kern;
+      double kern, kabs;
       if (form == ORC_DOUBLE_LAYER) {
         kern = (i == 0 && !on_gamma) ? -dG_dny(x, y, ny, dim)          /* u = -int dG/dny nu */
                                      : 2.0 * phi * dG_dny(x, y, ny, dim); /* nu = 2 phi int dG/dny nu + ... */
+        kabs = fabs(kern);
       } else if (form == ORC_DIRECT) {
         kern = on_gamma ? -2.0 * phi * dG_dny(x, y, ny, dim) /* boundary row */
                         : -phi * dG_dny(x, y, ny, dim);      /* interior / exterior row */
+        kabs = fabs(kern);
       } else {
         if (i == 0) {
           kern = G(x, y, dim); /* u = int G mu */
+          kabs = fabs(kern);
         } else {
           const double* nx = normals + 3 * cur;
           kern = -2.0 * phi * (dG_dnx(x, y, nx, dim) + prim_alpha(m, cur) * G(x, y, dim));
+          kabs = 2.0 * (fabs(dG_dnx(x, y, nx, dim)) + fabs(prim_alpha(m, cur) * G(x, y, dim)));
+        }
+        /* the single-layer weight carries 1 / |cos theta_y| */
+        {
+          double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+          double cy = fabs(dot(r, ny, dim)) / sqrt(dot(r, r, dim));
+          if (cy < res.cond_cos) res.cond_cos = cy;
         }
       }
       w = kern / p;
-      if (mixture) w /= (1.0 - bc->self_p);
+      wabs = kabs / p;
+      if (mixture) {
+        w /= (1.0 - bc->self_p);
+        wabs /= (1.0 - bc->self_p);
+      }
     }
 
     W *= w;
+    Wabs *= wabs;
     memcpy(x, y, sizeof(x));
     cur = next;
     if (vpos)
@@ -541,9 +569,8 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
          (Sec. 4.1.2, modified Neumann series) */
       double s = orc_boundary_datum(m, bc, cur, x);
       double e = (i + 1 < M ? 2.0 : 1.0) * phi * s;
-      double term = W * e;
-      acc += term;
-      abs_sum += fabs(term);
+      acc += W * e;
+      abs_sum += Wabs * fabs(e);
     }
   }
   res.value = acc;
@@ -593,6 +620,7 @@ int orc_trace(const orc_mesh* m, const double* points, const int32_t* point_prim
     if (out->value) out->value[it] = r.value;
     if (out->abs_sum) out->abs_sum[it] = r.abs_sum;
     if (out->graze) out->graze[it] = r.graze;
+    if (out->cond_cos) out->cond_cos[it] = r.cond_cos;
   }
   free(normals);
   return 0;

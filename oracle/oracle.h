@@ -63,8 +63,11 @@ typedef struct {
 /* Per (point, path) record produced by orc_trace. Arrays may be NULL. */
 typedef struct {
   double* value;           /* [n_items] per-path estimate u_hat */
-  double* abs_sum;         /* [n_items] sum of |terms| (scale for relative tolerances) */
+  double* abs_sum;         /* [n_items] the path sum with every factor and summand replaced
+                              by its magnitude (scale for relative tolerances) */
   double* graze;           /* [n_items] min over lines of |barycentric margin|*|cos| */
+  double* cond_cos;        /* [n_items] smallest |cos theta_y| entering a 1/|cos| factor
+                              (direct source hits, single-layer weights); inf if none */
   int32_t* vtx_prim;       /* [n_items * L] selected primitive per line, -1 none, -2-p self-panel */
   int32_t* vtx_m;          /* [n_items * L] number of hits per line */
   double* vtx_pos;         /* [n_items * L * dim] vertex reached by each line */

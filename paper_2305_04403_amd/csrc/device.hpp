@@ -35,6 +35,7 @@ template <typename R, int D>
 struct SceneView {
   const typename Rec<R, D>::Node* nodes;
   const typename Rec<R, D>::Prim* prims;
+  const R* normals;           // 4 per primitive (leaf order): unit outward normal, 0
   const int32_t* leaf_of_id;  // caller id -> leaf-order index
   int32_t n_nodes;
   int32_t n_prims;
@@ -144,17 +145,25 @@ __device__ __forceinline__ PrimGeo<R> load_prim(const SceneView<R, D>& s, int32_
   return g;
 }
 
-// Unit normal pointing out of Omega.
+// Unit normal pointing out of Omega.  Computed on the host in binary64 from
+// the rounded vertices and stored once: the cross product of two short edges
+// of a sliver triangle is too ill-conditioned to normalise in binary32.
 template <typename R, int D>
-__device__ __forceinline__ void prim_normal(const PrimGeo<R>& g, R n[3]) {
+__device__ __forceinline__ void load_normal(const SceneView<R, D>& s, int32_t idx, R n[3]) {
+  const R* p = s.normals + 4 * (int64_t)idx;
+  n[0] = p[0];
+  n[1] = p[1];
+  n[2] = D == 3 ? p[2] : (R)0;
+}
+
+// Orientation only: a vector along the outward normal, not normalised.
+template <typename R, int D>
+__device__ __forceinline__ void normal_dir(const PrimGeo<R>& g, R n[3]) {
   if constexpr (D == 3) {
     cross3(g.e1, g.e2, n);
-    const R il = rsqrt_<R>(dot3(n, n));
-    n[0] *= il; n[1] *= il; n[2] *= il;
   } else {
-    const R il = rsqrt_<R>(g.e1[0] * g.e1[0] + g.e1[1] * g.e1[1]);
-    n[0] = g.e1[1] * il;
-    n[1] = -g.e1[0] * il;
+    n[0] = g.e1[1];
+    n[1] = -g.e1[0];
     n[2] = 0;
   }
 }
@@ -201,12 +210,11 @@ __device__ __forceinline__ void program_eval(const ProgramView<R>& g, const R y[
 }
 
 template <typename R, int D>
-__device__ __forceinline__ R boundary_datum(const ProgramView<R>& prog, const PrimGeo<R>& g, const R y[3]) {
+__device__ __forceinline__ R boundary_datum(const ProgramView<R>& prog, const PrimGeo<R>& g,
+                                            const R n[3], const R y[3]) {
   R u, grad[3];
   program_eval<R, D>(prog, y, u, grad);
   if (g.kind == K_DIRICHLET) return u;
-  R n[3];
-  prim_normal<R, D>(g, n);
   const R q = dot3(n, grad);
   return g.kind == K_NEUMANN ? q : q + g.alpha * u;
 }
@@ -217,10 +225,10 @@ __device__ __forceinline__ R boundary_datum(const ProgramView<R>& prog, const Pr
 // 2D, y uniform on the segment: G/p = -L ln|y - x| / (2 pi).
 // --------------------------------------------------------------------------
 template <typename R, int D>
-__device__ __forceinline__ R self_panel(const PrimGeo<R>& g, const R x[3], R u0, R u1, R y[3]) {
+__device__ __forceinline__ R self_panel(const PrimGeo<R>& g, const R n[3], const R x[3], R u0, R u1,
+                                        R y[3]) {
   if constexpr (D == 3) {
-    R n[3], t1[3], t2[3];
-    prim_normal<R, D>(g, n);
+    R t1[3], t2[3];
     const R il = rsqrt_<R>(dot3(g.e1, g.e1));
     t1[0] = g.e1[0] * il; t1[1] = g.e1[1] * il; t1[2] = g.e1[2] * il;
     cross3(n, t1, t2);
@@ -274,6 +282,7 @@ struct HitAcc {
   uint32_t key;
   int32_t id, idx;
   R u, v;     // barycentric coordinates of the selected hit
+  R t;        // its line parameter: y - x = t d, so rhat = sign(t) d and rho = |t|
   R src;      // direct BIE: sum over hits of G q / p_all
 };
 
@@ -362,7 +371,7 @@ __device__ __forceinline__ void trace_line(const SceneView<R, D>& s, const Progr
   h.key = 0xffffffffu;
   h.id = 0x7fffffff;
   h.idx = -1;
-  h.u = h.v = 0;
+  h.u = h.v = h.t = 0;
   h.src = 0;
   if (COUNT) wc.lines += 1;
   int32_t i = 0;
@@ -393,18 +402,20 @@ __device__ __forceinline__ void trace_line(const SceneView<R, D>& s, const Progr
             h.idx = j;
             h.u = u;
             h.v = v;
+            h.t = t;
           }
         }
         if (source) {
           R y[3], n[3];
           hit_point(g, u, v, y);
-          prim_normal<R, D>(g, n);
+          load_normal<R, D>(s, j, n);
           R uu, grad[3];
           program_eval<R, D>(prog, y, uu, grad);
           const R q = dot3(n, grad);
-          const R r[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
-          const R rho = sqrt(dot3(r, r));
-          const R ac = fabs(dot3(r, n)) / rho;  // |cos theta_y|
+          // y - x = t d: distance and cosine from the line itself, free of the
+          // cancellation in y - x when the hit is close to x
+          const R rho = fabs(t);
+          const R ac = fabs(dot3(d, n));  // |cos theta_y|
           // G q / p_all: 3D rho q / (2 |c|); 2D -rho ln(rho) q / (2 |c|)
           const R gp = D == 3 ? rho / ((R)2 * ac) : -rho * log(rho) / ((R)2 * ac);
           h.src += gp * q;

@@ -66,7 +66,8 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
   if (FORM == F_DL && cur_idx >= 0) {
     // Table 1: on the boundary the Dirichlet solution is the given value
     const PrimGeo<R> g = load_prim<R, D>(a.scene, cur_idx);
-    return boundary_datum<R, D>(a.prog, g, x);
+    const R nz[3] = {0, 0, 0};
+    return boundary_datum<R, D>(a.prog, g, nz, x);
   }
   R W = 1, acc = 0;
   const uint32_t zbase = a.problem << 24;
@@ -77,7 +78,11 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
     R d[3];
     direction<R, D>(r0.x, r0.y, d);
     PrimGeo<R> gc;
-    if (on_gamma && (FORM != F_DL)) gc = load_prim<R, D>(a.scene, cur_idx);
+    R nc[3];
+    if (on_gamma && (FORM != F_DL)) {
+      gc = load_prim<R, D>(a.scene, cur_idx);
+      load_normal<R, D>(a.scene, cur_idx, nc);
+    }
     bool mixture = false, use_self = false;
     if constexpr (FORM == F_SL) {
       mixture = on_gamma && (i == 0 || gc.kind == K_ROBIN);
@@ -87,7 +92,7 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
     int32_t next_idx;
     if (use_self) {
       const U4 r1 = philox(path, point, z | 1u, 0u, a.k0, a.k1);
-      const R gp = self_panel<R, D>(gc, x, unit<R>(r1.x), unit<R>(r1.y), y);
+      const R gp = self_panel<R, D>(gc, nc, x, unit<R>(r1.x), unit<R>(r1.y), y);
       w = (i == 0 ? gp : (R)-2 * phi * gc.alpha * gp) / a.self_p;
       next_idx = cur_idx;
       if (TRACE && vprim) vprim[i] = -2 - gc.id;
@@ -107,8 +112,8 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
         if (on_gamma) {
           const U4 r1 = philox(path, point, z | 1u, 0u, a.k0, a.k1);
           R ys[3];
-          const R gp = self_panel<R, D>(gc, x, unit<R>(r1.x), unit<R>(r1.y), ys);
-          S = (R)2 * phi * (h.src + gp * boundary_datum<R, D>(a.prog, gc, ys));
+          const R gp = self_panel<R, D>(gc, nc, x, unit<R>(r1.x), unit<R>(r1.y), ys);
+          S = (R)2 * phi * (h.src + gp * boundary_datum<R, D>(a.prog, gc, nc, ys));
         } else {
           S = phi * h.src;
         }
@@ -118,26 +123,27 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
       if (h.m == 0) break;
       const PrimGeo<R> gy = load_prim<R, D>(a.scene, h.idx);
       hit_point(gy, h.u, h.v, y);
-      R ny[3];
-      prim_normal<R, D>(gy, ny);
-      const R r[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+      // y - x = t d: the unit direction to the hit is sign(t) d and rho = |t|
+      const R sgn_t = h.t > (R)0 ? (R)1 : (R)-1;
       const R mm = (R)h.m;
-      if constexpr (FORM == F_DL) {
-        const R sg = dot3(r, ny) > (R)0 ? (R)1 : (R)-1;
-        w = (i == 0 && !on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
-      } else if constexpr (FORM == F_DIRECT) {
-        const R sg = dot3(r, ny) > (R)0 ? (R)1 : (R)-1;
-        w = on_gamma ? phi * mm * sg : (R)0.5 * phi * mm * sg;
+      if constexpr (FORM == F_DL || FORM == F_DIRECT) {
+        R nd[3];
+        normal_dir<R, D>(gy, nd);
+        const R sg = sgn_t * dot3(d, nd) > (R)0 ? (R)1 : (R)-1;  // sgn(cos theta_y)
+        if constexpr (FORM == F_DL)
+          w = (i == 0 && !on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
+        else
+          w = on_gamma ? phi * mm * sg : (R)0.5 * phi * mm * sg;
       } else {
-        const R rho = sqrt(dot3(r, r));
-        const R acy = fabs(dot3(r, ny)) / rho;
+        R ny[3];
+        load_normal<R, D>(a.scene, h.idx, ny);
+        const R rho = fabs(h.t);
+        const R acy = fabs(dot3(d, ny));
         if (i == 0) {
           // G / p
           w = D == 3 ? mm * rho / ((R)2 * acy) : -mm * rho * log(rho) / ((R)2 * acy);
         } else {
-          R nx[3];
-          prim_normal<R, D>(gc, nx);
-          const R cx = dot3(r, nx) / rho;
+          const R cx = sgn_t * dot3(d, nc);
           w = D == 3 ? -phi * mm * (cx + gc.alpha * rho) / acy
                      : -phi * mm * (cx - gc.alpha * rho * log(rho)) / acy;
         }
@@ -152,7 +158,9 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
     cur_idx = next_idx;
     if constexpr (FORM != F_DIRECT) {
       const PrimGeo<R> gn = load_prim<R, D>(a.scene, cur_idx);
-      const R s = boundary_datum<R, D>(a.prog, gn, x);
+      R nn[3] = {0, 0, 0};
+      if (FORM != F_DL) load_normal<R, D>(a.scene, cur_idx, nn);
+      const R s = boundary_datum<R, D>(a.prog, gn, nn, x);
       acc += W * ((i + 1 < a.M) ? (R)2 * phi : phi) * s;
     }
   }

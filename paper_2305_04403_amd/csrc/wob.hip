@@ -17,6 +17,7 @@ struct wob_scene_s {
   int32_t depth = 0, max_leaf = 0;
   void* d_nodes = nullptr;
   void* d_prims = nullptr;
+  void* d_normals = nullptr;
   int32_t* d_leaf_of_id = nullptr;
   int64_t node_bytes = 0, prim_bytes = 0, device_bytes = 0;
   int32_t n_dirichlet = 0, n_neumann = 0, n_robin = 0;
@@ -79,6 +80,7 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
     n.child = fn.child;
   }
   std::vector<Prim> recs((size_t)T);
+  std::vector<R> normals((size_t)T * 4, (R)0);
   std::vector<int32_t> leaf_of_id((size_t)T);
   for (int64_t j = 0; j < T; ++j) {
     const int32_t id = bvh.order[j];
@@ -89,34 +91,48 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
     const int k = kind ? kind[id] : 0;
     p.idkind = id | (k << wob::kIdBits);
     p.alpha = alpha ? (R)alpha[id] : (R)0;
+    double e1d[3] = {0, 0, 0}, e2d[3] = {0, 0, 0};
     if constexpr (D == 3) {
       for (int a = 0; a < 3; ++a) {
         const double v0 = v[(int64_t)ix[0] * 3 + a], v1 = v[(int64_t)ix[1] * 3 + a],
                      v2 = v[(int64_t)ix[2] * 3 + a];
         p.v0[a] = (R)v0;
-        p.e1[a] = (R)(v1 - v0);
-        p.e2[a] = (R)(v2 - v0);
+        e1d[a] = v1 - v0;
+        e2d[a] = v2 - v0;
+        p.e1[a] = (R)e1d[a];
+        p.e2[a] = (R)e2d[a];
       }
+      double n[3] = {e1d[1] * e2d[2] - e1d[2] * e2d[1], e1d[2] * e2d[0] - e1d[0] * e2d[2],
+                     e1d[0] * e2d[1] - e1d[1] * e2d[0]};
+      const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      for (int a = 0; a < 3; ++a) normals[4 * j + a] = (R)(n[a] / l);
     } else {
       for (int a = 0; a < 2; ++a) {
         const double v0 = v[(int64_t)ix[0] * 2 + a], v1 = v[(int64_t)ix[1] * 2 + a];
         p.v0[a] = (R)v0;
-        p.e[a] = (R)(v1 - v0);
+        e1d[a] = v1 - v0;
+        p.e[a] = (R)e1d[a];
       }
+      const double l = std::sqrt(e1d[0] * e1d[0] + e1d[1] * e1d[1]);
+      normals[4 * j + 0] = (R)(e1d[1] / l);
+      normals[4 * j + 1] = (R)(-e1d[0] / l);
     }
   }
   sc->node_bytes = sizeof(Node);
   sc->prim_bytes = sizeof(Prim);
   const size_t nb = nodes.size() * sizeof(Node), pb = recs.size() * sizeof(Prim),
-               lb = leaf_of_id.size() * sizeof(int32_t);
+               lb = leaf_of_id.size() * sizeof(int32_t), qb = normals.size() * sizeof(R);
   if (hipMalloc(&sc->d_nodes, nb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc(&sc->d_prims, pb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc(&sc->d_normals, qb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMemcpy(sc->d_normals, normals.data(), qb, hipMemcpyHostToDevice) != hipSuccess)
+    return WOB_E_DEVICE;
   if (hipMalloc((void**)&sc->d_leaf_of_id, lb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMemcpy(sc->d_nodes, nodes.data(), nb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
   if (hipMemcpy(sc->d_prims, recs.data(), pb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
   if (hipMemcpy(sc->d_leaf_of_id, leaf_of_id.data(), lb, hipMemcpyHostToDevice) != hipSuccess)
     return WOB_E_DEVICE;
-  sc->device_bytes = (int64_t)(nb + pb + lb);
+  sc->device_bytes = (int64_t)(nb + pb + lb + qb);
   return WOB_OK;
 }
 
@@ -125,6 +141,7 @@ wob::SceneView<R, D> view(const wob_scene_s* sc) {
   wob::SceneView<R, D> s;
   s.nodes = (const typename wob::Rec<R, D>::Node*)sc->d_nodes;
   s.prims = (const typename wob::Rec<R, D>::Prim*)sc->d_prims;
+  s.normals = (const R*)sc->d_normals;
   s.leaf_of_id = sc->d_leaf_of_id;
   s.n_nodes = (int32_t)sc->n_nodes;
   s.n_prims = (int32_t)sc->n_prims;
@@ -372,6 +389,7 @@ void wob_free(wob_scene sc) {
   if (!sc) return;
   if (sc->d_nodes) (void)hipFree(sc->d_nodes);
   if (sc->d_prims) (void)hipFree(sc->d_prims);
+  if (sc->d_normals) (void)hipFree(sc->d_normals);
   if (sc->d_leaf_of_id) (void)hipFree(sc->d_leaf_of_id);
   delete sc;
 }
