@@ -181,6 +181,67 @@ wob_status wob_count_work(wob_scene scene, const void* points, const int32_t* po
 
 const char* wob_status_string(wob_status status);
 
+/* ------------------------------------------------------------------------- */
+/* Batched solves: many problems (scenes, point sets, data, N, M) in one      */
+/* persistent launch.  Not in the paper: its estimators are run per problem;  */
+/* batching only schedules them together.                                     */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  wob_scene scene;          /* all scenes of a batch share dim, precision and device */
+  const void* points;       /* DEVICE, n_points * dim */
+  const int32_t* point_prim;/* DEVICE or NULL, as in wob_solve */
+  int64_t n_points;
+  wob_bc bc;
+  int32_t samples;          /* N >= 2 */
+  int32_t walk_len;         /* M >= 1 */
+  uint64_t seed;
+  uint32_t stream_id;       /* random-number counter field "problem" (< 256); with the same
+                               seed and stream_id 0 a problem draws exactly the paths of
+                               wob_solve */
+  int32_t reserved;         /* must be 0 */
+  void* mean_out;           /* DEVICE, n_points */
+  void* var_out;            /* DEVICE, n_points, or NULL */
+} wob_problem;
+
+/* Launch shape of the persistent kernel. */
+typedef struct {
+  int32_t block;            /* lanes per workgroup: 128, 256 or 512 */
+  int32_t blocks_per_cu;    /* persistent workgroups per compute unit, 1..16 */
+} wob_tune;
+
+typedef struct wob_batch_s* wob_batch;
+
+/* Validate the problems, upload the problem table and capture the solve as a
+ * hipGraph {reset the tile counter, persistent kernel}.  The arrays of every
+ * problem must stay valid while the batch is used.  tune NULL = 256 lanes,
+ * 4 workgroups per CU.  Tiles (one workgroup's points of one problem) are
+ * ordered by decreasing estimated cost and pulled from an atomic counter.
+ * Errors: WOB_E_ARG, WOB_E_UNSUPPORTED, WOB_E_ALLOC, WOB_E_DEVICE. */
+wob_status wob_batch_create(const wob_problem* problems, int32_t n_problems,
+                            const wob_tune* tune, wob_batch* out);
+
+/* Replay the captured graph on `stream`: solves every problem. */
+wob_status wob_batch_launch(wob_batch batch, void* stream);
+
+/* Autotuner: time every candidate launch shape on a strided subset of the
+ * tiles (every sample_stride-th tile, >= 1) and keep the fastest; re-captures
+ * the graph.  With cache_path (or NULL), a text file of
+ * "<workload signature> <block> <blocks_per_cu>" lines is read first (a hit
+ * skips the timing) and appended after tuning.  Overwrites the problems'
+ * outputs.  chosen may be NULL.  Synchronous on `stream`. */
+wob_status wob_batch_autotune(wob_batch batch, int32_t sample_stride, const char* cache_path,
+                              wob_tune* chosen, void* stream);
+
+/* Current launch shape and total tiles. */
+wob_status wob_batch_get_tune(wob_batch batch, wob_tune* tune, int64_t* n_tiles);
+
+void wob_batch_free(wob_batch batch);
+
+/* One-shot: create, launch, wait on `stream`, free. */
+wob_status wob_solve_batched(const wob_problem* problems, int32_t n_problems,
+                             const wob_tune* tune, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,116 @@
+// Internal helpers shared by the ABI translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/wob.h"
+#include "walk.hpp"
+
+struct wob_scene_s {
+  int32_t dim = 0, precision = 0, device = 0;
+  int64_t n_prims = 0, n_nodes = 0, n_leaves = 0;
+  int32_t depth = 0, max_leaf = 0;
+  void* d_nodes = nullptr;
+  void* d_prims = nullptr;
+  void* d_normals = nullptr;
+  int32_t* d_leaf_of_id = nullptr;
+  int64_t node_bytes = 0, prim_bytes = 0, device_bytes = 0;
+  int32_t n_dirichlet = 0, n_neumann = 0, n_robin = 0;
+};
+
+namespace wobi {
+
+constexpr int kSolveBlock = 256;  // lanes per workgroup of the single-problem solve
+
+// log2 of the lanes that share one point: the smallest power of two >= N,
+// at least one wavefront, at most the block
+inline int lpp_shift_for(int32_t samples, int block) {
+  int s = 6;
+  while ((1 << s) < samples && (1 << s) < block) ++s;
+  return s;
+}
+
+template <typename R, int D>
+wob::SceneView<R, D> view(const wob_scene_s* sc) {
+  wob::SceneView<R, D> s;
+  s.nodes = (const typename wob::Rec<R, D>::Node*)sc->d_nodes;
+  s.prims = (const typename wob::Rec<R, D>::Prim*)sc->d_prims;
+  s.normals = (const R*)sc->d_normals;
+  s.leaf_of_id = sc->d_leaf_of_id;
+  s.n_nodes = (int32_t)sc->n_nodes;
+  s.n_prims = (int32_t)sc->n_prims;
+  return s;
+}
+
+inline int resolve_formulation(const wob_scene_s* sc, int f) {
+  const bool d = sc->n_dirichlet > 0, n = sc->n_neumann > 0, r = sc->n_robin > 0;
+  if (f == WOB_F_AUTO) {
+    if (!n && !r) return WOB_F_DOUBLE_LAYER;
+    if (!d && !r) return WOB_F_DIRECT;
+    if (!d) return WOB_F_SINGLE_LAYER;
+    return -1;
+  }
+  if (f == WOB_F_DOUBLE_LAYER) return (!n && !r) ? f : -1;
+  if (f == WOB_F_DIRECT) return (!d && !r) ? f : -1;
+  if (f == WOB_F_SINGLE_LAYER) return !d ? f : -1;
+  return -2;
+}
+
+struct Plan {
+  int form;
+  int32_t L;
+  uint32_t self_thr;
+  double self_p;
+};
+
+inline wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                     Plan* p) {
+  if (!sc || !bc) return WOB_E_ARG;
+  if (bc->domain != 1 && bc->domain != -1) return WOB_E_ARG;
+  if (bc->program < WOB_PROG_CONST || bc->program > WOB_PROG_INVDIST) return WOB_E_ARG;
+  if (bc->reserved != 0) return WOB_E_ARG;
+  if (samples < 1 || walk_len < 1 || walk_len >= 65535) return WOB_E_ARG;
+  const int f = resolve_formulation(sc, bc->formulation);
+  if (f == -2) return WOB_E_ARG;
+  if (f < 0) return WOB_E_UNSUPPORTED;
+  double ps = bc->self_panel_p == 0.0 ? 1.0 / 16.0 : bc->self_panel_p;
+  if (!(ps > 0.0 && ps < 1.0)) return WOB_E_ARG;
+  p->form = f;
+  p->L = f == WOB_F_DIRECT ? walk_len + 1 : walk_len;
+  p->self_thr = (uint32_t)std::floor(ps * 16777216.0);
+  if (p->self_thr == 0) return WOB_E_ARG;
+  p->self_p = p->self_thr / 16777216.0;
+  return WOB_OK;
+}
+
+template <typename R, int D>
+wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void* points,
+                              const int32_t* point_prim, int64_t n_points, const wob_bc* bc,
+                              int32_t samples, int32_t walk_len, uint64_t seed) {
+  wob::WalkArgs<R, D> a;
+  std::memset(&a, 0, sizeof(a));
+  a.scene = view<R, D>(sc);
+  a.prog.type = bc->program;
+  for (int k = 0; k < 8; ++k) a.prog.p[k] = (R)bc->params[k];
+  a.points = (const R*)points;
+  a.point_prim = point_prim;
+  a.n_points = n_points;
+  a.N = samples;
+  a.M = walk_len;
+  a.L = pl.L;
+  a.phi = (R)bc->domain;
+  a.self_thr = pl.self_thr;
+  a.self_p = (R)pl.self_p;
+  a.k0 = (uint32_t)(seed & 0xffffffffu);
+  a.k1 = (uint32_t)(seed >> 32);
+  a.problem = 0;
+  a.lpp_shift = lpp_shift_for(samples, kSolveBlock);
+  a.form = pl.form == WOB_F_DOUBLE_LAYER ? wob::F_DL : (pl.form == WOB_F_DIRECT ? wob::F_DIRECT : wob::F_SL);
+  return a;
+}
+
+
+}  // namespace wobi

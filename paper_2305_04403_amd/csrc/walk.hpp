@@ -20,7 +20,8 @@ struct WalkArgs {
   R self_p;                   // floor(p_s 2^24) / 2^24
   uint32_t k0, k1;            // Philox key
   uint32_t problem;           // problem index (counter word 2, bits 24..31)
-  int32_t lpp_shift;          // log2 of lanes per point (6, 7 or 8)
+  int32_t lpp_shift;          // log2 of lanes per point (6 .. log2 of the block size)
+  int32_t form;               // F_DL / F_DIRECT / F_SL (read by the batched kernel)
   R* mean_out;
   R* var_out;
   R* path_out;
@@ -183,11 +184,15 @@ __device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, 
   n = nn;
 }
 
-template <typename R, int D, int FORM, bool TRACE, bool COUNT>
-__global__ void __launch_bounds__(256) walk_kernel(WalkArgs<R, D> a) {
+// One block's share of a solve: BLOCK lanes cover BLOCK >> lpp_shift points,
+// the N paths of a point on 1 << lpp_shift consecutive lanes (a lane loops over
+// paths k, k + lpp, ...).  `red` is BLOCK / 64 x 3 doubles of LDS.
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK>
+__device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t block_index,
+                                           double (*red)[3]) {
   const int tid = threadIdx.x;
   const int lpp = 1 << a.lpp_shift;
-  const int64_t point = (int64_t)blockIdx.x * (256 >> a.lpp_shift) + (tid >> a.lpp_shift);
+  const int64_t point = block_index * (BLOCK >> a.lpp_shift) + (tid >> a.lpp_shift);
   const int lane_in_point = tid & (lpp - 1);
   double n = 0.0, mean = 0.0, m2 = 0.0;
   WorkCount wc = {0, 0, 0, 0};
@@ -236,7 +241,6 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs<R, D> a) {
       m2 = m22;
     }
   }
-  __shared__ double red[4][3];
   const int wave = tid >> 6;
   if ((tid & 63) == 0) {
     red[wave][0] = n;
@@ -252,6 +256,47 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs<R, D> a) {
     if (a.var_out) a.var_out[point] = (R)(tn > 1.0 ? ts / (tn - 1.0) : 0.0);
   }
 }
+
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs<R, D> a) {
+  __shared__ double red[BLOCK / 64][3];
+  walk_block<R, D, FORM, TRACE, COUNT, BLOCK>(a, blockIdx.x, red);
+}
+
+// Persistent batched solve: every block pulls tiles (problem, block of points)
+// from a device counter until none is left.  Tiles of one problem are
+// contiguous; tile_off (n_probs + 1 entries) is the prefix sum of tiles per
+// problem.  With stride > 1 only every stride-th tile runs (autotuner timing).
+template <typename R, int D, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) batch_kernel(const WalkArgs<R, D>* __restrict__ probs,
+                                                      const int64_t* __restrict__ tile_off,
+                                                      int32_t n_probs, int64_t stride,
+                                                      unsigned long long* __restrict__ counter) {
+  __shared__ double red[BLOCK / 64][3];
+  __shared__ long long s_tile;
+  const int64_t n_tiles = tile_off[n_probs];
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (long long)atomicAdd(counter, 1ull) * stride;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    __syncthreads();
+    if (tile >= n_tiles) break;
+    int lo = 0, hi = n_probs - 1;
+    while (lo < hi) {  // last problem whose first tile is <= tile
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_off[mid] <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    const int b = __builtin_amdgcn_readfirstlane(lo);
+    const WalkArgs<R, D>& a = probs[b];
+    const int64_t local = tile - tile_off[b];
+    const int form = __builtin_amdgcn_readfirstlane(a.form);
+    if (form == F_DL) walk_block<R, D, F_DL, false, false, BLOCK>(a, local, red);
+    else if (form == F_DIRECT) walk_block<R, D, F_DIRECT, false, false, BLOCK>(a, local, red);
+    else walk_block<R, D, F_SL, false, false, BLOCK>(a, local, red);
+  }
+}
+
 
 // Every hit of each line, in traversal order (parity / debugging).
 template <typename R, int D>

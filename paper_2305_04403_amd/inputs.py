@@ -71,39 +71,48 @@ _ICO_F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), 
 
 def icosphere(freq: int) -> Mesh:
     """Geodesic sphere: each icosahedron face split into freq^2 triangles, vertices
-    projected to the unit sphere. Shared vertices are merged exactly through their
-    integer barycentric keys, so the mesh is watertight."""
+    projected to the unit sphere.  A vertex is identified by its integer
+    barycentric weights on the icosahedron's vertices, so shared vertices merge
+    exactly and the mesh is watertight."""
     base = _ICO_V / np.linalg.norm(_ICO_V, axis=1, keepdims=True)
     faces = []
     for a, b, c in _ICO_F:
         n = np.cross(base[b] - base[a], base[c] - base[a])
         faces.append((a, b, c) if np.dot(n, base[a]) > 0 else (a, c, b))
+    faces = np.array(faces, dtype=np.int64)
     f = int(freq)
-    index: Dict[tuple, int] = {}
-    pos: List[np.ndarray] = []
-
-    def vid(wts: Tuple[Tuple[int, int], ...]) -> int:
-        key = tuple(sorted((v, w) for v, w in wts if w > 0))
-        got = index.get(key)
-        if got is None:
-            p = sum(w * base[v] for v, w in key) / f
-            pos.append(p / np.linalg.norm(p))
-            got = len(pos) - 1
-            index[key] = got
-        return got
-
-    tris = []
-    for a, b, c in faces:
-        grid = {}
-        for i in range(f + 1):
-            for j in range(f + 1 - i):
-                grid[(i, j)] = vid(((a, f - i - j), (b, i), (c, j)))
-        for i in range(f):
-            for j in range(f - i):
-                tris.append((grid[(i, j)], grid[(i + 1, j)], grid[(i, j + 1)]))
-                if i + j + 1 < f:
-                    tris.append((grid[(i + 1, j)], grid[(i + 1, j + 1)], grid[(i, j + 1)]))
-    return Mesh(3, np.array(pos), np.array(tris, dtype=np.int32))
+    ii, jj = np.meshgrid(np.arange(f + 1), np.arange(f + 1), indexing="ij")
+    keep = ii + jj <= f
+    ii, jj = ii[keep], jj[keep]                      # grid points of one face
+    local = -np.ones((f + 1, f + 1), dtype=np.int64)
+    local[ii, jj] = np.arange(len(ii))
+    F, G = len(faces), len(ii)
+    vid = np.stack([np.repeat(faces[:, 0], G), np.repeat(faces[:, 1], G), np.repeat(faces[:, 2], G)], 1)
+    w = np.stack([np.tile(f - ii - jj, F), np.tile(ii, F), np.tile(jj, F)], 1)
+    vid = np.where(w > 0, vid, 15)                   # absent corners sort last
+    o = np.argsort(vid, axis=1, kind="stable")
+    vid = np.take_along_axis(vid, o, 1)
+    w = np.take_along_axis(w, o, 1)
+    key = np.zeros(len(vid), dtype=np.int64)
+    for k in range(3):
+        key = (key << 15) | (vid[:, k] << 11) | np.where(vid[:, k] == 15, 0, w[:, k])
+    uniq, first, inv = np.unique(key, return_index=True, return_inverse=True)
+    V = np.zeros((len(uniq), 3))
+    vv, ww = vid[first], w[first]
+    for k in range(3):
+        m = vv[:, k] != 15
+        V[m] += ww[m, k, None] * base[vv[m, k]]
+    V /= f
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    # two triangles per grid cell (one at the cell touching the i + j = f edge)
+    ci, cj = np.meshgrid(np.arange(f), np.arange(f), indexing="ij")
+    up = ci + cj < f
+    dn = ci + cj + 1 < f
+    t_up = np.stack([local[ci[up], cj[up]], local[ci[up] + 1, cj[up]], local[ci[up], cj[up] + 1]], 1)
+    t_dn = np.stack([local[ci[dn] + 1, cj[dn]], local[ci[dn] + 1, cj[dn] + 1], local[ci[dn], cj[dn] + 1]], 1)
+    cell = np.concatenate([t_up, t_dn])
+    tris = (cell[None, :, :] + (np.arange(F) * G)[:, None, None]).reshape(-1, 3)
+    return Mesh(3, V, inv.reshape(-1)[tris].astype(np.int32))
 
 
 def perturb_radial(mesh: Mesh, amp: float = 0.1, k_theta: int = 3, k_phi: int = 4) -> Mesh:
@@ -390,3 +399,41 @@ def config_tori(grid_n: int = 87, n_points: int = 1_000_000, boundary_frac: floa
     return Workload(f"tori{mesh.n_prims}-exterior-neumann-robin-f32", mesh, pts, pp,
                     dict(domain=-1, formulation=3, program=3, params=tuple(xs)), samples, walk_len,
                     "f32", exact=exact)
+
+
+def config_batched(n_problems: int = 64, seed: int = 0, point_scale: float = 1.0) -> List[Workload]:
+    """Many problems of uneven size: perturbed-sphere meshes with a log-uniform
+    triangle count in [2k, 200k] (frequency-n icosphere, n = round(sqrt(T / 20))),
+    radius 1 + a sin(k1 theta) sin(k2 phi) with a ~ U[0, 0.15], k1, k2 in 1..5;
+    half interior Dirichlet (g = 1/|x - x0|, |x0| = 2, points uniform in the
+    ball r <= 0.8), half exterior Neumann through the direct BIE (point source
+    with |xs| <= 0.5, points uniform in the shell 1.2 <= |x| <= 2); points per
+    problem log-uniform in [1k, 256k] (times point_scale), paths log-uniform in
+    [128, 1024] rounded to a multiple of 64, M = 4, FP32."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(n_problems):
+        T = math.exp(rng.uniform(math.log(2000), math.log(200000)))
+        f = max(1, int(round(math.sqrt(T / 20.0))))
+        amp = float(rng.uniform(0.0, 0.15))
+        k1, k2 = (int(k) for k in rng.integers(1, 6, 2))
+        mesh = perturb_radial(icosphere(f), amp, k1, k2)
+        P = max(1, int(round(point_scale * math.exp(rng.uniform(math.log(1000), math.log(256000))))))
+        N = int(np.clip(64 * round(math.exp(rng.uniform(math.log(128), math.log(1024))) / 64), 128, 1024))
+        dirichlet = bool(rng.random() < 0.5)
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        if dirichlet:
+            c = 2.0 * d
+            pts = ball_points(P, 0.8, seed * 1000 + b)
+            bc = dict(domain=1, formulation=1, program=3, params=tuple(c))
+        else:
+            c = 0.5 * rng.random() ** (1 / 3) * d
+            pts = ball_points(P, 2.0, seed * 1000 + b, r_min=1.2)
+            mesh = dataclasses.replace(mesh, kind=np.full(mesh.n_prims, NEUMANN, np.uint8))
+            bc = dict(domain=-1, formulation=2, program=3, params=tuple(c))
+        mesh, pts = _round(mesh, pts, "f32")
+        exact = 1.0 / np.linalg.norm(pts - c, axis=1)
+        out.append(Workload(f"batch{b}-{'dirichlet' if dirichlet else 'neumann'}-{mesh.n_prims}", mesh,
+                            pts, None, bc, N, 4, "f32", seed=seed, exact=exact))
+    return out

@@ -23,7 +23,9 @@ PROG_CONST, PROG_LINEAR, PROG_QUAD, PROG_INVDIST = 0, 1, 2, 3
 DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 
 EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_path", "wob_solve",
-            "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string")
+            "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string",
+            "wob_batch_create", "wob_batch_launch", "wob_batch_autotune", "wob_batch_get_tune",
+            "wob_batch_free", "wob_solve_batched")
 
 
 class WobError(RuntimeError):
@@ -41,6 +43,17 @@ class _SceneInfo(C.Structure):
                 ("max_leaf", C.c_int32), ("device_bytes", C.c_int64), ("node_bytes", C.c_int64),
                 ("prim_bytes", C.c_int64), ("n_dirichlet", C.c_int32), ("n_neumann", C.c_int32),
                 ("n_robin", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("points", C.c_void_p), ("point_prim", C.c_void_p),
+                ("n_points", C.c_int64), ("bc", _BC), ("samples", C.c_int32),
+                ("walk_len", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint32),
+                ("reserved", C.c_int32), ("mean_out", C.c_void_p), ("var_out", C.c_void_p)]
+
+
+class _Tune(C.Structure):
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32)]
 
 
 _lib = None
@@ -65,6 +78,16 @@ def lib():
     L.wob_trace.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
     L.wob_count_work.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp]
     L.wob_intersect_all.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
+    L.wob_batch_create.argtypes = [C.POINTER(_Problem), i32, C.POINTER(_Tune), C.POINTER(vp)]
+    L.wob_batch_launch.argtypes = [vp, vp]
+    L.wob_batch_autotune.argtypes = [vp, i32, C.c_char_p, C.POINTER(_Tune), vp]
+    L.wob_batch_get_tune.argtypes = [vp, C.POINTER(_Tune), C.POINTER(i64)]
+    L.wob_batch_free.argtypes = [vp]
+    L.wob_batch_free.restype = None
+    L.wob_solve_batched.argtypes = [C.POINTER(_Problem), i32, C.POINTER(_Tune), vp]
+    for name in ("wob_batch_create", "wob_batch_launch", "wob_batch_autotune",
+                 "wob_batch_get_tune", "wob_solve_batched"):
+        getattr(L, name).restype = C.c_int
     L.wob_status_string.argtypes = [C.c_int]
     L.wob_status_string.restype = C.c_char_p
     for name in ("wob_build_bvh", "wob_get_scene_info", "wob_solve", "wob_trace",
@@ -228,3 +251,70 @@ def intersect_all(scene: Scene, orig, dirs, exclude=None, max_hits: int = 64, st
                                  _stream(stream))
     _check(st, "wob_intersect_all")
     return nh, hp, ht
+
+
+class Batch:
+    """Many problems solved by one persistent launch replayed from a hipGraph.
+
+    ``problems``: list of dicts with keys scene, points, bc, samples, walk_len and
+    optionally point_prim, seed, stream_id, want_var.  Output tensors are
+    allocated here; the batch keeps every tensor alive."""
+
+    def __init__(self, problems, tune=None):
+        torch = _torch()
+        self._keep = []
+        self.outputs = []
+        arr = (_Problem * len(problems))()
+        for i, p in enumerate(problems):
+            scene, pts = p["scene"], p["points"]
+            P = pts.shape[0]
+            mean = torch.empty(P, dtype=scene.dtype, device=pts.device)
+            var = torch.empty(P, dtype=scene.dtype, device=pts.device) if p.get("want_var", True) else None
+            pp = p.get("point_prim")
+            self._keep += [scene, pts, pp, mean, var]
+            self.outputs.append((mean, var))
+            arr[i].scene = scene.handle
+            arr[i].points = _dev_ptr(pts)
+            arr[i].point_prim = _dev_ptr(pp)
+            arr[i].n_points = P
+            arr[i].bc = p["bc"].c()
+            arr[i].samples = int(p["samples"])
+            arr[i].walk_len = int(p["walk_len"])
+            arr[i].seed = int(p.get("seed", 0))
+            arr[i].stream_id = int(p.get("stream_id", 0))
+            arr[i].reserved = 0
+            arr[i].mean_out = _dev_ptr(mean)
+            arr[i].var_out = _dev_ptr(var)
+        t = None if tune is None else _Tune(*tune)
+        h = C.c_void_p()
+        _check(lib().wob_batch_create(arr, len(problems), None if t is None else C.byref(t), C.byref(h)),
+               "wob_batch_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().wob_batch_launch(self.handle, _stream(stream)), "wob_batch_launch")
+        return self.outputs
+
+    def autotune(self, sample_stride: int = 16, cache_path: Optional[str] = None, stream=None):
+        t = _Tune()
+        path = None if cache_path is None else cache_path.encode()
+        _check(lib().wob_batch_autotune(self.handle, int(sample_stride), path, C.byref(t), _stream(stream)),
+               "wob_batch_autotune")
+        return (t.block, t.blocks_per_cu)
+
+    def tune(self):
+        t = _Tune()
+        n = C.c_int64()
+        _check(lib().wob_batch_get_tune(self.handle, C.byref(t), C.byref(n)), "wob_batch_get_tune")
+        return (t.block, t.blocks_per_cu), n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().wob_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,162 @@
+"""Batched persistent solve (one launch, hipGraph replay, autotuned shape)
+against single-problem solves and the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_04403_amd import inputs as I
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def W():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_04403_amd import wob
+    wob.lib()
+    return wob
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def small_problems(W):
+    """Uneven problems: interior Dirichlet and exterior Neumann, N from 64 to 512."""
+    specs = [
+        (I.perturb_radial(I.icosphere(8), 0.1, 3, 4), None, 1, 1, I.ball_points(301, 0.8, 1), 64, 4),
+        (I.perturb_radial(I.icosphere(12), 0.05, 2, 5), None, 1, 1, I.ball_points(77, 0.8, 2), 100, 6),
+        (I.icosphere(10), 1, -1, 2, I.ball_points(150, 2.0, 3, r_min=1.2), 256, 3),
+        (I.perturb_radial(I.icosphere(6), 0.12, 1, 1), None, 1, 1, I.ball_points(33, 0.7, 4), 512, 3),
+        (I.icosphere(5), 1, -1, 2, I.ball_points(1000, 2.0, 5, r_min=1.3), 128, 2),
+    ]
+    out = []
+    for k, (mesh, kind, dom, form, pts, N, M) in enumerate(specs):
+        if kind is not None:
+            mesh = I.Mesh(3, mesh.verts, mesh.prims, np.full(mesh.n_prims, kind, np.uint8))
+        mesh = PT.f32_mesh(mesh)
+        pts = PT.f32(pts)
+        c = (2.0, 0.5, 0.0) if dom == 1 else (0.2, -0.1, 0.05)
+        out.append(dict(mesh=mesh, scene=W.Scene(mesh, W.F32), points=dev(pts, torch.float32), pts=pts,
+                        bc=W.BC(dom, form, W.PROG_INVDIST, c), samples=N, walk_len=M, seed=11 + k,
+                        obc=oracle.make_bc(dom, form, oracle.PROG_INVDIST, c)))
+    return out
+
+
+def test_batch_equals_single_solves_and_replays(W):
+    probs = small_problems(W)
+    ref = [W.solve(p["scene"], p["points"], p["bc"], p["samples"], p["walk_len"], p["seed"]) for p in probs]
+    torch.cuda.synchronize()
+    for tune in ((256, 4), (128, 2), (512, 1)):
+        b = W.Batch(probs, tune=tune)
+        for rep in range(3):
+            outs = b.launch()
+            torch.cuda.synchronize()
+            for (m, v), (mr, vr) in zip(outs, ref):
+                assert torch.equal(m, mr), (tune, rep)
+                assert torch.equal(v, vr), (tune, rep)
+            # unrelated eager work between replays
+            _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+            for o in outs:
+                o[0].fill_(float("nan"))
+        b.close()
+
+
+def test_batch_stream_id_follows_oracle(W):
+    """A problem with stream_id q draws the counter field 'problem' = q: its mean
+    equals the oracle's mean over the same paths (FP32 vs FP64)."""
+    p = small_problems(W)[0]
+    b = W.Batch([dict(p, stream_id=7)])
+    (m, v), = b.launch()
+    torch.cuda.synchronize()
+    om = oracle.OracleMesh(p["mesh"])
+    P, N = p["pts"].shape[0], p["samples"]
+    tr = oracle.trace(om, p["pts"], None, p["obc"], p["walk_len"], p["seed"],
+                      np.repeat(np.arange(P), N), np.tile(np.arange(N), P), problem=7, want_pos=False)
+    mo = tr["value"].reshape(P, N).mean(axis=1)
+    scale = tr["abs_sum"].reshape(P, N).mean(axis=1)
+    ok = (tr["graze"].reshape(P, N) >= PT.GRAZE).all(axis=1)
+    assert ok.mean() > 0.97
+    err = np.abs(m.cpu().double().numpy() - mo)
+    assert np.all(err[ok] <= 2e-5 * scale[ok] + 1e-7)
+    # and it differs from stream 0
+    m0, _ = W.solve(p["scene"], p["points"], p["bc"], p["samples"], p["walk_len"], p["seed"])
+    assert not torch.equal(m, m0)
+    b.close()
+
+
+def test_batch_autotune_cache(W, tmp_path):
+    probs = small_problems(W)
+    ref = [W.solve(p["scene"], p["points"], p["bc"], p["samples"], p["walk_len"], p["seed"])[0] for p in probs]
+    cache = str(tmp_path / "tune.txt")
+    b = W.Batch(probs)
+    t1 = b.autotune(sample_stride=2, cache_path=cache)
+    assert t1[0] in (128, 256, 512) and 1 <= t1[1] <= 8
+    lines = open(cache).read().split("\n")
+    assert len([l for l in lines if l.strip()]) == 1
+    t2 = b.autotune(sample_stride=2, cache_path=cache)  # served from the cache
+    assert t2 == t1
+    assert len([l for l in open(cache).read().split("\n") if l.strip()]) == 1
+    outs = b.launch()
+    torch.cuda.synchronize()
+    for (m, _), mr in zip(outs, ref):
+        assert torch.equal(m, mr)
+    b.close()
+
+
+def test_batch_rejects_mixed_precision(W):
+    probs = small_problems(W)[:1]
+    s64 = W.Scene(I.icosphere(3), W.F64)
+    bad = dict(probs[0], scene=s64, points=dev(probs[0]["pts"], torch.float64))
+    with pytest.raises(W.WobError):
+        W.Batch([probs[0], bad])
+    with pytest.raises(W.WobError):
+        W.Batch([dict(probs[0], stream_id=256)])
+
+
+def test_full_size_batched_sampled(W):
+    """The full 64-problem batched workload in one persistent launch; at sampled
+    points of four problems the paths are re-traced with their original
+    random-number indices: the batch mean equals the traced paths' mean and the
+    traced paths match the oracle path by path."""
+    ws = I.config_batched()
+    scenes = [W.Scene(w.mesh, W.F32) for w in ws]
+    probs = []
+    for w, s in zip(ws, scenes):
+        probs.append(dict(scene=s, points=dev(w.points, torch.float32),
+                          bc=W.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], w.bc["params"]),
+                          samples=w.samples, walk_len=w.walk_len, seed=w.seed))
+    b = W.Batch(probs)
+    outs = b.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    checked = 0
+    for k in (0, 1, 17, 63):
+        w, s, (m, v) = ws[k], scenes[k], outs[k]
+        assert torch.isfinite(m).all()
+        ids = np.sort(rng.choice(w.points.shape[0], 3, replace=False))
+        sub = w.points[ids]
+        val, vprim, vm = W.trace(s, dev(sub, torch.float32), probs[k]["bc"], w.samples, w.walk_len,
+                                 w.seed, point_ids=dev(ids.astype(np.int32), torch.int32))
+        torch.cuda.synchronize()
+        vv = val.cpu().double().numpy()
+        np.testing.assert_allclose(m.cpu().numpy()[ids], vv.mean(axis=1), rtol=2e-6, atol=2e-6)
+        om = oracle.OracleMesh(w.mesh)
+        ob = oracle.make_bc(w.bc["domain"], w.bc["formulation"], w.bc["program"], w.bc["params"])
+        orc = PT.oracle_all_paths(om, sub, None, ob, w.samples, w.walk_len, w.seed, point_ids=ids)
+        L = orc["vtx_prim"].shape[1]
+        res = PT.compare_paths(orc, vv.reshape(-1), vprim.cpu().numpy().reshape(-1, L),
+                               vm.cpu().numpy().reshape(-1, L), PT.RTOL_F32)
+        print(w.name, res.summary(), flush=True)
+        assert res.n_graze <= 0.01 * res.n + 1
+        assert res.n_vertex_mismatch <= 0.002 * res.n_checked + 1
+        assert res.n_value_mismatch <= 0.002 * res.n_checked + 1
+        checked += res.n_checked
+    assert checked > 1000
+    b.close()
