@@ -37,6 +37,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--cpu-sample-points", type=int, default=640)
     p.add_argument("--skip-cpu-baseline", action="store_true")
+    p.add_argument("--copy-probe-mib", type=int, default=0,
+                   help="after timing, copy this many MiB device-to-device once (a kernel of known "
+                        "traffic that calibrates hardware byte counters)")
     return p.parse_args()
 
 
@@ -131,6 +134,14 @@ def main():
         "mean_se": float(np.mean(se)),
         "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")},
     }
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_probe_bytes"] = 4 * n
     if not args.skip_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_points)
     scene.close()

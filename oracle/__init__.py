@@ -28,7 +28,8 @@ class _Mesh(C.Structure):
 
 class _BC(C.Structure):
     _fields_ = [("domain", C.c_int), ("formulation", C.c_int), ("program", C.c_int),
-                ("params", C.c_double * 8), ("self_threshold", C.c_uint32), ("self_p", C.c_double)]
+                ("params", C.c_double * 8), ("self_threshold", C.c_uint32), ("self_p", C.c_double),
+                ("density", C.c_int)]
 
 
 class _TraceOut(C.Structure):
@@ -69,6 +70,26 @@ def lib():
         _lib.orc_lines_per_path.restype = C.c_int
         _lib.orc_lines_per_path.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
         _lib.orc_prim_normal.argtypes = [C.c_void_p, C.c_int64, C.c_void_p]
+        _lib.orc_prim_potential.argtypes = [vp, C.c_int64, vp]
+        _lib.orc_prim_potential.restype = C.c_double
+        _lib.orc_cv_addback.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int]
+        _lib.orc_cv_addback.restype = C.c_int
+        _lib.orc_trace_cv.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, vp,
+                                      C.c_int64, vp, vp, vp, C.c_int]
+        _lib.orc_trace_cv.restype = C.c_int
+        _lib.orc_mlp_n_params.argtypes = [C.c_int, C.c_int, C.c_int]
+        _lib.orc_mlp_n_params.restype = C.c_int64
+        _lib.orc_mlp_forward.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, vp,
+                                         C.c_int, vp]
+        _lib.orc_mlp_forward.restype = None
+        _lib.orc_mlp_loss_grad.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, vp,
+                                           vp, C.c_int, vp]
+        _lib.orc_mlp_loss_grad.restype = C.c_double
+        _lib.orc_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                       C.c_double, C.c_double]
+        _lib.orc_adam_step.restype = None
+        _lib.orc_bf16_round.argtypes = [C.c_double]
+        _lib.orc_bf16_round.restype = C.c_double
     return _lib
 
 
@@ -104,8 +125,9 @@ def self_threshold(p: float) -> int:
 
 
 def make_bc(domain: int = 1, formulation: int = AUTO, program: int = PROG_CONST,
-            params=(), self_p: float = 1.0 / 16.0) -> _BC:
+            params=(), self_p: float = 1.0 / 16.0, density: bool = False) -> _BC:
     b = _BC()
+    b.density = int(bool(density))
     b.domain = int(domain)
     b.formulation = int(formulation)
     b.program = int(program)
@@ -208,3 +230,76 @@ def program_value(mesh: OracleMesh, bc: _BC, y: np.ndarray) -> float:
     yy = np.zeros(3)
     yy[: mesh.dim] = y
     return lib().orc_program_value(mesh.ref, C.byref(bc), yy.ctypes.data)
+
+
+# --------------------------------------------------------------------------- control variate
+
+def prim_potential(mesh: OracleMesh, prim: int, x: np.ndarray) -> float:
+    xx = np.zeros(3)
+    xx[: mesh.dim] = x
+    return lib().orc_prim_potential(mesh.ref, int(prim), xx.ctypes.data)
+
+
+def cv_addback(mesh: OracleMesh, g: np.ndarray, points: np.ndarray, n_threads: int = 0) -> np.ndarray:
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    out = np.zeros(pts.shape[0])
+    if lib().orc_cv_addback(mesh.ref, gg.ctypes.data, pts.ctypes.data, pts.shape[0], out.ctypes.data,
+                            n_threads) != 0:
+        raise ValueError("orc_cv_addback rejected its arguments")
+    return out
+
+
+def trace_cv(mesh: OracleMesh, points, point_prim, bc: _BC, walk_len: int, seed: int, g,
+             item_point, item_path, problem: int = 0, n_threads: int = 0) -> np.ndarray:
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    pp = None if point_prim is None else np.ascontiguousarray(point_prim, dtype=np.int32)
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    ip = np.ascontiguousarray(item_point, dtype=np.int64)
+    ik = np.ascontiguousarray(item_path, dtype=np.int64)
+    out = np.zeros(ip.shape[0])
+    rc = lib().orc_trace_cv(mesh.ref, _ptr(pts), _ptr(pp), pts.shape[0], C.byref(bc), int(walk_len),
+                            C.c_uint64(seed), C.c_uint32(problem), _ptr(gg), ip.shape[0], _ptr(ip),
+                            _ptr(ik), _ptr(out), int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_trace_cv rejected its arguments")
+    return out
+
+
+# --------------------------------------------------------------------------- MLP
+
+def mlp_n_params(n_freq: int = 16, hidden: int = 128, layers: int = 4) -> int:
+    return int(lib().orc_mlp_n_params(n_freq, hidden, layers))
+
+
+def mlp_forward(params, Bmat, y, bf16: bool, n_freq=16, hidden=128, layers=4) -> np.ndarray:
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    B = np.ascontiguousarray(Bmat, dtype=np.float64)
+    Y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros(Y.shape[0])
+    lib().orc_mlp_forward(P.ctypes.data, B.ctypes.data, n_freq, hidden, layers, Y.shape[1], Y.shape[0],
+                          Y.ctypes.data, int(bf16), out.ctypes.data)
+    return out
+
+
+def mlp_loss_grad(params, Bmat, y, target, bf16: bool, n_freq=16, hidden=128, layers=4):
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    B = np.ascontiguousarray(Bmat, dtype=np.float64)
+    Y = np.ascontiguousarray(y, dtype=np.float64)
+    T = np.ascontiguousarray(target, dtype=np.float64)
+    grad = np.zeros(P.shape[0])
+    loss = lib().orc_mlp_loss_grad(P.ctypes.data, B.ctypes.data, n_freq, hidden, layers, Y.shape[1],
+                                   Y.shape[0], Y.ctypes.data, T.ctypes.data, int(bf16), grad.ctypes.data)
+    return loss, grad
+
+
+def adam_step(params, m, v, grad, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    lib().orc_adam_step(params.ctypes.data, m.ctypes.data, v.ctypes.data, g.ctypes.data, params.shape[0],
+                        int(step), lr, b1, b2, eps)
+
+
+def bf16_round(x: float) -> float:
+    return lib().orc_bf16_round(float(x))

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", LIB, os.path.join(HERE, "oracle.c"), "-lm"]
+           "-o", LIB, os.path.join(HERE, "oracle.c"), os.path.join(HERE, "mlp.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)

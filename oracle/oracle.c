@@ -436,7 +436,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
   }
 
   /* Table 1, Dirichlet: on the boundary the solution is the given value. */
-  if (form == ORC_DOUBLE_LAYER && prim0 >= 0) {
+  if (form == ORC_DOUBLE_LAYER && prim0 >= 0 && !bc->density) {
     res.value = orc_boundary_datum(m, bc, prim0, x0);
     res.abs_sum = fabs(res.value);
     return res;
@@ -469,8 +469,11 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
     /* single layer: where G acts on the own primitive (the first step from a
        boundary point, and the alpha G part at Robin vertices) mix the line
        sample with an in-plane self-panel sample */
+    /* step 0 from an evaluation point uses the representation formula; in
+       density mode x0 is itself a boundary vertex of the recursion */
+    const int first = i == 0 && !bc->density;
     int mixture = form == ORC_SINGLE_LAYER && on_gamma &&
-                  (i == 0 || prim_kind(m, cur) == ORC_ROBIN);
+                  (first || prim_kind(m, cur) == ORC_ROBIN);
     int use_self = mixture && (r0[2] >> 8) < bc->self_threshold;
 
     double y[3] = {0.0, 0.0, 0.0};
@@ -480,7 +483,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
       uint32_t r1[4];
       draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
       double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), y);
-      if (i == 0)
+      if (first)
         w = gp / bc->self_p; /* u = int G mu */
       else
         w = -2.0 * phi * prim_alpha(m, cur) * gp / bc->self_p; /* -2 phi alpha G */
@@ -526,7 +529,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
       double p = line_pdf(x, y, ny, h.m, dim);
       double kern, kabs;
       if (form == ORC_DOUBLE_LAYER) {
-        kern = (i == 0 && !on_gamma) ? -dG_dny(x, y, ny, dim)          /* u = -int dG/dny nu */
+        kern = (first && !on_gamma) ? -dG_dny(x, y, ny, dim)           /* u = -int dG/dny nu */
                                      : 2.0 * phi * dG_dny(x, y, ny, dim); /* nu = 2 phi int dG/dny nu + ... */
         kabs = fabs(kern);
       } else if (form == ORC_DIRECT) {
@@ -534,7 +537,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
                         : -phi * dG_dny(x, y, ny, dim);      /* interior / exterior row */
         kabs = fabs(kern);
       } else {
-        if (i == 0) {
+        if (first) {
           kern = G(x, y, dim); /* u = int G mu */
           kabs = fabs(kern);
         } else {
@@ -591,6 +594,7 @@ static int check_args(const orc_mesh* m, const orc_bc* bc, int walk_len) {
   if (walk_len < 1) return 1;
   if (bc->domain != 1 && bc->domain != -1) return 1;
   if (orc_resolve_formulation(m, bc->formulation) < 0) return 1;
+  if (bc->density && orc_resolve_formulation(m, bc->formulation) == ORC_DIRECT) return 1;
   return 0;
 }
 
@@ -705,5 +709,242 @@ int orc_intersect_all(const orc_mesh* m, const double* orig, const double* dir,
     n_hits[l] = cnt;
     if (line_graze) line_graze[l] = graze;
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Closed-form potential of a uniform primitive, int_T G(x, y) dA.            */
+/* 3D (Wilton et al. 1984): with n the unit normal, d = (x - p1).n, rho the   */
+/* projection of x on the plane, and per edge p_i -> p_i+1: unit tangent t,   */
+/* outward in-plane normal u = t x n, P = (p_i - rho).u, s- / s+ = the        */
+/* tangential coordinates of the edge's ends, R- / R+ their distances to x,   */
+/* R0^2 = P^2 + d^2:                                                          */
+/*   int_T 1/|x-y| dA = sum P ln((R+ + s+)/(R- + s-))                          */
+/*                    - |d| sum [atan(P s+/(R0^2 + |d| R+)) - atan(P s-/(R0^2 + |d| R-))]. */
+/* 2D: int over the segment of -ln|x - y| / (2 pi) dl in closed form.         */
+/* ------------------------------------------------------------------------- */
+static double log_ratio(double Rp, double sp, double Rm, double sm) {
+  /* ln((R+ + s+)/(R- + s-)) = ln((R- - s-)/(R+ - s+)); take the form without
+     cancellation */
+  if (sp + sm >= 0.0) return log((Rp + sp) / (Rm + sm));
+  return log((Rm - sm) / (Rp - sp));
+}
+
+double orc_prim_potential(const orc_mesh* m, int64_t prim, const double* x) {
+  if (m->dim == 3) {
+    double p[3][3], n[3];
+    for (int c = 0; c < 3; ++c) prim_vertex(m, prim, c, p[c]);
+    orc_prim_normal(m, prim, n);
+    double xv[3] = {x[0] - p[0][0], x[1] - p[0][1], x[2] - p[0][2]};
+    const double dn = dot(xv, n, 3);
+    const double ad = fabs(dn);
+    double rho[3] = {x[0] - dn * n[0], x[1] - dn * n[1], x[2] - dn * n[2]};
+    double sum_log = 0.0, sum_atan = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double* a = p[c];
+      const double* b = p[(c + 1) % 3];
+      double e[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+      const double L = sqrt(dot(e, e, 3));
+      double t[3] = {e[0] / L, e[1] / L, e[2] / L}, u[3];
+      cross3(t, n, u);
+      double ar[3] = {a[0] - rho[0], a[1] - rho[1], a[2] - rho[2]};
+      double br[3] = {b[0] - rho[0], b[1] - rho[1], b[2] - rho[2]};
+      const double P = dot(ar, u, 3);
+      const double sm = dot(ar, t, 3), sp = dot(br, t, 3);
+      double xa[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]};
+      double xb[3] = {x[0] - b[0], x[1] - b[1], x[2] - b[2]};
+      const double Rm = sqrt(dot(xa, xa, 3)), Rp = sqrt(dot(xb, xb, 3));
+      const double R02 = P * P + dn * dn;
+      if (P != 0.0) sum_log += P * log_ratio(Rp, sp, Rm, sm);
+      if (ad > 0.0) sum_atan += atan(P * sp / (R02 + ad * Rp)) - atan(P * sm / (R02 + ad * Rm));
+    }
+    return (sum_log - ad * sum_atan) / (4.0 * ORC_PI);
+  }
+  double a[3], b[3];
+  prim_vertex(m, prim, 0, a);
+  prim_vertex(m, prim, 1, b);
+  double e[2] = {b[0] - a[0], b[1] - a[1]};
+  const double L = sqrt(e[0] * e[0] + e[1] * e[1]);
+  double t[2] = {e[0] / L, e[1] / L};
+  double ax[2] = {x[0] - a[0], x[1] - a[1]};
+  const double s0 = -(ax[0] * t[0] + ax[1] * t[1]); /* tangential coordinate of a relative to x */
+  const double s1 = s0 + L;
+  const double h = fabs(ax[0] * t[1] - ax[1] * t[0]);
+  /* int_{s0}^{s1} ln sqrt(s^2 + h^2) ds */
+  double F1 = 0.5 * s1 * log(s1 * s1 + h * h) - s1 + (h > 0.0 ? h * atan(s1 / h) : 0.0);
+  double F0 = 0.5 * s0 * log(s0 * s0 + h * h) - s0 + (h > 0.0 ? h * atan(s0 / h) : 0.0);
+  if (s1 == 0.0 && h == 0.0) F1 = 0.0;
+  if (s0 == 0.0 && h == 0.0) F0 = 0.0;
+  return -(F1 - F0) / (2.0 * ORC_PI);
+}
+
+int orc_cv_addback(const orc_mesh* m, const double* g, const double* points, int64_t n_points,
+                   double* out, int n_threads) {
+  if (!m || !g || (m->dim != 2 && m->dim != 3)) return 1;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t p = 0; p < n_points; ++p) {
+    double x[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < m->dim; ++a) x[a] = points[p * m->dim + a];
+    double acc = 0.0;
+    for (int64_t j = 0; j < m->n_prims; ++j) acc += g[j] * orc_prim_potential(m, j, x);
+    out[p] = acc;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Learned control variate for the single layer (not in the paper).          */
+/*                                                                           */
+/* At a line with hits h (weights w(h) = m a(h), a(h) = kernel / p_all), the */
+/* plain estimator continues with w(j) * (value at y_j) for the picked j.    */
+/* For any function F, adding sum_h a(h) F(y_h) - w(j) F(y_j) changes        */
+/* nothing in expectation given the line (the pick is uniform over the m     */
+/* hits), so the estimator stays unbiased for every F:                       */
+/*  - line 0 from x0: F = g(T(y)) (the table); the subtraction is kept and   */
+/*    its exact expectation sum_T g_T int_T G(x0, y) dA is added per point   */
+/*    (orc_cv_addback) instead of the all-hits sum; a self-panel sample at a */
+/*    boundary x0 subtracts w g(T0) too, so the add-back covers all of Gamma;*/
+/*  - lines 1..M-2 (line branch): F = 2 phi s(y) + g(T(y));                  */
+/*  - line M-1 (line branch): F = phi s(y), the exact rest of the path, so   */
+/*    the pick is not needed at all.                                         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t prim;
+  double y[3];
+  uint32_t key;
+} hit_rec;
+
+static int collect_hits(const orc_mesh* m, const double* x, const double* d, int64_t exclude,
+                        hit_rec* out, int max_out, uint64_t seed, uint32_t path, uint32_t point,
+                        uint32_t problem, uint32_t line) {
+  int k = 0;
+  for (int64_t j = 0; j < m->n_prims; ++j) {
+    if (j == exclude) continue;
+    double t, y[3], margin, cosv;
+    if (!line_prim(m, j, x, d, &t, y, &margin, &cosv)) continue;
+    if (k < max_out) {
+      uint32_t r[4];
+      draw(seed, path, point, problem, line, 2u, (uint32_t)j, r);
+      out[k].prim = j;
+      memcpy(out[k].y, y, sizeof(out[k].y));
+      out[k].key = r[0];
+    }
+    ++k;
+  }
+  return k;
+}
+
+#define CV_MAX_HITS 256
+
+static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc* bc,
+                          const double* g, const double* x0, int64_t prim0, int M, uint64_t seed,
+                          uint32_t problem, uint32_t point, uint32_t path) {
+  const int dim = m->dim;
+  const double phi = (double)bc->domain;
+  double x[3] = {x0[0], x0[1], dim == 3 ? x0[2] : 0.0};
+  int64_t cur = prim0;
+  double W = 1.0, acc = 0.0;
+  hit_rec hits[CV_MAX_HITS];
+  for (int i = 0; i < M; ++i) {
+    const int on_gamma = cur >= 0, last = i == M - 1;
+    uint32_t r0[4];
+    draw(seed, path, point, problem, (uint32_t)i, 0u, 0u, r0);
+    double d[3] = {0.0, 0.0, 0.0};
+    if (dim == 3) {
+      double z = 1.0 - 2.0 * uniform(r0[0]);
+      double sq = sqrt(fmax(0.0, 1.0 - z * z));
+      double ph = 2.0 * ORC_PI * uniform(r0[1]);
+      d[0] = sq * cos(ph);
+      d[1] = sq * sin(ph);
+      d[2] = z;
+    } else {
+      double th = 2.0 * ORC_PI * uniform(r0[0]);
+      d[0] = cos(th);
+      d[1] = sin(th);
+    }
+    const int mixture = on_gamma && (i == 0 || prim_kind(m, cur) == ORC_ROBIN);
+    const int use_self = mixture && (r0[2] >> 8) < bc->self_threshold;
+    double y[3];
+    int64_t next;
+    double Wn;
+    if (use_self) {
+      uint32_t r1[4];
+      draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
+      const double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), y);
+      const double w = (i == 0 ? gp : -2.0 * phi * prim_alpha(m, cur) * gp) / bc->self_p;
+      Wn = W * w;
+      next = cur;
+      if (i == 0 && !last) acc -= Wn * g[cur];
+      acc += Wn * (last ? phi : 2.0 * phi) * orc_boundary_datum(m, bc, cur, y);
+    } else {
+      const int mh = collect_hits(m, x, d, cur, hits, CV_MAX_HITS, seed, path, point, problem,
+                                  (uint32_t)i);
+      if (mh == 0) break;
+      if (mh > CV_MAX_HITS) return NAN;
+      double a[CV_MAX_HITS];
+      int j = 0;
+      for (int h = 0; h < mh; ++h) {
+        const double* ny = normals + 3 * hits[h].prim;
+        double kern;
+        if (i == 0) {
+          kern = G(x, hits[h].y, dim);
+        } else {
+          const double* nx = normals + 3 * cur;
+          kern = -2.0 * phi * (dG_dnx(x, hits[h].y, nx, dim) + prim_alpha(m, cur) * G(x, hits[h].y, dim));
+        }
+        a[h] = kern / line_pdf(x, hits[h].y, ny, 1, dim) / (mixture ? 1.0 - bc->self_p : 1.0);
+        if (hits[h].key < hits[j].key || (hits[h].key == hits[j].key && hits[h].prim < hits[j].prim))
+          j = h;
+      }
+      if (last) {
+        for (int h = 0; h < mh; ++h)
+          acc += W * a[h] * phi * orc_boundary_datum(m, bc, hits[h].prim, hits[h].y);
+        break;
+      }
+      const double wj = a[j] * (double)mh;
+      Wn = W * wj;
+      memcpy(y, hits[j].y, sizeof(y));
+      next = hits[j].prim;
+      const double ej = 2.0 * phi * orc_boundary_datum(m, bc, next, y);
+      if (i == 0) {
+        acc -= Wn * g[next];
+        acc += Wn * ej;
+      } else {
+        for (int h = 0; h < mh; ++h)
+          acc += W * a[h] * (2.0 * phi * orc_boundary_datum(m, bc, hits[h].prim, hits[h].y) + g[hits[h].prim]);
+        acc -= Wn * g[next]; /* the picked hit's emission is kept as in the plain estimator */
+      }
+    }
+    W = Wn;
+    memcpy(x, y, sizeof(x));
+    cur = next;
+  }
+  return acc;
+}
+
+int orc_trace_cv(const orc_mesh* m, const double* points, const int32_t* point_prim,
+                 int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed, uint32_t problem,
+                 const double* g, int64_t n_items, const int64_t* item_point,
+                 const int64_t* item_path, double* value, int n_threads) {
+  if (check_args(m, bc, walk_len) || !g) return 1;
+  if (orc_resolve_formulation(m, bc->formulation) != ORC_SINGLE_LAYER || bc->density) return 1;
+  double* normals = make_normals(m);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+  for (int64_t it = 0; it < n_items; ++it) {
+    const int64_t p = item_point[it];
+    if (p < 0 || p >= n_points) continue;
+    double x0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
+    const int64_t prim0 = point_prim ? point_prim[p] : -1;
+    value[it] = one_path_cv(m, normals, bc, g, x0, prim0, walk_len, seed, problem, (uint32_t)p,
+                            (uint32_t)item_path[it]);
+  }
+  free(normals);
   return 0;
 }

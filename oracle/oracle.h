@@ -58,6 +58,8 @@ typedef struct {
   double params[8];        /* program parameters */
   uint32_t self_threshold; /* self-panel mixture probability as floor(p_s * 2^24) */
   double self_p;           /* the same probability as a real number, floor(p_s*2^24)/2^24 */
+  int density;             /* 1: estimate the boundary unknown (nu or mu) without its own
+                              emission, at points on the boundary (double / single layer) */
 } orc_bc;
 
 /* Per (point, path) record produced by orc_trace. Arrays may be NULL. */
@@ -112,6 +114,21 @@ double orc_boundary_datum(const orc_mesh* mesh, const orc_bc* bc, int64_t prim, 
  * returns G(x, y)/p(y) for the sample drawn from uniforms (u0, u1) and writes y. */
 double orc_self_panel(const orc_mesh* mesh, int64_t prim, const double* x, double u0,
                       double u1, double* y_out);
+
+/* int_T G(x, y) dA over primitive `prim` in closed form (3D: potential of a
+ * uniform triangle; 2D: of a uniform segment). */
+double orc_prim_potential(const orc_mesh* mesh, int64_t prim, const double* x);
+
+/* Learned control variate, single layer (see oracle.c): per-path values of the
+ * corrected estimator for a per-primitive table g (the network's prediction of
+ * the boundary unknown minus its emission).  The per-point add-back
+ * sum_T g_T int_T G(x0, y) dA comes from orc_cv_addback (zero when M = 1). */
+int orc_trace_cv(const orc_mesh* mesh, const double* points, const int32_t* point_prim,
+                 int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed,
+                 uint32_t problem, const double* g, int64_t n_items, const int64_t* item_point,
+                 const int64_t* item_path, double* value, int n_threads);
+int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points, int64_t n_points,
+                   double* out, int n_threads);
 
 /* Unit outward normal of a primitive. */
 void orc_prim_normal(const orc_mesh* mesh, int64_t prim, double* n_out);
