@@ -242,6 +242,49 @@ void wob_batch_free(wob_batch batch);
 wob_status wob_solve_batched(const wob_problem* problems, int32_t n_problems,
                              const wob_tune* tune, void* stream);
 
+/* ------------------------------------------------------------------------- */
+/* Learned control variate (not in the paper; an exact control variate for   */
+/* the single-layer estimator of Sec. 4.3, Table 1 Neumann / Robin rows).    */
+/* ------------------------------------------------------------------------- */
+
+/* Fourier-feature MLP on the matrix cores: z0 = [sin(2 pi B y), cos(2 pi B y)]
+ * (16 frequencies, B is 16 x dim), four hidden layers of 128 with SiLU, scalar
+ * output; bfloat16 weights and activations, binary32 accumulation.  Parameters
+ * are one flat binary32 array: W_1 [128][32], b_1, W_2..W_4 [128][128], b_2..b_4,
+ * W_5 [1][128], b_5 (53,889 values). */
+typedef struct wob_mlp_s* wob_mlp;
+
+int64_t wob_mlp_n_params(void);
+
+/* fourier: HOST 16 x dim; params: HOST wob_mlp_n_params() values; max_batch: the
+ * largest batch wob_mlp_backward / wob_mlp_train_step accept (0 = inference only).
+ * The library owns the device copies (parameters, Adam moments, bfloat16 copies,
+ * workspace).  Synchronous.  Errors: WOB_E_ARG, WOB_E_ALLOC, WOB_E_DEVICE. */
+wob_status wob_mlp_create(int32_t dim, const float* fourier, const float* params, int64_t max_batch,
+                          wob_mlp* out);
+void wob_mlp_free(wob_mlp net);
+/* HOST copies of the binary32 parameters (set also resets the Adam moments). */
+wob_status wob_mlp_get_params(wob_mlp net, float* params);
+wob_status wob_mlp_set_params(wob_mlp net, const float* params);
+
+/* out[i] = f(y_i); y DEVICE n x dim, out DEVICE n. */
+wob_status wob_mlp_forward(wob_mlp net, const float* y, int64_t n, float* out, void* stream);
+
+/* Mean squared error (1/n) sum (f(y_i) - target_i)^2 and its gradient with respect
+ * to every parameter (DEVICE grad, wob_mlp_n_params() floats; loss DEVICE 1 float or
+ * NULL).  Deterministic.  1 <= n <= max_batch. */
+wob_status wob_mlp_backward(wob_mlp net, const float* y, const float* target, int64_t n,
+                            float* grad, float* loss, void* stream);
+
+/* Adam (Kingma and Ba) on the binary32 parameters with bias correction for step
+ * >= 1, then refresh of the bfloat16 copies.  grad DEVICE. */
+wob_status wob_mlp_adam_step(wob_mlp net, const float* grad, int64_t step, float lr, float b1,
+                             float b2, float eps, void* stream);
+
+/* backward + Adam (b1 0.9, b2 0.999, eps 1e-8) with an internal gradient buffer. */
+wob_status wob_mlp_train_step(wob_mlp net, const float* y, const float* target, int64_t n,
+                              int64_t step, float lr, float* loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

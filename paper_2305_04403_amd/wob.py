@@ -25,7 +25,9 @@ DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_path", "wob_solve",
             "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string",
             "wob_batch_create", "wob_batch_launch", "wob_batch_autotune", "wob_batch_get_tune",
-            "wob_batch_free", "wob_solve_batched")
+            "wob_batch_free", "wob_solve_batched", "wob_mlp_n_params", "wob_mlp_create",
+            "wob_mlp_free", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
+            "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step")
 
 
 class WobError(RuntimeError):
@@ -87,6 +89,20 @@ def lib():
     L.wob_solve_batched.argtypes = [C.POINTER(_Problem), i32, C.POINTER(_Tune), vp]
     for name in ("wob_batch_create", "wob_batch_launch", "wob_batch_autotune",
                  "wob_batch_get_tune", "wob_solve_batched"):
+        getattr(L, name).restype = C.c_int
+    L.wob_mlp_n_params.argtypes = []
+    L.wob_mlp_n_params.restype = i64
+    L.wob_mlp_create.argtypes = [i32, vp, vp, i64, C.POINTER(vp)]
+    L.wob_mlp_free.argtypes = [vp]
+    L.wob_mlp_free.restype = None
+    L.wob_mlp_get_params.argtypes = [vp, vp]
+    L.wob_mlp_set_params.argtypes = [vp, vp]
+    L.wob_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.wob_mlp_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.wob_mlp_adam_step.argtypes = [vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.wob_mlp_train_step.argtypes = [vp, vp, vp, i64, i64, C.c_float, vp, vp]
+    for name in ("wob_mlp_create", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
+                 "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step"):
         getattr(L, name).restype = C.c_int
     L.wob_status_string.argtypes = [C.c_int]
     L.wob_status_string.restype = C.c_char_p
@@ -311,6 +327,68 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lib().wob_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The control-variate network on the device (parameters owned by the library)."""
+
+    def __init__(self, dim: int, fourier: np.ndarray, params: np.ndarray, max_batch: int = 0):
+        f = np.ascontiguousarray(fourier, dtype=np.float32)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        n = lib().wob_mlp_n_params()
+        if p.shape != (n,) or f.shape != (16, dim):
+            raise WobError("MLP: wrong parameter or Fourier-matrix shape")
+        h = C.c_void_p()
+        _check(lib().wob_mlp_create(int(dim), f.ctypes.data, p.ctypes.data, int(max_batch), C.byref(h)),
+               "wob_mlp_create")
+        self.handle = h
+        self.dim = dim
+        self.n_params = n
+        self.max_batch = max_batch
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().wob_mlp_get_params(self.handle, out.ctypes.data), "wob_mlp_get_params")
+        return out
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().wob_mlp_set_params(self.handle, p.ctypes.data), "wob_mlp_set_params")
+
+    def forward(self, y, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(y.shape[0], dtype=torch.float32, device=y.device)
+        _check(lib().wob_mlp_forward(self.handle, _dev_ptr(y), y.shape[0], _dev_ptr(out), _stream(stream)),
+               "wob_mlp_forward")
+        return out
+
+    def backward(self, y, target, stream=None):
+        torch = _torch()
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=y.device)
+        loss = torch.empty(1, dtype=torch.float32, device=y.device)
+        _check(lib().wob_mlp_backward(self.handle, _dev_ptr(y), _dev_ptr(target), y.shape[0],
+                                      _dev_ptr(grad), _dev_ptr(loss), _stream(stream)), "wob_mlp_backward")
+        return loss, grad
+
+    def adam_step(self, grad, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        _check(lib().wob_mlp_adam_step(self.handle, _dev_ptr(grad), int(step), lr, b1, b2, eps,
+                                       _stream(stream)), "wob_mlp_adam_step")
+
+    def train_step(self, y, target, step: int, lr: float, loss=None, stream=None):
+        _check(lib().wob_mlp_train_step(self.handle, _dev_ptr(y), _dev_ptr(target), y.shape[0], int(step),
+                                        lr, _dev_ptr(loss), _stream(stream)), "wob_mlp_train_step")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().wob_mlp_free(self.handle)
             self.handle = None
 
     def __del__(self):
