@@ -78,7 +78,10 @@ typedef struct {
   int32_t domain;       /* +1 interior (phi = +1), -1 exterior (phi = -1) */
   int32_t formulation;  /* WOB_F_* */
   int32_t program;      /* WOB_PROG_* */
-  int32_t reserved;     /* must be 0 */
+  int32_t density;      /* 0: the solution u at the points.  1: the boundary unknown (double
+                           layer nu, single layer mu) at points ON the boundary, without its
+                           own emission 2 phi s (the targets of the learned control variate);
+                           not with the direct BIE */
   double params[8];     /* program parameters */
   double self_panel_p;  /* single layer: probability of the in-plane sample on the own
                            primitive where G acts on it (0 selects 1/16); in (0, 1) */
@@ -284,6 +287,33 @@ wob_status wob_mlp_adam_step(wob_mlp net, const float* grad, int64_t step, float
 /* backward + Adam (b1 0.9, b2 0.999, eps 1e-8) with an internal gradient buffer. */
 wob_status wob_mlp_train_step(wob_mlp net, const float* y, const float* target, int64_t n,
                               int64_t step, float lr, float* loss, void* stream);
+
+/* Control-variate table: g[id] = net(centroid of primitive id), DEVICE n_prims floats.
+ * 3D binary32 scenes. */
+wob_status wob_cv_table(wob_scene scene, wob_mlp net, float* g_out, void* stream);
+
+/* Exact control variate for the single-layer estimator (3D, binary32 scenes).
+ * Same paths and picks as wob_solve; every line adds a term whose mean given the
+ * line is zero because the pick is uniform over the m hits: at line 0 the
+ * subtraction w(j) g(T_j), whose mean sum_T g_T int_T G(x0, y) dA is added per
+ * point in closed form; at lines 1..M-2 the all-hits sum of a(h) [2 phi s(y_h) +
+ * g(T_h)] minus the picked w(j) g(T_j); at the last line the all-hits mean of
+ * the last emission.  Unbiased for every table g (DEVICE, n_prims floats by
+ * primitive id); with g close to the boundary unknown minus its emission the
+ * variance falls.  Errors as wob_solve, WOB_E_UNSUPPORTED for other
+ * formulations, 2D or binary64 scenes. */
+wob_status wob_solve_cv(wob_scene scene, const void* points, const int32_t* point_prim,
+                        int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                        uint64_t seed, const float* g, void* mean_out, void* var_out, void* stream);
+
+/* Per-path values of the corrected estimator WITHOUT the per-point add-back. */
+wob_status wob_trace_cv(wob_scene scene, const void* points, const int32_t* point_prim,
+                        int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                        uint64_t seed, const float* g, void* path_out, void* stream);
+
+/* out[p] = sum_T g_T int_T G(x_p, y) dA (closed form per triangle), DEVICE. */
+wob_status wob_cv_addback(wob_scene scene, const float* g, const void* points, int64_t n_points,
+                          void* out, void* stream);
 
 #ifdef __cplusplus
 }

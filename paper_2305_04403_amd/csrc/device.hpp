@@ -270,6 +270,44 @@ __device__ __forceinline__ R self_panel(const PrimGeo<R>& g, const R n[3], const
 }
 
 // --------------------------------------------------------------------------
+// int_T G(x, y) dA over a triangle in closed form: with d = (x - v0).n, per
+// edge (unit tangent t, in-plane outward normal u = t x n) the log term
+// P ln((R+ + s+)/(R- + s-)) (P = A.u, s = A.t for A = vertex - x), minus |d|
+// times the solid angle of the triangle seen from x (Van Oosterom-Strackee).
+// Vertices v[3], edge tangents tt[3][3], edge normals uu[3][3], normal n.
+// --------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R tri_potential(const R v[3][3], const R tt[3][3], const R uu[3][3],
+                                           const R n[3], const R x[3]) {
+  R A[3][3], Rv[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    A[c][0] = v[c][0] - x[0];
+    A[c][1] = v[c][1] - x[1];
+    A[c][2] = v[c][2] - x[2];
+    Rv[c] = sqrt(dot3(A[c], A[c]));
+  }
+  R sum_log = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int c1 = c == 2 ? 0 : c + 1;
+    const R P = dot3(A[c], uu[c]);
+    const R sm = dot3(A[c], tt[c]), sp = dot3(A[c1], tt[c]);
+    // ln((R+ + s+)/(R- + s-)) = ln((R- - s-)/(R+ - s+)): the form without cancellation
+    const R lr = (sp + sm >= (R)0) ? log((Rv[c1] + sp) / (Rv[c] + sm)) : log((Rv[c] - sm) / (Rv[c1] - sp));
+    if (P != (R)0) sum_log += P * lr;
+  }
+  R bc[3];
+  cross3(A[1], A[2], bc);
+  const R num = dot3(A[0], bc);
+  const R den = Rv[0] * Rv[1] * Rv[2] + dot3(A[0], A[1]) * Rv[2] + dot3(A[0], A[2]) * Rv[1] +
+                dot3(A[1], A[2]) * Rv[0];
+  const R omega = fabs((R)2 * atan2(num, den));
+  const R d = fabs(dot3(A[0], n));
+  return (sum_log - d * omega) * (R)(0.25 / 3.14159265358979323846);
+}
+
+// --------------------------------------------------------------------------
 // All-hits line traversal
 // --------------------------------------------------------------------------
 struct WorkCount {

@@ -71,11 +71,12 @@ inline wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t sam
   if (!sc || !bc) return WOB_E_ARG;
   if (bc->domain != 1 && bc->domain != -1) return WOB_E_ARG;
   if (bc->program < WOB_PROG_CONST || bc->program > WOB_PROG_INVDIST) return WOB_E_ARG;
-  if (bc->reserved != 0) return WOB_E_ARG;
+  if (bc->density != 0 && bc->density != 1) return WOB_E_ARG;
   if (samples < 1 || walk_len < 1 || walk_len >= 65535) return WOB_E_ARG;
   const int f = resolve_formulation(sc, bc->formulation);
   if (f == -2) return WOB_E_ARG;
   if (f < 0) return WOB_E_UNSUPPORTED;
+  if (bc->density && f == WOB_F_DIRECT) return WOB_E_UNSUPPORTED;
   double ps = bc->self_panel_p == 0.0 ? 1.0 / 16.0 : bc->self_panel_p;
   if (!(ps > 0.0 && ps < 1.0)) return WOB_E_ARG;
   p->form = f;
@@ -108,6 +109,7 @@ wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void*
   a.k1 = (uint32_t)(seed >> 32);
   a.problem = 0;
   a.lpp_shift = lpp_shift_for(samples, kSolveBlock);
+  a.density = bc->density;
   a.form = pl.form == WOB_F_DOUBLE_LAYER ? wob::F_DL : (pl.form == WOB_F_DIRECT ? wob::F_DIRECT : wob::F_SL);
   return a;
 }

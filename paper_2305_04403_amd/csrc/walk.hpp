@@ -22,6 +22,8 @@ struct WalkArgs {
   uint32_t problem;           // problem index (counter word 2, bits 24..31)
   int32_t lpp_shift;          // log2 of lanes per point (6 .. log2 of the block size)
   int32_t form;               // F_DL / F_DIRECT / F_SL (read by the batched kernel)
+  int32_t density;            // estimate the boundary unknown at boundary points (no own emission)
+  const R* cv_g;              // control-variate table per caller primitive id (single layer), or null
   R* mean_out;
   R* var_out;
   R* path_out;
@@ -64,7 +66,7 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
   if (prim0 < -1 || prim0 >= a.scene.n_prims) return (R)NAN;
   int32_t cur_idx = prim0 >= 0 ? a.scene.leaf_of_id[prim0] : -1;
   R x[3] = {x0[0], x0[1], x0[2]};
-  if (FORM == F_DL && cur_idx >= 0) {
+  if (FORM == F_DL && cur_idx >= 0 && !a.density) {
     // Table 1: on the boundary the Dirichlet solution is the given value
     const PrimGeo<R> g = load_prim<R, D>(a.scene, cur_idx);
     const R nz[3] = {0, 0, 0};
@@ -84,9 +86,12 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
       gc = load_prim<R, D>(a.scene, cur_idx);
       load_normal<R, D>(a.scene, cur_idx, nc);
     }
+    // step 0 from an evaluation point uses the representation formula; in
+    // density mode x0 is itself a vertex of the boundary recursion
+    const bool first = i == 0 && !a.density;
     bool mixture = false, use_self = false;
     if constexpr (FORM == F_SL) {
-      mixture = on_gamma && (i == 0 || gc.kind == K_ROBIN);
+      mixture = on_gamma && (first || gc.kind == K_ROBIN);
       use_self = mixture && (r0.z >> 8) < a.self_thr;
     }
     R y[3], w;
@@ -94,7 +99,7 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
     if (use_self) {
       const U4 r1 = philox(path, point, z | 1u, 0u, a.k0, a.k1);
       const R gp = self_panel<R, D>(gc, nc, x, unit<R>(r1.x), unit<R>(r1.y), y);
-      w = (i == 0 ? gp : (R)-2 * phi * gc.alpha * gp) / a.self_p;
+      w = (first ? gp : (R)-2 * phi * gc.alpha * gp) / a.self_p;
       next_idx = cur_idx;
       if (TRACE && vprim) vprim[i] = -2 - gc.id;
     } else {
@@ -132,7 +137,7 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
         normal_dir<R, D>(gy, nd);
         const R sg = sgn_t * dot3(d, nd) > (R)0 ? (R)1 : (R)-1;  // sgn(cos theta_y)
         if constexpr (FORM == F_DL)
-          w = (i == 0 && !on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
+          w = (first && !on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
         else
           w = on_gamma ? phi * mm * sg : (R)0.5 * phi * mm * sg;
       } else {
@@ -140,7 +145,7 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
         load_normal<R, D>(a.scene, h.idx, ny);
         const R rho = fabs(h.t);
         const R acy = fabs(dot3(d, ny));
-        if (i == 0) {
+        if (first) {
           // G / p
           w = D == 3 ? mm * rho / ((R)2 * acy) : -mm * rho * log(rho) / ((R)2 * acy);
         } else {
@@ -168,6 +173,173 @@ __device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, u
   return acc;
 }
 
+
+// ---------------------------------------------------------------------------
+// Learned control variate, single layer, 3D (not in the paper).  Same paths
+// as run_path (same draws, same picks); the value adds, at every line, a term
+// with zero mean given the line (the pick is uniform over the m hits):
+//   line 0:        - w(j) g(T_j); its mean sum_T g_T int_T G(x0, y) dA is
+//                  added per point by the add-back kernel (a self-panel
+//                  sample at a boundary x0 subtracts w g(T0) the same way);
+//   lines 1..M-2:  sum_h a(h) [2 phi s(y_h) + g(T_h)] - w(j) g(T_j)
+//                  (the picked emission is kept, the rest of F cancels);
+//   line M-1:      sum_h a(h) phi s(y_h), the exact conditional mean of the
+//                  last emission, so no pick is needed;
+// with a(h) = w(h) / m the weight of hit h without the 1/m of the pick.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct CvAcc {
+  int32_t m;
+  uint32_t key;
+  int32_t id, idx;
+  R u, v, t;
+  R sum;  // sum over hits of a(h) F(y_h)
+};
+
+template <typename R, bool COUNT>
+__device__ __forceinline__ void trace_line_cv(const WalkArgs<R, 3>& a, const R x[3], const R d[3],
+                                              int32_t exclude, bool select, bool want_sum,
+                                              bool first, bool last, R mixf, const PrimGeo<R>& gc,
+                                              const R nc[3], uint32_t kc0, uint32_t kc1,
+                                              uint32_t kc2, CvAcc<R>& h, WorkCount& wc) {
+  const SceneView<R, 3>& s = a.scene;
+  const R phi = a.phi;
+  R inv[3], ox[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    inv[k] = safe_inv(d[k]);
+    ox[k] = -x[k] * inv[k];
+  }
+  h.m = 0;
+  h.key = 0xffffffffu;
+  h.id = 0x7fffffff;
+  h.idx = -1;
+  h.u = h.v = h.t = 0;
+  h.sum = 0;
+  if (COUNT) wc.lines += 1;
+  int32_t i = 0;
+  while (i < s.n_nodes) {
+    const typename Rec<R, 3>::Node node = s.nodes[i];
+    if (COUNT) wc.nodes += 1;
+    if (line_box<R, 3>(node, inv, ox)) {
+      if (node.child >= 0) {
+        i = node.child;
+        continue;
+      }
+      const int32_t code = -1 - node.child;
+      const int32_t first_p = code >> 3, count = (code & 7) + 1;
+      for (int32_t j = first_p; j < first_p + count; ++j) {
+        if (j == exclude) continue;
+        if (COUNT) wc.prims += 1;
+        const PrimGeo<R> g = load_prim<R, 3>(s, j);
+        R t, u, v;
+        if (!hit_prim<R, 3>(g, x, d, t, u, v)) continue;
+        if (COUNT) wc.hits += 1;
+        h.m += 1;
+        if (select) {
+          const uint32_t key = philox(kc0, kc1, kc2, (uint32_t)g.id, a.k0, a.k1).x;
+          if (key < h.key || (key == h.key && g.id < h.id)) {
+            h.key = key;
+            h.id = g.id;
+            h.idx = j;
+            h.u = u;
+            h.v = v;
+            h.t = t;
+          }
+        }
+        if (want_sum) {
+          R y[3], n[3];
+          hit_point(g, u, v, y);
+          load_normal<R, 3>(s, j, n);
+          const R rho = fabs(t);
+          const R acy = fabs(dot3(d, n));
+          const R sgn_t = t > (R)0 ? (R)1 : (R)-1;
+          R ah = first ? rho / ((R)2 * acy) : -phi * (sgn_t * dot3(d, nc) + gc.alpha * rho) / acy;
+          ah *= mixf;
+          const R sh = boundary_datum<R, 3>(a.prog, g, n, y);
+          const R F = last ? phi * sh : (R)2 * phi * sh + a.cv_g[g.id];
+          h.sum += ah * F;
+        }
+      }
+    }
+    i = node.skip;
+  }
+}
+
+template <typename R, bool TRACE, bool COUNT>
+__device__ __forceinline__ R run_path_cv(const WalkArgs<R, 3>& a, uint32_t point, uint32_t path,
+                                         const R x0[3], int32_t prim0, WorkCount& wc) {
+  const R phi = a.phi;
+  if (prim0 < -1 || prim0 >= a.scene.n_prims) return (R)NAN;
+  int32_t cur_idx = prim0 >= 0 ? a.scene.leaf_of_id[prim0] : -1;
+  R x[3] = {x0[0], x0[1], x0[2]};
+  R W = 1, acc = 0;
+  const uint32_t zbase = a.problem << 24;
+  for (int i = 0; i < a.M; ++i) {
+    const bool on_gamma = cur_idx >= 0, last = i == a.M - 1;
+    const uint32_t z = zbase | ((uint32_t)i << 8);
+    const U4 r0 = philox(path, point, z, 0u, a.k0, a.k1);
+    R d[3];
+    direction<R, 3>(r0.x, r0.y, d);
+    PrimGeo<R> gc;
+    R nc[3] = {0, 0, 0};
+    if (on_gamma) {
+      gc = load_prim<R, 3>(a.scene, cur_idx);
+      load_normal<R, 3>(a.scene, cur_idx, nc);
+    } else {
+      gc.alpha = 0;
+      gc.id = -1;
+      gc.kind = 0;
+    }
+    const bool mixture = on_gamma && (i == 0 || gc.kind == K_ROBIN);
+    const bool use_self = mixture && (r0.z >> 8) < a.self_thr;
+    R y[3], Wn;
+    int32_t next_idx;
+    if (use_self) {
+      const U4 r1 = philox(path, point, z | 1u, 0u, a.k0, a.k1);
+      const R gp = self_panel<R, 3>(gc, nc, x, unit<R>(r1.x), unit<R>(r1.y), y);
+      Wn = W * (i == 0 ? gp : (R)-2 * phi * gc.alpha * gp) / a.self_p;
+      next_idx = cur_idx;
+      if (i == 0 && !last) acc -= Wn * a.cv_g[gc.id];
+      acc += Wn * (last ? phi : (R)2 * phi) * boundary_datum<R, 3>(a.prog, gc, nc, y);
+    } else {
+      const R mixf = mixture ? (R)1 / ((R)1 - a.self_p) : (R)1;
+      CvAcc<R> h;
+      trace_line_cv<R, COUNT>(a, x, d, cur_idx, !last, i > 0 || last, i == 0, last, mixf, gc, nc,
+                              path, point, z | 2u, h, wc);
+      if (h.m == 0) break;
+      if (last) {
+        acc += W * h.sum;
+        break;
+      }
+      const PrimGeo<R> gy = load_prim<R, 3>(a.scene, h.idx);
+      hit_point(gy, h.u, h.v, y);
+      R ny[3];
+      load_normal<R, 3>(a.scene, h.idx, ny);
+      const R rho = fabs(h.t);
+      const R acy = fabs(dot3(d, ny));
+      const R sgn_t = h.t > (R)0 ? (R)1 : (R)-1;
+      R aj = i == 0 ? rho / ((R)2 * acy) : -phi * (sgn_t * dot3(d, nc) + gc.alpha * rho) / acy;
+      aj *= mixf;
+      Wn = W * aj * (R)h.m;
+      if (i == 0) {
+        acc -= Wn * a.cv_g[gy.id];
+        acc += Wn * (R)2 * phi * boundary_datum<R, 3>(a.prog, gy, ny, y);
+      } else {
+        acc += W * h.sum;
+        acc -= Wn * a.cv_g[gy.id];
+      }
+      next_idx = h.idx;
+    }
+    W = Wn;
+    x[0] = y[0];
+    x[1] = y[1];
+    x[2] = y[2];
+    cur_idx = next_idx;
+  }
+  return acc;
+}
+
 __device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, double nb,
                                            double meanb, double m2b) {
   if (nb == 0.0) return;
@@ -187,7 +359,7 @@ __device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, 
 // One block's share of a solve: BLOCK lanes cover BLOCK >> lpp_shift points,
 // the N paths of a point on 1 << lpp_shift consecutive lanes (a lane loops over
 // paths k, k + lpp, ...).  `red` is BLOCK / 64 x 3 doubles of LDS.
-template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK>
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK, bool CV = false>
 __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t block_index,
                                            double (*red)[3]) {
   const int tid = threadIdx.x;
@@ -207,7 +379,11 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       int32_t* vp = (TRACE && a.vtx_prim) ? a.vtx_prim + item * a.L : nullptr;
       int32_t* vm = (TRACE && a.vtx_m) ? a.vtx_m + item * a.L : nullptr;
       const uint32_t pid = a.point_ids ? a.point_ids[point] : (uint32_t)point;
-      const R v = run_path<R, D, FORM, TRACE, COUNT>(a, pid, (uint32_t)k, x0, prim0, vp, vm, wc);
+      R v;
+      if constexpr (CV && D == 3 && FORM == F_SL)
+        v = run_path_cv<R, TRACE, COUNT>(a, pid, (uint32_t)k, x0, prim0, wc);
+      else
+        v = run_path<R, D, FORM, TRACE, COUNT>(a, pid, (uint32_t)k, x0, prim0, vp, vm, wc);
       if (TRACE) a.path_out[item] = v;
       n += 1.0;
       const double dv = (double)v - mean;
@@ -257,10 +433,97 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   }
 }
 
-template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK>
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK, bool CV = false>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs<R, D> a) {
   __shared__ double red[BLOCK / 64][3];
-  walk_block<R, D, FORM, TRACE, COUNT, BLOCK>(a, blockIdx.x, red);
+  walk_block<R, D, FORM, TRACE, COUNT, BLOCK, CV>(a, blockIdx.x, red);
+}
+
+// Add-back of the control variate: out[p] (+)= sum_T g_T int_T G(x_p, y) dA.
+// Every workgroup streams all triangles through LDS in tiles of 256 (edge
+// frames precomputed on load); each lane keeps 4 points in registers.
+template <typename R>
+__global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, const R* __restrict__ g_by_id,
+                                                         const R* __restrict__ points, int64_t n,
+                                                         R* out, int accumulate) {
+  constexpr int TILE = 256, PPT = 4, NF = 31;
+  __shared__ R tile[TILE * NF];
+  const int tid = threadIdx.x;
+  R x[PPT][3], acc[PPT];
+  int64_t pidx[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    pidx[k] = ((int64_t)blockIdx.x * PPT + k) * 256 + tid;
+    const int64_t q = pidx[k] < n ? pidx[k] : 0;
+    x[k][0] = n > 0 ? points[q * 3 + 0] : (R)0;
+    x[k][1] = n > 0 ? points[q * 3 + 1] : (R)0;
+    x[k][2] = n > 0 ? points[q * 3 + 2] : (R)0;
+    acc[k] = 0;
+  }
+  for (int32_t t0 = 0; t0 < s.n_prims; t0 += TILE) {
+    __syncthreads();
+    const int32_t j = t0 + tid;
+    R* T = tile + tid * NF;
+    if (j < s.n_prims) {
+      const PrimGeo<R> g = load_prim<R, 3>(s, j);
+      R nn[3];
+      load_normal<R, 3>(s, j, nn);
+      R v[3][3];
+      for (int k = 0; k < 3; ++k) {
+        v[0][k] = g.v0[k];
+        v[1][k] = g.v0[k] + g.e1[k];
+        v[2][k] = g.v0[k] + g.e2[k];
+      }
+      for (int c = 0; c < 3; ++c) {
+        const int c1 = c == 2 ? 0 : c + 1;
+        R e[3] = {v[c1][0] - v[c][0], v[c1][1] - v[c][1], v[c1][2] - v[c][2]};
+        const R il = rsqrt_<R>(dot3(e, e));
+        R tt[3] = {e[0] * il, e[1] * il, e[2] * il}, uu[3];
+        cross3(tt, nn, uu);
+        for (int k = 0; k < 3; ++k) {
+          T[c * 3 + k] = v[c][k];
+          T[9 + c * 3 + k] = tt[k];
+          T[18 + c * 3 + k] = uu[k];
+        }
+      }
+      T[27] = nn[0];
+      T[28] = nn[1];
+      T[29] = nn[2];
+      T[30] = g_by_id[g.id];
+    }
+    __syncthreads();
+    const int cnt = s.n_prims - t0 < TILE ? s.n_prims - t0 : TILE;
+    for (int q = 0; q < cnt; ++q) {
+      const R* P = tile + q * NF;
+      R v[3][3], tt[3][3], uu[3][3], nn[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          v[c][k] = P[c * 3 + k];
+          tt[c][k] = P[9 + c * 3 + k];
+          uu[c][k] = P[18 + c * 3 + k];
+        }
+      nn[0] = P[27];
+      nn[1] = P[28];
+      nn[2] = P[29];
+      const R gq = P[30];
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) acc[k] += gq * tri_potential<R>(v, tt, uu, nn, x[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+    if (pidx[k] < n) out[pidx[k]] = accumulate ? out[pidx[k]] + acc[k] : acc[k];
+}
+
+// Centroid of every primitive, written at its caller id (3D).
+template <typename R>
+__global__ void centroid_kernel(SceneView<R, 3> s, float* out) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= s.n_prims) return;
+  const PrimGeo<R> g = load_prim<R, 3>(s, j);
+  for (int k = 0; k < 3; ++k) out[(int64_t)g.id * 3 + k] = (float)(g.v0[k] + (g.e1[k] + g.e2[k]) / (R)3);
 }
 
 // Persistent batched solve: every block pulls tiles (problem, block of points)

@@ -133,6 +133,17 @@ void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
   constexpr int B = kSolveBlock;
   const int ppb = B >> a.lpp_shift;
   const dim3 grid((unsigned)((a.n_points + ppb - 1) / ppb)), block(B);
+  if constexpr (D == 3 && FORM == wob::F_SL) {
+    if (a.cv_g) {
+      if (mode == MODE_SOLVE)
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, true>), grid, block, 0, st, a);
+      else if (mode == MODE_TRACE)
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, true>), grid, block, 0, st, a);
+      else
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B, true>), grid, block, 0, st, a);
+      return;
+    }
+  }
   if (mode == MODE_SOLVE)
     hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B>), grid, block, 0, st, a);
   else if (mode == MODE_TRACE)
@@ -152,10 +163,13 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
                     const wob_bc* bc, int32_t samples, int32_t walk_len, uint64_t seed,
                     const uint32_t* point_ids, void* mean_out, void* var_out, void* path_out,
                     int32_t* vtx_prim, int32_t* vtx_m, uint64_t* counters, int mode,
-                    void* stream) {
+                    void* stream, const float* cv_g = nullptr) {
   Plan pl;
   wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
   if (s != WOB_OK) return s;
+  if (cv_g && (sc->dim != 3 || sc->precision != WOB_F32 || pl.form != WOB_F_SINGLE_LAYER ||
+               bc->density))
+    return WOB_E_UNSUPPORTED;
   if (n_points < 0 || (n_points > 0 && !points)) return WOB_E_ARG;
   if (n_points >= (int64_t)1 << 32) return WOB_E_ARG;  // point index is a 32-bit counter word
   if (mode == MODE_SOLVE && n_points > 0 && !mean_out) return WOB_E_ARG;
@@ -170,6 +184,7 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
       a.mean_out = (float*)mean_out; a.var_out = (float*)var_out; a.path_out = (float*)path_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
+      a.cv_g = cv_g;
       launch_walk<float, 3>(a, pl.form, mode, st);
     } else {
       auto a = make_args<float, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
@@ -352,6 +367,55 @@ wob_status wob_count_work(wob_scene sc, const void* points, const int32_t* point
                           uint64_t seed, uint64_t* counters, void* stream) {
   return run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, nullptr, nullptr,
                   nullptr, nullptr, nullptr, nullptr, counters, MODE_COUNT, stream);
+}
+
+wob_status wob_cv_addback(wob_scene sc, const float* g, const void* points, int64_t n_points,
+                          void* out, void* stream) {
+  if (!sc || n_points < 0 || (n_points > 0 && (!g || !points || !out))) return WOB_E_ARG;
+  if (sc->dim != 3 || sc->precision != WOB_F32) return WOB_E_UNSUPPORTED;
+  if (n_points == 0) return WOB_OK;
+  const int64_t blocks = (n_points + 1023) / 1024;
+  hipLaunchKernelGGL((wob::cv_addback_kernel<float>), dim3((unsigned)blocks), dim3(256), 0,
+                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points, n_points,
+                     (float*)out, 0);
+  return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
+}
+
+wob_status wob_solve_cv(wob_scene sc, const void* points, const int32_t* point_prim,
+                        int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                        uint64_t seed, const float* g, void* mean_out, void* var_out, void* stream) {
+  if (!g) return WOB_E_ARG;
+  wob_status s = run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, nullptr,
+                          mean_out, var_out, nullptr, nullptr, nullptr, nullptr, MODE_SOLVE, stream, g);
+  if (s != WOB_OK || n_points == 0 || walk_len < 2) return s;
+  const int64_t blocks = (n_points + 1023) / 1024;
+  hipLaunchKernelGGL((wob::cv_addback_kernel<float>), dim3((unsigned)blocks), dim3(256), 0,
+                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points, n_points,
+                     (float*)mean_out, 1);
+  return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
+}
+
+wob_status wob_trace_cv(wob_scene sc, const void* points, const int32_t* point_prim,
+                        int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                        uint64_t seed, const float* g, void* path_out, void* stream) {
+  if (!g) return WOB_E_ARG;
+  return run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, nullptr, nullptr,
+                  nullptr, path_out, nullptr, nullptr, nullptr, MODE_TRACE, stream, g);
+}
+
+wob_status wob_cv_table(wob_scene sc, wob_mlp net, float* g_out, void* stream) {
+  if (!sc || !net || !g_out) return WOB_E_ARG;
+  if (sc->dim != 3 || sc->precision != WOB_F32) return WOB_E_UNSUPPORTED;
+  float* cen = nullptr;
+  if (hipMalloc((void**)&cen, sizeof(float) * 3 * sc->n_prims) != hipSuccess) return WOB_E_ALLOC;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL((wob::centroid_kernel<float>), dim3((unsigned)((sc->n_prims + 255) / 256)),
+                     dim3(256), 0, st, view<float, 3>(sc), cen);
+  wob_status s = hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
+  if (s == WOB_OK) s = wob_mlp_forward(net, cen, sc->n_prims, g_out, stream);
+  if (hipStreamSynchronize(st) != hipSuccess && s == WOB_OK) s = WOB_E_DEVICE;
+  (void)hipFree(cen);
+  return s;
 }
 
 wob_status wob_intersect_all(wob_scene sc, const void* orig, const void* dir,

@@ -27,7 +27,8 @@ EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_pa
             "wob_batch_create", "wob_batch_launch", "wob_batch_autotune", "wob_batch_get_tune",
             "wob_batch_free", "wob_solve_batched", "wob_mlp_n_params", "wob_mlp_create",
             "wob_mlp_free", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
-            "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step")
+            "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
+            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback")
 
 
 class WobError(RuntimeError):
@@ -36,7 +37,7 @@ class WobError(RuntimeError):
 
 class _BC(C.Structure):
     _fields_ = [("domain", C.c_int32), ("formulation", C.c_int32), ("program", C.c_int32),
-                ("reserved", C.c_int32), ("params", C.c_double * 8), ("self_panel_p", C.c_double)]
+                ("density", C.c_int32), ("params", C.c_double * 8), ("self_panel_p", C.c_double)]
 
 
 class _SceneInfo(C.Structure):
@@ -102,7 +103,14 @@ def lib():
     L.wob_mlp_adam_step.argtypes = [vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.wob_mlp_train_step.argtypes = [vp, vp, vp, i64, i64, C.c_float, vp, vp]
     for name in ("wob_mlp_create", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
-                 "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step"):
+                 "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
+            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback"):
+        getattr(L, name).restype = C.c_int
+    L.wob_cv_table.argtypes = [vp, vp, vp, vp]
+    L.wob_solve_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp]
+    L.wob_trace_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
+    L.wob_cv_addback.argtypes = [vp, vp, vp, i64, vp, vp]
+    for name in ("wob_cv_table", "wob_solve_cv", "wob_trace_cv", "wob_cv_addback"):
         getattr(L, name).restype = C.c_int
     L.wob_status_string.argtypes = [C.c_int]
     L.wob_status_string.restype = C.c_char_p
@@ -127,10 +135,12 @@ class BC:
     program: int = PROG_CONST
     params: Sequence[float] = ()
     self_panel_p: float = 1.0 / 16.0
+    density: bool = False
 
     def c(self) -> _BC:
         b = _BC()
-        b.domain, b.formulation, b.program, b.reserved = self.domain, self.formulation, self.program, 0
+        b.domain, b.formulation, b.program = self.domain, self.formulation, self.program
+        b.density = int(bool(self.density))
         for i, v in enumerate(self.params):
             b.params[i] = float(v)
         b.self_panel_p = float(self.self_panel_p)
@@ -396,3 +406,48 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------- control variate
+
+def cv_table(scene: Scene, net: "MLP", stream=None):
+    torch = _torch()
+    g = torch.empty(scene.info()["n_prims"], dtype=torch.float32, device="cuda")
+    _check(lib().wob_cv_table(scene.handle, net.handle, _dev_ptr(g), _stream(stream)), "wob_cv_table")
+    return g
+
+
+def solve_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed: int = 0,
+             point_prim=None, want_var: bool = True, stream=None, out=None):
+    torch = _torch()
+    P = points.shape[0]
+    if out is None:
+        mean = torch.empty(P, dtype=scene.dtype, device=points.device)
+        var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
+    else:
+        mean, var = out
+    b = bc.c()
+    _check(lib().wob_solve_cv(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
+                              int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(mean),
+                              _dev_ptr(var), _stream(stream)), "wob_solve_cv")
+    return mean, var
+
+
+def trace_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed: int = 0,
+             point_prim=None, stream=None):
+    torch = _torch()
+    P = points.shape[0]
+    path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
+    b = bc.c()
+    _check(lib().wob_trace_cv(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
+                              int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(path),
+                              _stream(stream)), "wob_trace_cv")
+    return path
+
+
+def cv_addback(scene: Scene, g, points, stream=None):
+    torch = _torch()
+    out = torch.empty(points.shape[0], dtype=scene.dtype, device=points.device)
+    _check(lib().wob_cv_addback(scene.handle, _dev_ptr(g), _dev_ptr(points), points.shape[0],
+                                _dev_ptr(out), _stream(stream)), "wob_cv_addback")
+    return out

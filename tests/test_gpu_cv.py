@@ -1,0 +1,138 @@
+"""Learned control variate on the GPU against the FP64 oracle: closed-form
+add-back, per-path corrected values, density-mode targets, the table from the
+network, and unbiasedness of the corrected solve."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_04403_amd import inputs as I
+from tests import parity as PT
+from tests.test_oracle_cv_pins import rand_net
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def W():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_04403_amd import wob
+    wob.lib()
+    return wob
+
+
+@pytest.fixture(scope="module")
+def tori():
+    return I.config_tori(grid_n=16, n_points=60, boundary_frac=0.25, samples=64, walk_len=4)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def bcs(W, w, **kw):
+    b = w.bc
+    return (W.BC(b["domain"], b["formulation"], b["program"], tuple(b["params"]), **kw),
+            oracle.make_bc(b["domain"], b["formulation"], b["program"], b["params"], **kw))
+
+
+def test_addback_matches_oracle(W, tori):
+    rng = np.random.default_rng(1)
+    g = PT.f32(rng.standard_normal(tori.mesh.n_prims) + 0.5)
+    scene = W.Scene(tori.mesh, W.F32)
+    out = W.cv_addback(scene, dev(g), dev(tori.points))
+    torch.cuda.synchronize()
+    om = oracle.OracleMesh(tori.mesh)
+    ref = oracle.cv_addback(om, g, tori.points)
+    scale = oracle.cv_addback(om, np.abs(g), tori.points)
+    err = np.abs(out.cpu().double().numpy() - ref) / scale
+    print(f"add-back max error / sum |g| potential: {err.max():.2e}")
+    assert err.max() < 2e-5
+    scene.close()
+
+
+def test_trace_cv_matches_oracle(W, tori):
+    rng = np.random.default_rng(2)
+    g = PT.f32(rng.standard_normal(tori.mesh.n_prims))
+    scene = W.Scene(tori.mesh, W.F32)
+    wb, ob = bcs(W, tori)
+    P, N, M = tori.points.shape[0], 64, 4
+    val = W.trace_cv(scene, dev(tori.points), wb, N, M, g=dev(g), seed=3,
+                     point_prim=dev(tori.point_prim, torch.int32))
+    torch.cuda.synchronize()
+    ip, ik = np.repeat(np.arange(P), N), np.tile(np.arange(N), P)
+    ref = oracle.trace_cv(oracle.OracleMesh(tori.mesh), tori.points, tori.point_prim, ob, M, 3, g, ip, ik)
+    plain = oracle.trace(oracle.OracleMesh(tori.mesh), tori.points, tori.point_prim, ob, M, 3, ip, ik,
+                         want_pos=False)
+    v = val.cpu().double().numpy().reshape(-1)
+    ok = plain["graze"] >= PT.GRAZE
+    scale = np.abs(ref) + np.median(np.abs(ref)) + plain["abs_sum"]
+    tol = scale * (PT.RTOL_F32 * 10 + PT.COS_ULP_F32 / np.maximum(plain["cond_cos"], 1e-300))
+    bad = ok & (np.abs(v - ref) > tol)
+    print(f"cv paths {len(v)}, grazing {int((~ok).sum())}, over tolerance {int(bad.sum())}, "
+          f"median rel {np.median(np.abs(v - ref)[ok] / scale[ok]):.2e}")
+    assert (~ok).mean() < 0.01
+    assert bad.sum() <= 0.005 * ok.sum() + 1
+    scene.close()
+
+
+def test_density_mode_paths_match_oracle(W, tori):
+    """Training targets: the boundary unknown at boundary points, without its emission."""
+    scene = W.Scene(tori.mesh, W.F32)
+    wb, ob = bcs(W, tori, density=True)
+    pts, prim = I.mesh_surface_points(tori.mesh, 48, 7)
+    pts = PT.f32(pts)
+    val, vprim, vm = W.trace(scene, dev(pts), wb, 32, 3, 9, point_prim=dev(prim, torch.int32))
+    torch.cuda.synchronize()
+    orc = PT.oracle_all_paths(oracle.OracleMesh(tori.mesh), pts, prim, ob, 32, 3, 9)
+    res = PT.compare_paths(orc, val.cpu().double().numpy().reshape(-1), vprim.cpu().numpy().reshape(-1, 3),
+                           vm.cpu().numpy().reshape(-1, 3), PT.RTOL_F32)
+    print(res.summary())
+    assert res.n_graze <= 0.01 * res.n + 1
+    assert res.n_vertex_mismatch <= 0.005 * res.n_checked + 1
+    assert res.n_value_mismatch <= 0.005 * res.n_checked + 1
+    scene.close()
+
+
+def test_cv_table_is_network_at_centroids(W, tori):
+    params, B = rand_net(21)
+    params, B = PT.f32(params), PT.f32(B)
+    scene = W.Scene(tori.mesh, W.F32)
+    net = W.MLP(3, B, params)
+    g = W.cv_table(scene, net).cpu().double().numpy()
+    v = tori.mesh.verts[tori.mesh.prims]
+    cen = PT.f32(v.mean(axis=1))
+    ref = oracle.mlp_forward(params, B, cen, bf16=True)
+    assert np.linalg.norm(g - ref) <= 2e-3 * np.linalg.norm(ref)
+    net.close()
+    scene.close()
+
+
+def test_solve_cv_is_unbiased_on_gpu(W, tori):
+    """Corrected and plain solves on the same points: the per-point difference of
+    the means is within 4.5 standard errors of zero, for an arbitrary table."""
+    rng = np.random.default_rng(5)
+    g = PT.f32(rng.standard_normal(tori.mesh.n_prims) * 2.0)
+    scene = W.Scene(tori.mesh, W.F32)
+    wb, _ = bcs(W, tori)
+    pts = dev(tori.points)
+    pp = dev(tori.point_prim, torch.int32)
+    N = 16384
+    mp, vp = W.solve(scene, pts, wb, N, 4, seed=1, point_prim=pp)
+    mc, vc = W.solve_cv(scene, pts, wb, N, 4, g=dev(g), seed=2, point_prim=pp)
+    torch.cuda.synchronize()
+    d = mc.double().cpu().numpy() - mp.double().cpu().numpy()
+    se = np.sqrt((vp.double().cpu().numpy() + vc.double().cpu().numpy()) / N)
+    z = d / se
+    print(f"max |z| = {np.abs(z).max():.2f}")
+    assert np.abs(z).max() < 4.5
+    # the mean of traced corrected paths plus the add-back is the solve's mean
+    val = W.trace_cv(scene, pts, wb, 256, 4, g=dev(g), seed=7, point_prim=pp)
+    add = W.cv_addback(scene, dev(g), pts)
+    m2, _ = W.solve_cv(scene, pts, wb, 256, 4, g=dev(g), seed=7, point_prim=pp)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(m2.cpu().numpy(), val.double().mean(dim=1).cpu().numpy() + add.cpu().numpy(),
+                               rtol=1e-5, atol=1e-5)
+    scene.close()
