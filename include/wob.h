@@ -288,6 +288,12 @@ wob_status wob_mlp_adam_step(wob_mlp net, const float* grad, int64_t step, float
 wob_status wob_mlp_train_step(wob_mlp net, const float* y, const float* target, int64_t n,
                               int64_t step, float lr, float* loss, void* stream);
 
+/* n area-uniform points on the boundary (DEVICE n * dim, scene precision) and the
+ * primitive each lies on (DEVICE n int32), from Philox counter (i, 0xffffffff,
+ * 0xffffff03, 0) with key seed: the training locations of the control variate. */
+wob_status wob_sample_boundary(wob_scene scene, int64_t n, uint64_t seed, void* points_out,
+                               int32_t* prim_out, void* stream);
+
 /* Control-variate table: g[id] = net(centroid of primitive id), DEVICE n_prims floats.
  * 3D binary32 scenes. */
 wob_status wob_cv_table(wob_scene scene, wob_mlp net, float* g_out, void* stream);

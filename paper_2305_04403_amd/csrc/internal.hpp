@@ -17,6 +17,7 @@ struct wob_scene_s {
   void* d_prims = nullptr;
   void* d_normals = nullptr;
   int32_t* d_leaf_of_id = nullptr;
+  float* d_area_cdf = nullptr;  // leaf order, cumulative area / total (last entry 1)
   int64_t node_bytes = 0, prim_bytes = 0, device_bytes = 0;
   int32_t n_dirichlet = 0, n_neumann = 0, n_robin = 0;
 };

@@ -517,6 +517,35 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
     if (pidx[k] < n) out[pidx[k]] = accumulate ? out[pidx[k]] + acc[k] : acc[k];
 }
 
+// Area-uniform points on the boundary: primitive by binary search of the
+// area CDF, then a uniform point on it.  Philox counter (i, 0xffffffff,
+// 0xffffff03, 0): block 3 of the last problem / line slot, a stream the walk
+// never draws.
+template <typename R, int D>
+__global__ void sample_boundary_kernel(SceneView<R, D> s, const float* __restrict__ cdf, int64_t n,
+                                       uint32_t k0, uint32_t k1, R* points, int32_t* prim_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const U4 r = philox((uint32_t)i, 0xffffffffu, 0xffffff03u, 0u, k0, k1);
+  const float u = unit<float>(r.x);
+  int32_t lo = 0, hi = s.n_prims - 1;
+  while (lo < hi) {  // first leaf index with cdf > u
+    const int32_t mid = (lo + hi) >> 1;
+    if (cdf[mid] > u) hi = mid;
+    else lo = mid + 1;
+  }
+  const PrimGeo<R> g = load_prim<R, D>(s, lo);
+  R a = unit<R>(r.y), b = D == 3 ? unit<R>(r.z) : (R)0;
+  if (a + b > (R)1) {
+    a = (R)1 - a;
+    b = (R)1 - b;
+  }
+  R y[3];
+  hit_point(g, a, b, y);
+  for (int k = 0; k < D; ++k) points[i * D + k] = y[k];
+  prim_out[i] = g.id;
+}
+
 // Centroid of every primitive, written at its caller id (3D).
 template <typename R>
 __global__ void centroid_kernel(SceneView<R, 3> s, float* out) {

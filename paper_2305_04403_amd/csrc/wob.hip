@@ -72,6 +72,7 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   std::vector<Prim> recs((size_t)T);
   std::vector<R> normals((size_t)T * 4, (R)0);
   std::vector<int32_t> leaf_of_id((size_t)T);
+  std::vector<double> area((size_t)T, 0.0);
   for (int64_t j = 0; j < T; ++j) {
     const int32_t id = bvh.order[j];
     leaf_of_id[id] = (int32_t)j;
@@ -96,6 +97,7 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
                      e1d[0] * e2d[1] - e1d[1] * e2d[0]};
       const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
       for (int a = 0; a < 3; ++a) normals[4 * j + a] = (R)(n[a] / l);
+      area[j] = 0.5 * l;
     } else {
       for (int a = 0; a < 2; ++a) {
         const double v0 = v[(int64_t)ix[0] * 2 + a], v1 = v[(int64_t)ix[1] * 2 + a];
@@ -106,6 +108,7 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
       const double l = std::sqrt(e1d[0] * e1d[0] + e1d[1] * e1d[1]);
       normals[4 * j + 0] = (R)(e1d[1] / l);
       normals[4 * j + 1] = (R)(-e1d[0] / l);
+      area[j] = l;
     }
   }
   sc->node_bytes = sizeof(Node);
@@ -122,7 +125,19 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   if (hipMemcpy(sc->d_prims, recs.data(), pb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
   if (hipMemcpy(sc->d_leaf_of_id, leaf_of_id.data(), lb, hipMemcpyHostToDevice) != hipSuccess)
     return WOB_E_DEVICE;
-  sc->device_bytes = (int64_t)(nb + pb + lb + qb);
+  std::vector<float> cdf((size_t)T);
+  double tot = 0.0;
+  for (int64_t j = 0; j < T; ++j) tot += area[j];
+  double run = 0.0;
+  for (int64_t j = 0; j < T; ++j) {
+    run += area[j];
+    cdf[j] = (float)(run / tot);
+  }
+  cdf[T - 1] = 1.0f;
+  if (hipMalloc((void**)&sc->d_area_cdf, sizeof(float) * T) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMemcpy(sc->d_area_cdf, cdf.data(), sizeof(float) * T, hipMemcpyHostToDevice) != hipSuccess)
+    return WOB_E_DEVICE;
+  sc->device_bytes = (int64_t)(nb + pb + lb + qb + sizeof(float) * T);
   return WOB_OK;
 }
 
@@ -318,6 +333,7 @@ void wob_free(wob_scene sc) {
   if (sc->d_nodes) (void)hipFree(sc->d_nodes);
   if (sc->d_prims) (void)hipFree(sc->d_prims);
   if (sc->d_normals) (void)hipFree(sc->d_normals);
+  if (sc->d_area_cdf) (void)hipFree(sc->d_area_cdf);
   if (sc->d_leaf_of_id) (void)hipFree(sc->d_leaf_of_id);
   delete sc;
 }
@@ -401,6 +417,32 @@ wob_status wob_trace_cv(wob_scene sc, const void* points, const int32_t* point_p
   if (!g) return WOB_E_ARG;
   return run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, nullptr, nullptr,
                   nullptr, path_out, nullptr, nullptr, nullptr, MODE_TRACE, stream, g);
+}
+
+wob_status wob_sample_boundary(wob_scene sc, int64_t n, uint64_t seed, void* points_out,
+                               int32_t* prim_out, void* stream) {
+  if (!sc || n < 0 || (n > 0 && (!points_out || !prim_out))) return WOB_E_ARG;
+  if (n >= ((int64_t)1 << 32)) return WOB_E_ARG;
+  if (n == 0) return WOB_OK;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  if (sc->precision == WOB_F32) {
+    if (sc->dim == 3)
+      hipLaunchKernelGGL((wob::sample_boundary_kernel<float, 3>), grid, block, 0, st, view<float, 3>(sc),
+                         (const float*)sc->d_area_cdf, n, k0, k1, (float*)points_out, prim_out);
+    else
+      hipLaunchKernelGGL((wob::sample_boundary_kernel<float, 2>), grid, block, 0, st, view<float, 2>(sc),
+                         (const float*)sc->d_area_cdf, n, k0, k1, (float*)points_out, prim_out);
+  } else {
+    if (sc->dim == 3)
+      hipLaunchKernelGGL((wob::sample_boundary_kernel<double, 3>), grid, block, 0, st, view<double, 3>(sc),
+                         (const float*)sc->d_area_cdf, n, k0, k1, (double*)points_out, prim_out);
+    else
+      hipLaunchKernelGGL((wob::sample_boundary_kernel<double, 2>), grid, block, 0, st, view<double, 2>(sc),
+                         (const float*)sc->d_area_cdf, n, k0, k1, (double*)points_out, prim_out);
+  }
+  return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 
 wob_status wob_cv_table(wob_scene sc, wob_mlp net, float* g_out, void* stream) {

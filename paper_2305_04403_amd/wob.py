@@ -28,7 +28,7 @@ EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_pa
             "wob_batch_free", "wob_solve_batched", "wob_mlp_n_params", "wob_mlp_create",
             "wob_mlp_free", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
             "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
-            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback")
+            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_sample_boundary")
 
 
 class WobError(RuntimeError):
@@ -104,9 +104,11 @@ def lib():
     L.wob_mlp_train_step.argtypes = [vp, vp, vp, i64, i64, C.c_float, vp, vp]
     for name in ("wob_mlp_create", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
                  "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
-            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback"):
+            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_sample_boundary"):
         getattr(L, name).restype = C.c_int
     L.wob_cv_table.argtypes = [vp, vp, vp, vp]
+    L.wob_sample_boundary.argtypes = [vp, i64, u64, vp, vp, vp]
+    L.wob_sample_boundary.restype = C.c_int
     L.wob_solve_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp]
     L.wob_trace_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
     L.wob_cv_addback.argtypes = [vp, vp, vp, i64, vp, vp]
@@ -409,6 +411,16 @@ class MLP:
 
 
 # --------------------------------------------------------------------------- control variate
+
+def sample_boundary(scene: Scene, n: int, seed: int = 0, stream=None):
+    """n area-uniform boundary points and their primitive ids (device tensors)."""
+    torch = _torch()
+    pts = torch.empty((n, scene.dim), dtype=scene.dtype, device="cuda")
+    prim = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(lib().wob_sample_boundary(scene.handle, int(n), C.c_uint64(seed), _dev_ptr(pts), _dev_ptr(prim),
+                                     _stream(stream)), "wob_sample_boundary")
+    return pts, prim
+
 
 def cv_table(scene: Scene, net: "MLP", stream=None):
     torch = _torch()
