@@ -302,7 +302,7 @@ wob_status wob_cv_table(wob_scene scene, wob_mlp net, float* g_out, void* stream
  * Same paths and picks as wob_solve; every line adds a term whose mean given the
  * line is zero because the pick is uniform over the m hits: at line 0 the
  * subtraction w(j) g(T_j), whose mean sum_T g_T int_T G(x0, y) dA is added per
- * point in closed form; at lines 1..M-2 the all-hits sum of a(h) [2 phi s(y_h) +
+ * point (wob_cv_addback, with the solve's seed); at lines 1..M-2 the all-hits sum of a(h) [2 phi s(y_h) +
  * g(T_h)] minus the picked w(j) g(T_j); at the last line the all-hits mean of
  * the last emission.  Unbiased for every table g (DEVICE, n_prims floats by
  * primitive id); with g close to the boundary unknown minus its emission the
@@ -317,9 +317,14 @@ wob_status wob_trace_cv(wob_scene scene, const void* points, const int32_t* poin
                         int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
                         uint64_t seed, const float* g, void* path_out, void* stream);
 
-/* out[p] = sum_T g_T int_T G(x_p, y) dA (closed form per triangle), DEVICE. */
-wob_status wob_cv_addback(wob_scene scene, const float* g, const void* points, int64_t n_points,
-                          void* out, void* stream);
+/* out[p] = an unbiased value of sum_T g_T int_T G(x_p, y) dA: the closed form for
+ * triangles whose centroid is within four bounding radii of x_p, and for every
+ * other triangle g_T A_T G(x_p, y) at one point y uniform in T drawn from a
+ * 32-bit hash of (seed, triangle id, point id) (point id = point_ids[p], or p when
+ * point_ids is NULL).  DEVICE arrays. */
+wob_status wob_cv_addback(wob_scene scene, const float* g, const void* points,
+                          const uint32_t* point_ids, int64_t n_points, uint64_t seed, void* out,
+                          void* stream);
 
 #ifdef __cplusplus
 }

@@ -72,7 +72,7 @@ def lib():
         _lib.orc_prim_normal.argtypes = [C.c_void_p, C.c_int64, C.c_void_p]
         _lib.orc_prim_potential.argtypes = [vp, C.c_int64, vp]
         _lib.orc_prim_potential.restype = C.c_double
-        _lib.orc_cv_addback.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int]
+        _lib.orc_cv_addback.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_uint32, C.c_int, vp, C.c_int]
         _lib.orc_cv_addback.restype = C.c_int
         _lib.orc_trace_cv.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, vp,
                                       C.c_int64, vp, vp, vp, C.c_int]
@@ -240,11 +240,14 @@ def prim_potential(mesh: OracleMesh, prim: int, x: np.ndarray) -> float:
     return lib().orc_prim_potential(mesh.ref, int(prim), xx.ctypes.data)
 
 
-def cv_addback(mesh: OracleMesh, g: np.ndarray, points: np.ndarray, n_threads: int = 0) -> np.ndarray:
+def cv_addback(mesh: OracleMesh, g: np.ndarray, points: np.ndarray, seed: int = 0,
+               randomized: bool = False, point_ids=None, n_threads: int = 0) -> np.ndarray:
     gg = np.ascontiguousarray(g, dtype=np.float64)
     pts = np.ascontiguousarray(points, dtype=np.float64)
+    ids = None if point_ids is None else np.ascontiguousarray(point_ids, dtype=np.uint32)
     out = np.zeros(pts.shape[0])
-    if lib().orc_cv_addback(mesh.ref, gg.ctypes.data, pts.ctypes.data, pts.shape[0], out.ctypes.data,
+    if lib().orc_cv_addback(mesh.ref, gg.ctypes.data, pts.ctypes.data, _ptr(ids), pts.shape[0],
+                            C.c_uint32(seed & 0xffffffff), int(randomized), out.ctypes.data,
                             n_threads) != 0:
         raise ValueError("orc_cv_addback rejected its arguments")
     return out

@@ -778,18 +778,64 @@ double orc_prim_potential(const orc_mesh* m, int64_t prim, const double* x) {
   return -(F1 - F0) / (2.0 * ORC_PI);
 }
 
-int orc_cv_addback(const orc_mesh* m, const double* g, const double* points, int64_t n_points,
+/* 32-bit integer hash (the "lowbias32" constants of C. Wellons' hash prospector) */
+static uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+int orc_cv_addback(const orc_mesh* m, const double* g, const double* points,
+                   const uint32_t* point_ids, int64_t n_points, uint32_t seed, int randomized,
                    double* out, int n_threads) {
-  if (!m || !g || (m->dim != 2 && m->dim != 3)) return 1;
+  if (!m || !g || m->dim != 3) return 1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 16)
 #endif
   for (int64_t p = 0; p < n_points; ++p) {
-    double x[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < m->dim; ++a) x[a] = points[p * m->dim + a];
+    double x[3] = {points[p * 3], points[p * 3 + 1], points[p * 3 + 2]};
+    const uint32_t pid = point_ids ? point_ids[p] : (uint32_t)p;
     double acc = 0.0;
-    for (int64_t j = 0; j < m->n_prims; ++j) acc += g[j] * orc_prim_potential(m, j, x);
+    for (int64_t j = 0; j < m->n_prims; ++j) {
+      if (!randomized) {
+        acc += g[j] * orc_prim_potential(m, j, x);
+        continue;
+      }
+      double v[3][3], c[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < 3; ++k) prim_vertex(m, j, k, v[k]);
+      for (int k = 0; k < 3; ++k) c[k] = (v[0][k] + v[1][k] + v[2][k]) / 3.0;
+      double r2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        double dv[3] = {v[k][0] - c[0], v[k][1] - c[1], v[k][2] - c[2]};
+        double q = dot(dv, dv, 3);
+        if (q > r2) r2 = q;
+      }
+      double dx[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+      if (dot(dx, dx, 3) < 16.0 * r2) {
+        acc += g[j] * orc_prim_potential(m, j, x);
+      } else {
+        const uint32_t h = hash32((uint32_t)j + 0x9e3779b9u * (seed + 1u));
+        const uint32_t h2 = hash32(h ^ pid);
+        double a = uniform(hash32(h2 ^ 0x68e31da4u)), b = uniform(hash32(h2 ^ 0xb5297a4du));
+        if (a + b > 1.0) {
+          a = 1.0 - a;
+          b = 1.0 - b;
+        }
+        double e1[3], e2[3], y[3], nn[3];
+        for (int k = 0; k < 3; ++k) {
+          e1[k] = v[1][k] - v[0][k];
+          e2[k] = v[2][k] - v[0][k];
+          y[k] = v[0][k] + a * e1[k] + b * e2[k];
+        }
+        cross3(e1, e2, nn);
+        const double area = 0.5 * sqrt(dot(nn, nn, 3));
+        acc += g[j] * area * G(x, y, 3);
+      }
+    }
     out[p] = acc;
   }
   return 0;

@@ -127,7 +127,13 @@ int orc_trace_cv(const orc_mesh* mesh, const double* points, const int32_t* poin
                  int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed,
                  uint32_t problem, const double* g, int64_t n_items, const int64_t* item_point,
                  const int64_t* item_path, double* value, int n_threads);
-int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points, int64_t n_points,
+/* randomized = 0: sum_T g_T int_T G(x0, y) dA in closed form.  randomized = 1:
+ * closed form only for triangles whose centroid lies within four bounding radii of
+ * x0; every other triangle contributes g_T A_T G(x0, y) at one uniform point y
+ * drawn from a 32-bit integer hash of (seed, triangle, point id) (an unbiased
+ * value of the same sum). point_ids NULL = 0..n-1. */
+int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points,
+                   const uint32_t* point_ids, int64_t n_points, uint32_t seed, int randomized,
                    double* out, int n_threads);
 
 /* Unit outward normal of a primitive. */

@@ -70,6 +70,18 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
   return U4{c0, c1, c2, c3};
 }
 
+// A 32-bit integer hash (Wellons' "lowbias32" constants) for the add-back's
+// far-field sample points, where a full Philox block per (point, triangle)
+// pair would cost more than the geometry.
+__host__ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
 // u = ((w >> 9) + 1/2) 2^-23: exact in binary32 and binary64, never 0 or 1.
 template <typename R>
 __device__ __forceinline__ R unit(uint32_t w) {
@@ -287,15 +299,20 @@ __device__ __forceinline__ R tri_potential(const R v[3][3], const R tt[3][3], co
     A[c][2] = v[c][2] - x[2];
     Rv[c] = sqrt(dot3(A[c], A[c]));
   }
+  const R d = dot3(A[0], n);
   R sum_log = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int c1 = c == 2 ? 0 : c + 1;
     const R P = dot3(A[c], uu[c]);
+    if (P == (R)0) continue;
     const R sm = dot3(A[c], tt[c]), sp = dot3(A[c1], tt[c]);
-    // ln((R+ + s+)/(R- + s-)) = ln((R- - s-)/(R+ - s+)): the form without cancellation
-    const R lr = (sp + sm >= (R)0) ? log((Rv[c1] + sp) / (Rv[c] + sm)) : log((Rv[c] - sm) / (Rv[c1] - sp));
-    if (P != (R)0) sum_log += P * lr;
+    // ln(R + s), for s < 0 as ln(R0^2) - ln(R - s) with R0^2 = P^2 + d^2 (R^2 = R0^2 + s^2),
+    // which never subtracts nearly equal numbers
+    const R r02 = P * P + d * d;
+    const R lp = sp >= (R)0 ? log(Rv[c1] + sp) : log(r02) - log(Rv[c1] - sp);
+    const R lm = sm >= (R)0 ? log(Rv[c] + sm) : log(r02) - log(Rv[c] - sm);
+    sum_log += P * (lp - lm);
   }
   R bc[3];
   cross3(A[1], A[2], bc);
@@ -303,8 +320,7 @@ __device__ __forceinline__ R tri_potential(const R v[3][3], const R tt[3][3], co
   const R den = Rv[0] * Rv[1] * Rv[2] + dot3(A[0], A[1]) * Rv[2] + dot3(A[0], A[2]) * Rv[1] +
                 dot3(A[1], A[2]) * Rv[0];
   const R omega = fabs((R)2 * atan2(num, den));
-  const R d = fabs(dot3(A[0], n));
-  return (sum_log - d * omega) * (R)(0.25 / 3.14159265358979323846);
+  return (sum_log - fabs(d) * omega) * (R)(0.25 / 3.14159265358979323846);
 }
 
 // --------------------------------------------------------------------------

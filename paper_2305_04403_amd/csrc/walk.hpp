@@ -439,25 +439,38 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs<R, D> a) {
   walk_block<R, D, FORM, TRACE, COUNT, BLOCK, CV>(a, blockIdx.x, red);
 }
 
-// Add-back of the control variate: out[p] (+)= sum_T g_T int_T G(x_p, y) dA.
-// Every workgroup streams all triangles through LDS in tiles of 256 (edge
+// Add-back of the control variate: out[p] (+)= an unbiased value of
+// sum_T g_T int_T G(x_p, y) dA.  Triangles whose centroid lies within four
+// bounding radii of x_p ("near") use the closed form; every other triangle uses
+// g_T A_T G(x_p, y) at one point y uniform in T (its expectation is the exact
+// integral; G varies by at most ~30 % over a far triangle).  The point comes
+// from hash32 of (seed, triangle id, point id):
+//   h = hash32(id + 0x9e3779b9 (seed_lo + 1)), h2 = hash32(h ^ point),
+//   u0 = unit(hash32(h2 ^ 0x68e31da4)), u1 = unit(hash32(h2 ^ 0xb5297a4d)),
+//   reflected into the triangle when u0 + u1 > 1.
+// Every workgroup streams the triangles through LDS in tiles of 256 (edge
 // frames precomputed on load); each lane keeps 4 points in registers.
 template <typename R>
 __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, const R* __restrict__ g_by_id,
-                                                         const R* __restrict__ points, int64_t n,
-                                                         R* out, int accumulate) {
-  constexpr int TILE = 256, PPT = 4, NF = 31;
+                                                         const R* __restrict__ points,
+                                                         const uint32_t* __restrict__ point_ids,
+                                                         int64_t n, uint32_t seed, R* out,
+                                                         int accumulate) {
+  constexpr int TILE = 256, PPT = 4, NF = 37;
   __shared__ R tile[TILE * NF];
+  __shared__ uint32_t thash[TILE];
   const int tid = threadIdx.x;
   R x[PPT][3], acc[PPT];
   int64_t pidx[PPT];
+  uint32_t pid[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     pidx[k] = ((int64_t)blockIdx.x * PPT + k) * 256 + tid;
     const int64_t q = pidx[k] < n ? pidx[k] : 0;
-    x[k][0] = n > 0 ? points[q * 3 + 0] : (R)0;
-    x[k][1] = n > 0 ? points[q * 3 + 1] : (R)0;
-    x[k][2] = n > 0 ? points[q * 3 + 2] : (R)0;
+    x[k][0] = points[q * 3 + 0];
+    x[k][1] = points[q * 3 + 1];
+    x[k][2] = points[q * 3 + 2];
+    pid[k] = point_ids ? point_ids[q] : (uint32_t)q;
     acc[k] = 0;
   }
   for (int32_t t0 = 0; t0 < s.n_prims; t0 += TILE) {
@@ -474,42 +487,74 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
         v[1][k] = g.v0[k] + g.e1[k];
         v[2][k] = g.v0[k] + g.e2[k];
       }
+      R cen[3], rad2 = 0;
+      for (int k = 0; k < 3; ++k) cen[k] = (v[0][k] + v[1][k] + v[2][k]) / (R)3;
       for (int c = 0; c < 3; ++c) {
         const int c1 = c == 2 ? 0 : c + 1;
         R e[3] = {v[c1][0] - v[c][0], v[c1][1] - v[c][1], v[c1][2] - v[c][2]};
         const R il = rsqrt_<R>(dot3(e, e));
         R tt[3] = {e[0] * il, e[1] * il, e[2] * il}, uu[3];
         cross3(tt, nn, uu);
+        R dc[3] = {v[c][0] - cen[0], v[c][1] - cen[1], v[c][2] - cen[2]};
+        rad2 = fmax(rad2, dot3(dc, dc));
         for (int k = 0; k < 3; ++k) {
           T[c * 3 + k] = v[c][k];
           T[9 + c * 3 + k] = tt[k];
           T[18 + c * 3 + k] = uu[k];
         }
       }
+      R cr[3];
+      cross3(g.e1, g.e2, cr);
       T[27] = nn[0];
       T[28] = nn[1];
       T[29] = nn[2];
       T[30] = g_by_id[g.id];
+      T[31] = cen[0];
+      T[32] = cen[1];
+      T[33] = cen[2];
+      T[34] = (R)16 * rad2;                                 // (4 r)^2
+      T[35] = (R)0.5 * sqrt(dot3(cr, cr));                  // area
+      T[36] = (R)0;
+      thash[tid] = hash32((uint32_t)g.id + 0x9e3779b9u * (seed + 1u));
     }
     __syncthreads();
     const int cnt = s.n_prims - t0 < TILE ? s.n_prims - t0 : TILE;
     for (int q = 0; q < cnt; ++q) {
       const R* P = tile + q * NF;
-      R v[3][3], tt[3][3], uu[3][3], nn[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          v[c][k] = P[c * 3 + k];
-          tt[c][k] = P[9 + c * 3 + k];
-          uu[c][k] = P[18 + c * 3 + k];
-        }
-      nn[0] = P[27];
-      nn[1] = P[28];
-      nn[2] = P[29];
       const R gq = P[30];
+      const R c0 = P[31], c1 = P[32], c2 = P[33], near2 = P[34], area = P[35];
+      const uint32_t hq = thash[q];
 #pragma unroll
-      for (int k = 0; k < PPT; ++k) acc[k] += gq * tri_potential<R>(v, tt, uu, nn, x[k]);
+      for (int k = 0; k < PPT; ++k) {
+        const R dx = x[k][0] - c0, dy = x[k][1] - c1, dz = x[k][2] - c2;
+        if (dx * dx + dy * dy + dz * dz < near2) {
+          R v[3][3], tt[3][3], uu[3][3], nn[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+              v[c][m] = P[c * 3 + m];
+              tt[c][m] = P[9 + c * 3 + m];
+              uu[c][m] = P[18 + c * 3 + m];
+            }
+          nn[0] = P[27];
+          nn[1] = P[28];
+          nn[2] = P[29];
+          acc[k] += gq * tri_potential<R>(v, tt, uu, nn, x[k]);
+        } else {
+          const uint32_t h2 = hash32(hq ^ pid[k]);
+          R a = unit<R>(hash32(h2 ^ 0x68e31da4u)), b = unit<R>(hash32(h2 ^ 0xb5297a4du));
+          if (a + b > (R)1) {
+            a = (R)1 - a;
+            b = (R)1 - b;
+          }
+          // y = v0 + a (v1 - v0) + b (v2 - v0)
+          const R yx = P[0] + a * (P[3] - P[0]) + b * (P[6] - P[0]) - x[k][0];
+          const R yy = P[1] + a * (P[4] - P[1]) + b * (P[7] - P[1]) - x[k][1];
+          const R yz = P[2] + a * (P[5] - P[2]) + b * (P[8] - P[2]) - x[k][2];
+          acc[k] += gq * area * (R)(0.25 / 3.14159265358979323846) * rsqrt_<R>(yx * yx + yy * yy + yz * yz);
+        }
+      }
     }
   }
 #pragma unroll

@@ -385,15 +385,16 @@ wob_status wob_count_work(wob_scene sc, const void* points, const int32_t* point
                   nullptr, nullptr, nullptr, nullptr, counters, MODE_COUNT, stream);
 }
 
-wob_status wob_cv_addback(wob_scene sc, const float* g, const void* points, int64_t n_points,
-                          void* out, void* stream) {
+wob_status wob_cv_addback(wob_scene sc, const float* g, const void* points,
+                          const uint32_t* point_ids, int64_t n_points, uint64_t seed, void* out,
+                          void* stream) {
   if (!sc || n_points < 0 || (n_points > 0 && (!g || !points || !out))) return WOB_E_ARG;
   if (sc->dim != 3 || sc->precision != WOB_F32) return WOB_E_UNSUPPORTED;
   if (n_points == 0) return WOB_OK;
   const int64_t blocks = (n_points + 1023) / 1024;
   hipLaunchKernelGGL((wob::cv_addback_kernel<float>), dim3((unsigned)blocks), dim3(256), 0,
-                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points, n_points,
-                     (float*)out, 0);
+                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points, point_ids,
+                     n_points, (uint32_t)(seed & 0xffffffffu), (float*)out, 0);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 
@@ -406,7 +407,8 @@ wob_status wob_solve_cv(wob_scene sc, const void* points, const int32_t* point_p
   if (s != WOB_OK || n_points == 0 || walk_len < 2) return s;
   const int64_t blocks = (n_points + 1023) / 1024;
   hipLaunchKernelGGL((wob::cv_addback_kernel<float>), dim3((unsigned)blocks), dim3(256), 0,
-                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points, n_points,
+                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points,
+                     (const uint32_t*)nullptr, n_points, (uint32_t)(seed & 0xffffffffu),
                      (float*)mean_out, 1);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }

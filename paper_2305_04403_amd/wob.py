@@ -111,7 +111,7 @@ def lib():
     L.wob_sample_boundary.restype = C.c_int
     L.wob_solve_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp]
     L.wob_trace_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
-    L.wob_cv_addback.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.wob_cv_addback.argtypes = [vp, vp, vp, vp, i64, u64, vp, vp]
     for name in ("wob_cv_table", "wob_solve_cv", "wob_trace_cv", "wob_cv_addback"):
         getattr(L, name).restype = C.c_int
     L.wob_status_string.argtypes = [C.c_int]
@@ -457,9 +457,10 @@ def trace_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed:
     return path
 
 
-def cv_addback(scene: Scene, g, points, stream=None):
+def cv_addback(scene: Scene, g, points, seed: int = 0, point_ids=None, stream=None):
     torch = _torch()
     out = torch.empty(points.shape[0], dtype=scene.dtype, device=points.device)
-    _check(lib().wob_cv_addback(scene.handle, _dev_ptr(g), _dev_ptr(points), points.shape[0],
-                                _dev_ptr(out), _stream(stream)), "wob_cv_addback")
+    _check(lib().wob_cv_addback(scene.handle, _dev_ptr(g), _dev_ptr(points), _dev_ptr(point_ids),
+                                points.shape[0], C.c_uint64(seed), _dev_ptr(out), _stream(stream)),
+           "wob_cv_addback")
     return out

@@ -42,13 +42,15 @@ def test_addback_matches_oracle(W, tori):
     rng = np.random.default_rng(1)
     g = PT.f32(rng.standard_normal(tori.mesh.n_prims) + 0.5)
     scene = W.Scene(tori.mesh, W.F32)
-    out = W.cv_addback(scene, dev(g), dev(tori.points))
+    out = W.cv_addback(scene, dev(g), dev(tori.points), seed=9)
     torch.cuda.synchronize()
     om = oracle.OracleMesh(tori.mesh)
-    ref = oracle.cv_addback(om, g, tori.points)
+    ref = oracle.cv_addback(om, g, tori.points, seed=9, randomized=True)
+    exact = oracle.cv_addback(om, g, tori.points)
     scale = oracle.cv_addback(om, np.abs(g), tori.points)
     err = np.abs(out.cpu().double().numpy() - ref) / scale
-    print(f"add-back max error / sum |g| potential: {err.max():.2e}")
+    print(f"add-back max error / sum |g| potential: {err.max():.2e}; "
+          f"randomized vs closed form {np.max(np.abs(ref - exact) / scale):.2e}")
     assert err.max() < 2e-5
     scene.close()
 
@@ -72,7 +74,7 @@ def test_trace_cv_matches_oracle(W, tori):
     tol = scale * (PT.RTOL_F32 * 10 + PT.COS_ULP_F32 / np.maximum(plain["cond_cos"], 1e-300))
     bad = ok & (np.abs(v - ref) > tol)
     print(f"cv paths {len(v)}, grazing {int((~ok).sum())}, over tolerance {int(bad.sum())}, "
-          f"median rel {np.median(np.abs(v - ref)[ok] / scale[ok]):.2e}")
+          f"median rel {np.nanmedian(np.abs(v - ref)[ok] / scale[ok]):.2e}")
     assert (~ok).mean() < 0.01
     assert bad.sum() <= 0.005 * ok.sum() + 1
     scene.close()
@@ -130,7 +132,7 @@ def test_solve_cv_is_unbiased_on_gpu(W, tori):
     assert np.abs(z).max() < 4.5
     # the mean of traced corrected paths plus the add-back is the solve's mean
     val = W.trace_cv(scene, pts, wb, 256, 4, g=dev(g), seed=7, point_prim=pp)
-    add = W.cv_addback(scene, dev(g), pts)
+    add = W.cv_addback(scene, dev(g), pts, seed=7)
     m2, _ = W.solve_cv(scene, pts, wb, 256, 4, g=dev(g), seed=7, point_prim=pp)
     torch.cuda.synchronize()
     np.testing.assert_allclose(m2.cpu().numpy(), val.double().mean(dim=1).cpu().numpy() + add.cpu().numpy(),

@@ -182,7 +182,7 @@ def test_control_variate_is_unbiased_for_any_table():
     ip, ik = np.repeat(np.arange(P), N), np.tile(np.arange(N), P)
     plain = oracle.trace(om, w.points, w.point_prim, bc, w.walk_len, 1, ip, ik, want_pos=False)["value"]
     cv = oracle.trace_cv(om, w.points, w.point_prim, bc, w.walk_len, 1, g, ip, ik)
-    add = oracle.cv_addback(om, g, w.points)
+    add = oracle.cv_addback(om, g, w.points, seed=1, randomized=True)
     d = (cv.reshape(P, N) - plain.reshape(P, N))
     diff = d.mean(axis=1) + add
     se = d.std(axis=1, ddof=1) / np.sqrt(N)
@@ -225,3 +225,18 @@ def test_density_mode_on_exterior_sphere():
         est = np.sum(w * mean) / np.sum(w)
         se = 1 / np.sqrt(np.sum(w))
         assert abs(est + 1.0) < 4 * se + 0.02, (M, est, se)
+
+
+def test_randomized_addback_averages_to_the_closed_form():
+    """The far-field one-point values average (over seeds) to the exact integrals:
+    the randomized add-back is unbiased, and its spread is small."""
+    w = _tori_problem()
+    om = oracle.OracleMesh(w.mesh)
+    g = np.random.default_rng(4).standard_normal(w.mesh.n_prims) + 1.0
+    exact = oracle.cv_addback(om, g, w.points)
+    runs = np.array([oracle.cv_addback(om, g, w.points, seed=s, randomized=True) for s in range(200)])
+    mean, sd = runs.mean(axis=0), runs.std(axis=0, ddof=1)
+    z = (mean - exact) / (sd / np.sqrt(runs.shape[0]) + 1e-300)
+    assert np.max(np.abs(z)) < 4.5
+    scale = oracle.cv_addback(om, np.abs(g), w.points)
+    assert np.max(sd / scale) < 0.02
