@@ -12,6 +12,14 @@ a model's weights would be; inputs are resident in device memory.
 
 Prints one JSON line: path samples/s (value), lines/s, the roofline record of
 the walk kernel and the FP64 oracle timed on a bounded sample on host cores.
+Two more legs are reported in the same line (each with its own timing):
+  batched   - 64 problems of uneven size (2k-200k triangles, 1k-256k points,
+              128-1024 paths, Dirichlet and exterior Neumann) in one persistent
+              launch replayed from a hipGraph, launch shape autotuned;
+  cv        - exterior Neumann / Robin single layer on a 200,992-triangle
+              union of three tori, 1M points: RMSE against the analytic
+              solution at equal wall time, plain WoB with 512 paths against
+              the learned control variate (fit + corrected solve).
 """
 import argparse
 import json
@@ -37,6 +45,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--cpu-sample-points", type=int, default=640)
     p.add_argument("--skip-cpu-baseline", action="store_true")
+    p.add_argument("--legs", default="main,batched,cv",
+                   help="comma-separated subset of main, batched, cv")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device once (a kernel of known "
                         "traffic that calibrates hardware byte counters)")
@@ -59,6 +69,97 @@ def cpu_baseline(w, n_points):
                       f"{dt:.1f} s"}
 
 
+def batched_leg(torch, wob, I, steps=2):
+    from concurrent.futures import ThreadPoolExecutor
+    ws = I.config_batched()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)))) as ex:
+        scenes = list(ex.map(lambda w: wob.Scene(w.mesh, wob.F32), ws))
+    t_build = time.perf_counter() - t0
+    probs = [dict(scene=s, points=torch.as_tensor(w.points, dtype=torch.float32, device="cuda"),
+                  bc=wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"])),
+                  samples=w.samples, walk_len=w.walk_len, seed=w.seed) for w, s in zip(ws, scenes)]
+    b = wob.Batch(probs)
+    t0 = time.perf_counter()
+    tune = b.autotune(sample_stride=16)
+    t_tune = time.perf_counter() - t0
+    b.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs = b.launch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    paths = sum(w.points.shape[0] * w.samples for w in ws)
+    lines = sum(w.points.shape[0] * w.samples * (w.walk_len + (1 if w.bc["formulation"] == 2 else 0))
+                for w in ws)
+    rel = []
+    for w, (m, v) in zip(ws, outs):
+        mm = m.double().cpu().numpy()
+        rel.append(float(np.sqrt(np.mean((mm - w.exact) ** 2)) / np.sqrt(np.mean(w.exact ** 2))))
+    (blk, bpc), n_tiles = b.tune()
+    b.close()
+    for s in scenes:
+        s.close()
+    return {"workload": "64 perturbed spheres, 2k-200k triangles (sum %d), %d points, 128-1024 paths, M=4, "
+                        "Dirichlet interior + Neumann exterior, FP32" % (sum(w.mesh.n_prims for w in ws),
+                                                                         sum(w.points.shape[0] for w in ws)),
+            "value": paths / dt, "unit": "path samples/s", "ms_per_launch": 1e3 * dt, "lines_per_s": lines / dt,
+            "paths": paths, "tiles": n_tiles, "launch": "persistent, hipGraph replay",
+            "autotuned": {"block": blk, "blocks_per_cu": bpc, "tune_s": t_tune},
+            "bvh_build_s": t_build, "median_relative_rmse_vs_analytic": float(np.median(rel))}
+
+
+def cv_leg(torch, wob, I):
+    import math
+    from paper_2305_04403_amd import cv as CV
+    w = I.config_tori()
+    scene = wob.Scene(w.mesh, wob.F32)
+    bc = wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"]))
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device="cuda")
+    pp = torch.as_tensor(w.point_prim, dtype=torch.int32, device="cuda")
+    N, M = w.samples, w.walk_len
+    sync = torch.cuda.synchronize
+    wob.solve(scene, pts[:4096].contiguous(), bc, 64, M, point_prim=pp[:4096].contiguous())
+    sync()
+    t0 = time.perf_counter()
+    mp, vp = wob.solve(scene, pts, bc, N, M, seed=1, point_prim=pp)
+    sync()
+    t_plain = time.perf_counter() - t0
+    lcv = CV.LearnedControlVariate(scene, bc, M, CV.CVConfig(epochs=1, target_paths=4))
+    fit = lcv.fit()
+    # per-path cost of the corrected walk and the add-back, measured on the same points
+    wob.cv_addback(scene, lcv.g, pts[:1024].contiguous())
+    sync()
+    t0 = time.perf_counter()
+    wob.cv_addback(scene, lcv.g, pts)
+    sync()
+    t_add = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lcv.solve(pts, 64, seed=2, point_prim=pp)
+    sync()
+    per_path = max(time.perf_counter() - t0 - t_add, 1e-9) / 64
+    n_cv = int(max(64, (t_plain - fit["fit_s"] - t_add) / per_path // 64 * 64))
+    t0 = time.perf_counter()
+    mc, vc = lcv.solve(pts, n_cv, seed=3, point_prim=pp)
+    sync()
+    t_cv = time.perf_counter() - t0
+    ex = w.exact
+    a, b = mp.double().cpu().numpy(), mc.double().cpu().numpy()
+    rp, rc = math.sqrt(np.mean((a - ex) ** 2)), math.sqrt(np.mean((b - ex) ** 2))
+    ep, ec = float(np.median(np.abs(a - ex))), float(np.median(np.abs(b - ex)))
+    out = {"workload": w.name + ", 1M points (10% on the boundary), M=4",
+           "plain": {"paths": N, "seconds": t_plain, "rmse": rp, "median_abs_err": ep,
+                     "mean_var": float(vp.double().mean())},
+           "cv": {"paths": n_cv, "seconds": fit["fit_s"] + t_cv, "fit_s": fit["fit_s"], "solve_s": t_cv,
+                  "train_steps": fit["train_steps"], "rmse": rc, "median_abs_err": ec,
+                  "mean_var": float(vc.double().mean())},
+           "rmse_ratio_equal_time": rp / rc, "median_err_ratio_equal_time": ep / ec}
+    lcv.close()
+    scene.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -70,6 +171,12 @@ def main():
     from paper_2305_04403_amd import wob
 
     torch.cuda.set_device(0)
+    legs = set(args.legs.split(","))
+    extra = {}
+    if "batched" in legs:
+        extra["batched"] = batched_leg(torch, wob, I)
+    if "cv" in legs:
+        extra["cv_equal_time"] = cv_leg(torch, wob, I)
     w = I.config_icosphere_slice()
     scene = wob.Scene(w.mesh, wob.F32)
     info = scene.info()
@@ -134,6 +241,7 @@ def main():
         "mean_se": float(np.mean(se)),
         "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")},
     }
+    rec.update(extra)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
