@@ -273,11 +273,21 @@ wob_status wob_mlp_set_params(wob_mlp net, const float* params);
 /* out[i] = f(y_i); y DEVICE n x dim, out DEVICE n. */
 wob_status wob_mlp_forward(wob_mlp net, const float* y, int64_t n, float* out, void* stream);
 
-/* Mean squared error (1/n) sum (f(y_i) - target_i)^2 and its gradient with respect
- * to every parameter (DEVICE grad, wob_mlp_n_params() floats; loss DEVICE 1 float or
- * NULL).  Deterministic.  1 <= n <= max_batch. */
-wob_status wob_mlp_backward(wob_mlp net, const float* y, const float* target, int64_t n,
-                            float* grad, float* loss, void* stream);
+/* Optional transform of the targets inside the loss: t -> (t - shift) / scale,
+ * then clamped to [-clip, clip] when clip > 0 (scale > 0). */
+typedef struct {
+  float shift;
+  float scale;
+  float clip;
+} wob_target_map;
+
+/* Mean squared error (1/n) sum (f(y_i) - t_i)^2, t_i = target_i mapped by tmap
+ * (NULL = unchanged), and its gradient with respect to every parameter (DEVICE
+ * grad, wob_mlp_n_params() floats; loss DEVICE 1 float or NULL).  Deterministic.
+ * 1 <= n <= max_batch. */
+wob_status wob_mlp_backward(wob_mlp net, const float* y, const float* target,
+                            const wob_target_map* tmap, int64_t n, float* grad, float* loss,
+                            void* stream);
 
 /* Adam (Kingma and Ba) on the binary32 parameters with bias correction for step
  * >= 1, then refresh of the bfloat16 copies.  grad DEVICE. */
@@ -285,8 +295,9 @@ wob_status wob_mlp_adam_step(wob_mlp net, const float* grad, int64_t step, float
                              float b2, float eps, void* stream);
 
 /* backward + Adam (b1 0.9, b2 0.999, eps 1e-8) with an internal gradient buffer. */
-wob_status wob_mlp_train_step(wob_mlp net, const float* y, const float* target, int64_t n,
-                              int64_t step, float lr, float* loss, void* stream);
+wob_status wob_mlp_train_step(wob_mlp net, const float* y, const float* target,
+                              const wob_target_map* tmap, int64_t n, int64_t step, float lr,
+                              float* loss, void* stream);
 
 /* n area-uniform points on the boundary (DEVICE n * dim, scene precision) and the
  * primitive each lies on (DEVICE n int32), from Philox counter (i, 0xffffffff,
@@ -298,33 +309,44 @@ wob_status wob_sample_boundary(wob_scene scene, int64_t n, uint64_t seed, void* 
  * 3D binary32 scenes. */
 wob_status wob_cv_table(wob_scene scene, wob_mlp net, float* g_out, void* stream);
 
-/* Exact control variate for the single-layer estimator (3D, binary32 scenes).
- * Same paths and picks as wob_solve; every line adds a term whose mean given the
- * line is zero because the pick is uniform over the m hits: at line 0 the
- * subtraction w(j) g(T_j), whose mean sum_T g_T int_T G(x0, y) dA is added per
- * point (wob_cv_addback, with the solve's seed); at lines 1..M-2 the all-hits sum of a(h) [2 phi s(y_h) +
- * g(T_h)] minus the picked w(j) g(T_j); at the last line the all-hits mean of
- * the last emission.  Unbiased for every table g (DEVICE, n_prims floats by
- * primitive id); with g close to the boundary unknown minus its emission the
- * variance falls.  Errors as wob_solve, WOB_E_UNSUPPORTED for other
- * formulations, 2D or binary64 scenes. */
+/* Exact control variate for the single-layer estimator (3D, binary32 scenes;
+ * the control variate is not part of the paper).  Same paths and picks as
+ * wob_solve; every line adds a term whose mean given the line is zero because
+ * the pick is uniform over the m hits:
+ *   line 0:     the subtraction w(j) g0(T_j), whose mean sum_T g0_T int_T G(x0, y) dA
+ *               is added per point (wob_cv_addback, with the solve's seed);
+ *   lines 1..M-2: the all-hits sum of a(h) [2 phi s(y_h) + g(T_h)] minus the
+ *               picked w(j) g(T_j);
+ *   last line:  the all-hits mean of the last emission.
+ * Unbiased for all tables g, g0 (DEVICE, n_prims floats by primitive id; g0 NULL
+ * means g0 = g).  With g close to the boundary unknown minus its emission and
+ * g0 = g + the emission at the centroid (wob_cv_emission) the variance falls.
+ * Errors as wob_solve; WOB_E_UNSUPPORTED for other formulations, 2D or binary64
+ * scenes. */
 wob_status wob_solve_cv(wob_scene scene, const void* points, const int32_t* point_prim,
                         int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
-                        uint64_t seed, const float* g, void* mean_out, void* var_out, void* stream);
+                        uint64_t seed, const float* g, const float* g0, void* mean_out,
+                        void* var_out, void* stream);
 
 /* Per-path values of the corrected estimator WITHOUT the per-point add-back. */
 wob_status wob_trace_cv(wob_scene scene, const void* points, const int32_t* point_prim,
                         int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
-                        uint64_t seed, const float* g, void* path_out, void* stream);
+                        uint64_t seed, const float* g, const float* g0, void* path_out,
+                        void* stream);
 
 /* out[p] = an unbiased value of sum_T g_T int_T G(x_p, y) dA: the closed form for
  * triangles whose centroid is within four bounding radii of x_p, and for every
- * other triangle g_T A_T G(x_p, y) at one point y uniform in T drawn from a
- * 32-bit hash of (seed, triangle id, point id) (point id = point_ids[p], or p when
- * point_ids is NULL).  DEVICE arrays. */
-wob_status wob_cv_addback(wob_scene scene, const float* g, const void* points,
-                          const uint32_t* point_ids, int64_t n_points, uint64_t seed, void* out,
-                          void* stream);
+ * other triangle g_T A_T G(x_p, y_T) at one point y_T uniform in T drawn from a
+ * 32-bit hash of (seed, triangle id), the same for every point.  DEVICE arrays
+ * (points n_points x 3, out n_points). */
+wob_status wob_cv_addback(wob_scene scene, const float* g, const void* points, int64_t n_points,
+                          uint64_t seed, void* out, void* stream);
+
+/* g0_out[id] = (g ? g[id] : 0) + 2 phi s(c_id), s the boundary datum of bc on
+ * primitive id at its centroid c_id, phi = bc->domain: the line-0 table of
+ * wob_solve_cv.  Single-layer problems, 3D binary32 scenes.  DEVICE arrays. */
+wob_status wob_cv_emission(wob_scene scene, const wob_bc* bc, const float* g, float* g0_out,
+                           void* stream);
 
 #ifdef __cplusplus
 }

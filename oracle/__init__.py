@@ -72,10 +72,10 @@ def lib():
         _lib.orc_prim_normal.argtypes = [C.c_void_p, C.c_int64, C.c_void_p]
         _lib.orc_prim_potential.argtypes = [vp, C.c_int64, vp]
         _lib.orc_prim_potential.restype = C.c_double
-        _lib.orc_cv_addback.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_uint32, C.c_int, vp, C.c_int]
+        _lib.orc_cv_addback.argtypes = [vp, vp, vp, C.c_int64, C.c_uint32, C.c_int, vp, C.c_int]
         _lib.orc_cv_addback.restype = C.c_int
         _lib.orc_trace_cv.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, vp,
-                                      C.c_int64, vp, vp, vp, C.c_int]
+                                      vp, C.c_int64, vp, vp, vp, C.c_int]
         _lib.orc_trace_cv.restype = C.c_int
         _lib.orc_mlp_n_params.argtypes = [C.c_int, C.c_int, C.c_int]
         _lib.orc_mlp_n_params.restype = C.c_int64
@@ -241,12 +241,11 @@ def prim_potential(mesh: OracleMesh, prim: int, x: np.ndarray) -> float:
 
 
 def cv_addback(mesh: OracleMesh, g: np.ndarray, points: np.ndarray, seed: int = 0,
-               randomized: bool = False, point_ids=None, n_threads: int = 0) -> np.ndarray:
+               randomized: bool = False, n_threads: int = 0) -> np.ndarray:
     gg = np.ascontiguousarray(g, dtype=np.float64)
     pts = np.ascontiguousarray(points, dtype=np.float64)
-    ids = None if point_ids is None else np.ascontiguousarray(point_ids, dtype=np.uint32)
     out = np.zeros(pts.shape[0])
-    if lib().orc_cv_addback(mesh.ref, gg.ctypes.data, pts.ctypes.data, _ptr(ids), pts.shape[0],
+    if lib().orc_cv_addback(mesh.ref, gg.ctypes.data, pts.ctypes.data, pts.shape[0],
                             C.c_uint32(seed & 0xffffffff), int(randomized), out.ctypes.data,
                             n_threads) != 0:
         raise ValueError("orc_cv_addback rejected its arguments")
@@ -254,15 +253,17 @@ def cv_addback(mesh: OracleMesh, g: np.ndarray, points: np.ndarray, seed: int = 
 
 
 def trace_cv(mesh: OracleMesh, points, point_prim, bc: _BC, walk_len: int, seed: int, g,
-             item_point, item_path, problem: int = 0, n_threads: int = 0) -> np.ndarray:
+             item_point, item_path, problem: int = 0, n_threads: int = 0, g0=None) -> np.ndarray:
+    """Corrected per-path values; g0 (line-0 table) defaults to g."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     pp = None if point_prim is None else np.ascontiguousarray(point_prim, dtype=np.int32)
     gg = np.ascontiguousarray(g, dtype=np.float64)
+    g00 = None if g0 is None else np.ascontiguousarray(g0, dtype=np.float64)
     ip = np.ascontiguousarray(item_point, dtype=np.int64)
     ik = np.ascontiguousarray(item_path, dtype=np.int64)
     out = np.zeros(ip.shape[0])
     rc = lib().orc_trace_cv(mesh.ref, _ptr(pts), _ptr(pp), pts.shape[0], C.byref(bc), int(walk_len),
-                            C.c_uint64(seed), C.c_uint32(problem), _ptr(gg), ip.shape[0], _ptr(ip),
+                            C.c_uint64(seed), C.c_uint32(problem), _ptr(gg), _ptr(g00), ip.shape[0], _ptr(ip),
                             _ptr(ik), _ptr(out), int(n_threads))
     if rc != 0:
         raise ValueError("orc_trace_cv rejected its arguments")

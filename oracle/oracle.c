@@ -788,9 +788,8 @@ static uint32_t hash32(uint32_t x) {
   return x;
 }
 
-int orc_cv_addback(const orc_mesh* m, const double* g, const double* points,
-                   const uint32_t* point_ids, int64_t n_points, uint32_t seed, int randomized,
-                   double* out, int n_threads) {
+int orc_cv_addback(const orc_mesh* m, const double* g, const double* points, int64_t n_points,
+                   uint32_t seed, int randomized, double* out, int n_threads) {
   if (!m || !g || m->dim != 3) return 1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -798,7 +797,6 @@ int orc_cv_addback(const orc_mesh* m, const double* g, const double* points,
 #endif
   for (int64_t p = 0; p < n_points; ++p) {
     double x[3] = {points[p * 3], points[p * 3 + 1], points[p * 3 + 2]};
-    const uint32_t pid = point_ids ? point_ids[p] : (uint32_t)p;
     double acc = 0.0;
     for (int64_t j = 0; j < m->n_prims; ++j) {
       if (!randomized) {
@@ -818,9 +816,9 @@ int orc_cv_addback(const orc_mesh* m, const double* g, const double* points,
       if (dot(dx, dx, 3) < 16.0 * r2) {
         acc += g[j] * orc_prim_potential(m, j, x);
       } else {
+        /* one point per (seed, triangle), the same for every evaluation point */
         const uint32_t h = hash32((uint32_t)j + 0x9e3779b9u * (seed + 1u));
-        const uint32_t h2 = hash32(h ^ pid);
-        double a = uniform(hash32(h2 ^ 0x68e31da4u)), b = uniform(hash32(h2 ^ 0xb5297a4du));
+        double a = uniform(hash32(h ^ 0x68e31da4u)), b = uniform(hash32(h ^ 0xb5297a4du));
         if (a + b > 1.0) {
           a = 1.0 - a;
           b = 1.0 - b;
@@ -849,10 +847,12 @@ int orc_cv_addback(const orc_mesh* m, const double* g, const double* points,
 /* For any function F, adding sum_h a(h) F(y_h) - w(j) F(y_j) changes        */
 /* nothing in expectation given the line (the pick is uniform over the m     */
 /* hits), so the estimator stays unbiased for every F:                       */
-/*  - line 0 from x0: F = g(T(y)) (the table); the subtraction is kept and   */
-/*    its exact expectation sum_T g_T int_T G(x0, y) dA is added per point   */
-/*    (orc_cv_addback) instead of the all-hits sum; a self-panel sample at a */
-/*    boundary x0 subtracts w g(T0) too, so the add-back covers all of Gamma;*/
+/*  - line 0 from x0: F = g0(T(y)) (a second table); the subtraction is     */
+/*    kept and its exact expectation sum_T g0_T int_T G(x0, y) dA is added   */
+/*    per point (orc_cv_addback) instead of the all-hits sum; a self-panel   */
+/*    sample at a boundary x0 subtracts w g0(T0) too, so the add-back covers */
+/*    all of Gamma.  With g0 = g + (emission at the centroid) the step-0     */
+/*    emission is corrected as well, up to its variation over a triangle;    */
 /*  - lines 1..M-2 (line branch): F = 2 phi s(y) + g(T(y));                  */
 /*  - line M-1 (line branch): F = phi s(y), the exact rest of the path, so   */
 /*    the pick is not needed at all.                                         */
@@ -886,8 +886,8 @@ static int collect_hits(const orc_mesh* m, const double* x, const double* d, int
 #define CV_MAX_HITS 256
 
 static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc* bc,
-                          const double* g, const double* x0, int64_t prim0, int M, uint64_t seed,
-                          uint32_t problem, uint32_t point, uint32_t path) {
+                          const double* g, const double* g0, const double* x0, int64_t prim0,
+                          int M, uint64_t seed, uint32_t problem, uint32_t point, uint32_t path) {
   const int dim = m->dim;
   const double phi = (double)bc->domain;
   double x[3] = {x0[0], x0[1], dim == 3 ? x0[2] : 0.0};
@@ -923,7 +923,7 @@ static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc
       const double w = (i == 0 ? gp : -2.0 * phi * prim_alpha(m, cur) * gp) / bc->self_p;
       Wn = W * w;
       next = cur;
-      if (i == 0 && !last) acc -= Wn * g[cur];
+      if (i == 0 && !last) acc -= Wn * g0[cur];
       acc += Wn * (last ? phi : 2.0 * phi) * orc_boundary_datum(m, bc, cur, y);
     } else {
       const int mh = collect_hits(m, x, d, cur, hits, CV_MAX_HITS, seed, path, point, problem,
@@ -956,7 +956,7 @@ static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc
       next = hits[j].prim;
       const double ej = 2.0 * phi * orc_boundary_datum(m, bc, next, y);
       if (i == 0) {
-        acc -= Wn * g[next];
+        acc -= Wn * g0[next];
         acc += Wn * ej;
       } else {
         for (int h = 0; h < mh; ++h)
@@ -973,9 +973,10 @@ static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc
 
 int orc_trace_cv(const orc_mesh* m, const double* points, const int32_t* point_prim,
                  int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed, uint32_t problem,
-                 const double* g, int64_t n_items, const int64_t* item_point,
+                 const double* g, const double* g0, int64_t n_items, const int64_t* item_point,
                  const int64_t* item_path, double* value, int n_threads) {
   if (check_args(m, bc, walk_len) || !g) return 1;
+  if (!g0) g0 = g;
   if (orc_resolve_formulation(m, bc->formulation) != ORC_SINGLE_LAYER || bc->density) return 1;
   double* normals = make_normals(m);
 #ifdef _OPENMP
@@ -988,8 +989,8 @@ int orc_trace_cv(const orc_mesh* m, const double* points, const int32_t* point_p
     double x0[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
     const int64_t prim0 = point_prim ? point_prim[p] : -1;
-    value[it] = one_path_cv(m, normals, bc, g, x0, prim0, walk_len, seed, problem, (uint32_t)p,
-                            (uint32_t)item_path[it]);
+    value[it] = one_path_cv(m, normals, bc, g, g0, x0, prim0, walk_len, seed, problem,
+                            (uint32_t)p, (uint32_t)item_path[it]);
   }
   free(normals);
   return 0;

@@ -120,21 +120,23 @@ double orc_self_panel(const orc_mesh* mesh, int64_t prim, const double* x, doubl
 double orc_prim_potential(const orc_mesh* mesh, int64_t prim, const double* x);
 
 /* Learned control variate, single layer (see oracle.c): per-path values of the
- * corrected estimator for a per-primitive table g (the network's prediction of
- * the boundary unknown minus its emission).  The per-point add-back
- * sum_T g_T int_T G(x0, y) dA comes from orc_cv_addback (zero when M = 1). */
+ * corrected estimator for per-primitive tables g (lines 1.., the network's
+ * prediction of the boundary unknown minus its emission) and g0 (line 0; NULL
+ * means g0 = g).  The per-point add-back sum_T g0_T int_T G(x0, y) dA comes
+ * from orc_cv_addback (zero when M = 1). */
 int orc_trace_cv(const orc_mesh* mesh, const double* points, const int32_t* point_prim,
                  int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed,
-                 uint32_t problem, const double* g, int64_t n_items, const int64_t* item_point,
-                 const int64_t* item_path, double* value, int n_threads);
+                 uint32_t problem, const double* g, const double* g0, int64_t n_items,
+                 const int64_t* item_point, const int64_t* item_path, double* value,
+                 int n_threads);
 /* randomized = 0: sum_T g_T int_T G(x0, y) dA in closed form.  randomized = 1:
  * closed form only for triangles whose centroid lies within four bounding radii of
- * x0; every other triangle contributes g_T A_T G(x0, y) at one uniform point y
- * drawn from a 32-bit integer hash of (seed, triangle, point id) (an unbiased
- * value of the same sum). point_ids NULL = 0..n-1. */
-int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points,
-                   const uint32_t* point_ids, int64_t n_points, uint32_t seed, int randomized,
-                   double* out, int n_threads);
+ * x0; every other triangle contributes g_T A_T G(x0, y_T) at one uniform point
+ * y_T of the triangle drawn from a 32-bit integer hash of (seed, triangle) and
+ * shared by all evaluation points (an unbiased value of the same sum at each
+ * point). */
+int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points, int64_t n_points,
+                   uint32_t seed, int randomized, double* out, int n_threads);
 
 /* Unit outward normal of a primitive. */
 void orc_prim_normal(const orc_mesh* mesh, int64_t prim, double* n_out);

@@ -26,10 +26,10 @@ namespace wobi {
 
 constexpr int kSolveBlock = 256;  // lanes per workgroup of the single-problem solve
 
-// log2 of the lanes that share one point: the smallest power of two >= N,
-// at least one wavefront, at most the block
+// log2 of the lanes that share one point: the smallest power of two >= N, at
+// most the block (a wavefront holds 64 / lanes points when N < 64)
 inline int lpp_shift_for(int32_t samples, int block) {
-  int s = 6;
+  int s = 0;
   while ((1 << s) < samples && (1 << s) < block) ++s;
   return s;
 }

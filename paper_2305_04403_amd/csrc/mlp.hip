@@ -158,11 +158,18 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(Net net, const float* y
   if ((threadIdx.x & 3) == 0 && r0 + r < n) out[r0 + r] = f;
 }
 
+// Target transform t -> (t - shift) inv_scale, clamped to [-clip, clip] when clip > 0.
+struct TargetMap {
+  int on;
+  float shift, inv_scale, clip;
+};
+
 // Loss and gradient of one tile: writes the tile's partial gradient (NP floats)
 // and partial loss (sum of squared errors).  scale = 1 / (rows in the batch).
 __global__ void __launch_bounds__(NT) mlp_grad_kernel(Net net, const float* y, const float* target,
-                                                      int64_t n, float scale, float* part_grad,
-                                                      float* part_loss, float* sbuf_all) {
+                                                      TargetMap tm, int64_t n, float scale,
+                                                      float* part_grad, float* part_loss,
+                                                      float* sbuf_all) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Smem& sm = *reinterpret_cast<Smem*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -173,7 +180,14 @@ __global__ void __launch_bounds__(NT) mlp_grad_kernel(Net net, const float* y, c
   int r;
   const float f = output_row(net, sm, r);
   float e = 0.f;
-  if (r0 + r < n) e = f - target[r0 + r];
+  if (r0 + r < n) {
+    float tv = target[r0 + r];
+    if (tm.on) {
+      tv = (tv - tm.shift) * tm.inv_scale;
+      if (tm.clip > 0.f) tv = fminf(fmaxf(tv, -tm.clip), tm.clip);
+    }
+    e = f - tv;
+  }
   if ((tid & 3) == 0) sm.g5[r] = 2.f * e * scale;
   sm.red[tid] = (tid & 3) == 0 ? e * e : 0.f;
   __syncthreads();
@@ -430,14 +444,22 @@ wob_status wob_mlp_forward(wob_mlp h, const float* y, int64_t n, float* out, voi
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 
-wob_status wob_mlp_backward(wob_mlp h, const float* y, const float* target, int64_t n, float* grad,
-                            float* loss, void* stream) {
+wob_status wob_mlp_backward(wob_mlp h, const float* y, const float* target,
+                            const wob_target_map* tmap, int64_t n, float* grad, float* loss,
+                            void* stream) {
   if (!h || n <= 0 || n > h->max_batch || !y || !target || !grad) return WOB_E_ARG;
+  TargetMap tm{0, 0.f, 1.f, 0.f};
+  if (tmap) {
+    if (!std::isfinite(tmap->shift) || !(tmap->scale > 0.f) || !std::isfinite(tmap->scale) ||
+        !(tmap->clip >= 0.f))
+      return WOB_E_ARG;
+    tm = TargetMap{1, tmap->shift, 1.f / tmap->scale, tmap->clip};
+  }
   hipStream_t st = (hipStream_t)stream;
   const int tiles = (int)((n + TR - 1) / TR);
   const float scale = 1.f / (float)n;
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(tiles), dim3(NT), sizeof(Smem), st, h->net, y, target, n,
-                     scale, h->part, h->part_loss, h->sbuf);
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3(tiles), dim3(NT), sizeof(Smem), st, h->net, y, target, tm,
+                     n, scale, h->part, h->part_loss, h->sbuf);
   hipLaunchKernelGGL(reduce_grad_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, h->part, tiles,
                      grad, h->part_loss, loss, scale);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
@@ -454,9 +476,10 @@ wob_status wob_mlp_adam_step(wob_mlp h, const float* grad, int64_t step, float l
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 
-wob_status wob_mlp_train_step(wob_mlp h, const float* y, const float* target, int64_t n, int64_t step,
-                              float lr, float* loss, void* stream) {
-  wob_status s = wob_mlp_backward(h, y, target, n, h ? h->grad : nullptr, loss, stream);
+wob_status wob_mlp_train_step(wob_mlp h, const float* y, const float* target,
+                              const wob_target_map* tmap, int64_t n, int64_t step, float lr,
+                              float* loss, void* stream) {
+  wob_status s = wob_mlp_backward(h, y, target, tmap, n, h ? h->grad : nullptr, loss, stream);
   if (s != WOB_OK) return s;
   return wob_mlp_adam_step(h, h->grad, step, lr, 0.9f, 0.999f, 1e-8f, stream);
 }

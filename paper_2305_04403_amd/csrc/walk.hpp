@@ -20,10 +20,11 @@ struct WalkArgs {
   R self_p;                   // floor(p_s 2^24) / 2^24
   uint32_t k0, k1;            // Philox key
   uint32_t problem;           // problem index (counter word 2, bits 24..31)
-  int32_t lpp_shift;          // log2 of lanes per point (6 .. log2 of the block size)
+  int32_t lpp_shift;          // log2 of lanes per point (0 .. log2 of the block size)
   int32_t form;               // F_DL / F_DIRECT / F_SL (read by the batched kernel)
   int32_t density;            // estimate the boundary unknown at boundary points (no own emission)
   const R* cv_g;              // control-variate table per caller primitive id (single layer), or null
+  const R* cv_g0;             // its line-0 table (the add-back's), set whenever cv_g is
   R* mean_out;
   R* var_out;
   R* path_out;
@@ -300,7 +301,7 @@ __device__ __forceinline__ R run_path_cv(const WalkArgs<R, 3>& a, uint32_t point
       const R gp = self_panel<R, 3>(gc, nc, x, unit<R>(r1.x), unit<R>(r1.y), y);
       Wn = W * (i == 0 ? gp : (R)-2 * phi * gc.alpha * gp) / a.self_p;
       next_idx = cur_idx;
-      if (i == 0 && !last) acc -= Wn * a.cv_g[gc.id];
+      if (i == 0 && !last) acc -= Wn * a.cv_g0[gc.id];
       acc += Wn * (last ? phi : (R)2 * phi) * boundary_datum<R, 3>(a.prog, gc, nc, y);
     } else {
       const R mixf = mixture ? (R)1 / ((R)1 - a.self_p) : (R)1;
@@ -323,7 +324,7 @@ __device__ __forceinline__ R run_path_cv(const WalkArgs<R, 3>& a, uint32_t point
       aj *= mixf;
       Wn = W * aj * (R)h.m;
       if (i == 0) {
-        acc -= Wn * a.cv_g[gy.id];
+        acc -= Wn * a.cv_g0[gy.id];
         acc += Wn * (R)2 * phi * boundary_datum<R, 3>(a.prog, gy, ny, y);
       } else {
         acc += W * h.sum;
@@ -402,8 +403,9 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   }
   if (TRACE) return;
 
-  // per-point reduction: within the wavefront, then across the point's wavefronts
-  for (int off = 32; off > 0; off >>= 1) {
+  // per-point reduction: within the point's lanes of the wavefront, then across
+  // the point's wavefronts
+  for (int off = (lpp < 64 ? lpp : 64) >> 1; off > 0; off >>= 1) {
     const double nb = __shfl_xor(n, off, 64);
     const double mb = __shfl_xor(mean, off, 64);
     const double sb = __shfl_xor(m2, off, 64);
@@ -416,6 +418,13 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       mean = mean2;
       m2 = m22;
     }
+  }
+  if (lpp <= 64) {
+    if (lane_in_point == 0 && point < a.n_points) {
+      a.mean_out[point] = (R)mean;
+      if (a.var_out) a.var_out[point] = (R)(n > 1.0 ? m2 / (n - 1.0) : 0.0);
+    }
+    return;
   }
   const int wave = tid >> 6;
   if ((tid & 63) == 0) {
@@ -442,27 +451,26 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs<R, D> a) {
 // Add-back of the control variate: out[p] (+)= an unbiased value of
 // sum_T g_T int_T G(x_p, y) dA.  Triangles whose centroid lies within four
 // bounding radii of x_p ("near") use the closed form; every other triangle uses
-// g_T A_T G(x_p, y) at one point y uniform in T (its expectation is the exact
-// integral; G varies by at most ~30 % over a far triangle).  The point comes
-// from hash32 of (seed, triangle id, point id):
-//   h = hash32(id + 0x9e3779b9 (seed_lo + 1)), h2 = hash32(h ^ point),
-//   u0 = unit(hash32(h2 ^ 0x68e31da4)), u1 = unit(hash32(h2 ^ 0xb5297a4d)),
-//   reflected into the triangle when u0 + u1 > 1.
-// Every workgroup streams the triangles through LDS in tiles of 256 (edge
-// frames precomputed on load); each lane keeps 4 points in registers.
+// g_T A_T G(x_p, y_T) at one point y_T uniform in T (its expectation is the
+// exact integral; G varies by at most ~30 % over a far triangle).  y_T depends
+// on (seed, triangle) only, so it is drawn once per triangle when the triangle
+// is staged and shared by every point:
+//   h = hash32(id + 0x9e3779b9 (seed_lo + 1)),
+//   u0 = unit(hash32(h ^ 0x68e31da4)), u1 = unit(hash32(h ^ 0xb5297a4d)),
+//   reflected into the triangle when u0 + u1 > 1, y_T = v0 + u0 e1 + u1 e2.
+// Every workgroup streams the triangles through LDS in tiles of 256; a far pair
+// costs one distance test and one reciprocal square root.  Each lane keeps 4
+// points in registers.
 template <typename R>
 __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, const R* __restrict__ g_by_id,
-                                                         const R* __restrict__ points,
-                                                         const uint32_t* __restrict__ point_ids,
-                                                         int64_t n, uint32_t seed, R* out,
-                                                         int accumulate) {
-  constexpr int TILE = 256, PPT = 4, NF = 37;
-  __shared__ R tile[TILE * NF];
-  __shared__ uint32_t thash[TILE];
+                                                         const R* __restrict__ points, int64_t n,
+                                                         uint32_t seed, R* out, int accumulate) {
+  // per triangle: [c (3), (4 r)^2] [y_T (3), g A / (4 pi)] [v (9), t (9), u (9), n (3), g, pad]
+  constexpr int TILE = 256, PPT = 4, NF = 40;
+  __shared__ __align__(16) R tile[TILE * NF];
   const int tid = threadIdx.x;
   R x[PPT][3], acc[PPT];
   int64_t pidx[PPT];
-  uint32_t pid[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     pidx[k] = ((int64_t)blockIdx.x * PPT + k) * 256 + tid;
@@ -470,7 +478,6 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
     x[k][0] = points[q * 3 + 0];
     x[k][1] = points[q * 3 + 1];
     x[k][2] = points[q * 3 + 2];
-    pid[k] = point_ids ? point_ids[q] : (uint32_t)q;
     acc[k] = 0;
   }
   for (int32_t t0 = 0; t0 < s.n_prims; t0 += TILE) {
@@ -498,32 +505,38 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
         R dc[3] = {v[c][0] - cen[0], v[c][1] - cen[1], v[c][2] - cen[2]};
         rad2 = fmax(rad2, dot3(dc, dc));
         for (int k = 0; k < 3; ++k) {
-          T[c * 3 + k] = v[c][k];
-          T[9 + c * 3 + k] = tt[k];
-          T[18 + c * 3 + k] = uu[k];
+          T[8 + c * 3 + k] = v[c][k];
+          T[17 + c * 3 + k] = tt[k];
+          T[26 + c * 3 + k] = uu[k];
         }
       }
       R cr[3];
       cross3(g.e1, g.e2, cr);
-      T[27] = nn[0];
-      T[28] = nn[1];
-      T[29] = nn[2];
-      T[30] = g_by_id[g.id];
-      T[31] = cen[0];
-      T[32] = cen[1];
-      T[33] = cen[2];
-      T[34] = (R)16 * rad2;                                 // (4 r)^2
-      T[35] = (R)0.5 * sqrt(dot3(cr, cr));                  // area
-      T[36] = (R)0;
-      thash[tid] = hash32((uint32_t)g.id + 0x9e3779b9u * (seed + 1u));
+      const R gT = g_by_id[g.id];
+      const uint32_t h = hash32((uint32_t)g.id + 0x9e3779b9u * (seed + 1u));
+      R a = unit<R>(hash32(h ^ 0x68e31da4u)), b = unit<R>(hash32(h ^ 0xb5297a4du));
+      if (a + b > (R)1) {
+        a = (R)1 - a;
+        b = (R)1 - b;
+      }
+      T[0] = cen[0];
+      T[1] = cen[1];
+      T[2] = cen[2];
+      T[3] = (R)16 * rad2;  // (4 r)^2
+      for (int k = 0; k < 3; ++k) T[4 + k] = v[0][k] + a * (v[1][k] - v[0][k]) + b * (v[2][k] - v[0][k]);
+      T[7] = gT * (R)0.5 * sqrt(dot3(cr, cr)) * (R)(0.25 / 3.14159265358979323846);
+      T[35] = nn[0];
+      T[36] = nn[1];
+      T[37] = nn[2];
+      T[38] = gT;
+      T[39] = (R)0;
     }
     __syncthreads();
     const int cnt = s.n_prims - t0 < TILE ? s.n_prims - t0 : TILE;
     for (int q = 0; q < cnt; ++q) {
       const R* P = tile + q * NF;
-      const R gq = P[30];
-      const R c0 = P[31], c1 = P[32], c2 = P[33], near2 = P[34], area = P[35];
-      const uint32_t hq = thash[q];
+      const R c0 = P[0], c1 = P[1], c2 = P[2], near2 = P[3];
+      const R y0 = P[4], y1 = P[5], y2 = P[6], gw = P[7];
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const R dx = x[k][0] - c0, dy = x[k][1] - c1, dz = x[k][2] - c2;
@@ -533,26 +546,17 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
           for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-              v[c][m] = P[c * 3 + m];
-              tt[c][m] = P[9 + c * 3 + m];
-              uu[c][m] = P[18 + c * 3 + m];
+              v[c][m] = P[8 + c * 3 + m];
+              tt[c][m] = P[17 + c * 3 + m];
+              uu[c][m] = P[26 + c * 3 + m];
             }
-          nn[0] = P[27];
-          nn[1] = P[28];
-          nn[2] = P[29];
-          acc[k] += gq * tri_potential<R>(v, tt, uu, nn, x[k]);
+          nn[0] = P[35];
+          nn[1] = P[36];
+          nn[2] = P[37];
+          acc[k] += P[38] * tri_potential<R>(v, tt, uu, nn, x[k]);
         } else {
-          const uint32_t h2 = hash32(hq ^ pid[k]);
-          R a = unit<R>(hash32(h2 ^ 0x68e31da4u)), b = unit<R>(hash32(h2 ^ 0xb5297a4du));
-          if (a + b > (R)1) {
-            a = (R)1 - a;
-            b = (R)1 - b;
-          }
-          // y = v0 + a (v1 - v0) + b (v2 - v0)
-          const R yx = P[0] + a * (P[3] - P[0]) + b * (P[6] - P[0]) - x[k][0];
-          const R yy = P[1] + a * (P[4] - P[1]) + b * (P[7] - P[1]) - x[k][1];
-          const R yz = P[2] + a * (P[5] - P[2]) + b * (P[8] - P[2]) - x[k][2];
-          acc[k] += gq * area * (R)(0.25 / 3.14159265358979323846) * rsqrt_<R>(yx * yx + yy * yy + yz * yz);
+          const R yx = y0 - x[k][0], yy = y1 - x[k][1], yz = y2 - x[k][2];
+          acc[k] += gw * rsqrt_<R>(yx * yx + yy * yy + yz * yz);
         }
       }
     }
@@ -561,6 +565,22 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
   for (int k = 0; k < PPT; ++k)
     if (pidx[k] < n) out[pidx[k]] = accumulate ? out[pidx[k]] + acc[k] : acc[k];
 }
+
+// g0[id] = (g ? g[id] : 0) + 2 phi s(centroid of id): the line-0 table of the
+// control variate with the first emission frozen per triangle (3D).
+template <typename R>
+__global__ void emission_table_kernel(SceneView<R, 3> s, ProgramView<R> prog, R phi, const float* g,
+                                      float* g0) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= s.n_prims) return;
+  const PrimGeo<R> p = load_prim<R, 3>(s, j);
+  R n[3], y[3];
+  load_normal<R, 3>(s, j, n);
+  for (int k = 0; k < 3; ++k) y[k] = p.v0[k] + (p.e1[k] + p.e2[k]) / (R)3;
+  const R e = (R)2 * phi * boundary_datum<R, 3>(prog, p, n, y);
+  g0[p.id] = (float)((g ? (R)g[p.id] : (R)0) + e);
+}
+
 
 // Area-uniform points on the boundary: primitive by binary search of the
 // area CDF, then a uniform point on it.  Philox counter (i, 0xffffffff,
@@ -592,6 +612,7 @@ __global__ void sample_boundary_kernel(SceneView<R, D> s, const float* __restric
 }
 
 // Centroid of every primitive, written at its caller id (3D).
+
 template <typename R>
 __global__ void centroid_kernel(SceneView<R, 3> s, float* out) {
   const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;

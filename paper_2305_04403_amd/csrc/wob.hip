@@ -178,7 +178,7 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
                     const wob_bc* bc, int32_t samples, int32_t walk_len, uint64_t seed,
                     const uint32_t* point_ids, void* mean_out, void* var_out, void* path_out,
                     int32_t* vtx_prim, int32_t* vtx_m, uint64_t* counters, int mode,
-                    void* stream, const float* cv_g = nullptr) {
+                    void* stream, const float* cv_g = nullptr, const float* cv_g0 = nullptr) {
   Plan pl;
   wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
   if (s != WOB_OK) return s;
@@ -200,6 +200,7 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
       a.cv_g = cv_g;
+      a.cv_g0 = cv_g0 ? cv_g0 : cv_g;
       launch_walk<float, 3>(a, pl.form, mode, st);
     } else {
       auto a = make_args<float, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
@@ -385,40 +386,56 @@ wob_status wob_count_work(wob_scene sc, const void* points, const int32_t* point
                   nullptr, nullptr, nullptr, nullptr, counters, MODE_COUNT, stream);
 }
 
-wob_status wob_cv_addback(wob_scene sc, const float* g, const void* points,
-                          const uint32_t* point_ids, int64_t n_points, uint64_t seed, void* out,
-                          void* stream) {
+wob_status wob_cv_addback(wob_scene sc, const float* g, const void* points, int64_t n_points,
+                          uint64_t seed, void* out, void* stream) {
   if (!sc || n_points < 0 || (n_points > 0 && (!g || !points || !out))) return WOB_E_ARG;
   if (sc->dim != 3 || sc->precision != WOB_F32) return WOB_E_UNSUPPORTED;
   if (n_points == 0) return WOB_OK;
   const int64_t blocks = (n_points + 1023) / 1024;
   hipLaunchKernelGGL((wob::cv_addback_kernel<float>), dim3((unsigned)blocks), dim3(256), 0,
-                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points, point_ids,
-                     n_points, (uint32_t)(seed & 0xffffffffu), (float*)out, 0);
+                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points, n_points,
+                     (uint32_t)(seed & 0xffffffffu), (float*)out, 0);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 
 wob_status wob_solve_cv(wob_scene sc, const void* points, const int32_t* point_prim,
                         int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
-                        uint64_t seed, const float* g, void* mean_out, void* var_out, void* stream) {
+                        uint64_t seed, const float* g, const float* g0, void* mean_out,
+                        void* var_out, void* stream) {
   if (!g) return WOB_E_ARG;
+  if (!g0) g0 = g;
   wob_status s = run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, nullptr,
-                          mean_out, var_out, nullptr, nullptr, nullptr, nullptr, MODE_SOLVE, stream, g);
+                          mean_out, var_out, nullptr, nullptr, nullptr, nullptr, MODE_SOLVE, stream,
+                          g, g0);
   if (s != WOB_OK || n_points == 0 || walk_len < 2) return s;
   const int64_t blocks = (n_points + 1023) / 1024;
   hipLaunchKernelGGL((wob::cv_addback_kernel<float>), dim3((unsigned)blocks), dim3(256), 0,
-                     (hipStream_t)stream, view<float, 3>(sc), g, (const float*)points,
-                     (const uint32_t*)nullptr, n_points, (uint32_t)(seed & 0xffffffffu),
-                     (float*)mean_out, 1);
+                     (hipStream_t)stream, view<float, 3>(sc), g0, (const float*)points, n_points,
+                     (uint32_t)(seed & 0xffffffffu), (float*)mean_out, 1);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 
 wob_status wob_trace_cv(wob_scene sc, const void* points, const int32_t* point_prim,
                         int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
-                        uint64_t seed, const float* g, void* path_out, void* stream) {
+                        uint64_t seed, const float* g, const float* g0, void* path_out,
+                        void* stream) {
   if (!g) return WOB_E_ARG;
   return run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, nullptr, nullptr,
-                  nullptr, path_out, nullptr, nullptr, nullptr, MODE_TRACE, stream, g);
+                  nullptr, path_out, nullptr, nullptr, nullptr, MODE_TRACE, stream, g, g0 ? g0 : g);
+}
+
+wob_status wob_cv_emission(wob_scene sc, const wob_bc* bc, const float* g, float* g0_out,
+                           void* stream) {
+  if (!sc || !bc || !g0_out) return WOB_E_ARG;
+  if (sc->dim != 3 || sc->precision != WOB_F32) return WOB_E_UNSUPPORTED;
+  Plan pl;
+  wob_status s = plan_walk(sc, bc, 2, 2, &pl);
+  if (s != WOB_OK) return s;
+  if (pl.form != WOB_F_SINGLE_LAYER || bc->density) return WOB_E_UNSUPPORTED;
+  const auto a = make_args<float, 3>(sc, pl, nullptr, nullptr, 0, bc, 2, 2, 0);
+  hipLaunchKernelGGL((wob::emission_table_kernel<float>), dim3((unsigned)((sc->n_prims + 255) / 256)),
+                     dim3(256), 0, (hipStream_t)stream, view<float, 3>(sc), a.prog, a.phi, g, g0_out);
+  return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 
 wob_status wob_sample_boundary(wob_scene sc, int64_t n, uint64_t seed, void* points_out,

@@ -11,10 +11,13 @@ Steps, each a call into libwob.so (this module only sequences them):
   2. ``wob_solve`` in density mode (walk length M - 1, a few paths each):
      one noisy estimate of the target per point;
   3. ``wob_mlp_train_step`` (matrix-core forward / backward + Adam) over the
-     points, cosine learning-rate decay, on standardised and clipped targets
-     (clipping only shapes the fit: the estimator stays exact for any g);
-  4. the output layer is rescaled to the raw targets and ``wob_cv_table``
-     evaluates the network at every centroid.
+     points, cosine learning-rate decay, on targets standardised and clipped
+     inside the loss (median and interquartile range of a 64k subsample read
+     back to the host; clipping only shapes the fit: the estimator stays exact
+     for any g);
+  4. the output layer is rescaled to the raw targets, ``wob_cv_table``
+     evaluates the network at every centroid (g) and ``wob_cv_emission`` adds
+     the line-0 emission at the centroid (g0 = g + 2 phi s).
 """
 from __future__ import annotations
 
@@ -65,6 +68,7 @@ class LearnedControlVariate:
         self.cfg = cfg or CVConfig()
         self.net = None
         self.g = None
+        self.g0 = None
         self.timings = {}
         self.history = []
 
@@ -77,13 +81,13 @@ class LearnedControlVariate:
         dbc = dataclasses.replace(self.bc, density=True)
         target, _ = wob.solve(self.scene, pts, dbc, cfg.target_paths, self.walk_len - 1,
                               seed=cfg.seed + 1, point_prim=prim, want_var=False, stream=stream)
-        sync()
+        sub = target[: min(cfg.n_train, 1 << 16)].cpu().numpy().astype(np.float64)
         t1 = time.perf_counter()
-        med = target.median()
-        q = torch.quantile(target[: min(cfg.n_train, 1 << 20)].float(),
-                           torch.tensor([0.25, 0.75], device=target.device))
-        scale = float(max((q[1] - q[0]).item() / 1.349, 1e-12))
-        tn = ((target - med) / scale).clamp_(-cfg.clip, cfg.clip).contiguous()
+        sub = sub[np.isfinite(sub)]
+        med = float(np.median(sub)) if sub.size else 0.0
+        q25, q75 = np.quantile(sub, [0.25, 0.75]) if sub.size else (0.0, 1.0)
+        scale = float(max((q75 - q25) / 1.349, 1e-12))
+        tmap = (med, scale, cfg.clip)
         p0, B = init_params(self.scene.dim, cfg.sigma, cfg.seed + 2)
         self.net = wob.MLP(self.scene.dim, B, p0, max_batch=cfg.batch)
         steps_per_epoch = max(1, cfg.n_train // cfg.batch)
@@ -95,7 +99,7 @@ class LearnedControlVariate:
                 step += 1
                 lr = cfg.lr * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / total))
                 sl = slice(k * cfg.batch, (k + 1) * cfg.batch)
-                self.net.train_step(pts[sl], tn[sl], step, lr, loss=loss, stream=stream)
+                self.net.train_step(pts[sl], target[sl], step, lr, loss=loss, target_map=tmap, stream=stream)
                 if k == steps_per_epoch - 1:
                     self.history.append(float(loss.item()))
         sync()
@@ -104,21 +108,22 @@ class LearnedControlVariate:
         p = self.net.params()
         o = p.shape[0] - HIDDEN - 1
         p[o:o + HIDDEN] *= scale
-        p[-1] = p[-1] * scale + float(med.item())
+        p[-1] = p[-1] * scale + med
         self.net.set_params(p)
         self.g = wob.cv_table(self.scene, self.net, stream=stream)
+        self.g0 = wob.cv_emission(self.scene, self.bc, self.g, stream=stream)
         sync()
         t3 = time.perf_counter()
         self.timings = {"targets_s": t1 - t0, "train_s": t2 - t1, "table_s": t3 - t2, "fit_s": t3 - t0,
                         "train_steps": total, "final_loss": self.history[-1] if self.history else None,
-                        "target_median": float(med.item()), "target_scale": scale}
+                        "target_median": med, "target_scale": scale}
         return self.timings
 
     def solve(self, points, samples: int, seed: int = 0, point_prim=None, want_var=True, stream=None):
         if self.g is None:
             raise wob.WobError("fit() first")
         return wob.solve_cv(self.scene, points, self.bc, samples, self.walk_len, self.g, seed=seed,
-                            point_prim=point_prim, want_var=want_var, stream=stream)
+                            point_prim=point_prim, want_var=want_var, stream=stream, g0=self.g0)
 
     def close(self):
         if self.net is not None:

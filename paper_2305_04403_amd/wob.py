@@ -28,7 +28,7 @@ EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_pa
             "wob_batch_free", "wob_solve_batched", "wob_mlp_n_params", "wob_mlp_create",
             "wob_mlp_free", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
             "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
-            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_sample_boundary")
+            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary")
 
 
 class WobError(RuntimeError):
@@ -57,6 +57,14 @@ class _Problem(C.Structure):
 
 class _Tune(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
+class _TargetMap(C.Structure):
+    _fields_ = [("shift", C.c_float), ("scale", C.c_float), ("clip", C.c_float)]
+
+
+def _tmap(m):
+    return None if m is None else C.byref(_TargetMap(float(m[0]), float(m[1]), float(m[2])))
 
 
 _lib = None
@@ -99,9 +107,9 @@ def lib():
     L.wob_mlp_get_params.argtypes = [vp, vp]
     L.wob_mlp_set_params.argtypes = [vp, vp]
     L.wob_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
-    L.wob_mlp_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.wob_mlp_backward.argtypes = [vp, vp, vp, C.POINTER(_TargetMap), i64, vp, vp, vp]
     L.wob_mlp_adam_step.argtypes = [vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, vp]
-    L.wob_mlp_train_step.argtypes = [vp, vp, vp, i64, i64, C.c_float, vp, vp]
+    L.wob_mlp_train_step.argtypes = [vp, vp, vp, C.POINTER(_TargetMap), i64, i64, C.c_float, vp, vp]
     for name in ("wob_mlp_create", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
                  "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
             "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_sample_boundary"):
@@ -109,10 +117,11 @@ def lib():
     L.wob_cv_table.argtypes = [vp, vp, vp, vp]
     L.wob_sample_boundary.argtypes = [vp, i64, u64, vp, vp, vp]
     L.wob_sample_boundary.restype = C.c_int
-    L.wob_solve_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp]
-    L.wob_trace_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
-    L.wob_cv_addback.argtypes = [vp, vp, vp, vp, i64, u64, vp, vp]
-    for name in ("wob_cv_table", "wob_solve_cv", "wob_trace_cv", "wob_cv_addback"):
+    L.wob_solve_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
+    L.wob_trace_cv.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp]
+    L.wob_cv_addback.argtypes = [vp, vp, vp, i64, u64, vp, vp]
+    L.wob_cv_emission.argtypes = [vp, C.POINTER(_BC), vp, vp, vp]
+    for name in ("wob_cv_table", "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission"):
         getattr(L, name).restype = C.c_int
     L.wob_status_string.argtypes = [C.c_int]
     L.wob_status_string.restype = C.c_char_p
@@ -382,21 +391,24 @@ class MLP:
                "wob_mlp_forward")
         return out
 
-    def backward(self, y, target, stream=None):
+    def backward(self, y, target, target_map=None, stream=None):
+        """target_map: (shift, scale, clip) applied to the targets inside the loss."""
         torch = _torch()
         grad = torch.empty(self.n_params, dtype=torch.float32, device=y.device)
         loss = torch.empty(1, dtype=torch.float32, device=y.device)
-        _check(lib().wob_mlp_backward(self.handle, _dev_ptr(y), _dev_ptr(target), y.shape[0],
-                                      _dev_ptr(grad), _dev_ptr(loss), _stream(stream)), "wob_mlp_backward")
+        _check(lib().wob_mlp_backward(self.handle, _dev_ptr(y), _dev_ptr(target), _tmap(target_map),
+                                      y.shape[0], _dev_ptr(grad), _dev_ptr(loss), _stream(stream)),
+               "wob_mlp_backward")
         return loss, grad
 
     def adam_step(self, grad, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8, stream=None):
         _check(lib().wob_mlp_adam_step(self.handle, _dev_ptr(grad), int(step), lr, b1, b2, eps,
                                        _stream(stream)), "wob_mlp_adam_step")
 
-    def train_step(self, y, target, step: int, lr: float, loss=None, stream=None):
-        _check(lib().wob_mlp_train_step(self.handle, _dev_ptr(y), _dev_ptr(target), y.shape[0], int(step),
-                                        lr, _dev_ptr(loss), _stream(stream)), "wob_mlp_train_step")
+    def train_step(self, y, target, step: int, lr: float, loss=None, target_map=None, stream=None):
+        _check(lib().wob_mlp_train_step(self.handle, _dev_ptr(y), _dev_ptr(target), _tmap(target_map),
+                                        y.shape[0], int(step), lr, _dev_ptr(loss), _stream(stream)),
+               "wob_mlp_train_step")
 
     def close(self):
         if getattr(self, "handle", None):
@@ -429,8 +441,18 @@ def cv_table(scene: Scene, net: "MLP", stream=None):
     return g
 
 
+def cv_emission(scene: Scene, bc: BC, g=None, stream=None):
+    """Line-0 table g0 = g + 2 phi s(centroid) (g None = 0)."""
+    torch = _torch()
+    g0 = torch.empty(scene.info()["n_prims"], dtype=torch.float32, device="cuda")
+    b = bc.c()
+    _check(lib().wob_cv_emission(scene.handle, C.byref(b), _dev_ptr(g), _dev_ptr(g0), _stream(stream)),
+           "wob_cv_emission")
+    return g0
+
+
 def solve_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed: int = 0,
-             point_prim=None, want_var: bool = True, stream=None, out=None):
+             point_prim=None, want_var: bool = True, stream=None, out=None, g0=None):
     torch = _torch()
     P = points.shape[0]
     if out is None:
@@ -440,27 +462,27 @@ def solve_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed:
         mean, var = out
     b = bc.c()
     _check(lib().wob_solve_cv(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
-                              int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(mean),
-                              _dev_ptr(var), _stream(stream)), "wob_solve_cv")
+                              int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(g0),
+                              _dev_ptr(mean), _dev_ptr(var), _stream(stream)), "wob_solve_cv")
     return mean, var
 
 
 def trace_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed: int = 0,
-             point_prim=None, stream=None):
+             point_prim=None, stream=None, g0=None):
     torch = _torch()
     P = points.shape[0]
     path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
     b = bc.c()
     _check(lib().wob_trace_cv(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
-                              int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(path),
-                              _stream(stream)), "wob_trace_cv")
+                              int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(g0),
+                              _dev_ptr(path), _stream(stream)), "wob_trace_cv")
     return path
 
 
-def cv_addback(scene: Scene, g, points, seed: int = 0, point_ids=None, stream=None):
+def cv_addback(scene: Scene, g, points, seed: int = 0, stream=None):
     torch = _torch()
     out = torch.empty(points.shape[0], dtype=scene.dtype, device=points.device)
-    _check(lib().wob_cv_addback(scene.handle, _dev_ptr(g), _dev_ptr(points), _dev_ptr(point_ids),
-                                points.shape[0], C.c_uint64(seed), _dev_ptr(out), _stream(stream)),
+    _check(lib().wob_cv_addback(scene.handle, _dev_ptr(g), _dev_ptr(points), points.shape[0],
+                                C.c_uint64(seed), _dev_ptr(out), _stream(stream)),
            "wob_cv_addback")
     return out

@@ -55,17 +55,20 @@ def test_addback_matches_oracle(W, tori):
     scene.close()
 
 
-def test_trace_cv_matches_oracle(W, tori):
+@pytest.mark.parametrize("separate_g0", [False, True])
+def test_trace_cv_matches_oracle(W, tori, separate_g0):
     rng = np.random.default_rng(2)
     g = PT.f32(rng.standard_normal(tori.mesh.n_prims))
+    g0 = PT.f32(rng.standard_normal(tori.mesh.n_prims) * 2.0 + 1.0) if separate_g0 else None
     scene = W.Scene(tori.mesh, W.F32)
     wb, ob = bcs(W, tori)
     P, N, M = tori.points.shape[0], 64, 4
     val = W.trace_cv(scene, dev(tori.points), wb, N, M, g=dev(g), seed=3,
-                     point_prim=dev(tori.point_prim, torch.int32))
+                     point_prim=dev(tori.point_prim, torch.int32), g0=None if g0 is None else dev(g0))
     torch.cuda.synchronize()
     ip, ik = np.repeat(np.arange(P), N), np.tile(np.arange(N), P)
-    ref = oracle.trace_cv(oracle.OracleMesh(tori.mesh), tori.points, tori.point_prim, ob, M, 3, g, ip, ik)
+    ref = oracle.trace_cv(oracle.OracleMesh(tori.mesh), tori.points, tori.point_prim, ob, M, 3, g, ip, ik,
+                          g0=g0)
     plain = oracle.trace(oracle.OracleMesh(tori.mesh), tori.points, tori.point_prim, ob, M, 3, ip, ik,
                          want_pos=False)
     v = val.cpu().double().numpy().reshape(-1)
@@ -112,6 +115,26 @@ def test_cv_table_is_network_at_centroids(W, tori):
     scene.close()
 
 
+def test_emission_table_matches_oracle(W, tori):
+    """g0 = g + 2 phi s(centroid) with the triangle's own kind (Neumann or Robin)."""
+    rng = np.random.default_rng(8)
+    g = PT.f32(rng.standard_normal(tori.mesh.n_prims))
+    scene = W.Scene(tori.mesh, W.F32)
+    wb, ob = bcs(W, tori)
+    g0 = W.cv_emission(scene, wb, dev(g)).cpu().double().numpy()
+    e0 = W.cv_emission(scene, wb).cpu().double().numpy()
+    torch.cuda.synchronize()
+    om = oracle.OracleMesh(tori.mesh)
+    cen = tori.mesh.verts[tori.mesh.prims].mean(axis=1)
+    ref = np.array([2.0 * ob.domain * oracle.boundary_datum(om, ob, j, cen[j]) for j in range(tori.mesh.n_prims)])
+    scale = np.abs(ref) + np.median(np.abs(ref))
+    assert np.max(np.abs(e0 - ref) / scale) < 1e-5
+    assert np.max(np.abs(g0 - (g + ref)) / (scale + np.abs(g))) < 1e-5
+    with pytest.raises(W.WobError):  # not a single-layer problem
+        W.cv_emission(scene, W.BC(1, W.DOUBLE_LAYER, W.PROG_CONST, (1.0,)))
+    scene.close()
+
+
 def test_solve_cv_is_unbiased_on_gpu(W, tori):
     """Corrected and plain solves on the same points: the per-point difference of
     the means is within 4.5 standard errors of zero, for an arbitrary table."""
@@ -123,7 +146,8 @@ def test_solve_cv_is_unbiased_on_gpu(W, tori):
     pp = dev(tori.point_prim, torch.int32)
     N = 16384
     mp, vp = W.solve(scene, pts, wb, N, 4, seed=1, point_prim=pp)
-    mc, vc = W.solve_cv(scene, pts, wb, N, 4, g=dev(g), seed=2, point_prim=pp)
+    g0 = W.cv_emission(scene, wb, dev(g))
+    mc, vc = W.solve_cv(scene, pts, wb, N, 4, g=dev(g), seed=2, point_prim=pp, g0=g0)
     torch.cuda.synchronize()
     d = mc.double().cpu().numpy() - mp.double().cpu().numpy()
     se = np.sqrt((vp.double().cpu().numpy() + vc.double().cpu().numpy()) / N)
@@ -131,9 +155,9 @@ def test_solve_cv_is_unbiased_on_gpu(W, tori):
     print(f"max |z| = {np.abs(z).max():.2f}")
     assert np.abs(z).max() < 4.5
     # the mean of traced corrected paths plus the add-back is the solve's mean
-    val = W.trace_cv(scene, pts, wb, 256, 4, g=dev(g), seed=7, point_prim=pp)
-    add = W.cv_addback(scene, dev(g), pts, seed=7)
-    m2, _ = W.solve_cv(scene, pts, wb, 256, 4, g=dev(g), seed=7, point_prim=pp)
+    val = W.trace_cv(scene, pts, wb, 256, 4, g=dev(g), seed=7, point_prim=pp, g0=g0)
+    add = W.cv_addback(scene, g0, pts, seed=7)
+    m2, _ = W.solve_cv(scene, pts, wb, 256, 4, g=dev(g), seed=7, point_prim=pp, g0=g0)
     torch.cuda.synchronize()
     np.testing.assert_allclose(m2.cpu().numpy(), val.double().mean(dim=1).cpu().numpy() + add.cpu().numpy(),
                                rtol=1e-5, atol=1e-5)

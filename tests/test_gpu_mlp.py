@@ -67,6 +67,31 @@ def test_gradient_matches_bf16_oracle(W):
     net.close()
 
 
+def test_target_map_is_applied_inside_the_loss(W):
+    """Raw targets with (shift, scale, clip) on the GPU against the oracle given
+    the mapped targets (t - shift) / scale clamped to [-clip, clip]."""
+    params, B = rand_net(14)
+    params, B = f32(params), f32(B)
+    rng = np.random.default_rng(4)
+    y = f32(rng.uniform(-1.5, 1.5, (700, 3)))
+    t = f32(rng.standard_cauchy(700) * 3.0 + 2.0)
+    shift, scale, clip = 2.0, 3.0, 4.0
+    net = W.MLP(3, B, params, max_batch=1024)
+    loss, grad = net.backward(torch.as_tensor(y, dtype=torch.float32, device="cuda"),
+                              torch.as_tensor(t, dtype=torch.float32, device="cuda"),
+                              target_map=(shift, scale, clip))
+    torch.cuda.synchronize()
+    tm = np.clip((t.astype(np.float64) - shift) / scale, -clip, clip)
+    assert np.sum(np.abs(tm) == clip) > 20  # the clamp is exercised
+    lo, go = oracle.mlp_loss_grad(params, B, y, tm, bf16=True)
+    assert loss.item() == pytest.approx(lo, rel=2e-3)
+    assert np.linalg.norm(grad.cpu().double().numpy() - go) <= 1e-2 * np.linalg.norm(go)
+    with pytest.raises(W.WobError):
+        net.backward(torch.as_tensor(y, dtype=torch.float32, device="cuda"),
+                     torch.as_tensor(t, dtype=torch.float32, device="cuda"), target_map=(0.0, 0.0, 1.0))
+    net.close()
+
+
 def test_adam_matches_oracle_and_training_reduces_loss(W):
     params, B = rand_net(13)
     params, B = f32(params), f32(B)

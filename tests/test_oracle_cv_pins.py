@@ -178,11 +178,12 @@ def test_control_variate_is_unbiased_for_any_table():
     bc = oracle.make_bc(**{k: w.bc[k] for k in ("domain", "formulation", "program", "params")})
     rng = np.random.default_rng(3)
     g = rng.standard_normal(w.mesh.n_prims) * 3.0 + 1.0
+    g0 = rng.standard_normal(w.mesh.n_prims) * 2.0 - 1.0   # a different line-0 table
     P, N = w.points.shape[0], 3000
     ip, ik = np.repeat(np.arange(P), N), np.tile(np.arange(N), P)
     plain = oracle.trace(om, w.points, w.point_prim, bc, w.walk_len, 1, ip, ik, want_pos=False)["value"]
-    cv = oracle.trace_cv(om, w.points, w.point_prim, bc, w.walk_len, 1, g, ip, ik)
-    add = oracle.cv_addback(om, g, w.points, seed=1, randomized=True)
+    cv = oracle.trace_cv(om, w.points, w.point_prim, bc, w.walk_len, 1, g, ip, ik, g0=g0)
+    add = oracle.cv_addback(om, g0, w.points, seed=1, randomized=True)
     d = (cv.reshape(P, N) - plain.reshape(P, N))
     diff = d.mean(axis=1) + add
     se = d.std(axis=1, ddof=1) / np.sqrt(N)
@@ -240,3 +241,28 @@ def test_randomized_addback_averages_to_the_closed_form():
     assert np.max(np.abs(z)) < 4.5
     scale = oracle.cv_addback(om, np.abs(g), w.points)
     assert np.max(sd / scale) < 0.02
+
+
+def emission_table(om, mesh, bc):
+    """2 phi s at each triangle's centroid (the line-0 emission, frozen per triangle)."""
+    cen = mesh.verts[mesh.prims].mean(axis=1)
+    return np.array([2.0 * bc.domain * oracle.boundary_datum(om, bc, j, cen[j]) for j in range(mesh.n_prims)])
+
+
+def test_line0_emission_table_removes_most_first_line_variance():
+    """g = 0 and g0 = emission at the centroid: the step-0 emission is replaced by
+    its closed-form integral up to its variation over one triangle, so with M = 2
+    (line 1 is the exact all-hits average) the corrected variance is far below
+    the plain one, and the mean is unchanged."""
+    w = _tori_problem()
+    om = oracle.OracleMesh(w.mesh)
+    bc = oracle.make_bc(**{k: w.bc[k] for k in ("domain", "formulation", "program", "params")})
+    e0 = emission_table(om, w.mesh, bc)
+    P, N = w.points.shape[0], 1500
+    ip, ik = np.repeat(np.arange(P), N), np.tile(np.arange(N), P)
+    plain = oracle.trace(om, w.points, w.point_prim, bc, 2, 5, ip, ik, want_pos=False)["value"].reshape(P, N)
+    cv = oracle.trace_cv(om, w.points, w.point_prim, bc, 2, 5, np.zeros_like(e0), ip, ik, g0=e0).reshape(P, N)
+    cv = cv + oracle.cv_addback(om, e0, w.points)[:, None]
+    se = np.sqrt(plain.var(axis=1, ddof=1) / N + cv.var(axis=1, ddof=1) / N)
+    assert np.max(np.abs(plain.mean(axis=1) - cv.mean(axis=1)) / se) < 4.5
+    assert np.mean(cv.var(axis=1)) < 0.5 * np.mean(plain.var(axis=1))
