@@ -345,17 +345,22 @@ struct HitAcc {
 template <typename R, int D>
 __device__ __forceinline__ bool hit_prim(const PrimGeo<R>& g, const R x[3], const R d[3], R& t, R& u, R& v) {
   if constexpr (D == 3) {
+    // Moller-Trumbore with the barycentric tests on the numerators: with
+    // U = (x - v0).(d x e2), V = d.((x - v0) x e1) and det = e1.(d x e2), the
+    // hit condition u = U / det in [0, 1], v = V / det >= 0, u + v <= 1 is
+    // U sd >= 0, V sd >= 0, (U + V) sd <= |det| for sd = sign(det); the
+    // division is left for the accepted hits.
     R pv[3], qv[3];
     cross3(d, g.e2, pv);
     const R det = dot3(g.e1, pv);
-    if (det == (R)0) return false;
-    const R inv = (R)1 / det;
     const R sv[3] = {x[0] - g.v0[0], x[1] - g.v0[1], x[2] - g.v0[2]};
-    u = dot3(sv, pv) * inv;
-    if (u < (R)0 || u > (R)1) return false;
     cross3(sv, g.e1, qv);
-    v = dot3(d, qv) * inv;
-    if (v < (R)0 || u + v > (R)1) return false;
+    const R sd = det < (R)0 ? (R)-1 : (R)1;
+    const R us = dot3(sv, pv) * sd, vs = dot3(d, qv) * sd, ad = det * sd;
+    if (det == (R)0 || us < (R)0 || vs < (R)0 || us + vs > ad) return false;
+    const R inv = (R)1 / det;
+    u = us * sd * inv;
+    v = vs * sd * inv;
     t = dot3(g.e2, qv) * inv;
     return true;
   } else {
@@ -406,6 +411,33 @@ template <typename R> __device__ __forceinline__ R safe_inv(R d) {
   return d == (R)0 ? big : (R)1 / d;
 }
 
+// Calls leaf(first, count) for every leaf whose box the line crosses, in the
+// BVH's pre-order, with a stackless walk over the skip links: a crossed inner
+// node continues at its first child, anything else at its skip link.  One loop
+// handles inner nodes and leaves; variants that split them (separate loops,
+// speculative node steps) measured slower on gfx950 here, because the extra
+// live state cost a wavefront per SIMD while saving under a tenth of the
+// vector instructions.
+template <typename R, int D, bool COUNT, typename Leaf>
+__device__ __forceinline__ void for_each_leaf(const SceneView<R, D>& s, const R inv[3], const R ox[3],
+                                              WorkCount& wc, Leaf&& leaf) {
+  int32_t i = 0;
+  const int32_t end = s.n_nodes;
+  while (i < end) {
+    const typename Rec<R, D>::Node node = s.nodes[i];
+    if (COUNT) wc.nodes += 1;
+    if (line_box<R, D>(node, inv, ox)) {
+      if (node.child >= 0) {
+        i = node.child;
+        continue;
+      }
+      const int32_t code = -1 - node.child;
+      leaf(code >> 3, (code & 7) + 1);
+    }
+    i = node.skip;
+  }
+}
+
 // Visit every hit of the line through x with direction d, skipping primitive
 // `exclude` (leaf-order index).  Per hit: count it; with `select`, draw its
 // key (Philox block 2, w = caller id) and keep the smallest (key, id); with
@@ -428,56 +460,43 @@ __device__ __forceinline__ void trace_line(const SceneView<R, D>& s, const Progr
   h.u = h.v = h.t = 0;
   h.src = 0;
   if (COUNT) wc.lines += 1;
-  int32_t i = 0;
-  const int32_t end = s.n_nodes;
-  while (i < end) {
-    const typename Rec<R, D>::Node node = s.nodes[i];
-    if (COUNT) wc.nodes += 1;
-    if (line_box<R, D>(node, inv, ox)) {
-      if (node.child >= 0) {
-        i = node.child;
-        continue;
+  for_each_leaf<R, D, COUNT>(s, inv, ox, wc, [&](int32_t first, int32_t count) {
+    for (int32_t j = first; j < first + count; ++j) {
+      if (j == exclude) continue;
+      if (COUNT) wc.prims += 1;
+      const PrimGeo<R> g = load_prim<R, D>(s, j);
+      R t, u, v;
+      if (!hit_prim<R, D>(g, x, d, t, u, v)) continue;
+      if (COUNT) wc.hits += 1;
+      h.m += 1;
+      if (select) {
+        const uint32_t key = philox(kc0, kc1, kc2, (uint32_t)g.id, k0, k1).x;
+        if (key < h.key || (key == h.key && g.id < h.id)) {
+          h.key = key;
+          h.id = g.id;
+          h.idx = j;
+          h.u = u;
+          h.v = v;
+          h.t = t;
+        }
       }
-      const int32_t code = -1 - node.child;
-      const int32_t first = code >> 3, count = (code & 7) + 1;
-      for (int32_t j = first; j < first + count; ++j) {
-        if (j == exclude) continue;
-        if (COUNT) wc.prims += 1;
-        const PrimGeo<R> g = load_prim<R, D>(s, j);
-        R t, u, v;
-        if (!hit_prim<R, D>(g, x, d, t, u, v)) continue;
-        if (COUNT) wc.hits += 1;
-        h.m += 1;
-        if (select) {
-          const uint32_t key = philox(kc0, kc1, kc2, (uint32_t)g.id, k0, k1).x;
-          if (key < h.key || (key == h.key && g.id < h.id)) {
-            h.key = key;
-            h.id = g.id;
-            h.idx = j;
-            h.u = u;
-            h.v = v;
-            h.t = t;
-          }
-        }
-        if (source) {
-          R y[3], n[3];
-          hit_point(g, u, v, y);
-          load_normal<R, D>(s, j, n);
-          R uu, grad[3];
-          program_eval<R, D>(prog, y, uu, grad);
-          const R q = dot3(n, grad);
-          // y - x = t d: distance and cosine from the line itself, free of the
-          // cancellation in y - x when the hit is close to x
-          const R rho = fabs(t);
-          const R ac = fabs(dot3(d, n));  // |cos theta_y|
-          // G q / p_all: 3D rho q / (2 |c|); 2D -rho ln(rho) q / (2 |c|)
-          const R gp = D == 3 ? rho / ((R)2 * ac) : -rho * log(rho) / ((R)2 * ac);
-          h.src += gp * q;
-        }
+      if (source) {
+        R y[3], n[3];
+        hit_point(g, u, v, y);
+        load_normal<R, D>(s, j, n);
+        R uu, grad[3];
+        program_eval<R, D>(prog, y, uu, grad);
+        const R q = dot3(n, grad);
+        // y - x = t d: distance and cosine from the line itself, free of the
+        // cancellation in y - x when the hit is close to x
+        const R rho = fabs(t);
+        const R ac = fabs(dot3(d, n));  // |cos theta_y|
+        // G q / p_all: 3D rho q / (2 |c|); 2D -rho ln(rho) q / (2 |c|)
+        const R gp = D == 3 ? rho / ((R)2 * ac) : -rho * log(rho) / ((R)2 * ac);
+        h.src += gp * q;
       }
     }
-    i = node.skip;
-  }
+  });
 }
 
 }  // namespace wob

@@ -218,53 +218,41 @@ __device__ __forceinline__ void trace_line_cv(const WalkArgs<R, 3>& a, const R x
   h.u = h.v = h.t = 0;
   h.sum = 0;
   if (COUNT) wc.lines += 1;
-  int32_t i = 0;
-  while (i < s.n_nodes) {
-    const typename Rec<R, 3>::Node node = s.nodes[i];
-    if (COUNT) wc.nodes += 1;
-    if (line_box<R, 3>(node, inv, ox)) {
-      if (node.child >= 0) {
-        i = node.child;
-        continue;
+  for_each_leaf<R, 3, COUNT>(s, inv, ox, wc, [&](int32_t first_p, int32_t count) {
+    for (int32_t j = first_p; j < first_p + count; ++j) {
+      if (j == exclude) continue;
+      if (COUNT) wc.prims += 1;
+      const PrimGeo<R> g = load_prim<R, 3>(s, j);
+      R t, u, v;
+      if (!hit_prim<R, 3>(g, x, d, t, u, v)) continue;
+      if (COUNT) wc.hits += 1;
+      h.m += 1;
+      if (select) {
+        const uint32_t key = philox(kc0, kc1, kc2, (uint32_t)g.id, a.k0, a.k1).x;
+        if (key < h.key || (key == h.key && g.id < h.id)) {
+          h.key = key;
+          h.id = g.id;
+          h.idx = j;
+          h.u = u;
+          h.v = v;
+          h.t = t;
+        }
       }
-      const int32_t code = -1 - node.child;
-      const int32_t first_p = code >> 3, count = (code & 7) + 1;
-      for (int32_t j = first_p; j < first_p + count; ++j) {
-        if (j == exclude) continue;
-        if (COUNT) wc.prims += 1;
-        const PrimGeo<R> g = load_prim<R, 3>(s, j);
-        R t, u, v;
-        if (!hit_prim<R, 3>(g, x, d, t, u, v)) continue;
-        if (COUNT) wc.hits += 1;
-        h.m += 1;
-        if (select) {
-          const uint32_t key = philox(kc0, kc1, kc2, (uint32_t)g.id, a.k0, a.k1).x;
-          if (key < h.key || (key == h.key && g.id < h.id)) {
-            h.key = key;
-            h.id = g.id;
-            h.idx = j;
-            h.u = u;
-            h.v = v;
-            h.t = t;
-          }
-        }
-        if (want_sum) {
-          R y[3], n[3];
-          hit_point(g, u, v, y);
-          load_normal<R, 3>(s, j, n);
-          const R rho = fabs(t);
-          const R acy = fabs(dot3(d, n));
-          const R sgn_t = t > (R)0 ? (R)1 : (R)-1;
-          R ah = first ? rho / ((R)2 * acy) : -phi * (sgn_t * dot3(d, nc) + gc.alpha * rho) / acy;
-          ah *= mixf;
-          const R sh = boundary_datum<R, 3>(a.prog, g, n, y);
-          const R F = last ? phi * sh : (R)2 * phi * sh + a.cv_g[g.id];
-          h.sum += ah * F;
-        }
+      if (want_sum) {
+        R y[3], n[3];
+        hit_point(g, u, v, y);
+        load_normal<R, 3>(s, j, n);
+        const R rho = fabs(t);
+        const R acy = fabs(dot3(d, n));
+        const R sgn_t = t > (R)0 ? (R)1 : (R)-1;
+        R ah = first ? rho / ((R)2 * acy) : -phi * (sgn_t * dot3(d, nc) + gc.alpha * rho) / acy;
+        ah *= mixf;
+        const R sh = boundary_datum<R, 3>(a.prog, g, n, y);
+        const R F = last ? phi * sh : (R)2 * phi * sh + a.cv_g[g.id];
+        h.sum += ah * F;
       }
     }
-    i = node.skip;
-  }
+  });
 }
 
 template <typename R, bool TRACE, bool COUNT>
@@ -674,30 +662,20 @@ __global__ void __launch_bounds__(256) intersect_kernel(SceneView<R, D> s, const
   const int32_t ex_id = exclude ? exclude[l] : -1;
   const int32_t ex = (ex_id >= 0 && ex_id < s.n_prims) ? s.leaf_of_id[ex_id] : -1;
   int32_t cnt = 0;
-  int32_t i = 0;
-  while (i < s.n_nodes) {
-    const typename Rec<R, D>::Node node = s.nodes[i];
-    if (line_box<R, D>(node, inv, ox)) {
-      if (node.child >= 0) {
-        i = node.child;
-        continue;
+  WorkCount wc = {0, 0, 0, 0};
+  for_each_leaf<R, D, false>(s, inv, ox, wc, [&](int32_t first, int32_t count) {
+    for (int32_t j = first; j < first + count; ++j) {
+      if (j == ex) continue;
+      const PrimGeo<R> g = load_prim<R, D>(s, j);
+      R t, u, v;
+      if (!hit_prim<R, D>(g, x, d, t, u, v)) continue;
+      if (cnt < max_hits) {
+        hit_ids[l * max_hits + cnt] = g.id;
+        if (hit_t) hit_t[l * max_hits + cnt] = t;
       }
-      const int32_t code = -1 - node.child;
-      const int32_t first = code >> 3, count = (code & 7) + 1;
-      for (int32_t j = first; j < first + count; ++j) {
-        if (j == ex) continue;
-        const PrimGeo<R> g = load_prim<R, D>(s, j);
-        R t, u, v;
-        if (!hit_prim<R, D>(g, x, d, t, u, v)) continue;
-        if (cnt < max_hits) {
-          hit_ids[l * max_hits + cnt] = g.id;
-          if (hit_t) hit_t[l * max_hits + cnt] = t;
-        }
-        ++cnt;
-      }
+      ++cnt;
     }
-    i = node.skip;
-  }
+  });
   n_hits[l] = cnt;
 }
 
