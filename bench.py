@@ -38,6 +38,33 @@ HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, HIT_BYTES = 32, 36, 12
 
 
+KERNEL_SOURCES = ("paper_2305_04403_amd/csrc/device.hpp", "paper_2305_04403_amd/csrc/walk.hpp",
+                  "paper_2305_04403_amd/csrc/internal.hpp", "paper_2305_04403_amd/csrc/wob.hip")
+TRAFFIC_PROFILE = "profiles/walk_kernel_icosphere20480_slice512_traffic.md"
+
+
+def measured_traffic():
+    """HBM bytes per launch (FETCH + WRITE, calibrated) from the committed
+    counter summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    rec = dict(line.strip().split(": ", 1) for line in text.splitlines()
+               if line.strip().startswith(("source-sha256-prefix:", "traffic-bytes-per-launch:")))
+    prefix = rec.get("source-sha256-prefix", "")
+    if not prefix or not h.hexdigest().startswith(prefix):
+        return None
+    fetch, write = (int(v) for v in rec["traffic-bytes-per-launch"].split())
+    return fetch + write
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -263,7 +290,8 @@ def main():
                           "hits": cnt["hits"] / lines},
         "kernel_ms": float(np.mean(kern_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic()},
+        "algorithmic_bytes_per_launch": alg_bytes,
         "rmse_vs_analytic": rmse,
         "mean_se": float(np.mean(se)),
         "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")},
