@@ -33,7 +33,7 @@ struct WalkArgs {
   unsigned long long* counters;
 };
 
-// One path.  Returns the path value u_hat(x_0).
+// One path estimates u_hat(x_0):
 //
 // Double layer (Table 1, Dirichlet; eq. mc_dirichlet_interior_sol and
 // eq. indirect_double_boundary_reordered2):  first weight -dG/dn_y / p, then
@@ -52,126 +52,243 @@ struct WalkArgs {
 // -phi m (cos_x + alpha rho) / |cos_y| (3D); where G acts on the own primitive
 // (boundary x_0, Robin vertices) the line sample is mixed with the in-plane
 // sample with probability p_s.  Emission 2 phi s, halved at x_M.
+//
+// A lane runs its paths as a state machine: begin_step draws the vertex's
+// direction (and performs in-plane self-panel steps, which trace nothing)
+// until a line has to be traced; node_step advances that line's traversal by
+// one BVH node; end_step consumes the line's hits and calls begin_step for the
+// next vertex.  The lanes of a wavefront therefore trace lines independently
+// instead of every line waiting for the wavefront's longest one.
+
+enum { ST_NONE = 0, ST_LINE = 1, ST_DONE = 2 };
+
+template <typename R, int D>
+struct PathState {
+  uint32_t point, path;  // random-number indices
+  R x0[3];
+  int32_t prim0;
+  R x[3], W, acc;
+  int32_t cur_idx, i;
+  int32_t* vp;           // per-line records (trace mode)
+  int32_t* vm;
+  uint32_t z;            // counter word 2 of the current line
+  bool first, on_gamma, mixture, last, select;
+  PrimGeo<R> gc;         // the primitive the vertex lies on (direct, single layer)
+  R nc[3];
+  R d[3], inv[3], ox[3];
+  HitAcc<R> h;
+  int32_t ni;            // traversal position (node index)
+};
+
 template <typename R, int D, int FORM, bool TRACE, bool COUNT>
-__device__ __forceinline__ R run_path(const WalkArgs<R, D>& a, uint32_t point, uint32_t path,
-                                      const R x0[3], int32_t prim0, int32_t* vprim, int32_t* vm,
-                                      WorkCount& wc) {
+__device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, D>& s, WorkCount& wc) {
   const R phi = a.phi;
-  if (TRACE) {
-    for (int i = 0; i < a.L; ++i) {
-      if (vprim) vprim[i] = -1;
-      if (vm) vm[i] = 0;
-    }
-  }
-  // a primitive id outside [-1, n_prims) is a caller error: the path is NaN
-  if (prim0 < -1 || prim0 >= a.scene.n_prims) return (R)NAN;
-  int32_t cur_idx = prim0 >= 0 ? a.scene.leaf_of_id[prim0] : -1;
-  R x[3] = {x0[0], x0[1], x0[2]};
-  if (FORM == F_DL && cur_idx >= 0 && !a.density) {
-    // Table 1: on the boundary the Dirichlet solution is the given value
-    const PrimGeo<R> g = load_prim<R, D>(a.scene, cur_idx);
-    const R nz[3] = {0, 0, 0};
-    return boundary_datum<R, D>(a.prog, g, nz, x);
-  }
-  R W = 1, acc = 0;
-  const uint32_t zbase = a.problem << 24;
-  for (int i = 0; i < a.L; ++i) {
-    const bool on_gamma = cur_idx >= 0;
-    const uint32_t z = zbase | ((uint32_t)i << 8);
-    const U4 r0 = philox(path, point, z, 0u, a.k0, a.k1);
-    R d[3];
-    direction<R, D>(r0.x, r0.y, d);
-    PrimGeo<R> gc;
-    R nc[3];
-    if (on_gamma && (FORM != F_DL)) {
-      gc = load_prim<R, D>(a.scene, cur_idx);
-      load_normal<R, D>(a.scene, cur_idx, nc);
+  for (;;) {
+    if (s.i >= a.L) return ST_DONE;
+    s.on_gamma = s.cur_idx >= 0;
+    s.z = (a.problem << 24) | ((uint32_t)s.i << 8);
+    const U4 r0 = philox(s.path, s.point, s.z, 0u, a.k0, a.k1);
+    direction<R, D>(r0.x, r0.y, s.d);
+    if (s.on_gamma && FORM != F_DL) {
+      s.gc = load_prim<R, D>(a.scene, s.cur_idx);
+      load_normal<R, D>(a.scene, s.cur_idx, s.nc);
     }
     // step 0 from an evaluation point uses the representation formula; in
     // density mode x0 is itself a vertex of the boundary recursion
-    const bool first = i == 0 && !a.density;
-    bool mixture = false, use_self = false;
+    s.first = s.i == 0 && !a.density;
+    bool use_self = false;
+    s.mixture = false;
     if constexpr (FORM == F_SL) {
-      mixture = on_gamma && (first || gc.kind == K_ROBIN);
-      use_self = mixture && (r0.z >> 8) < a.self_thr;
+      s.mixture = s.on_gamma && (s.first || s.gc.kind == K_ROBIN);
+      use_self = s.mixture && (r0.z >> 8) < a.self_thr;
     }
-    R y[3], w;
-    int32_t next_idx;
     if (use_self) {
-      const U4 r1 = philox(path, point, z | 1u, 0u, a.k0, a.k1);
-      const R gp = self_panel<R, D>(gc, nc, x, unit<R>(r1.x), unit<R>(r1.y), y);
-      w = (first ? gp : (R)-2 * phi * gc.alpha * gp) / a.self_p;
-      next_idx = cur_idx;
-      if (TRACE && vprim) vprim[i] = -2 - gc.id;
-    } else {
-      const bool last = i == a.L - 1;
-      const bool src_line = FORM == F_DIRECT;
-      const bool select = !(src_line && last);
-      HitAcc<R> h;
-      trace_line<R, D, COUNT>(a.scene, a.prog, x, d, cur_idx, select, src_line, path, point, z | 2u,
-                              a.k0, a.k1, h, wc);
-      if (TRACE) {
-        if (vm) vm[i] = h.m;
-        if (vprim) vprim[i] = (select && h.m > 0) ? h.id : -1;
-      }
-      if constexpr (FORM == F_DIRECT) {
-        R S;
-        if (on_gamma) {
-          const U4 r1 = philox(path, point, z | 1u, 0u, a.k0, a.k1);
-          R ys[3];
-          const R gp = self_panel<R, D>(gc, nc, x, unit<R>(r1.x), unit<R>(r1.y), ys);
-          S = (R)2 * phi * (h.src + gp * boundary_datum<R, D>(a.prog, gc, nc, ys));
-        } else {
-          S = phi * h.src;
-        }
-        acc += W * S * (last ? (R)0.5 : (R)1);
-        if (last) break;
-      }
-      if (h.m == 0) break;
-      const PrimGeo<R> gy = load_prim<R, D>(a.scene, h.idx);
-      hit_point(gy, h.u, h.v, y);
-      // y - x = t d: the unit direction to the hit is sign(t) d and rho = |t|
-      const R sgn_t = h.t > (R)0 ? (R)1 : (R)-1;
-      const R mm = (R)h.m;
-      if constexpr (FORM == F_DL || FORM == F_DIRECT) {
-        R nd[3];
-        normal_dir<R, D>(gy, nd);
-        const R sg = sgn_t * dot3(d, nd) > (R)0 ? (R)1 : (R)-1;  // sgn(cos theta_y)
-        if constexpr (FORM == F_DL)
-          w = (first && !on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
-        else
-          w = on_gamma ? phi * mm * sg : (R)0.5 * phi * mm * sg;
-      } else {
-        R ny[3];
-        load_normal<R, D>(a.scene, h.idx, ny);
-        const R rho = fabs(h.t);
-        const R acy = fabs(dot3(d, ny));
-        if (first) {
-          // G / p
-          w = D == 3 ? mm * rho / ((R)2 * acy) : -mm * rho * log(rho) / ((R)2 * acy);
-        } else {
-          const R cx = sgn_t * dot3(d, nc);
-          w = D == 3 ? -phi * mm * (cx + gc.alpha * rho) / acy
-                     : -phi * mm * (cx - gc.alpha * rho * log(rho)) / acy;
-        }
-        if (mixture) w /= ((R)1 - a.self_p);
-      }
-      next_idx = h.idx;
+      const U4 r1 = philox(s.path, s.point, s.z | 1u, 0u, a.k0, a.k1);
+      R y[3];
+      const R gp = self_panel<R, D>(s.gc, s.nc, s.x, unit<R>(r1.x), unit<R>(r1.y), y);
+      const R w = (s.first ? gp : (R)-2 * phi * s.gc.alpha * gp) / a.self_p;
+      if (TRACE && s.vp) s.vp[s.i] = -2 - s.gc.id;
+      s.W *= w;
+      s.x[0] = y[0];
+      s.x[1] = y[1];
+      s.x[2] = y[2];
+      // emission at the new vertex (same primitive)
+      const R sv = boundary_datum<R, D>(a.prog, s.gc, s.nc, s.x);
+      s.acc += s.W * ((s.i + 1 < a.M) ? (R)2 * phi : phi) * sv;
+      ++s.i;
+      continue;
     }
-    W *= w;
-    x[0] = y[0];
-    x[1] = y[1];
-    x[2] = y[2];
-    cur_idx = next_idx;
-    if constexpr (FORM != F_DIRECT) {
-      const PrimGeo<R> gn = load_prim<R, D>(a.scene, cur_idx);
-      R nn[3] = {0, 0, 0};
-      if (FORM != F_DL) load_normal<R, D>(a.scene, cur_idx, nn);
-      const R s = boundary_datum<R, D>(a.prog, gn, nn, x);
-      acc += W * ((i + 1 < a.M) ? (R)2 * phi : phi) * s;
+    s.last = s.i == a.L - 1;
+    s.select = !(FORM == F_DIRECT && s.last);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.inv[k] = safe_inv(s.d[k]);
+      s.ox[k] = -s.x[k] * s.inv[k];
+    }
+    s.h.m = 0;
+    s.h.key = 0xffffffffu;
+    s.h.id = 0x7fffffff;
+    s.h.idx = -1;
+    s.h.u = s.h.v = s.h.t = 0;
+    s.h.src = 0;
+    s.ni = 0;
+    if (COUNT) wc.lines += 1;
+    return ST_LINE;
+  }
+}
+
+template <typename R, int D, int FORM, bool TRACE, bool COUNT>
+__device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, D>& s, uint32_t path,
+                                          int64_t item, WorkCount& wc) {
+  s.path = path;
+  if (TRACE) {
+    s.vp = a.vtx_prim ? a.vtx_prim + item * a.L : nullptr;
+    s.vm = a.vtx_m ? a.vtx_m + item * a.L : nullptr;
+    for (int i = 0; i < a.L; ++i) {
+      if (s.vp) s.vp[i] = -1;
+      if (s.vm) s.vm[i] = 0;
     }
   }
-  return acc;
+  // a primitive id outside [-1, n_prims) is a caller error: the path is NaN
+  if (s.prim0 < -1 || s.prim0 >= a.scene.n_prims) {
+    s.acc = (R)NAN;
+    return ST_DONE;
+  }
+  s.cur_idx = s.prim0 >= 0 ? a.scene.leaf_of_id[s.prim0] : -1;
+  s.x[0] = s.x0[0];
+  s.x[1] = s.x0[1];
+  s.x[2] = s.x0[2];
+  if (FORM == F_DL && s.cur_idx >= 0 && !a.density) {
+    // Table 1: on the boundary the Dirichlet solution is the given value
+    const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
+    const R nz[3] = {0, 0, 0};
+    s.acc = boundary_datum<R, D>(a.prog, g, nz, s.x);
+    return ST_DONE;
+  }
+  s.W = 1;
+  s.acc = 0;
+  s.i = 0;
+  return begin_step<R, D, FORM, TRACE, COUNT>(a, s, wc);
+}
+
+// One BVH node of the current line; returns false once the traversal ends.
+// Per hit: count it; with `select`, draw its key (Philox block 2, w = caller
+// id) and keep the smallest (key, id); for the direct BIE add G q / p_all to
+// the source sum.
+template <typename R, int D, int FORM, bool COUNT>
+__device__ __forceinline__ bool node_step(const WalkArgs<R, D>& a, PathState<R, D>& s, WorkCount& wc) {
+  const SceneView<R, D>& sc = a.scene;
+  const typename Rec<R, D>::Node node = sc.nodes[s.ni];
+  if (COUNT) wc.nodes += 1;
+  if (line_box<R, D>(node, s.inv, s.ox)) {
+    if (node.child >= 0) {
+      s.ni = node.child;
+      return true;
+    }
+    const int32_t code = -1 - node.child;
+    const int32_t first = code >> 3, count = (code & 7) + 1;
+    for (int32_t j = first; j < first + count; ++j) {
+      if (j == s.cur_idx) continue;
+      if (COUNT) wc.prims += 1;
+      const PrimGeo<R> g = load_prim<R, D>(sc, j);
+      R t, u, v;
+      if (!hit_prim<R, D>(g, s.x, s.d, t, u, v)) continue;
+      if (COUNT) wc.hits += 1;
+      s.h.m += 1;
+      if (s.select) {
+        const uint32_t key = philox(s.path, s.point, s.z | 2u, (uint32_t)g.id, a.k0, a.k1).x;
+        if (key < s.h.key || (key == s.h.key && g.id < s.h.id)) {
+          s.h.key = key;
+          s.h.id = g.id;
+          s.h.idx = j;
+          s.h.u = u;
+          s.h.v = v;
+          s.h.t = t;
+        }
+      }
+      if constexpr (FORM == F_DIRECT) {
+        R y[3], n[3];
+        hit_point(g, u, v, y);
+        load_normal<R, D>(sc, j, n);
+        R uu, grad[3];
+        program_eval<R, D>(a.prog, y, uu, grad);
+        const R q = dot3(n, grad);
+        // y - x = t d: distance and cosine from the line itself, free of the
+        // cancellation in y - x when the hit is close to x
+        const R rho = fabs(t);
+        const R ac = fabs(dot3(s.d, n));  // |cos theta_y|
+        // G q / p_all: 3D rho q / (2 |c|); 2D -rho ln(rho) q / (2 |c|)
+        const R gp = D == 3 ? rho / ((R)2 * ac) : -rho * log(rho) / ((R)2 * ac);
+        s.h.src += gp * q;
+      }
+    }
+  }
+  s.ni = node.skip;
+  return s.ni < sc.n_nodes;
+}
+
+template <typename R, int D, int FORM, bool TRACE, bool COUNT>
+__device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>& s, WorkCount& wc) {
+  const R phi = a.phi;
+  HitAcc<R>& h = s.h;
+  if (TRACE) {
+    if (s.vm) s.vm[s.i] = h.m;
+    if (s.vp) s.vp[s.i] = (s.select && h.m > 0) ? h.id : -1;
+  }
+  if constexpr (FORM == F_DIRECT) {
+    R S;
+    if (s.on_gamma) {
+      const U4 r1 = philox(s.path, s.point, s.z | 1u, 0u, a.k0, a.k1);
+      R ys[3];
+      const R gp = self_panel<R, D>(s.gc, s.nc, s.x, unit<R>(r1.x), unit<R>(r1.y), ys);
+      S = (R)2 * phi * (h.src + gp * boundary_datum<R, D>(a.prog, s.gc, s.nc, ys));
+    } else {
+      S = phi * h.src;
+    }
+    s.acc += s.W * S * (s.last ? (R)0.5 : (R)1);
+    if (s.last) return ST_DONE;
+  }
+  if (h.m == 0) return ST_DONE;
+  const PrimGeo<R> gy = load_prim<R, D>(a.scene, h.idx);
+  R y[3], w;
+  hit_point(gy, h.u, h.v, y);
+  // y - x = t d: the unit direction to the hit is sign(t) d and rho = |t|
+  const R sgn_t = h.t > (R)0 ? (R)1 : (R)-1;
+  const R mm = (R)h.m;
+  R ny[3] = {0, 0, 0};
+  if constexpr (FORM == F_DL || FORM == F_DIRECT) {
+    R nd[3];
+    normal_dir<R, D>(gy, nd);
+    const R sg = sgn_t * dot3(s.d, nd) > (R)0 ? (R)1 : (R)-1;  // sgn(cos theta_y)
+    if constexpr (FORM == F_DL)
+      w = (s.first && !s.on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
+    else
+      w = s.on_gamma ? phi * mm * sg : (R)0.5 * phi * mm * sg;
+  } else {
+    load_normal<R, D>(a.scene, h.idx, ny);
+    const R rho = fabs(h.t);
+    const R acy = fabs(dot3(s.d, ny));
+    if (s.first) {
+      // G / p
+      w = D == 3 ? mm * rho / ((R)2 * acy) : -mm * rho * log(rho) / ((R)2 * acy);
+    } else {
+      const R cx = sgn_t * dot3(s.d, s.nc);
+      w = D == 3 ? -phi * mm * (cx + s.gc.alpha * rho) / acy
+                 : -phi * mm * (cx - s.gc.alpha * rho * log(rho)) / acy;
+    }
+    if (s.mixture) w /= ((R)1 - a.self_p);
+  }
+  s.W *= w;
+  s.x[0] = y[0];
+  s.x[1] = y[1];
+  s.x[2] = y[2];
+  s.cur_idx = h.idx;
+  if constexpr (FORM != F_DIRECT) {
+    const R sv = boundary_datum<R, D>(a.prog, gy, ny, s.x);
+    s.acc += s.W * ((s.i + 1 < a.M) ? (R)2 * phi : phi) * sv;
+  }
+  ++s.i;
+  return begin_step<R, D, FORM, TRACE, COUNT>(a, s, wc);
 }
 
 
@@ -357,27 +474,61 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   const int lane_in_point = tid & (lpp - 1);
   double n = 0.0, mean = 0.0, m2 = 0.0;
   WorkCount wc = {0, 0, 0, 0};
-  if (point < a.n_points) {
-    R x0[3];
-    x0[0] = a.points[point * D + 0];
-    x0[1] = a.points[point * D + 1];
-    x0[2] = D == 3 ? a.points[point * D + 2] : (R)0;
-    const int32_t prim0 = a.point_prim ? a.point_prim[point] : -1;
-    for (int k = lane_in_point; k < a.N; k += lpp) {
-      const int64_t item = point * (int64_t)a.N + k;
-      int32_t* vp = (TRACE && a.vtx_prim) ? a.vtx_prim + item * a.L : nullptr;
-      int32_t* vm = (TRACE && a.vtx_m) ? a.vtx_m + item * a.L : nullptr;
+  if constexpr (CV && D == 3 && FORM == F_SL) {
+    if (point < a.n_points) {
+      R x0[3];
+      x0[0] = a.points[point * D + 0];
+      x0[1] = a.points[point * D + 1];
+      x0[2] = a.points[point * D + 2];
+      const int32_t prim0 = a.point_prim ? a.point_prim[point] : -1;
       const uint32_t pid = a.point_ids ? a.point_ids[point] : (uint32_t)point;
-      R v;
-      if constexpr (CV && D == 3 && FORM == F_SL)
-        v = run_path_cv<R, TRACE, COUNT>(a, pid, (uint32_t)k, x0, prim0, wc);
-      else
-        v = run_path<R, D, FORM, TRACE, COUNT>(a, pid, (uint32_t)k, x0, prim0, vp, vm, wc);
-      if (TRACE) a.path_out[item] = v;
-      n += 1.0;
-      const double dv = (double)v - mean;
-      mean += dv / n;
-      m2 += dv * ((double)v - mean);
+      for (int k = lane_in_point; k < a.N; k += lpp) {
+        const R v = run_path_cv<R, TRACE, COUNT>(a, pid, (uint32_t)k, x0, prim0, wc);
+        if (TRACE) a.path_out[point * (int64_t)a.N + k] = v;
+        n += 1.0;
+        const double dv = (double)v - mean;
+        mean += dv / n;
+        m2 += dv * ((double)v - mean);
+      }
+    }
+  } else {
+    // Paths k = lane_in_point, + lpp, ... of this lane, run as one state
+    // machine.  Lanes whose line has ended wait until a quarter of the
+    // wavefront's working lanes wait (or no lane traverses), then take their
+    // next step together, so the step logic runs on many lanes at once.
+    PathState<R, D> s;
+    int k = lane_in_point;
+    int st = ST_NONE;
+    if (point < a.n_points) {
+      s.x0[0] = a.points[point * D + 0];
+      s.x0[1] = a.points[point * D + 1];
+      s.x0[2] = D == 3 ? a.points[point * D + 2] : (R)0;
+      s.prim0 = a.point_prim ? a.point_prim[point] : -1;
+      s.point = a.point_ids ? a.point_ids[point] : (uint32_t)point;
+      if (k < a.N) st = start_path<R, D, FORM, TRACE, COUNT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc);
+    }
+    for (;;) {
+      // finished paths: record, start the lane's next one
+      while (st == ST_DONE) {
+        const R v = s.acc;
+        if (TRACE) a.path_out[point * (int64_t)a.N + k] = v;
+        n += 1.0;
+        const double dv = (double)v - mean;
+        mean += dv / n;
+        m2 += dv * ((double)v - mean);
+        k += lpp;
+        st = k < a.N ? start_path<R, D, FORM, TRACE, COUNT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc)
+                     : ST_NONE;
+      }
+      const int idle = __popcll(__ballot(st == ST_NONE));
+      if (idle == 64) break;
+      const int want = (64 - idle + 3) >> 2;  // lanes that must wait before the step logic runs
+      bool trav = st == ST_LINE;
+      while (trav) {
+        if (64 - idle - __popcll(__ballot(1)) >= want) break;
+        trav = node_step<R, D, FORM, COUNT>(a, s, wc);
+      }
+      if (st == ST_LINE && !trav) st = end_step<R, D, FORM, TRACE, COUNT>(a, s, wc);
     }
   }
   if (COUNT) {
