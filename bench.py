@@ -32,7 +32,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+# MI355X published fp32 vector peak (256 CUs at 2.4 GHz; counts an FMA as two
+# operations and includes packed math, which this build does not use, so one
+# half of it is the attainable issue rate)
+FP32_PEAK_TFLOPS = 157.3
+# algorithmic operations of the traversal: a node's slab test is 6 FMA (12),
+# 6 min / max, 2 three-way min / max (4) and one compare = 23; a tested
+# triangle (numerator form of Moller-Trumbore, a miss) is two cross products
+# (18), three dots (15), x - v0 (3), three sign products and four compares = 43
+NODE_FLOP, TRI_FLOP = 23, 43
 # algorithmic bytes: a node is its box (6 x 4 B) plus two links; a tested
 # triangle is v0, e1, e2 (9 x 4 B); a hit also reads id, kind and alpha (12 B)
 NODE_BYTES, TRI_BYTES, HIT_BYTES = 32, 36, 12
@@ -141,7 +149,9 @@ def cv_leg(torch, wob, I):
     """Equal wall time on the 1M points: plain WoB at 512 paths against the
     corrected estimator with (a) g = g0 = 0 (hit-selection Rao-Blackwellisation
     only), (b) g = 0, g0 = line-0 emission at the centroid, (c) the learned
-    network (fit included in its time) and (d) the same without the fit time."""
+    network (fit included in its time) and (d) the same without the fit time.
+    Every variant runs with 3 seeds and reports the RMSE pooled over them (the
+    single-layer weights are heavy-tailed, so one seed's RMSE is noisy)."""
     import math
     from paper_2305_04403_amd import cv as CV
     w = I.config_tori()
@@ -165,14 +175,27 @@ def cv_leg(torch, wob, I):
     warm.close()
     sync()
 
-    t0 = time.perf_counter()
-    mp, vp = wob.solve(scene, pts, bc, N, M, seed=1, point_prim=pp)
-    sync()
-    t_plain = time.perf_counter() - t0
-    rp, ep = score(mp)
+    seeds = (11, 12, 13)
+
+    def pooled(runs):
+        """RMSE pooled over seeds (mean of the per-seed squared errors), median error, time."""
+        mse = [np.mean((m.double().cpu().numpy() - ex) ** 2) for m, _ in runs]
+        med = [np.median(np.abs(m.double().cpu().numpy() - ex)) for m, _ in runs]
+        return (math.sqrt(float(np.mean(mse))), float(np.mean(med)),
+                [math.sqrt(float(v)) for v in mse], float(np.mean([v.double().mean().item() for _, v in runs])))
+
+    runs, times = [], []
+    for sd in seeds:
+        t0 = time.perf_counter()
+        runs.append(wob.solve(scene, pts, bc, N, M, seed=sd, point_prim=pp))
+        sync()
+        times.append(time.perf_counter() - t0)
+    t_plain = float(np.mean(times))
+    rp, ep, per_seed, mv = pooled(runs)
     out = {"workload": w.name + ", 1M points (10% on the boundary), M=4",
-           "plain": {"paths": N, "seconds": t_plain, "rmse": rp, "median_abs_err": ep,
-                     "mean_var": float(vp.double().mean())}}
+           "seeds": len(seeds),
+           "plain": {"paths": N, "seconds": t_plain, "rmse": rp, "rmse_per_seed": per_seed,
+                     "median_abs_err": ep, "mean_var": mv}}
 
     lcv = CV.LearnedControlVariate(scene, bc, M, CV.CVConfig(epochs=1, target_paths=4))
     fit = lcv.fit()
@@ -185,20 +208,28 @@ def cv_leg(torch, wob, I):
     wob.cv_addback(scene, lcv.g0, pts)
     sync()
     t_add = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    wob.solve_cv(scene, pts, bc, 64, M, lcv.g, seed=2, point_prim=pp, g0=lcv.g0)
-    sync()
-    per_path = max(time.perf_counter() - t0 - t_add, 1e-9) / 64
-
-    def run(name, g, g0, fixed_s, seed):
-        n = int(max(16, (t_plain - fixed_s - t_add) / per_path // 16 * 16))
+    # cost per corrected path: slope between 64 and 128 paths (fixed costs cancel)
+    tt = []
+    for n_probe in (64, 128):
         t0 = time.perf_counter()
-        m, v = wob.solve_cv(scene, pts, bc, n, M, g, seed=seed, point_prim=pp, g0=g0)
+        wob.solve_cv(scene, pts, bc, n_probe, M, lcv.g, seed=2, point_prim=pp, g0=lcv.g0)
         sync()
-        t = time.perf_counter() - t0
-        r, e = score(m)
-        out[name] = {"paths": n, "seconds": fixed_s + t, "solve_s": t, "rmse": r, "median_abs_err": e,
-                     "mean_var": float(v.double().mean()), "rmse_ratio": rp / r, "median_err_ratio": ep / e}
+        tt.append(time.perf_counter() - t0)
+    per_path = max((tt[1] - tt[0]) / 64, 1e-9)
+    base = max(tt[0] - 64 * per_path, 0.0)   # add-back and launch overheads
+
+    def run(name, g, g0, fixed_s, seed0):
+        n = int(max(16, (t_plain - fixed_s - base) / per_path // 16 * 16))
+        rr, tm = [], []
+        for j, sd in enumerate(seeds):
+            t0 = time.perf_counter()
+            rr.append(wob.solve_cv(scene, pts, bc, n, M, g, seed=sd + 100 * seed0, point_prim=pp, g0=g0))
+            sync()
+            tm.append(time.perf_counter() - t0)
+        r, e, ps, v = pooled(rr)
+        t = float(np.mean(tm))
+        out[name] = {"paths": n, "seconds": fixed_s + t, "solve_s": t, "rmse": r, "rmse_per_seed": ps,
+                     "median_abs_err": e, "mean_var": v, "rmse_ratio": rp / r, "median_err_ratio": ep / e}
 
     run("rb_only", zero, zero, 0.0, 3)
     run("emission_table", zero, e0, t_e0, 4)
@@ -207,6 +238,7 @@ def cv_leg(torch, wob, I):
                            "train_steps": fit["train_steps"]})
     run("learned_inference_only", lcv.g, lcv.g0, 0.0, 6)
     out["addback_s"] = t_add
+    out["corrected_path_cost_vs_plain"] = per_path / (t_plain / N)
     out["rmse_ratio_equal_time"] = out["learned"]["rmse_ratio"]
     out["median_err_ratio_equal_time"] = out["learned"]["median_err_ratio"]
     lcv.close()
@@ -264,7 +296,8 @@ def main():
     value = paths * args.steps / wall
     lines = cnt["lines"]
     alg_bytes = cnt["nodes"] * NODE_BYTES + cnt["prims"] * TRI_BYTES + cnt["hits"] * HIT_BYTES
-    achieved = alg_bytes / avg_kern_s / 1e9
+    alg_flop = cnt["nodes"] * NODE_FLOP + cnt["prims"] * TRI_FLOP
+    achieved = alg_flop / avg_kern_s / 1e12
     m = mean.double().cpu().numpy()
     se = np.sqrt(var.double().cpu().numpy() / N)
     rmse = float(np.sqrt(np.mean((m - w.exact) ** 2)))
@@ -289,9 +322,11 @@ def main():
         "work_per_line": {"nodes": cnt["nodes"] / lines, "triangles": cnt["prims"] / lines,
                           "hits": cnt["hits"] / lines},
         "kernel_ms": float(np.mean(kern_ms)),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic()},
-        "algorithmic_bytes_per_launch": alg_bytes,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic()},
+        "algorithmic_flop_per_launch": alg_flop,
+        "gather": {"bytes_per_launch": alg_bytes, "GB/s": alg_bytes / avg_kern_s / 1e9,
+                   "note": "node, triangle and hit records the traversal reads; served by L2 (scene 2.2 MB)"},
         "rmse_vs_analytic": rmse,
         "mean_se": float(np.mean(se)),
         "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")},

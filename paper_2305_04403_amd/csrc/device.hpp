@@ -413,11 +413,10 @@ template <typename R> __device__ __forceinline__ R safe_inv(R d) {
 
 // Calls leaf(first, count) for every leaf whose box the line crosses, in the
 // BVH's pre-order, with a stackless walk over the skip links: a crossed inner
-// node continues at its first child, anything else at its skip link.  One loop
-// handles inner nodes and leaves; variants that split them (separate loops,
-// speculative node steps) measured slower on gfx950 here, because the extra
-// live state cost a wavefront per SIMD while saving under a tenth of the
-// vector instructions.
+// node continues at its first child, anything else at its skip link.  One
+// loop, one line per thread (the hit-list query); the path kernel steps
+// through the same nodes in its own loop, where lanes park at crossed leaves
+// and test them together.
 template <typename R, int D, bool COUNT, typename Leaf>
 __device__ __forceinline__ void for_each_leaf(const SceneView<R, D>& s, const R inv[3], const R ox[3],
                                               WorkCount& wc, Leaf&& leaf) {
@@ -436,67 +435,6 @@ __device__ __forceinline__ void for_each_leaf(const SceneView<R, D>& s, const R 
     }
     i = node.skip;
   }
-}
-
-// Visit every hit of the line through x with direction d, skipping primitive
-// `exclude` (leaf-order index).  Per hit: count it; with `select`, draw its
-// key (Philox block 2, w = caller id) and keep the smallest (key, id); with
-// `source`, add G q / p_all for the direct BIE's source integral.
-template <typename R, int D, bool COUNT>
-__device__ __forceinline__ void trace_line(const SceneView<R, D>& s, const ProgramView<R>& prog,
-                                           const R x[3], const R d[3], int32_t exclude, bool select,
-                                           bool source, uint32_t kc0, uint32_t kc1, uint32_t kc2,
-                                           uint32_t k0, uint32_t k1, HitAcc<R>& h, WorkCount& wc) {
-  R inv[3], ox[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    inv[a] = safe_inv(d[a]);
-    ox[a] = -x[a] * inv[a];
-  }
-  h.m = 0;
-  h.key = 0xffffffffu;
-  h.id = 0x7fffffff;
-  h.idx = -1;
-  h.u = h.v = h.t = 0;
-  h.src = 0;
-  if (COUNT) wc.lines += 1;
-  for_each_leaf<R, D, COUNT>(s, inv, ox, wc, [&](int32_t first, int32_t count) {
-    for (int32_t j = first; j < first + count; ++j) {
-      if (j == exclude) continue;
-      if (COUNT) wc.prims += 1;
-      const PrimGeo<R> g = load_prim<R, D>(s, j);
-      R t, u, v;
-      if (!hit_prim<R, D>(g, x, d, t, u, v)) continue;
-      if (COUNT) wc.hits += 1;
-      h.m += 1;
-      if (select) {
-        const uint32_t key = philox(kc0, kc1, kc2, (uint32_t)g.id, k0, k1).x;
-        if (key < h.key || (key == h.key && g.id < h.id)) {
-          h.key = key;
-          h.id = g.id;
-          h.idx = j;
-          h.u = u;
-          h.v = v;
-          h.t = t;
-        }
-      }
-      if (source) {
-        R y[3], n[3];
-        hit_point(g, u, v, y);
-        load_normal<R, D>(s, j, n);
-        R uu, grad[3];
-        program_eval<R, D>(prog, y, uu, grad);
-        const R q = dot3(n, grad);
-        // y - x = t d: distance and cosine from the line itself, free of the
-        // cancellation in y - x when the hit is close to x
-        const R rho = fabs(t);
-        const R ac = fabs(dot3(d, n));  // |cos theta_y|
-        // G q / p_all: 3D rho q / (2 |c|); 2D -rho ln(rho) q / (2 |c|)
-        const R gp = D == 3 ? rho / ((R)2 * ac) : -rho * log(rho) / ((R)2 * ac);
-        h.src += gp * q;
-      }
-    }
-  });
 }
 
 }  // namespace wob
