@@ -366,11 +366,12 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   {
     // Paths k = lane_in_point, + lpp, ... of this lane, run as one state
     // machine.  Lanes step through BVH nodes; a lane that reaches a crossed
-    // leaf, or the end of its line, waits until most of the wavefront's
-    // working lanes wait (or no lane steps), and then the waiting lanes test
-    // their leaves and take their path steps together, so that code runs on
-    // many lanes at once instead of on the one or two lanes that stand at a
-    // leaf in a given node step.
+    // leaf parks until most of the stepping lanes have parked, and the parked
+    // lanes then test their leaves together; a lane at the end of its line
+    // parks until a quarter of the working lanes have, and those lanes then
+    // take their path steps together.  That code thus runs on many lanes at
+    // once instead of on the one or two lanes that stand at a leaf or a line
+    // end in a given node step.
     PathState<R, D> s;
     int k = lane_in_point;
     int st = ST_NONE;
@@ -398,16 +399,18 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       }
       const int idle = __popcll(__ballot(st == ST_NONE));
       if (idle == 64) break;
-      // lanes that must wait before leaves and steps run: 5/8 of the working
-      // lanes (measured on the icosphere benchmark, 1/16 .. 16/16: 236, 286,
-      // 352, 393, 395, 388, 352, 244 M path samples/s at 1/16, 1/8, 1/4, 1/2,
-      // 5/8, 3/4, 7/8, 1)
-      const int want = ((64 - idle) * 5 + 7) >> 3;
-      // node steps: a lane stops at a crossed leaf (kept in `pend`) or at the
-      // end of its line
-      bool trav = st == ST_LINE && pend < 0 && s.ni < a.scene.n_nodes;
+      const int nn = a.scene.n_nodes;
+      // lanes parked at the end of their line, and lanes that step through nodes
+      const int ends = __popcll(__ballot(st == ST_LINE && pend < 0 && s.ni >= nn));
+      const int active = 64 - idle - ends;
+      // node steps until 5/8 of the stepping lanes stand at a crossed leaf
+      // (measured on the icosphere benchmark, 1/16 .. 16/16 of the lanes:
+      // 236, 286, 352, 393, 395, 388, 352, 244 M path samples/s at 1/16, 1/8,
+      // 1/4, 1/2, 5/8, 3/4, 7/8, 1)
+      const int want = (active * 5 + 7) >> 3;
+      bool trav = st == ST_LINE && pend < 0 && s.ni < nn;
       while (trav) {
-        if (64 - idle - __popcll(__ballot(1)) >= want) break;
+        if (active - __popcll(__ballot(1)) >= want) break;
         const typename Rec<R, D>::Node node = a.scene.nodes[s.ni];
         if (COUNT) wc.nodes += 1;
         const bool crossed = line_box<R, D>(node, s.inv, s.ox);
@@ -419,17 +422,24 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         if (crossed) {
           pend = -1 - node.child;
           trav = false;
-        } else if (s.ni >= a.scene.n_nodes) {
+        } else if (s.ni >= nn) {
           trav = false;
         }
       }
-      // the stopped lanes test their leaves together, then finish their lines
+      // the parked lanes test their leaves together
       if (pend >= 0) {
         leaf_work<R, D, FORM, COUNT, KCV>(a, s, pend, wc);
         pend = -1;
       }
-      if (st == ST_LINE && pend < 0 && s.ni >= a.scene.n_nodes)
-        st = end_step<R, D, FORM, TRACE, COUNT, KCV>(a, s, wc);
+      // path steps run once a quarter of the working lanes stand at the end of
+      // their line, or when no lane steps (measured: 396, 402, 404, 403, 400 M
+      // path samples/s for 0, 1/8, 1/4, 3/8, 1/2)
+      const bool at_end = st == ST_LINE && s.ni >= nn;
+      const int n_end = __popcll(__ballot(at_end));
+      const int stepping = __popcll(__ballot(st == ST_LINE && s.ni < nn));
+      if (4 * n_end >= 64 - idle || stepping == 0) {
+        if (at_end) st = end_step<R, D, FORM, TRACE, COUNT, KCV>(a, s, wc);
+      }
     }
   }
   if (COUNT) {
