@@ -160,6 +160,17 @@ def test_trace_parity_interior_single_layer_2d_f64(W):
     run_trace_parity(W, mesh, pts, pp, bc, 64, 3, 2, "f64")
 
 
+@pytest.mark.parametrize("N", [1, 3, 5, 7, 130])
+def test_trace_parity_paths_not_a_multiple_of_lanes(W, N):
+    """A lane runs several paths back to back and a wavefront may hold several
+    points: path counts that leave lanes partly used, and a point count that
+    leaves the last workgroup ragged, against the oracle path by path."""
+    mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(6), 0.1, 2, 3))
+    pts = PT.f32(I.ball_points(13, 0.8, 21))
+    bc = dict(domain=1, formulation=1, program=3, params=(2.0, 0.5, 0.0))
+    run_trace_parity(W, mesh, pts, None, bc, N, 3, 17, "f32", max_vertex_mismatch_frac=0.002)
+
+
 # ------------------------------------------------------------------- solve
 
 def test_solve_mean_var_equal_trace_statistics(W):
@@ -179,13 +190,16 @@ def test_solve_mean_var_equal_trace_statistics(W):
     scene.close()
 
 
-def test_solve_matches_oracle_mean(W):
-    w = I.config_circle(n_points=128, samples=256)
+@pytest.mark.parametrize("N", [256, 37, 2])
+def test_solve_matches_oracle_mean(W, N):
+    """FP64 per-point mean and variance against the oracle's two-pass values,
+    including path counts that leave lanes partly used."""
+    w = I.config_circle(n_points=129, samples=N)
     scene = W.Scene(w.mesh, W.F64)
-    mean, var = W.solve(scene, dev(w.points, torch.float64), wbc(W, w.bc), 256, 4, 0)
+    mean, var = W.solve(scene, dev(w.points, torch.float64), wbc(W, w.bc), N, 4, 0)
     torch.cuda.synchronize()
     om = oracle.OracleMesh(w.mesh)
-    m_o, v_o = oracle.solve(om, w.points, None, obc(w.bc), 256, 4, 0)
+    m_o, v_o = oracle.solve(om, w.points, None, obc(w.bc), N, 4, 0)
     np.testing.assert_allclose(mean.cpu().numpy(), m_o, rtol=0, atol=1e-11)
     np.testing.assert_allclose(var.cpu().numpy(), v_o, rtol=1e-9, atol=1e-11)
     scene.close()
