@@ -29,7 +29,7 @@ class _Mesh(C.Structure):
 class _BC(C.Structure):
     _fields_ = [("domain", C.c_int), ("formulation", C.c_int), ("program", C.c_int),
                 ("params", C.c_double * 8), ("self_threshold", C.c_uint32), ("self_p", C.c_double),
-                ("density", C.c_int)]
+                ("density", C.c_int), ("sampling", C.c_int), ("candidates", C.c_int)]
 
 
 class _TraceOut(C.Structure):
@@ -124,10 +124,16 @@ def self_threshold(p: float) -> int:
     return int(np.floor(p * 2.0 ** 24))
 
 
+SAMPLE_LINE, SAMPLE_RIS = 0, 1
+
+
 def make_bc(domain: int = 1, formulation: int = AUTO, program: int = PROG_CONST,
-            params=(), self_p: float = 1.0 / 16.0, density: bool = False) -> _BC:
+            params=(), self_p: float = 1.0 / 16.0, density: bool = False, sampling: int = SAMPLE_LINE,
+            candidates: int = 16) -> _BC:
     b = _BC()
     b.density = int(bool(density))
+    b.sampling = int(sampling)
+    b.candidates = int(candidates)
     b.domain = int(domain)
     b.formulation = int(formulation)
     b.program = int(program)

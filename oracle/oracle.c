@@ -414,16 +414,72 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Area-uniform boundary points for resampled importance sampling.            */
+/* The primitive is the first id whose cumulative area fraction exceeds a     */
+/* uniform u; the fractions are summed in binary64 in id order and rounded    */
+/* once to binary32, and u is a binary32 value, so the choice of primitive is */
+/* an exact decision.  The point is v0 + a e1 + b e2 with (a, b) uniform on   */
+/* the unit square and reflected into the triangle when a + b > 1.            */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  float* cdf;   /* n_prims */
+  double total; /* |Gamma| */
+} area_table;
+
+static double prim_area(const orc_mesh* m, int64_t j) {
+  double v0[3], v1[3], v2[3] = {0.0, 0.0, 0.0};
+  prim_vertex(m, j, 0, v0);
+  prim_vertex(m, j, 1, v1);
+  if (m->dim == 2) {
+    double e[2] = {v1[0] - v0[0], v1[1] - v0[1]};
+    return sqrt(e[0] * e[0] + e[1] * e[1]);
+  }
+  prim_vertex(m, j, 2, v2);
+  double e1[3], e2[3], n[3];
+  for (int a = 0; a < 3; ++a) {
+    e1[a] = v1[a] - v0[a];
+    e2[a] = v2[a] - v0[a];
+  }
+  cross3(e1, e2, n);
+  return 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+}
+
+static area_table make_area_table(const orc_mesh* m) {
+  area_table t;
+  t.cdf = (float*)malloc(sizeof(float) * (size_t)m->n_prims);
+  double tot = 0.0;
+  for (int64_t j = 0; j < m->n_prims; ++j) tot += prim_area(m, j);
+  double run = 0.0;
+  for (int64_t j = 0; j < m->n_prims; ++j) {
+    run += prim_area(m, j);
+    t.cdf[j] = (float)(run / tot);
+  }
+  t.cdf[m->n_prims - 1] = 1.0f;
+  t.total = tot;
+  return t;
+}
+
+static int64_t area_pick(const area_table* t, int64_t n, float u) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (t->cdf[mid] > u) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+/* ------------------------------------------------------------------------- */
 /* One path (point p, path k).                                                */
 /* ------------------------------------------------------------------------- */
 typedef struct {
   double value, abs_sum, graze, cond_cos;
 } path_result;
 
-static path_result one_path(const orc_mesh* m, const double* normals, const orc_bc* bc,
-                            int form, const double* x0, int64_t prim0, int M, uint64_t seed,
-                            uint32_t problem, uint32_t point, uint32_t path, int32_t* vprim,
-                            int32_t* vm, double* vpos) {
+static path_result one_path(const orc_mesh* m, const double* normals, const area_table* at,
+                            const orc_bc* bc, int form, const double* x0, int64_t prim0, int M,
+                            uint64_t seed, uint32_t problem, uint32_t point, uint32_t path,
+                            int32_t* vprim, int32_t* vm, double* vpos) {
   const int dim = m->dim;
   const double phi = (double)bc->domain;
   const int L = form == ORC_DIRECT ? M + 1 : M;
@@ -466,12 +522,78 @@ static path_result one_path(const orc_mesh* m, const double* normals, const orc_
       d[1] = sin(th);
     }
 
-    /* single layer: where G acts on the own primitive (the first step from a
-       boundary point, and the alpha G part at Robin vertices) mix the line
-       sample with an in-plane self-panel sample */
     /* step 0 from an evaluation point uses the representation formula; in
        density mode x0 is itself a boundary vertex of the recursion */
     const int first = i == 0 && !bc->density;
+
+    if (form == ORC_SINGLE_LAYER && bc->sampling == ORC_SAMPLE_RIS) {
+      /* Resampled importance sampling (Results: Robin and mixed problems use
+         area-uniform candidates and resample them by the integral kernel).
+         The kernel k(y) is G(x, y) on the first step and
+         -2 phi (dG/dn_x + alpha G) on the recursion; target |k|.  Candidate j
+         draws Philox block 3 with w = j: word 0 picks the primitive, words 1, 2
+         the point, word 3 the resampling uniform u_j; a weighted reservoir
+         keeps candidate j when u_j S_j < |k_j| (S_j the running sum of |k|),
+         so the kept one has probability |k_j| / S.  Weight
+         k(y) / |k(y)| * S |Gamma| / C, the RIS estimate of int k(y) (.) dy. */
+      const int C = bc->candidates;
+      double S = 0.0, kpick = 0.0, ypick[3] = {0.0, 0.0, 0.0};
+      int64_t jpick = -1;
+      const double* nx = on_gamma ? normals + 3 * cur : NULL;
+      const double ax = on_gamma ? prim_alpha(m, cur) : 0.0;
+      for (int j = 0; j < C; ++j) {
+        uint32_t rj[4];
+        draw(seed, path, point, problem, (uint32_t)i, 3u, (uint32_t)j, rj);
+        const int64_t pj = area_pick(at, m->n_prims, (float)uniform(rj[0]));
+        double a = uniform(rj[1]), b = dim == 3 ? uniform(rj[2]) : 0.0;
+        if (a + b > 1.0) {
+          a = 1.0 - a;
+          b = 1.0 - b;
+        }
+        double v0[3], v1[3], v2[3] = {0.0, 0.0, 0.0}, yc[3] = {0.0, 0.0, 0.0};
+        prim_vertex(m, pj, 0, v0);
+        prim_vertex(m, pj, 1, v1);
+        if (dim == 3) prim_vertex(m, pj, 2, v2);
+        for (int c = 0; c < dim; ++c) yc[c] = v0[c] + a * (v1[c] - v0[c]) + b * (v2[c] - v0[c]);
+        double r[3] = {yc[0] - x[0], yc[1] - x[1], dim == 3 ? yc[2] - x[2] : 0.0};
+        double k = 0.0;
+        if (dot(r, r, dim) > 0.0) {
+          if (first) k = G(x, yc, dim);
+          else k = -2.0 * phi * (dG_dnx(x, yc, nx, dim) + ax * G(x, yc, dim));
+        }
+        const double pk = fabs(k);
+        S += pk;
+        const double u = uniform(rj[3]);
+        if (S > 0.0) {
+          double margin = fabs(u * S - pk) / S; /* distance of the keep decision from its threshold */
+          if (margin < res.graze) res.graze = margin;
+        }
+        if (u * S < pk) {
+          jpick = pj;
+          kpick = k;
+          memcpy(ypick, yc, sizeof(ypick));
+        }
+      }
+      if (vm) vm[i] = 0;
+      if (jpick < 0 || !(S > 0.0)) break; /* no candidate carries kernel mass */
+      if (vprim) vprim[i] = (int32_t)jpick;
+      const double w = (kpick > 0.0 ? 1.0 : -1.0) * S * at->total / (double)C;
+      W *= w;
+      Wabs *= fabs(w);
+      memcpy(x, ypick, sizeof(x));
+      cur = jpick;
+      if (vpos)
+        for (int a = 0; a < dim; ++a) vpos[i * dim + a] = x[a];
+      double s = orc_boundary_datum(m, bc, cur, x);
+      double e = (i + 1 < M ? 2.0 : 1.0) * phi * s;
+      acc += W * e;
+      abs_sum += Wabs * fabs(e);
+      continue;
+    }
+
+    /* single layer: where G acts on the own primitive (the first step from a
+       boundary point, and the alpha G part at Robin vertices) mix the line
+       sample with an in-plane self-panel sample */
     int mixture = form == ORC_SINGLE_LAYER && on_gamma &&
                   (first || prim_kind(m, cur) == ORC_ROBIN);
     int use_self = mixture && (r0[2] >> 8) < bc->self_threshold;
@@ -595,6 +717,11 @@ static int check_args(const orc_mesh* m, const orc_bc* bc, int walk_len) {
   if (bc->domain != 1 && bc->domain != -1) return 1;
   if (orc_resolve_formulation(m, bc->formulation) < 0) return 1;
   if (bc->density && orc_resolve_formulation(m, bc->formulation) == ORC_DIRECT) return 1;
+  if (bc->sampling != ORC_SAMPLE_LINE && bc->sampling != ORC_SAMPLE_RIS) return 1;
+  if (bc->sampling == ORC_SAMPLE_RIS &&
+      (orc_resolve_formulation(m, bc->formulation) != ORC_SINGLE_LAYER || bc->candidates < 1 ||
+       bc->candidates > 64))
+    return 1;
   return 0;
 }
 
@@ -606,6 +733,7 @@ int orc_trace(const orc_mesh* m, const double* points, const int32_t* point_prim
   const int form = orc_resolve_formulation(m, bc->formulation);
   const int L = form == ORC_DIRECT ? walk_len + 1 : walk_len;
   double* normals = make_normals(m);
+  area_table at = make_area_table(m);
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -616,7 +744,7 @@ int orc_trace(const orc_mesh* m, const double* points, const int32_t* point_prim
     double x0[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
     int64_t prim0 = point_prim ? point_prim[p] : -1;
-    path_result r = one_path(m, normals, bc, form, x0, prim0, walk_len, seed, problem,
+    path_result r = one_path(m, normals, &at, bc, form, x0, prim0, walk_len, seed, problem,
                              (uint32_t)p, (uint32_t)item_path[it],
                              out->vtx_prim ? out->vtx_prim + it * L : NULL,
                              out->vtx_m ? out->vtx_m + it * L : NULL,
@@ -627,6 +755,7 @@ int orc_trace(const orc_mesh* m, const double* points, const int32_t* point_prim
     if (out->cond_cos) out->cond_cos[it] = r.cond_cos;
   }
   free(normals);
+  free(at.cdf);
   return 0;
 }
 
@@ -636,6 +765,7 @@ int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim
   if (check_args(m, bc, walk_len) || samples < 1) return 1;
   const int form = orc_resolve_formulation(m, bc->formulation);
   double* normals = make_normals(m);
+  area_table at = make_area_table(m);
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -647,7 +777,7 @@ int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim
     double* v = (double*)malloc(sizeof(double) * (size_t)samples);
     double sum = 0.0;
     for (int k = 0; k < samples; ++k) {
-      v[k] = one_path(m, normals, bc, form, x0, prim0, walk_len, seed, problem, (uint32_t)p,
+      v[k] = one_path(m, normals, &at, bc, form, x0, prim0, walk_len, seed, problem, (uint32_t)p,
                       (uint32_t)k, NULL, NULL, NULL)
                  .value;
       sum += v[k];
@@ -660,6 +790,7 @@ int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim
     free(v);
   }
   free(normals);
+  free(at.cdf);
   return 0;
 }
 

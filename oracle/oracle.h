@@ -60,7 +60,13 @@ typedef struct {
   double self_p;           /* the same probability as a real number, floor(p_s*2^24)/2^24 */
   int density;             /* 1: estimate the boundary unknown (nu or mu) without its own
                               emission, at points on the boundary (double / single layer) */
+  int sampling;            /* single layer: ORC_SAMPLE_LINE (line sampling of Sec. 4.4.1 with
+                              the self-panel mixture) or ORC_SAMPLE_RIS (resampled importance
+                              sampling over area-uniform candidates, Results) */
+  int candidates;          /* RIS candidates per vertex, 1..64 */
 } orc_bc;
+
+enum { ORC_SAMPLE_LINE = 0, ORC_SAMPLE_RIS = 1 };
 
 /* Per (point, path) record produced by orc_trace. Arrays may be NULL. */
 typedef struct {

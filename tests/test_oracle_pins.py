@@ -268,12 +268,14 @@ def _sphere_problem(kind, alpha, freq=6):
     return I.Mesh(3, s.verts, s.prims, np.full(n, kind, np.uint8), np.full(n, float(alpha)))
 
 
-@pytest.mark.parametrize("name,kind,alpha,form,M", [
-    ("single-layer Neumann", 1, 0.0, oracle.SINGLE_LAYER, 3),
-    ("direct Neumann", 1, 0.0, oracle.DIRECT, 3),
-    ("single-layer Robin", 2, 0.5, oracle.SINGLE_LAYER, 3),
+@pytest.mark.parametrize("name,kind,alpha,form,M,sampling", [
+    ("single-layer Neumann", 1, 0.0, oracle.SINGLE_LAYER, 3, oracle.SAMPLE_LINE),
+    ("direct Neumann", 1, 0.0, oracle.DIRECT, 3, oracle.SAMPLE_LINE),
+    ("single-layer Robin", 2, 0.5, oracle.SINGLE_LAYER, 3, oracle.SAMPLE_LINE),
+    ("single-layer Neumann, RIS", 1, 0.0, oracle.SINGLE_LAYER, 3, oracle.SAMPLE_RIS),
+    ("single-layer Robin, RIS", 2, 0.5, oracle.SINGLE_LAYER, 3, oracle.SAMPLE_RIS),
 ])
-def test_exterior_sphere_monopole(name, kind, alpha, form, M):
+def test_exterior_sphere_monopole(name, kind, alpha, form, M, sampling):
     """Exterior problems on a sphere with the monopole u = 1/|x| (Neumann or Robin
     data derived from it with each triangle's normal).  The l = 0 recursion
     eigenvalue is -1 (single-layer and direct Neumann) or 2 alpha R - 1 = 0
@@ -282,7 +284,7 @@ def test_exterior_sphere_monopole(name, kind, alpha, form, M):
     mesh = _sphere_problem(kind, alpha)
     om = oracle.OracleMesh(mesh)
     pts = I.ball_points(24, 2.5, 3, r_min=1.5)
-    bc = oracle.make_bc(-1, form, oracle.PROG_INVDIST, (0.0, 0.0, 0.0))
+    bc = oracle.make_bc(-1, form, oracle.PROG_INVDIST, (0.0, 0.0, 0.0), sampling=sampling)
     N = 3000
     mean, var = oracle.solve(om, pts, None, bc, N, M, 5)
     exact = 1.0 / np.linalg.norm(pts, axis=1)
@@ -292,13 +294,15 @@ def test_exterior_sphere_monopole(name, kind, alpha, form, M):
     assert abs(est - 1.0) < 4 * se + 0.01, (name, est, se)
 
 
-def test_robin_first_step_is_half():
+@pytest.mark.parametrize("sampling", [oracle.SAMPLE_LINE, oracle.SAMPLE_RIS])
+def test_robin_first_step_is_half(sampling):
     """Robin, alpha R = 1/2: lambda_0 = 0, so the one-line estimator returns exactly
-    half of the l = 0 solution (tau_1(0) = 1/2)."""
+    half of the l = 0 solution (tau_1(0) = 1/2), with either sampling of the
+    single-layer integrals."""
     mesh = _sphere_problem(2, 0.5)
     om = oracle.OracleMesh(mesh)
     pts = I.ball_points(24, 2.5, 3, r_min=1.5)
-    bc = oracle.make_bc(-1, oracle.SINGLE_LAYER, oracle.PROG_INVDIST, (0.0, 0.0, 0.0))
+    bc = oracle.make_bc(-1, oracle.SINGLE_LAYER, oracle.PROG_INVDIST, (0.0, 0.0, 0.0), sampling=sampling)
     N = 2000
     mean, var = oracle.solve(om, pts, None, bc, N, 1, 5)
     exact = 1.0 / np.linalg.norm(pts, axis=1)
@@ -306,19 +310,20 @@ def test_robin_first_step_is_half():
     assert ratio == pytest.approx(0.5, abs=0.03)
 
 
-@pytest.mark.parametrize("name,kind,alpha,form", [
-    ("single-layer Neumann", 1, 0.0, oracle.SINGLE_LAYER),
-    ("direct Neumann", 1, 0.0, oracle.DIRECT),
-    ("single-layer Robin", 2, 0.5, oracle.SINGLE_LAYER),
+@pytest.mark.parametrize("name,kind,alpha,form,sampling", [
+    ("single-layer Neumann", 1, 0.0, oracle.SINGLE_LAYER, oracle.SAMPLE_LINE),
+    ("direct Neumann", 1, 0.0, oracle.DIRECT, oracle.SAMPLE_LINE),
+    ("single-layer Robin", 2, 0.5, oracle.SINGLE_LAYER, oracle.SAMPLE_LINE),
+    ("single-layer Robin, RIS", 2, 0.5, oracle.SINGLE_LAYER, oracle.SAMPLE_RIS),
 ])
-def test_solution_on_the_boundary(name, kind, alpha, form):
+def test_solution_on_the_boundary(name, kind, alpha, form, sampling):
     """Estimates exactly on the boundary (Table 1 "boundary" rows, with the
     self-panel term for the part of G on the own triangle): u = 1 on the unit
     sphere for the exterior monopole."""
     mesh = _sphere_problem(kind, alpha)
     om = oracle.OracleMesh(mesh)
     pts, prim = I.mesh_surface_points(mesh, 24, 8)
-    bc = oracle.make_bc(-1, form, oracle.PROG_INVDIST, (0.0, 0.0, 0.0))
+    bc = oracle.make_bc(-1, form, oracle.PROG_INVDIST, (0.0, 0.0, 0.0), sampling=sampling)
     N = 3000
     mean, var = oracle.solve(om, pts, prim, bc, N, 4, 2)
     exact = 1.0 / np.linalg.norm(pts, axis=1)
@@ -378,3 +383,40 @@ def test_selection_is_uniform_over_hits():
     expected = len(ranks) / 4
     chi2 = np.sum((counts - expected) ** 2 / expected)
     assert chi2 < 16.3  # 99.9% quantile of chi^2 with 3 degrees of freedom
+
+
+def test_ris_candidates_are_area_uniform():
+    """With one candidate the reservoir always keeps it, so a one-vertex RIS path
+    lands on primitives in proportion to their area: sampled counts against the
+    area fractions (chi-square) on a mesh with very uneven triangles."""
+    s = I.perturb_radial(I.icosphere(3), 0.3, 2, 3)
+    mesh = I.Mesh(3, s.verts, s.prims, np.full(s.n_prims, 1, np.uint8), None)
+    om = oracle.OracleMesh(mesh)
+    # a boundary point and a single step: the pick is the first vertex x_1
+    pts, prim = I.mesh_surface_points(mesh, 1, 4)
+    bc = oracle.make_bc(-1, oracle.SINGLE_LAYER, oracle.PROG_CONST, (1.0,), sampling=oracle.SAMPLE_RIS,
+                        candidates=1)
+    n = 40000
+    tr = oracle.trace(om, pts, prim, bc, 1, 9, np.zeros(n, np.int64), np.arange(n), want_pos=False)
+    picked = tr["vtx_prim"][:, 0]
+    v = mesh.verts[mesh.prims]
+    area = 0.5 * np.linalg.norm(np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]), axis=1)
+    expect = n * area / area.sum()
+    counts = np.bincount(picked, minlength=mesh.n_prims)
+    chi2 = np.sum((counts - expect) ** 2 / expect)
+    dof = mesh.n_prims - 1
+    assert abs(chi2 - dof) < 5 * np.sqrt(2 * dof), (chi2, dof)
+
+
+def test_ris_and_line_sampling_agree_on_the_tori():
+    """Both samplings estimate the same truncated series: on the tori union
+    (Neumann / Robin, points off and on the boundary) their means agree within
+    the combined standard error."""
+    w = I.config_tori(grid_n=14, n_points=30, boundary_frac=0.3, samples=8, walk_len=3)
+    om = oracle.OracleMesh(w.mesh)
+    b = {k: w.bc[k] for k in ("domain", "formulation", "program", "params")}
+    N = 4000
+    m_l, v_l = oracle.solve(om, w.points, w.point_prim, oracle.make_bc(**b), N, 3, 7)
+    m_r, v_r = oracle.solve(om, w.points, w.point_prim, oracle.make_bc(**b, sampling=oracle.SAMPLE_RIS), N, 3, 8)
+    z = (m_l - m_r) / np.sqrt((v_l + v_r) / N)
+    assert np.max(np.abs(z)) < 4.5, z
