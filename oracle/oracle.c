@@ -557,9 +557,30 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
         for (int c = 0; c < dim; ++c) yc[c] = v0[c] + a * (v1[c] - v0[c]) + b * (v2[c] - v0[c]);
         double r[3] = {yc[0] - x[0], yc[1] - x[1], dim == 3 ? yc[2] - x[2] : 0.0};
         double k = 0.0;
-        if (dot(r, r, dim) > 0.0) {
-          if (first) k = G(x, yc, dim);
-          else k = -2.0 * phi * (dG_dnx(x, yc, nx, dim) + ax * G(x, yc, dim));
+        const double rr = dot(r, r, dim);
+        if (rr > 0.0) {
+          if (first) {
+            k = G(x, yc, dim);
+          } else {
+            /* dG/dn_x = (y - x) . n_x / (4 pi rho^3) (2D: / (2 pi rho^2)).  The
+               vertex x lies in the plane of its primitive, so
+               (y - x) . n_x = (v0_y - v0_x) . n_x + a e1_y . n_x + b e2_y . n_x,
+               which keeps its accuracy when y is close to x and nearly coplanar
+               (forming y - x first would lose it to cancellation); it is zero on
+               the own primitive */
+            double rn = 0.0;
+            if (pj != cur) {
+              double w0[3];
+              prim_vertex(m, cur, 0, w0);
+              double dv[3] = {v0[0] - w0[0], v0[1] - w0[1], dim == 3 ? v0[2] - w0[2] : 0.0};
+              double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], dim == 3 ? v1[2] - v0[2] : 0.0};
+              double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], dim == 3 ? v2[2] - v0[2] : 0.0};
+              rn = dot(dv, nx, dim) + a * dot(e1, nx, dim) + (dim == 3 ? b * dot(e2, nx, dim) : 0.0);
+            }
+            const double rho = sqrt(rr);
+            const double dgdn = dim == 3 ? rn / (4.0 * ORC_PI * rr * rho) : rn / (2.0 * ORC_PI * rr);
+            k = -2.0 * phi * (dgdn + ax * G(x, yc, dim));
+          }
         }
         const double pk = fabs(k);
         S += pk;
