@@ -74,6 +74,15 @@ enum { WOB_PROG_CONST = 0, WOB_PROG_LINEAR = 1, WOB_PROG_QUAD = 2, WOB_PROG_INVD
 /* Scene precision: geometry, arithmetic of the walk and element type of arrays. */
 enum { WOB_F32 = 0, WOB_F64 = 1 };
 
+/* How the single layer samples its integrals (see wob_bc.sampling).  RIS, per
+ * vertex x: C candidates y_j area-uniform on the boundary (Philox block 3,
+ * w = j: word 0 picks the primitive by the binary32 cumulative area fraction in
+ * id order, words 1, 2 the point, reflected into the triangle); kernel k = G on
+ * the first step, -2 phi (dG/dn_x + alpha G) on the recursion; a weighted
+ * reservoir keeps candidate j when u_j S_j < |k_j| (u_j from word 3, S_j the
+ * running sum of |k|); weight sign(k) S |Gamma| / C.  No lines are traced. */
+enum { WOB_SAMPLE_LINE = 0, WOB_SAMPLE_RIS = 1 };
+
 typedef struct {
   int32_t domain;       /* +1 interior (phi = +1), -1 exterior (phi = -1) */
   int32_t formulation;  /* WOB_F_* */
@@ -82,6 +91,12 @@ typedef struct {
                            layer nu, single layer mu) at points ON the boundary, without its
                            own emission 2 phi s (the targets of the learned control variate);
                            not with the direct BIE */
+  int32_t sampling;     /* single layer only: WOB_SAMPLE_LINE (line sampling of Sec. 4.4.1,
+                           all hits, uniform pick, self-panel mixture) or WOB_SAMPLE_RIS
+                           (resampled importance sampling over area-uniform boundary
+                           candidates, as the paper does for Robin and mixed problems,
+                           Results).  Other formulations: WOB_SAMPLE_LINE only */
+  int32_t candidates;   /* RIS candidates per vertex, 1..64 (0 selects 16) */
   double params[8];     /* program parameters */
   double self_panel_p;  /* single layer: probability of the in-plane sample on the own
                            primitive where G acts on it (0 selects 1/16); in (0, 1) */

@@ -37,6 +37,8 @@ struct SceneView {
   const typename Rec<R, D>::Prim* prims;
   const R* normals;           // 4 per primitive (leaf order): unit outward normal, 0
   const int32_t* leaf_of_id;  // caller id -> leaf-order index
+  const float* area_cdf;      // caller-id order, cumulative area / |Gamma| (binary32, last 1)
+  R area_total;               // |Gamma|
   int32_t n_nodes;
   int32_t n_prims;
 };

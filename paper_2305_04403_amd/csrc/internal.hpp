@@ -17,7 +17,8 @@ struct wob_scene_s {
   void* d_prims = nullptr;
   void* d_normals = nullptr;
   int32_t* d_leaf_of_id = nullptr;
-  float* d_area_cdf = nullptr;  // leaf order, cumulative area / total (last entry 1)
+  float* d_area_cdf = nullptr;  // caller-id order, cumulative area / total (last entry 1)
+  double area_total = 0.0;      // |Gamma|
   int64_t node_bytes = 0, prim_bytes = 0, device_bytes = 0;
   int32_t n_dirichlet = 0, n_neumann = 0, n_robin = 0;
 };
@@ -49,6 +50,8 @@ wob::SceneView<R, D> view(const wob_scene_s* sc) {
   s.prims = (const typename wob::Rec<R, D>::Prim*)sc->d_prims;
   s.normals = (const R*)sc->d_normals;
   s.leaf_of_id = sc->d_leaf_of_id;
+  s.area_cdf = sc->d_area_cdf;
+  s.area_total = (R)sc->area_total;
   s.n_nodes = (int32_t)sc->n_nodes;
   s.n_prims = (int32_t)sc->n_prims;
   return s;
@@ -73,6 +76,7 @@ struct Plan {
   int32_t L;
   uint32_t self_thr;
   double self_p;
+  int32_t ris_c;  // RIS candidates, 0 = line sampling
 };
 
 inline wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t samples, int32_t walk_len,
@@ -93,6 +97,14 @@ inline wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t sam
   p->self_thr = (uint32_t)std::floor(ps * 16777216.0);
   if (p->self_thr == 0) return WOB_E_ARG;
   p->self_p = p->self_thr / 16777216.0;
+  if (bc->sampling != WOB_SAMPLE_LINE && bc->sampling != WOB_SAMPLE_RIS) return WOB_E_ARG;
+  p->ris_c = 0;
+  if (bc->sampling == WOB_SAMPLE_RIS) {
+    if (f != WOB_F_SINGLE_LAYER) return WOB_E_UNSUPPORTED;
+    const int32_t c = bc->candidates == 0 ? 16 : bc->candidates;
+    if (c < 1 || c > 64) return WOB_E_ARG;
+    p->ris_c = c;
+  }
   return WOB_OK;
 }
 
@@ -119,6 +131,7 @@ wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void*
   a.problem = 0;
   a.lpp_shift = lpp_shift_for(samples, kSolveBlock);
   a.density = bc->density;
+  a.ris_c = pl.ris_c;
   a.form = pl.form == WOB_F_DOUBLE_LAYER ? wob::F_DL : (pl.form == WOB_F_DIRECT ? wob::F_DIRECT : wob::F_SL);
   return a;
 }

@@ -23,6 +23,7 @@ struct WalkArgs {
   int32_t lpp_shift;          // log2 of lanes per point (0 .. log2 of the block size)
   int32_t form;               // F_DL / F_DIRECT / F_SL (read by the batched kernel)
   int32_t density;            // estimate the boundary unknown at boundary points (no own emission)
+  int32_t ris_c;              // single layer: RIS candidates per vertex, 0 = line sampling
   const R* cv_g;              // control-variate table per caller primitive id (single layer), or null
   const R* cv_g0;             // its line-0 table (the add-back's), set whenever cv_g is
   R* mean_out;
@@ -82,6 +83,89 @@ struct PathState {
   int32_t ni;            // traversal position (node index)
 };
 
+// One single-layer vertex by resampled importance sampling (the paper's
+// sampling for Robin and mixed problems, Results): C candidates uniform by
+// area on the boundary (Philox block 3, w = j: word 0 the primitive through
+// the binary32 cumulative area fraction in caller-id order, words 1, 2 the
+// point, word 3 the reservoir uniform), target |k| with k = G on the first step
+// and -2 phi (dG/dn_x + alpha G) on the recursion; a weighted reservoir keeps
+// candidate j when u_j S_j < |k_j|; weight sign(k) S |Gamma| / C.  Moves the
+// path to the kept point and adds its emission; returns false when no
+// candidate carries kernel mass (the path ends).
+template <typename R, int D, bool TRACE>
+__device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D>& s) {
+  const SceneView<R, D>& sc = a.scene;
+  const R phi = a.phi;
+  const R inv4pi = (R)(0.25 / 3.14159265358979323846), inv2pi = (R)(0.5 / 3.14159265358979323846);
+  R S = 0, kpick = 0, ypick[3] = {0, 0, 0};
+  int32_t lpick = -1;
+  for (int j = 0; j < a.ris_c; ++j) {
+    const U4 rj = philox(s.path, s.point, s.z | 3u, (uint32_t)j, a.k0, a.k1);
+    const float u = unit<float>(rj.x);
+    int32_t lo = 0, hi = sc.n_prims - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (sc.area_cdf[mid] > u) hi = mid;
+      else lo = mid + 1;
+    }
+    const int32_t leaf = sc.leaf_of_id[lo];
+    const PrimGeo<R> g = load_prim<R, D>(sc, leaf);
+    R bu = unit<R>(rj.y), bv = D == 3 ? unit<R>(rj.z) : (R)0;
+    if (bu + bv > (R)1) {
+      bu = (R)1 - bu;
+      bv = (R)1 - bv;
+    }
+    R y[3];
+    hit_point(g, bu, bv, y);
+    const R r[3] = {y[0] - s.x[0], y[1] - s.x[1], D == 3 ? y[2] - s.x[2] : (R)0};
+    const R rr = dot3(r, r);
+    R k = 0;
+    if (rr > (R)0) {
+      const R rho = sqrt(rr);
+      if (s.first) {
+        k = D == 3 ? inv4pi / rho : -inv2pi * log(rho);
+      } else {
+        // (y - x) . n_x from the candidate's own vertex and edges: x lies in
+        // the plane of its primitive, so (y - x) . n_x = (v0_y - v0_x) . n_x +
+        // a e1_y . n_x + b e2_y . n_x, free of the cancellation of y - x (whose
+        // binary32 rounding would swamp the small normal component of nearby,
+        // nearly coplanar candidates); zero on the own primitive
+        R rn = 0;
+        if (g.id != s.gc.id) {
+          const R dv[3] = {g.v0[0] - s.gc.v0[0], g.v0[1] - s.gc.v0[1],
+                           D == 3 ? g.v0[2] - s.gc.v0[2] : (R)0};
+          rn = dot3(dv, s.nc) + bu * dot3(g.e1, s.nc) + (D == 3 ? bv * dot3(g.e2, s.nc) : (R)0);
+        }
+        k = D == 3 ? (R)-2 * phi * (inv4pi * rn / (rr * rho) + s.gc.alpha * inv4pi / rho)
+                   : (R)-2 * phi * (inv2pi * rn / rr - s.gc.alpha * inv2pi * log(rho));
+      }
+    }
+    const R pk = fabs(k);
+    S += pk;
+    if (unit<R>(rj.w) * S < pk) {
+      lpick = leaf;
+      kpick = k;
+      ypick[0] = y[0];
+      ypick[1] = y[1];
+      ypick[2] = y[2];
+    }
+  }
+  if (lpick < 0 || !(S > (R)0)) return false;
+  const R w = (kpick > (R)0 ? (R)1 : (R)-1) * S * sc.area_total / (R)a.ris_c;
+  s.W *= w;
+  s.x[0] = ypick[0];
+  s.x[1] = ypick[1];
+  s.x[2] = ypick[2];
+  s.cur_idx = lpick;
+  const PrimGeo<R> gn = load_prim<R, D>(sc, lpick);
+  R nn[3];
+  load_normal<R, D>(sc, lpick, nn);
+  if (TRACE && s.vp) s.vp[s.i] = gn.id;
+  const R sv = boundary_datum<R, D>(a.prog, gn, nn, s.x);
+  s.acc += s.W * ((s.i + 1 < a.M) ? (R)2 * phi : phi) * sv;
+  return true;
+}
+
 template <typename R, int D, int FORM, bool TRACE, bool COUNT, bool CV>
 __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, D>& s, WorkCount& wc) {
   const R phi = a.phi;
@@ -89,8 +173,6 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     if (s.i >= a.L) return ST_DONE;
     s.on_gamma = s.cur_idx >= 0;
     s.z = (a.problem << 24) | ((uint32_t)s.i << 8);
-    const U4 r0 = philox(s.path, s.point, s.z, 0u, a.k0, a.k1);
-    direction<R, D>(r0.x, r0.y, s.d);
     if (s.on_gamma && FORM != F_DL) {
       s.gc = load_prim<R, D>(a.scene, s.cur_idx);
       load_normal<R, D>(a.scene, s.cur_idx, s.nc);
@@ -98,6 +180,15 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     // step 0 from an evaluation point uses the representation formula; in
     // density mode x0 is itself a vertex of the boundary recursion
     s.first = s.i == 0 && !a.density;
+    if constexpr (FORM == F_SL) {
+      if (a.ris_c > 0) {
+        if (!ris_step<R, D, TRACE>(a, s)) return ST_DONE;
+        ++s.i;
+        continue;
+      }
+    }
+    const U4 r0 = philox(s.path, s.point, s.z, 0u, a.k0, a.k1);
+    direction<R, D>(r0.x, r0.y, s.d);
     bool use_self = false;
     s.mixture = false;
     if constexpr (FORM == F_SL) {
@@ -644,12 +735,12 @@ __global__ void sample_boundary_kernel(SceneView<R, D> s, const float* __restric
   const U4 r = philox((uint32_t)i, 0xffffffffu, 0xffffff03u, 0u, k0, k1);
   const float u = unit<float>(r.x);
   int32_t lo = 0, hi = s.n_prims - 1;
-  while (lo < hi) {  // first leaf index with cdf > u
+  while (lo < hi) {  // first caller id with cdf > u
     const int32_t mid = (lo + hi) >> 1;
     if (cdf[mid] > u) hi = mid;
     else lo = mid + 1;
   }
-  const PrimGeo<R> g = load_prim<R, D>(s, lo);
+  const PrimGeo<R> g = load_prim<R, D>(s, s.leaf_of_id[lo]);
   R a = unit<R>(r.y), b = D == 3 ? unit<R>(r.z) : (R)0;
   if (a + b > (R)1) {
     a = (R)1 - a;

@@ -97,7 +97,7 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
                      e1d[0] * e2d[1] - e1d[1] * e2d[0]};
       const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
       for (int a = 0; a < 3; ++a) normals[4 * j + a] = (R)(n[a] / l);
-      area[j] = 0.5 * l;
+      area[id] = 0.5 * l;
     } else {
       for (int a = 0; a < 2; ++a) {
         const double v0 = v[(int64_t)ix[0] * 2 + a], v1 = v[(int64_t)ix[1] * 2 + a];
@@ -108,7 +108,7 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
       const double l = std::sqrt(e1d[0] * e1d[0] + e1d[1] * e1d[1]);
       normals[4 * j + 0] = (R)(e1d[1] / l);
       normals[4 * j + 1] = (R)(-e1d[0] / l);
-      area[j] = l;
+      area[id] = l;
     }
   }
   sc->node_bytes = sizeof(Node);
@@ -125,6 +125,8 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   if (hipMemcpy(sc->d_prims, recs.data(), pb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
   if (hipMemcpy(sc->d_leaf_of_id, leaf_of_id.data(), lb, hipMemcpyHostToDevice) != hipSuccess)
     return WOB_E_DEVICE;
+  // cumulative area fraction in caller-id order: summed in binary64, rounded
+  // once to binary32 (an area-uniform pick compares a binary32 uniform with it)
   std::vector<float> cdf((size_t)T);
   double tot = 0.0;
   for (int64_t j = 0; j < T; ++j) tot += area[j];
@@ -134,6 +136,7 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
     cdf[j] = (float)(run / tot);
   }
   cdf[T - 1] = 1.0f;
+  sc->area_total = tot;
   if (hipMalloc((void**)&sc->d_area_cdf, sizeof(float) * T) != hipSuccess) return WOB_E_ALLOC;
   if (hipMemcpy(sc->d_area_cdf, cdf.data(), sizeof(float) * T, hipMemcpyHostToDevice) != hipSuccess)
     return WOB_E_DEVICE;
@@ -183,7 +186,7 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
   wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
   if (s != WOB_OK) return s;
   if (cv_g && (sc->dim != 3 || sc->precision != WOB_F32 || pl.form != WOB_F_SINGLE_LAYER ||
-               bc->density))
+               bc->density || pl.ris_c > 0))
     return WOB_E_UNSUPPORTED;
   if (n_points < 0 || (n_points > 0 && !points)) return WOB_E_ARG;
   if (n_points >= (int64_t)1 << 32) return WOB_E_ARG;  // point index is a 32-bit counter word

@@ -21,6 +21,7 @@ F32, F64 = 0, 1
 AUTO, DOUBLE_LAYER, DIRECT, SINGLE_LAYER = 0, 1, 2, 3
 PROG_CONST, PROG_LINEAR, PROG_QUAD, PROG_INVDIST = 0, 1, 2, 3
 DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
+SAMPLE_LINE, SAMPLE_RIS = 0, 1
 
 EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_path", "wob_solve",
             "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string",
@@ -37,7 +38,8 @@ class WobError(RuntimeError):
 
 class _BC(C.Structure):
     _fields_ = [("domain", C.c_int32), ("formulation", C.c_int32), ("program", C.c_int32),
-                ("density", C.c_int32), ("params", C.c_double * 8), ("self_panel_p", C.c_double)]
+                ("density", C.c_int32), ("sampling", C.c_int32), ("candidates", C.c_int32),
+                ("params", C.c_double * 8), ("self_panel_p", C.c_double)]
 
 
 class _SceneInfo(C.Structure):
@@ -147,11 +149,14 @@ class BC:
     params: Sequence[float] = ()
     self_panel_p: float = 1.0 / 16.0
     density: bool = False
+    sampling: int = 0             # SAMPLE_LINE or SAMPLE_RIS (single layer)
+    candidates: int = 0           # RIS candidates (0 = 16)
 
     def c(self) -> _BC:
         b = _BC()
         b.domain, b.formulation, b.program = self.domain, self.formulation, self.program
         b.density = int(bool(self.density))
+        b.sampling, b.candidates = int(self.sampling), int(self.candidates)
         for i, v in enumerate(self.params):
             b.params[i] = float(v)
         b.self_panel_p = float(self.self_panel_p)

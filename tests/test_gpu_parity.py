@@ -30,11 +30,13 @@ def dev(a, dtype):
 
 
 def obc(bc: dict, self_p=1.0 / 16.0):
-    return oracle.make_bc(bc["domain"], bc["formulation"], bc["program"], bc["params"], self_p)
+    return oracle.make_bc(bc["domain"], bc["formulation"], bc["program"], bc["params"], self_p,
+                          sampling=bc.get("sampling", 0), candidates=bc.get("candidates", 0) or 16)
 
 
 def wbc(W, bc: dict, self_p=1.0 / 16.0):
-    return W.BC(bc["domain"], bc["formulation"], bc["program"], tuple(bc["params"]), self_p)
+    return W.BC(bc["domain"], bc["formulation"], bc["program"], tuple(bc["params"]), self_p,
+                sampling=bc.get("sampling", 0), candidates=bc.get("candidates", 0))
 
 
 def run_trace_parity(W, mesh, pts, pp, bc, N, M, seed, precision, max_vertex_mismatch_frac=0.0):
@@ -158,6 +160,48 @@ def test_trace_parity_interior_single_layer_2d_f64(W):
     pp = np.concatenate([np.full(40, -1), bp]).astype(np.int32)
     bc = dict(domain=1, formulation=3, program=2, params=())
     run_trace_parity(W, mesh, pts, pp, bc, 64, 3, 2, "f64")
+
+
+def test_trace_parity_single_layer_ris_tori(W):
+    """Single layer with resampled importance sampling (16 area-uniform
+    candidates) on the tori union, Neumann / Robin, points off and on the
+    boundary: the kept candidate of every vertex and the path values."""
+    w = I.config_tori(grid_n=20, n_points=80, boundary_frac=0.25, samples=64, walk_len=4)
+    bc = dict(w.bc, sampling=1, candidates=16)
+    run_trace_parity(W, w.mesh, w.points, w.point_prim, bc, 64, 4, 13, "f32",
+                     max_vertex_mismatch_frac=0.002)
+
+
+def test_trace_parity_single_layer_ris_2d_f64(W):
+    """2D interior Robin single layer with RIS (8 candidates) in FP64."""
+    m = I.circle_polygon(96)
+    mesh = I.Mesh(2, m.verts, m.prims, np.full(96, 2, np.uint8), np.full(96, 0.5))
+    pts = I.disk_points(40, 0.8, 9)
+    bc = dict(domain=1, formulation=3, program=2, params=(), sampling=1, candidates=8)
+    run_trace_parity(W, mesh, pts, None, bc, 64, 3, 2, "f64")
+
+
+def test_ris_arguments(W):
+    mesh = PT.f32_mesh(I.icosphere(4))
+    scene = W.Scene(mesh, W.F32)
+    pts = dev(PT.f32(I.ball_points(5, 0.5, 1)), torch.float32)
+    # RIS is a single-layer sampling: the double layer rejects it
+    with pytest.raises(W.WobError):
+        W.solve(scene, pts, W.BC(1, W.AUTO, W.PROG_CONST, (1.0,), sampling=W.SAMPLE_RIS), 8, 2)
+    neu = I.Mesh(3, mesh.verts, mesh.prims, np.full(mesh.n_prims, 1, np.uint8), None)
+    s2 = W.Scene(neu, W.F32)
+    for c in (-1, 65):
+        with pytest.raises(W.WobError):
+            W.solve(s2, pts, W.BC(-1, W.SINGLE_LAYER, W.PROG_CONST, (1.0,), sampling=W.SAMPLE_RIS,
+                                  candidates=c), 8, 2)
+    with pytest.raises(W.WobError):
+        W.solve(s2, pts, W.BC(-1, W.SINGLE_LAYER, W.PROG_CONST, (1.0,), sampling=2), 8, 2)
+    # the corrected (control-variate) walk is built for line sampling only
+    g = torch.zeros(mesh.n_prims, dtype=torch.float32, device="cuda")
+    with pytest.raises(W.WobError):
+        W.solve_cv(s2, pts, W.BC(-1, W.SINGLE_LAYER, W.PROG_CONST, (1.0,), sampling=W.SAMPLE_RIS), 8, 2, g)
+    s2.close()
+    scene.close()
 
 
 @pytest.mark.parametrize("N", [1, 3, 5, 7, 130])
