@@ -149,9 +149,11 @@ def cv_leg(torch, wob, I):
     """Equal wall time on the 1M points: plain WoB at 512 paths against the
     corrected estimator with (a) g = g0 = 0 (hit-selection Rao-Blackwellisation
     only), (b) g = 0, g0 = line-0 emission at the centroid, (c) the learned
-    network (fit included in its time) and (d) the same without the fit time.
-    Every variant runs with 3 seeds and reports the RMSE pooled over them (the
-    single-layer weights are heavy-tailed, so one seed's RMSE is noisy)."""
+    network (fit included in its time) and (d) the same without the fit time;
+    and plain resampled importance sampling (4 and 16 area candidates) in place
+    of line sampling.  Every variant runs with 3 seeds and reports the RMSE
+    pooled over them (the single-layer weights are heavy-tailed, so one seed's
+    RMSE is noisy) and the median error."""
     import math
     from paper_2305_04403_amd import cv as CV
     w = I.config_tori()
@@ -237,6 +239,31 @@ def cv_leg(torch, wob, I):
     out["learned"].update({"fit_s": fit["fit_s"], "targets_s": fit["targets_s"], "train_s": fit["train_s"],
                            "train_steps": fit["train_steps"]})
     run("learned_inference_only", lcv.g, lcv.g0, 0.0, 6)
+
+    # the paper's sampling for Robin / mixed problems: RIS over area-uniform
+    # candidates (16 in the paper; 4 is cheaper than a traced line)
+    import dataclasses
+    for C in (4, 16):
+        b = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=C)
+        wob.solve(scene, pts[:4096].contiguous(), b, 64, M, point_prim=pp[:4096].contiguous())
+        tt = []
+        for n_probe in (64, 128):
+            t0 = time.perf_counter()
+            wob.solve(scene, pts, b, n_probe, M, seed=2, point_prim=pp)
+            sync()
+            tt.append(time.perf_counter() - t0)
+        pp_cost = max((tt[1] - tt[0]) / 64, 1e-9)
+        n = int(max(16, (t_plain - max(tt[0] - 64 * pp_cost, 0.0)) / pp_cost // 16 * 16))
+        rr, tm = [], []
+        for sd in seeds:
+            t0 = time.perf_counter()
+            rr.append(wob.solve(scene, pts, b, n, M, seed=sd + 700 + C, point_prim=pp))
+            sync()
+            tm.append(time.perf_counter() - t0)
+        r, e, ps, v = pooled(rr)
+        out[f"ris_{C}"] = {"paths": n, "seconds": float(np.mean(tm)), "path_cost_vs_line": pp_cost / (t_plain / N),
+                           "rmse": r, "rmse_per_seed": ps, "median_abs_err": e, "mean_var": v,
+                           "rmse_ratio": rp / r, "median_err_ratio": ep / e}
     out["addback_s"] = t_add
     out["corrected_path_cost_vs_plain"] = per_path / (t_plain / N)
     out["rmse_ratio_equal_time"] = out["learned"]["rmse_ratio"]
