@@ -29,7 +29,8 @@ class _Mesh(C.Structure):
 class _BC(C.Structure):
     _fields_ = [("domain", C.c_int), ("formulation", C.c_int), ("program", C.c_int),
                 ("params", C.c_double * 8), ("self_threshold", C.c_uint32), ("self_p", C.c_double),
-                ("density", C.c_int), ("sampling", C.c_int), ("candidates", C.c_int)]
+                ("density", C.c_int), ("sampling", C.c_int), ("candidates", C.c_int),
+                ("mixed_k", C.c_double), ("mixed_threshold", C.c_uint32), ("mixed_p", C.c_double)]
 
 
 class _TraceOut(C.Structure):
@@ -129,8 +130,11 @@ SAMPLE_LINE, SAMPLE_RIS = 0, 1
 
 def make_bc(domain: int = 1, formulation: int = AUTO, program: int = PROG_CONST,
             params=(), self_p: float = 1.0 / 16.0, density: bool = False, sampling: int = SAMPLE_LINE,
-            candidates: int = 16) -> _BC:
+            candidates: int = 16, mixed_k: float = 4.0, mixed_p: float = 2.0 / 3.0) -> _BC:
     b = _BC()
+    b.mixed_k = float(mixed_k)
+    b.mixed_threshold = self_threshold(mixed_p)
+    b.mixed_p = b.mixed_threshold / 2.0 ** 24
     b.density = int(bool(density))
     b.sampling = int(sampling)
     b.candidates = int(candidates)

@@ -344,12 +344,11 @@ int orc_resolve_formulation(const orc_mesh* m, int formulation) {
   if (formulation == ORC_AUTO) {
     if (nn == 0 && nr == 0) return ORC_DOUBLE_LAYER;
     if (nd == 0 && nr == 0) return ORC_DIRECT;
-    if (nd == 0) return ORC_SINGLE_LAYER;
-    return -1;
+    return ORC_SINGLE_LAYER; /* Robin, Neumann / Robin, and mixed with Dirichlet parts */
   }
   if (formulation == ORC_DOUBLE_LAYER) return (nn == 0 && nr == 0) ? formulation : -1;
   if (formulation == ORC_DIRECT) return (nd == 0 && nr == 0) ? formulation : -1;
-  if (formulation == ORC_SINGLE_LAYER) return nd == 0 ? formulation : -1;
+  if (formulation == ORC_SINGLE_LAYER) return formulation;
   return -1;
 }
 
@@ -469,6 +468,17 @@ static int64_t area_pick(const area_table* t, int64_t n, float u) {
   return lo;
 }
 
+/* Single-layer emission at a vertex y on primitive prim, before the running
+   weight: 2 phi s(y) on Neumann / Robin parts (Table 1) and k u_D(y) on
+   Dirichlet parts (eq. mixed_second_kind_ish); half of it at the last vertex
+   x_M (Sec. 4.1.2). */
+static double sl_emission(const orc_mesh* m, const orc_bc* bc, int64_t prim, const double* y,
+                          int last_vertex) {
+  const double s = orc_boundary_datum(m, bc, prim, y);
+  const double e = prim_kind(m, prim) == ORC_DIRICHLET ? bc->mixed_k * s : 2.0 * (double)bc->domain * s;
+  return last_vertex ? 0.5 * e : e;
+}
+
 /* ------------------------------------------------------------------------- */
 /* One path (point p, path k).                                                */
 /* ------------------------------------------------------------------------- */
@@ -491,8 +501,10 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       for (int a = 0; a < dim; ++a) vpos[i * dim + a] = NAN;
   }
 
-  /* Table 1, Dirichlet: on the boundary the solution is the given value. */
-  if (form == ORC_DOUBLE_LAYER && prim0 >= 0 && !bc->density) {
+  /* Table 1, Dirichlet: on the boundary the solution is the given value (also
+     on the Dirichlet parts of a mixed problem) */
+  if (prim0 >= 0 && !bc->density &&
+      (form == ORC_DOUBLE_LAYER || (form == ORC_SINGLE_LAYER && prim_kind(m, prim0) == ORC_DIRICHLET))) {
     res.value = orc_boundary_datum(m, bc, prim0, x0);
     res.abs_sum = fabs(res.value);
     return res;
@@ -525,6 +537,25 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
     /* step 0 from an evaluation point uses the representation formula; in
        density mode x0 is itself a boundary vertex of the recursion */
     const int first = i == 0 && !bc->density;
+    /* a Dirichlet vertex of the single-layer recursion (mixed problems): the
+       transformed first-kind row mu = mu - k int G mu + k u_D, sampled term by
+       term: with probability p_k the next point comes from k G (weight
+       -k G / (p p_k)), otherwise the walk stays at x (weight 1 / (1 - p_k)) */
+    const int dvert = form == ORC_SINGLE_LAYER && on_gamma && !first && prim_kind(m, cur) == ORC_DIRICHLET;
+    if (dvert && (r0[3] >> 8) >= bc->mixed_threshold) {
+      const double w = 1.0 / (1.0 - bc->mixed_p);
+      W *= w;
+      Wabs *= w;
+      if (vprim) vprim[i] = (int32_t)(-2 - cur);
+      if (vm) vm[i] = 0;
+      if (vpos)
+        for (int a = 0; a < dim; ++a) vpos[i * dim + a] = x[a];
+      const double e = sl_emission(m, bc, cur, x, i + 1 >= M);
+      acc += W * e;
+      abs_sum += Wabs * fabs(e);
+      continue;
+    }
+    const double gscale = dvert ? -bc->mixed_k / bc->mixed_p : 1.0; /* kernel k G / p_k or G */
 
     if (form == ORC_SINGLE_LAYER && bc->sampling == ORC_SAMPLE_RIS) {
       /* Resampled importance sampling (Results: Robin and mixed problems use
@@ -559,8 +590,8 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
         double k = 0.0;
         const double rr = dot(r, r, dim);
         if (rr > 0.0) {
-          if (first) {
-            k = G(x, yc, dim);
+          if (first || dvert) {
+            k = gscale * G(x, yc, dim);
           } else {
             /* dG/dn_x = (y - x) . n_x / (4 pi rho^3) (2D: / (2 pi rho^2)).  The
                vertex x lies in the plane of its primitive, so
@@ -605,8 +636,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       cur = jpick;
       if (vpos)
         for (int a = 0; a < dim; ++a) vpos[i * dim + a] = x[a];
-      double s = orc_boundary_datum(m, bc, cur, x);
-      double e = (i + 1 < M ? 2.0 : 1.0) * phi * s;
+      const double e = sl_emission(m, bc, cur, x, i + 1 >= M);
       acc += W * e;
       abs_sum += Wabs * fabs(e);
       continue;
@@ -616,7 +646,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
        boundary point, and the alpha G part at Robin vertices) mix the line
        sample with an in-plane self-panel sample */
     int mixture = form == ORC_SINGLE_LAYER && on_gamma &&
-                  (first || prim_kind(m, cur) == ORC_ROBIN);
+                  (first || dvert || prim_kind(m, cur) == ORC_ROBIN);
     int use_self = mixture && (r0[2] >> 8) < bc->self_threshold;
 
     double y[3] = {0.0, 0.0, 0.0};
@@ -626,8 +656,8 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       uint32_t r1[4];
       draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
       double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), y);
-      if (first)
-        w = gp / bc->self_p; /* u = int G mu */
+      if (first || dvert)
+        w = gscale * gp / bc->self_p; /* u = int G mu; Dirichlet vertex: -k G / p_k */
       else
         w = -2.0 * phi * prim_alpha(m, cur) * gp / bc->self_p; /* -2 phi alpha G */
       wabs = fabs(w);
@@ -680,8 +710,8 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
                         : -phi * dG_dny(x, y, ny, dim);      /* interior / exterior row */
         kabs = fabs(kern);
       } else {
-        if (first) {
-          kern = G(x, y, dim); /* u = int G mu */
+        if (first || dvert) {
+          kern = gscale * G(x, y, dim); /* u = int G mu; Dirichlet vertex: -k G / p_k */
           kabs = fabs(kern);
         } else {
           const double* nx = normals + 3 * cur;
@@ -711,10 +741,15 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       for (int a = 0; a < dim; ++a) vpos[i * dim + a] = x[a];
 
     if (form != ORC_DIRECT) {
-      /* emission 2 phi s at x_{i+1}; the last vertex gets half of it
-         (Sec. 4.1.2, modified Neumann series) */
-      double s = orc_boundary_datum(m, bc, cur, x);
-      double e = (i + 1 < M ? 2.0 : 1.0) * phi * s;
+      /* emission 2 phi s at x_{i+1} (single layer on Dirichlet parts: k u_D);
+         the last vertex gets half of it (Sec. 4.1.2, modified Neumann series) */
+      double e;
+      if (form == ORC_SINGLE_LAYER) {
+        e = sl_emission(m, bc, cur, x, i + 1 >= M);
+      } else {
+        double s = orc_boundary_datum(m, bc, cur, x);
+        e = (i + 1 < M ? 2.0 : 1.0) * phi * s;
+      }
       acc += W * e;
       abs_sum += Wabs * fabs(e);
     }
@@ -739,6 +774,9 @@ static int check_args(const orc_mesh* m, const orc_bc* bc, int walk_len) {
   if (orc_resolve_formulation(m, bc->formulation) < 0) return 1;
   if (bc->density && orc_resolve_formulation(m, bc->formulation) == ORC_DIRECT) return 1;
   if (bc->sampling != ORC_SAMPLE_LINE && bc->sampling != ORC_SAMPLE_RIS) return 1;
+  if (!(bc->mixed_p > 0.0 && bc->mixed_p < 1.0) || bc->mixed_threshold == 0 || !isfinite(bc->mixed_k) ||
+      bc->mixed_k == 0.0)
+    return 1;
   if (bc->sampling == ORC_SAMPLE_RIS &&
       (orc_resolve_formulation(m, bc->formulation) != ORC_SINGLE_LAYER || bc->candidates < 1 ||
        bc->candidates > 64))
@@ -1130,6 +1168,8 @@ int orc_trace_cv(const orc_mesh* m, const double* points, const int32_t* point_p
   if (check_args(m, bc, walk_len) || !g) return 1;
   if (!g0) g0 = g;
   if (orc_resolve_formulation(m, bc->formulation) != ORC_SINGLE_LAYER || bc->density) return 1;
+  for (int64_t j = 0; j < m->n_prims; ++j)
+    if (prim_kind(m, j) == ORC_DIRICHLET) return 1; /* the corrected walk has no Dirichlet rows */
   double* normals = make_normals(m);
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);

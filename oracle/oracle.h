@@ -64,6 +64,13 @@ typedef struct {
                               the self-panel mixture) or ORC_SAMPLE_RIS (resampled importance
                               sampling over area-uniform candidates, Results) */
   int candidates;          /* RIS candidates per vertex, 1..64 */
+  /* single layer with Dirichlet parts (mixed problems, eq. mixed_second_kind_ish):
+     at a Dirichlet vertex the next point is sampled from k G with probability
+     p_k (weight -k G / (p p_k)) and otherwise the walk stays (weight 1/(1-p_k));
+     the emission there is k u_D */
+  double mixed_k;
+  uint32_t mixed_threshold; /* p_k as floor(p_k * 2^24) */
+  double mixed_p;           /* floor(p_k * 2^24) / 2^24 */
 } orc_bc;
 
 enum { ORC_SAMPLE_LINE = 0, ORC_SAMPLE_RIS = 1 };

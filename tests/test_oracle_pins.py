@@ -420,3 +420,63 @@ def test_ris_and_line_sampling_agree_on_the_tori():
     m_r, v_r = oracle.solve(om, w.points, w.point_prim, oracle.make_bc(**b, sampling=oracle.SAMPLE_RIS), N, 3, 8)
     z = (m_l - m_r) / np.sqrt((v_l + v_r) / N)
     assert np.max(np.abs(z)) < 4.5, z
+
+
+# --------------------------------------------------------------------------- mixed problems
+
+@pytest.mark.parametrize("sampling", [oracle.SAMPLE_LINE, oracle.SAMPLE_RIS])
+def test_dirichlet_rows_of_the_single_layer_on_the_sphere(sampling):
+    """Dirichlet parts of the single layer (eq. mixed_second_kind_ish: mu = mu -
+    k S mu + k u_D, sampled as eq. mixed_second_kind_ish_mc), all-Dirichlet unit
+    sphere.  S has eigenvalue 1 / (2l + 1), so the recursion has lambda_l =
+    1 - k / (2l + 1) and the truncated estimate is tau_M(lambda) times the
+    solution, tau_M = 1 - lambda^(M-1) (1 + lambda) / 2.  k = 1: constant data
+    (lambda 0) gives 1/2, 1; the data z (lambda 2/3) gives 1/6, 4/9."""
+    s = I.icosphere(6)
+    mesh = I.Mesh(3, s.verts, s.prims, np.zeros(s.n_prims, np.uint8), None)
+    om = oracle.OracleMesh(mesh)
+    pts = I.ball_points(20, 0.6, 3)
+    cases = [(oracle.PROG_CONST, (1.0,), np.ones(len(pts)), {1: 0.5, 2: 1.0}),
+             (oracle.PROG_LINEAR, (0.0, 0.0, 1.0, 0.0), pts[:, 2], {1: 1 / 6, 2: 4 / 9})]
+    N = 3000
+    for prog, params, ex, taus in cases:
+        for M, tau in taus.items():
+            bc = oracle.make_bc(1, oracle.SINGLE_LAYER, prog, params, sampling=sampling, mixed_k=1.0)
+            m, v = oracle.solve(om, pts, None, bc, N, M, 5)
+            w = N / np.maximum(v, 1e-30)
+            est = np.sum(w * m * ex) / np.sum(w * ex * ex)
+            se = 1.0 / np.sqrt(np.sum(w * ex * ex))
+            assert abs(est - tau) < 4 * se + 0.015, (prog, M, est, tau, se)
+
+
+@pytest.mark.parametrize("sampling", [oracle.SAMPLE_LINE, oracle.SAMPLE_RIS])
+def test_mixed_problem_2d_matches_analytic(sampling):
+    """The paper's mixed setup (Results): every segment of the 256-gon Dirichlet,
+    Neumann or Robin (alpha = 1) at random, k = 4, p_k = 2/3, interior harmonic
+    u = x^2 - y^2: the means sit within 4.5 SE of u at M = 2 and 4 (the
+    truncation bias is below the noise there)."""
+    c = I.circle_polygon(256)
+    kind = np.random.default_rng(1).integers(0, 3, 256).astype(np.uint8)
+    mesh = I.Mesh(2, c.verts, c.prims, kind, np.full(256, 1.0))
+    om = oracle.OracleMesh(mesh)
+    pts = I.disk_points(30, 0.8, 2)
+    ex = pts[:, 0] ** 2 - pts[:, 1] ** 2
+    N = 4000
+    for M in (2, 4):
+        bc = oracle.make_bc(1, oracle.AUTO, oracle.PROG_QUAD, (), sampling=sampling)
+        m, v = oracle.solve(om, pts, None, bc, N, M, 7)
+        z = (m - ex) / np.sqrt(v / N)
+        assert np.max(np.abs(z)) < 4.5, (M, z)
+
+
+def test_mixed_problem_dirichlet_boundary_point_returns_data():
+    c = I.circle_polygon(64)
+    kind = np.array([0, 1] * 32, np.uint8)
+    mesh = I.Mesh(2, c.verts, c.prims, kind, None)
+    om = oracle.OracleMesh(mesh)
+    on = 0.5 * (c.verts[c.prims[::2, 0]] + c.verts[c.prims[::2, 1]])  # midpoints of Dirichlet segments
+    prim = np.arange(0, 64, 2, dtype=np.int32)
+    bc = oracle.make_bc(1, oracle.AUTO, oracle.PROG_QUAD, ())
+    m, v = oracle.solve(om, on, prim, bc, 4, 3, 0)
+    np.testing.assert_allclose(m, on[:, 0] ** 2 - on[:, 1] ** 2, rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(v, 0.0)
