@@ -127,6 +127,26 @@ static double G(const double* x, const double* y, int dim) {
   double rn = sqrt(dot(r, r, dim));
   return dim == 3 ? 1.0 / (4.0 * ORC_PI * rn) : -log(rn) / (2.0 * ORC_PI);
 }
+/* Conditioning of a kernel evaluated at distance rho = |y - x| formed from
+   coordinates of size |x|: rho, and G through it, carry a relative error of
+   order (unit roundoff) |x| / rho.  Folded into the path's cond_cos (the
+   parity tolerance grows like 1 / cond_cos). */
+static double rho_cond(const double* x, const double* y, int dim) {
+  double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+  const double rho = sqrt(dot(r, r, dim));
+  return rho / fmax(1.0, sqrt(dot(x, x, dim)));
+}
+
+/* Error scale of a G factor for the parity tolerance (the magnitude sum of a
+   path): |G| in 3D; in 2D max(|ln rho|, 1) / (2 pi), because ln rho carries an
+   absolute rounding error of order one unit of the arithmetic, which does not
+   vanish where G itself does (rho near 1). */
+static double G_mag(const double* x, const double* y, int dim) {
+  if (dim == 3) return fabs(G(x, y, dim));
+  double r[2] = {y[0] - x[0], y[1] - x[1]};
+  return fmax(fabs(log(sqrt(r[0] * r[0] + r[1] * r[1]))), 1.0) / (2.0 * ORC_PI);
+}
+
 static double dG_dny(const double* x, const double* y, const double* ny, int dim) {
   double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
   double rn = sqrt(dot(r, r, dim));
@@ -217,8 +237,19 @@ double orc_boundary_datum(const orc_mesh* m, const orc_bc* bc, int64_t prim, con
 /* Returns 1 on a hit.  *margin is the signed smallest barycentric coordinate  */
 /* (negative outside), *cosv = |d . n| of the primitive.                       */
 /* ------------------------------------------------------------------------- */
+static int line_prim_b(const orc_mesh* m, int64_t j, const double* x, const double* d,
+                       double* t, double* y, double* margin, double* cosv, double* bary);
+
 static int line_prim(const orc_mesh* m, int64_t j, const double* x, const double* d,
                      double* t, double* y, double* margin, double* cosv) {
+  double b[2];
+  return line_prim_b(m, j, x, d, t, y, margin, cosv, b);
+}
+
+/* As line_prim; also writes the barycentric coordinates of y along e1, e2
+   (2D: along the segment, and 0). */
+static int line_prim_b(const orc_mesh* m, int64_t j, const double* x, const double* d,
+                       double* t, double* y, double* margin, double* cosv, double* bary) {
   double v0[3] = {0.0, 0.0, 0.0}, v1[3] = {0.0, 0.0, 0.0}, v2[3] = {0.0, 0.0, 0.0};
   prim_vertex(m, j, 0, v0);
   prim_vertex(m, j, 1, v1);
@@ -247,6 +278,8 @@ static int line_prim(const orc_mesh* m, int64_t j, const double* x, const double
     mg = mg < w ? mg : w;
     *margin = mg;
     for (int a = 0; a < 3; ++a) y[a] = v0[a] + u * e1[a] + v * e2[a];
+    bary[0] = u;
+    bary[1] = v;
     return mg >= 0.0;
   } else {
     double e[2] = {v1[0] - v0[0], v1[1] - v0[1]};
@@ -266,6 +299,8 @@ static int line_prim(const orc_mesh* m, int64_t j, const double* x, const double
     y[0] = v0[0] + s * e[0];
     y[1] = v0[1] + s * e[1];
     y[2] = 0.0;
+    bary[0] = s;
+    bary[1] = 0.0;
     return mg >= 0.0;
   }
 }
@@ -365,6 +400,7 @@ typedef struct {
   int64_t sel;           /* selected primitive (smallest key, then id), -1 if none */
   uint32_t sel_key;
   double sel_y[3];
+  double sel_b[2];       /* barycentric coordinates of the selected hit */
   double src;            /* sum over hits of G(x,y) q(y) / p_all(y) (direct Neumann) */
   double src_abs;        /* sum over hits of |G(x,y) q(y) / p_all(y)| */
   double src_cos;        /* smallest |cos theta_y| among the source hits */
@@ -384,8 +420,8 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
   h->graze = INFINITY;
   for (int64_t j = 0; j < m->n_prims; ++j) {
     if (j == exclude) continue;
-    double t, y[3], margin, cosv;
-    int hit = line_prim(m, j, x, d, &t, y, &margin, &cosv);
+    double t, y[3], margin, cosv, b[2];
+    int hit = line_prim_b(m, j, x, d, &t, y, &margin, &cosv, b);
     double g = fabs(margin) * cosv;
     if (g < h->graze) h->graze = g;
     if (!hit) continue;
@@ -397,6 +433,8 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
         h->sel = j;
         h->sel_key = r[0];
         memcpy(h->sel_y, y, sizeof(h->sel_y));
+        h->sel_b[0] = b[0];
+        h->sel_b[1] = b[1];
       }
     }
     if (want_src) {
@@ -568,7 +606,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
          so the kept one has probability |k_j| / S.  Weight
          k(y) / |k(y)| * S |Gamma| / C, the RIS estimate of int k(y) (.) dy. */
       const int C = bc->candidates;
-      double S = 0.0, kpick = 0.0, ypick[3] = {0.0, 0.0, 0.0};
+      double S = 0.0, Smag = 0.0, kpick = 0.0, ypick[3] = {0.0, 0.0, 0.0};
       int64_t jpick = -1;
       const double* nx = on_gamma ? normals + 3 * cur : NULL;
       const double ax = on_gamma ? prim_alpha(m, cur) : 0.0;
@@ -615,6 +653,17 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
         }
         const double pk = fabs(k);
         S += pk;
+        if (rr > 0.0) {
+          const double c = rho_cond(x, yc, dim);
+          if (c < res.cond_cos) res.cond_cos = c;
+        }
+        if (rr > 0.0) { /* the same kernel with its error scale (G_mag) */
+          if (first || dvert) {
+            Smag += fabs(gscale) * G_mag(x, yc, dim);
+          } else { /* |2 dG/dn_x| + 2 |alpha| G_mag, with 2 dG/dn_x = -k / phi - 2 alpha G */
+            Smag += fabs(k + 2.0 * phi * ax * G(x, yc, dim)) + 2.0 * fabs(ax) * G_mag(x, yc, dim);
+          }
+        }
         const double u = uniform(rj[3]);
         if (S > 0.0) {
           double margin = fabs(u * S - pk) / S; /* distance of the keep decision from its threshold */
@@ -631,7 +680,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       if (vprim) vprim[i] = (int32_t)jpick;
       const double w = (kpick > 0.0 ? 1.0 : -1.0) * S * at->total / (double)C;
       W *= w;
-      Wabs *= fabs(w);
+      Wabs *= Smag * at->total / (double)C;
       memcpy(x, ypick, sizeof(x));
       cur = jpick;
       if (vpos)
@@ -656,6 +705,12 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       uint32_t r1[4];
       draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
       double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), y);
+      {
+        /* 2D: G at rho = |y - x|; 3D: the distance R(theta) to the triangle's
+           boundary, from coordinate differences (rho <= R bounds it below) */
+        const double c = rho_cond(x, y, dim);
+        if (c < res.cond_cos) res.cond_cos = c;
+      }
       if (first || dvert)
         w = gscale * gp / bc->self_p; /* u = int G mu; Dirichlet vertex: -k G / p_k */
       else
@@ -712,11 +767,41 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       } else {
         if (first || dvert) {
           kern = gscale * G(x, y, dim); /* u = int G mu; Dirichlet vertex: -k G / p_k */
-          kabs = fabs(kern);
+          kabs = fabs(gscale) * G_mag(x, y, dim);
+          const double c = rho_cond(x, y, dim);
+          if (c < res.cond_cos) res.cond_cos = c;
         } else {
+          /* dG/dn_x with its numerator (y - x) . n_x in vertex-and-edge form:
+             x lies in the plane of its primitive, so (y - x) . n_x =
+             (v0_y - v0_x) . n_x + b1 e1_y . n_x + b2 e2_y . n_x, accurate also
+             for a hit close to x on a nearly coplanar neighbour (where forming
+             y - x first loses digits to cancellation) */
           const double* nx = normals + 3 * cur;
-          kern = -2.0 * phi * (dG_dnx(x, y, nx, dim) + prim_alpha(m, cur) * G(x, y, dim));
-          kabs = 2.0 * (fabs(dG_dnx(x, y, nx, dim)) + fabs(prim_alpha(m, cur) * G(x, y, dim)));
+          double w0[3] = {0.0, 0.0, 0.0}, u0[3] = {0.0, 0.0, 0.0}, u1[3] = {0.0, 0.0, 0.0},
+                 u2[3] = {0.0, 0.0, 0.0};
+          prim_vertex(m, cur, 0, w0);
+          prim_vertex(m, next, 0, u0);
+          prim_vertex(m, next, 1, u1);
+          if (dim == 3) prim_vertex(m, next, 2, u2);
+          double dv[3], e1[3], e2[3];
+          for (int a = 0; a < 3; ++a) {
+            dv[a] = u0[a] - w0[a];
+            e1[a] = u1[a] - u0[a];
+            e2[a] = dim == 3 ? u2[a] - u0[a] : 0.0;
+          }
+          const double rn = dot(dv, nx, dim) + h.sel_b[0] * dot(e1, nx, dim) +
+                            (dim == 3 ? h.sel_b[1] * dot(e2, nx, dim) : 0.0);
+          double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+          const double rr = dot(r, r, dim), rho = sqrt(rr);
+          const double dgdn = dim == 3 ? rn / (4.0 * ORC_PI * rr * rho) : rn / (2.0 * ORC_PI * rr);
+          kern = -2.0 * phi * (dgdn + prim_alpha(m, cur) * G(x, y, dim));
+          kabs = 2.0 * (fabs(dgdn) + fabs(prim_alpha(m, cur)) * G_mag(x, y, dim));
+          /* a binary32 cos theta_x carries ~1e-7 absolute error, and rho from
+             coordinates a relative error ~ |x| / rho units */
+          const double cx = fabs(rn) / rho;
+          if (cx < res.cond_cos) res.cond_cos = cx;
+          const double cr = rho_cond(x, y, dim);
+          if (cr < res.cond_cos) res.cond_cos = cr;
         }
         /* the single-layer weight carries 1 / |cos theta_y| */
         {
