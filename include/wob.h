@@ -59,8 +59,10 @@ typedef enum {
 enum { WOB_BC_DIRICHLET = 0, WOB_BC_NEUMANN = 1, WOB_BC_ROBIN = 2 };
 
 /* BIE formulation (Table 1).  AUTO: all Dirichlet -> double layer, all Neumann
- * -> direct, Robin or Neumann/Robin mixture -> single layer.  Mixtures with
- * Dirichlet parts return WOB_E_UNSUPPORTED. */
+ * -> direct, anything with Robin parts or mixing kinds -> single layer (on
+ * Dirichlet parts the transformed first-kind row of eq. mixed_second_kind_ish,
+ * see wob_bc.mixed_k).  The double layer takes Dirichlet meshes only, the
+ * direct BIE Neumann meshes only; the single layer takes any mesh. */
 enum { WOB_F_AUTO = 0, WOB_F_DOUBLE_LAYER = 1, WOB_F_DIRECT = 2, WOB_F_SINGLE_LAYER = 3 };
 
 /* Harmonic function u whose boundary traces give the data: Dirichlet u,
@@ -100,6 +102,11 @@ typedef struct {
   double params[8];     /* program parameters */
   double self_panel_p;  /* single layer: probability of the in-plane sample on the own
                            primitive where G acts on it (0 selects 1/16); in (0, 1) */
+  double mixed_k;       /* single layer with Dirichlet parts (mixed problems): the constant k
+                           of the transformed first-kind row mu = mu - k int G mu + k u_D
+                           (eq. mixed_second_kind_ish); 0 selects 4 (the paper's Results) */
+  double mixed_p;       /* its probability p_k of sampling the k G term (else the walk stays
+                           at x), in (0, 1); 0 selects 2/3 */
 } wob_bc;
 
 typedef struct {

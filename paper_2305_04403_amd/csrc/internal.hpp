@@ -62,12 +62,11 @@ inline int resolve_formulation(const wob_scene_s* sc, int f) {
   if (f == WOB_F_AUTO) {
     if (!n && !r) return WOB_F_DOUBLE_LAYER;
     if (!d && !r) return WOB_F_DIRECT;
-    if (!d) return WOB_F_SINGLE_LAYER;
-    return -1;
+    return WOB_F_SINGLE_LAYER;  // Robin parts or mixed kinds (Dirichlet parts: first-kind rows)
   }
   if (f == WOB_F_DOUBLE_LAYER) return (!n && !r) ? f : -1;
   if (f == WOB_F_DIRECT) return (!d && !r) ? f : -1;
-  if (f == WOB_F_SINGLE_LAYER) return !d ? f : -1;
+  if (f == WOB_F_SINGLE_LAYER) return f;
   return -2;
 }
 
@@ -77,6 +76,8 @@ struct Plan {
   uint32_t self_thr;
   double self_p;
   int32_t ris_c;  // RIS candidates, 0 = line sampling
+  uint32_t mixed_thr;
+  double mixed_p, mixed_k;
 };
 
 inline wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t samples, int32_t walk_len,
@@ -97,6 +98,13 @@ inline wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t sam
   p->self_thr = (uint32_t)std::floor(ps * 16777216.0);
   if (p->self_thr == 0) return WOB_E_ARG;
   p->self_p = p->self_thr / 16777216.0;
+  const double mk = bc->mixed_k == 0.0 ? 4.0 : bc->mixed_k;
+  const double mp = bc->mixed_p == 0.0 ? 2.0 / 3.0 : bc->mixed_p;
+  if (!std::isfinite(mk) || !(mp > 0.0 && mp < 1.0)) return WOB_E_ARG;
+  p->mixed_k = mk;
+  p->mixed_thr = (uint32_t)std::floor(mp * 16777216.0);
+  if (p->mixed_thr == 0) return WOB_E_ARG;
+  p->mixed_p = p->mixed_thr / 16777216.0;
   if (bc->sampling != WOB_SAMPLE_LINE && bc->sampling != WOB_SAMPLE_RIS) return WOB_E_ARG;
   p->ris_c = 0;
   if (bc->sampling == WOB_SAMPLE_RIS) {
@@ -132,6 +140,9 @@ wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void*
   a.lpp_shift = lpp_shift_for(samples, kSolveBlock);
   a.density = bc->density;
   a.ris_c = pl.ris_c;
+  a.mixed_thr = pl.mixed_thr;
+  a.mixed_p = (R)pl.mixed_p;
+  a.mixed_k = (R)pl.mixed_k;
   a.form = pl.form == WOB_F_DOUBLE_LAYER ? wob::F_DL : (pl.form == WOB_F_DIRECT ? wob::F_DIRECT : wob::F_SL);
   return a;
 }

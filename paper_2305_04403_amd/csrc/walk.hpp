@@ -24,6 +24,8 @@ struct WalkArgs {
   int32_t form;               // F_DL / F_DIRECT / F_SL (read by the batched kernel)
   int32_t density;            // estimate the boundary unknown at boundary points (no own emission)
   int32_t ris_c;              // single layer: RIS candidates per vertex, 0 = line sampling
+  uint32_t mixed_thr;         // single layer, Dirichlet vertices: floor(p_k 2^24)
+  R mixed_p, mixed_k;         // p_k (as floor(p_k 2^24) / 2^24) and k
   const R* cv_g;              // control-variate table per caller primitive id (single layer), or null
   const R* cv_g0;             // its line-0 table (the add-back's), set whenever cv_g is
   R* mean_out;
@@ -64,6 +66,17 @@ struct WalkArgs {
 
 enum { ST_NONE = 0, ST_LINE = 1, ST_DONE = 2 };
 
+// Single-layer emission at vertex y on primitive g, before the running
+// weight: 2 phi s(y) on Neumann / Robin parts (Table 1), k u_D(y) on Dirichlet
+// parts (eq. mixed_second_kind_ish); half of it at the last vertex x_M.
+template <typename R, int D>
+__device__ __forceinline__ R sl_emission(const WalkArgs<R, D>& a, const PrimGeo<R>& g, const R n[3],
+                                         const R y[3], bool last_vertex) {
+  const R sv = boundary_datum<R, D>(a.prog, g, n, y);
+  const R e = g.kind == K_DIRICHLET ? a.mixed_k * sv : (R)2 * a.phi * sv;
+  return last_vertex ? (R)0.5 * e : e;
+}
+
 template <typename R, int D>
 struct PathState {
   uint32_t point, path;  // random-number indices
@@ -76,6 +89,7 @@ struct PathState {
   uint32_t z;            // counter word 2 of the current line
   bool first, on_gamma, mixture, last, select;
   bool sum;              // corrected walk: accumulate the all-hits sum of a(h) F(y_h)
+  R gscale;              // single layer: factor of the G kernel (1, or -k / p_k at a Dirichlet vertex)
   PrimGeo<R> gc;         // the primitive the vertex lies on (direct, single layer)
   R nc[3];
   R d[3], inv[3], ox[3];
@@ -122,8 +136,8 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
     R k = 0;
     if (rr > (R)0) {
       const R rho = sqrt(rr);
-      if (s.first) {
-        k = D == 3 ? inv4pi / rho : -inv2pi * log(rho);
+      if (s.gscale != (R)0) {  // first step, or a Dirichlet vertex: the G kernel
+        k = s.gscale * (D == 3 ? inv4pi / rho : -inv2pi * log(rho));
       } else {
         // (y - x) . n_x from the candidate's own vertex and edges: x lies in
         // the plane of its primitive, so (y - x) . n_x = (v0_y - v0_x) . n_x +
@@ -161,8 +175,7 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
   R nn[3];
   load_normal<R, D>(sc, lpick, nn);
   if (TRACE && s.vp) s.vp[s.i] = gn.id;
-  const R sv = boundary_datum<R, D>(a.prog, gn, nn, s.x);
-  s.acc += s.W * ((s.i + 1 < a.M) ? (R)2 * phi : phi) * sv;
+  s.acc += s.W * sl_emission<R, D>(a, gn, nn, s.x, s.i + 1 >= a.M);
   return true;
 }
 
@@ -180,26 +193,47 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     // step 0 from an evaluation point uses the representation formula; in
     // density mode x0 is itself a vertex of the boundary recursion
     s.first = s.i == 0 && !a.density;
+    U4 r0;
+    bool have_r0 = false;
     if constexpr (FORM == F_SL) {
+      // a Dirichlet vertex (mixed problems): the transformed first-kind row
+      // mu = mu - k int G mu + k u_D, one term at a time (eq.
+      // mixed_second_kind_ish_mc): with probability p_k the next point is
+      // sampled from k G (weight -k G / (p p_k)), otherwise the walk stays at x
+      // (weight 1 / (1 - p_k)); the p_k decision is word 3 of block 0
+      const bool dvert = s.on_gamma && !s.first && s.gc.kind == K_DIRICHLET;
+      s.gscale = s.first ? (R)1 : (R)0;
+      if (dvert) {
+        r0 = philox(s.path, s.point, s.z, 0u, a.k0, a.k1);
+        have_r0 = true;
+        if ((r0.w >> 8) >= a.mixed_thr) {
+          s.W *= (R)1 / ((R)1 - a.mixed_p);
+          if (TRACE && s.vp) s.vp[s.i] = -2 - s.gc.id;
+          s.acc += s.W * sl_emission<R, D>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
+          ++s.i;
+          continue;
+        }
+        s.gscale = -a.mixed_k / a.mixed_p;
+      }
       if (a.ris_c > 0) {
         if (!ris_step<R, D, TRACE>(a, s)) return ST_DONE;
         ++s.i;
         continue;
       }
     }
-    const U4 r0 = philox(s.path, s.point, s.z, 0u, a.k0, a.k1);
+    if (!have_r0) r0 = philox(s.path, s.point, s.z, 0u, a.k0, a.k1);
     direction<R, D>(r0.x, r0.y, s.d);
     bool use_self = false;
     s.mixture = false;
     if constexpr (FORM == F_SL) {
-      s.mixture = s.on_gamma && (s.first || s.gc.kind == K_ROBIN);
+      s.mixture = s.on_gamma && (s.gscale != (R)0 || s.gc.kind == K_ROBIN);
       use_self = s.mixture && (r0.z >> 8) < a.self_thr;
     }
     if (use_self) {
       const U4 r1 = philox(s.path, s.point, s.z | 1u, 0u, a.k0, a.k1);
       R y[3];
       const R gp = self_panel<R, D>(s.gc, s.nc, s.x, unit<R>(r1.x), unit<R>(r1.y), y);
-      const R w = (s.first ? gp : (R)-2 * phi * s.gc.alpha * gp) / a.self_p;
+      const R w = (s.gscale != (R)0 ? s.gscale * gp : (R)-2 * phi * s.gc.alpha * gp) / a.self_p;
       if (TRACE && s.vp) s.vp[s.i] = -2 - s.gc.id;
       s.W *= w;
       // control variate, line 0: subtract the line-0 table at the own primitive
@@ -208,8 +242,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
       s.x[1] = y[1];
       s.x[2] = y[2];
       // emission at the new vertex (same primitive)
-      const R sv = boundary_datum<R, D>(a.prog, s.gc, s.nc, s.x);
-      s.acc += s.W * ((s.i + 1 < a.M) ? (R)2 * phi : phi) * sv;
+      s.acc += s.W * sl_emission<R, D>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
       ++s.i;
       continue;
     }
@@ -255,12 +288,15 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
   s.x[0] = s.x0[0];
   s.x[1] = s.x0[1];
   s.x[2] = s.x0[2];
-  if (FORM == F_DL && s.cur_idx >= 0 && !a.density) {
-    // Table 1: on the boundary the Dirichlet solution is the given value
+  if ((FORM == F_DL || FORM == F_SL) && s.cur_idx >= 0 && !a.density) {
+    // Table 1: on the boundary the Dirichlet solution is the given value (also
+    // on the Dirichlet parts of a mixed problem)
     const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
-    const R nz[3] = {0, 0, 0};
-    s.acc = boundary_datum<R, D>(a.prog, g, nz, s.x);
-    return ST_DONE;
+    if (FORM == F_DL || g.kind == K_DIRICHLET) {
+      const R nz[3] = {0, 0, 0};
+      s.acc = boundary_datum<R, D>(a.prog, g, nz, s.x);
+      return ST_DONE;
+    }
   }
   s.W = 1;
   s.acc = 0;
@@ -379,9 +415,9 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     load_normal<R, D>(a.scene, h.idx, ny);
     const R rho = fabs(h.t);
     const R acy = fabs(dot3(s.d, ny));
-    if (s.first) {
-      // G / p
-      w = D == 3 ? mm * rho / ((R)2 * acy) : -mm * rho * log(rho) / ((R)2 * acy);
+    if (s.gscale != (R)0) {
+      // G / p (times -k / p_k at a Dirichlet vertex)
+      w = s.gscale * (D == 3 ? mm * rho / ((R)2 * acy) : -mm * rho * log(rho) / ((R)2 * acy));
     } else {
       const R cx = sgn_t * dot3(s.d, s.nc);
       w = D == 3 ? -phi * mm * (cx + s.gc.alpha * rho) / acy
@@ -404,7 +440,9 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     } else {
       s.acc -= s.W * a.cv_g[gy.id];
     }
-  } else if constexpr (FORM != F_DIRECT) {
+  } else if constexpr (FORM == F_SL) {
+    s.acc += s.W * sl_emission<R, D>(a, gy, ny, s.x, s.i + 1 >= a.M);
+  } else if constexpr (FORM == F_DL) {
     const R sv = boundary_datum<R, D>(a.prog, gy, ny, s.x);
     s.acc += s.W * ((s.i + 1 < a.M) ? (R)2 * phi : phi) * sv;
   }

@@ -186,7 +186,7 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
   wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
   if (s != WOB_OK) return s;
   if (cv_g && (sc->dim != 3 || sc->precision != WOB_F32 || pl.form != WOB_F_SINGLE_LAYER ||
-               bc->density || pl.ris_c > 0))
+               bc->density || pl.ris_c > 0 || sc->n_dirichlet > 0))
     return WOB_E_UNSUPPORTED;
   if (n_points < 0 || (n_points > 0 && !points)) return WOB_E_ARG;
   if (n_points >= (int64_t)1 << 32) return WOB_E_ARG;  // point index is a 32-bit counter word
@@ -434,7 +434,7 @@ wob_status wob_cv_emission(wob_scene sc, const wob_bc* bc, const float* g, float
   Plan pl;
   wob_status s = plan_walk(sc, bc, 2, 2, &pl);
   if (s != WOB_OK) return s;
-  if (pl.form != WOB_F_SINGLE_LAYER || bc->density) return WOB_E_UNSUPPORTED;
+  if (pl.form != WOB_F_SINGLE_LAYER || bc->density || sc->n_dirichlet > 0) return WOB_E_UNSUPPORTED;
   const auto a = make_args<float, 3>(sc, pl, nullptr, nullptr, 0, bc, 2, 2, 0);
   hipLaunchKernelGGL((wob::emission_table_kernel<float>), dim3((unsigned)((sc->n_prims + 255) / 256)),
                      dim3(256), 0, (hipStream_t)stream, view<float, 3>(sc), a.prog, a.phi, g, g0_out);

@@ -39,7 +39,8 @@ class WobError(RuntimeError):
 class _BC(C.Structure):
     _fields_ = [("domain", C.c_int32), ("formulation", C.c_int32), ("program", C.c_int32),
                 ("density", C.c_int32), ("sampling", C.c_int32), ("candidates", C.c_int32),
-                ("params", C.c_double * 8), ("self_panel_p", C.c_double)]
+                ("params", C.c_double * 8), ("self_panel_p", C.c_double), ("mixed_k", C.c_double),
+                ("mixed_p", C.c_double)]
 
 
 class _SceneInfo(C.Structure):
@@ -151,12 +152,15 @@ class BC:
     density: bool = False
     sampling: int = 0             # SAMPLE_LINE or SAMPLE_RIS (single layer)
     candidates: int = 0           # RIS candidates (0 = 16)
+    mixed_k: float = 0.0          # Dirichlet parts of the single layer: k (0 = 4)
+    mixed_p: float = 0.0          # and p_k (0 = 2/3)
 
     def c(self) -> _BC:
         b = _BC()
         b.domain, b.formulation, b.program = self.domain, self.formulation, self.program
         b.density = int(bool(self.density))
         b.sampling, b.candidates = int(self.sampling), int(self.candidates)
+        b.mixed_k, b.mixed_p = float(self.mixed_k), float(self.mixed_p)
         for i, v in enumerate(self.params):
             b.params[i] = float(v)
         b.self_panel_p = float(self.self_panel_p)

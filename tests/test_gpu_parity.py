@@ -181,6 +181,29 @@ def test_trace_parity_single_layer_ris_2d_f64(W):
     run_trace_parity(W, mesh, pts, None, bc, 64, 3, 2, "f64")
 
 
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_trace_parity_mixed_tori(W, sampling):
+    """Mixed problem on the tori union: every triangle Dirichlet, Neumann or
+    Robin (alpha = 1) at random, single layer with the transformed first-kind
+    rows on the Dirichlet parts (k = 4, p_k = 2/3), points off and on the
+    boundary; line sampling and RIS."""
+    w = I.config_tori(grid_n=20, n_points=80, boundary_frac=0.25, samples=64, walk_len=4)
+    kind = np.random.default_rng(5).integers(0, 3, w.mesh.n_prims).astype(np.uint8)
+    mesh = I.Mesh(3, w.mesh.verts, w.mesh.prims, kind, np.full(w.mesh.n_prims, 1.0))
+    bc = dict(w.bc, formulation=0, sampling=sampling, candidates=16)
+    run_trace_parity(W, mesh, w.points, w.point_prim, bc, 64, 4, 19, "f32", max_vertex_mismatch_frac=0.002)
+
+
+def test_trace_parity_mixed_2d_f64(W):
+    """2D interior mixed problem (random Dirichlet / Neumann / Robin segments) in FP64."""
+    c = I.circle_polygon(128)
+    kind = np.random.default_rng(1).integers(0, 3, 128).astype(np.uint8)
+    mesh = I.Mesh(2, c.verts, c.prims, kind, np.full(128, 1.0))
+    pts = I.disk_points(40, 0.8, 4)
+    bc = dict(domain=1, formulation=0, program=2, params=())
+    run_trace_parity(W, mesh, pts, None, bc, 64, 4, 8, "f64")
+
+
 def test_ris_arguments(W):
     mesh = PT.f32_mesh(I.icosphere(4))
     scene = W.Scene(mesh, W.F32)
@@ -310,11 +333,16 @@ def test_edge_cases(W):
     torch.cuda.synchronize()
     mm = m.cpu().numpy()
     assert np.isnan(mm[2]) and np.isnan(mm[3]) and np.isfinite(mm[1])
-    # Dirichlet mixed with Neumann is not supported
+    # Dirichlet mixed with Neumann: the single layer (AUTO) solves it, the double
+    # layer and the direct BIE do not
     mixed = I.Mesh(3, mesh.verts, mesh.prims, np.array([0, 1] * (mesh.n_prims // 2), np.uint8))
     s2 = W.Scene(mixed, W.F32)
-    with pytest.raises(W.WobError):
-        W.solve(s2, pts, bc, 8, 2)
+    m, _ = W.solve(s2, pts, bc, 8, 2)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(m.cpu().numpy()))
+    for f in (W.DOUBLE_LAYER, W.DIRECT):
+        with pytest.raises(W.WobError):
+            W.solve(s2, pts, W.BC(1, f, W.PROG_CONST, (1.0,)), 8, 2)
     s2.close()
     scene.close()
 
