@@ -78,6 +78,12 @@ def lib():
         _lib.orc_trace_cv.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, vp,
                                       vp, C.c_int64, vp, vp, vp, C.c_int]
         _lib.orc_trace_cv.restype = C.c_int
+        _lib.orc_forward_paths.argtypes = [vp, vp, vp, C.c_int64, C.c_int, C.c_uint64, C.c_uint32, vp,
+                                           C.c_int]
+        _lib.orc_forward_paths.restype = C.c_int
+        _lib.orc_forward_gather.argtypes = [C.c_int, C.c_int64, C.c_int, vp, vp, vp, C.c_int64, vp, vp,
+                                            vp, C.c_int]
+        _lib.orc_forward_gather.restype = C.c_int
         _lib.orc_mlp_n_params.argtypes = [C.c_int, C.c_int, C.c_int]
         _lib.orc_mlp_n_params.restype = C.c_int64
         _lib.orc_mlp_forward.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, vp,
@@ -201,6 +207,48 @@ def solve(mesh: OracleMesh, points: np.ndarray, point_prim: Optional[np.ndarray]
     if rc != 0:
         raise ValueError("orc_solve rejected its arguments")
     return mean, var
+
+
+class _ForwardOut(C.Structure):
+    _fields_ = [("vtx_pos", C.c_void_p), ("vtx_w", C.c_void_p), ("vtx_prim", C.c_void_p),
+                ("vtx_m", C.c_void_p), ("graze", C.c_void_p), ("cond_cos", C.c_void_p)]
+
+
+def forward_paths(mesh: OracleMesh, bc: _BC, n_paths: int, walk_len: int, seed: int,
+                  start_weight: Optional[np.ndarray] = None, problem: int = 0,
+                  n_threads: int = 0) -> dict:
+    """Forward (adjoint) single-layer paths from the boundary (all-Neumann
+    meshes): per path and vertex the position, primitive, hit count and source
+    strength; per path the grazing margin and smallest |cos| of a sampled hit."""
+    M = int(walk_len)
+    sw = None if start_weight is None else np.ascontiguousarray(start_weight, dtype=np.float64)
+    out = {"pos": np.zeros((n_paths, M, mesh.dim)), "w": np.zeros((n_paths, M)),
+           "prim": np.zeros((n_paths, M), dtype=np.int32), "m": np.zeros((n_paths, M), dtype=np.int32),
+           "graze": np.zeros(n_paths), "cond_cos": np.zeros(n_paths)}
+    t = _ForwardOut(_ptr(out["pos"]), _ptr(out["w"]), _ptr(out["prim"]), _ptr(out["m"]),
+                    _ptr(out["graze"]), _ptr(out["cond_cos"]))
+    rc = lib().orc_forward_paths(mesh.ref, C.byref(bc), _ptr(sw), C.c_int64(n_paths), C.c_int(M),
+                                 C.c_uint64(seed), C.c_uint32(problem), C.byref(t), C.c_int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_forward_paths rejected its arguments")
+    return out
+
+
+def forward_gather(pos: np.ndarray, w: np.ndarray, points: np.ndarray, n_threads: int = 0):
+    """Mean, variance over paths and magnitude scale of the connection of every
+    point to every forward-path vertex (pos: (n_paths, M, dim), w: (n_paths, M))."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n_paths, M, dim = pos.shape
+    P = pts.shape[0]
+    mean, var, sabs = np.zeros(P), np.zeros(P), np.zeros(P)
+    rc = lib().orc_forward_gather(C.c_int(dim), C.c_int64(n_paths), C.c_int(M), _ptr(pos), _ptr(w),
+                                  _ptr(pts), C.c_int64(P), _ptr(mean), _ptr(var), _ptr(sabs),
+                                  C.c_int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_forward_gather rejected its arguments")
+    return mean, var, sabs
 
 
 def intersect_all(mesh: OracleMesh, orig: np.ndarray, dirs: np.ndarray,

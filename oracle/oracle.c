@@ -938,6 +938,204 @@ int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim
   return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Forward (adjoint) estimator of the single layer on Neumann boundaries     */
+/* (Sec. 4.4 "Forward estimator"; Table 1, single-layer Neumann rows).        */
+/*                                                                           */
+/* The single layer writes u(x) = int G(x, y) mu(y) dA with mu = f + K mu,    */
+/* f = 2 phi q and K(x, y) = -2 phi dG/dn_x(x, y).  Truncated with the halved  */
+/* last term (Sec. 4.1.2) the estimate is                                    */
+/*     u(x) ~ sum_{j < M} c_j < G(x, .), K^j f >,   c = (1, ..., 1, 1/2).     */
+/* The backward walk samples these integrals from x outwards.  The forward    */
+/* walk samples the same sum from the data towards x: y_1 is drawn on the      */
+/* boundary with density p_0 and carries W_1 = f(y_1) / p_0(y_1); y_{k+1} is  */
+/* the picked hit of a uniformly random line through y_k and carries           */
+/* W_{k+1} = W_k K(y_{k+1}, y_k) / p(y_{k+1} | y_k), the kernel read with its   */
+/* arguments swapped (its normal derivative now acts at the sampled point,     */
+/* whose |cos| the line density contains).  Then E[W_k h(y_k)] =              */
+/* < K^{k-1} f, h > for every h, and vertex k of a path is a source of         */
+/* strength c_{k-1} W_k at y_k that every evaluation point connects to:        */
+/*     u(x) ~ (1 / n_paths) sum_paths sum_k c_{k-1} W_k G(x, y_k).             */
+/*                                                                           */
+/* Start density: primitive T with probability P_T from a binary32 cumulative  */
+/* table of caller weights w_T in id order (binary64 running sum, rounded      */
+/* once; P_T = cdf_T - cdf_{T-1} evaluated in binary64), then uniform in T, so */
+/* p_0 = P_T / A_T.  Weights proportional to |q| A_T place the starts where    */
+/* the data are large (the boundary sampling by the magnitude of the boundary  */
+/* value in the paper's Neumann example); NULL means w_T = A_T.                */
+/*                                                                           */
+/* Random numbers of path j (point word 0xfffffffe):                          */
+/*   start  (j, 0xfffffffe, (problem << 24) | 0xffff03, 0): word 0 the         */
+/*          primitive (binary32 uniform against the table), words 1, 2 the    */
+/*          point (reflected into the triangle when a + b > 1);                */
+/*   line i (from y_{i+1}): blocks 0 and 2 exactly as in the backward walk.    */
+/* ------------------------------------------------------------------------- */
+#define ORC_FWD_POINT 0xfffffffeu
+
+static int all_neumann(const orc_mesh* m) {
+  if (!m->kind) return 0;
+  for (int64_t j = 0; j < m->n_prims; ++j)
+    if (m->kind[j] != ORC_NEUMANN) return 0;
+  return 1;
+}
+
+int orc_forward_paths(const orc_mesh* m, const orc_bc* bc, const double* start_weight,
+                      int64_t n_paths, int walk_len, uint64_t seed, uint32_t problem,
+                      orc_forward_out* out, int n_threads) {
+  if (!m || !bc || !out || m->dim < 2 || m->dim > 3 || m->n_prims <= 0 || walk_len < 1 ||
+      walk_len >= 65535 || n_paths < 0)
+    return 1;
+  if (bc->domain != 1 && bc->domain != -1) return 1;
+  if (!all_neumann(m)) return 1;
+  const int dim = m->dim, M = walk_len;
+  const double phi = (double)bc->domain;
+  /* start table */
+  float* cdf = (float*)malloc(sizeof(float) * (size_t)m->n_prims);
+  double tot = 0.0;
+  for (int64_t j = 0; j < m->n_prims; ++j) {
+    const double w = start_weight ? start_weight[j] : prim_area(m, j);
+    if (!(w >= 0.0) || !isfinite(w)) {
+      free(cdf);
+      return 1;
+    }
+    tot += w;
+  }
+  if (!(tot > 0.0)) {
+    free(cdf);
+    return 1;
+  }
+  double run = 0.0;
+  for (int64_t j = 0; j < m->n_prims; ++j) {
+    run += start_weight ? start_weight[j] : prim_area(m, j);
+    cdf[j] = (float)(run / tot);
+  }
+  cdf[m->n_prims - 1] = 1.0f;
+  area_table st = {cdf, tot};
+  double* normals = make_normals(m);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t p = 0; p < n_paths; ++p) {
+    const uint32_t path = (uint32_t)p;
+    double* pos = out->vtx_pos ? out->vtx_pos + p * M * dim : NULL;
+    for (int k = 0; k < M; ++k) {
+      if (out->vtx_w) out->vtx_w[p * M + k] = 0.0;
+      if (out->vtx_prim) out->vtx_prim[p * M + k] = -1;
+      if (out->vtx_m) out->vtx_m[p * M + k] = 0;
+      if (pos)
+        for (int a = 0; a < dim; ++a) pos[k * dim + a] = 0.0;
+    }
+    double graze = INFINITY, cond = INFINITY;
+    /* y_1 ~ p_0 */
+    uint32_t r[4];
+    draw(seed, path, ORC_FWD_POINT, problem, 0xffffu, 3u, 0u, r);
+    const int64_t T = area_pick(&st, m->n_prims, (float)uniform(r[0]));
+    double a = uniform(r[1]), b = dim == 3 ? uniform(r[2]) : 0.0;
+    if (a + b > 1.0) {
+      a = 1.0 - a;
+      b = 1.0 - b;
+    }
+    double v0[3], v1[3], v2[3] = {0.0, 0.0, 0.0}, x[3] = {0.0, 0.0, 0.0};
+    prim_vertex(m, T, 0, v0);
+    prim_vertex(m, T, 1, v1);
+    if (dim == 3) prim_vertex(m, T, 2, v2);
+    for (int c = 0; c < dim; ++c) x[c] = v0[c] + a * (v1[c] - v0[c]) + b * (v2[c] - v0[c]);
+    const double P_T = (double)cdf[T] - (T > 0 ? (double)cdf[T - 1] : 0.0);
+    const double p0 = P_T / prim_area(m, T);
+    double W = 2.0 * phi * orc_boundary_datum(m, bc, T, x) / p0;
+    int64_t cur = T;
+    for (int k = 0; k < M; ++k) {
+      if (k > 0) {
+        /* line k - 1 from y_k */
+        uint32_t r0[4];
+        draw(seed, path, ORC_FWD_POINT, problem, (uint32_t)(k - 1), 0u, 0u, r0);
+        double d[3] = {0.0, 0.0, 0.0};
+        if (dim == 3) {
+          double z = 1.0 - 2.0 * uniform(r0[0]);
+          double s = sqrt(fmax(0.0, 1.0 - z * z));
+          double ph = 2.0 * ORC_PI * uniform(r0[1]);
+          d[0] = s * cos(ph);
+          d[1] = s * sin(ph);
+          d[2] = z;
+        } else {
+          double th = 2.0 * ORC_PI * uniform(r0[0]);
+          d[0] = cos(th);
+          d[1] = sin(th);
+        }
+        line_hits h;
+        all_hits(m, normals, bc, 0, 1, x, d, cur, seed, path, ORC_FWD_POINT, problem,
+                 (uint32_t)(k - 1), &h);
+        if (h.graze < graze) graze = h.graze;
+        if (out->vtx_m) out->vtx_m[p * M + k] = h.m;
+        if (h.m == 0) break;
+        const double* ny = normals + 3 * h.sel;
+        /* K(y_{k+1}, y_k) / p(y_{k+1} | y_k) */
+        const double kern = -2.0 * phi * dG_dnx(h.sel_y, x, ny, dim);
+        const double pdf = line_pdf(x, h.sel_y, ny, h.m, dim);
+        {
+          double rr[3] = {h.sel_y[0] - x[0], h.sel_y[1] - x[1], dim == 3 ? h.sel_y[2] - x[2] : 0.0};
+          const double c = fabs(dot(rr, ny, dim)) / sqrt(dot(rr, rr, dim));
+          if (c < cond) cond = c;
+        }
+        W *= kern / pdf;
+        memcpy(x, h.sel_y, sizeof(x));
+        cur = h.sel;
+      }
+      if (out->vtx_w) out->vtx_w[p * M + k] = (k + 1 < M ? 1.0 : 0.5) * W;
+      if (out->vtx_prim) out->vtx_prim[p * M + k] = (int32_t)cur;
+      if (pos)
+        for (int c = 0; c < dim; ++c) pos[k * dim + c] = x[c];
+    }
+    if (out->graze) out->graze[p] = graze;
+    if (out->cond_cos) out->cond_cos[p] = cond;
+  }
+  free(normals);
+  free(cdf);
+  return 0;
+}
+
+/* Connection of every evaluation point to every vertex of the forward paths:
+ * per point, the per-path values c_j(x) = sum_k w_jk G(x, y_jk) (a vertex at
+ * distance zero contributes nothing), their mean over the n_paths paths and
+ * unbiased variance, and the sum of |w G| / n_paths (the rounding scale). */
+int orc_forward_gather(int dim, int64_t n_paths, int walk_len, const double* vtx_pos,
+                       const double* vtx_w, const double* points, int64_t n_points,
+                       double* mean_out, double* var_out, double* abs_out, int n_threads) {
+  if ((dim != 2 && dim != 3) || n_paths < 1 || walk_len < 1 || n_points < 0) return 1;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+  for (int64_t p = 0; p < n_points; ++p) {
+    const double* x = points + p * dim;
+    double* cj = (double*)malloc(sizeof(double) * (size_t)n_paths);
+    double sum = 0.0, sabs = 0.0;
+    for (int64_t j = 0; j < n_paths; ++j) {
+      double c = 0.0;
+      for (int k = 0; k < walk_len; ++k) {
+        const double* y = vtx_pos + (j * walk_len + k) * dim;
+        const double w = vtx_w[j * walk_len + k];
+        double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+        if (w == 0.0 || dot(r, r, dim) == 0.0) continue;
+        const double t = w * G(x, y, dim);
+        c += t;
+        sabs += fabs(w) * G_mag(x, y, dim);
+      }
+      cj[j] = c;
+      sum += c;
+    }
+    const double mean = sum / (double)n_paths;
+    double ss = 0.0;
+    for (int64_t j = 0; j < n_paths; ++j) ss += (cj[j] - mean) * (cj[j] - mean);
+    free(cj);
+    mean_out[p] = mean;
+    if (var_out) var_out[p] = n_paths > 1 ? ss / (double)(n_paths - 1) : 0.0;
+    if (abs_out) abs_out[p] = sabs / (double)n_paths;
+  }
+  return 0;
+}
+
 int orc_intersect_all(const orc_mesh* m, const double* orig, const double* dir,
                       const int32_t* exclude, int64_t n_lines, int max_hits, int32_t* n_hits,
                       int32_t* hit_prim, double* hit_t, double* hit_margin, double* line_graze,

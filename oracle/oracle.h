@@ -151,6 +151,31 @@ int orc_trace_cv(const orc_mesh* mesh, const double* points, const int32_t* poin
 int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points, int64_t n_points,
                    uint32_t seed, int randomized, double* out, int n_threads);
 
+/* Forward (adjoint) estimator of the single layer, all-Neumann boundary
+ * (Sec. 4.4 "Forward estimator"; see oracle.c for the derivation and the
+ * random-number layout).  orc_forward_paths writes, per path and vertex
+ * k = 1..M, the vertex y_k, its primitive, the hits of the line that reached
+ * it (0 for k = 1) and its source strength c_{k-1} W_k (0 and prim -1 once the
+ * path has ended).  start_weight: per-primitive start weights w_T >= 0 in id
+ * order (sum > 0), or NULL for area-uniform starts. */
+typedef struct {
+  double* vtx_pos;         /* [n_paths * M * dim] */
+  double* vtx_w;           /* [n_paths * M] */
+  int32_t* vtx_prim;       /* [n_paths * M] */
+  int32_t* vtx_m;          /* [n_paths * M] */
+  double* graze;           /* [n_paths] min over lines of |barycentric margin|*|cos| */
+  double* cond_cos;        /* [n_paths] smallest |cos theta| at a sampled hit (its sign sets
+                              the weight) */
+} orc_forward_out;
+int orc_forward_paths(const orc_mesh* mesh, const orc_bc* bc, const double* start_weight,
+                      int64_t n_paths, int walk_len, uint64_t seed, uint32_t problem,
+                      orc_forward_out* out, int n_threads);
+/* u(x_p) ~ (1 / n_paths) sum_paths sum_k w_k G(x_p, y_k): mean, unbiased variance
+ * over paths, and the magnitude sum (1 / n_paths) sum |w_k| |G| (rounding scale). */
+int orc_forward_gather(int dim, int64_t n_paths, int walk_len, const double* vtx_pos,
+                       const double* vtx_w, const double* points, int64_t n_points,
+                       double* mean_out, double* var_out, double* abs_out, int n_threads);
+
 /* Unit outward normal of a primitive. */
 void orc_prim_normal(const orc_mesh* mesh, int64_t prim, double* n_out);
 
