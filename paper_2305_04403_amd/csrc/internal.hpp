@@ -143,7 +143,10 @@ wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void*
   a.mixed_thr = pl.mixed_thr;
   a.mixed_p = (R)pl.mixed_p;
   a.mixed_k = (R)pl.mixed_k;
-  a.form = pl.form == WOB_F_DOUBLE_LAYER ? wob::F_DL : (pl.form == WOB_F_DIRECT ? wob::F_DIRECT : wob::F_SL);
+  a.form = pl.form == WOB_F_DOUBLE_LAYER ? wob::F_DL
+           : pl.form == WOB_F_DIRECT    ? wob::F_DIRECT
+           : pl.ris_c > 0               ? wob::F_SL_RIS
+                                        : wob::F_SL;
   return a;
 }
 

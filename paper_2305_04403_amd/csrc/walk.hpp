@@ -21,7 +21,7 @@ struct WalkArgs {
   uint32_t k0, k1;            // Philox key
   uint32_t problem;           // problem index (counter word 2, bits 24..31)
   int32_t lpp_shift;          // log2 of lanes per point (0 .. log2 of the block size)
-  int32_t form;               // F_DL / F_DIRECT / F_SL (read by the batched kernel)
+  int32_t form;               // F_DL / F_DIRECT / F_SL / F_SL_RIS (read by the batched kernel)
   int32_t density;            // estimate the boundary unknown at boundary points (no own emission)
   int32_t ris_c;              // single layer: RIS candidates per vertex, 0 = line sampling
   uint32_t mixed_thr;         // single layer, Dirichlet vertices: floor(p_k 2^24)
@@ -193,9 +193,19 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     // step 0 from an evaluation point uses the representation formula; in
     // density mode x0 is itself a vertex of the boundary recursion
     s.first = s.i == 0 && !a.density;
+    if constexpr (is_sl(FORM)) {
+      // Table 1: on a Dirichlet part the solution is the given value (tested
+      // here, where the primitive is loaded anyway, rather than in start_path:
+      // a second load there costs the single-layer kernel ~35 registers)
+      if (s.first && s.on_gamma && s.gc.kind == K_DIRICHLET) {
+        const R nz[3] = {0, 0, 0};
+        s.acc = boundary_datum<R, D>(a.prog, s.gc, nz, s.x);
+        return ST_DONE;
+      }
+    }
     U4 r0;
     bool have_r0 = false;
-    if constexpr (FORM == F_SL) {
+    if constexpr (is_sl(FORM)) {
       // a Dirichlet vertex (mixed problems): the transformed first-kind row
       // mu = mu - k int G mu + k u_D, one term at a time (eq.
       // mixed_second_kind_ish_mc): with probability p_k the next point is
@@ -215,7 +225,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
         }
         s.gscale = -a.mixed_k / a.mixed_p;
       }
-      if (a.ris_c > 0) {
+      if constexpr (FORM == F_SL_RIS) {
         if (!ris_step<R, D, TRACE>(a, s)) return ST_DONE;
         ++s.i;
         continue;
@@ -225,7 +235,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     direction<R, D>(r0.x, r0.y, s.d);
     bool use_self = false;
     s.mixture = false;
-    if constexpr (FORM == F_SL) {
+    if constexpr (is_sl(FORM)) {
       s.mixture = s.on_gamma && (s.gscale != (R)0 || s.gc.kind == K_ROBIN);
       use_self = s.mixture && (r0.z >> 8) < a.self_thr;
     }
@@ -288,15 +298,12 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
   s.x[0] = s.x0[0];
   s.x[1] = s.x0[1];
   s.x[2] = s.x0[2];
-  if ((FORM == F_DL || FORM == F_SL) && s.cur_idx >= 0 && !a.density) {
-    // Table 1: on the boundary the Dirichlet solution is the given value (also
-    // on the Dirichlet parts of a mixed problem)
+  if (FORM == F_DL && s.cur_idx >= 0 && !a.density) {
+    // Table 1: on the boundary the Dirichlet solution is the given value
     const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
-    if (FORM == F_DL || g.kind == K_DIRICHLET) {
-      const R nz[3] = {0, 0, 0};
-      s.acc = boundary_datum<R, D>(a.prog, g, nz, s.x);
-      return ST_DONE;
-    }
+    const R nz[3] = {0, 0, 0};
+    s.acc = boundary_datum<R, D>(a.prog, g, nz, s.x);
+    return ST_DONE;
   }
   s.W = 1;
   s.acc = 0;
@@ -440,7 +447,7 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     } else {
       s.acc -= s.W * a.cv_g[gy.id];
     }
-  } else if constexpr (FORM == F_SL) {
+  } else if constexpr (is_sl(FORM)) {
     s.acc += s.W * sl_emission<R, D>(a, gy, ny, s.x, s.i + 1 >= a.M);
   } else if constexpr (FORM == F_DL) {
     const R sv = boundary_datum<R, D>(a.prog, gy, ny, s.x);
@@ -830,6 +837,7 @@ __global__ void __launch_bounds__(BLOCK) batch_kernel(const WalkArgs<R, D>* __re
     const int form = __builtin_amdgcn_readfirstlane(a.form);
     if (form == F_DL) walk_block<R, D, F_DL, false, false, BLOCK>(a, local, red);
     else if (form == F_DIRECT) walk_block<R, D, F_DIRECT, false, false, BLOCK>(a, local, red);
+    else if (form == F_SL_RIS) walk_block<R, D, F_SL_RIS, false, false, BLOCK>(a, local, red);
     else walk_block<R, D, F_SL, false, false, BLOCK>(a, local, red);
   }
 }

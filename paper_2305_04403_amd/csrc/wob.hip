@@ -171,9 +171,10 @@ void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
 }
 
 template <typename R, int D>
-void launch_walk(const wob::WalkArgs<R, D>& a, int form, int mode, hipStream_t st) {
-  if (form == WOB_F_DOUBLE_LAYER) launch_form<R, D, wob::F_DL>(a, mode, st);
-  else if (form == WOB_F_DIRECT) launch_form<R, D, wob::F_DIRECT>(a, mode, st);
+void launch_walk(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
+  if (a.form == wob::F_DL) launch_form<R, D, wob::F_DL>(a, mode, st);
+  else if (a.form == wob::F_DIRECT) launch_form<R, D, wob::F_DIRECT>(a, mode, st);
+  else if (a.form == wob::F_SL_RIS) launch_form<R, D, wob::F_SL_RIS>(a, mode, st);
   else launch_form<R, D, wob::F_SL>(a, mode, st);
 }
 
@@ -204,13 +205,13 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
       a.point_ids = point_ids;
       a.cv_g = cv_g;
       a.cv_g0 = cv_g0 ? cv_g0 : cv_g;
-      launch_walk<float, 3>(a, pl.form, mode, st);
+      launch_walk<float, 3>(a, mode, st);
     } else {
       auto a = make_args<float, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
       a.mean_out = (float*)mean_out; a.var_out = (float*)var_out; a.path_out = (float*)path_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
-      launch_walk<float, 2>(a, pl.form, mode, st);
+      launch_walk<float, 2>(a, mode, st);
     }
   } else {
     if (sc->dim == 3) {
@@ -218,13 +219,13 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
       a.mean_out = (double*)mean_out; a.var_out = (double*)var_out; a.path_out = (double*)path_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
-      launch_walk<double, 3>(a, pl.form, mode, st);
+      launch_walk<double, 3>(a, mode, st);
     } else {
       auto a = make_args<double, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
       a.mean_out = (double*)mean_out; a.var_out = (double*)var_out; a.path_out = (double*)path_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
-      launch_walk<double, 2>(a, pl.form, mode, st);
+      launch_walk<double, 2>(a, mode, st);
     }
   }
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;

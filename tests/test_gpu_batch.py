@@ -68,6 +68,38 @@ def test_batch_equals_single_solves_and_replays(W):
         b.close()
 
 
+def test_batch_single_layer_forms_equal_single_solves(W):
+    """A batch holding every kernel form (double layer, direct BIE, single
+    layer with line sampling and with RIS, on a mixed Dirichlet / Neumann /
+    Robin mesh, points off and on the boundary) equals the single solves."""
+    w = I.config_tori(grid_n=12, n_points=200, boundary_frac=0.25, samples=64, walk_len=4)
+    kind = np.random.default_rng(3).integers(0, 3, w.mesh.n_prims).astype(np.uint8)
+    mixed = PT.f32_mesh(I.Mesh(3, w.mesh.verts, w.mesh.prims, kind, np.full(w.mesh.n_prims, 1.0)))
+    sm = W.Scene(mixed, W.F32)
+    pm = dev(PT.f32(w.points), torch.float32)
+    pp = torch.as_tensor(w.point_prim, dtype=torch.int32, device="cuda")
+    base = small_problems(W)
+    probs = [base[0], base[2]]
+    for k, (sampling, N) in enumerate(((W.SAMPLE_LINE, 64), (W.SAMPLE_RIS, 96))):
+        bc = W.BC(-1, 0, W.PROG_INVDIST, (0.2, -0.1, 0.05), sampling=sampling, candidates=8)
+        probs.append(dict(scene=sm, points=pm, point_prim=pp, bc=bc, samples=N, walk_len=3, seed=40 + k))
+    ref = [W.solve(p["scene"], p["points"], p["bc"], p["samples"], p["walk_len"], p["seed"],
+                   point_prim=p.get("point_prim")) for p in probs]
+    torch.cuda.synchronize()
+    for tune in ((128, 2), (256, 1)):
+        b = W.Batch(probs, tune=tune)
+        for rep in range(2):
+            outs = b.launch()
+            torch.cuda.synchronize()
+            for i, ((m, v), (mr, vr)) in enumerate(zip(outs, ref)):
+                assert torch.isfinite(mr).all(), i
+                assert torch.equal(m, mr), (tune, rep, i)
+                assert torch.equal(v, vr), (tune, rep, i)
+            for o in outs:
+                o[0].fill_(float("nan"))
+        b.close()
+
+
 def test_batch_stream_id_follows_oracle(W):
     """A problem with stream_id q draws the counter field 'problem' = q: its mean
     equals the oracle's mean over the same paths (FP32 vs FP64)."""
