@@ -19,7 +19,11 @@ Two more legs are reported in the same line (each with its own timing):
   cv        - exterior Neumann / Robin single layer on a 200,992-triangle
               union of three tori, 1M points: RMSE against the analytic
               solution at equal wall time, plain WoB with 512 paths against
-              the learned control variate (fit + corrected solve).
+              the learned control variate (fit + corrected solve);
+  forward   - exterior Neumann data concentrated near one spot of the same
+              tori: the forward (adjoint) estimator with every point connected
+              to every path vertex against the backward walks at equal wall
+              time, and the throughput of its two kernels.
 """
 import argparse
 import json
@@ -80,8 +84,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--cpu-sample-points", type=int, default=640)
     p.add_argument("--skip-cpu-baseline", action="store_true")
-    p.add_argument("--legs", default="main,batched,cv",
-                   help="comma-separated subset of main, batched, cv")
+    p.add_argument("--legs", default="main,batched,cv,forward",
+                   help="comma-separated subset of main, batched, cv, forward")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device once (a kernel of known "
                         "traffic that calibrates hardware byte counters)")
@@ -273,6 +277,109 @@ def cv_leg(torch, wob, I):
     return out
 
 
+# connection of a point to a forward-path vertex: 3 differences, 3 products and
+# 2 sums for rho^2, one reciprocal square root, one multiply-add = 11
+GATHER_PAIR_FLOP = 11
+
+
+def forward_leg(torch, wob, I):
+    """Forward (adjoint) single-layer estimator with path reuse against the
+    backward walks, exterior Neumann data concentrated near one spot of the
+    three-tori union (source 0.05 below the surface), 1M points off the
+    boundary, M = 4, FP32: RMSE against the analytic solution at equal wall
+    time (3 seeds pooled), the backward direct BIE at 512 paths per point
+    setting the time; forward paths started uniformly by area and by the
+    magnitude of the data; plus the throughput of the forward path kernel and
+    of the connection kernel."""
+    import math
+    w = I.config_tori_neumann()
+    scene = wob.Scene(w.mesh, wob.F32)
+    xs = tuple(w.bc["params"])
+    bc_direct = wob.BC(-1, wob.AUTO, wob.PROG_INVDIST, xs)
+    bc_sl = wob.BC(-1, wob.SINGLE_LAYER, wob.PROG_INVDIST, xs)
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device="cuda")
+    M, N = w.walk_len, w.samples
+    ex = w.exact
+    sync = torch.cuda.synchronize
+    seeds = (21, 22, 23)
+    starts_q = wob.Starts(scene, data=bc_sl, floor=0.05)
+    # warm every kernel on small inputs
+    wob.solve(scene, pts[:4096].contiguous(), bc_direct, 16, M)
+    wob.solve(scene, pts[:4096].contiguous(), bc_sl, 16, M)
+    v, _, _ = wob.forward_paths(scene, bc_sl, 4096, M, 1)
+    wob.forward_gather(scene, v, pts[:4096].contiguous())
+    sync()
+
+    def pooled(ms):
+        mse = [np.mean((m.double().cpu().numpy() - ex) ** 2) for m in ms]
+        med = [np.median(np.abs(m.double().cpu().numpy() - ex)) for m in ms]
+        return math.sqrt(float(np.mean(mse))), float(np.mean(med)), [math.sqrt(float(x)) for x in mse]
+
+    out = {"workload": w.name + ", 1M points off the boundary, M=4", "seeds": len(seeds)}
+    t_ref = None
+    for name, bc in (("backward_direct", bc_direct), ("backward_single_layer", bc_sl)):
+        ms, tm = [], []
+        for sd in seeds:
+            t0 = time.perf_counter()
+            m, _ = wob.solve(scene, pts, bc, N, M, seed=sd, want_var=False)
+            sync()
+            tm.append(time.perf_counter() - t0)
+            ms.append(m)
+        r, e, ps = pooled(ms)
+        out[name] = {"paths": N, "seconds": float(np.mean(tm)), "rmse": r, "rmse_per_seed": ps,
+                     "median_abs_err": e}
+        if t_ref is None:
+            t_ref = float(np.mean(tm))
+
+    # kernel throughput: 2^20 forward paths, and the connection of every point
+    n_probe = 1 << 20
+    vtx = torch.empty((n_probe, M, 4), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record(st)
+    wob.forward_paths(scene, bc_sl, n_probe, M, 7, starts=starts_q, out=vtx)
+    e[1].record(st)
+    n_g = 1 << 16
+    mean = torch.empty(pts.shape[0], dtype=torch.float32, device="cuda")
+    var = torch.empty_like(mean)
+    e[2].record(st)
+    wob.forward_gather(scene, vtx[:n_g], pts, out=(mean, var))
+    e[3].record(st)
+    sync()
+    t_paths = 1e-3 * e[0].elapsed_time(e[1])
+    t_gather = 1e-3 * e[2].elapsed_time(e[3])
+    pairs = pts.shape[0] * n_g * M
+    out["paths_kernel"] = {"paths": n_probe, "ms": 1e3 * t_paths, "path_samples_per_s": n_probe / t_paths,
+                           "lines_per_s": n_probe * (M - 1) / t_paths}
+    gf = pairs * GATHER_PAIR_FLOP / t_gather / 1e12
+    out["gather_kernel"] = {"points": int(pts.shape[0]), "paths": n_g, "vertices": n_g * M, "ms": 1e3 * t_gather,
+                            "pairs_per_s": pairs / t_gather,
+                            "roofline": {"bound": "alu", "achieved": gf, "peak": FP32_PEAK_TFLOPS,
+                                         "unit": "TFLOP/s", "frac": gf / FP32_PEAK_TFLOPS,
+                                         "flop_per_pair": GATHER_PAIR_FLOP}}
+    per_path = t_gather / n_g + t_paths / n_probe
+    n_eq = int(max(1024, t_ref / per_path // 1024 * 1024))
+    del vtx
+    for name, starts in (("forward_area_starts", None), ("forward_data_starts", starts_q)):
+        ms, tm = [], []
+        for sd in seeds:
+            t0 = time.perf_counter()
+            v, _, _ = wob.forward_paths(scene, bc_sl, n_eq, M, sd + 50, starts=starts)
+            m, _ = wob.forward_gather(scene, v, pts, want_var=False)
+            sync()
+            tm.append(time.perf_counter() - t0)
+            ms.append(m)
+            del v
+        r, e2, ps = pooled(ms)
+        ref = out["backward_direct"]
+        out[name] = {"paths_shared_by_all_points": n_eq, "seconds": float(np.mean(tm)), "rmse": r,
+                     "rmse_per_seed": ps, "median_abs_err": e2, "rmse_ratio_vs_backward_direct": ref["rmse"] / r,
+                     "median_err_ratio_vs_backward_direct": ref["median_abs_err"] / e2}
+    starts_q.close()
+    scene.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -290,6 +397,8 @@ def main():
         extra["batched"] = batched_leg(torch, wob, I)
     if "cv" in legs:
         extra["cv_equal_time"] = cv_leg(torch, wob, I)
+    if "forward" in legs:
+        extra["forward_equal_time"] = forward_leg(torch, wob, I)
     w = I.config_icosphere_slice()
     scene = wob.Scene(w.mesh, wob.F32)
     info = scene.info()

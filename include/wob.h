@@ -207,6 +207,86 @@ wob_status wob_count_work(wob_scene scene, const void* points, const int32_t* po
 const char* wob_status_string(wob_status status);
 
 /* ------------------------------------------------------------------------- */
+/* Forward (adjoint) estimator of the single layer, Neumann boundaries        */
+/* (Sec. 4.4 "Forward estimator"; the Neumann rows of Table 1 for the single  */
+/* layer; boundary starts by the magnitude of the data as in the paper's      */
+/* Neumann example, and the reuse of boundary subpaths by every evaluation    */
+/* point as in its potential-flow example).                                   */
+/*                                                                           */
+/* The single layer reads u(x) = int G(x, y) mu(y) dA with mu = f + K mu,     */
+/* f = 2 phi q (q the Neumann datum, phi = bc->domain) and K(x, y) =          */
+/* -2 phi dG/dn_x(x, y).  A forward path starts at y_1 on the boundary with   */
+/* density p_0 and strength W_1 = f(y_1) / p_0(y_1); y_{k+1} is the picked    */
+/* hit of a uniformly random line through y_k (one of its m hits, as in the   */
+/* backward walk) and W_{k+1} = W_k phi m sgn(cos theta), theta the angle at  */
+/* y_{k+1} between y_{k+1} - y_k and the normal there (K with its arguments   */
+/* swapped, over the line density).  Vertex k carries c_{k-1} W_k with        */
+/* c = (1, ..., 1, 1/2) (the truncated series with the halved last term,      */
+/* Sec. 4.1.2), and                                                           */
+/*     u(x) ~ (1 / n_paths) sum_paths sum_k c_{k-1} W_k G(x, y_k),            */
+/* the same truncated series as the backward single-layer walk.               */
+/* ------------------------------------------------------------------------- */
+
+/* Start distribution: primitive T with probability w_T / sum(w), uniform
+ * inside T (density P_T / A_T, with P_T read from the binary32 cumulative
+ * table built here: binary64 running sum in caller-id order, each entry
+ * rounded once).  Weights proportional to |q| A_T put the starts where the
+ * data are large; a primitive with w_T = 0 never starts a path, so its data
+ * are dropped.
+ *   weight  HOST, n_prims values >= 0, finite, sum > 0 (caller-id order)
+ * Allocates a device table of n_prims floats.  The table refers to the scene:
+ * free it before the scene.  Errors: WOB_E_ARG, WOB_E_ALLOC, WOB_E_DEVICE. */
+typedef struct wob_starts_s* wob_starts;
+wob_status wob_starts_create(wob_scene scene, const double* weight, wob_starts* out);
+
+/* Starts by the magnitude of the data (the paper's boundary sampling for
+ * sparse Neumann values): w_T = (|q(c_T)| + floor * qbar) A_T with q the datum
+ * of bc (program and params; Neumann rows) at the centroid c_T and
+ * qbar = sum |q(c_T)| A_T / sum A_T.  floor >= 0; with floor > 0 every
+ * primitive can start a path, so the estimate stays unbiased where q vanishes
+ * at a centroid but not elsewhere on the primitive.  The weights are computed
+ * on the device in the scene's precision, the table as in wob_starts_create.
+ * Errors: WOB_E_ARG (also: all weights zero), WOB_E_ALLOC, WOB_E_DEVICE. */
+wob_status wob_starts_from_data(wob_scene scene, const wob_bc* bc, double floor, wob_starts* out);
+void wob_starts_free(wob_starts starts);
+
+/* Forward paths.  Scene: every primitive Neumann; bc: formulation AUTO or
+ * SINGLE_LAYER, density 0, sampling LINE (program and params give q).
+ *   starts     from wob_starts_create on this scene, or NULL = uniform by area
+ *   n_paths    0 <= n_paths < 2^32; path j draws Philox counters
+ *              (j, 0xfffffffe, (0 << 24) | 0xffff03, 0) for its start (word 0
+ *              the primitive, words 1, 2 the point) and, for line i from y_{i+1},
+ *              blocks 0 (direction) and 2 (hit keys) as the backward walk
+ *   walk_len   M vertices per path, 1 <= M < 65535 (M - 1 lines)
+ *   vtx_out    DEVICE, n_paths * M * 4 values of the scene's precision, path-major:
+ *              (y_x, y_y, y_z (0 in 2D), c_{k-1} W_k); 16-byte (binary64:
+ *              32-byte) aligned.  A path whose line finds no hit ends: its
+ *              later vertices are (0, 0, 0, 0).
+ *   vtx_prim   DEVICE, n_paths * M caller ids of the vertices (-1 after the end),
+ *              or NULL
+ *   vtx_m      DEVICE, n_paths * M hits of the line that reached each vertex
+ *              (0 for the start and after the end), or NULL
+ * Errors: WOB_E_ARG, WOB_E_UNSUPPORTED (not all Neumann, another formulation,
+ * density or RIS), WOB_E_DEVICE. */
+wob_status wob_forward_paths(wob_scene scene, const wob_bc* bc, wob_starts starts, int64_t n_paths,
+                             int32_t walk_len, uint64_t seed, void* vtx_out, int32_t* vtx_prim,
+                             int32_t* vtx_m, void* stream);
+
+/* Every evaluation point connected to every forward-path vertex:
+ * mean_out[p] = (1 / n_paths) sum_j c_j(x_p), c_j(x) = sum_k v_jk.w G(x, v_jk.y)
+ * (a vertex at distance zero adds nothing), var_out[p] = unbiased variance of
+ * the c_j.  The paths' correlation across points is the price of the reuse.
+ *   vtx        DEVICE, as written by wob_forward_paths (n_paths * walk_len records)
+ *   n_paths    >= 1 (>= 2 with var_out)
+ *   points     DEVICE, n_points * dim of the scene's precision
+ *   mean_out   DEVICE, n_points;  var_out DEVICE, n_points, or NULL
+ * The scene gives dimension, precision and device only.
+ * Errors: WOB_E_ARG, WOB_E_DEVICE. */
+wob_status wob_forward_gather(wob_scene scene, const void* vtx, int64_t n_paths, int32_t walk_len,
+                              const void* points, int64_t n_points, void* mean_out, void* var_out,
+                              void* stream);
+
+/* ------------------------------------------------------------------------- */
 /* Batched solves: many problems (scenes, point sets, data, N, M) in one      */
 /* persistent launch.  Not in the paper: its estimators are run per problem;  */
 /* batching only schedules them together.                                     */

@@ -12,8 +12,9 @@
 namespace wob {
 
 // F_SL_RIS is the single layer with resampled importance sampling: its own
-// kernel form, so that the line-sampling kernels carry none of its registers
-enum Formulation { F_DL = 1, F_DIRECT = 2, F_SL = 3, F_SL_RIS = 4 };
+// kernel form, so that the line-sampling kernels carry none of its registers.
+// F_FWD is the forward (adjoint) single-layer walk from the boundary.
+enum Formulation { F_DL = 1, F_DIRECT = 2, F_SL = 3, F_SL_RIS = 4, F_FWD = 5 };
 __host__ __device__ constexpr bool is_sl(int f) { return f == F_SL || f == F_SL_RIS; }
 enum Kind { K_DIRICHLET = 0, K_NEUMANN = 1, K_ROBIN = 2 };
 enum Program { P_CONST = 0, P_LINEAR = 1, P_QUAD = 2, P_INVDIST = 3 };

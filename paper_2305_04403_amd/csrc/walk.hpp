@@ -26,6 +26,9 @@ struct WalkArgs {
   int32_t ris_c;              // single layer: RIS candidates per vertex, 0 = line sampling
   uint32_t mixed_thr;         // single layer, Dirichlet vertices: floor(p_k 2^24)
   R mixed_p, mixed_k;         // p_k (as floor(p_k 2^24) / 2^24) and k
+  const float* fwd_cdf;       // forward walk: start table, binary32 cumulative weight fraction (caller-id order)
+  int64_t fwd_paths;          // forward walk: number of paths (path id = point * N + k)
+  R* fwd_vtx;                 // forward walk: per path and vertex (y, strength), 4 values each
   const R* cv_g;              // control-variate table per caller primitive id (single layer), or null
   const R* cv_g0;             // its line-0 table (the add-back's), set whenever cv_g is
   R* mean_out;
@@ -96,6 +99,32 @@ struct PathState {
   HitAcc<R> h;
   int32_t ni;            // traversal position (node index)
 };
+
+// Forward walk: vertex k of the current path, (y_k, c_{k-1} W_k) with
+// c = (1, ..., 1, 1/2), its caller id and the hits of the line that reached it.
+template <typename R, int D>
+__device__ __forceinline__ void fwd_record(const WalkArgs<R, D>& a, const PathState<R, D>& s, int k,
+                                           int32_t id, int32_t m) {
+  const int64_t v = (int64_t)s.path * a.M + k;
+  const R c = k + 1 < a.M ? (R)1 : (R)0.5;
+  struct alignas(4 * sizeof(R)) R4 { R x, y, z, w; };
+  *reinterpret_cast<R4*>(a.fwd_vtx + v * 4) = R4{s.x[0], s.x[1], D == 3 ? s.x[2] : (R)0, c * s.W};
+  if (a.vtx_prim) a.vtx_prim[v] = id;
+  if (a.vtx_m) a.vtx_m[v] = m;
+}
+
+// Forward walk: the path ended at vertex k - 1 (its line found no hit); the
+// remaining vertices carry nothing.
+template <typename R, int D>
+__device__ __forceinline__ void fwd_end(const WalkArgs<R, D>& a, const PathState<R, D>& s, int k) {
+  struct alignas(4 * sizeof(R)) R4 { R x, y, z, w; };
+  for (; k < a.M; ++k) {
+    const int64_t v = (int64_t)s.path * a.M + k;
+    *reinterpret_cast<R4*>(a.fwd_vtx + v * 4) = R4{0, 0, 0, 0};
+    if (a.vtx_prim) a.vtx_prim[v] = -1;
+    if (a.vtx_m) a.vtx_m[v] = 0;
+  }
+}
 
 // One single-layer vertex by resampled importance sampling (the paper's
 // sampling for Robin and mixed problems, Results): C candidates uniform by
@@ -186,13 +215,13 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     if (s.i >= a.L) return ST_DONE;
     s.on_gamma = s.cur_idx >= 0;
     s.z = (a.problem << 24) | ((uint32_t)s.i << 8);
-    if (s.on_gamma && FORM != F_DL) {
+    if (s.on_gamma && FORM != F_DL && FORM != F_FWD) {
       s.gc = load_prim<R, D>(a.scene, s.cur_idx);
       load_normal<R, D>(a.scene, s.cur_idx, s.nc);
     }
     // step 0 from an evaluation point uses the representation formula; in
     // density mode x0 is itself a vertex of the boundary recursion
-    s.first = s.i == 0 && !a.density;
+    s.first = FORM != F_FWD && s.i == 0 && !a.density;
     if constexpr (is_sl(FORM)) {
       // Table 1: on a Dirichlet part the solution is the given value (tested
       // here, where the primitive is loaded anyway, rather than in start_path:
@@ -281,6 +310,48 @@ template <typename R, int D, int FORM, bool TRACE, bool COUNT, bool CV>
 __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, D>& s, uint32_t path,
                                           int64_t item, WorkCount& wc) {
   s.path = path;
+  if constexpr (FORM == F_FWD) {
+    // y_1 on the boundary: primitive T from the start table (Philox
+    // (id, 0xfffffffe, (problem << 24) | 0xffff03, 0): word 0 against the
+    // binary32 table, words 1, 2 the point, reflected into the triangle), with
+    // density p_0 = P_T / A_T; W_1 = 2 phi q(y_1) / p_0
+    if (item >= a.fwd_paths) return ST_NONE;
+    s.path = (uint32_t)item;
+    const SceneView<R, D>& sc = a.scene;
+    const U4 r = philox(s.path, s.point, (a.problem << 24) | 0xffff03u, 0u, a.k0, a.k1);
+    const float u = unit<float>(r.x);
+    int32_t lo = 0, hi = sc.n_prims - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (a.fwd_cdf[mid] > u) hi = mid;
+      else lo = mid + 1;
+    }
+    const int32_t leaf = sc.leaf_of_id[lo];
+    const PrimGeo<R> g = load_prim<R, D>(sc, leaf);
+    R bu = unit<R>(r.y), bv = D == 3 ? unit<R>(r.z) : (R)0;
+    if (bu + bv > (R)1) {
+      bu = (R)1 - bu;
+      bv = (R)1 - bv;
+    }
+    hit_point(g, bu, bv, s.x);
+    R n[3];
+    load_normal<R, D>(sc, leaf, n);
+    R area;
+    if constexpr (D == 3) {
+      R c[3];
+      cross3(g.e1, g.e2, c);
+      area = (R)0.5 * sqrt(dot3(c, c));
+    } else {
+      area = sqrt(g.e1[0] * g.e1[0] + g.e1[1] * g.e1[1]);
+    }
+    const R pt = (R)a.fwd_cdf[lo] - (lo > 0 ? (R)a.fwd_cdf[lo - 1] : (R)0);
+    s.W = (R)2 * a.phi * boundary_datum<R, D>(a.prog, g, n, s.x) * area / pt;
+    s.acc = 0;
+    s.i = 0;
+    s.cur_idx = leaf;
+    fwd_record<R, D>(a, s, 0, g.id, 0);
+    return begin_step<R, D, FORM, TRACE, COUNT, CV>(a, s, wc);
+  }
   if (TRACE) {
     s.vp = a.vtx_prim ? a.vtx_prim + item * a.L : nullptr;
     s.vm = a.vtx_m ? a.vtx_m + item * a.L : nullptr;
@@ -397,7 +468,10 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     s.acc += s.W * S * (s.last ? (R)0.5 : (R)1);
     if (s.last) return ST_DONE;
   }
-  if (h.m == 0) return ST_DONE;
+  if (h.m == 0) {
+    if constexpr (FORM == F_FWD) fwd_end<R, D>(a, s, s.i + 1);
+    return ST_DONE;
+  }
   if (CV && s.last) {
     // the all-hits mean of the last emission
     s.acc += s.W * h.src;
@@ -410,14 +484,16 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
   const R sgn_t = h.t > (R)0 ? (R)1 : (R)-1;
   const R mm = (R)h.m;
   R ny[3] = {0, 0, 0};
-  if constexpr (FORM == F_DL || FORM == F_DIRECT) {
+  if constexpr (FORM == F_DL || FORM == F_DIRECT || FORM == F_FWD) {
     R nd[3];
     normal_dir<R, D>(gy, nd);
     const R sg = sgn_t * dot3(s.d, nd) > (R)0 ? (R)1 : (R)-1;  // sgn(cos theta_y)
     if constexpr (FORM == F_DL)
       w = (s.first && !s.on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
-    else
+    else if constexpr (FORM == F_DIRECT)
       w = s.on_gamma ? phi * mm * sg : (R)0.5 * phi * mm * sg;
+    else  // the Neumann row's kernel with its arguments swapped, over the line density
+      w = phi * mm * sg;
   } else {
     load_normal<R, D>(a.scene, h.idx, ny);
     const R rho = fabs(h.t);
@@ -452,6 +528,8 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
   } else if constexpr (FORM == F_DL) {
     const R sv = boundary_datum<R, D>(a.prog, gy, ny, s.x);
     s.acc += s.W * ((s.i + 1 < a.M) ? (R)2 * phi : phi) * sv;
+  } else if constexpr (FORM == F_FWD) {
+    fwd_record<R, D>(a, s, s.i + 1, gy.id, h.m);
   }
   ++s.i;
   return begin_step<R, D, FORM, TRACE, COUNT, CV>(a, s, wc);
@@ -513,11 +591,15 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     int st = ST_NONE;
     int32_t pend = -1;  // crossed leaf waiting to be tested
     if (point < a.n_points) {
-      s.x0[0] = a.points[point * D + 0];
-      s.x0[1] = a.points[point * D + 1];
-      s.x0[2] = D == 3 ? a.points[point * D + 2] : (R)0;
-      s.prim0 = a.point_prim ? a.point_prim[point] : -1;
-      s.point = a.point_ids ? a.point_ids[point] : (uint32_t)point;
+      if constexpr (FORM == F_FWD) {
+        s.point = 0xfffffffeu;  // forward paths: no evaluation point
+      } else {
+        s.x0[0] = a.points[point * D + 0];
+        s.x0[1] = a.points[point * D + 1];
+        s.x0[2] = D == 3 ? a.points[point * D + 2] : (R)0;
+        s.prim0 = a.point_prim ? a.point_prim[point] : -1;
+        s.point = a.point_ids ? a.point_ids[point] : (uint32_t)point;
+      }
       if (k < a.N) st = start_path<R, D, FORM, TRACE, COUNT, KCV>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc);
     }
     for (;;) {
@@ -587,7 +669,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     }
     return;
   }
-  if (TRACE) return;
+  if (TRACE || FORM == F_FWD) return;
 
   // per-point reduction: within the point's lanes of the wavefront, then across
   // the point's wavefronts

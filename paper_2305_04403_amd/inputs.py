@@ -276,6 +276,24 @@ def ball_points(n: int, r_max: float, seed: int, r_min: float = 0.0) -> np.ndarr
     return d * r[:, None]
 
 
+def forward_records(n_paths: int, walk_len: int, dim: int, seed: int,
+                    end_frac: float = 0.1) -> Tuple[np.ndarray, np.ndarray]:
+    """Synthetic vertex records of forward paths, for tests of the connection
+    step: positions uniform on the unit sphere (circle), strengths standard
+    normal; a fraction ``end_frac`` of the paths end after a random vertex
+    (later records zero, as a path whose line found no hit)."""
+    rng = np.random.default_rng(seed)
+    pos = rng.standard_normal((n_paths, walk_len, dim))
+    pos /= np.linalg.norm(pos, axis=2, keepdims=True)
+    w = rng.standard_normal((n_paths, walk_len))
+    ended = rng.random(n_paths) < end_frac
+    last = rng.integers(1, max(walk_len, 2), n_paths)
+    for j in np.nonzero(ended)[0]:
+        pos[j, last[j]:] = 0.0
+        w[j, last[j]:] = 0.0
+    return pos, w
+
+
 def slice_grid_inside(res: int, extent: float, amp: float, k_theta: int, k_phi: int,
                       margin: float) -> np.ndarray:
     """Cell centres of a res x res grid on z = 0 over [-extent, extent]^2 that lie
@@ -398,6 +416,28 @@ def config_tori(grid_n: int = 87, n_points: int = 1_000_000, boundary_frac: floa
     exact = 1.0 / np.linalg.norm(pts - xs, axis=1)
     return Workload(f"tori{mesh.n_prims}-exterior-neumann-robin-f32", mesh, pts, pp,
                     dict(domain=-1, formulation=3, program=3, params=tuple(xs)), samples, walk_len,
+                    "f32", exact=exact)
+
+
+def config_tori_neumann(grid_n: int = 87, n_points: int = 1_000_000, depth: float = 0.05,
+                        samples: int = 512, walk_len: int = 4, seed: int = 0) -> Workload:
+    """3D exterior Neumann on the union of three tori of ``config_tori`` (every
+    triangle Neumann), data from the point source u = 1/|x - xs| with xs inside
+    torus 0 at distance ``depth`` below its outer equator (depth 0.3 puts it on
+    the core circle; small depths concentrate the data near one spot, like the
+    sparse boundary values of the paper's Neumann example); the same evaluation
+    points off the boundary."""
+    rng = np.random.default_rng(seed)
+    mesh, rots = torus_union(grid_n=grid_n, seed=seed)
+    mesh = dataclasses.replace(mesh, kind=np.full(mesh.n_prims, NEUMANN, np.uint8))
+    xs = rots[0] @ np.array([1.0 + 0.3 - depth, 0.0, 0.0])
+    sdf = lambda p: torus_union_sdf(p, rots, 1.0, 0.3)
+    pts = box_points_outside(n_points, -2.0, 2.0, sdf, 0.02, seed + 2)
+    mesh = mesh.as_float32_geometry()
+    pts = pts.astype(np.float32).astype(np.float64)[rng.permutation(n_points)]
+    exact = 1.0 / np.linalg.norm(pts - xs, axis=1)
+    return Workload(f"tori{mesh.n_prims}-exterior-neumann-depth{depth:g}-f32", mesh, pts, None,
+                    dict(domain=-1, formulation=0, program=3, params=tuple(xs)), samples, walk_len,
                     "f32", exact=exact)
 
 

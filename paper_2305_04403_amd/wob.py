@@ -29,7 +29,9 @@ EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_pa
             "wob_batch_free", "wob_solve_batched", "wob_mlp_n_params", "wob_mlp_create",
             "wob_mlp_free", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
             "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
-            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary")
+            "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary",
+            "wob_starts_create", "wob_starts_from_data", "wob_starts_free", "wob_forward_paths",
+            "wob_forward_gather")
 
 
 class WobError(RuntimeError):
@@ -126,6 +128,16 @@ def lib():
     L.wob_cv_emission.argtypes = [vp, C.POINTER(_BC), vp, vp, vp]
     for name in ("wob_cv_table", "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission"):
         getattr(L, name).restype = C.c_int
+    L.wob_starts_create.argtypes = [vp, vp, C.POINTER(vp)]
+    L.wob_starts_create.restype = C.c_int
+    L.wob_starts_from_data.argtypes = [vp, C.POINTER(_BC), C.c_double, C.POINTER(vp)]
+    L.wob_starts_from_data.restype = C.c_int
+    L.wob_starts_free.argtypes = [vp]
+    L.wob_starts_free.restype = None
+    L.wob_forward_paths.argtypes = [vp, C.POINTER(_BC), vp, i64, i32, u64, vp, vp, vp, vp]
+    L.wob_forward_paths.restype = C.c_int
+    L.wob_forward_gather.argtypes = [vp, vp, i64, i32, vp, i64, vp, vp, vp]
+    L.wob_forward_gather.restype = C.c_int
     L.wob_status_string.argtypes = [C.c_int]
     L.wob_status_string.restype = C.c_char_p
     for name in ("wob_build_bvh", "wob_get_scene_info", "wob_solve", "wob_trace",
@@ -251,6 +263,70 @@ def solve(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int =
                          int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(mean),
                          _dev_ptr(var), _stream(stream))
     _check(st, "wob_solve")
+    return mean, var
+
+
+class Starts:
+    """Start distribution of forward paths on a scene: primitive T with
+    probability weight[T] / sum(weight), uniform inside T (``wob_starts_create``),
+    or weights (|q(c_T)| + floor * mean |q|) A_T from the data of ``data``
+    (``wob_starts_from_data``)."""
+
+    def __init__(self, scene: Scene, weight=None, data: Optional["BC"] = None, floor: float = 0.0):
+        h = C.c_void_p()
+        if data is not None:
+            b = data.c()
+            _check(lib().wob_starts_from_data(scene.handle, C.byref(b), float(floor), C.byref(h)),
+                   "wob_starts_from_data")
+        else:
+            w = np.ascontiguousarray(weight, dtype=np.float64)
+            _check(lib().wob_starts_create(scene.handle, w.ctypes.data, C.byref(h)), "wob_starts_create")
+        self.handle = h
+        self.scene = scene
+
+    def close(self):
+        if self.handle:
+            lib().wob_starts_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def forward_paths(scene: Scene, bc: BC, n_paths: int, walk_len: int, seed: int = 0, starts=None,
+                  want_vertices: bool = False, stream=None, out=None):
+    """Forward single-layer paths from the boundary (``wob_forward_paths``):
+    (n_paths, walk_len, 4) records (y, strength), plus the vertices' primitives
+    and line hit counts when ``want_vertices``."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    vtx = out if out is not None else torch.empty((n_paths, walk_len, 4), dtype=scene.dtype, device=dev)
+    vp = torch.empty((n_paths, walk_len), dtype=torch.int32, device=dev) if want_vertices else None
+    vm = torch.empty((n_paths, walk_len), dtype=torch.int32, device=dev) if want_vertices else None
+    b = bc.c()
+    st = lib().wob_forward_paths(scene.handle, C.byref(b), None if starts is None else starts.handle,
+                                 int(n_paths), int(walk_len), C.c_uint64(seed), _dev_ptr(vtx),
+                                 _dev_ptr(vp), _dev_ptr(vm), _stream(stream))
+    _check(st, "wob_forward_paths")
+    return vtx, vp, vm
+
+
+def forward_gather(scene: Scene, vtx, points, want_var: bool = True, stream=None, out=None):
+    """Connect every point to every forward-path vertex (``wob_forward_gather``):
+    per-point mean and variance over the paths of ``vtx`` (n_paths, walk_len, 4)."""
+    torch = _torch()
+    P = points.shape[0]
+    if out is None:
+        mean = torch.empty(P, dtype=scene.dtype, device=points.device)
+        var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
+    else:
+        mean, var = out
+    st = lib().wob_forward_gather(scene.handle, _dev_ptr(vtx), int(vtx.shape[0]), int(vtx.shape[1]),
+                                  _dev_ptr(points), P, _dev_ptr(mean), _dev_ptr(var), _stream(stream))
+    _check(st, "wob_forward_gather")
     return mean, var
 
 
