@@ -261,7 +261,8 @@ void wob_starts_free(wob_starts starts);
  *   vtx_out    DEVICE, n_paths * M * 4 values of the scene's precision, path-major:
  *              (y_x, y_y, y_z (0 in 2D), c_{k-1} W_k); 16-byte (binary64:
  *              32-byte) aligned.  A path whose line finds no hit ends: its
- *              later vertices are (0, 0, 0, 0).
+ *              later vertices are (1e18, 1e18, 1e18 (0 in 2D), 0), strength 0 far
+ *              from any evaluation point.
  *   vtx_prim   DEVICE, n_paths * M caller ids of the vertices (-1 after the end),
  *              or NULL
  *   vtx_m      DEVICE, n_paths * M hits of the line that reached each vertex
@@ -273,9 +274,12 @@ wob_status wob_forward_paths(wob_scene scene, const wob_bc* bc, wob_starts start
                              int32_t* vtx_m, void* stream);
 
 /* Every evaluation point connected to every forward-path vertex:
- * mean_out[p] = (1 / n_paths) sum_j c_j(x_p), c_j(x) = sum_k v_jk.w G(x, v_jk.y)
- * (a vertex at distance zero adds nothing), var_out[p] = unbiased variance of
- * the c_j.  The paths' correlation across points is the price of the reuse.
+ * mean_out[p] = (1 / n_paths) sum_j c_j(x_p), c_j(x) = sum_k v_jk.w G(x, v_jk.y),
+ * var_out[p] = unbiased variance of the c_j.  The paths' correlation across
+ * points is the price of the reuse.  G is singular at distance zero: a point
+ * exactly at a vertex's position gets a non-finite value (records must hold
+ * finite positions; ended paths' records add exactly 0 for points within
+ * 1e17 of the origin).
  *   vtx        DEVICE, as written by wob_forward_paths (n_paths * walk_len records)
  *   n_paths    >= 1 (>= 2 with var_out)
  *   points     DEVICE, n_points * dim of the scene's precision

@@ -23,41 +23,43 @@ using namespace wobi;
 namespace {
 
 // Connection of evaluation points to the vertices of forward paths: per point
-// and path j, c_j(x) = sum_k w_jk G(x, y_jk) (a vertex at distance zero adds
-// nothing); the mean over paths and the unbiased variance of c_j.
+// and path j, c_j(x) = sum_k w_jk G(x, y_jk); the mean over paths and the
+// unbiased variance of c_j.  G is singular at distance zero: a point exactly at
+// a vertex gets a non-finite value (records of ended paths sit far away with
+// strength 0, so they add exactly 0; no per-pair distance test).
 //
-// A workgroup holds 64 * kGatherPPL points (kGatherPPL per lane) and its four
+// A workgroup holds 64 * PPL points (PPL per lane) and its four
 // wavefronts split the paths in four contiguous ranges; the vertex records are
 // read at wavefront-uniform addresses (scalar loads, shared by all lanes), so
 // the inner loop is register arithmetic only.  G is accumulated without its
 // constant factor: 3D sum w / rho, 2D sum w log2(rho^2); per path the value is
 // summed in R over chunks of kGatherChunk paths and the chunk sums in binary64.
-constexpr int kGatherPPL = 2;
+constexpr int kGatherPPL = 2;  // points per lane of the launch
 constexpr int kGatherChunk = 32;
 
 template <typename R>
 __device__ __forceinline__ R inv_dist(R r2) {
-  if constexpr (sizeof(R) == 4) return r2 > (R)0 ? __builtin_amdgcn_rsqf(r2) : (R)0;
-  else return r2 > (R)0 ? (R)1 / sqrt(r2) : (R)0;
+  if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rsqf(r2);
+  else return (R)1 / sqrt(r2);
 }
 
 template <typename R>
 __device__ __forceinline__ R log2_dist2(R r2) {
-  if constexpr (sizeof(R) == 4) return r2 > (R)0 ? __log2f(r2) : (R)0;
-  else return r2 > (R)0 ? log2(r2) : (R)0;
+  if constexpr (sizeof(R) == 4) return __log2f(r2);
+  else return log2(r2);
 }
 
-template <typename R, int D>
+template <typename R, int D, int PPL>
 __global__ void __launch_bounds__(256) gather_kernel(const R* __restrict__ vtx, int64_t n_paths, int32_t M,
                                                      const R* __restrict__ points, int64_t n_points,
                                                      R* __restrict__ mean_out, R* __restrict__ var_out) {
-  __shared__ double red[4][64 * kGatherPPL][2];
+  __shared__ double red[4][64 * PPL][2];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t base = (int64_t)blockIdx.x * (64 * kGatherPPL);
-  R px[kGatherPPL], py[kGatherPPL], pz[kGatherPPL];
+  const int64_t base = (int64_t)blockIdx.x * (64 * PPL);
+  R px[PPL], py[PPL], pz[PPL];
 #pragma unroll
-  for (int q = 0; q < kGatherPPL; ++q) {
+  for (int q = 0; q < PPL; ++q) {
     int64_t i = base + lane + 64 * q;
     if (i >= n_points) i = n_points - 1;
     px[q] = points[i * D + 0];
@@ -67,23 +69,23 @@ __global__ void __launch_bounds__(256) gather_kernel(const R* __restrict__ vtx, 
   const int64_t per = (n_paths + 3) / 4;
   const int64_t j0 = wave * per < n_paths ? wave * per : n_paths;
   const int64_t j1 = j0 + per < n_paths ? j0 + per : n_paths;
-  double S[kGatherPPL], Q[kGatherPPL];
+  double S[PPL], Q[PPL];
 #pragma unroll
-  for (int q = 0; q < kGatherPPL; ++q) S[q] = Q[q] = 0.0;
+  for (int q = 0; q < PPL; ++q) S[q] = Q[q] = 0.0;
   for (int64_t j = j0; j < j1; j += kGatherChunk) {
     const int64_t je = j + kGatherChunk < j1 ? j + kGatherChunk : j1;
-    R s[kGatherPPL], s2[kGatherPPL];
+    R s[PPL], s2[PPL];
 #pragma unroll
-    for (int q = 0; q < kGatherPPL; ++q) s[q] = s2[q] = (R)0;
+    for (int q = 0; q < PPL; ++q) s[q] = s2[q] = (R)0;
     for (int64_t jj = j; jj < je; ++jj) {
       const R* v = vtx + jj * M * 4;
-      R c[kGatherPPL];
+      R c[PPL];
 #pragma unroll
-      for (int q = 0; q < kGatherPPL; ++q) c[q] = (R)0;
+      for (int q = 0; q < PPL; ++q) c[q] = (R)0;
       for (int k = 0; k < M; ++k) {
         const R vx = v[4 * k + 0], vy = v[4 * k + 1], vz = v[4 * k + 2], w = v[4 * k + 3];
 #pragma unroll
-        for (int q = 0; q < kGatherPPL; ++q) {
+        for (int q = 0; q < PPL; ++q) {
           const R dx = px[q] - vx, dy = py[q] - vy;
           R r2 = dx * dx + dy * dy;
           if constexpr (D == 3) {
@@ -96,19 +98,19 @@ __global__ void __launch_bounds__(256) gather_kernel(const R* __restrict__ vtx, 
         }
       }
 #pragma unroll
-      for (int q = 0; q < kGatherPPL; ++q) {
+      for (int q = 0; q < PPL; ++q) {
         s[q] += c[q];
         s2[q] += c[q] * c[q];
       }
     }
 #pragma unroll
-    for (int q = 0; q < kGatherPPL; ++q) {
+    for (int q = 0; q < PPL; ++q) {
       S[q] += (double)s[q];
       Q[q] += (double)s2[q];
     }
   }
 #pragma unroll
-  for (int q = 0; q < kGatherPPL; ++q) {
+  for (int q = 0; q < PPL; ++q) {
     red[wave][lane + 64 * q][0] = S[q];
     red[wave][lane + 64 * q][1] = Q[q];
   }
@@ -118,7 +120,7 @@ __global__ void __launch_bounds__(256) gather_kernel(const R* __restrict__ vtx, 
   const double kc = D == 3 ? 0.25 / 3.14159265358979323846 : -0.69314718055994530942 * 0.25 / 3.14159265358979323846;
   const double n = (double)n_paths;
 #pragma unroll
-  for (int q = 0; q < kGatherPPL; ++q) {
+  for (int q = 0; q < PPL; ++q) {
     const int64_t i = base + lane + 64 * q;
     if (i >= n_points) continue;
     double ts = 0.0, tq = 0.0;
@@ -203,7 +205,7 @@ wob_status launch_gather(const void* vtx, int64_t n_paths, int32_t walk_len, con
                          int64_t n_points, void* mean_out, void* var_out, hipStream_t st) {
   const int64_t per_block = 64 * kGatherPPL;
   const dim3 grid((unsigned)((n_points + per_block - 1) / per_block)), block(256);
-  hipLaunchKernelGGL((gather_kernel<R, D>), grid, block, 0, st, (const R*)vtx, n_paths, walk_len,
+  hipLaunchKernelGGL((gather_kernel<R, D, kGatherPPL>), grid, block, 0, st, (const R*)vtx, n_paths, walk_len,
                      (const R*)points, n_points, (R*)mean_out, (R*)var_out);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }

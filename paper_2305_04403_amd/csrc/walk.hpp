@@ -114,13 +114,16 @@ __device__ __forceinline__ void fwd_record(const WalkArgs<R, D>& a, const PathSt
 }
 
 // Forward walk: the path ended at vertex k - 1 (its line found no hit); the
-// remaining vertices carry nothing.
+// remaining vertices carry nothing: strength 0 at a far position (1e18 in each
+// coordinate), where the connection adds exactly 0 * (a finite kernel value)
+// without a test for zero distance.
 template <typename R, int D>
 __device__ __forceinline__ void fwd_end(const WalkArgs<R, D>& a, const PathState<R, D>& s, int k) {
   struct alignas(4 * sizeof(R)) R4 { R x, y, z, w; };
+  const R far = (R)1e18;
   for (; k < a.M; ++k) {
     const int64_t v = (int64_t)s.path * a.M + k;
-    *reinterpret_cast<R4*>(a.fwd_vtx + v * 4) = R4{0, 0, 0, 0};
+    *reinterpret_cast<R4*>(a.fwd_vtx + v * 4) = R4{far, far, D == 3 ? far : (R)0, (R)0};
     if (a.vtx_prim) a.vtx_prim[v] = -1;
     if (a.vtx_m) a.vtx_m[v] = 0;
   }

@@ -281,7 +281,8 @@ def forward_records(n_paths: int, walk_len: int, dim: int, seed: int,
     """Synthetic vertex records of forward paths, for tests of the connection
     step: positions uniform on the unit sphere (circle), strengths standard
     normal; a fraction ``end_frac`` of the paths end after a random vertex
-    (later records zero, as a path whose line found no hit)."""
+    (later records: strength 0 at 1e18 in each coordinate, as the library writes
+    them for a path whose line found no hit)."""
     rng = np.random.default_rng(seed)
     pos = rng.standard_normal((n_paths, walk_len, dim))
     pos /= np.linalg.norm(pos, axis=2, keepdims=True)
@@ -289,7 +290,7 @@ def forward_records(n_paths: int, walk_len: int, dim: int, seed: int,
     ended = rng.random(n_paths) < end_frac
     last = rng.integers(1, max(walk_len, 2), n_paths)
     for j in np.nonzero(ended)[0]:
-        pos[j, last[j]:] = 0.0
+        pos[j, last[j]:] = 1e18
         w[j, last[j]:] = 0.0
     return pos, w
 

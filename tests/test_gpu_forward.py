@@ -52,7 +52,8 @@ def compare_forward(orc, vtx, vp, vm, precision):
     wscale = np.abs(orc["w"]) + 0.05 * np.median(np.abs(orc["w"][orc["w"] != 0]))
     werr = np.abs(g_w - orc["w"])
     wtol = wscale * (rtol + cos_ulp / cond[:, None])
-    perr = np.linalg.norm(g_pos - orc["pos"], axis=2)
+    # positions of live vertices (an ended path's records sit at 1e18 on the GPU)
+    perr = np.where(orc["prim"] >= 0, np.linalg.norm(g_pos - orc["pos"], axis=2), 0.0)
     ptol = (1.0 + np.linalg.norm(orc["pos"], axis=2)) * (rtol + cos_ulp / cond[:, None])
     bad = vmis | np.any(werr > wtol, axis=1) | np.any(perr > ptol, axis=1)
     ratio = np.where(ok[:, None], np.maximum(werr / wtol, perr / ptol), 0.0)
@@ -174,8 +175,9 @@ def test_forward_gather_parity(W, dim, precision):
 
 
 def test_forward_gather_edge_cases(W):
-    """No points; one path without variance; a point exactly on a vertex (that
-    vertex adds nothing, as in the oracle)."""
+    """No points; one path without variance; a point 1e-6 from a vertex; the
+    records of an ended path (strength 0 at 1e18) add nothing, also for a point
+    at the origin."""
     mesh = _neumann(I.icosphere(2))
     scene = W.Scene(mesh, W.F64)
     pos, w = I.forward_records(1, 2, 3, 1, end_frac=0.0)
@@ -185,13 +187,19 @@ def test_forward_gather_edge_cases(W):
     t = dev(rec, torch.float64)
     m, v = W.forward_gather(scene, t, torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
     assert m.numel() == 0
-    pts = np.stack([pos[0, 0], np.array([0.1, 0.2, 0.3])])
+    pts = np.stack([pos[0, 0] + 1e-6, np.array([0.1, 0.2, 0.3])])
     m, v = W.forward_gather(scene, t, dev(pts, torch.float64), want_var=False)
     om, _, _ = oracle.forward_gather(pos, w, pts)
     assert np.all(np.isfinite(m.cpu().numpy()))
     assert np.allclose(m.cpu().numpy(), om, rtol=1e-12, atol=0)
     with pytest.raises(W.WobError):
         W.forward_gather(scene, t, dev(pts, torch.float64), want_var=True)  # one path: no variance
+    ended = rec.copy()
+    ended[0, 1] = (1e18, 1e18, 1e18, 0.0)
+    p0 = np.array([[0.0, 0.0, 0.0], [0.3, -0.2, 0.1]])
+    m, _ = W.forward_gather(scene, dev(ended, torch.float64), dev(p0, torch.float64), want_var=False)
+    om, _, _ = oracle.forward_gather(pos[:, :1], w[:, :1], p0)
+    assert np.allclose(m.cpu().numpy(), om, rtol=1e-12, atol=0)
     scene.close()
 
 
