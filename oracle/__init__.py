@@ -78,6 +78,12 @@ def lib():
         _lib.orc_trace_cv.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, vp,
                                       vp, C.c_int64, vp, vp, vp, C.c_int]
         _lib.orc_trace_cv.restype = C.c_int
+        _lib.orc_trace_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, C.c_int64,
+                                        vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
+        _lib.orc_trace_grad.restype = C.c_int
+        _lib.orc_solve_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
+                                        vp, vp, vp, vp, C.c_int]
+        _lib.orc_solve_grad.restype = C.c_int
         _lib.orc_forward_paths.argtypes = [vp, vp, vp, C.c_int64, C.c_int, C.c_uint64, C.c_uint32, vp,
                                            C.c_int]
         _lib.orc_forward_paths.restype = C.c_int
@@ -207,6 +213,41 @@ def solve(mesh: OracleMesh, points: np.ndarray, point_prim: Optional[np.ndarray]
     if rc != 0:
         raise ValueError("orc_solve rejected its arguments")
     return mean, var
+
+
+def trace_grad(mesh: OracleMesh, points: np.ndarray, bc: _BC, walk_len: int, seed: int,
+               item_point: np.ndarray, item_path: np.ndarray, problem: int = 0, n_threads: int = 0) -> dict:
+    """Per-path value and gradient in x0 (points off the boundary), with the
+    rounding scales, grazing margin and conditioning of each path."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    ip = np.ascontiguousarray(item_point, dtype=np.int64)
+    ik = np.ascontiguousarray(item_path, dtype=np.int64)
+    n = ip.shape[0]
+    out = {"value": np.zeros(n), "grad": np.zeros((n, mesh.dim)), "abs_sum": np.zeros(n),
+           "grad_abs": np.zeros(n), "graze": np.zeros(n), "cond_cos": np.zeros(n)}
+    rc = lib().orc_trace_grad(mesh.ref, _ptr(pts), C.c_int64(pts.shape[0]), C.byref(bc), C.c_int(walk_len),
+                              C.c_uint64(seed), C.c_uint32(problem), C.c_int64(n), _ptr(ip), _ptr(ik),
+                              _ptr(out["value"]), _ptr(out["grad"]), _ptr(out["abs_sum"]),
+                              _ptr(out["grad_abs"]), _ptr(out["graze"]), _ptr(out["cond_cos"]),
+                              C.c_int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_trace_grad rejected its arguments")
+    return out
+
+
+def solve_grad(mesh: OracleMesh, points: np.ndarray, bc: _BC, samples: int, walk_len: int, seed: int,
+               problem: int = 0, n_threads: int = 0):
+    """Mean and variance of the value and of the gradient (P, dim) over paths."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    P = pts.shape[0]
+    mean, var = np.zeros(P), np.zeros(P)
+    g, gv = np.zeros((P, mesh.dim)), np.zeros((P, mesh.dim))
+    rc = lib().orc_solve_grad(mesh.ref, _ptr(pts), C.c_int64(P), C.byref(bc), C.c_int(samples),
+                              C.c_int(walk_len), C.c_uint64(seed), C.c_uint32(problem), _ptr(mean), _ptr(var),
+                              _ptr(g), _ptr(gv), C.c_int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_solve_grad rejected its arguments")
+    return mean, var, g, gv
 
 
 class _ForwardOut(C.Structure):

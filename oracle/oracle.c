@@ -160,6 +160,26 @@ static double dG_dnx(const double* x, const double* y, const double* nx, int dim
   return dim == 3 ? rdn / (4.0 * ORC_PI * rn * rn * rn) : rdn / (2.0 * ORC_PI * rn * rn);
 }
 
+/* Gradients in x (the evaluation point) of G and of dG/dn_y, for the gradient
+ * estimators (Sec. 4.4: the gradient equations of the three formulations).
+ * With r = y - x, rho = |r| and S_D = 4 pi (3D), 2 pi (2D):
+ *   grad_x G        = r / (S_D rho^D)
+ *   grad_x dG/dn_y  = (n_y / rho^D - D (r . n_y) r / rho^(D+2)) / S_D        */
+static void grad_G(const double* x, const double* y, int dim, double* g) {
+  double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+  const double rho = sqrt(dot(r, r, dim));
+  const double c = dim == 3 ? 1.0 / (4.0 * ORC_PI * rho * rho * rho) : 1.0 / (2.0 * ORC_PI * rho * rho);
+  for (int a = 0; a < 3; ++a) g[a] = c * r[a];
+}
+static void grad_dG_dny(const double* x, const double* y, const double* ny, int dim, double* g) {
+  double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+  const double rr = dot(r, r, dim), rho = sqrt(rr), rdn = dot(r, ny, dim);
+  const double sd = dim == 3 ? 4.0 * ORC_PI : 2.0 * ORC_PI;
+  const double rd = dim == 3 ? rr * rho : rr; /* rho^D */
+  for (int a = 0; a < 3; ++a) g[a] = (ny[a] / rd - (double)dim * rdn * r[a] / (rd * rr)) / sd;
+  if (dim == 2) g[2] = 0.0;
+}
+
 /* Area density of the point y reached by a uniformly random line through x
  * that is one of m hits picked uniformly: the line direction is uniform on the
  * sphere (circle) and covers +d and -d, so the density per unit solid angle is
@@ -405,6 +425,8 @@ typedef struct {
   double src_abs;        /* sum over hits of |G(x,y) q(y) / p_all(y)| */
   double src_cos;        /* smallest |cos theta_y| among the source hits */
   double graze;          /* min over primitives of |margin| * cos */
+  double src_grad[3];    /* sum over hits of grad_x G(x,y) q(y) / p_all(y) */
+  double src_grad_abs;   /* sum over hits of |grad_x G q / p_all|, all components */
 } line_hits;
 
 static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc, int want_src,
@@ -418,6 +440,8 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
   h->src_abs = 0.0;
   h->src_cos = INFINITY;
   h->graze = INFINITY;
+  h->src_grad[0] = h->src_grad[1] = h->src_grad[2] = 0.0;
+  h->src_grad_abs = 0.0;
   for (int64_t j = 0; j < m->n_prims; ++j) {
     if (j == exclude) continue;
     double t, y[3], margin, cosv, b[2];
@@ -446,6 +470,13 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
       h->src += term;
       h->src_abs += fabs(term);
       if (cosv < h->src_cos) h->src_cos = cosv;
+      double gg[3];
+      grad_G(x, y, m->dim, gg);
+      const double pa = line_pdf(x, y, ny, 1, m->dim);
+      for (int a = 0; a < 3; ++a) {
+        h->src_grad[a] += gg[a] * q / pa;
+        h->src_grad_abs += fabs(gg[a] * q / pa);
+      }
     }
   }
 }
@@ -527,7 +558,8 @@ typedef struct {
 static path_result one_path(const orc_mesh* m, const double* normals, const area_table* at,
                             const orc_bc* bc, int form, const double* x0, int64_t prim0, int M,
                             uint64_t seed, uint32_t problem, uint32_t point, uint32_t path,
-                            int32_t* vprim, int32_t* vm, double* vpos) {
+                            int32_t* vprim, int32_t* vm, double* vpos, double* grad,
+                            double* grad_abs) {
   const int dim = m->dim;
   const double phi = (double)bc->domain;
   const int L = form == ORC_DIRECT ? M + 1 : M;
@@ -553,6 +585,14 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
   /* abs_sum: the same sum with every factor and summand replaced by its
      magnitude (the scale of the rounding error of the sum) */
   double W = 1.0, acc = 0.0, abs_sum = 0.0, Wabs = 1.0;
+  /* gradient in x0 (x0 off the boundary): the same path with the kernel of
+     the first step differentiated in x0 (the gradient equations of Sec. 4.4;
+     the rest of the path estimates the same boundary unknown).  Wg is the
+     derivative of W: a step multiplies it by its weight w, and step 0 adds
+     W w' (w' = grad_x kernel / pdf); the step-0 source of the direct BIE adds
+     its own derivative; every emission e adds Wg e. */
+  const int want_grad = grad != NULL;
+  double Wg[3] = {0.0, 0.0, 0.0}, gacc[3] = {0.0, 0.0, 0.0}, Wgabs = 0.0, gabs = 0.0;
 
   for (int i = 0; i < L; ++i) {
     const int on_gamma = cur >= 0;
@@ -584,6 +624,8 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       const double w = 1.0 / (1.0 - bc->mixed_p);
       W *= w;
       Wabs *= w;
+      for (int a = 0; a < 3; ++a) Wg[a] *= w;
+      Wgabs *= w;
       if (vprim) vprim[i] = (int32_t)(-2 - cur);
       if (vm) vm[i] = 0;
       if (vpos)
@@ -591,6 +633,8 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       const double e = sl_emission(m, bc, cur, x, i + 1 >= M);
       acc += W * e;
       abs_sum += Wabs * fabs(e);
+      for (int a = 0; a < 3; ++a) gacc[a] += Wg[a] * e;
+      gabs += Wgabs * fabs(e);
       continue;
     }
     const double gscale = dvert ? -bc->mixed_k / bc->mixed_p : 1.0; /* kernel k G / p_k or G */
@@ -679,6 +723,22 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       if (jpick < 0 || !(S > 0.0)) break; /* no candidate carries kernel mass */
       if (vprim) vprim[i] = (int32_t)jpick;
       const double w = (kpick > 0.0 ? 1.0 : -1.0) * S * at->total / (double)C;
+      if (want_grad && first) {
+        /* RIS estimate of int grad_x G mu: grad_x G(y) / |G(y)| S |Gamma| / C */
+        double gg[3];
+        grad_G(x, ypick, dim, gg);
+        const double f = S * at->total / (double)C / fabs(kpick);
+        Wgabs = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          Wg[a] = Wg[a] * w + W * gg[a] * f;
+          Wgabs += fabs(W * gg[a] * f);
+        }
+        const double c = rho_cond(x, ypick, dim);
+        if (c < res.cond_cos) res.cond_cos = c;
+      } else {
+        for (int a = 0; a < 3; ++a) Wg[a] *= w;
+        Wgabs *= Smag * at->total / (double)C;
+      }
       W *= w;
       Wabs *= Smag * at->total / (double)C;
       memcpy(x, ypick, sizeof(x));
@@ -688,6 +748,8 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       const double e = sl_emission(m, bc, cur, x, i + 1 >= M);
       acc += W * e;
       abs_sum += Wabs * fabs(e);
+      for (int a = 0; a < 3; ++a) gacc[a] += Wg[a] * e;
+      gabs += Wgabs * fabs(e);
       continue;
     }
 
@@ -748,6 +810,13 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
         double term = W * S * (last ? 0.5 : 1.0);
         acc += term;
         abs_sum += Wabs * Sabs * (last ? 0.5 : 1.0);
+        if (want_grad) {
+          /* the step-0 source phi int G q is a function of x0 (off the boundary) */
+          const double c0 = last ? 0.5 : 1.0;
+          for (int a = 0; a < 3; ++a)
+            gacc[a] += (Wg[a] * S + (i == 0 ? W * phi * h.src_grad[a] : 0.0)) * c0;
+          gabs += (Wgabs * Sabs + (i == 0 ? W * h.src_grad_abs : 0.0)) * c0;
+        }
         if (last) break;
       }
       if (h.m == 0) break;
@@ -816,6 +885,39 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
         w /= (1.0 - bc->self_p);
         wabs /= (1.0 - bc->self_p);
       }
+      if (want_grad && i == 0) {
+        /* step 0 from x0 off the boundary: w' = grad_x kernel / p */
+        double kg[3];
+        if (form == ORC_SINGLE_LAYER) {
+          grad_G(x, y, dim, kg);
+          for (int a = 0; a < 3; ++a) kg[a] *= gscale;
+        } else {
+          grad_dG_dny(x, y, ny, dim, kg);
+          const double f = form == ORC_DOUBLE_LAYER ? -1.0 : -phi; /* -dG/dn_y, -phi dG/dn_y */
+          for (int a = 0; a < 3; ++a) kg[a] *= f;
+        }
+        double wg[3], wgabs = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          wg[a] = kg[a] / p;
+          wgabs += fabs(wg[a]);
+        }
+        /* the derivative kernels carry 1 / |cos theta_y| (double layer,
+           direct) and powers of 1 / rho */
+        double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+        const double cy = fabs(dot(r, ny, dim)) / sqrt(dot(r, r, dim));
+        if (cy < res.cond_cos) res.cond_cos = cy;
+        const double cr = rho_cond(x, y, dim);
+        if (cr < res.cond_cos) res.cond_cos = cr;
+        for (int a = 0; a < 3; ++a) Wg[a] = Wg[a] * w + W * wg[a];
+        Wgabs = Wgabs * wabs + Wabs * wgabs;
+      } else {
+        for (int a = 0; a < 3; ++a) Wg[a] *= w;
+        Wgabs *= wabs;
+      }
+    }
+    if (use_self) {
+      for (int a = 0; a < 3; ++a) Wg[a] *= w;
+      Wgabs *= wabs;
     }
 
     W *= w;
@@ -837,10 +939,16 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       }
       acc += W * e;
       abs_sum += Wabs * fabs(e);
+      for (int a = 0; a < 3; ++a) gacc[a] += Wg[a] * e;
+      gabs += Wgabs * fabs(e);
     }
   }
   res.value = acc;
   res.abs_sum = abs_sum;
+  if (want_grad) {
+    for (int a = 0; a < dim; ++a) grad[a] = gacc[a];
+    if (grad_abs) *grad_abs = gabs;
+  }
   return res;
 }
 
@@ -892,7 +1000,7 @@ int orc_trace(const orc_mesh* m, const double* points, const int32_t* point_prim
                              (uint32_t)p, (uint32_t)item_path[it],
                              out->vtx_prim ? out->vtx_prim + it * L : NULL,
                              out->vtx_m ? out->vtx_m + it * L : NULL,
-                             out->vtx_pos ? out->vtx_pos + it * L * m->dim : NULL);
+                             out->vtx_pos ? out->vtx_pos + it * L * m->dim : NULL, NULL, NULL);
     if (out->value) out->value[it] = r.value;
     if (out->abs_sum) out->abs_sum[it] = r.abs_sum;
     if (out->graze) out->graze[it] = r.graze;
@@ -922,7 +1030,7 @@ int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim
     double sum = 0.0;
     for (int k = 0; k < samples; ++k) {
       v[k] = one_path(m, normals, &at, bc, form, x0, prim0, walk_len, seed, problem, (uint32_t)p,
-                      (uint32_t)k, NULL, NULL, NULL)
+                      (uint32_t)k, NULL, NULL, NULL, NULL, NULL)
                  .value;
       sum += v[k];
     }
@@ -1133,6 +1241,86 @@ int orc_forward_gather(int dim, int64_t n_paths, int walk_len, const double* vtx
     if (var_out) var_out[p] = n_paths > 1 ? ss / (double)(n_paths - 1) : 0.0;
     if (abs_out) abs_out[p] = sabs / (double)n_paths;
   }
+  return 0;
+}
+
+/* Per-path values and gradients in x0 for (point, path) items; every point
+ * off the boundary (the gradient equations hold inside the domain only). */
+int orc_trace_grad(const orc_mesh* m, const double* points, int64_t n_points, const orc_bc* bc,
+                   int walk_len, uint64_t seed, uint32_t problem, int64_t n_items,
+                   const int64_t* item_point, const int64_t* item_path, double* value, double* grad,
+                   double* abs_sum, double* grad_abs, double* graze, double* cond_cos, int n_threads) {
+  if (check_args(m, bc, walk_len) || bc->density || !grad) return 1;
+  const int form = orc_resolve_formulation(m, bc->formulation);
+  double* normals = make_normals(m);
+  area_table at = make_area_table(m);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+  for (int64_t it = 0; it < n_items; ++it) {
+    int64_t p = item_point[it];
+    if (p < 0 || p >= n_points) continue;
+    double x0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
+    double gabs = 0.0;
+    path_result r = one_path(m, normals, &at, bc, form, x0, -1, walk_len, seed, problem, (uint32_t)p,
+                             (uint32_t)item_path[it], NULL, NULL, NULL, grad + it * m->dim, &gabs);
+    if (value) value[it] = r.value;
+    if (abs_sum) abs_sum[it] = r.abs_sum;
+    if (grad_abs) grad_abs[it] = gabs;
+    if (graze) graze[it] = r.graze;
+    if (cond_cos) cond_cos[it] = r.cond_cos;
+  }
+  free(normals);
+  free(at.cdf);
+  return 0;
+}
+
+/* Mean and unbiased variance over paths 0..N-1 of the value and of each
+ * gradient component (two-pass), every point off the boundary. */
+int orc_solve_grad(const orc_mesh* m, const double* points, int64_t n_points, const orc_bc* bc,
+                   int samples, int walk_len, uint64_t seed, uint32_t problem, double* mean_out,
+                   double* var_out, double* grad_out, double* grad_var_out, int n_threads) {
+  if (check_args(m, bc, walk_len) || bc->density || samples < 1) return 1;
+  const int form = orc_resolve_formulation(m, bc->formulation);
+  const int dim = m->dim;
+  double* normals = make_normals(m);
+  area_table at = make_area_table(m);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t p = 0; p < n_points; ++p) {
+    double x0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; ++a) x0[a] = points[p * dim + a];
+    double* v = (double*)malloc(sizeof(double) * (size_t)samples * (1 + (size_t)dim));
+    double* g = v + samples;
+    for (int k = 0; k < samples; ++k)
+      v[k] = one_path(m, normals, &at, bc, form, x0, -1, walk_len, seed, problem, (uint32_t)p, (uint32_t)k,
+                      NULL, NULL, NULL, g + (size_t)k * dim, NULL)
+                 .value;
+    for (int c = -1; c < dim; ++c) {
+      double sum = 0.0, ss = 0.0;
+      for (int k = 0; k < samples; ++k) sum += c < 0 ? v[k] : g[(size_t)k * dim + c];
+      const double mean = sum / samples;
+      for (int k = 0; k < samples; ++k) {
+        const double d = (c < 0 ? v[k] : g[(size_t)k * dim + c]) - mean;
+        ss += d * d;
+      }
+      const double var = samples > 1 ? ss / (samples - 1) : 0.0;
+      if (c < 0) {
+        if (mean_out) mean_out[p] = mean;
+        if (var_out) var_out[p] = var;
+      } else {
+        if (grad_out) grad_out[p * dim + c] = mean;
+        if (grad_var_out) grad_var_out[p * dim + c] = var;
+      }
+    }
+    free(v);
+  }
+  free(normals);
+  free(at.cdf);
   return 0;
 }
 

@@ -151,6 +151,21 @@ int orc_trace_cv(const orc_mesh* mesh, const double* points, const int32_t* poin
 int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points, int64_t n_points,
                    uint32_t seed, int randomized, double* out, int n_threads);
 
+/* Gradient estimators (Sec. 4.4, gradient estimation with the same paths):
+ * the path of orc_trace with the kernel of its first step replaced by its
+ * gradient in x0 (double layer: -grad dG/dn_y; direct BIE: -phi grad dG/dn_y
+ * and phi grad G in the step-0 source; single layer: grad G), the rest of the
+ * path unchanged.  Points must lie off the boundary (the gradient equations
+ * hold inside the domain); no density mode.  grad: [n_items * dim];
+ * grad_abs: the magnitude sum of the gradient terms (rounding scale). */
+int orc_trace_grad(const orc_mesh* mesh, const double* points, int64_t n_points, const orc_bc* bc,
+                   int walk_len, uint64_t seed, uint32_t problem, int64_t n_items,
+                   const int64_t* item_point, const int64_t* item_path, double* value, double* grad,
+                   double* abs_sum, double* grad_abs, double* graze, double* cond_cos, int n_threads);
+int orc_solve_grad(const orc_mesh* mesh, const double* points, int64_t n_points, const orc_bc* bc,
+                   int samples, int walk_len, uint64_t seed, uint32_t problem, double* mean_out,
+                   double* var_out, double* grad_out, double* grad_var_out, int n_threads);
+
 /* Forward (adjoint) estimator of the single layer, all-Neumann boundary
  * (Sec. 4.4 "Forward estimator"; see oracle.c for the derivation and the
  * random-number layout).  orc_forward_paths writes, per path and vertex

@@ -1,0 +1,128 @@
+"""Pins of the oracle's gradient estimators (Sec. 4.4: the gradient is
+estimated with the same paths, the kernel of the first step replaced by its
+gradient in the evaluation point) against closed forms.
+
+On a sphere or circle the gradient of each harmonic degree comes out with the
+same truncation factor tau_M as the value, so a wrong derivative kernel (a sign,
+a missing n_y term, a factor D) or a derivative that leaks into later steps
+moves a target.  CPU only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_04403_amd import inputs as I
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build(oracle_lib):
+    return oracle_lib
+
+
+def _fit(g, gv, ref, N):
+    w = N / np.maximum(gv, 1e-300)
+    est = np.sum(w * g * ref) / np.sum(w * ref * ref)
+    return est, 1.0 / np.sqrt(np.sum(w * ref * ref))
+
+
+def test_double_layer_gradient_sphere_truncation_factors():
+    """Interior Dirichlet on the unit sphere with u = z: the gradient estimate
+    is tau_M e_z with tau_1 = 2/3, tau_2 = 10/9, tau_4 = 82/81 (the value's
+    factors, Sec. 4.1.2), through the hypersingular kernel grad dG/dn_y."""
+    om = oracle.OracleMesh(I.icosphere(6))
+    pts = I.ball_points(16, 0.5, 9)
+    bc = oracle.make_bc(1, oracle.DOUBLE_LAYER, oracle.PROG_LINEAR, (0.0, 0.0, 1.0, 0.0))
+    ref = np.tile([0.0, 0.0, 1.0], (16, 1))
+    for M, tau in ((1, 2 / 3), (2, 10 / 9), (4, 82 / 81)):
+        N = 4000
+        _, _, g, gv = oracle.solve_grad(om, pts, bc, N, M, 3 + M)
+        est, se = _fit(g, gv, ref, N)
+        assert abs(est - tau) < 4 * se + 0.01, (M, est, tau, se)
+        # the other components vanish
+        assert np.all(np.abs(g[:, :2]) < 4.5 * np.sqrt(gv[:, :2] / N) + 0.01)
+
+
+def test_double_layer_gradient_circle():
+    """Interior Dirichlet on the 256-gon with u = x^2 - y^2: grad u = (2x, -2y)
+    scaled by tau_1 = 1/2 and tau_M = 1 for M >= 2 (the double-layer kernel is
+    constant on a circle)."""
+    om = oracle.OracleMesh(I.circle_polygon(256))
+    pts = I.disk_points(16, 0.7, 4)
+    bc = oracle.make_bc(1, oracle.DOUBLE_LAYER, oracle.PROG_QUAD, ())
+    ref = np.stack([2 * pts[:, 0], -2 * pts[:, 1]], axis=1)
+    for M, tau in ((1, 0.5), (3, 1.0)):
+        N = 4000
+        _, _, g, gv = oracle.solve_grad(om, pts, bc, N, M, 7)
+        est, se = _fit(g, gv, ref, N)
+        assert abs(est - tau) < 4 * se + 0.01, (M, est, tau, se)
+
+
+@pytest.mark.parametrize("name,form,sampling,N", [
+    ("single layer, lines", oracle.SINGLE_LAYER, oracle.SAMPLE_LINE, 20000),
+    ("single layer, RIS", oracle.SINGLE_LAYER, oracle.SAMPLE_RIS, 6000),
+    ("direct BIE", oracle.DIRECT, oracle.SAMPLE_LINE, 6000),
+])
+def test_neumann_gradient_exterior_monopole(name, form, sampling, N):
+    """Exterior Neumann, u = 1/|x| on a sphere (lambda_0 = -1: exact for every
+    M): grad u = -x / |x|^3 per point and component within 4.5 SE (the single
+    layer's first weight has an infinite-variance tail, hence more paths)."""
+    s = I.icosphere(6)
+    mesh = I.Mesh(3, s.verts, s.prims, np.full(s.n_prims, 1, np.uint8))
+    om = oracle.OracleMesh(mesh)
+    pts = I.ball_points(12, 2.5, 3, r_min=1.5)
+    bc = oracle.make_bc(-1, form, oracle.PROG_INVDIST, (0.0, 0.0, 0.0), sampling=sampling)
+    _, _, g, gv = oracle.solve_grad(om, pts, bc, N, 3, 6)
+    exact = -pts / np.linalg.norm(pts, axis=1)[:, None] ** 3
+    z = (g - exact) / np.sqrt(gv / N)
+    assert np.max(np.abs(z)) < 4.5, (name, z)
+    assert abs(np.sum(g * exact) / np.sum(exact * exact) - 1.0) < 0.03, name
+
+
+def test_gradient_matches_finite_differences():
+    """A perturbed sphere, interior Dirichlet with off-centre data, M = 3: the
+    mean gradient equals the central difference (h = 0.02) of the mean value
+    along each axis, the two sides of the difference sharing their paths."""
+    mesh = I.perturb_radial(I.icosphere(6), 0.1, 2, 3)
+    om = oracle.OracleMesh(mesh)
+    bc = oracle.make_bc(1, oracle.DOUBLE_LAYER, oracle.PROG_INVDIST, (2.0, 0.5, 0.0))
+    x0 = np.array([[0.2, -0.1, 0.15], [-0.3, 0.25, -0.1]])
+    N, M, h = 20000, 3, 0.02
+    _, _, g, gv = oracle.solve_grad(om, x0, bc, N, M, 9)
+    for p in range(2):
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            pts = np.stack([x0[p] + e, x0[p] - e])
+            items = np.arange(N)
+            vp = oracle.trace(om, pts, None, bc, M, 9, np.zeros(N, np.int64), items, want_pos=False)["value"]
+            vm = oracle.trace(om, pts, None, bc, M, 9, np.ones(N, np.int64), items, want_pos=False)["value"]
+            d = (vp - vm) / (2 * h)
+            fd, fd_se = d.mean(), d.std(ddof=1) / np.sqrt(N)
+            z = (g[p, a] - fd) / np.sqrt(gv[p, a] / N + fd_se ** 2)
+            assert abs(z) < 4.5, (p, a, g[p, a], fd, z)
+
+
+def test_gradient_paths_keep_their_values():
+    """The value of every path is unchanged by the gradient bookkeeping, and
+    the per-path records agree with the solve's statistics."""
+    mesh = I.perturb_radial(I.icosphere(5), 0.1, 2, 3)
+    om = oracle.OracleMesh(mesh)
+    pts = I.ball_points(5, 0.6, 2)
+    for form, prog, dom, params in ((oracle.DOUBLE_LAYER, oracle.PROG_INVDIST, 1, (2.0, 0.5, 0.0)),):
+        bc = oracle.make_bc(dom, form, prog, params)
+        N, M = 64, 3
+        ip = np.repeat(np.arange(5), N)
+        ik = np.tile(np.arange(N), 5)
+        t = oracle.trace(om, pts, None, bc, M, 4, ip, ik, want_pos=False)
+        tg = oracle.trace_grad(om, pts, bc, M, 4, ip, ik)
+        assert np.array_equal(t["value"], tg["value"])
+        mean, var, g, gv = oracle.solve_grad(om, pts, bc, N, M, 4)
+        assert np.allclose(g, tg["grad"].reshape(5, N, 3).mean(axis=1), rtol=1e-12, atol=1e-14)
+        assert np.allclose(mean, t["value"].reshape(5, N).mean(axis=1), rtol=1e-12, atol=1e-14)
+
+
+def test_gradient_rejects_density_mode():
+    om = oracle.OracleMesh(I.icosphere(2))
+    bc = oracle.make_bc(1, oracle.DOUBLE_LAYER, oracle.PROG_CONST, (1.0,), density=True)
+    with pytest.raises(ValueError):
+        oracle.solve_grad(om, np.zeros((1, 3)), bc, 4, 2, 1)
