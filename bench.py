@@ -23,7 +23,9 @@ Two more legs are reported in the same line (each with its own timing):
   forward   - exterior Neumann data concentrated near one spot of the same
               tori: the forward (adjoint) estimator with every point connected
               to every path vertex against the backward walks at equal wall
-              time, and the throughput of its two kernels.
+              time, and the throughput of its two kernels;
+  grad      - value and gradient along the same paths on the main workload:
+              cost relative to the value alone, gradient error.
 """
 import argparse
 import json
@@ -84,8 +86,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--cpu-sample-points", type=int, default=640)
     p.add_argument("--skip-cpu-baseline", action="store_true")
-    p.add_argument("--legs", default="main,batched,cv,forward",
-                   help="comma-separated subset of main, batched, cv, forward")
+    p.add_argument("--legs", default="main,batched,cv,forward,grad",
+                   help="comma-separated subset of main, batched, cv, forward, grad")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device once (a kernel of known "
                         "traffic that calibrates hardware byte counters)")
@@ -380,6 +382,40 @@ def forward_leg(torch, wob, I):
     return out
 
 
+def grad_leg(torch, wob, I):
+    """Value and gradient along the same paths on the benchmark workload
+    (icosphere slice, 167,604 points x 256 paths x 6 lines): the time of
+    wob_solve_grad against wob_solve, and the gradient error against the
+    analytic gradient of g = 1/|x - x0|."""
+    w = I.config_icosphere_slice()
+    scene = wob.Scene(w.mesh, wob.F32)
+    bc = wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"]))
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device="cuda")
+    N, M = w.samples, w.walk_len
+    wob.solve_grad(scene, pts[:4096].contiguous(), bc, 16, M)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(st)
+    m0, _ = wob.solve(scene, pts, bc, N, M, w.seed)
+    ev[1].record(st)
+    mean, var, g, gv = wob.solve_grad(scene, pts, bc, N, M, w.seed)
+    ev[2].record(st)
+    torch.cuda.synchronize()
+    t_val = ev[0].elapsed_time(ev[1])
+    t_grad = ev[1].elapsed_time(ev[2])
+    x0 = np.array(w.bc["params"])
+    r = w.points - x0
+    exact = -r / np.linalg.norm(r, axis=1)[:, None] ** 3
+    gn = g.double().cpu().numpy()
+    err = np.linalg.norm(gn - exact, axis=1)
+    scene.close()
+    return {"workload": w.name, "solve_ms": t_val, "solve_grad_ms": t_grad, "cost_ratio": t_grad / t_val,
+            "grad_rmse": float(np.sqrt(np.mean(err ** 2))), "grad_median_err": float(np.median(err)),
+            "grad_rms_exact": float(np.sqrt(np.mean(np.sum(exact ** 2, axis=1)))),
+            "value_rmse": float(np.sqrt(np.mean((mean.double().cpu().numpy() - w.exact) ** 2)))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -393,12 +429,12 @@ def main():
     torch.cuda.set_device(0)
     legs = set(args.legs.split(","))
     extra = {}
-    if "batched" in legs:
-        extra["batched"] = batched_leg(torch, wob, I)
-    if "cv" in legs:
-        extra["cv_equal_time"] = cv_leg(torch, wob, I)
-    if "forward" in legs:
-        extra["forward_equal_time"] = forward_leg(torch, wob, I)
+    for leg, key, fn in (("batched", "batched", batched_leg), ("cv", "cv_equal_time", cv_leg),
+                         ("forward", "forward_equal_time", forward_leg), ("grad", "gradient", grad_leg)):
+        if leg in legs:
+            t0 = time.perf_counter()
+            extra[key] = fn(torch, wob, I)
+            print(f"[bench] {leg} leg done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     w = I.config_icosphere_slice()
     scene = wob.Scene(w.mesh, wob.F32)
     info = scene.info()

@@ -204,6 +204,34 @@ wob_status wob_count_work(wob_scene scene, const void* points, const int32_t* po
                           int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
                           uint64_t seed, uint64_t* counters, void* stream);
 
+/* Gradient of the solution at points inside the domain, estimated along the
+ * same paths as the value (Sec. 4.4, gradient estimation: the first step's
+ * kernel replaced by its gradient in x0, the rest of each path unchanged;
+ * the gradient equations of the three formulations).  Per path the gradient
+ * is W' times the path's remaining sum, with, for the step from x0 to the
+ * picked hit y (rhat = (y - x0) / rho, c = rhat . n_y, m hits):
+ *   double layer  -grad_x dG/dn_y / p = -m (n_y - D c rhat) / (2 rho |c|)
+ *   direct BIE    phi times the same, plus phi grad_x G q / p_all summed
+ *                 over the hits of line 0 for the source (q sgn(t) d / (2|c|))
+ *   single layer  grad_x G / p = m rhat / (2 |c|)  (RIS: grad_x G / |G| S |Gamma| / C)
+ * The double-layer and direct kernels are hypersingular (1 / |c|): noisier
+ * near the boundary, as the paper observes.  Every point must lie off the
+ * boundary (no point_prim argument); no density mode.
+ *   points        DEVICE, n_points * dim
+ *   mean_out, var_out   as wob_solve (var_out may be NULL)
+ *   grad_out      DEVICE, n_points * dim: mean gradient, point-major
+ *   grad_var_out  DEVICE, n_points * dim: variance of each component, or NULL
+ * Errors: WOB_E_ARG, WOB_E_UNSUPPORTED, WOB_E_DEVICE. */
+wob_status wob_solve_grad(wob_scene scene, const void* points, int64_t n_points, const wob_bc* bc,
+                          int32_t samples, int32_t walk_len, uint64_t seed, void* mean_out, void* var_out,
+                          void* grad_out, void* grad_var_out, void* stream);
+
+/* Per-path values (n_points * samples) and gradients (n_points * samples * dim)
+ * of the estimator of wob_solve_grad (the same paths). */
+wob_status wob_trace_grad(wob_scene scene, const void* points, int64_t n_points, const wob_bc* bc,
+                          int32_t samples, int32_t walk_len, uint64_t seed, void* path_out,
+                          void* path_grad_out, void* stream);
+
 const char* wob_status_string(wob_status status);
 
 /* ------------------------------------------------------------------------- */

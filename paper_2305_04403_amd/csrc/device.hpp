@@ -344,6 +344,7 @@ struct HitAcc {
   R u, v;     // barycentric coordinates of the selected hit
   R t;        // its line parameter: y - x = t d, so rhat = sign(t) d and rho = |t|
   R src;      // direct BIE: sum over hits of G q / p_all
+  R srcg[3];  // gradient walk, direct BIE, line 0: sum over hits of grad_x G q / p_all
 };
 
 // Test one primitive against the line x + t d (t real, inclusive edges).

@@ -34,6 +34,9 @@ struct WalkArgs {
   R* mean_out;
   R* var_out;
   R* path_out;
+  R* grad_out;                // gradient walk: per point, D components of the mean gradient
+  R* grad_var_out;            // and their variances (or null)
+  R* path_grad_out;           // gradient walk, trace mode: per path, D components
   int32_t* vtx_prim;
   int32_t* vtx_m;
   unsigned long long* counters;
@@ -69,6 +72,10 @@ struct WalkArgs {
 
 enum { ST_NONE = 0, ST_LINE = 1, ST_DONE = 2 };
 
+// Extensions of the walk: the corrected walk of the control variate, and the
+// gradient in the evaluation point carried along the same paths.
+enum Ext { X_NONE = 0, X_CV = 1, X_GRAD = 2 };
+
 // Single-layer emission at vertex y on primitive g, before the running
 // weight: 2 phi s(y) on Neumann / Robin parts (Table 1), k u_D(y) on Dirichlet
 // parts (eq. mixed_second_kind_ish); half of it at the last vertex x_M.
@@ -98,6 +105,7 @@ struct PathState {
   R d[3], inv[3], ox[3];
   HitAcc<R> h;
   int32_t ni;            // traversal position (node index)
+  R Wg[3], gacc[3];      // gradient walk: d W / d x0 and the gradient sum
 };
 
 // Forward walk: vertex k of the current path, (y_k, c_{k-1} W_k) with
@@ -138,7 +146,7 @@ __device__ __forceinline__ void fwd_end(const WalkArgs<R, D>& a, const PathState
 // candidate j when u_j S_j < |k_j|; weight sign(k) S |Gamma| / C.  Moves the
 // path to the kept point and adds its emission; returns false when no
 // candidate carries kernel mass (the path ends).
-template <typename R, int D, bool TRACE>
+template <typename R, int D, bool TRACE, bool GRAD>
 __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D>& s) {
   const SceneView<R, D>& sc = a.scene;
   const R phi = a.phi;
@@ -198,6 +206,21 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
   }
   if (lpick < 0 || !(S > (R)0)) return false;
   const R w = (kpick > (R)0 ? (R)1 : (R)-1) * S * sc.area_total / (R)a.ris_c;
+  if constexpr (GRAD) {
+    if (s.first) {
+      // RIS estimate of int grad_x G mu: grad_x G(y) / |G(y)| S |Gamma| / C,
+      // grad_x G = r / (S_D rho^D), r = y - x
+      const R r[3] = {ypick[0] - s.x[0], ypick[1] - s.x[1], D == 3 ? ypick[2] - s.x[2] : (R)0};
+      const R rr = dot3(r, r);
+      const R gr = (D == 3 ? inv4pi / (rr * sqrt(rr)) : inv2pi / rr) * S * sc.area_total /
+                   ((R)a.ris_c * fabs(kpick));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s.Wg[k] = s.Wg[k] * w + s.W * gr * r[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s.Wg[k] *= w;
+    }
+  }
   s.W *= w;
   s.x[0] = ypick[0];
   s.x[1] = ypick[1];
@@ -207,12 +230,18 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
   R nn[3];
   load_normal<R, D>(sc, lpick, nn);
   if (TRACE && s.vp) s.vp[s.i] = gn.id;
-  s.acc += s.W * sl_emission<R, D>(a, gn, nn, s.x, s.i + 1 >= a.M);
+  const R e = sl_emission<R, D>(a, gn, nn, s.x, s.i + 1 >= a.M);
+  s.acc += s.W * e;
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.gacc[k] += s.Wg[k] * e;
+  }
   return true;
 }
 
-template <typename R, int D, int FORM, bool TRACE, bool COUNT, bool CV>
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
 __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, D>& s, WorkCount& wc) {
+  constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
   const R phi = a.phi;
   for (;;) {
     if (s.i >= a.L) return ST_DONE;
@@ -249,16 +278,25 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
         r0 = philox(s.path, s.point, s.z, 0u, a.k0, a.k1);
         have_r0 = true;
         if ((r0.w >> 8) >= a.mixed_thr) {
-          s.W *= (R)1 / ((R)1 - a.mixed_p);
+          const R ws = (R)1 / ((R)1 - a.mixed_p);
+          s.W *= ws;
           if (TRACE && s.vp) s.vp[s.i] = -2 - s.gc.id;
-          s.acc += s.W * sl_emission<R, D>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
+          const R e = sl_emission<R, D>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
+          s.acc += s.W * e;
+          if constexpr (GRAD) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              s.Wg[k] *= ws;
+              s.gacc[k] += s.Wg[k] * e;
+            }
+          }
           ++s.i;
           continue;
         }
         s.gscale = -a.mixed_k / a.mixed_p;
       }
       if constexpr (FORM == F_SL_RIS) {
-        if (!ris_step<R, D, TRACE>(a, s)) return ST_DONE;
+        if (!ris_step<R, D, TRACE, GRAD>(a, s)) return ST_DONE;
         ++s.i;
         continue;
       }
@@ -284,7 +322,15 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
       s.x[1] = y[1];
       s.x[2] = y[2];
       // emission at the new vertex (same primitive)
-      s.acc += s.W * sl_emission<R, D>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
+      const R e = sl_emission<R, D>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
+      s.acc += s.W * e;
+      if constexpr (GRAD) {  // a vertex on the boundary: never the first step
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          s.Wg[k] *= w;
+          s.gacc[k] += s.Wg[k] * e;
+        }
+      }
       ++s.i;
       continue;
     }
@@ -303,15 +349,17 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     s.h.idx = -1;
     s.h.u = s.h.v = s.h.t = 0;
     s.h.src = 0;
+    if constexpr (GRAD) s.h.srcg[0] = s.h.srcg[1] = s.h.srcg[2] = 0;
     s.ni = 0;
     if (COUNT) wc.lines += 1;
     return ST_LINE;
   }
 }
 
-template <typename R, int D, int FORM, bool TRACE, bool COUNT, bool CV>
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
 __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, D>& s, uint32_t path,
                                           int64_t item, WorkCount& wc) {
+  constexpr bool GRAD = EXT == X_GRAD;
   s.path = path;
   if constexpr (FORM == F_FWD) {
     // y_1 on the boundary: primitive T from the start table (Philox
@@ -353,7 +401,7 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
     s.i = 0;
     s.cur_idx = leaf;
     fwd_record<R, D>(a, s, 0, g.id, 0);
-    return begin_step<R, D, FORM, TRACE, COUNT, CV>(a, s, wc);
+    return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
   }
   if (TRACE) {
     s.vp = a.vtx_prim ? a.vtx_prim + item * a.L : nullptr;
@@ -382,16 +430,21 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
   s.W = 1;
   s.acc = 0;
   s.i = 0;
-  return begin_step<R, D, FORM, TRACE, COUNT, CV>(a, s, wc);
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.Wg[k] = s.gacc[k] = 0;
+  }
+  return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
 // The primitives of one crossed leaf of the current line.  Per hit: count
 // it; with `select`, draw its key (Philox block 2, w = caller id) and keep the
 // smallest (key, id); for the direct BIE add G q / p_all to the source sum;
 // for the corrected walk add a(h) F(y_h).
-template <typename R, int D, int FORM, bool COUNT, bool CV>
+template <typename R, int D, int FORM, bool COUNT, int EXT>
 __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, D>& s, int32_t code,
                                           WorkCount& wc) {
+  constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
   const SceneView<R, D>& sc = a.scene;
   {
     const int32_t first = code >> 3, count = (code & 7) + 1;
@@ -428,6 +481,15 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
         // G q / p_all: 3D rho q / (2 |c|); 2D -rho ln(rho) q / (2 |c|)
         const R gp = D == 3 ? rho / ((R)2 * ac) : -rho * log(rho) / ((R)2 * ac);
         s.h.src += gp * q;
+        if constexpr (GRAD) {
+          // grad_x G q / p_all = q sgn(t) d / (2 |c|) in 2D and 3D (line 0 only:
+          // later sources do not depend on x0)
+          if (s.i == 0) {
+            const R gq = (t > (R)0 ? q : -q) / ((R)2 * ac);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s.h.srcg[k] += gq * s.d[k];
+          }
+        }
       }
       if constexpr (CV && FORM == F_SL && D == 3) {
         if (s.sum) {
@@ -450,8 +512,9 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
   }
 }
 
-template <typename R, int D, int FORM, bool TRACE, bool COUNT, bool CV>
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
 __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>& s, WorkCount& wc) {
+  constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
   const R phi = a.phi;
   HitAcc<R>& h = s.h;
   if (TRACE) {
@@ -468,7 +531,14 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     } else {
       S = phi * h.src;
     }
-    s.acc += s.W * S * (s.last ? (R)0.5 : (R)1);
+    const R cl = s.last ? (R)0.5 : (R)1;
+    s.acc += s.W * S * cl;
+    if constexpr (GRAD) {
+      // line 0 from x0 off the boundary: the source phi int G q depends on x0
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        s.gacc[k] += (s.Wg[k] * S + (s.i == 0 ? s.W * phi * h.srcg[k] : (R)0)) * cl;
+    }
     if (s.last) return ST_DONE;
   }
   if (h.m == 0) {
@@ -512,6 +582,32 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     if (s.mixture) w /= ((R)1 - a.self_p);
   }
   if (CV && s.i > 0) s.acc += s.W * h.src;  // all-hits sum of a(h) F(y_h), emissions included
+  if constexpr (GRAD) {
+    if (s.i == 0) {
+      // line 0 from x0 off the boundary: w' = grad_x kernel / p, with
+      // rhat = sgn(t) d, rho = |t|, c = rhat . n_y (2D and 3D alike):
+      //   single layer  grad G / p           = m rhat / (2 |c|)
+      //   double layer  -grad dG/dn_y / p    = -m (n_y - D c rhat) / (2 rho |c|)
+      //   direct BIE    -phi grad dG/dn_y / p (the same times phi)
+      R n[3], wg[3];
+      load_normal<R, D>(a.scene, h.idx, n);
+      const R c = sgn_t * dot3(s.d, n), ac = fabs(c), rho = fabs(h.t);
+      if constexpr (is_sl(FORM)) {
+        const R f = s.gscale * mm * sgn_t / ((R)2 * ac);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wg[k] = f * s.d[k];
+      } else {
+        const R f = (FORM == F_DL ? (R)-1 : -phi) * mm / ((R)2 * rho * ac);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wg[k] = f * (n[k] - (R)D * c * sgn_t * s.d[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s.Wg[k] = s.Wg[k] * w + s.W * wg[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s.Wg[k] *= w;
+    }
+  }
   s.W *= w;
   s.x[0] = y[0];
   s.x[1] = y[1];
@@ -527,15 +623,24 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
       s.acc -= s.W * a.cv_g[gy.id];
     }
   } else if constexpr (is_sl(FORM)) {
-    s.acc += s.W * sl_emission<R, D>(a, gy, ny, s.x, s.i + 1 >= a.M);
+    const R e = sl_emission<R, D>(a, gy, ny, s.x, s.i + 1 >= a.M);
+    s.acc += s.W * e;
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s.gacc[k] += s.Wg[k] * e;
+    }
   } else if constexpr (FORM == F_DL) {
-    const R sv = boundary_datum<R, D>(a.prog, gy, ny, s.x);
-    s.acc += s.W * ((s.i + 1 < a.M) ? (R)2 * phi : phi) * sv;
+    const R e = ((s.i + 1 < a.M) ? (R)2 * phi : phi) * boundary_datum<R, D>(a.prog, gy, ny, s.x);
+    s.acc += s.W * e;
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s.gacc[k] += s.Wg[k] * e;
+    }
   } else if constexpr (FORM == F_FWD) {
     fwd_record<R, D>(a, s, s.i + 1, gy.id, h.m);
   }
   ++s.i;
-  return begin_step<R, D, FORM, TRACE, COUNT, CV>(a, s, wc);
+  return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
 
@@ -569,17 +674,26 @@ __device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, 
 
 // One block's share of a solve: BLOCK lanes cover BLOCK >> lpp_shift points,
 // the N paths of a point on 1 << lpp_shift consecutive lanes (a lane loops over
-// paths k, k + lpp, ...).  `red` is BLOCK / 64 x 3 doubles of LDS.
-template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK, bool CV = false>
-__device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t block_index,
-                                           double (*red)[3]) {
+// paths k, k + lpp, ...).  `red` is BLOCK / 64 x red_stride<EXT, D>() doubles
+// of LDS.
+template <int EXT, int D>
+constexpr int red_stride() { return EXT == X_GRAD ? 3 + 2 * D : 3; }
+
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK, int EXT = X_NONE>
+__device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t block_index, double* red) {
   const int tid = threadIdx.x;
   const int lpp = 1 << a.lpp_shift;
   const int64_t point = block_index * (BLOCK >> a.lpp_shift) + (tid >> a.lpp_shift);
   const int lane_in_point = tid & (lpp - 1);
   double n = 0.0, mean = 0.0, m2 = 0.0;
+  constexpr bool GRAD = EXT == X_GRAD;
+  constexpr int GD = GRAD ? D : 1;  // gradient statistics per component (unused otherwise)
+  double gmean[GD], gm2[GD];
+#pragma unroll
+  for (int c = 0; c < GD; ++c) gmean[c] = gm2[c] = 0.0;
   WorkCount wc = {0, 0, 0, 0};
-  constexpr bool KCV = CV && D == 3 && FORM == F_SL;
+  // the corrected walk exists for the 3D single layer only
+  constexpr int KEXT = EXT == X_CV ? ((D == 3 && FORM == F_SL) ? X_CV : X_NONE) : EXT;
   {
     // Paths k = lane_in_point, + lpp, ... of this lane, run as one state
     // machine.  Lanes step through BVH nodes; a lane that reaches a crossed
@@ -603,7 +717,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         s.prim0 = a.point_prim ? a.point_prim[point] : -1;
         s.point = a.point_ids ? a.point_ids[point] : (uint32_t)point;
       }
-      if (k < a.N) st = start_path<R, D, FORM, TRACE, COUNT, KCV>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc);
+      if (k < a.N) st = start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc);
     }
     for (;;) {
       // finished paths: record, start the lane's next one
@@ -614,8 +728,17 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         const double dv = (double)v - mean;
         mean += dv / n;
         m2 += dv * ((double)v - mean);
+        if constexpr (GRAD) {
+#pragma unroll
+          for (int c = 0; c < GD; ++c) {
+            if (TRACE) a.path_grad_out[(point * (int64_t)a.N + k) * D + c] = s.gacc[c];
+            const double dg = (double)s.gacc[c] - gmean[c];
+            gmean[c] += dg / n;
+            gm2[c] += dg * ((double)s.gacc[c] - gmean[c]);
+          }
+        }
         k += lpp;
-        st = k < a.N ? start_path<R, D, FORM, TRACE, COUNT, KCV>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc)
+        st = k < a.N ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc)
                      : ST_NONE;
       }
       const int idle = __popcll(__ballot(st == ST_NONE));
@@ -649,7 +772,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       }
       // the parked lanes test their leaves together
       if (pend >= 0) {
-        leaf_work<R, D, FORM, COUNT, KCV>(a, s, pend, wc);
+        leaf_work<R, D, FORM, COUNT, KEXT>(a, s, pend, wc);
         pend = -1;
       }
       // path steps run once a quarter of the working lanes stand at the end of
@@ -659,7 +782,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       const int n_end = __popcll(__ballot(at_end));
       const int stepping = __popcll(__ballot(st == ST_LINE && s.ni < nn));
       if (4 * n_end >= 64 - idle || stepping == 0) {
-        if (at_end) st = end_step<R, D, FORM, TRACE, COUNT, KCV>(a, s, wc);
+        if (at_end) st = end_step<R, D, FORM, TRACE, COUNT, KEXT>(a, s, wc);
       }
     }
   }
@@ -676,11 +799,29 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
 
   // per-point reduction: within the point's lanes of the wavefront, then across
   // the point's wavefronts
+  // (the gradient components merge with the same counts, in the same order)
   for (int off = (lpp < 64 ? lpp : 64) >> 1; off > 0; off >>= 1) {
     const double nb = __shfl_xor(n, off, 64);
     const double mb = __shfl_xor(mean, off, 64);
     const double sb = __shfl_xor(m2, off, 64);
-    if (((tid & 63) & off) == 0) {
+    const bool low = ((tid & 63) & off) == 0;
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int c = 0; c < GD; ++c) {
+        const double gmb = __shfl_xor(gmean[c], off, 64);
+        const double gsb = __shfl_xor(gm2[c], off, 64);
+        double n1 = n, n2 = nb;
+        if (low) {
+          chan_merge(n1, gmean[c], gm2[c], nb, gmb, gsb);
+        } else {
+          double mean2 = gmb, m22 = gsb;
+          chan_merge(n2, mean2, m22, n, gmean[c], gm2[c]);
+          gmean[c] = mean2;
+          gm2[c] = m22;
+        }
+      }
+    }
+    if (low) {
       chan_merge(n, mean, m2, nb, mb, sb);
     } else {
       double n2 = nb, mean2 = mb, m22 = sb;
@@ -694,29 +835,56 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     if (lane_in_point == 0 && point < a.n_points) {
       a.mean_out[point] = (R)mean;
       if (a.var_out) a.var_out[point] = (R)(n > 1.0 ? m2 / (n - 1.0) : 0.0);
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int c = 0; c < GD; ++c) {
+          a.grad_out[point * D + c] = (R)gmean[c];
+          if (a.grad_var_out) a.grad_var_out[point * D + c] = (R)(n > 1.0 ? gm2[c] / (n - 1.0) : 0.0);
+        }
+      }
     }
     return;
   }
+  constexpr int RS = red_stride<EXT, D>();
   const int wave = tid >> 6;
   if ((tid & 63) == 0) {
-    red[wave][0] = n;
-    red[wave][1] = mean;
-    red[wave][2] = m2;
+    red[wave * RS + 0] = n;
+    red[wave * RS + 1] = mean;
+    red[wave * RS + 2] = m2;
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int c = 0; c < GD; ++c) {
+        red[wave * RS + 3 + 2 * c] = gmean[c];
+        red[wave * RS + 4 + 2 * c] = gm2[c];
+      }
+    }
   }
   __syncthreads();
   if (lane_in_point == 0 && point < a.n_points) {
     const int waves = lpp >> 6;
-    double tn = red[wave][0], tm = red[wave][1], ts = red[wave][2];
-    for (int w = 1; w < waves; ++w) chan_merge(tn, tm, ts, red[wave + w][0], red[wave + w][1], red[wave + w][2]);
+    double tn = red[wave * RS + 0], tm = red[wave * RS + 1], ts = red[wave * RS + 2];
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int c = 0; c < GD; ++c) {
+        double gn = tn, gm = red[wave * RS + 3 + 2 * c], gs = red[wave * RS + 4 + 2 * c];
+        for (int w = 1; w < waves; ++w)
+          chan_merge(gn, gm, gs, red[(wave + w) * RS + 0], red[(wave + w) * RS + 3 + 2 * c],
+                     red[(wave + w) * RS + 4 + 2 * c]);
+        a.grad_out[point * D + c] = (R)gm;
+        if (a.grad_var_out) a.grad_var_out[point * D + c] = (R)(gn > 1.0 ? gs / (gn - 1.0) : 0.0);
+      }
+    }
+    for (int w = 1; w < waves; ++w)
+      chan_merge(tn, tm, ts, red[(wave + w) * RS + 0], red[(wave + w) * RS + 1], red[(wave + w) * RS + 2]);
     a.mean_out[point] = (R)tm;
     if (a.var_out) a.var_out[point] = (R)(tn > 1.0 ? ts / (tn - 1.0) : 0.0);
   }
 }
 
-template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK, bool CV = false>
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK, int EXT = X_NONE>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs<R, D> a) {
-  __shared__ double red[BLOCK / 64][3];
-  walk_block<R, D, FORM, TRACE, COUNT, BLOCK, CV>(a, blockIdx.x, red);
+  __shared__ double red[(BLOCK / 64) * red_stride<EXT, D>()];
+  walk_block<R, D, FORM, TRACE, COUNT, BLOCK, EXT>(a, blockIdx.x, red);
 }
 
 // Add-back of the control variate: out[p] (+)= an unbiased value of
@@ -901,7 +1069,7 @@ __global__ void __launch_bounds__(BLOCK) batch_kernel(const WalkArgs<R, D>* __re
                                                       const int64_t* __restrict__ tile_off,
                                                       int32_t n_probs, int64_t stride,
                                                       unsigned long long* __restrict__ counter) {
-  __shared__ double red[BLOCK / 64][3];
+  __shared__ double red[(BLOCK / 64) * 3];
   __shared__ long long s_tile;
   const int64_t n_tiles = tile_off[n_probs];
   for (;;) {

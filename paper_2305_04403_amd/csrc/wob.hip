@@ -151,14 +151,23 @@ void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
   constexpr int B = kSolveBlock;
   const int ppb = B >> a.lpp_shift;
   const dim3 grid((unsigned)((a.n_points + ppb - 1) / ppb)), block(B);
+  if constexpr (FORM != wob::F_FWD) {
+    if (a.grad_out || a.path_grad_out) {  // value and gradient along the same paths
+      if (mode == MODE_TRACE)
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_GRAD>), grid, block, 0, st, a);
+      else
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_GRAD>), grid, block, 0, st, a);
+      return;
+    }
+  }
   if constexpr (D == 3 && FORM == wob::F_SL) {
     if (a.cv_g) {
       if (mode == MODE_SOLVE)
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_CV>), grid, block, 0, st, a);
       else if (mode == MODE_TRACE)
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_CV>), grid, block, 0, st, a);
       else
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B, wob::X_CV>), grid, block, 0, st, a);
       return;
     }
   }
@@ -182,13 +191,19 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
                     const wob_bc* bc, int32_t samples, int32_t walk_len, uint64_t seed,
                     const uint32_t* point_ids, void* mean_out, void* var_out, void* path_out,
                     int32_t* vtx_prim, int32_t* vtx_m, uint64_t* counters, int mode,
-                    void* stream, const float* cv_g = nullptr, const float* cv_g0 = nullptr) {
+                    void* stream, const float* cv_g = nullptr, const float* cv_g0 = nullptr,
+                    void* grad_out = nullptr, void* grad_var_out = nullptr, void* path_grad_out = nullptr) {
   Plan pl;
   wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
   if (s != WOB_OK) return s;
   if (cv_g && (sc->dim != 3 || sc->precision != WOB_F32 || pl.form != WOB_F_SINGLE_LAYER ||
                bc->density || pl.ris_c > 0 || sc->n_dirichlet > 0))
     return WOB_E_UNSUPPORTED;
+  const bool grad = grad_out || path_grad_out;
+  // gradients: evaluation points inside the domain, no density mode, no control variate
+  if (grad && (point_prim || bc->density || cv_g)) return WOB_E_UNSUPPORTED;
+  if (grad && mode == MODE_SOLVE && n_points > 0 && !grad_out) return WOB_E_ARG;
+  if (mode == MODE_SOLVE && grad_var_out && samples < 2) return WOB_E_ARG;
   if (n_points < 0 || (n_points > 0 && !points)) return WOB_E_ARG;
   if (n_points >= (int64_t)1 << 32) return WOB_E_ARG;  // point index is a 32-bit counter word
   if (mode == MODE_SOLVE && n_points > 0 && !mean_out) return WOB_E_ARG;
@@ -201,6 +216,7 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
     if (sc->dim == 3) {
       auto a = make_args<float, 3>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
       a.mean_out = (float*)mean_out; a.var_out = (float*)var_out; a.path_out = (float*)path_out;
+      a.grad_out = (float*)grad_out; a.grad_var_out = (float*)grad_var_out; a.path_grad_out = (float*)path_grad_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
       a.cv_g = cv_g;
@@ -209,6 +225,7 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
     } else {
       auto a = make_args<float, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
       a.mean_out = (float*)mean_out; a.var_out = (float*)var_out; a.path_out = (float*)path_out;
+      a.grad_out = (float*)grad_out; a.grad_var_out = (float*)grad_var_out; a.path_grad_out = (float*)path_grad_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
       launch_walk<float, 2>(a, mode, st);
@@ -217,12 +234,14 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
     if (sc->dim == 3) {
       auto a = make_args<double, 3>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
       a.mean_out = (double*)mean_out; a.var_out = (double*)var_out; a.path_out = (double*)path_out;
+      a.grad_out = (double*)grad_out; a.grad_var_out = (double*)grad_var_out; a.path_grad_out = (double*)path_grad_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
       launch_walk<double, 3>(a, mode, st);
     } else {
       auto a = make_args<double, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
       a.mean_out = (double*)mean_out; a.var_out = (double*)var_out; a.path_out = (double*)path_out;
+      a.grad_out = (double*)grad_out; a.grad_var_out = (double*)grad_var_out; a.path_grad_out = (double*)path_grad_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
       launch_walk<double, 2>(a, mode, st);
@@ -381,6 +400,24 @@ wob_status wob_trace(wob_scene sc, const void* points, const int32_t* point_prim
                      void* stream) {
   return run_walk(sc, points, point_prim, n_points, bc, samples, walk_len, seed, point_ids, nullptr,
                   nullptr, path_out, vtx_prim, vtx_m, nullptr, MODE_TRACE, stream);
+}
+
+wob_status wob_solve_grad(wob_scene sc, const void* points, int64_t n_points, const wob_bc* bc,
+                          int32_t samples, int32_t walk_len, uint64_t seed, void* mean_out, void* var_out,
+                          void* grad_out, void* grad_var_out, void* stream) {
+  if (n_points > 0 && !grad_out) return WOB_E_ARG;
+  return run_walk(sc, points, nullptr, n_points, bc, samples, walk_len, seed, nullptr, mean_out, var_out,
+                  nullptr, nullptr, nullptr, nullptr, MODE_SOLVE, stream, nullptr, nullptr,
+                  n_points > 0 ? grad_out : nullptr, grad_var_out, nullptr);
+}
+
+wob_status wob_trace_grad(wob_scene sc, const void* points, int64_t n_points, const wob_bc* bc,
+                          int32_t samples, int32_t walk_len, uint64_t seed, void* path_out,
+                          void* path_grad_out, void* stream) {
+  if (n_points > 0 && (!path_out || !path_grad_out)) return WOB_E_ARG;
+  return run_walk(sc, points, nullptr, n_points, bc, samples, walk_len, seed, nullptr, nullptr, nullptr,
+                  path_out, nullptr, nullptr, nullptr, MODE_TRACE, stream, nullptr, nullptr, nullptr, nullptr,
+                  n_points > 0 ? path_grad_out : nullptr);
 }
 
 wob_status wob_count_work(wob_scene sc, const void* points, const int32_t* point_prim,

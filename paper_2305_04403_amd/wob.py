@@ -31,7 +31,7 @@ EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_pa
             "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
             "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary",
             "wob_starts_create", "wob_starts_from_data", "wob_starts_free", "wob_forward_paths",
-            "wob_forward_gather")
+            "wob_forward_gather", "wob_solve_grad", "wob_trace_grad")
 
 
 class WobError(RuntimeError):
@@ -128,6 +128,10 @@ def lib():
     L.wob_cv_emission.argtypes = [vp, C.POINTER(_BC), vp, vp, vp]
     for name in ("wob_cv_table", "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission"):
         getattr(L, name).restype = C.c_int
+    L.wob_solve_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
+    L.wob_solve_grad.restype = C.c_int
+    L.wob_trace_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
+    L.wob_trace_grad.restype = C.c_int
     L.wob_starts_create.argtypes = [vp, vp, C.POINTER(vp)]
     L.wob_starts_create.restype = C.c_int
     L.wob_starts_from_data.argtypes = [vp, C.POINTER(_BC), C.c_double, C.POINTER(vp)]
@@ -328,6 +332,37 @@ def forward_gather(scene: Scene, vtx, points, want_var: bool = True, stream=None
                                   _dev_ptr(points), P, _dev_ptr(mean), _dev_ptr(var), _stream(stream))
     _check(st, "wob_forward_gather")
     return mean, var
+
+
+def solve_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
+               want_var: bool = True, stream=None):
+    """Per-point mean value and gradient (and variances) along the same paths
+    (``wob_solve_grad``); points off the boundary."""
+    torch = _torch()
+    P, D = points.shape[0], scene.dim
+    mean = torch.empty(P, dtype=scene.dtype, device=points.device)
+    grad = torch.empty((P, D), dtype=scene.dtype, device=points.device)
+    var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
+    gvar = torch.empty((P, D), dtype=scene.dtype, device=points.device) if want_var else None
+    b = bc.c()
+    st = lib().wob_solve_grad(scene.handle, _dev_ptr(points), P, C.byref(b), int(samples), int(walk_len),
+                              C.c_uint64(seed), _dev_ptr(mean), _dev_ptr(var), _dev_ptr(grad), _dev_ptr(gvar),
+                              _stream(stream))
+    _check(st, "wob_solve_grad")
+    return mean, var, grad, gvar
+
+
+def trace_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0, stream=None):
+    """Per-path values (P, samples) and gradients (P, samples, dim) (``wob_trace_grad``)."""
+    torch = _torch()
+    P, D = points.shape[0], scene.dim
+    path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
+    pg = torch.empty((P, samples, D), dtype=scene.dtype, device=points.device)
+    b = bc.c()
+    st = lib().wob_trace_grad(scene.handle, _dev_ptr(points), P, C.byref(b), int(samples), int(walk_len),
+                              C.c_uint64(seed), _dev_ptr(path), _dev_ptr(pg), _stream(stream))
+    _check(st, "wob_trace_grad")
+    return path, pg
 
 
 def trace(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
