@@ -1026,19 +1026,24 @@ int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim
     double x0[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
     int64_t prim0 = point_prim ? point_prim[p] : -1;
+    /* statistics over the finite path values only: a non-finite path
+       (degenerate geometry, data singular at a boundary point) is left out */
     double* v = (double*)malloc(sizeof(double) * (size_t)samples);
     double sum = 0.0;
+    int n = 0;
     for (int k = 0; k < samples; ++k) {
-      v[k] = one_path(m, normals, &at, bc, form, x0, prim0, walk_len, seed, problem, (uint32_t)p,
-                      (uint32_t)k, NULL, NULL, NULL, NULL, NULL)
-                 .value;
-      sum += v[k];
+      const double val = one_path(m, normals, &at, bc, form, x0, prim0, walk_len, seed, problem,
+                                  (uint32_t)p, (uint32_t)k, NULL, NULL, NULL, NULL, NULL)
+                             .value;
+      if (!isfinite(val)) continue;
+      v[n++] = val;
+      sum += val;
     }
-    double mean = sum / samples;
+    double mean = n > 0 ? sum / n : NAN;
     double ss = 0.0;
-    for (int k = 0; k < samples; ++k) ss += (v[k] - mean) * (v[k] - mean);
+    for (int k = 0; k < n; ++k) ss += (v[k] - mean) * (v[k] - mean);
     mean_out[p] = mean;
-    if (var_out) var_out[p] = samples > 1 ? ss / (samples - 1) : 0.0;
+    if (var_out) var_out[p] = n > 1 ? ss / (n - 1) : 0.0;
     free(v);
   }
   free(normals);
@@ -1294,21 +1299,27 @@ int orc_solve_grad(const orc_mesh* m, const double* points, int64_t n_points, co
   for (int64_t p = 0; p < n_points; ++p) {
     double x0[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < dim; ++a) x0[a] = points[p * dim + a];
+    /* finite paths only (value and every gradient component finite) */
     double* v = (double*)malloc(sizeof(double) * (size_t)samples * (1 + (size_t)dim));
     double* g = v + samples;
-    for (int k = 0; k < samples; ++k)
-      v[k] = one_path(m, normals, &at, bc, form, x0, -1, walk_len, seed, problem, (uint32_t)p, (uint32_t)k,
-                      NULL, NULL, NULL, g + (size_t)k * dim, NULL)
+    int n = 0;
+    for (int k = 0; k < samples; ++k) {
+      v[n] = one_path(m, normals, &at, bc, form, x0, -1, walk_len, seed, problem, (uint32_t)p, (uint32_t)k,
+                      NULL, NULL, NULL, g + (size_t)n * dim, NULL)
                  .value;
+      int finite = isfinite(v[n]);
+      for (int c = 0; c < dim; ++c) finite = finite && isfinite(g[(size_t)n * dim + c]);
+      if (finite) ++n;
+    }
     for (int c = -1; c < dim; ++c) {
       double sum = 0.0, ss = 0.0;
-      for (int k = 0; k < samples; ++k) sum += c < 0 ? v[k] : g[(size_t)k * dim + c];
-      const double mean = sum / samples;
-      for (int k = 0; k < samples; ++k) {
+      for (int k = 0; k < n; ++k) sum += c < 0 ? v[k] : g[(size_t)k * dim + c];
+      const double mean = n > 0 ? sum / n : NAN;
+      for (int k = 0; k < n; ++k) {
         const double d = (c < 0 ? v[k] : g[(size_t)k * dim + c]) - mean;
         ss += d * d;
       }
-      const double var = samples > 1 ? ss / (samples - 1) : 0.0;
+      const double var = n > 1 ? ss / (n - 1) : 0.0;
       if (c < 0) {
         if (mean_out) mean_out[p] = mean;
         if (var_out) var_out[p] = var;

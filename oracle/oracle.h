@@ -105,7 +105,9 @@ int orc_trace(const orc_mesh* mesh, const double* points, const int32_t* point_p
               uint32_t problem, int64_t n_items, const int64_t* item_point,
               const int64_t* item_path, orc_trace_out* out, int n_threads);
 
-/* Mean and unbiased variance over paths 0..N-1 for every point (two-pass). */
+/* Mean and unbiased variance over paths 0..N-1 for every point (two-pass),
+ * over the finite path values (a non-finite one is left out; NaN mean when
+ * none is finite). */
 int orc_solve(const orc_mesh* mesh, const double* points, const int32_t* point_prim,
               int64_t n_points, const orc_bc* bc, int samples, int walk_len,
               uint64_t seed, uint32_t problem, double* mean_out, double* var_out,

@@ -480,3 +480,26 @@ def test_mixed_problem_dirichlet_boundary_point_returns_data():
     m, v = oracle.solve(om, on, prim, bc, 4, 3, 0)
     np.testing.assert_allclose(m, on[:, 0] ** 2 - on[:, 1] ** 2, rtol=0, atol=1e-15)
     np.testing.assert_array_equal(v, 0.0)
+
+
+def test_nonfinite_paths_are_left_out():
+    """A boundary point where the Dirichlet data are singular (the source of
+    g = 1/|x - x0| on the boundary) has no finite path: its mean is NaN and
+    its variance 0, and the other points are unaffected (their statistics are
+    those of their finite paths)."""
+    mesh = I.icosphere(3)
+    om = oracle.OracleMesh(mesh)
+    j = 7
+    c = mesh.verts[mesh.prims[j]].mean(axis=0)
+    bc = oracle.make_bc(1, oracle.DOUBLE_LAYER, oracle.PROG_INVDIST, tuple(c))
+    pts = np.stack([c, 0.3 * c, -0.2 * c])
+    pp = np.array([j, -1, -1], np.int32)
+    mean, var = oracle.solve(om, pts, pp, bc, 16, 3, 4)
+    assert np.isnan(mean[0]) and var[0] == 0.0
+    t = oracle.trace(om, pts, pp, bc, 3, 4, np.repeat(np.arange(3), 16), np.tile(np.arange(16), 3),
+                     want_pos=False)
+    v = t["value"].reshape(3, 16)
+    assert not np.isfinite(v[0]).any()
+    for p in (1, 2):
+        f = v[p][np.isfinite(v[p])]
+        assert np.isclose(mean[p], f.mean(), rtol=1e-12) and np.isclose(var[p], f.var(ddof=1), rtol=1e-10)
