@@ -147,6 +147,17 @@ void wob_free(wob_scene scene);
 
 wob_status wob_get_scene_info(wob_scene scene, wob_scene_info* info);
 
+/* Device-side status of the solves on a scene, sticky until read: the number
+ * of path values that were not finite (a degenerate primitive, an invalid
+ * point_prim id, data singular at a boundary point) since the last call.  Such
+ * paths are left out of the per-point statistics of wob_solve, wob_solve_cv,
+ * wob_solve_grad and the batched solves (a point with no finite path gets a
+ * NaN mean); wob_trace returns them as they are.  Reads the counter with an
+ * asynchronous copy on `stream`, resets it, and waits for the stream: call it
+ * after the solves it should cover have been enqueued on that stream, and
+ * never inside a captured graph.  Errors: WOB_E_ARG, WOB_E_DEVICE. */
+wob_status wob_last_device_status(wob_scene scene, uint64_t* nonfinite_paths, void* stream);
+
 /* Number of lines traced per path: walk_len for the double and single layer,
  * walk_len + 1 for the direct BIE (the last vertex traces one more line for its
  * source integral).  Returns -1 on bad arguments. */

@@ -18,6 +18,7 @@ struct wob_scene_s {
   void* d_normals = nullptr;
   int32_t* d_leaf_of_id = nullptr;
   float* d_area_cdf = nullptr;  // caller-id order, cumulative area / total (last entry 1)
+  unsigned long long* d_status = nullptr;  // non-finite path values excluded from solves (sticky)
   double area_total = 0.0;      // |Gamma|
   int64_t node_bytes = 0, prim_bytes = 0, device_bytes = 0;
   int32_t n_dirichlet = 0, n_neumann = 0, n_robin = 0;
@@ -139,6 +140,7 @@ wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void*
   a.problem = 0;
   a.lpp_shift = lpp_shift_for(samples, kSolveBlock);
   a.density = bc->density;
+  a.status = sc->d_status;
   a.ris_c = pl.ris_c;
   a.mixed_thr = pl.mixed_thr;
   a.mixed_p = (R)pl.mixed_p;

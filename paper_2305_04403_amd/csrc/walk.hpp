@@ -40,6 +40,7 @@ struct WalkArgs {
   int32_t* vtx_prim;
   int32_t* vtx_m;
   unsigned long long* counters;
+  unsigned long long* status;  // solves: count of non-finite path values (excluded from the statistics)
 };
 
 // One path estimates u_hat(x_0):
@@ -724,18 +725,31 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       while (st == ST_DONE) {
         const R v = s.acc;
         if (TRACE) a.path_out[point * (int64_t)a.N + k] = v;
-        n += 1.0;
-        const double dv = (double)v - mean;
-        mean += dv / n;
-        m2 += dv * ((double)v - mean);
+        bool finite = isfinite(v);
         if constexpr (GRAD) {
 #pragma unroll
           for (int c = 0; c < GD; ++c) {
             if (TRACE) a.path_grad_out[(point * (int64_t)a.N + k) * D + c] = s.gacc[c];
-            const double dg = (double)s.gacc[c] - gmean[c];
-            gmean[c] += dg / n;
-            gm2[c] += dg * ((double)s.gacc[c] - gmean[c]);
+            finite = finite && isfinite(s.gacc[c]);
           }
+        }
+        if (finite) {
+          n += 1.0;
+          const double dv = (double)v - mean;
+          mean += dv / n;
+          m2 += dv * ((double)v - mean);
+          if constexpr (GRAD) {
+#pragma unroll
+            for (int c = 0; c < GD; ++c) {
+              const double dg = (double)s.gacc[c] - gmean[c];
+              gmean[c] += dg / n;
+              gm2[c] += dg * ((double)s.gacc[c] - gmean[c]);
+            }
+          }
+        } else if (!TRACE && !COUNT && FORM != F_FWD && a.status) {
+          // a non-finite path (degenerate geometry, an invalid primitive id, data
+          // singular on the boundary) is counted and left out of the statistics
+          atomicAdd(a.status, 1ull);
         }
         k += lpp;
         st = k < a.N ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc)
@@ -833,12 +847,12 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   }
   if (lpp <= 64) {
     if (lane_in_point == 0 && point < a.n_points) {
-      a.mean_out[point] = (R)mean;
+      a.mean_out[point] = n > 0.0 ? (R)mean : (R)NAN;
       if (a.var_out) a.var_out[point] = (R)(n > 1.0 ? m2 / (n - 1.0) : 0.0);
       if constexpr (GRAD) {
 #pragma unroll
         for (int c = 0; c < GD; ++c) {
-          a.grad_out[point * D + c] = (R)gmean[c];
+          a.grad_out[point * D + c] = n > 0.0 ? (R)gmean[c] : (R)NAN;
           if (a.grad_var_out) a.grad_var_out[point * D + c] = (R)(n > 1.0 ? gm2[c] / (n - 1.0) : 0.0);
         }
       }
@@ -870,13 +884,13 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         for (int w = 1; w < waves; ++w)
           chan_merge(gn, gm, gs, red[(wave + w) * RS + 0], red[(wave + w) * RS + 3 + 2 * c],
                      red[(wave + w) * RS + 4 + 2 * c]);
-        a.grad_out[point * D + c] = (R)gm;
+        a.grad_out[point * D + c] = gn > 0.0 ? (R)gm : (R)NAN;
         if (a.grad_var_out) a.grad_var_out[point * D + c] = (R)(gn > 1.0 ? gs / (gn - 1.0) : 0.0);
       }
     }
     for (int w = 1; w < waves; ++w)
       chan_merge(tn, tm, ts, red[(wave + w) * RS + 0], red[(wave + w) * RS + 1], red[(wave + w) * RS + 2]);
-    a.mean_out[point] = (R)tm;
+    a.mean_out[point] = tn > 0.0 ? (R)tm : (R)NAN;
     if (a.var_out) a.var_out[point] = (R)(tn > 1.0 ? ts / (tn - 1.0) : 0.0);
   }
 }

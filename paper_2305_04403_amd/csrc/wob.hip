@@ -140,7 +140,9 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   if (hipMalloc((void**)&sc->d_area_cdf, sizeof(float) * T) != hipSuccess) return WOB_E_ALLOC;
   if (hipMemcpy(sc->d_area_cdf, cdf.data(), sizeof(float) * T, hipMemcpyHostToDevice) != hipSuccess)
     return WOB_E_DEVICE;
-  sc->device_bytes = (int64_t)(nb + pb + lb + qb + sizeof(float) * T);
+  if (hipMalloc((void**)&sc->d_status, sizeof(unsigned long long)) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMemset(sc->d_status, 0, sizeof(unsigned long long)) != hipSuccess) return WOB_E_DEVICE;
+  sc->device_bytes = (int64_t)(nb + pb + lb + qb + sizeof(float) * T + sizeof(unsigned long long));
   return WOB_OK;
 }
 
@@ -359,7 +361,22 @@ void wob_free(wob_scene sc) {
   if (sc->d_normals) (void)hipFree(sc->d_normals);
   if (sc->d_area_cdf) (void)hipFree(sc->d_area_cdf);
   if (sc->d_leaf_of_id) (void)hipFree(sc->d_leaf_of_id);
+  if (sc->d_status) (void)hipFree(sc->d_status);
   delete sc;
+}
+
+wob_status wob_last_device_status(wob_scene sc, uint64_t* nonfinite_paths, void* stream) {
+  if (!sc || !nonfinite_paths) return WOB_E_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != sc->device) return WOB_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long v = 0;
+  if (hipMemcpyAsync(&v, sc->d_status, sizeof(v), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return WOB_E_DEVICE;
+  if (hipMemsetAsync(sc->d_status, 0, sizeof(v), st) != hipSuccess) return WOB_E_DEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return WOB_E_DEVICE;
+  *nonfinite_paths = (uint64_t)v;
+  return WOB_OK;
 }
 
 wob_status wob_get_scene_info(wob_scene sc, wob_scene_info* info) {

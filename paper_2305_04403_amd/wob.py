@@ -31,7 +31,7 @@ EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_pa
             "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
             "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary",
             "wob_starts_create", "wob_starts_from_data", "wob_starts_free", "wob_forward_paths",
-            "wob_forward_gather", "wob_solve_grad", "wob_trace_grad")
+            "wob_forward_gather", "wob_solve_grad", "wob_trace_grad", "wob_last_device_status")
 
 
 class WobError(RuntimeError):
@@ -128,6 +128,8 @@ def lib():
     L.wob_cv_emission.argtypes = [vp, C.POINTER(_BC), vp, vp, vp]
     for name in ("wob_cv_table", "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission"):
         getattr(L, name).restype = C.c_int
+    L.wob_last_device_status.argtypes = [vp, C.POINTER(C.c_uint64), vp]
+    L.wob_last_device_status.restype = C.c_int
     L.wob_solve_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
     L.wob_solve_grad.restype = C.c_int
     L.wob_trace_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
@@ -231,6 +233,13 @@ class Scene:
         i = _SceneInfo()
         _check(lib().wob_get_scene_info(self.handle, C.byref(i)), "wob_get_scene_info")
         return {f: getattr(i, f) for f, _ in _SceneInfo._fields_ if f != "reserved"}
+
+    def nonfinite_paths(self, stream=None) -> int:
+        """Non-finite path values left out of solves on this scene since the
+        last call (``wob_last_device_status``; resets the count)."""
+        v = C.c_uint64()
+        _check(lib().wob_last_device_status(self.handle, C.byref(v), _stream(stream)), "wob_last_device_status")
+        return int(v.value)
 
     def lines_per_path(self, bc: BC, walk_len: int) -> int:
         b = bc.c()

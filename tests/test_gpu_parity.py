@@ -371,3 +371,39 @@ def test_work_counters(W):
     assert c["hits"] >= c["lines"]
     assert c["nodes"] > c["lines"] and c["prims"] >= c["hits"]
     scene.close()
+
+
+def test_nonfinite_paths_counted_and_left_out(W):
+    """A boundary point where the data are singular and a point with an
+    invalid primitive id have no finite path: their means are NaN, the other
+    points match the oracle's finite-path statistics, and the scene's device
+    status counts every left-out path once (reset on read); the same through
+    a batched launch."""
+    mesh = PT.f32_mesh(I.icosphere(6))
+    j = 7
+    c = PT.f32(mesh.verts[mesh.prims[j]].mean(axis=0))
+    pts = PT.f32(np.stack([c, 0.3 * c, -0.2 * c, 0.1 * c]))
+    pp = np.array([j, -1, -1, mesh.n_prims + 3], np.int32)
+    scene = W.Scene(mesh, W.F32)
+    assert scene.nonfinite_paths() == 0
+    bc = W.BC(1, 1, W.PROG_INVDIST, tuple(c))
+    tp, tpp = dev(pts, torch.float32), dev(pp, torch.int32)
+    N = 64
+    mean, var = W.solve(scene, tp, bc, N, 3, 4, point_prim=tpp)
+    torch.cuda.synchronize()
+    m = mean.cpu().double().numpy()
+    assert np.isnan(m[0]) and np.isnan(m[3]) and np.all(np.isfinite(m[1:3]))
+    assert scene.nonfinite_paths() == 2 * N
+    assert scene.nonfinite_paths() == 0
+    om, ov = oracle.solve(oracle.OracleMesh(mesh), pts[:3], pp[:3],
+                          oracle.make_bc(1, oracle.DOUBLE_LAYER, oracle.PROG_INVDIST, tuple(c)), N, 3, 4)
+    assert np.isnan(om[0])
+    assert np.allclose(m[1:3], om[1:3], rtol=1e-5)
+    b = W.Batch([dict(scene=scene, points=tp, point_prim=tpp, bc=bc, samples=N, walk_len=3, seed=4)],
+                tune=(256, 1))
+    (bm, _), = b.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(bm.isnan(), mean.isnan())
+    assert scene.nonfinite_paths() == 2 * N
+    b.close()
+    scene.close()
