@@ -207,6 +207,19 @@ def cv_leg(torch, wob, I):
 
     lcv = CV.LearnedControlVariate(scene, bc, M, CV.CVConfig(epochs=1, target_paths=4))
     fit = lcv.fit()
+    # the network on the matrix cores: forward over 2^20 points (106,752 FLOP each)
+    yq = torch.rand((1 << 20, 3), dtype=torch.float32, device="cuda") * 4.0 - 2.0
+    fq = torch.empty(1 << 20, dtype=torch.float32, device="cuda")
+    lcv.net.forward(yq, out=fq)
+    st_ = torch.cuda.current_stream()
+    q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    q0.record(st_)
+    for _ in range(5):
+        lcv.net.forward(yq, out=fq)
+    q1.record(st_)
+    sync()
+    t_mlp = 1e-3 * q0.elapsed_time(q1) / 5
+    mlp_tflops = (1 << 20) * 106752 / t_mlp / 1e12
     zero = torch.zeros_like(lcv.g)
     t0 = time.perf_counter()
     e0 = wob.cv_emission(scene, bc)
@@ -270,6 +283,8 @@ def cv_leg(torch, wob, I):
         out[f"ris_{C}"] = {"paths": n, "seconds": float(np.mean(tm)), "path_cost_vs_line": pp_cost / (t_plain / N),
                            "rmse": r, "rmse_per_seed": ps, "median_abs_err": e, "mean_var": v,
                            "rmse_ratio": rp / r, "median_err_ratio": ep / e}
+    out["mlp_forward"] = {"points": 1 << 20, "ms": 1e3 * t_mlp, "TFLOP/s": mlp_tflops, "peak_bf16_TFLOP/s": 2500.0,
+                          "frac": mlp_tflops / 2500.0}
     out["addback_s"] = t_add
     out["corrected_path_cost_vs_plain"] = per_path / (t_plain / N)
     out["rmse_ratio_equal_time"] = out["learned"]["rmse_ratio"]
@@ -282,6 +297,32 @@ def cv_leg(torch, wob, I):
 # connection of a point to a forward-path vertex: 3 differences, 3 products and
 # 2 sums for rho^2, one reciprocal square root, one multiply-add = 11
 GATHER_PAIR_FLOP = 11
+
+
+def gather_calibration(torch, wob, sizes=(("32KiB", 32 << 10), ("2MiB", 2 << 20), ("20MiB", 20 << 20),
+                                          ("256MiB", 256 << 20)), reads=64, reps=5):
+    """Random 32-byte gather rate (GB/s) at each working-set size, measured with
+    the library's probe kernel: the bandwidth roof of the memory level that
+    holds a working set of that size (32 KiB: the CU's L1; 2 MiB: L2; 20 MiB
+    and 256 MiB: MALL / HBM)."""
+    lanes = 256 * 2048  # 8 waves on each SIMD of 256 CUs
+    out = torch.empty(lanes, dtype=torch.float32, device="cuda")
+    res = {}
+    for name, nb in sizes:
+        buf = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            wob.gather_probe(buf, lanes, reads, 1, out=out)
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for r in range(reps):
+            wob.gather_probe(buf, lanes, reads, 2 + r, out=out)
+        e1.record(st)
+        torch.cuda.synchronize()
+        t = 1e-3 * e0.elapsed_time(e1) / reps
+        res[name] = lanes * reads * 32 / t / 1e9
+        del buf
+    return res
 
 
 def forward_leg(torch, wob, I):
@@ -503,6 +544,12 @@ def main():
         "mean_se": float(np.mean(se)),
         "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")},
     }
+    cal = gather_calibration(torch, wob)
+    rec["gather"]["calibrated_random_32B_GB/s"] = cal
+    # above 1: the traversal's reads are not uniformly random (the upper tree
+    # levels are shared by all lanes and stay in the CU caches), so the L2
+    # gather rate does not bound it
+    rec["gather"]["ratio_to_random_2MiB"] = rec["gather"]["GB/s"] / cal["2MiB"]
     rec.update(extra)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4

@@ -26,7 +26,7 @@ def build(verbose: bool = False) -> str:
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     objs = []
-    for src in ("wob.hip", "batch.hip", "mlp.hip", "forward.hip"):
+    for src in ("wob.hip", "batch.hip", "mlp.hip", "forward.hip", "probe.hip"):
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
         cmd = [hipcc, "-c", *HIP_FLAGS, os.path.join(CSRC, src), "-o", obj]
         if verbose:

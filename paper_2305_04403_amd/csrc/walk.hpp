@@ -769,20 +769,19 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       bool trav = st == ST_LINE && pend < 0 && s.ni < nn;
       while (trav) {
         if (active - __popcll(__ballot(1)) >= want) break;
-        const typename Rec<R, D>::Node node = a.scene.nodes[s.ni];
+        // a 32-bit byte offset from the uniform base (one address instruction);
+        // the step is written without branches: crossed internal node -> its
+        // first child, anything else -> the skip index; a crossed leaf parks
+        using Node = typename Rec<R, D>::Node;
+        const Node node = *reinterpret_cast<const Node*>(reinterpret_cast<const char*>(a.scene.nodes) +
+                                                         (uint32_t)s.ni * (uint32_t)sizeof(Node));
         if (COUNT) wc.nodes += 1;
         const bool crossed = line_box<R, D>(node, s.inv, s.ox);
-        if (crossed && node.child >= 0) {
-          s.ni = node.child;
-          continue;
-        }
-        s.ni = node.skip;
-        if (crossed) {
-          pend = -1 - node.child;
-          trav = false;
-        } else if (s.ni >= nn) {
-          trav = false;
-        }
+        const bool at_leaf = crossed && node.child < 0;
+        const int32_t nxt = (crossed && node.child >= 0) ? node.child : node.skip;
+        pend = at_leaf ? -1 - node.child : pend;
+        s.ni = nxt;
+        trav = !at_leaf && nxt < nn;
       }
       // the parked lanes test their leaves together
       if (pend >= 0) {

@@ -55,6 +55,8 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   using Node = typename wob::Rec<R, D>::Node;
   using Prim = typename wob::Rec<R, D>::Prim;
   const int64_t T = sc->n_prims;
+  // the traversal addresses nodes by a 32-bit byte offset
+  if ((uint64_t)bvh.nodes.size() * sizeof(Node) > 0xffffffffull) return WOB_E_ARG;
   std::vector<Node> nodes(bvh.nodes.size());
   for (size_t i = 0; i < bvh.nodes.size(); ++i) {
     const auto& fn = bvh.nodes[i];

@@ -31,7 +31,8 @@ EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_pa
             "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
             "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary",
             "wob_starts_create", "wob_starts_from_data", "wob_starts_free", "wob_forward_paths",
-            "wob_forward_gather", "wob_solve_grad", "wob_trace_grad", "wob_last_device_status")
+            "wob_forward_gather", "wob_solve_grad", "wob_trace_grad", "wob_last_device_status",
+            "wob_gather_probe")
 
 
 class WobError(RuntimeError):
@@ -128,6 +129,8 @@ def lib():
     L.wob_cv_emission.argtypes = [vp, C.POINTER(_BC), vp, vp, vp]
     for name in ("wob_cv_table", "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission"):
         getattr(L, name).restype = C.c_int
+    L.wob_gather_probe.argtypes = [vp, i64, i64, i32, C.c_uint32, vp, vp]
+    L.wob_gather_probe.restype = C.c_int
     L.wob_last_device_status.argtypes = [vp, C.POINTER(C.c_uint64), vp]
     L.wob_last_device_status.restype = C.c_int
     L.wob_solve_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
@@ -372,6 +375,19 @@ def trace_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
                               C.c_uint64(seed), _dev_ptr(path), _dev_ptr(pg), _stream(stream))
     _check(st, "wob_trace_grad")
     return path, pg
+
+
+def gather_probe(buf, lanes: int, reads: int, seed: int = 0, out=None, stream=None):
+    """Random 32-byte gathers from the device buffer ``buf`` (``wob_gather_probe``):
+    returns one float per lane (the sum of the first and last float of each
+    record read)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(lanes, dtype=torch.float32, device=buf.device)
+    st = lib().wob_gather_probe(_dev_ptr(buf), buf.numel() * buf.element_size(), int(lanes), int(reads),
+                                C.c_uint32(seed), _dev_ptr(out), _stream(stream))
+    _check(st, "wob_gather_probe")
+    return out
 
 
 def trace(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
