@@ -83,10 +83,21 @@ struct Smem {
   float red[NT];
 };
 
-// Features and the four hidden layers for rows r0 .. r0 + 63.  Pre-activations
-// go to `sbuf` (4 x 64 x 128 floats) when it is not null.
-__device__ void forward_tile(const Net& net, const float* y, int64_t n, int64_t r0, Smem& sm,
-                             float* sbuf) {
+// The forward pass alone keeps two activation buffers (layer l writes buffer
+// l % 2): 36 KiB of LDS, four workgroups per CU instead of the backward pass's
+// one.
+struct FwdSmem {
+  __bf16 a0[TR * F0];
+  __bf16 act[2][TR * HD];
+};
+
+// Features and the four hidden layers for rows r0 .. r0 + 63 into LDS: the
+// features to a0, layer l's activations to act + (ALL ? l : l % 2) TR HD (ALL:
+// every layer kept, for the backward pass).  Pre-activations go to `sbuf`
+// (4 x 64 x 128 floats) when it is not null.  Returns the last layer's buffer.
+template <bool ALL>
+__device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n, int64_t r0,
+                                      __bf16* a0, __bf16* act, float* sbuf) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int idx = tid; idx < TR * KF; idx += NT) {
     const int r = idx / KF, k = idx % KF;
@@ -97,13 +108,14 @@ __device__ void forward_tile(const Net& net, const float* y, int64_t n, int64_t 
       for (int d = 0; d < net.dim; ++d) arg += net.fourier[k * net.dim + d] * y[row * net.dim + d];
       sincospif(2.f * arg, &sv, &cv);
     }
-    sm.a0[r * F0 + k] = (__bf16)sv;
-    sm.a0[r * F0 + KF + k] = (__bf16)cv;
+    a0[r * F0 + k] = (__bf16)sv;
+    a0[r * F0 + KF + k] = (__bf16)cv;
   }
   __syncthreads();
   for (int l = 0; l < NL; ++l) {
     const int K = in_of(l);
-    const __bf16* A = l == 0 ? sm.a0 : sm.act[l - 1];
+    const __bf16* A = l == 0 ? a0 : act + (ALL ? l - 1 : (l - 1) & 1) * TR * HD;
+    __bf16* O = act + (ALL ? l : l & 1) * TR * HD;
     const __bf16* W = net.wq + offW(l);
     const float* b = net.p + offB(l);
     floatx4 acc[8];
@@ -128,20 +140,21 @@ __device__ void forward_tile(const Net& net, const float* y, int64_t n, int64_t 
         const int r = wave * 16 + 4 * (lane >> 4) + v;
         const float s = acc[cb][v] + b[col];
         if (sbuf) sbuf[(l * TR + r) * HD + col] = s;
-        sm.act[l][r * HD + col] = (__bf16)silu(s);
+        O[r * HD + col] = (__bf16)silu(s);
       }
     }
     __syncthreads();
   }
+  return act + (ALL ? NL - 1 : (NL - 1) & 1) * TR * HD;
 }
 
 // Output layer f = W5 . h4 + b5 for the 64 rows; 4 lanes per row.
-__device__ float output_row(const Net& net, const Smem& sm, int& r_out) {
+__device__ float output_row(const Net& net, const __bf16* h4, int& r_out) {
   const int tid = threadIdx.x;
   const int r = tid >> 2, part = tid & 3;
   float acc = 0.f;
   for (int i = part * 32; i < part * 32 + 32; ++i)
-    acc += (float)net.wq[offW(NL) + i] * (float)sm.act[NL - 1][r * HD + i];
+    acc += (float)net.wq[offW(NL) + i] * (float)h4[r * HD + i];
   acc += __shfl_xor(acc, 1, 64);
   acc += __shfl_xor(acc, 2, 64);
   r_out = r;
@@ -150,11 +163,11 @@ __device__ float output_row(const Net& net, const Smem& sm, int& r_out) {
 
 __global__ void __launch_bounds__(NT) mlp_forward_kernel(Net net, const float* y, int64_t n, float* out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Smem& sm = *reinterpret_cast<Smem*>(smem_raw);
+  FwdSmem& sm = *reinterpret_cast<FwdSmem*>(smem_raw);
   const int64_t r0 = (int64_t)blockIdx.x * TR;
-  forward_tile(net, y, n, r0, sm, nullptr);
+  const __bf16* h4 = forward_tile<false>(net, y, n, r0, sm.a0, sm.act[0], nullptr);
   int r;
-  const float f = output_row(net, sm, r);
+  const float f = output_row(net, h4, r);
   if ((threadIdx.x & 3) == 0 && r0 + r < n) out[r0 + r] = f;
 }
 
@@ -176,9 +189,9 @@ __global__ void __launch_bounds__(NT) mlp_grad_kernel(Net net, const float* y, c
   const int64_t r0 = (int64_t)blockIdx.x * TR;
   float* sbuf = sbuf_all + (int64_t)blockIdx.x * NL * TR * HD;
   float* G = part_grad + (int64_t)blockIdx.x * NP;
-  forward_tile(net, y, n, r0, sm, sbuf);
+  const __bf16* h4 = forward_tile<true>(net, y, n, r0, sm.a0, sm.act[0], sbuf);
   int r;
-  const float f = output_row(net, sm, r);
+  const float f = output_row(net, h4, r);
   float e = 0.f;
   if (r0 + r < n) {
     float tv = target[r0 + r];
@@ -377,7 +390,7 @@ wob_status wob_mlp_create(int32_t dim, const float* fourier, const float* params
     if (!std::isfinite(params[i])) return WOB_E_ARG;
   // the workgroups keep every activation of their 64 rows in LDS (> 64 KiB)
   if (hipFuncSetAttribute((const void*)mlp_forward_kernel,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, sizeof(Smem)) != hipSuccess ||
+                          hipFuncAttributeMaxDynamicSharedMemorySize, sizeof(FwdSmem)) != hipSuccess ||
       hipFuncSetAttribute((const void*)mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                           sizeof(Smem)) != hipSuccess)
     return WOB_E_DEVICE;
@@ -439,7 +452,7 @@ wob_status wob_mlp_forward(wob_mlp h, const float* y, int64_t n, float* out, voi
   if (n == 0) return WOB_OK;
   const int64_t tiles = (n + TR - 1) / TR;
   if (tiles > 0x7fffffff) return WOB_E_ARG;
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)tiles), dim3(NT), sizeof(Smem),
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)tiles), dim3(NT), sizeof(FwdSmem),
                      (hipStream_t)stream, h->net, y, n, out);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
