@@ -47,9 +47,12 @@ struct Net {
   float* fourier; // KF x dim
 };
 
-__device__ __forceinline__ float silu(float s) { return s / (1.f + __expf(-s)); }
+// SiLU with the hardware reciprocal (1 ulp; the result is rounded to bfloat16
+// or multiplies a bfloat16-rounded gradient, so an IEEE division buys nothing)
+__device__ __forceinline__ float sigmoid_(float s) { return __builtin_amdgcn_rcpf(1.f + __expf(-s)); }
+__device__ __forceinline__ float silu(float s) { return s * sigmoid_(s); }
 __device__ __forceinline__ float silu_grad(float s) {
-  const float sg = 1.f / (1.f + __expf(-s));
+  const float sg = sigmoid_(s);
   return sg * (1.f + s * (1.f - sg));
 }
 
@@ -89,15 +92,19 @@ struct Smem {
 struct FwdSmem {
   __bf16 a0[TR * F0];
   __bf16 act[2][TR * HD];
+  __bf16 w[HD * (HD + 8)];  // the current layer's weights, rows padded by 8 (bank spread)
 };
 
 // Features and the four hidden layers for rows r0 .. r0 + 63 into LDS: the
 // features to a0, layer l's activations to act + (ALL ? l : l % 2) TR HD (ALL:
 // every layer kept, for the backward pass).  Pre-activations go to `sbuf`
-// (4 x 64 x 128 floats) when it is not null.  Returns the last layer's buffer.
+// (4 x 64 x 128 floats) when it is not null.  With `wlds`, each layer's
+// weights are first staged in LDS (every wavefront reads all of them: staged,
+// they come from L2 once per workgroup instead of once per wavefront).
+// Returns the last layer's buffer.
 template <bool ALL>
 __device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n, int64_t r0,
-                                      __bf16* a0, __bf16* act, float* sbuf) {
+                                      __bf16* a0, __bf16* act, float* sbuf, __bf16* wlds = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int idx = tid; idx < TR * KF; idx += NT) {
     const int r = idx / KF, k = idx % KF;
@@ -117,6 +124,16 @@ __device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n,
     const __bf16* A = l == 0 ? a0 : act + (ALL ? l - 1 : (l - 1) & 1) * TR * HD;
     __bf16* O = act + (ALL ? l : l & 1) * TR * HD;
     const __bf16* W = net.wq + offW(l);
+    int ldw = K;
+    if (wlds) {
+      for (int idx = tid * 8; idx < HD * K; idx += NT * 8) {
+        const int o = idx / K, k = idx - o * K;
+        *(bf16x8*)(wlds + o * (K + 8) + k) = *(const bf16x8*)(W + idx);
+      }
+      __syncthreads();
+      W = wlds;
+      ldw = K + 8;
+    }
     const float* b = net.p + offB(l);
     floatx4 acc[8];
 #pragma unroll
@@ -128,7 +145,7 @@ __device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n,
       for (int cb = 0; cb < 8; ++cb) {
         // B[k][o] = W[o][k]: eight consecutive k of row o of W
         const int o = cb * 16 + (lane & 15);
-        const bf16x8 bf = *(const bf16x8*)(W + o * K + k0 + 8 * (lane >> 4));
+        const bf16x8 bf = *(const bf16x8*)(W + o * ldw + k0 + 8 * (lane >> 4));
         acc[cb] = mfma(af, bf, acc[cb]);
       }
     }
@@ -165,7 +182,7 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(Net net, const float* y
   extern __shared__ __align__(16) unsigned char smem_raw[];
   FwdSmem& sm = *reinterpret_cast<FwdSmem*>(smem_raw);
   const int64_t r0 = (int64_t)blockIdx.x * TR;
-  const __bf16* h4 = forward_tile<false>(net, y, n, r0, sm.a0, sm.act[0], nullptr);
+  const __bf16* h4 = forward_tile<false>(net, y, n, r0, sm.a0, sm.act[0], nullptr, sm.w);
   int r;
   const float f = output_row(net, h4, r);
   if ((threadIdx.x & 3) == 0 && r0 + r < n) out[r0 + r] = f;
