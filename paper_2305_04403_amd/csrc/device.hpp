@@ -25,7 +25,10 @@ enum Program { P_CONST = 0, P_LINEAR = 1, P_QUAD = 2, P_INVDIST = 3 };
 // --------------------------------------------------------------------------
 template <typename R> struct alignas(16) Node3 { R lo[3]; int32_t skip; R hi[3]; int32_t child; };
 template <typename R> struct alignas(16) Node2 { R lo[2]; R hi[2]; int32_t skip; int32_t child; };
-template <typename R> struct alignas(16) Prim3 { R v0[3]; int32_t idkind; R e1[3]; R alpha; R e2[3]; int32_t pad; };
+// An FP32 triangle record is padded to 64 bytes so that it never straddles a
+// 64-byte block: the traversal is bound by the rate of L1-miss requests, and a
+// straddling record costs two.
+template <typename R> struct alignas(sizeof(R) == 4 ? 64 : 32) Prim3 { R v0[3]; int32_t idkind; R e1[3]; R alpha; R e2[3]; int32_t pad; };
 template <typename R> struct alignas(16) Prim2 { R v0[2]; R e[2]; R alpha; int32_t idkind; };
 
 template <typename R, int D> struct Rec;
@@ -341,8 +344,8 @@ struct HitAcc {
   int32_t m;
   uint32_t key;
   int32_t id, idx;
-  R u, v;     // barycentric coordinates of the selected hit
-  R t;        // its line parameter: y - x = t d, so rhat = sign(t) d and rho = |t|
+  R t;        // line parameter of the selected hit (set when the step is taken):
+              // y - x = t d, so rhat = sign(t) d and rho = |t|
   R src;      // direct BIE: sum over hits of G q / p_all
   R srcg[3];  // gradient walk, direct BIE, line 0: sum over hits of grad_x G q / p_all
 };

@@ -348,7 +348,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     s.h.key = 0xffffffffu;
     s.h.id = 0x7fffffff;
     s.h.idx = -1;
-    s.h.u = s.h.v = s.h.t = 0;
+    s.h.t = 0;
     s.h.src = 0;
     if constexpr (GRAD) s.h.srcg[0] = s.h.srcg[1] = s.h.srcg[2] = 0;
     s.ni = 0;
@@ -438,10 +438,15 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
   return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
-// The primitives of one crossed leaf of the current line.  Per hit: count
-// it; with `select`, draw its key (Philox block 2, w = caller id) and keep the
-// smallest (key, id); for the direct BIE add G q / p_all to the source sum;
-// for the corrected walk add a(h) F(y_h).
+// The primitives of one crossed leaf of the current line.  The primitive loop
+// only tests and records the accepted primitives in a bit mask; the hits are
+// then handled in a loop of their own, so that the lanes with a hit in this
+// leaf phase do that work together instead of one or two at a time inside the
+// primitive loop.  Per hit: count it; with `select`, draw its key (Philox
+// block 2, w = caller id) and keep the smallest (key, id) -- the line
+// parameter and barycentrics of the kept hit are computed once, in end_step;
+// for the direct BIE add G q / p_all to the source sum; for the corrected walk
+// add a(h) F(y_h).
 template <typename R, int D, int FORM, bool COUNT, int EXT>
 __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, D>& s, int32_t code,
                                           WorkCount& wc) {
@@ -449,25 +454,40 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
   const SceneView<R, D>& sc = a.scene;
   {
     const int32_t first = code >> 3, count = (code & 7) + 1;
-    for (int32_t j = first; j < first + count; ++j) {
+    constexpr bool GEO = FORM == F_DIRECT || CV;  // per-hit work needs the hit's geometry
+    uint32_t accepted = 0;  // bit b: primitive first + b is hit
+    int32_t id0 = 0;        // caller id of the first hit (no reload for it)
+    for (int32_t b = 0; b < count; ++b) {
+      const int32_t j = first + b;
       if (j == s.cur_idx) continue;
       if (COUNT) wc.prims += 1;
       const PrimGeo<R> g = load_prim<R, D>(sc, j);
       R t, u, v;
-      if (!hit_prim<R, D>(g, s.x, s.d, t, u, v)) continue;
+      if (hit_prim<R, D>(g, s.x, s.d, t, u, v)) {
+        if (!accepted) id0 = g.id;
+        accepted |= 1u << b;
+      }
+    }
+    bool later = false;
+    while (accepted) {
+      const int32_t j = first + __builtin_ctz(accepted);
+      accepted &= accepted - 1;
+      PrimGeo<R> g;
+      if (GEO || later) g = load_prim<R, D>(sc, j);
+      const int32_t id = (GEO || later) ? g.id : id0;
+      later = true;
       if (COUNT) wc.hits += 1;
       s.h.m += 1;
       if (s.select) {
-        const uint32_t key = philox(s.path, s.point, s.z | 2u, (uint32_t)g.id, a.k0, a.k1).x;
-        if (key < s.h.key || (key == s.h.key && g.id < s.h.id)) {
+        const uint32_t key = philox(s.path, s.point, s.z | 2u, (uint32_t)id, a.k0, a.k1).x;
+        if (key < s.h.key || (key == s.h.key && id < s.h.id)) {
           s.h.key = key;
-          s.h.id = g.id;
+          s.h.id = id;
           s.h.idx = j;
-          s.h.u = u;
-          s.h.v = v;
-          s.h.t = t;
         }
       }
+      R t = 0, u = 0, v = 0;
+      if constexpr (GEO) hit_prim<R, D>(g, s.x, s.d, t, u, v);
       if constexpr (FORM == F_DIRECT) {
         R y[3], n[3];
         hit_point(g, u, v, y);
@@ -553,7 +573,13 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
   }
   const PrimGeo<R> gy = load_prim<R, D>(a.scene, h.idx);
   R y[3], w;
-  hit_point(gy, h.u, h.v, y);
+  {
+    // the kept hit's line parameter and barycentrics (the same test that
+    // accepted it, on the same line)
+    R u, v;
+    hit_prim<R, D>(gy, s.x, s.d, h.t, u, v);
+    hit_point(gy, u, v, y);
+  }
   // y - x = t d: the unit direction to the hit is sign(t) d and rho = |t|
   const R sgn_t = h.t > (R)0 ? (R)1 : (R)-1;
   const R mm = (R)h.m;
