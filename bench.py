@@ -42,14 +42,16 @@ sys.path.insert(0, ROOT)
 # operations and includes packed math, which this build does not use, so one
 # half of it is the attainable issue rate)
 FP32_PEAK_TFLOPS = 157.3
-# algorithmic operations of the traversal: a node's slab test is 6 FMA (12),
-# 6 min / max, 2 three-way min / max (4) and one compare = 23; a tested
-# triangle (numerator form of Moller-Trumbore, a miss) is two cross products
-# (18), three dots (15), x - v0 (3), three sign products and four compares = 43
-NODE_FLOP, TRI_FLOP = 23, 43
-# algorithmic bytes: a node is its box (6 x 4 B) plus two links; a tested
-# triangle is v0, e1, e2 (9 x 4 B); a hit also reads id, kind and alpha (12 B)
-NODE_BYTES, TRI_BYTES, HIT_BYTES = 32, 36, 12
+# algorithmic operations of the traversal: a visited interior node tests the
+# boxes of its two children, each slab test 6 FMA (12), 6 min / max, 2
+# three-way min / max (4) and one compare = 23; a tested triangle (numerator
+# form of Moller-Trumbore, a miss) is two cross products (18), three dots (15),
+# x - v0 (3), three sign products and four compares = 43
+NODE_FLOP, TRI_FLOP = 2 * 23, 43
+# algorithmic bytes: an interior node is its children's boxes (12 x 4 B) and
+# entries (2 x 4 B); a tested triangle is v0, e1, e2 (9 x 4 B); a hit also
+# reads id, kind and alpha (12 B)
+NODE_BYTES, TRI_BYTES, HIT_BYTES = 56, 36, 12
 
 
 KERNEL_SOURCES = ("paper_2305_04403_amd/csrc/device.hpp", "paper_2305_04403_amd/csrc/walk.hpp",
@@ -532,7 +534,8 @@ def main():
                    "triangles": w.mesh.n_prims, "formulation": "double layer (interior Dirichlet)",
                    "parallelism": "none (1 GPU)"},
         "lines_per_s": lines * args.steps / wall,
-        "work_per_line": {"nodes": cnt["nodes"] / lines, "triangles": cnt["prims"] / lines,
+        "work_per_line": {"interior_nodes": cnt["nodes"] / lines, "box_tests": 2 * cnt["nodes"] / lines,
+                          "triangles": cnt["prims"] / lines,
                           "hits": cnt["hits"] / lines},
         "kernel_ms": float(np.mean(kern_ms)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

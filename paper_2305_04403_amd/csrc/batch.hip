@@ -24,6 +24,7 @@ struct wob_batch_s {
   int64_t* d_tile_off = nullptr;
   unsigned long long* d_counter = nullptr;
   int64_t n_tiles = 0;
+  int32_t stack_cap = 1;  // largest traversal stack of the problems' scenes
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -49,10 +50,12 @@ wob_status upload_table(wob_batch_s* b, int block) {
   const int n = (int)b->probs.size();
   std::vector<wob::WalkArgs<R, D>> args(n);
   std::vector<int64_t> off(n + 1, 0);
+  b->stack_cap = 1;
   for (int i = 0; i < n; ++i) {
     const wob_problem& p = b->probs[b->order[i]];
     Plan pl;
     if (plan_walk(p.scene, &p.bc, p.samples, p.walk_len, &pl) != WOB_OK) return WOB_E_ARG;
+    b->stack_cap = std::max(b->stack_cap, p.scene->stack_cap);
     auto a = make_args<R, D>(p.scene, pl, p.points, p.point_prim, p.n_points, &p.bc, p.samples,
                              p.walk_len, p.seed);
     a.problem = p.stream_id;
@@ -87,7 +90,8 @@ template <typename R, int D, int BLOCK>
 void launch_persistent_t(wob_batch_s* b, int bpc, int64_t stride, hipStream_t st) {
   hipLaunchKernelGGL(zero_counter, dim3(1), dim3(64), 0, st, b->d_counter);
   const dim3 grid((unsigned)(b->n_cu * bpc)), block(BLOCK);
-  hipLaunchKernelGGL((wob::batch_kernel<R, D, BLOCK>), grid, block, 0, st,
+  hipLaunchKernelGGL((wob::batch_kernel<R, D, BLOCK>), grid, block,
+                     (size_t)b->stack_cap * BLOCK * sizeof(int32_t), st,
                      (const wob::WalkArgs<R, D>*)b->d_args, (const int64_t*)b->d_tile_off,
                      (int32_t)b->probs.size(), stride, b->d_counter);
 }

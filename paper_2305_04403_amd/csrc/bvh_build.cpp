@@ -18,6 +18,10 @@ constexpr int kBins = 32;
 // per line); leaves of up to 8 with cost 0.5 / 0.35 / 0.25 were slower.
 constexpr double kNodeCost = 1.0;
 constexpr double kPrimCost = 0.5;
+// Below this depth subtrees are split at the centroid median, which bounds
+// the depth by kSahDepth + log2(n) whatever the geometry (the traversal stack
+// holds one entry per level).
+constexpr int32_t kSahDepth = 40;
 
 void grow(Box& b, const Box& o) {
   for (int a = 0; a < 3; ++a) {
@@ -74,6 +78,21 @@ struct Builder {
 
     if (count == 1) {
       make_leaf(idx, first, count);
+      out.nodes[idx].skip = (int32_t)out.nodes.size();
+      return;
+    }
+
+    if (depth >= kSahDepth && count > max_leaf) {
+      int axis = 0;
+      for (int a = 1; a < dim; ++a)
+        if (cb.hi[a] - cb.lo[a] > cb.hi[axis] - cb.lo[axis]) axis = a;
+      auto* beg = out.order.data() + first;
+      const int32_t half = count / 2;
+      std::nth_element(beg, beg + half, beg + count,
+                       [&](int32_t p, int32_t q) { return cen[3 * p + axis] < cen[3 * q + axis]; });
+      out.nodes[idx].child = idx + 1;
+      build(first, half, depth + 1);
+      build(first + half, count - half, depth + 1);
       out.nodes[idx].skip = (int32_t)out.nodes.size();
       return;
     }

@@ -23,8 +23,27 @@ enum Program { P_CONST = 0, P_LINEAR = 1, P_QUAD = 2, P_INVDIST = 3 };
 // Scene records.  Primitives are stored in BVH leaf order.  idkind packs the
 // caller's primitive id (bits 0..28) and its boundary kind (bits 29..30).
 // --------------------------------------------------------------------------
-template <typename R> struct alignas(16) Node3 { R lo[3]; int32_t skip; R hi[3]; int32_t child; };
-template <typename R> struct alignas(16) Node2 { R lo[2]; R hi[2]; int32_t skip; int32_t child; };
+// The BVH is stored as its interior nodes, each record holding the boxes of
+// both children and their entries: one record tests two boxes.  The traversal
+// is bound by the rate at which the CUs' vector memory path serves the lanes'
+// gathers, so records are kept to two 16-byte loads: in an FP32 scene the
+// boxes are binary16 in a normalised frame (scene centre c, power-of-two scale
+// k, y' = (y - c) k in [-1, 1]), rounded outward, and the slab test reads them
+// with mixed-precision FMAs.  A child entry is the index of an interior record
+// (>= 0) or a leaf, -1 - ((first << 3) | (count - 1)) with first the
+// leaf-order index of its first primitive (< 2^27).
+template <typename R> struct BoxScalar { using T = R; };
+template <> struct BoxScalar<float> { using T = _Float16; };
+template <typename R> using BoxT = typename BoxScalar<R>::T;
+template <typename R> struct alignas(32) Inner3 { BoxT<R> lo0[3], hi0[3], lo1[3], hi1[3]; int32_t child[2]; };
+template <typename R> struct alignas(32) Inner2 { BoxT<R> lo0[2], hi0[2], lo1[2], hi1[2]; int32_t child[2]; };
+// Traversal positions besides entries: take the next entry from the stack,
+// and the line's traversal is over.
+constexpr int32_t kPop = INT32_MIN;
+constexpr int32_t kDone = INT32_MAX;
+// Largest BVH depth (root 0) the builder produces: the traversal stack holds
+// at most one entry per level below the root.
+constexpr int kMaxDepth = 72;
 // An FP32 triangle record is padded to 64 bytes so that it never straddles a
 // 64-byte block: the traversal is bound by the rate of L1-miss requests, and a
 // straddling record costs two.
@@ -32,8 +51,8 @@ template <typename R> struct alignas(sizeof(R) == 4 ? 64 : 32) Prim3 { R v0[3]; 
 template <typename R> struct alignas(16) Prim2 { R v0[2]; R e[2]; R alpha; int32_t idkind; };
 
 template <typename R, int D> struct Rec;
-template <typename R> struct Rec<R, 3> { using Node = Node3<R>; using Prim = Prim3<R>; };
-template <typename R> struct Rec<R, 2> { using Node = Node2<R>; using Prim = Prim2<R>; };
+template <typename R> struct Rec<R, 3> { using Node = Inner3<R>; using Prim = Prim3<R>; };
+template <typename R> struct Rec<R, 2> { using Node = Inner2<R>; using Prim = Prim2<R>; };
 
 constexpr int kIdBits = 29;
 constexpr int32_t kIdMask = (1 << kIdBits) - 1;
@@ -46,8 +65,11 @@ struct SceneView {
   const int32_t* leaf_of_id;  // caller id -> leaf-order index
   const float* area_cdf;      // caller-id order, cumulative area / |Gamma| (binary32, last 1)
   R area_total;               // |Gamma|
-  int32_t n_nodes;
+  int32_t n_nodes;            // interior records
   int32_t n_prims;
+  int32_t root;               // entry of the root: record 0, or a leaf when the tree is one leaf
+  int32_t stack_cap;          // traversal stack entries per lane (the tree depth, >= 1)
+  R fc[3], fk;                // frame of the boxes: y' = (y - fc) fk (fc[2] = 0 in 2D)
 };
 
 template <typename R>
@@ -394,22 +416,23 @@ __device__ __forceinline__ void hit_point(const PrimGeo<R>& g, R u, R v, R y[3])
   for (int k = 0; k < 3; ++k) y[k] = g.v0[k] + u * g.e1[k] + v * g.e2[k];
 }
 
-// Slab test of a line against a box; inv = 1 / d (finite), ox = -x * inv.
-template <typename R, int D>
-__device__ __forceinline__ bool line_box(const typename Rec<R, D>::Node& n, const R inv[3], const R ox[3]) {
+// Slab test of a line against a box in the scene's box frame; inv = 1 / d
+// (finite), ox = -x' inv with x' the line's point in that frame.
+template <typename R, int D, typename B>
+__device__ __forceinline__ bool line_box(const B lo[3], const B hi[3], const R inv[3], const R ox[3]) {
   R tmin, tmax;
   {
-    const R a = fma(n.lo[0], inv[0], ox[0]), b = fma(n.hi[0], inv[0], ox[0]);
+    const R a = fma((R)lo[0], inv[0], ox[0]), b = fma((R)hi[0], inv[0], ox[0]);
     tmin = fmin(a, b);
     tmax = fmax(a, b);
   }
   {
-    const R a = fma(n.lo[1], inv[1], ox[1]), b = fma(n.hi[1], inv[1], ox[1]);
+    const R a = fma((R)lo[1], inv[1], ox[1]), b = fma((R)hi[1], inv[1], ox[1]);
     tmin = fmax(tmin, fmin(a, b));
     tmax = fmin(tmax, fmax(a, b));
   }
   if constexpr (D == 3) {
-    const R a = fma(n.lo[2], inv[2], ox[2]), b = fma(n.hi[2], inv[2], ox[2]);
+    const R a = fma((R)lo[2], inv[2], ox[2]), b = fma((R)hi[2], inv[2], ox[2]);
     tmin = fmax(tmin, fmin(a, b));
     tmax = fmin(tmax, fmax(a, b));
   }
@@ -421,29 +444,43 @@ template <typename R> __device__ __forceinline__ R safe_inv(R d) {
   return d == (R)0 ? big : (R)1 / d;
 }
 
-// Calls leaf(first, count) for every leaf whose box the line crosses, in the
-// BVH's pre-order, with a stackless walk over the skip links: a crossed inner
-// node continues at its first child, anything else at its skip link.  One
-// loop, one line per thread (the hit-list query); the path kernel steps
-// through the same nodes in its own loop, where lanes park at crossed leaves
-// and test them together.
+// Slab-test constants of the line x + t d: inv = 1 / d, ox = -x' inv.
+template <typename R, int D>
+__device__ __forceinline__ void line_slabs(const SceneView<R, D>& s, const R x[3], const R d[3], R inv[3],
+                                           R ox[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    inv[k] = safe_inv(d[k]);
+    ox[k] = -((x[k] - s.fc[k]) * s.fk) * inv[k];
+  }
+}
+
+// Calls leaf(first, count) for every leaf whose box the line crosses, depth
+// first with a private stack (one line per thread: the hit-list query).  The
+// path kernel runs the same traversal in its own loop, with the stack in LDS,
+// where lanes park at crossed leaves and test them together.
 template <typename R, int D, bool COUNT, typename Leaf>
 __device__ __forceinline__ void for_each_leaf(const SceneView<R, D>& s, const R inv[3], const R ox[3],
                                               WorkCount& wc, Leaf&& leaf) {
-  int32_t i = 0;
-  const int32_t end = s.n_nodes;
-  while (i < end) {
-    const typename Rec<R, D>::Node node = s.nodes[i];
-    if (COUNT) wc.nodes += 1;
-    if (line_box<R, D>(node, inv, ox)) {
-      if (node.child >= 0) {
-        i = node.child;
-        continue;
-      }
-      const int32_t code = -1 - node.child;
+  int32_t stk[kMaxDepth];
+  int sp = 0;
+  int32_t e = s.root;
+  for (;;) {
+    if (e >= 0) {
+      const typename Rec<R, D>::Node n = s.nodes[e];
+      if (COUNT) wc.nodes += 1;
+      const bool h0 = line_box<R, D>(n.lo0, n.hi0, inv, ox), h1 = line_box<R, D>(n.lo1, n.hi1, inv, ox);
+      if (h0 && h1 && sp < kMaxDepth) stk[sp++] = n.child[1];
+      e = h0 ? n.child[0] : (h1 ? n.child[1] : kPop);
+    } else if (e != kPop) {
+      const int32_t code = -1 - e;
       leaf(code >> 3, (code & 7) + 1);
+      e = kPop;
     }
-    i = node.skip;
+    if (e == kPop) {
+      if (sp == 0) break;
+      e = stk[--sp];
+    }
   }
 }
 

@@ -196,7 +196,8 @@ wob_status launch_paths(const wob_scene_s* sc, const wob_bc* bc, const float* cd
   a.vtx_m = vtx_m;
   constexpr int B = kSolveBlock;
   const dim3 grid((unsigned)((a.n_points + B - 1) / B)), block(B);
-  hipLaunchKernelGGL((wob::walk_kernel<R, D, wob::F_FWD, false, false, B>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((wob::walk_kernel<R, D, wob::F_FWD, false, false, B>), grid, block,
+                     (size_t)a.scene.stack_cap * B * sizeof(int32_t), st, a);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 

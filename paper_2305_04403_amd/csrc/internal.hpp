@@ -12,6 +12,10 @@
 struct wob_scene_s {
   int32_t dim = 0, precision = 0, device = 0;
   int64_t n_prims = 0, n_nodes = 0, n_leaves = 0;
+  int32_t n_inner = 0;    // interior records on the device
+  int32_t root = 0;       // root entry (record 0, or a leaf)
+  int32_t stack_cap = 1;  // traversal stack entries per lane
+  double frame_c[3] = {0, 0, 0}, frame_k = 1;  // frame of the stored boxes
   int32_t depth = 0, max_leaf = 0;
   void* d_nodes = nullptr;
   void* d_prims = nullptr;
@@ -53,8 +57,12 @@ wob::SceneView<R, D> view(const wob_scene_s* sc) {
   s.leaf_of_id = sc->d_leaf_of_id;
   s.area_cdf = sc->d_area_cdf;
   s.area_total = (R)sc->area_total;
-  s.n_nodes = (int32_t)sc->n_nodes;
+  s.n_nodes = sc->n_inner;
   s.n_prims = (int32_t)sc->n_prims;
+  s.root = sc->root;
+  s.stack_cap = sc->stack_cap;
+  for (int a = 0; a < 3; ++a) s.fc[a] = (R)sc->frame_c[a];
+  s.fk = (R)sc->frame_k;
   return s;
 }
 

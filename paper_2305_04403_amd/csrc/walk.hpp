@@ -6,6 +6,10 @@
 
 namespace wob {
 
+// Dynamic LDS of the path kernels: the lanes' traversal stacks, stack_cap
+// entries of 4 bytes per thread of the block (sized at launch).
+extern __shared__ int32_t wob_stack[];
+
 template <typename R, int D>
 struct WalkArgs {
   SceneView<R, D> scene;
@@ -105,7 +109,7 @@ struct PathState {
   R nc[3];
   R d[3], inv[3], ox[3];
   HitAcc<R> h;
-  int32_t ni;            // traversal position (node index)
+  int32_t ni;            // traversal position: an entry, kPop or kDone
   R Wg[3], gacc[3];      // gradient walk: d W / d x0 and the gradient sum
 };
 
@@ -339,11 +343,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     // the direct BIE's last line and the corrected walk's last line need no pick
     s.select = !((FORM == F_DIRECT || CV) && s.last);
     s.sum = CV && (s.i > 0 || s.last);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      s.inv[k] = safe_inv(s.d[k]);
-      s.ox[k] = -s.x[k] * s.inv[k];
-    }
+    line_slabs<R, D>(a.scene, s.x, s.d, s.inv, s.ox);
     s.h.m = 0;
     s.h.key = 0xffffffffu;
     s.h.id = 0x7fffffff;
@@ -351,7 +351,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     s.h.t = 0;
     s.h.src = 0;
     if constexpr (GRAD) s.h.srcg[0] = s.h.srcg[1] = s.h.srcg[2] = 0;
-    s.ni = 0;
+    s.ni = a.scene.root;
     if (COUNT) wc.lines += 1;
     return ST_LINE;
   }
@@ -734,6 +734,10 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     int k = lane_in_point;
     int st = ST_NONE;
     int32_t pend = -1;  // crossed leaf waiting to be tested
+    // the lane's traversal stack: LDS, entry k at wob_stack[k * BLOCK + tid]
+    // (consecutive lanes in consecutive banks); empty between lines
+    int32_t* const stk = wob_stack + tid;
+    int sp = 0;
     if (point < a.n_points) {
       if constexpr (FORM == F_FWD) {
         s.point = 0xfffffffeu;  // forward paths: no evaluation point
@@ -783,31 +787,36 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       }
       const int idle = __popcll(__ballot(st == ST_NONE));
       if (idle == 64) break;
-      const int nn = a.scene.n_nodes;
       // lanes parked at the end of their line, and lanes that step through nodes
-      const int ends = __popcll(__ballot(st == ST_LINE && pend < 0 && s.ni >= nn));
+      const int ends = __popcll(__ballot(st == ST_LINE && pend < 0 && s.ni == kDone));
       const int active = 64 - idle - ends;
       // node steps until 5/8 of the stepping lanes stand at a crossed leaf
       // (measured on the icosphere benchmark, 1/16 .. 16/16 of the lanes:
       // 236, 286, 352, 393, 395, 388, 352, 244 M path samples/s at 1/16, 1/8,
       // 1/4, 1/2, 5/8, 3/4, 7/8, 1)
       const int want = (active * 5 + 7) >> 3;
-      bool trav = st == ST_LINE && pend < 0 && s.ni < nn;
+      bool trav = st == ST_LINE && pend < 0 && s.ni != kDone;
       while (trav) {
         if (active - __popcll(__ballot(1)) >= want) break;
-        // a 32-bit byte offset from the uniform base (one address instruction);
-        // the step is written without branches: crossed internal node -> its
-        // first child, anything else -> the skip index; a crossed leaf parks
-        using Node = typename Rec<R, D>::Node;
-        const Node node = *reinterpret_cast<const Node*>(reinterpret_cast<const char*>(a.scene.nodes) +
-                                                         (uint32_t)s.ni * (uint32_t)sizeof(Node));
-        if (COUNT) wc.nodes += 1;
-        const bool crossed = line_box<R, D>(node, s.inv, s.ox);
-        const bool at_leaf = crossed && node.child < 0;
-        const int32_t nxt = (crossed && node.child >= 0) ? node.child : node.skip;
-        pend = at_leaf ? -1 - node.child : pend;
-        s.ni = nxt;
-        trav = !at_leaf && nxt < nn;
+        // one step: take the position (or pop it), fetch an interior record by
+        // a 32-bit byte offset from the uniform base, test both child boxes;
+        // both crossed -> push the second; a leaf entry parks the lane
+        int32_t e = s.ni;
+        if (e == kPop) e = sp > 0 ? stk[--sp * BLOCK] : kDone;
+        if (e >= 0 && e != kDone) {
+          using Node = typename Rec<R, D>::Node;
+          const Node node = *reinterpret_cast<const Node*>(reinterpret_cast<const char*>(a.scene.nodes) +
+                                                           (uint32_t)e * (uint32_t)sizeof(Node));
+          if (COUNT) wc.nodes += 1;
+          const bool h0 = line_box<R, D>(node.lo0, node.hi0, s.inv, s.ox);
+          const bool h1 = line_box<R, D>(node.lo1, node.hi1, s.inv, s.ox);
+          if (h0 && h1 && sp < a.scene.stack_cap) stk[sp++ * BLOCK] = node.child[1];
+          e = h0 ? node.child[0] : (h1 ? node.child[1] : kPop);
+        }
+        const bool at_leaf = e < 0 && e != kPop;
+        pend = at_leaf ? -1 - e : pend;
+        s.ni = at_leaf ? kPop : e;
+        trav = !at_leaf && e != kDone;
       }
       // the parked lanes test their leaves together
       if (pend >= 0) {
@@ -817,9 +826,9 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       // path steps run once a quarter of the working lanes stand at the end of
       // their line, or when no lane steps (measured: 396, 402, 404, 403, 400 M
       // path samples/s for 0, 1/8, 1/4, 3/8, 1/2)
-      const bool at_end = st == ST_LINE && s.ni >= nn;
+      const bool at_end = st == ST_LINE && s.ni == kDone;
       const int n_end = __popcll(__ballot(at_end));
-      const int stepping = __popcll(__ballot(st == ST_LINE && s.ni < nn));
+      const int stepping = __popcll(__ballot(st == ST_LINE && s.ni != kDone));
       if (4 * n_end >= 64 - idle || stepping == 0) {
         if (at_end) st = end_step<R, D, FORM, TRACE, COUNT, KEXT>(a, s, wc);
       }
@@ -1147,9 +1156,8 @@ __global__ void __launch_bounds__(256) intersect_kernel(SceneView<R, D> s, const
   for (int a = 0; a < 3; ++a) {
     x[a] = a < D ? orig[l * D + a] : (R)0;
     d[a] = a < D ? dir[l * D + a] : (R)0;
-    inv[a] = safe_inv(d[a]);
-    ox[a] = -x[a] * inv[a];
   }
+  line_slabs<R, D>(s, x, d, inv, ox);
   const int32_t ex_id = exclude ? exclude[l] : -1;
   const int32_t ex = (ex_id >= 0 && ex_id < s.n_prims) ? s.leaf_of_id[ex_id] : -1;
   int32_t cnt = 0;

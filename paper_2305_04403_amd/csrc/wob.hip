@@ -2,6 +2,7 @@
 // kernel dispatch.  The kernels themselves live in walk.hpp / device.hpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -17,34 +18,59 @@ using namespace wobi;
 namespace {
 
 constexpr int kMaxLeaf = 4;
-// Round a double to float toward -inf / +inf so boxes stay conservative.
-float down_f(double v) {
-  float f = (float)v;
-  if ((double)f > v) f = std::nextafter(f, -INFINITY);
-  return f;
+// Round a double to binary16 toward -inf / +inf (|v| well inside the range).
+_Float16 step_h(_Float16 h, bool up) {
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  if ((u & 0x7fff) == 0) u = up ? 0x0001 : 0x8001;  // +-0 -> the smallest subnormal
+  else if ((u & 0x8000) != 0) u = up ? u - 1 : u + 1;
+  else u = up ? u + 1 : u - 1;
+  std::memcpy(&h, &u, 2);
+  return h;
 }
-float up_f(double v) {
-  float f = (float)v;
-  if ((double)f < v) f = std::nextafter(f, INFINITY);
-  return f;
+_Float16 down_h(double v) {
+  _Float16 h = (_Float16)v;
+  if ((double)h > v) h = step_h(h, false);
+  return h;
+}
+_Float16 up_h(double v) {
+  _Float16 h = (_Float16)v;
+  if ((double)h < v) h = step_h(h, true);
+  return h;
 }
 
-template <typename R> R round_to(double v) { return (R)v; }
-
-// Pad a box so that the FMA slab test in R precision never misses a primitive
-// that the exact test would hit.
+// Frame of the stored boxes: y' = (y - c) k with c the root box's centre
+// (rounded to R, as the kernels use it) and k a power of two, |y'| <= 1.
 template <typename R>
-void padded_box(const wobhost::Box& b, int dim, R lo[3], R hi[3]) {
-  double mag = 0.0;
-  for (int a = 0; a < dim; ++a) mag = std::fmax(mag, std::fmax(std::fabs(b.lo[a]), std::fabs(b.hi[a])));
-  const double pad = (sizeof(R) == 4 ? 0x1p-19 : 0x1p-45) * (mag + 1e-30);
+void box_frame(const wobhost::Box& root, int dim, double c[3], double& k) {
+  double half = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    c[a] = a < dim ? (double)(R)(0.5 * (root.lo[a] + root.hi[a])) : 0.0;
+    if (a < dim) half = std::fmax(half, std::fmax(std::fabs(root.lo[a] - c[a]), std::fabs(root.hi[a] - c[a])));
+  }
+  k = half > 0.0 ? std::ldexp(1.0, -std::ilogb(half) - 1) : 1.0;
+}
+
+// A box in the frame, padded so that the FMA slab test in R precision never
+// misses a primitive that the exact test would hit, then rounded outward to
+// the stored type (binary16 in FP32 scenes).
+template <typename R>
+void framed_box(const wobhost::Box& b, int dim, const double c[3], double k, wob::BoxT<R> lo[3],
+                wob::BoxT<R> hi[3]) {
+  double l[3], h[3], mag = 0.0;
   for (int a = 0; a < dim; ++a) {
-    if (sizeof(R) == 4) {
-      lo[a] = (R)down_f(b.lo[a] - pad);
-      hi[a] = (R)up_f(b.hi[a] + pad);
+    l[a] = (b.lo[a] - c[a]) * k;
+    h[a] = (b.hi[a] - c[a]) * k;
+    mag = std::fmax(mag, std::fmax(std::fabs(l[a]), std::fabs(h[a])));
+  }
+  const double pad = (sizeof(R) == 4 ? 0x1p-19 : 0x1p-45) * (mag + 1.0);
+  for (int a = 0; a < dim; ++a) {
+    if constexpr (sizeof(R) == 4) {
+      lo[a] = down_h(l[a] - pad);
+      hi[a] = up_h(h[a] + pad);
     } else {
-      lo[a] = (R)(b.lo[a] - pad);
-      hi[a] = (R)(b.hi[a] + pad);
+      lo[a] = (R)(l[a] - pad);
+      hi[a] = (R)(h[a] + pad);
     }
   }
 }
@@ -55,22 +81,35 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   using Node = typename wob::Rec<R, D>::Node;
   using Prim = typename wob::Rec<R, D>::Prim;
   const int64_t T = sc->n_prims;
-  // the traversal addresses nodes by a 32-bit byte offset
-  if ((uint64_t)bvh.nodes.size() * sizeof(Node) > 0xffffffffull) return WOB_E_ARG;
-  std::vector<Node> nodes(bvh.nodes.size());
-  for (size_t i = 0; i < bvh.nodes.size(); ++i) {
-    const auto& fn = bvh.nodes[i];
-    Node& n = nodes[i];
+  // interior records in pre-order; the first child of interior node i is
+  // node i + 1, the second the first node after the first child's subtree
+  const auto& fn = bvh.nodes;
+  std::vector<int32_t> rec_of(fn.size(), -1);
+  int32_t n_inner = 0;
+  for (size_t i = 0; i < fn.size(); ++i)
+    if (fn[i].child >= 0) rec_of[i] = n_inner++;
+  // the traversal addresses records by a 32-bit byte offset
+  if ((uint64_t)n_inner * sizeof(Node) > 0xffffffffull) return WOB_E_ARG;
+  auto entry = [&](size_t i) { return fn[i].child >= 0 ? rec_of[i] : fn[i].child; };
+  double fc[3], fk;
+  box_frame<R>(fn[0].box, D, fc, fk);
+  std::vector<Node> nodes((size_t)n_inner);
+  for (size_t i = 0; i < fn.size(); ++i) {
+    if (fn[i].child < 0) continue;
+    Node& n = nodes[rec_of[i]];
     std::memset(&n, 0, sizeof(Node));
-    R lo[3], hi[3];
-    padded_box<R>(fn.box, D, lo, hi);
-    for (int a = 0; a < D; ++a) {
-      n.lo[a] = lo[a];
-      n.hi[a] = hi[a];
-    }
-    n.skip = fn.skip;
-    n.child = fn.child;
+    const size_t c0 = (size_t)fn[i].child, c1 = (size_t)fn[c0].skip;
+    framed_box<R>(fn[c0].box, D, fc, fk, n.lo0, n.hi0);
+    framed_box<R>(fn[c1].box, D, fc, fk, n.lo1, n.hi1);
+    n.child[0] = entry(c0);
+    n.child[1] = entry(c1);
   }
+  sc->n_inner = n_inner;
+  for (int a = 0; a < 3; ++a) sc->frame_c[a] = fc[a];
+  sc->frame_k = fk;
+  sc->root = entry(0);
+  sc->stack_cap = std::max(bvh.depth - 1, 1);
+  if (sc->stack_cap > wob::kMaxDepth) return WOB_E_MESH;
   std::vector<Prim> recs((size_t)T);
   std::vector<R> normals((size_t)T * 4, (R)0);
   std::vector<int32_t> leaf_of_id((size_t)T);
@@ -115,7 +154,7 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   }
   sc->node_bytes = sizeof(Node);
   sc->prim_bytes = sizeof(Prim);
-  const size_t nb = nodes.size() * sizeof(Node), pb = recs.size() * sizeof(Prim),
+  const size_t nb = std::max(nodes.size(), (size_t)1) * sizeof(Node), pb = recs.size() * sizeof(Prim),
                lb = leaf_of_id.size() * sizeof(int32_t), qb = normals.size() * sizeof(R);
   if (hipMalloc(&sc->d_nodes, nb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc(&sc->d_prims, pb) != hipSuccess) return WOB_E_ALLOC;
@@ -123,7 +162,9 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   if (hipMemcpy(sc->d_normals, normals.data(), qb, hipMemcpyHostToDevice) != hipSuccess)
     return WOB_E_DEVICE;
   if (hipMalloc((void**)&sc->d_leaf_of_id, lb) != hipSuccess) return WOB_E_ALLOC;
-  if (hipMemcpy(sc->d_nodes, nodes.data(), nb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
+  if (!nodes.empty() &&
+      hipMemcpy(sc->d_nodes, nodes.data(), nodes.size() * sizeof(Node), hipMemcpyHostToDevice) != hipSuccess)
+    return WOB_E_DEVICE;
   if (hipMemcpy(sc->d_prims, recs.data(), pb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
   if (hipMemcpy(sc->d_leaf_of_id, leaf_of_id.data(), lb, hipMemcpyHostToDevice) != hipSuccess)
     return WOB_E_DEVICE;
@@ -155,32 +196,33 @@ void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
   constexpr int B = kSolveBlock;
   const int ppb = B >> a.lpp_shift;
   const dim3 grid((unsigned)((a.n_points + ppb - 1) / ppb)), block(B);
+  const size_t lds = (size_t)a.scene.stack_cap * B * sizeof(int32_t);  // traversal stacks
   if constexpr (FORM != wob::F_FWD) {
     if (a.grad_out || a.path_grad_out) {  // value and gradient along the same paths
       if (mode == MODE_TRACE)
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_GRAD>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_GRAD>), grid, block, lds, st, a);
       else
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_GRAD>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_GRAD>), grid, block, lds, st, a);
       return;
     }
   }
   if constexpr (D == 3 && FORM == wob::F_SL) {
     if (a.cv_g) {
       if (mode == MODE_SOLVE)
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_CV>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_CV>), grid, block, lds, st, a);
       else if (mode == MODE_TRACE)
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_CV>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_CV>), grid, block, lds, st, a);
       else
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B, wob::X_CV>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B, wob::X_CV>), grid, block, lds, st, a);
       return;
     }
   }
   if (mode == MODE_SOLVE)
-    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B>), grid, block, lds, st, a);
   else if (mode == MODE_TRACE)
-    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B>), grid, block, lds, st, a);
   else
-    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B>), grid, block, lds, st, a);
 }
 
 template <typename R, int D>
@@ -278,7 +320,7 @@ wob_status wob_build_bvh(int32_t dim, int32_t precision, const double* verts, in
   if (dim != 2 && dim != 3) return WOB_E_ARG;
   if (precision != WOB_F32 && precision != WOB_F64) return WOB_E_ARG;
   if (!verts || !prims || n_verts <= 0 || n_prims <= 0) return WOB_E_ARG;
-  if (n_prims > wob::kIdMask) return WOB_E_ARG;
+  if (n_prims >= ((int64_t)1 << 27)) return WOB_E_ARG;  // leaf entries pack the first index in 27 bits
   // vertices rounded to the scene precision: both the walk and any external
   // checker then see the same geometry
   std::vector<double> v((size_t)(n_verts * dim));
