@@ -10,14 +10,13 @@ namespace wobhost {
 namespace {
 
 constexpr int kBins = 32;
-// SAH costs of one box test and one primitive test.  The walk tests crossed
-// leaves in batches (parked lanes), which makes a primitive test relatively
-// cheap: measured on the 20,480-triangle icosphere benchmark (leaves of at
-// most 4), primitive cost 0.5 / 0.75 / 1 / 1.5: 103.6 / 103.7 / 105.2 / 114.1
-// ms per solve (100 / 107 / 112 / 120 nodes and 22 / 17 / 14 / 11 triangles
-// per line); leaves of up to 8 with cost 0.5 / 0.35 / 0.25 were slower.
+// SAH costs of visiting an interior node (one record: the two child boxes)
+// and of one primitive test.  Measured on the 20,480-triangle icosphere
+// benchmark (leaves of at most 4), primitive cost 0.5 / 0.75 / 1 / 1.5: 75.9 /
+// 75.0 / 75.9 / 80.6 ms per solve (50 / 53 / 56 / 60 interior nodes and 23 /
+// 17 / 14 / 11 triangles per line).
 constexpr double kNodeCost = 1.0;
-constexpr double kPrimCost = 0.5;
+constexpr double kPrimCost = 0.75;
 // Below this depth subtrees are split at the centroid median, which bounds
 // the depth by kSahDepth + log2(n) whatever the geometry (the traversal stack
 // holds one entry per level).

@@ -32,11 +32,14 @@ enum Program { P_CONST = 0, P_LINEAR = 1, P_QUAD = 2, P_INVDIST = 3 };
 // with mixed-precision FMAs.  A child entry is the index of an interior record
 // (>= 0) or a leaf, -1 - ((first << 3) | (count - 1)) with first the
 // leaf-order index of its first primitive (< 2^27).
-template <typename R> struct BoxScalar { using T = R; };
-template <> struct BoxScalar<float> { using T = _Float16; };
-template <typename R> using BoxT = typename BoxScalar<R>::T;
-template <typename R> struct alignas(32) Inner3 { BoxT<R> lo0[3], hi0[3], lo1[3], hi1[3]; int32_t child[2]; };
-template <typename R> struct alignas(32) Inner2 { BoxT<R> lo0[2], hi0[2], lo1[2], hi1[2]; int32_t child[2]; };
+template <typename R> struct alignas(32) Inner3 { R lo0[3], hi0[3], lo1[3], hi1[3]; int32_t child[2]; };
+template <typename R> struct alignas(32) Inner2 { R lo0[2], hi0[2], lo1[2], hi1[2]; int32_t child[2]; };
+// FP32 scenes: one word per box and axis, binary16 lo in the low half and hi
+// in the high half.  A lane rotates each word by 16 bits when its direction is
+// negative on that axis, so the low half is the slab's near side and the high
+// half its far side without a min / max per axis.
+template <> struct alignas(32) Inner3<float> { uint32_t box0[3], box1[3]; int32_t child[2]; };
+template <> struct alignas(32) Inner2<float> { uint32_t box0[2], box1[2]; int32_t child[2]; };
 // Traversal positions besides entries: take the next entry from the stack,
 // and the line's traversal is over.
 constexpr int32_t kPop = INT32_MIN;
@@ -418,21 +421,21 @@ __device__ __forceinline__ void hit_point(const PrimGeo<R>& g, R u, R v, R y[3])
 
 // Slab test of a line against a box in the scene's box frame; inv = 1 / d
 // (finite), ox = -x' inv with x' the line's point in that frame.
-template <typename R, int D, typename B>
-__device__ __forceinline__ bool line_box(const B lo[3], const B hi[3], const R inv[3], const R ox[3]) {
+template <typename R, int D>
+__device__ __forceinline__ bool line_box(const R lo[3], const R hi[3], const R inv[3], const R ox[3]) {
   R tmin, tmax;
   {
-    const R a = fma((R)lo[0], inv[0], ox[0]), b = fma((R)hi[0], inv[0], ox[0]);
+    const R a = fma(lo[0], inv[0], ox[0]), b = fma(hi[0], inv[0], ox[0]);
     tmin = fmin(a, b);
     tmax = fmax(a, b);
   }
   {
-    const R a = fma((R)lo[1], inv[1], ox[1]), b = fma((R)hi[1], inv[1], ox[1]);
+    const R a = fma(lo[1], inv[1], ox[1]), b = fma(hi[1], inv[1], ox[1]);
     tmin = fmax(tmin, fmin(a, b));
     tmax = fmin(tmax, fmax(a, b));
   }
   if constexpr (D == 3) {
-    const R a = fma((R)lo[2], inv[2], ox[2]), b = fma((R)hi[2], inv[2], ox[2]);
+    const R a = fma(lo[2], inv[2], ox[2]), b = fma(hi[2], inv[2], ox[2]);
     tmin = fmax(tmin, fmin(a, b));
     tmax = fmin(tmax, fmax(a, b));
   }
@@ -444,14 +447,47 @@ template <typename R> __device__ __forceinline__ R safe_inv(R d) {
   return d == (R)0 ? big : (R)1 / d;
 }
 
-// Slab-test constants of the line x + t d: inv = 1 / d, ox = -x' inv.
+// Slab-test constants of the line x + t d: inv = 1 / d, ox = -x' inv, and
+// the rotation that puts a packed box word's near side in its low half.
 template <typename R, int D>
 __device__ __forceinline__ void line_slabs(const SceneView<R, D>& s, const R x[3], const R d[3], R inv[3],
-                                           R ox[3]) {
+                                           R ox[3], uint32_t rot[3]) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     inv[k] = safe_inv(d[k]);
     ox[k] = -((x[k] - s.fc[k]) * s.fk) * inv[k];
+    rot[k] = inv[k] < (R)0 ? 16u : 0u;
+  }
+}
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// Slab test against a packed binary16 box (FP32 scenes).
+template <int D>
+__device__ __forceinline__ bool packed_box(const uint32_t b[3], const float inv[3], const float ox[3],
+                                           const uint32_t rot[3]) {
+  float tn[3], tf[3];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const half2_t v = __builtin_bit_cast(half2_t, __builtin_amdgcn_alignbit(b[k], b[k], rot[k]));
+    tn[k] = fmaf((float)v.x, inv[k], ox[k]);
+    tf[k] = fmaf((float)v.y, inv[k], ox[k]);
+  }
+  const float tmin = D == 3 ? fmaxf(fmaxf(tn[0], tn[1]), tn[2]) : fmaxf(tn[0], tn[1]);
+  const float tmax = D == 3 ? fminf(fminf(tf[0], tf[1]), tf[2]) : fminf(tf[0], tf[1]);
+  return tmin <= tmax;
+}
+
+// Which of an interior record's two child boxes the line crosses.
+template <typename R, int D>
+__device__ __forceinline__ void child_hits(const typename Rec<R, D>::Node& n, const R inv[3], const R ox[3],
+                                           const uint32_t rot[3], bool& h0, bool& h1) {
+  if constexpr (sizeof(R) == 4) {
+    h0 = packed_box<D>(n.box0, inv, ox, rot);
+    h1 = packed_box<D>(n.box1, inv, ox, rot);
+  } else {
+    h0 = line_box<R, D>(n.lo0, n.hi0, inv, ox);
+    h1 = line_box<R, D>(n.lo1, n.hi1, inv, ox);
   }
 }
 
@@ -461,7 +497,7 @@ __device__ __forceinline__ void line_slabs(const SceneView<R, D>& s, const R x[3
 // where lanes park at crossed leaves and test them together.
 template <typename R, int D, bool COUNT, typename Leaf>
 __device__ __forceinline__ void for_each_leaf(const SceneView<R, D>& s, const R inv[3], const R ox[3],
-                                              WorkCount& wc, Leaf&& leaf) {
+                                              const uint32_t rot[3], WorkCount& wc, Leaf&& leaf) {
   int32_t stk[kMaxDepth];
   int sp = 0;
   int32_t e = s.root;
@@ -469,7 +505,8 @@ __device__ __forceinline__ void for_each_leaf(const SceneView<R, D>& s, const R 
     if (e >= 0) {
       const typename Rec<R, D>::Node n = s.nodes[e];
       if (COUNT) wc.nodes += 1;
-      const bool h0 = line_box<R, D>(n.lo0, n.hi0, inv, ox), h1 = line_box<R, D>(n.lo1, n.hi1, inv, ox);
+      bool h0, h1;
+      child_hits<R, D>(n, inv, ox, rot, h0, h1);
       if (h0 && h1 && sp < kMaxDepth) stk[sp++] = n.child[1];
       e = h0 ? n.child[0] : (h1 ? n.child[1] : kPop);
     } else if (e != kPop) {

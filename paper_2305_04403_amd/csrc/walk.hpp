@@ -108,6 +108,7 @@ struct PathState {
   PrimGeo<R> gc;         // the primitive the vertex lies on (direct, single layer)
   R nc[3];
   R d[3], inv[3], ox[3];
+  uint32_t rot[3];        // slab-test rotations of packed box words
   HitAcc<R> h;
   int32_t ni;            // traversal position: an entry, kPop or kDone
   R Wg[3], gacc[3];      // gradient walk: d W / d x0 and the gradient sum
@@ -343,7 +344,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
     // the direct BIE's last line and the corrected walk's last line need no pick
     s.select = !((FORM == F_DIRECT || CV) && s.last);
     s.sum = CV && (s.i > 0 || s.last);
-    line_slabs<R, D>(a.scene, s.x, s.d, s.inv, s.ox);
+    line_slabs<R, D>(a.scene, s.x, s.d, s.inv, s.ox, s.rot);
     s.h.m = 0;
     s.h.key = 0xffffffffu;
     s.h.id = 0x7fffffff;
@@ -790,11 +791,10 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       // lanes parked at the end of their line, and lanes that step through nodes
       const int ends = __popcll(__ballot(st == ST_LINE && pend < 0 && s.ni == kDone));
       const int active = 64 - idle - ends;
-      // node steps until 5/8 of the stepping lanes stand at a crossed leaf
-      // (measured on the icosphere benchmark, 1/16 .. 16/16 of the lanes:
-      // 236, 286, 352, 393, 395, 388, 352, 244 M path samples/s at 1/16, 1/8,
-      // 1/4, 1/2, 5/8, 3/4, 7/8, 1)
-      const int want = (active * 5 + 7) >> 3;
+      // node steps until half of the stepping lanes stand at a crossed leaf
+      // (measured on the icosphere benchmark: 579, 574, 544 M path samples/s
+      // at 1/2, 5/8, 3/4)
+      const int want = (active * 4 + 7) >> 3;
       bool trav = st == ST_LINE && pend < 0 && s.ni != kDone;
       while (trav) {
         if (active - __popcll(__ballot(1)) >= want) break;
@@ -808,8 +808,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
           const Node node = *reinterpret_cast<const Node*>(reinterpret_cast<const char*>(a.scene.nodes) +
                                                            (uint32_t)e * (uint32_t)sizeof(Node));
           if (COUNT) wc.nodes += 1;
-          const bool h0 = line_box<R, D>(node.lo0, node.hi0, s.inv, s.ox);
-          const bool h1 = line_box<R, D>(node.lo1, node.hi1, s.inv, s.ox);
+          bool h0, h1;
+          child_hits<R, D>(node, s.inv, s.ox, s.rot, h0, h1);
           if (h0 && h1 && sp < a.scene.stack_cap) stk[sp++ * BLOCK] = node.child[1];
           e = h0 ? node.child[0] : (h1 ? node.child[1] : kPop);
         }
@@ -824,8 +824,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         pend = -1;
       }
       // path steps run once a quarter of the working lanes stand at the end of
-      // their line, or when no lane steps (measured: 396, 402, 404, 403, 400 M
-      // path samples/s for 0, 1/8, 1/4, 3/8, 1/2)
+      // their line, or when no lane steps (measured: 557, 574, 566 M path
+      // samples/s for 1/8, 1/4, 3/8)
       const bool at_end = st == ST_LINE && s.ni == kDone;
       const int n_end = __popcll(__ballot(at_end));
       const int stepping = __popcll(__ballot(st == ST_LINE && s.ni != kDone));
@@ -1153,16 +1153,17 @@ __global__ void __launch_bounds__(256) intersect_kernel(SceneView<R, D> s, const
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= n_lines) return;
   R x[3], d[3], inv[3], ox[3];
+  uint32_t rot[3];
   for (int a = 0; a < 3; ++a) {
     x[a] = a < D ? orig[l * D + a] : (R)0;
     d[a] = a < D ? dir[l * D + a] : (R)0;
   }
-  line_slabs<R, D>(s, x, d, inv, ox);
+  line_slabs<R, D>(s, x, d, inv, ox, rot);
   const int32_t ex_id = exclude ? exclude[l] : -1;
   const int32_t ex = (ex_id >= 0 && ex_id < s.n_prims) ? s.leaf_of_id[ex_id] : -1;
   int32_t cnt = 0;
   WorkCount wc = {0, 0, 0, 0};
-  for_each_leaf<R, D, false>(s, inv, ox, wc, [&](int32_t first, int32_t count) {
+  for_each_leaf<R, D, false>(s, inv, ox, rot, wc, [&](int32_t first, int32_t count) {
     for (int32_t j = first; j < first + count; ++j) {
       if (j == ex) continue;
       const PrimGeo<R> g = load_prim<R, D>(s, j);

@@ -52,25 +52,27 @@ void box_frame(const wobhost::Box& root, int dim, double c[3], double& k) {
 }
 
 // A box in the frame, padded so that the FMA slab test in R precision never
-// misses a primitive that the exact test would hit, then rounded outward to
-// the stored type (binary16 in FP32 scenes).
-template <typename R>
-void framed_box(const wobhost::Box& b, int dim, const double c[3], double k, wob::BoxT<R> lo[3],
-                wob::BoxT<R> hi[3]) {
+// misses a primitive that the exact test would hit, stored rounded outward
+// (FP32 scenes: binary16 pairs, lo in the low half of each word).
+template <typename R, int D, typename Node>
+void store_box(const wobhost::Box& b, const double c[3], double k, Node& n, int which) {
   double l[3], h[3], mag = 0.0;
-  for (int a = 0; a < dim; ++a) {
+  for (int a = 0; a < D; ++a) {
     l[a] = (b.lo[a] - c[a]) * k;
     h[a] = (b.hi[a] - c[a]) * k;
     mag = std::fmax(mag, std::fmax(std::fabs(l[a]), std::fabs(h[a])));
   }
   const double pad = (sizeof(R) == 4 ? 0x1p-19 : 0x1p-45) * (mag + 1.0);
-  for (int a = 0; a < dim; ++a) {
+  for (int a = 0; a < D; ++a) {
     if constexpr (sizeof(R) == 4) {
-      lo[a] = down_h(l[a] - pad);
-      hi[a] = up_h(h[a] + pad);
+      const _Float16 lo = down_h(l[a] - pad), hi = up_h(h[a] + pad);
+      uint16_t ul, uh;
+      std::memcpy(&ul, &lo, 2);
+      std::memcpy(&uh, &hi, 2);
+      (which == 0 ? n.box0 : n.box1)[a] = (uint32_t)ul | ((uint32_t)uh << 16);
     } else {
-      lo[a] = (R)(l[a] - pad);
-      hi[a] = (R)(h[a] + pad);
+      (which == 0 ? n.lo0 : n.lo1)[a] = (R)(l[a] - pad);
+      (which == 0 ? n.hi0 : n.hi1)[a] = (R)(h[a] + pad);
     }
   }
 }
@@ -99,8 +101,8 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
     Node& n = nodes[rec_of[i]];
     std::memset(&n, 0, sizeof(Node));
     const size_t c0 = (size_t)fn[i].child, c1 = (size_t)fn[c0].skip;
-    framed_box<R>(fn[c0].box, D, fc, fk, n.lo0, n.hi0);
-    framed_box<R>(fn[c1].box, D, fc, fk, n.lo1, n.hi1);
+    store_box<R, D>(fn[c0].box, fc, fk, n, 0);
+    store_box<R, D>(fn[c1].box, fc, fk, n, 1);
     n.child[0] = entry(c0);
     n.child[1] = entry(c1);
   }
