@@ -43,15 +43,16 @@ sys.path.insert(0, ROOT)
 # half of it is the attainable issue rate)
 FP32_PEAK_TFLOPS = 157.3
 # algorithmic operations of the traversal: a visited interior node tests the
-# boxes of its two children, each slab test 6 FMA (12), 6 min / max, 2
-# three-way min / max (4) and one compare = 23; a tested triangle (numerator
-# form of Moller-Trumbore, a miss) is two cross products (18), three dots (15),
-# x - v0 (3), three sign products and four compares = 43
-NODE_FLOP, TRI_FLOP = 2 * 23, 43
-# algorithmic bytes: an interior node is its children's boxes (12 x 4 B) and
-# entries (2 x 4 B); a tested triangle is v0, e1, e2 (9 x 4 B); a hit also
-# reads id, kind and alpha (12 B)
-NODE_BYTES, TRI_BYTES, HIT_BYTES = 56, 36, 12
+# boxes of its two children, each slab test (near / far sides ordered by the
+# direction's signs, fixed per line) 6 FMA (12), 2 three-way max / min (4) and
+# one compare = 17; a tested triangle (numerator form of Moller-Trumbore, a
+# miss) is two cross products (18), three dots (15), x - v0 (3), three sign
+# products and four compares = 43
+NODE_FLOP, TRI_FLOP = 2 * 17, 43
+# algorithmic bytes: an interior node is its children's boxes (12 binary16
+# values, 24 B) and entries (2 x 4 B); a tested triangle is v0, e1, e2
+# (9 x 4 B); a hit also reads id, kind and alpha (12 B)
+NODE_BYTES, TRI_BYTES, HIT_BYTES = 32, 36, 12
 
 
 KERNEL_SOURCES = ("paper_2305_04403_amd/csrc/device.hpp", "paper_2305_04403_amd/csrc/walk.hpp",
@@ -549,10 +550,12 @@ def main():
     }
     cal = gather_calibration(torch, wob)
     rec["gather"]["calibrated_random_32B_GB/s"] = cal
-    # above 1: the traversal's reads are not uniformly random (the upper tree
-    # levels are shared by all lanes and stay in the CU caches), so the L2
-    # gather rate does not bound it
-    rec["gather"]["ratio_to_random_2MiB"] = rec["gather"]["GB/s"] / cal["2MiB"]
+    # records the traversal reads per second (interior nodes, triangles, hits)
+    # against the rate of random 32-byte records from an L2-resident buffer;
+    # above 1: the upper tree levels, shared by all lanes, stay in the CU caches
+    recs = (cnt["nodes"] + cnt["prims"] + cnt["hits"]) / avg_kern_s
+    rec["gather"]["records_per_s"] = recs
+    rec["gather"]["ratio_to_random_2MiB_records"] = recs / (cal["2MiB"] * 1e9 / 32)
     rec.update(extra)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4

@@ -244,12 +244,12 @@ wob_status wob_trace_grad(wob_scene scene, const void* points, int64_t n_points,
                           void* path_grad_out, void* stream);
 
 /* Measurement helper (not part of the method): `lanes` lanes each read
- * `reads` 32-byte records at independent pseudo-random record indices of
- * buf (`bytes` long, a multiple of 32, 16-byte aligned) and write the sum of
- * the first and last float of the records they read to out[lane].  Timed
- * around, it gives the random-gather rate of the memory level that holds a
- * working set of that size: the bandwidth roof of the traversal, which reads
- * node and triangle records the same way.  Errors: WOB_E_ARG, WOB_E_DEVICE. */
+ * `reads` 32-byte records (two 16-byte loads) at independent pseudo-random
+ * record indices of buf (`bytes` long, a multiple of 32, 16-byte aligned) and
+ * write the sum of all eight floats of the records they read to out[lane].
+ * Timed around, it gives the random-gather rate of the memory level that
+ * holds a working set of that size, for records read the way the traversal
+ * reads its interior-node records.  Errors: WOB_E_ARG, WOB_E_DEVICE. */
 wob_status wob_gather_probe(const void* buf, int64_t bytes, int64_t lanes, int32_t reads, uint32_t seed,
                             float* out, void* stream);
 

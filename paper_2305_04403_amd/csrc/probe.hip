@@ -20,8 +20,8 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 }
 
 // Each lane reads `reads` records (two 16-byte loads) at independent
-// pseudo-random record indices and writes the sum of the first and last word
-// of every record it read (so that no load is dead).
+// pseudo-random record indices and writes the sum of all words of every
+// record it read (so that every load is whole and none is dead).
 __global__ void __launch_bounds__(256) gather_probe_kernel(const float4* __restrict__ buf, uint32_t n_rec,
                                                            int32_t reads, uint32_t seed,
                                                            float* __restrict__ out, int64_t lanes) {
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(256) gather_probe_kernel(const float4* __restr
     h = mix32(h + 0x632be5abu);
     const uint32_t i = (uint32_t)(((uint64_t)h * n_rec) >> 32);  // uniform in [0, n_rec)
     const float4 a = buf[2 * (uint64_t)i], b = buf[2 * (uint64_t)i + 1];
-    acc += a.x + b.w;
+    acc += ((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w));
   }
   out[t] = acc;
 }

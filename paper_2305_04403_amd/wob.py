@@ -379,8 +379,8 @@ def trace_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
 
 def gather_probe(buf, lanes: int, reads: int, seed: int = 0, out=None, stream=None):
     """Random 32-byte gathers from the device buffer ``buf`` (``wob_gather_probe``):
-    returns one float per lane (the sum of the first and last float of each
-    record read)."""
+    returns one float per lane (the sum of all eight floats of each record
+    read)."""
     torch = _torch()
     if out is None:
         out = torch.empty(lanes, dtype=torch.float32, device=buf.device)

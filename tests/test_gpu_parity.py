@@ -411,11 +411,11 @@ def test_nonfinite_paths_counted_and_left_out(W):
 
 def test_gather_probe(W):
     """The bandwidth probe reads whole 32-byte records inside the buffer: on a
-    buffer of ones every lane returns 2 per read; bad sizes are rejected."""
+    buffer of ones every lane returns 8 per read; bad sizes are rejected."""
     buf = torch.ones((1 << 20) // 4, dtype=torch.float32, device="cuda")
     out = W.gather_probe(buf, 1000, 7, seed=3)
     torch.cuda.synchronize()
-    assert torch.all(out == 14.0)
+    assert torch.all(out == 56.0)
     with pytest.raises(W.WobError):
         W.gather_probe(buf[:3], 10, 1)  # 12 bytes: not a whole record
     with pytest.raises(W.WobError):
