@@ -439,7 +439,8 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
   return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
-// The primitives of one crossed leaf of the current line.  The primitive loop
+// The primitives of the crossed leaves a lane holds (one to three, codes -1 =
+// none after the first) on the current line.  The primitive loop
 // only tests and records the accepted primitives in a bit mask; the hits are
 // then handled in a loop of their own, so that the lanes with a hit in this
 // leaf phase do that work together instead of one or two at a time inside the
@@ -450,18 +451,21 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
 // add a(h) F(y_h).
 template <typename R, int D, int FORM, bool COUNT, int EXT>
 __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, D>& s, int32_t code,
-                                          int32_t code2, WorkCount& wc) {
+                                          int32_t code2, int32_t code3, WorkCount& wc) {
   constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
   const SceneView<R, D>& sc = a.scene;
   {
-    // one or two leaves: primitives first + b (b < count) and first2 + b - count
+    // one to three leaves: primitive b is first + b (b < count), then the
+    // second leaf's, then the third's
     const int32_t first = code >> 3, count = (code & 7) + 1;
-    const int32_t first2 = (code2 >> 3) - count, total = count + (code2 >= 0 ? (code2 & 7) + 1 : 0);
+    const int32_t c2 = code2 >= 0 ? (code2 & 7) + 1 : 0;
+    const int32_t first2 = (code2 >> 3) - count, first3 = (code3 >> 3) - count - c2;
+    const int32_t total = count + c2 + (code3 >= 0 ? (code3 & 7) + 1 : 0);
     constexpr bool GEO = FORM == F_DIRECT || CV;  // per-hit work needs the hit's geometry
     uint32_t accepted = 0;  // bit b: primitive b of the leaves is hit
     int32_t id0 = 0;        // caller id of the first hit (no reload for it)
     for (int32_t b = 0; b < total; ++b) {
-      const int32_t j = (b < count ? first : first2) + b;
+      const int32_t j = (b < count ? first : (b < count + c2 ? first2 : first3)) + b;
       if (j == s.cur_idx) continue;
       if (COUNT) wc.prims += 1;
       const PrimGeo<R> g = load_prim<R, D>(sc, j);
@@ -474,7 +478,7 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
     bool later = false;
     while (accepted) {
       const int32_t b = __builtin_ctz(accepted);
-      const int32_t j = (b < count ? first : first2) + b;
+      const int32_t j = (b < count ? first : (b < count + c2 ? first2 : first3)) + b;
       accepted &= accepted - 1;
       PrimGeo<R> g;
       if (GEO || later) g = load_prim<R, D>(sc, j);
@@ -727,7 +731,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   constexpr int KEXT = EXT == X_CV ? ((D == 3 && FORM == F_SL) ? X_CV : X_NONE) : EXT;
   {
     // Paths k = lane_in_point, + lpp, ... of this lane, run as one state
-    // machine.  Lanes step through BVH nodes; a lane that has reached two
+    // machine.  Lanes step through BVH nodes; a lane that has reached three
     // crossed leaves parks until half of the stepping lanes have parked, and
     // the lanes holding leaves then test them together; a lane at the end of its line
     // parks until a quarter of the working lanes have, and those lanes then
@@ -738,7 +742,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     int k = lane_in_point;
     int st = ST_NONE;
     int32_t pend = -1;   // crossed leaf waiting to be tested
-    int32_t pend2 = -1;  // a second one: a lane holding one leaf keeps stepping
+    int32_t pend2 = -1;  // a second and a third one: a lane holding fewer than
+    int32_t pend3 = -1;  // three leaves keeps stepping
     // the lane's traversal stack: LDS, entry k at wob_stack[k * BLOCK + tid]
     // (consecutive lanes in consecutive banks); empty between lines
     int32_t* const stk = wob_stack + tid;
@@ -795,10 +800,11 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       // lanes parked at the end of their line, and lanes that step through nodes
       const int ends = __popcll(__ballot(st == ST_LINE && pend < 0 && s.ni == kDone));
       const int active = 64 - idle - ends;
-      // node steps until half of the stepping lanes hold two crossed leaves or
-      // stand at the end of their line; a lane keeps stepping while it holds
-      // one (measured on the icosphere benchmark, 3/8, 1/2, 5/8: 678, 688,
-      // 677 M path samples/s; parking at the first leaf: 622)
+      // node steps until half of the stepping lanes hold three crossed leaves
+      // or stand at the end of their line; a lane keeps stepping while it
+      // holds fewer (measured on the icosphere benchmark: parking at the
+      // first / second / third leaf 622 / 694 / 711 M path samples/s; with
+      // two, a wait for 3/8, 1/2, 5/8 of the lanes: 678, 688, 677)
       const int want = (active * 4 + 7) >> 3;
       bool trav = st == ST_LINE && pend < 0 && s.ni != kDone;
       while (trav) {
@@ -819,16 +825,18 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
           e = h0 ? node.child[0] : (h1 ? node.child[1] : kPop);
         }
         const bool at_leaf = e < 0 && e != kPop;
-        const bool second = at_leaf && pend >= 0;
+        const bool second = at_leaf && pend >= 0 && pend2 < 0;
+        const bool third = at_leaf && pend2 >= 0;
+        pend3 = third ? -1 - e : pend3;
         pend2 = second ? -1 - e : pend2;
-        pend = at_leaf ? (second ? pend : -1 - e) : pend;
+        pend = (at_leaf && pend < 0) ? -1 - e : pend;
         s.ni = at_leaf ? kPop : e;
-        trav = !second && e != kDone;
+        trav = !third && e != kDone;
       }
       // the lanes holding leaves test them together
       if (pend >= 0) {
-        leaf_work<R, D, FORM, COUNT, KEXT>(a, s, pend, pend2, wc);
-        pend = pend2 = -1;
+        leaf_work<R, D, FORM, COUNT, KEXT>(a, s, pend, pend2, pend3, wc);
+        pend = pend2 = pend3 = -1;
       }
       // path steps run once a quarter of the working lanes stand at the end of
       // their line, or when no lane steps (measured: 557, 574, 566 M path
