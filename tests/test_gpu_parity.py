@@ -108,6 +108,86 @@ def test_intersect_all_matches_brute_force(W, shape):
     scene.close()
 
 
+def staircase_mesh(n=300, r=0.75):
+    """n triangles, copies of one triangle scaled by r^i toward the origin: a
+    binned SAH tree deeper than 40 levels (the builder's median splits take
+    over there), every stack level of the traversal in use."""
+    tri = np.array([[1.0, 0.0, 0.0], [1.5, 0.5, 0.0], [1.2, 0.0, 0.5]])
+    s = r ** np.arange(n, dtype=np.float64)
+    verts = (s[:, None, None] * tri[None]).reshape(-1, 3)
+    return I.Mesh(3, verts, np.arange(3 * n, dtype=np.int32).reshape(n, 3))
+
+
+def square_mesh():
+    """Two triangles: the whole tree is one leaf (the root entry is a leaf)."""
+    verts = np.array([[-1.0, -1.0, 0.0], [1.0, -1.0, 0.0], [1.0, 1.0, 0.0], [-1.0, 1.0, 0.0]])
+    return I.Mesh(3, verts, np.array([[0, 1, 2], [0, 2, 3]], np.int32))
+
+
+@pytest.mark.parametrize("shape", ["one-leaf-f32", "staircase-f64", "staircase-f32"])
+def test_intersect_all_tree_shapes(W, shape):
+    """Hit lists against the oracle on a scene whose tree is a single leaf and
+    on one deeper than 40 levels (lines through the region where the small
+    triangles nest, so that the traversal goes down the deep branches)."""
+    rng = np.random.default_rng(8)
+    mesh = square_mesh() if shape.startswith("one-leaf") else staircase_mesh()
+    f32 = shape.endswith("f32")
+    if f32:
+        mesh = PT.f32_mesh(mesh)
+    scene = W.Scene(mesh, W.F32 if f32 else W.F64)
+    info = scene.info()
+    if shape.startswith("one-leaf"):
+        assert info["n_leaves"] == 1
+    else:
+        assert info["depth"] > 40
+    n = 4000
+    orig = rng.uniform(-1.5, 1.5, (n, 3))
+    if not shape.startswith("one-leaf"):
+        orig[: n // 2] = rng.uniform(-1.0, 1.0, (n // 2, 3)) * (10.0 ** rng.uniform(-6, 0, (n // 2, 1)))
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    dt = torch.float32 if f32 else torch.float64
+    if f32:
+        orig, d = PT.f32(orig), PT.f32(d)
+    excl = np.full(n, -1, np.int32)
+    nh, hp, ht = W.intersect_all(scene, dev(orig, dt), dev(d, dt), dev(excl, torch.int32), max_hits=64)
+    torch.cuda.synchronize()
+    nh, hp = nh.cpu().numpy(), hp.cpu().numpy()
+    o = oracle.intersect_all(oracle.OracleMesh(mesh), orig, d, excl, max_hits=64)
+    ok = o["graze"] >= PT.GRAZE
+    assert ok.mean() > 0.98
+    assert o["n_hits"][ok].sum() > 100
+    if f32 and not shape.startswith("one-leaf"):
+        # binary32 cannot resolve triangles below about 1e-7 of the distance
+        # to the line's origin: compare the hits of the larger ones (>= 1e-5)
+        big = np.arange(mesh.n_prims) < 40
+        for l in np.nonzero(ok)[0]:
+            g = np.sort(hp[l, :nh[l]])
+            r = np.sort(o["prim"][l, :o["n_hits"][l]])
+            assert np.array_equal(g[big[g]], r[big[r]]), l
+    else:
+        np.testing.assert_array_equal(nh[ok], o["n_hits"][ok])
+        for l in np.nonzero(ok)[0]:
+            assert np.array_equal(np.sort(hp[l, :nh[l]]), np.sort(o["prim"][l, :o["n_hits"][l]])), l
+    scene.close()
+
+
+@pytest.mark.parametrize("shape", ["one-leaf-f32", "staircase-f64"])
+def test_trace_parity_tree_shapes(W, shape):
+    """Per-path parity of a double-layer walk on the one-leaf and the deep
+    scene (the walk kernel's root-leaf start and its full stack)."""
+    mesh = square_mesh() if shape.startswith("one-leaf") else staircase_mesh()
+    prec = "f32" if shape.endswith("f32") else "f64"
+    if prec == "f32":
+        mesh = PT.f32_mesh(mesh)
+    pts = np.random.default_rng(9).uniform(-0.9, 0.9, (40, 3))
+    pts[:, 2] = np.where(np.abs(pts[:, 2]) < 0.05, 0.05, pts[:, 2])
+    if prec == "f32":
+        pts = PT.f32(pts)
+    bc = dict(domain=1, formulation=1, program=oracle.PROG_INVDIST, params=(2.0, 0.5, 0.0))
+    run_trace_parity(W, mesh, pts, None, bc, 64, 4, 21, prec, max_vertex_mismatch_frac=0.002)
+
+
 # ------------------------------------------------------------------- per-path parity
 
 def test_trace_parity_circle_fp64_full_config(W):
