@@ -378,6 +378,13 @@ struct HitAcc {
   R srcg[3];  // gradient walk, direct BIE, line 0: sum over hits of grad_x G q / p_all
 };
 
+// 1 / x for x != 0: in FP32 the hardware reciprocal (1 ulp) unless |x| is
+// below 1e-30 (no denormal reaches it), in FP64 the division.
+template <typename R> __device__ __forceinline__ R recip_(R x) {
+  if constexpr (sizeof(R) == 4) return fabsf(x) >= 1e-30f ? __builtin_amdgcn_rcpf(x) : 1.0f / x;
+  else return 1.0 / x;
+}
+
 // Test one primitive against the line x + t d (t real, inclusive edges).
 // On a hit returns true and writes t and the barycentrics.
 template <typename R, int D>
@@ -396,7 +403,7 @@ __device__ __forceinline__ bool hit_prim(const PrimGeo<R>& g, const R x[3], cons
     const R sd = det < (R)0 ? (R)-1 : (R)1;
     const R us = dot3(sv, pv) * sd, vs = dot3(d, qv) * sd, ad = det * sd;
     if (det == (R)0 || us < (R)0 || vs < (R)0 || us + vs > ad) return false;
-    const R inv = (R)1 / det;
+    const R inv = recip_(det);
     u = us * sd * inv;
     v = vs * sd * inv;
     t = dot3(g.e2, qv) * inv;
@@ -445,9 +452,13 @@ __device__ __forceinline__ bool line_box(const R lo[3], const R hi[3], const R i
   return tmin <= tmax;
 }
 
+// 1 / d for the slab tests, a large finite value for d = 0.  In FP32 the
+// hardware reciprocal (1 ulp) serves: the boxes are padded by far more than
+// the resulting error in the slab parameters; components below 1e-30 count as
+// zero (no denormal reaches the reciprocal).
 template <typename R> __device__ __forceinline__ R safe_inv(R d) {
-  const R big = sizeof(R) == 4 ? (R)1e30 : (R)1e300;
-  return d == (R)0 ? big : (R)1 / d;
+  if constexpr (sizeof(R) == 4) return fabsf(d) < 1e-30f ? 1e30f : __builtin_amdgcn_rcpf(d);
+  else return d == 0.0 ? 1e300 : 1.0 / d;
 }
 
 // Slab-test constants of the line x + t d: inv = 1 / d, ox = -x' inv, and
