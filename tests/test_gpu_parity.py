@@ -62,7 +62,7 @@ def run_trace_parity(W, mesh, pts, pp, bc, N, M, seed, precision, max_vertex_mis
 
 # ------------------------------------------------------------------- hit lists
 
-@pytest.mark.parametrize("shape", ["sphere-f32", "tori-f32", "circle-f64"])
+@pytest.mark.parametrize("shape", ["sphere-f32", "tori-f32", "circle-f64", "circle-f32"])
 def test_intersect_all_matches_brute_force(W, shape):
     rng = np.random.default_rng(3)
     if shape == "sphere-f32":
@@ -71,9 +71,12 @@ def test_intersect_all_matches_brute_force(W, shape):
     elif shape == "tori-f32":
         mesh = PT.f32_mesh(I.torus_union(grid_n=24, seed=2)[0])
         prec, dt = W.F32, torch.float32
-    else:
+    elif shape == "circle-f64":
         mesh = I.circle_polygon(256)
         prec, dt = W.F64, torch.float64
+    else:
+        mesh = PT.f32_mesh(I.circle_polygon(256))
+        prec, dt = W.F32, torch.float32
     dim = mesh.dim
     n = 3000
     orig = rng.uniform(-1.5, 1.5, (n, dim))
@@ -189,6 +192,18 @@ def test_trace_parity_tree_shapes(W, shape):
 
 
 # ------------------------------------------------------------------- per-path parity
+
+def test_trace_parity_dirichlet_2d_f32(W):
+    """2D interior Dirichlet on a perturbed 300-gon in FP32 (binary16 box
+    words of the 2D records), ragged sizes."""
+    c = I.circle_polygon(300)
+    ang = np.arctan2(c.verts[:, 1], c.verts[:, 0])
+    verts = c.verts * (1.0 + 0.1 * np.sin(3 * ang))[:, None]
+    mesh = PT.f32_mesh(I.Mesh(2, verts, c.prims))
+    pts = PT.f32(I.disk_points(45, 0.8, 6))
+    bc = dict(domain=1, formulation=1, program=oracle.PROG_QUAD, params=())
+    run_trace_parity(W, mesh, pts, None, bc, 70, 5, 23, "f32", max_vertex_mismatch_frac=0.002)
+
 
 def test_trace_parity_circle_fp64_full_config(W):
     """2D interior Dirichlet on the 256-gon, FP64, at its full size
