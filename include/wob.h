@@ -113,12 +113,14 @@ typedef struct {
   int32_t dim;          /* 2 or 3 */
   int32_t precision;    /* WOB_F32 / WOB_F64 */
   int64_t n_prims;
-  int64_t n_nodes;
+  int64_t n_nodes;      /* tree nodes (interior + leaves); the device holds the
+                           n_nodes - n_leaves interior ones, each with both
+                           children's boxes */
   int64_t n_leaves;
-  int32_t depth;        /* longest root-to-leaf path */
+  int32_t depth;        /* nodes on the longest root-to-leaf path (root = 1) */
   int32_t max_leaf;     /* most primitives in one leaf */
   int64_t device_bytes; /* bytes of device memory the scene holds */
-  int64_t node_bytes;   /* size of one node record */
+  int64_t node_bytes;   /* size of one interior-node record */
   int64_t prim_bytes;   /* size of one primitive record */
   int32_t n_dirichlet, n_neumann, n_robin, reserved;
 } wob_scene_info;
@@ -129,7 +131,8 @@ typedef struct {
  *   dim        2 (line segments) or 3 (triangles)
  *   precision  WOB_F32 or WOB_F64; vertices are rounded to that precision
  *   verts      HOST array, n_verts * dim doubles
- *   prims      HOST array, n_prims * dim vertex indices; orientation such that
+ *   prims      HOST array, n_prims * dim vertex indices (n_prims < 2^27);
+ *              orientation such that
  *              (v1 - v0) x (v2 - v0) (3D) or the tangent turned by -90 degrees
  *              (2D, counter-clockwise boundary) points OUT of the interior Omega
  *              (Sec. 4.5.1: normals stay outward from Omega for exterior problems)
@@ -209,7 +212,8 @@ wob_status wob_intersect_all(wob_scene scene, const void* orig, const void* dir,
                              int32_t* n_hits, int32_t* hit_prim, void* hit_t, void* stream);
 
 /* Work counters for the same walk as wob_solve (measurement only).
- *   counters  DEVICE, 4 uint64: lines traced, nodes visited, primitives tested,
+ *   counters  DEVICE, 4 uint64: lines traced, interior nodes visited (each
+ *             visit tests the boxes of both children), primitives tested,
  *             hits found; accumulated (the caller zeroes them). */
 wob_status wob_count_work(wob_scene scene, const void* points, const int32_t* point_prim,
                           int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,

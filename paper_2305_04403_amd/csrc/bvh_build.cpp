@@ -20,8 +20,8 @@ constexpr double kNodeCost = 1.0;
 constexpr double kPrimCost = 0.75;
 // Below this depth subtrees are split at the centroid median, which bounds
 // the depth by kSahDepth + log2(n) whatever the geometry (the traversal stack
-// holds one entry per level).
-constexpr int32_t kSahDepth = 40;
+// holds one entry per level; 32 + 26 levels keep it under 64 entries).
+constexpr int32_t kSahDepth = 32;
 
 void grow(Box& b, const Box& o) {
   for (int a = 0; a < 3; ++a) {

@@ -113,7 +113,7 @@ def test_intersect_all_matches_brute_force(W, shape):
 
 def staircase_mesh(n=300, r=0.75):
     """n triangles, copies of one triangle scaled by r^i toward the origin: a
-    binned SAH tree deeper than 40 levels (the builder's median splits take
+    binned SAH tree deeper than 32 levels (the builder's median splits take
     over there), every stack level of the traversal in use."""
     tri = np.array([[1.0, 0.0, 0.0], [1.5, 0.5, 0.0], [1.2, 0.0, 0.5]])
     s = r ** np.arange(n, dtype=np.float64)
@@ -130,7 +130,7 @@ def square_mesh():
 @pytest.mark.parametrize("shape", ["one-leaf-f32", "staircase-f64", "staircase-f32"])
 def test_intersect_all_tree_shapes(W, shape):
     """Hit lists against the oracle on a scene whose tree is a single leaf and
-    on one deeper than 40 levels (lines through the region where the small
+    on one deeper than 32 levels (lines through the region where the small
     triangles nest, so that the traversal goes down the deep branches)."""
     rng = np.random.default_rng(8)
     mesh = square_mesh() if shape.startswith("one-leaf") else staircase_mesh()
@@ -142,7 +142,7 @@ def test_intersect_all_tree_shapes(W, shape):
     if shape.startswith("one-leaf"):
         assert info["n_leaves"] == 1
     else:
-        assert info["depth"] > 40
+        assert info["depth"] > 32
     n = 4000
     orig = rng.uniform(-1.5, 1.5, (n, 3))
     if not shape.startswith("one-leaf"):
