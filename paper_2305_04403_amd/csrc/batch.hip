@@ -91,7 +91,7 @@ void launch_persistent_t(wob_batch_s* b, int bpc, int64_t stride, hipStream_t st
   hipLaunchKernelGGL(zero_counter, dim3(1), dim3(64), 0, st, b->d_counter);
   const dim3 grid((unsigned)(b->n_cu * bpc)), block(BLOCK);
   hipLaunchKernelGGL((wob::batch_kernel<R, D, BLOCK>), grid, block,
-                     (size_t)b->stack_cap * BLOCK * sizeof(int32_t), st,
+                     wob::walk_lds_bytes(b->stack_cap, BLOCK), st,
                      (const wob::WalkArgs<R, D>*)b->d_args, (const int64_t*)b->d_tile_off,
                      (int32_t)b->probs.size(), stride, b->d_counter);
 }

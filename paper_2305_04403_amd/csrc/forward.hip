@@ -197,7 +197,7 @@ wob_status launch_paths(const wob_scene_s* sc, const wob_bc* bc, const float* cd
   constexpr int B = kSolveBlock;
   const dim3 grid((unsigned)((a.n_points + B - 1) / B)), block(B);
   hipLaunchKernelGGL((wob::walk_kernel<R, D, wob::F_FWD, false, false, B>), grid, block,
-                     (size_t)a.scene.stack_cap * B * sizeof(int32_t), st, a);
+                     wob::walk_lds_bytes(a.scene.stack_cap, B), st, a);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 

@@ -6,9 +6,14 @@
 
 namespace wob {
 
-// Dynamic LDS of the path kernels: the lanes' traversal stacks, stack_cap
-// entries of 4 bytes per thread of the block (sized at launch).
+// Dynamic LDS of the path kernels: the lanes' traversal stacks and held
+// leaves, stack_cap + kLeafSlots entries of 4 bytes per thread of the block
+// (sized at launch).
 extern __shared__ int32_t wob_stack[];
+constexpr int kLeafSlots = 3;
+inline size_t walk_lds_bytes(int stack_cap, int block) {
+  return (size_t)(stack_cap + kLeafSlots) * (size_t)block * sizeof(int32_t);
+}
 
 template <typename R, int D>
 struct WalkArgs {
@@ -439,8 +444,8 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
   return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
-// The primitives of the crossed leaves a lane holds (one to three, codes -1 =
-// none after the first) on the current line.  The primitive loop
+// The primitives of the crossed leaves a lane holds (one to three) on the
+// current line.  The primitive loop
 // only tests and records the accepted primitives in a bit mask; the hits are
 // then handled in a loop of their own, so that the lanes with a hit in this
 // leaf phase do that work together instead of one or two at a time inside the
@@ -452,11 +457,12 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
 template <typename R, int D, int FORM, bool COUNT, int EXT>
 __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, D>& s, int32_t code,
                                           int32_t code2, int32_t code3, WorkCount& wc) {
+  static_assert(kLeafSlots == 3, "leaf_work takes three leaf codes");
   constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
   const SceneView<R, D>& sc = a.scene;
   {
-    // one to three leaves: primitive b is first + b (b < count), then the
-    // second leaf's, then the third's
+    // one to three leaves (codes -1 = none after the first): primitive b of
+    // the row is first + b (b < count), then the second leaf's, then the third's
     const int32_t first = code >> 3, count = (code & 7) + 1;
     const int32_t c2 = code2 >= 0 ? (code2 & 7) + 1 : 0;
     const int32_t first2 = (code2 >> 3) - count, first3 = (code3 >> 3) - count - c2;
@@ -741,13 +747,14 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     PathState<R, D> s;
     int k = lane_in_point;
     int st = ST_NONE;
-    int32_t pend = -1;   // crossed leaf waiting to be tested
-    int32_t pend2 = -1;  // a second and a third one: a lane holding fewer than
-    int32_t pend3 = -1;  // three leaves keeps stepping
     // the lane's traversal stack: LDS, entry k at wob_stack[k * BLOCK + tid]
-    // (consecutive lanes in consecutive banks); empty between lines
+    // (consecutive lanes in consecutive banks); empty between lines.  After
+    // its stack_cap entries come kLeafSlots more: the crossed leaves the lane
+    // holds (nq of them) until the leaf test; a lane holding fewer than
+    // kLeafSlots keeps stepping
     int32_t* const stk = wob_stack + tid;
-    int sp = 0;
+    int32_t* const leafq = stk + a.scene.stack_cap * BLOCK;
+    int sp = 0, nq = 0;
     if (point < a.n_points) {
       if constexpr (FORM == F_FWD) {
         s.point = 0xfffffffeu;  // forward paths: no evaluation point
@@ -798,7 +805,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       const int idle = __popcll(__ballot(st == ST_NONE));
       if (idle == 64) break;
       // lanes parked at the end of their line, and lanes that step through nodes
-      const int ends = __popcll(__ballot(st == ST_LINE && pend < 0 && s.ni == kDone));
+      const int ends = __popcll(__ballot(st == ST_LINE && nq == 0 && s.ni == kDone));
       const int active = 64 - idle - ends;
       // node steps until half of the stepping lanes hold three crossed leaves
       // or stand at the end of their line; a lane keeps stepping while it
@@ -806,7 +813,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       // first / second / third leaf 622 / 694 / 711 M path samples/s; with
       // two, a wait for 3/8, 1/2, 5/8 of the lanes: 678, 688, 677)
       const int want = (active * 4 + 7) >> 3;
-      bool trav = st == ST_LINE && pend < 0 && s.ni != kDone;
+      bool trav = st == ST_LINE && nq == 0 && s.ni != kDone;
       while (trav) {
         if (active - __popcll(__ballot(1)) >= want) break;
         // one step: take the position (or pop it), fetch an interior record by
@@ -825,18 +832,15 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
           e = h0 ? node.child[0] : (h1 ? node.child[1] : kPop);
         }
         const bool at_leaf = e < 0 && e != kPop;
-        const bool second = at_leaf && pend >= 0 && pend2 < 0;
-        const bool third = at_leaf && pend2 >= 0;
-        pend3 = third ? -1 - e : pend3;
-        pend2 = second ? -1 - e : pend2;
-        pend = (at_leaf && pend < 0) ? -1 - e : pend;
+        if (at_leaf) leafq[nq++ * BLOCK] = -1 - e;
         s.ni = at_leaf ? kPop : e;
-        trav = !third && e != kDone;
+        trav = nq < kLeafSlots && e != kDone;
       }
       // the lanes holding leaves test them together
-      if (pend >= 0) {
-        leaf_work<R, D, FORM, COUNT, KEXT>(a, s, pend, pend2, pend3, wc);
-        pend = pend2 = pend3 = -1;
+      if (nq > 0) {
+        const int32_t c1 = leafq[0], c2 = nq > 1 ? leafq[BLOCK] : -1, c3 = nq > 2 ? leafq[2 * BLOCK] : -1;
+        leaf_work<R, D, FORM, COUNT, KEXT>(a, s, c1, c2, c3, wc);
+        nq = 0;
       }
       // path steps run once a quarter of the working lanes stand at the end of
       // their line, or when no lane steps (measured: 557, 574, 566 M path

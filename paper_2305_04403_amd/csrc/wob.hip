@@ -202,7 +202,7 @@ void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
   constexpr int B = kSolveBlock;
   const int ppb = B >> a.lpp_shift;
   const dim3 grid((unsigned)((a.n_points + ppb - 1) / ppb)), block(B);
-  const size_t lds = (size_t)a.scene.stack_cap * B * sizeof(int32_t);  // traversal stacks
+  const size_t lds = wob::walk_lds_bytes(a.scene.stack_cap, B);  // traversal stacks, held leaves
   if constexpr (FORM != wob::F_FWD) {
     if (a.grad_out || a.path_grad_out) {  // value and gradient along the same paths
       if (mode == MODE_TRACE)
