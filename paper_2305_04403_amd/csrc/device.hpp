@@ -44,11 +44,12 @@ template <> struct alignas(32) Inner2<float> { uint32_t box0[2], box1[2]; int32_
 // and the line's traversal is over.
 constexpr int32_t kPop = INT32_MIN;
 constexpr int32_t kDone = INT32_MAX;
-// Bound on the BVH depth the builder produces (32 SAH levels, then at most
-// 26 halvings of fewer than 2^27 primitives): the traversal stack holds at
-// most one entry per level below the root, so a lane's LDS stack stays under
-// 64 entries (a 256-thread workgroup: under 64 KB).
-constexpr int kMaxDepth = 64;
+// Bound on the traversal stack (the builder's trees have at most 32 SAH
+// levels, then at most 26 halvings of fewer than 2^27 primitives, and the
+// stack holds at most one entry per level below the root): with the leaf
+// queue a lane's LDS stays within 64 entries, a 256-thread workgroup's within
+// 64 KB.
+constexpr int kMaxDepth = 60;
 // An FP32 triangle record is padded to 64 bytes so that it never straddles a
 // 64-byte block: the traversal is bound by the rate of L1-miss requests, and a
 // straddling record costs two.

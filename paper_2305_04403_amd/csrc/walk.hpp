@@ -10,7 +10,7 @@ namespace wob {
 // leaves, stack_cap + kLeafSlots entries of 4 bytes per thread of the block
 // (sized at launch).
 extern __shared__ int32_t wob_stack[];
-constexpr int kLeafSlots = 3;
+constexpr int kLeafSlots = 4;
 inline size_t walk_lds_bytes(int stack_cap, int block) {
   return (size_t)(stack_cap + kLeafSlots) * (size_t)block * sizeof(int32_t);
 }
@@ -444,7 +444,7 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
   return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
-// The primitives of the crossed leaves a lane holds (one to three) on the
+// The primitives of the crossed leaves a lane holds (one to four) on the
 // current line.  The primitive loop
 // only tests and records the accepted primitives in a bit mask; the hits are
 // then handled in a loop of their own, so that the lanes with a hit in this
@@ -456,22 +456,23 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
 // add a(h) F(y_h).
 template <typename R, int D, int FORM, bool COUNT, int EXT>
 __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, D>& s, int32_t code,
-                                          int32_t code2, int32_t code3, WorkCount& wc) {
-  static_assert(kLeafSlots == 3, "leaf_work takes three leaf codes");
+                                          int32_t code2, int32_t code3, int32_t code4, WorkCount& wc) {
+  static_assert(kLeafSlots == 4, "leaf_work takes four leaf codes");
   constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
   const SceneView<R, D>& sc = a.scene;
   {
-    // one to three leaves (codes -1 = none after the first): primitive b of
-    // the row is first + b (b < count), then the second leaf's, then the third's
+    // one to four leaves (codes -1 = none after the first): primitive b of the
+    // row is first + b (b < count), then the second leaf's, and so on
     const int32_t first = code >> 3, count = (code & 7) + 1;
-    const int32_t c2 = code2 >= 0 ? (code2 & 7) + 1 : 0;
+    const int32_t c2 = code2 >= 0 ? (code2 & 7) + 1 : 0, c3 = code3 >= 0 ? (code3 & 7) + 1 : 0;
     const int32_t first2 = (code2 >> 3) - count, first3 = (code3 >> 3) - count - c2;
-    const int32_t total = count + c2 + (code3 >= 0 ? (code3 & 7) + 1 : 0);
+    const int32_t first4 = (code4 >> 3) - count - c2 - c3;
+    const int32_t total = count + c2 + c3 + (code4 >= 0 ? (code4 & 7) + 1 : 0);
     constexpr bool GEO = FORM == F_DIRECT || CV;  // per-hit work needs the hit's geometry
     uint32_t accepted = 0;  // bit b: primitive b of the leaves is hit
     int32_t id0 = 0;        // caller id of the first hit (no reload for it)
     for (int32_t b = 0; b < total; ++b) {
-      const int32_t j = (b < count ? first : (b < count + c2 ? first2 : first3)) + b;
+      const int32_t j = (b < count ? first : (b < count + c2 ? first2 : (b < count + c2 + c3 ? first3 : first4))) + b;
       if (j == s.cur_idx) continue;
       if (COUNT) wc.prims += 1;
       const PrimGeo<R> g = load_prim<R, D>(sc, j);
@@ -484,7 +485,7 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
     bool later = false;
     while (accepted) {
       const int32_t b = __builtin_ctz(accepted);
-      const int32_t j = (b < count ? first : (b < count + c2 ? first2 : first3)) + b;
+      const int32_t j = (b < count ? first : (b < count + c2 ? first2 : (b < count + c2 + c3 ? first3 : first4))) + b;
       accepted &= accepted - 1;
       PrimGeo<R> g;
       if (GEO || later) g = load_prim<R, D>(sc, j);
@@ -737,7 +738,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   constexpr int KEXT = EXT == X_CV ? ((D == 3 && FORM == F_SL) ? X_CV : X_NONE) : EXT;
   {
     // Paths k = lane_in_point, + lpp, ... of this lane, run as one state
-    // machine.  Lanes step through BVH nodes; a lane that has reached three
+    // machine.  Lanes step through BVH nodes; a lane that has reached four
     // crossed leaves parks until half of the stepping lanes have parked, and
     // the lanes holding leaves then test them together; a lane at the end of its line
     // parks until a quarter of the working lanes have, and those lanes then
@@ -807,18 +808,20 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       // lanes parked at the end of their line, and lanes that step through nodes
       const int ends = __popcll(__ballot(st == ST_LINE && nq == 0 && s.ni == kDone));
       const int active = 64 - idle - ends;
-      // node steps until half of the stepping lanes hold three crossed leaves
+      // node steps until half of the stepping lanes hold four crossed leaves
       // or stand at the end of their line; a lane keeps stepping while it
       // holds fewer (measured on the icosphere benchmark: parking at the
-      // first / second / third leaf 622 / 694 / 711 M path samples/s; with
-      // two, a wait for 3/8, 1/2, 5/8 of the lanes: 678, 688, 677)
+      // first / second / third / fourth leaf 622 / 694 / 725 / 733 M path
+      // samples/s; with two, a wait for 3/8, 1/2, 5/8 of the lanes: 678, 688,
+      // 677)
       const int want = (active * 4 + 7) >> 3;
       bool trav = st == ST_LINE && nq == 0 && s.ni != kDone;
       while (trav) {
         if (active - __popcll(__ballot(1)) >= want) break;
         // one step: take the position (or pop it), fetch an interior record by
         // a 32-bit byte offset from the uniform base, test both child boxes;
-        // both crossed -> push the second; a leaf entry parks the lane
+        // both crossed -> push the second; a leaf entry goes to the lane's
+        // leaf queue, and the fourth one parks the lane
         int32_t e = s.ni;
         if (e == kPop) e = sp > 0 ? stk[--sp * BLOCK] : kDone;
         if (e >= 0 && e != kDone) {
@@ -839,7 +842,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       // the lanes holding leaves test them together
       if (nq > 0) {
         const int32_t c1 = leafq[0], c2 = nq > 1 ? leafq[BLOCK] : -1, c3 = nq > 2 ? leafq[2 * BLOCK] : -1;
-        leaf_work<R, D, FORM, COUNT, KEXT>(a, s, c1, c2, c3, wc);
+        const int32_t c4 = nq > 3 ? leafq[3 * BLOCK] : -1;
+        leaf_work<R, D, FORM, COUNT, KEXT>(a, s, c1, c2, c3, c4, wc);
         nq = 0;
       }
       // path steps run once a quarter of the working lanes stand at the end of
