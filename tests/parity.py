@@ -8,8 +8,8 @@ import numpy as np
 import oracle
 from paper_2305_04403_amd import inputs as I
 
-# Grazing class (the north-star tolerance "exactly, except at grazing hits within
-# 1e-6"): a path is grazing when some line of it passes within 1e-6 of a
+# Grazing class (the parity bar: paths agree exactly except where a hit grazes
+# a primitive within 1e-6): a path is grazing when some line of it passes within 1e-6 of a
 # primitive's edge, measured as |smallest barycentric coordinate| * |cos| where
 # cos is the angle between the line and the primitive's normal (the factor
 # 1/|cos| is how FP32 barycentric error grows towards grazing incidence).
