@@ -68,6 +68,38 @@ def test_batch_equals_single_solves_and_replays(W):
         b.close()
 
 
+def test_batch_trees_of_different_depth(W):
+    """Problems whose trees differ in depth share one persistent launch (the
+    workgroup's LDS stacks are sized for the deepest): a one-leaf tree, the
+    37-level staircase and a sphere, each equal to its single solve."""
+    from tests.test_gpu_parity import square_mesh, staircase_mesh
+    meshes = [square_mesh(), staircase_mesh(), I.perturb_radial(I.icosphere(8), 0.1, 3, 4)]
+    rng = np.random.default_rng(12)
+    probs = []
+    for k, mesh in enumerate(meshes):
+        mesh = PT.f32_mesh(mesh)
+        pts = PT.f32(rng.uniform(-0.7, 0.7, (90 + 37 * k, 3)))
+        pts[:, 2] = np.where(np.abs(pts[:, 2]) < 0.05, 0.05, pts[:, 2])
+        probs.append(dict(scene=W.Scene(mesh, W.F32), points=dev(pts, torch.float32),
+                          bc=W.BC(1, 1, W.PROG_INVDIST, (2.0, 0.5, 0.0)), samples=96, walk_len=4, seed=31 + k))
+    assert probs[1]["scene"].info()["depth"] > 32 and probs[0]["scene"].info()["n_leaves"] == 1
+    ref = [W.solve(p["scene"], p["points"], p["bc"], p["samples"], p["walk_len"], p["seed"]) for p in probs]
+    torch.cuda.synchronize()
+    b = W.Batch(probs, tune=(128, 2))
+    for rep in range(2):
+        outs = b.launch()
+        torch.cuda.synchronize()
+        for (m, v), (mr, vr) in zip(outs, ref):
+            # bitwise equal (a point whose paths all miss the open meshes has no
+            # finite path and a NaN mean on both sides)
+            for x, xr in ((m, mr), (v, vr)):
+                assert torch.equal(x.isnan(), xr.isnan()), rep
+                assert torch.equal(x[~x.isnan()], xr[~xr.isnan()]), rep
+    b.close()
+    for p in probs:
+        p["scene"].close()
+
+
 def test_batch_single_layer_forms_equal_single_solves(W):
     """A batch holding every kernel form (double layer, direct BIE, single
     layer with line sampling and with RIS, on a mixed Dirichlet / Neumann /
