@@ -377,7 +377,9 @@ typedef struct wob_batch_s* wob_batch;
 /* Validate the problems, upload the problem table and capture the solve as a
  * hipGraph {reset the tile counter, persistent kernel}.  The arrays of every
  * problem must stay valid while the batch is used.  tune NULL = 256 lanes,
- * 4 workgroups per CU.  Tiles (one workgroup's points of one problem) are
+ * 4 workgroups per CU (128 lanes when the traversal stacks of the deepest
+ * scene would not fit a 256-lane workgroup's LDS; a given tune that does not
+ * fit is WOB_E_ARG).  Tiles (one workgroup's points of one problem) are
  * ordered by decreasing estimated cost and pulled from an atomic counter.
  * Errors: WOB_E_ARG, WOB_E_UNSUPPORTED, WOB_E_ALLOC, WOB_E_DEVICE. */
 wob_status wob_batch_create(const wob_problem* problems, int32_t n_problems,

@@ -25,6 +25,7 @@ struct wob_batch_s {
   unsigned long long* d_counter = nullptr;
   int64_t n_tiles = 0;
   int32_t stack_cap = 1;  // largest traversal stack of the problems' scenes
+  int32_t max_lds = 0;    // LDS bytes a workgroup may use on the device
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -37,6 +38,12 @@ namespace {
 // a memset node).
 __global__ void zero_counter(unsigned long long* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
+}
+
+// Whether a workgroup of `block` threads fits the device's LDS with the
+// traversal stacks of the deepest scene (and the kernel's small static LDS).
+bool fits_lds(const wob_batch_s* b, int block) {
+  return wob::walk_lds_bytes(b->stack_cap, block) + 1024 <= (size_t)b->max_lds;
 }
 
 bool valid_tune(const wob_tune& t) {
@@ -197,7 +204,8 @@ wob_status wob_batch_create(const wob_problem* problems, int32_t n, const wob_tu
                    [&](int x, int y) { return cost[x] > cost[y]; });
   if (tune) b->tune = *tune;
   if (hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      b->n_cu <= 0) {
+      b->n_cu <= 0 ||
+      hipDeviceGetAttribute(&b->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
     destroy(b);
     return WOB_E_DEVICE;
   }
@@ -210,6 +218,16 @@ wob_status wob_batch_create(const wob_problem* problems, int32_t n, const wob_tu
     return WOB_E_DEVICE;
   }
   wob_status st = upload(b, b->tune.block);
+  if (st == WOB_OK && !fits_lds(b, b->tune.block)) {
+    // very deep trees: a caller's shape that does not fit is an error; the
+    // default falls back to the smallest workgroup
+    if (tune) st = WOB_E_ARG;
+    else {
+      b->tune = wob_tune{128, 8};
+      st = upload(b, b->tune.block);
+      if (st == WOB_OK && !fits_lds(b, b->tune.block)) st = WOB_E_ARG;
+    }
+  }
   if (st == WOB_OK) st = capture(b);
   if (st != WOB_OK) {
     destroy(b);
@@ -243,7 +261,7 @@ wob_status wob_batch_autotune(wob_batch b, int32_t sample_stride, const char* ca
     std::string key;
     wob_tune t;
     while (in >> key >> t.block >> t.blocks_per_cu) {
-      if (key == b->signature && valid_tune(t)) {
+      if (key == b->signature && valid_tune(t) && fits_lds(b, t.block)) {
         best = t;
         have = true;
       }
@@ -259,6 +277,7 @@ wob_status wob_batch_autotune(wob_batch b, int32_t sample_stride, const char* ca
       // the table is rewritten synchronously: wait for the kernels that read it
       if (hipStreamSynchronize(st) != hipSuccess) return WOB_E_DEVICE;
       if (upload(b, blocks[bi]) != WOB_OK) return WOB_E_DEVICE;
+      if (!fits_lds(b, blocks[bi])) continue;
       for (int ci = 0; ci < 6; ++ci) {
         const wob_tune t{blocks[bi], bpcs[ci]};
         if (t.blocks_per_cu * t.block / 64 > 24) continue;  // beyond what a CU can hold
