@@ -35,8 +35,8 @@ constexpr int kSolveBlock = 256;  // lanes per workgroup of the single-problem s
 // Paths each lane runs back to back: a lane's work is then the sum of many
 // lines, whose spread across the lanes of a wavefront is smaller than that of
 // single lines (measured on the 20,480-triangle icosphere benchmark with 2, 4,
-// 8, 16, 32 paths per lane: 390, 396, 394, 386, 367 M path samples/s).
-constexpr int kPathsPerLane = 4;
+// 8, 16 paths per lane: 708, 732, 738, 728 M path samples/s).
+constexpr int kPathsPerLane = 8;
 
 // log2 of the lanes that share one point: the smallest power of two >=
 // ceil(N / kPathsPerLane), at most the block (a wavefront holds several points
