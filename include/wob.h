@@ -220,7 +220,7 @@ wob_status wob_count_work(wob_scene scene, const void* points, const int32_t* po
                           uint64_t seed, uint64_t* counters, void* stream);
 
 /* Gradient of the solution at points inside the domain, estimated along the
- * same paths as the value (Sec. 4.4, gradient estimation: the first step's
+ * same paths as the value (Sec. 4.1.3, derivative estimators: the first step's
  * kernel replaced by its gradient in x0, the rest of each path unchanged;
  * the gradient equations of the three formulations).  Per path the gradient
  * is W' times the path's remaining sum, with, for the step from x0 to the
@@ -261,7 +261,7 @@ const char* wob_status_string(wob_status status);
 
 /* ------------------------------------------------------------------------- */
 /* Forward (adjoint) estimator of the single layer, Neumann boundaries        */
-/* (Sec. 4.4 "Forward estimator"; the Neumann rows of Table 1 for the single  */
+/* (Sec. 4.4.3 "Forward estimator"; the Neumann rows of Table 1 for the single  */
 /* layer; boundary starts by the magnitude of the data as in the paper's      */
 /* Neumann example, and the reuse of boundary subpaths by every evaluation    */
 /* point as in its potential-flow example).                                   */

@@ -35,7 +35,7 @@ class _BC(C.Structure):
 
 class _TraceOut(C.Structure):
     _fields_ = [("value", C.c_void_p), ("abs_sum", C.c_void_p), ("graze", C.c_void_p),
-                ("cond_cos", C.c_void_p), ("vtx_prim", C.c_void_p), ("vtx_m", C.c_void_p),
+                ("err", C.c_void_p), ("vtx_prim", C.c_void_p), ("vtx_m", C.c_void_p),
                 ("vtx_pos", C.c_void_p)]
 
 
@@ -76,10 +76,10 @@ def lib():
         _lib.orc_cv_addback.argtypes = [vp, vp, vp, C.c_int64, C.c_uint32, C.c_int, vp, C.c_int]
         _lib.orc_cv_addback.restype = C.c_int
         _lib.orc_trace_cv.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, vp,
-                                      vp, C.c_int64, vp, vp, vp, C.c_int]
+                                      vp, C.c_int64, vp, vp, vp, vp, vp, C.c_int]
         _lib.orc_trace_cv.restype = C.c_int
         _lib.orc_trace_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, C.c_int64,
-                                        vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
+                                        vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
         _lib.orc_trace_grad.restype = C.c_int
         _lib.orc_solve_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
                                         vp, vp, vp, vp, C.c_int]
@@ -185,12 +185,12 @@ def trace(mesh: OracleMesh, points: np.ndarray, point_prim: Optional[np.ndarray]
     ik = np.ascontiguousarray(item_path, dtype=np.int64)
     n = ip.shape[0]
     L = lines_per_path(mesh, bc, walk_len)
-    out = {"value": np.zeros(n), "abs_sum": np.zeros(n), "graze": np.zeros(n), "cond_cos": np.zeros(n),
+    out = {"value": np.zeros(n), "abs_sum": np.zeros(n), "graze": np.zeros(n), "err": np.zeros(n),
            "vtx_prim": np.zeros((n, L), dtype=np.int32), "vtx_m": np.zeros((n, L), dtype=np.int32)}
     if want_pos:
         out["vtx_pos"] = np.zeros((n, L, mesh.dim))
     t = _TraceOut(_ptr(out["value"]), _ptr(out["abs_sum"]), _ptr(out["graze"]),
-                  _ptr(out["cond_cos"]), _ptr(out["vtx_prim"]), _ptr(out["vtx_m"]),
+                  _ptr(out["err"]), _ptr(out["vtx_prim"]), _ptr(out["vtx_m"]),
                   _ptr(out.get("vtx_pos")))
     rc = lib().orc_trace(mesh.ref, _ptr(pts), _ptr(pp), C.c_int64(pts.shape[0]), C.byref(bc),
                          C.c_int(walk_len), C.c_uint64(seed), C.c_uint32(problem), C.c_int64(n),
@@ -218,18 +218,19 @@ def solve(mesh: OracleMesh, points: np.ndarray, point_prim: Optional[np.ndarray]
 def trace_grad(mesh: OracleMesh, points: np.ndarray, bc: _BC, walk_len: int, seed: int,
                item_point: np.ndarray, item_path: np.ndarray, problem: int = 0, n_threads: int = 0) -> dict:
     """Per-path value and gradient in x0 (points off the boundary), with the
-    rounding scales, grazing margin and conditioning of each path."""
+    magnitude sums, grazing margin and rounding-error bounds (units of u) of
+    each path."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     ip = np.ascontiguousarray(item_point, dtype=np.int64)
     ik = np.ascontiguousarray(item_path, dtype=np.int64)
     n = ip.shape[0]
     out = {"value": np.zeros(n), "grad": np.zeros((n, mesh.dim)), "abs_sum": np.zeros(n),
-           "grad_abs": np.zeros(n), "graze": np.zeros(n), "cond_cos": np.zeros(n)}
+           "grad_abs": np.zeros(n), "graze": np.zeros(n), "err": np.zeros(n), "grad_err": np.zeros(n)}
     rc = lib().orc_trace_grad(mesh.ref, _ptr(pts), C.c_int64(pts.shape[0]), C.byref(bc), C.c_int(walk_len),
                               C.c_uint64(seed), C.c_uint32(problem), C.c_int64(n), _ptr(ip), _ptr(ik),
                               _ptr(out["value"]), _ptr(out["grad"]), _ptr(out["abs_sum"]),
-                              _ptr(out["grad_abs"]), _ptr(out["graze"]), _ptr(out["cond_cos"]),
-                              C.c_int(n_threads))
+                              _ptr(out["grad_abs"]), _ptr(out["graze"]), _ptr(out["err"]),
+                              _ptr(out["grad_err"]), C.c_int(n_threads))
     if rc != 0:
         raise ValueError("orc_trace_grad rejected its arguments")
     return out
@@ -252,7 +253,8 @@ def solve_grad(mesh: OracleMesh, points: np.ndarray, bc: _BC, samples: int, walk
 
 class _ForwardOut(C.Structure):
     _fields_ = [("vtx_pos", C.c_void_p), ("vtx_w", C.c_void_p), ("vtx_prim", C.c_void_p),
-                ("vtx_m", C.c_void_p), ("graze", C.c_void_p), ("cond_cos", C.c_void_p)]
+                ("vtx_m", C.c_void_p), ("graze", C.c_void_p), ("perr", C.c_void_p),
+                ("werr", C.c_void_p)]
 
 
 def forward_paths(mesh: OracleMesh, bc: _BC, n_paths: int, walk_len: int, seed: int,
@@ -260,14 +262,15 @@ def forward_paths(mesh: OracleMesh, bc: _BC, n_paths: int, walk_len: int, seed: 
                   n_threads: int = 0) -> dict:
     """Forward (adjoint) single-layer paths from the boundary (all-Neumann
     meshes): per path and vertex the position, primitive, hit count and source
-    strength; per path the grazing margin and smallest |cos| of a sampled hit."""
+    strength with the rounding-error bounds (units of u) of both; per path the
+    grazing margin."""
     M = int(walk_len)
     sw = None if start_weight is None else np.ascontiguousarray(start_weight, dtype=np.float64)
     out = {"pos": np.zeros((n_paths, M, mesh.dim)), "w": np.zeros((n_paths, M)),
            "prim": np.zeros((n_paths, M), dtype=np.int32), "m": np.zeros((n_paths, M), dtype=np.int32),
-           "graze": np.zeros(n_paths), "cond_cos": np.zeros(n_paths)}
+           "graze": np.zeros(n_paths), "perr": np.zeros((n_paths, M)), "werr": np.zeros((n_paths, M))}
     t = _ForwardOut(_ptr(out["pos"]), _ptr(out["w"]), _ptr(out["prim"]), _ptr(out["m"]),
-                    _ptr(out["graze"]), _ptr(out["cond_cos"]))
+                    _ptr(out["graze"]), _ptr(out["perr"]), _ptr(out["werr"]))
     rc = lib().orc_forward_paths(mesh.ref, C.byref(bc), _ptr(sw), C.c_int64(n_paths), C.c_int(M),
                                  C.c_uint64(seed), C.c_uint32(problem), C.byref(t), C.c_int(n_threads))
     if rc != 0:
@@ -352,8 +355,11 @@ def cv_addback(mesh: OracleMesh, g: np.ndarray, points: np.ndarray, seed: int = 
 
 
 def trace_cv(mesh: OracleMesh, points, point_prim, bc: _BC, walk_len: int, seed: int, g,
-             item_point, item_path, problem: int = 0, n_threads: int = 0, g0=None) -> np.ndarray:
-    """Corrected per-path values; g0 (line-0 table) defaults to g."""
+             item_point, item_path, problem: int = 0, n_threads: int = 0, g0=None,
+             with_scales: bool = False):
+    """Corrected per-path values; g0 (line-0 table) defaults to g.  With
+    with_scales, a dict of the values, their magnitude sums and rounding-error
+    bounds (units of u)."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     pp = None if point_prim is None else np.ascontiguousarray(point_prim, dtype=np.int32)
     gg = np.ascontiguousarray(g, dtype=np.float64)
@@ -361,11 +367,14 @@ def trace_cv(mesh: OracleMesh, points, point_prim, bc: _BC, walk_len: int, seed:
     ip = np.ascontiguousarray(item_point, dtype=np.int64)
     ik = np.ascontiguousarray(item_path, dtype=np.int64)
     out = np.zeros(ip.shape[0])
+    sabs, err = np.zeros(ip.shape[0]), np.zeros(ip.shape[0])
     rc = lib().orc_trace_cv(mesh.ref, _ptr(pts), _ptr(pp), pts.shape[0], C.byref(bc), int(walk_len),
                             C.c_uint64(seed), C.c_uint32(problem), _ptr(gg), _ptr(g00), ip.shape[0], _ptr(ip),
-                            _ptr(ik), _ptr(out), int(n_threads))
+                            _ptr(ik), _ptr(out), _ptr(sabs), _ptr(err), int(n_threads))
     if rc != 0:
         raise ValueError("orc_trace_cv rejected its arguments")
+    if with_scales:
+        return {"value": out, "abs_sum": sabs, "err": err}
     return out
 
 

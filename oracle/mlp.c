@@ -121,6 +121,10 @@ double orc_mlp_loss_grad(const double* params, const double* Bmat, int n_freq, i
   }
   double loss = 0.0;
   for (int64_t r = 0; r < n; ++r) {
+    /* a non-finite target (a boundary point whose every path was non-finite)
+       has no weight: it adds nothing to the loss or the gradient, whose
+       normalisation stays 1 / n */
+    if (!isfinite(target[r])) continue;
     const double f = forward_one(params, Bmat, sh, y + r * dim, bf16, a, s);
     const double e = f - target[r];
     loss += e * e;

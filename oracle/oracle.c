@@ -127,16 +127,6 @@ static double G(const double* x, const double* y, int dim) {
   double rn = sqrt(dot(r, r, dim));
   return dim == 3 ? 1.0 / (4.0 * ORC_PI * rn) : -log(rn) / (2.0 * ORC_PI);
 }
-/* Conditioning of a kernel evaluated at distance rho = |y - x| formed from
-   coordinates of size |x|: rho, and G through it, carry a relative error of
-   order (unit roundoff) |x| / rho.  Folded into the path's cond_cos (the
-   parity tolerance grows like 1 / cond_cos). */
-static double rho_cond(const double* x, const double* y, int dim) {
-  double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
-  const double rho = sqrt(dot(r, r, dim));
-  return rho / fmax(1.0, sqrt(dot(x, x, dim)));
-}
-
 /* Error scale of a G factor for the parity tolerance (the magnitude sum of a
    path): |G| in 3D; in 2D max(|ln rho|, 1) / (2 pi), because ln rho carries an
    absolute rounding error of order one unit of the arithmetic, which does not
@@ -161,8 +151,8 @@ static double dG_dnx(const double* x, const double* y, const double* nx, int dim
 }
 
 /* Gradients in x (the evaluation point) of G and of dG/dn_y, for the gradient
- * estimators (Sec. 4.4: the gradient equations of the three formulations).
- * With r = y - x, rho = |r| and S_D = 4 pi (3D), 2 pi (2D):
+ * estimators (Sec. 4.1.3, derivative estimators; the gradient equations of
+ * the three formulations of Table 1 and Sec. 4.3).  With r = y - x, rho = |r| and S_D = 4 pi (3D), 2 pi (2D):
  *   grad_x G        = r / (S_D rho^D)
  *   grad_x dG/dn_y  = (n_y / rho^D - D (r . n_y) r / rho^(D+2)) / S_D        */
 static void grad_G(const double* x, const double* y, int dim, double* g) {
@@ -325,6 +315,32 @@ static int line_prim_b(const orc_mesh* m, int64_t j, const double* x, const doub
   }
 }
 
+/* Grazing measure of a line / primitive decision: the smallest barycentric
+   margin expressed in units of the rounding scale of the decision a binary
+   intersection test takes.  Such a test decides on the numerators of the
+   barycentric coordinates, (x - v0) . (d x e2) and d . ((x - v0) x e1) in 3D
+   (-(x - v0) x d in 2D), whose rounding is of order |x - v0| |e| units, against
+   the margin times |det| = 2 A cos (|e| cos in 2D); the sum test adds |e1| |e2|.
+   So g = |margin| |det| / (|x - v0| (|e1| + |e2|) + |e1| |e2|) (2D:
+   |margin| |e| cos / (|x - v0| + |e|)).  Near the line's start on a
+   well-shaped triangle g is about |margin| cos / 3; it is far smaller on
+   slivers and on primitives far from x, whose decisions are ill-conditioned. */
+static double decision_margin(const orc_mesh* m, int64_t j, const double* x, double margin, double cosv) {
+  double v0[3] = {0.0, 0.0, 0.0}, v1[3] = {0.0, 0.0, 0.0}, v2[3] = {0.0, 0.0, 0.0};
+  prim_vertex(m, j, 0, v0);
+  prim_vertex(m, j, 1, v1);
+  const int dim = m->dim;
+  double s[3] = {x[0] - v0[0], x[1] - v0[1], dim == 3 ? x[2] - v0[2] : 0.0};
+  double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], dim == 3 ? v1[2] - v0[2] : 0.0};
+  const double l1 = sqrt(dot(e1, e1, dim)), ls = sqrt(dot(s, s, dim));
+  if (dim == 2) return fabs(margin) * l1 * cosv / (ls + l1);
+  prim_vertex(m, j, 2, v2);
+  double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]}, n[3];
+  cross3(e1, e2, n);
+  const double l2 = sqrt(dot(e2, e2, 3)), a2 = sqrt(dot(n, n, 3));
+  return fabs(margin) * a2 * cosv / (ls * (l1 + l2) + l1 * l2);
+}
+
 /* ------------------------------------------------------------------------- */
 /* In-plane sample on the primitive that contains x ("self panel").  A line   */
 /* through x never meets the primitive it starts on (its plane contains the  */
@@ -336,8 +352,12 @@ static int line_prim_b(const orc_mesh* m, int64_t j, const double* x, const doub
 /*  2D: y uniform along the segment; density 1 / length.                       */
 /* Returns G(x, y) / p(y).                                                     */
 /* ------------------------------------------------------------------------- */
-double orc_self_panel(const orc_mesh* m, int64_t prim, const double* x, double u0, double u1,
-                      double* y) {
+/* The sample itself; R_out and sinb_out (3D, may be NULL) receive the
+   distance R(theta) to the triangle's boundary and the sine of the angle at
+   which the in-plane ray leaves through its edge (the rounding-error bound
+   below needs both). */
+static double self_panel_geo(const orc_mesh* m, int64_t prim, const double* x, double u0, double u1,
+                             double* y, double* R_out, double* sinb_out) {
   double v[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   for (int c = 0; c < m->dim; ++c) prim_vertex(m, prim, c, v[c]);
   if (m->dim == 3) {
@@ -355,7 +375,7 @@ double orc_self_panel(const orc_mesh* m, int64_t prim, const double* x, double u
     }
     double theta = 2.0 * ORC_PI * u0;
     double dir[2] = {cos(theta), sin(theta)};
-    double R = INFINITY;
+    double R = INFINITY, sinb = 1.0;
     for (int c = 0; c < 3; ++c) {
       const double* a = loc[c];
       const double* b = loc[(c + 1) % 3];
@@ -363,10 +383,15 @@ double orc_self_panel(const orc_mesh* m, int64_t prim, const double* x, double u
       double den = cross2(dir, e);
       if (den != 0.0) {
         double s = cross2(a, e) / den;
-        if (s > 0.0 && s < R) R = s;
+        if (s > 0.0 && s < R) {
+          R = s;
+          sinb = fabs(den) / sqrt(e[0] * e[0] + e[1] * e[1]);
+        }
       }
     }
     if (!(R < INFINITY)) R = 0.0;
+    if (R_out) *R_out = R;
+    if (sinb_out) *sinb_out = sinb;
     double rho = u1 * R;
     for (int a = 0; a < 3; ++a) y[a] = x[a] + rho * (dir[0] * t1[a] + dir[1] * t2[a]);
     if (rho <= 0.0) return 0.0;
@@ -379,8 +404,15 @@ double orc_self_panel(const orc_mesh* m, int64_t prim, const double* x, double u
     y[1] = v[0][1] + u0 * e[1];
     y[2] = 0.0;
     double pdf = 1.0 / len;
+    if (R_out) *R_out = len;
+    if (sinb_out) *sinb_out = 1.0;
     return G(x, y, 2) / pdf;
   }
+}
+
+double orc_self_panel(const orc_mesh* m, int64_t prim, const double* x, double u0, double u1,
+                      double* y) {
+  return self_panel_geo(m, prim, x, u0, u1, y, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -413,6 +445,81 @@ int orc_lines_per_path(const orc_mesh* m, const orc_bc* bc, int walk_len) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* First-order rounding-error bound of a path.  Used only as the parity       */
+/* tolerance of the tests; it plays no part in any estimate.                  */
+/*                                                                           */
+/* A device evaluation of the same path in a binary format with unit roundoff */
+/* u rounds every vertex, weight and emission.  Their first-order effect on   */
+/* the path value is bounded here in units of u (so one bound serves binary32 */
+/* and binary64), from the geometry of the path alone:                        */
+/*  - vertex position: the hit y of the line x + t d on a primitive met at     */
+/*    incidence c = |cos theta_y| moves in the primitive's plane by the line's */
+/*    own displacement over c.  The line is displaced by the error P(x) of its */
+/*    start and by the rounding of x - v0, of d and of the products of the     */
+/*    intersection test, whose operands have sizes |x|, |y| and rho = |t|:     */
+/*        P(y) = (P(x) + |x| + |y| + rho) / c;                                 */
+/*    the same displacement moves y along the line, so rho carries P(y) too.  */
+/*    A self-panel sample moves with x and with R(theta), which the ray's     */
+/*    exit edge fixes at incidence sin beta: dR = (P(x) + |x| + R) / sin beta; */
+/*    a point drawn on a primitive by its barycentrics (RIS candidates, 2D     */
+/*    self-panel points) carries |y| only.                                     */
+/*  - weight w: relative error eps(w) from the errors of rho, of cos theta_y   */
+/*    (one unit absolute, so 1/c relative) and of cos theta_x; a running       */
+/*    product W carries the sum of the eps of its factors.  Line weights of    */
+/*    the double layer and the direct BIE are +-m (times 1/2): exact.          */
+/*  - emission e = k s(y) moves by |k| |grad s(y)| (P(y) + |y| + |c_p|), the    */
+/*    last two the rounding of the coordinates the data program subtracts      */
+/*    (c_p the program's centre).                                              */
+/* The bound of a path sums over its terms T = W e: |W| (error of e) +        */
+/* (sum of eps in W) |W e|, with the magnitude forms of W and e of abs_sum.    */
+/* A constant of a few units per rounding is left to the test's multiplier.   */
+/* ------------------------------------------------------------------------- */
+static double norm_d(const double* a, int dim) { return sqrt(dot(a, a, dim)); }
+
+/* |grad u| and the spectral norm of the Hessian of the harmonic program at y. */
+static void program_sens(const orc_mesh* m, const orc_bc* bc, const double* y, double* g1,
+                         double* g2) {
+  const double* p = bc->params;
+  const int dim = m->dim;
+  *g1 = 0.0;
+  *g2 = 0.0;
+  if (bc->program == ORC_PROG_LINEAR) {
+    *g1 = sqrt(p[0] * p[0] + p[1] * p[1] + (dim == 3 ? p[2] * p[2] : 0.0));
+  } else if (bc->program == ORC_PROG_QUAD) {
+    *g1 = 2.0 * sqrt(y[0] * y[0] + y[1] * y[1]);
+    *g2 = 2.0;
+  } else if (bc->program == ORC_PROG_INVDIST) {
+    double r[3] = {y[0] - p[0], y[1] - p[1], dim == 3 ? y[2] - p[2] : 0.0};
+    const double rn = norm_d(r, dim);
+    /* 3D u = 1/r: |grad u| = 1/r^2, Hessian eigenvalues 2/r^3, -1/r^3 (twice);
+       2D u = ln r: 1/r and +-1/r^2 */
+    *g1 = dim == 3 ? 1.0 / (rn * rn) : 1.0 / rn;
+    *g2 = dim == 3 ? 2.0 / (rn * rn * rn) : 1.0 / (rn * rn);
+  }
+}
+
+/* |grad s| of the boundary datum of primitive prim at y (s = u, n . grad u, or
+   n . grad u + alpha u), and the size of the coordinates the program
+   subtracts from y's (its centre). */
+static double datum_sens(const orc_mesh* m, const orc_bc* bc, int64_t prim, const double* y) {
+  double g1, g2;
+  program_sens(m, bc, y, &g1, &g2);
+  const int kind = prim_kind(m, prim);
+  if (kind == ORC_DIRICHLET) return g1;
+  if (kind == ORC_NEUMANN) return g2;
+  return g2 + fabs(prim_alpha(m, prim)) * g1;
+}
+static double program_centre(const orc_mesh* m, const orc_bc* bc) {
+  return bc->program == ORC_PROG_INVDIST ? norm_d(bc->params, m->dim) : 0.0;
+}
+
+/* Error of an emission k s(y) (units of u) from the position error P of y. */
+static double emission_err(const orc_mesh* m, const orc_bc* bc, int64_t prim, const double* y, double k,
+                           double P) {
+  return fabs(k) * datum_sens(m, bc, prim, y) * (P + norm_d(y, m->dim) + program_centre(m, bc));
+}
+
+/* ------------------------------------------------------------------------- */
 /* All hits of one line, brute force.                                         */
 /* ------------------------------------------------------------------------- */
 typedef struct {
@@ -423,30 +530,33 @@ typedef struct {
   double sel_b[2];       /* barycentric coordinates of the selected hit */
   double src;            /* sum over hits of G(x,y) q(y) / p_all(y) (direct Neumann) */
   double src_abs;        /* sum over hits of |G(x,y) q(y) / p_all(y)| */
-  double src_cos;        /* smallest |cos theta_y| among the source hits */
-  double graze;          /* min over primitives of |margin| * cos */
+  double graze;          /* min over primitives of the decision margin (decision_margin) */
   double src_grad[3];    /* sum over hits of grad_x G(x,y) q(y) / p_all(y) */
   double src_grad_abs;   /* sum over hits of |grad_x G q / p_all|, all components */
+  double src_err;        /* rounding-error bound of src (units of u) */
+  double src_grad_err;   /* and of src_grad, all components */
 } line_hits;
 
+/* P: position error of x (units of u), for the error bounds of the source sums. */
 static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc, int want_src,
                      int want_sel, const double* x, const double* d, int64_t exclude,
                      uint64_t seed, uint32_t path, uint32_t point, uint32_t problem,
-                     uint32_t line, line_hits* h) {
+                     uint32_t line, double P, line_hits* h) {
   h->m = 0;
   h->sel = -1;
   h->sel_key = 0xffffffffu;
   h->src = 0.0;
   h->src_abs = 0.0;
-  h->src_cos = INFINITY;
   h->graze = INFINITY;
   h->src_grad[0] = h->src_grad[1] = h->src_grad[2] = 0.0;
   h->src_grad_abs = 0.0;
+  h->src_err = 0.0;
+  h->src_grad_err = 0.0;
   for (int64_t j = 0; j < m->n_prims; ++j) {
     if (j == exclude) continue;
     double t, y[3], margin, cosv, b[2];
     int hit = line_prim_b(m, j, x, d, &t, y, &margin, &cosv, b);
-    double g = fabs(margin) * cosv;
+    double g = decision_margin(m, j, x, margin, cosv);
     if (g < h->graze) h->graze = g;
     if (!hit) continue;
     h->m += 1;
@@ -469,7 +579,6 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
       double term = G(x, y, m->dim) * q / line_pdf(x, y, ny, 1, m->dim);
       h->src += term;
       h->src_abs += fabs(term);
-      if (cosv < h->src_cos) h->src_cos = cosv;
       double gg[3];
       grad_G(x, y, m->dim, gg);
       const double pa = line_pdf(x, y, ny, 1, m->dim);
@@ -477,6 +586,16 @@ static void all_hits(const orc_mesh* m, const double* normals, const orc_bc* bc,
         h->src_grad[a] += gg[a] * q / pa;
         h->src_grad_abs += fabs(gg[a] * q / pa);
       }
+      /* error bound of the term: G / p_all is rho / (2c) (2D: -rho ln rho / (2c)),
+         with rho and y moved by (P + |x| + |y| + rho) / c and c rounded by one
+         unit; the gradient term q sgn(t) d / (2c) the same way */
+      const double rho = fabs(t), c = cosv;
+      const double dy = (P + norm_d(x, m->dim) + norm_d(y, m->dim) + rho) / c;
+      const double gp = fabs(G(x, y, m->dim) / pa);
+      const double dgp = m->dim == 3 ? 1.0 / (2.0 * c) : (fabs(log(rho)) + 1.0) / (2.0 * c);
+      const double sq = datum_sens(m, bc, j, y) * (dy + norm_d(y, m->dim) + program_centre(m, bc));
+      h->src_err += fabs(q) * (dgp * dy + gp / c) + gp * sq;
+      h->src_grad_err += (fabs(q) * (1.0 / c + 2.0) + sq) / (2.0 * c);
     }
   }
 }
@@ -552,7 +671,9 @@ static double sl_emission(const orc_mesh* m, const orc_bc* bc, int64_t prim, con
 /* One path (point p, path k).                                                */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-  double value, abs_sum, graze, cond_cos;
+  double value, abs_sum, graze;
+  double err;      /* first-order rounding-error bound of the value (units of u) */
+  double grad_err; /* and of each gradient component (gradient walks) */
 } path_result;
 
 static path_result one_path(const orc_mesh* m, const double* normals, const area_table* at,
@@ -563,7 +684,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
   const int dim = m->dim;
   const double phi = (double)bc->domain;
   const int L = form == ORC_DIRECT ? M + 1 : M;
-  path_result res = {0.0, 0.0, INFINITY, INFINITY};
+  path_result res = {0.0, 0.0, INFINITY, 0.0, 0.0};
   for (int i = 0; i < L; ++i) {
     if (vprim) vprim[i] = -1;
     if (vm) vm[i] = 0;
@@ -577,6 +698,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       (form == ORC_DOUBLE_LAYER || (form == ORC_SINGLE_LAYER && prim_kind(m, prim0) == ORC_DIRICHLET))) {
     res.value = orc_boundary_datum(m, bc, prim0, x0);
     res.abs_sum = fabs(res.value);
+    res.err = emission_err(m, bc, prim0, x0, 1.0, 0.0);
     return res;
   }
 
@@ -585,8 +707,11 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
   /* abs_sum: the same sum with every factor and summand replaced by its
      magnitude (the scale of the rounding error of the sum) */
   double W = 1.0, acc = 0.0, abs_sum = 0.0, Wabs = 1.0;
+  /* rounding-error bound (units of u): position error P of the current vertex,
+     summed relative errors of the weights in W (eW) and in Wg (eWg) */
+  double P = 0.0, eW = 0.0, eWg = 0.0, err = 0.0, gerr = 0.0;
   /* gradient in x0 (x0 off the boundary): the same path with the kernel of
-     the first step differentiated in x0 (the gradient equations of Sec. 4.4;
+     the first step differentiated in x0 (the gradient estimators of Sec. 4.1.3;
      the rest of the path estimates the same boundary unknown).  Wg is the
      derivative of W: a step multiplies it by its weight w, and step 0 adds
      W w' (w' = grad_x kernel / pdf); the step-0 source of the direct BIE adds
@@ -596,6 +721,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
 
   for (int i = 0; i < L; ++i) {
     const int on_gamma = cur >= 0;
+    const double xn = norm_d(x, dim);
     uint32_t r0[4];
     draw(seed, path, point, problem, (uint32_t)i, 0u, 0u, r0);
     double d[3] = {0.0, 0.0, 0.0};
@@ -635,6 +761,9 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       abs_sum += Wabs * fabs(e);
       for (int a = 0; a < 3; ++a) gacc[a] += Wg[a] * e;
       gabs += Wgabs * fabs(e);
+      const double ee = emission_err(m, bc, cur, x, bc->mixed_k * (i + 1 >= M ? 0.5 : 1.0), P);
+      err += Wabs * ee + eW * Wabs * fabs(e);
+      gerr += Wgabs * ee + eWg * Wgabs * fabs(e);
       continue;
     }
     const double gscale = dvert ? -bc->mixed_k / bc->mixed_p : 1.0; /* kernel k G / p_k or G */
@@ -650,7 +779,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
          so the kept one has probability |k_j| / S.  Weight
          k(y) / |k(y)| * S |Gamma| / C, the RIS estimate of int k(y) (.) dy. */
       const int C = bc->candidates;
-      double S = 0.0, Smag = 0.0, kpick = 0.0, ypick[3] = {0.0, 0.0, 0.0};
+      double S = 0.0, Smag = 0.0, kpick = 0.0, ypick[3] = {0.0, 0.0, 0.0}, dS = 0.0;
       int64_t jpick = -1;
       const double* nx = on_gamma ? normals + 3 * cur : NULL;
       const double ax = on_gamma ? prim_alpha(m, cur) : 0.0;
@@ -697,15 +826,20 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
         }
         const double pk = fabs(k);
         S += pk;
-        if (rr > 0.0) {
-          const double c = rho_cond(x, yc, dim);
-          if (c < res.cond_cos) res.cond_cos = c;
-        }
         if (rr > 0.0) { /* the same kernel with its error scale (G_mag) */
+          /* error of k: rho moves by P + |x| + |y| (x's error and the rounding of
+             y - x); the numerator (y - x) . n_x of the recursion, formed from
+             vertices and edges, by |x| + |y| */
+          const double rho = sqrt(rr), drho = P + xn + norm_d(yc, dim);
           if (first || dvert) {
             Smag += fabs(gscale) * G_mag(x, yc, dim);
+            dS += fabs(gscale) * (dim == 3 ? 1.0 / (4.0 * ORC_PI * rr) : 1.0 / (2.0 * ORC_PI * rho)) * drho;
           } else { /* |2 dG/dn_x| + 2 |alpha| G_mag, with 2 dG/dn_x = -k / phi - 2 alpha G */
-            Smag += fabs(k + 2.0 * phi * ax * G(x, yc, dim)) + 2.0 * fabs(ax) * G_mag(x, yc, dim);
+            const double dn2 = fabs(k + 2.0 * phi * ax * G(x, yc, dim));
+            Smag += dn2 + 2.0 * fabs(ax) * G_mag(x, yc, dim);
+            const double sd = dim == 3 ? 4.0 * ORC_PI * rr * rho : 2.0 * ORC_PI * rr;
+            dS += dn2 * (double)dim * drho / rho + 2.0 * (xn + norm_d(yc, dim)) / sd +
+                  2.0 * fabs(ax) * (dim == 3 ? 1.0 / (4.0 * ORC_PI * rr) : 1.0 / (2.0 * ORC_PI * rho)) * drho;
           }
         }
         const double u = uniform(rj[3]);
@@ -723,6 +857,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       if (jpick < 0 || !(S > 0.0)) break; /* no candidate carries kernel mass */
       if (vprim) vprim[i] = (int32_t)jpick;
       const double w = (kpick > 0.0 ? 1.0 : -1.0) * S * at->total / (double)C;
+      const double eps = dS / Smag;
       if (want_grad && first) {
         /* RIS estimate of int grad_x G mu: grad_x G(y) / |G(y)| S |Gamma| / C */
         double gg[3];
@@ -733,16 +868,23 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
           Wg[a] = Wg[a] * w + W * gg[a] * f;
           Wgabs += fabs(W * gg[a] * f);
         }
-        const double c = rho_cond(x, ypick, dim);
-        if (c < res.cond_cos) res.cond_cos = c;
+        /* grad G / |G| = r / rho^2 (2D: r / (rho^2 |ln rho|)): the picked
+           point's distance carries P + |x| + |y| */
+        double r[3] = {ypick[0] - x[0], ypick[1] - x[1], dim == 3 ? ypick[2] - x[2] : 0.0};
+        const double rho = norm_d(r, dim);
+        eWg = eps + 3.0 * (P + xn + norm_d(ypick, dim)) / rho +
+              (dim == 2 ? (P + xn + norm_d(ypick, dim)) / (rho * fmax(fabs(log(rho)), 1e-300)) : 0.0);
       } else {
         for (int a = 0; a < 3; ++a) Wg[a] *= w;
         Wgabs *= Smag * at->total / (double)C;
+        eWg += eps;
       }
       W *= w;
       Wabs *= Smag * at->total / (double)C;
+      eW += eps;
       memcpy(x, ypick, sizeof(x));
       cur = jpick;
+      P = norm_d(x, dim); /* a point drawn by its barycentrics */
       if (vpos)
         for (int a = 0; a < dim; ++a) vpos[i * dim + a] = x[a];
       const double e = sl_emission(m, bc, cur, x, i + 1 >= M);
@@ -750,6 +892,10 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       abs_sum += Wabs * fabs(e);
       for (int a = 0; a < 3; ++a) gacc[a] += Wg[a] * e;
       gabs += Wgabs * fabs(e);
+      const double ke = (prim_kind(m, cur) == ORC_DIRICHLET ? bc->mixed_k : 2.0) * (i + 1 >= M ? 0.5 : 1.0);
+      const double ee = emission_err(m, bc, cur, x, ke, P);
+      err += Wabs * ee + eW * Wabs * fabs(e);
+      gerr += Wgabs * ee + eWg * Wgabs * fabs(e);
       continue;
     }
 
@@ -762,16 +908,24 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
 
     double y[3] = {0.0, 0.0, 0.0};
     int64_t next = -1;
-    double w, wabs;
+    double w, wabs, eps = 0.0, Pn = 0.0;
     if (use_self) {
       uint32_t r1[4];
       draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
-      double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), y);
-      {
-        /* 2D: G at rho = |y - x|; 3D: the distance R(theta) to the triangle's
-           boundary, from coordinate differences (rho <= R bounds it below) */
-        const double c = rho_cond(x, y, dim);
-        if (c < res.cond_cos) res.cond_cos = c;
+      double R, sinb;
+      double gp = self_panel_geo(m, cur, x, uniform(r1[0]), uniform(r1[1]), y, &R, &sinb);
+      if (dim == 3) {
+        /* G / p = R(theta) / 2: R moves by (P + |x| + R) / sin beta, and y,
+           a fraction of R from x, with it */
+        const double dR = (P + xn + R) / sinb;
+        eps = dR / R;
+        Pn = P + dR + xn + R;
+      } else {
+        /* G / p = -L ln rho / (2 pi) with y on the segment by its parameter:
+           rho moves by P + |x| + |y| */
+        const double rho = sqrt((y[0] - x[0]) * (y[0] - x[0]) + (y[1] - x[1]) * (y[1] - x[1]));
+        eps = (P + xn + norm_d(y, dim)) / (rho * fmax(fabs(log(rho)), 1.0));
+        Pn = norm_d(y, dim);
       }
       if (first || dvert)
         w = gscale * gp / bc->self_p; /* u = int G mu; Dirichlet vertex: -k G / p_k */
@@ -786,36 +940,50 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       const int src_line = form == ORC_DIRECT;
       const int last = i == L - 1;
       all_hits(m, normals, bc, src_line, !(src_line && last), x, d, cur, seed, path, point,
-               problem, (uint32_t)i, &h);
+               problem, (uint32_t)i, P, &h);
       if (h.graze < res.graze) res.graze = h.graze;
       if (vm) vm[i] = h.m;
       if (vprim) vprim[i] = (int32_t)h.sel;
       if (form == ORC_DIRECT) {
         /* source integral of the direct BIE: phi int G q off the boundary,
            2 phi int G q on it (Table 1, Neumann rows) */
-        double S, Sabs;
+        double S, Sabs, Serr = h.src_err;
         if (on_gamma) {
           uint32_t r1[4];
-          double ys[3];
+          double ys[3], R, sinb;
           draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
-          double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), ys);
-          double own = gp * orc_boundary_datum(m, bc, cur, ys);
+          double gp = self_panel_geo(m, cur, x, uniform(r1[0]), uniform(r1[1]), ys, &R, &sinb);
+          double qs = orc_boundary_datum(m, bc, cur, ys);
+          double own = gp * qs;
           S = 2.0 * phi * (h.src + own);
           Sabs = 2.0 * (h.src_abs + fabs(own));
+          /* the own-panel term as in the self-panel step above */
+          double dgp, dys;
+          if (dim == 3) {
+            const double dR = (P + xn + R) / sinb;
+            dgp = 0.5 * dR;
+            dys = P + dR + xn + R;
+          } else {
+            const double rho = sqrt((ys[0] - x[0]) * (ys[0] - x[0]) + (ys[1] - x[1]) * (ys[1] - x[1]));
+            dgp = R * (P + xn + norm_d(ys, dim)) / (2.0 * ORC_PI * rho);
+            dys = norm_d(ys, dim);
+          }
+          Serr = 2.0 * (h.src_err + fabs(qs) * dgp + emission_err(m, bc, cur, ys, gp, dys));
         } else {
           S = phi * h.src;
           Sabs = h.src_abs;
         }
-        if (h.src_cos < res.cond_cos) res.cond_cos = h.src_cos;
-        double term = W * S * (last ? 0.5 : 1.0);
+        const double cl = last ? 0.5 : 1.0;
+        double term = W * S * cl;
         acc += term;
-        abs_sum += Wabs * Sabs * (last ? 0.5 : 1.0);
+        abs_sum += Wabs * Sabs * cl;
+        err += (Wabs * Serr + eW * Wabs * Sabs) * cl;
         if (want_grad) {
           /* the step-0 source phi int G q is a function of x0 (off the boundary) */
-          const double c0 = last ? 0.5 : 1.0;
           for (int a = 0; a < 3; ++a)
-            gacc[a] += (Wg[a] * S + (i == 0 ? W * phi * h.src_grad[a] : 0.0)) * c0;
-          gabs += (Wgabs * Sabs + (i == 0 ? W * h.src_grad_abs : 0.0)) * c0;
+            gacc[a] += (Wg[a] * S + (i == 0 ? W * phi * h.src_grad[a] : 0.0)) * cl;
+          gabs += (Wgabs * Sabs + (i == 0 ? W * h.src_grad_abs : 0.0)) * cl;
+          gerr += (Wgabs * Serr + eWg * Wgabs * Sabs + (i == 0 ? Wabs * h.src_grad_err : 0.0)) * cl;
         }
         if (last) break;
       }
@@ -824,6 +992,10 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       next = h.sel;
       const double* ny = normals + 3 * next;
       double p = line_pdf(x, y, ny, h.m, dim);
+      /* the picked hit: incidence c, distance rho, and its position error */
+      double ry[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
+      const double rho = norm_d(ry, dim), cy = fabs(dot(ry, ny, dim)) / rho;
+      Pn = (P + xn + norm_d(y, dim) + rho) / cy;
       double kern, kabs;
       if (form == ORC_DOUBLE_LAYER) {
         kern = (first && !on_gamma) ? -dG_dny(x, y, ny, dim)           /* u = -int dG/dny nu */
@@ -837,8 +1009,9 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
         if (first || dvert) {
           kern = gscale * G(x, y, dim); /* u = int G mu; Dirichlet vertex: -k G / p_k */
           kabs = fabs(gscale) * G_mag(x, y, dim);
-          const double c = rho_cond(x, y, dim);
-          if (c < res.cond_cos) res.cond_cos = c;
+          /* G / p = m rho / (2c) (2D: -m rho ln rho / (2c)) */
+          eps = (dim == 3 ? Pn / rho : Pn * (fabs(log(rho)) + 1.0) / (rho * fmax(fabs(log(rho)), 1.0))) +
+                1.0 / cy;
         } else {
           /* dG/dn_x with its numerator (y - x) . n_x in vertex-and-edge form:
              x lies in the plane of its primitive, so (y - x) . n_x =
@@ -861,22 +1034,19 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
           const double rn = dot(dv, nx, dim) + h.sel_b[0] * dot(e1, nx, dim) +
                             (dim == 3 ? h.sel_b[1] * dot(e2, nx, dim) : 0.0);
           double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
-          const double rr = dot(r, r, dim), rho = sqrt(rr);
-          const double dgdn = dim == 3 ? rn / (4.0 * ORC_PI * rr * rho) : rn / (2.0 * ORC_PI * rr);
+          const double rr = dot(r, r, dim), rho2 = sqrt(rr);
+          const double dgdn = dim == 3 ? rn / (4.0 * ORC_PI * rr * rho2) : rn / (2.0 * ORC_PI * rr);
           kern = -2.0 * phi * (dgdn + prim_alpha(m, cur) * G(x, y, dim));
           kabs = 2.0 * (fabs(dgdn) + fabs(prim_alpha(m, cur)) * G_mag(x, y, dim));
-          /* a binary32 cos theta_x carries ~1e-7 absolute error, and rho from
-             coordinates a relative error ~ |x| / rho units */
-          const double cx = fabs(rn) / rho;
-          if (cx < res.cond_cos) res.cond_cos = cx;
-          const double cr = rho_cond(x, y, dim);
-          if (cr < res.cond_cos) res.cond_cos = cr;
-        }
-        /* the single-layer weight carries 1 / |cos theta_y| */
-        {
-          double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
-          double cy = fabs(dot(r, ny, dim)) / sqrt(dot(r, r, dim));
-          if (cy < res.cond_cos) res.cond_cos = cy;
+          /* w = -phi m (c_x + alpha rho) / c (2D: c_x - alpha rho ln rho): c
+             rounded by one unit, rho moved by Pn, and c_x by one unit plus
+             |x| / rho: a rounded vertex lies about |x| units off its
+             primitive's plane, which moves (y - x) . n_x by as much */
+          const double al = fabs(prim_alpha(m, cur)), cx = fabs(rn) / rho2;
+          const double lr = fabs(log(rho2));
+          eps = dim == 3 ? (1.0 + xn / rho2 + al * Pn) / (cx + al * rho2) + 1.0 / cy
+                         : (1.0 + xn / rho2 + al * Pn * (lr + 1.0)) / (cx + al * rho2 * fmax(lr, 1.0)) +
+                               1.0 / cy;
         }
       }
       w = kern / p;
@@ -901,27 +1071,28 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
           wg[a] = kg[a] / p;
           wgabs += fabs(wg[a]);
         }
-        /* the derivative kernels carry 1 / |cos theta_y| (double layer,
-           direct) and powers of 1 / rho */
-        double r[3] = {y[0] - x[0], y[1] - x[1], dim == 3 ? y[2] - x[2] : 0.0};
-        const double cy = fabs(dot(r, ny, dim)) / sqrt(dot(r, r, dim));
-        if (cy < res.cond_cos) res.cond_cos = cy;
-        const double cr = rho_cond(x, y, dim);
-        if (cr < res.cond_cos) res.cond_cos = cr;
         for (int a = 0; a < 3; ++a) Wg[a] = Wg[a] * w + W * wg[a];
         Wgabs = Wgabs * wabs + Wabs * wgabs;
+        /* w': single layer m sgn(t) d / (2c); double layer and direct
+           -m (n - D c rhat) / (2 rho c) (times phi): c rounded by one unit, rho
+           moved by Pn, the D c rhat part by D units */
+        eWg = form == ORC_SINGLE_LAYER ? 1.0 / cy + 2.0 : Pn / rho + (1.0 + dim) / cy + 2.0;
       } else {
         for (int a = 0; a < 3; ++a) Wg[a] *= w;
         Wgabs *= wabs;
+        eWg += eps;
       }
     }
     if (use_self) {
       for (int a = 0; a < 3; ++a) Wg[a] *= w;
       Wgabs *= wabs;
+      eWg += eps;
     }
 
     W *= w;
     Wabs *= wabs;
+    eW += eps;
+    P = Pn;
     memcpy(x, y, sizeof(x));
     cur = next;
     if (vpos)
@@ -930,21 +1101,28 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
     if (form != ORC_DIRECT) {
       /* emission 2 phi s at x_{i+1} (single layer on Dirichlet parts: k u_D);
          the last vertex gets half of it (Sec. 4.1.2, modified Neumann series) */
-      double e;
+      double e, k;
       if (form == ORC_SINGLE_LAYER) {
         e = sl_emission(m, bc, cur, x, i + 1 >= M);
+        k = (prim_kind(m, cur) == ORC_DIRICHLET ? bc->mixed_k : 2.0) * (i + 1 >= M ? 0.5 : 1.0);
       } else {
         double s = orc_boundary_datum(m, bc, cur, x);
-        e = (i + 1 < M ? 2.0 : 1.0) * phi * s;
+        k = (i + 1 < M ? 2.0 : 1.0);
+        e = k * phi * s;
       }
       acc += W * e;
       abs_sum += Wabs * fabs(e);
       for (int a = 0; a < 3; ++a) gacc[a] += Wg[a] * e;
       gabs += Wgabs * fabs(e);
+      const double ee = emission_err(m, bc, cur, x, k, P);
+      err += Wabs * ee + eW * Wabs * fabs(e);
+      gerr += Wgabs * ee + eWg * Wgabs * fabs(e);
     }
   }
   res.value = acc;
   res.abs_sum = abs_sum;
+  res.err = err;
+  res.grad_err = gerr;
   if (want_grad) {
     for (int a = 0; a < dim; ++a) grad[a] = gacc[a];
     if (grad_abs) *grad_abs = gabs;
@@ -1004,7 +1182,7 @@ int orc_trace(const orc_mesh* m, const double* points, const int32_t* point_prim
     if (out->value) out->value[it] = r.value;
     if (out->abs_sum) out->abs_sum[it] = r.abs_sum;
     if (out->graze) out->graze[it] = r.graze;
-    if (out->cond_cos) out->cond_cos[it] = r.cond_cos;
+    if (out->err) out->err[it] = r.err;
   }
   free(normals);
   free(at.cdf);
@@ -1053,7 +1231,7 @@ int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim
 
 /* ------------------------------------------------------------------------- */
 /* Forward (adjoint) estimator of the single layer on Neumann boundaries     */
-/* (Sec. 4.4 "Forward estimator"; Table 1, single-layer Neumann rows).        */
+/* (Sec. 4.4.3 "Forward estimator"; Table 1, single-layer Neumann rows).        */
 /*                                                                           */
 /* The single layer writes u(x) = int G(x, y) mu(y) dA with mu = f + K mu,    */
 /* f = 2 phi q and K(x, y) = -2 phi dG/dn_x(x, y).  Truncated with the halved  */
@@ -1136,10 +1314,15 @@ int orc_forward_paths(const orc_mesh* m, const orc_bc* bc, const double* start_w
       if (out->vtx_w) out->vtx_w[p * M + k] = 0.0;
       if (out->vtx_prim) out->vtx_prim[p * M + k] = -1;
       if (out->vtx_m) out->vtx_m[p * M + k] = 0;
+      if (out->vtx_perr) out->vtx_perr[p * M + k] = 0.0;
+      if (out->vtx_werr) out->vtx_werr[p * M + k] = 0.0;
       if (pos)
         for (int a = 0; a < dim; ++a) pos[k * dim + a] = 0.0;
     }
-    double graze = INFINITY, cond = INFINITY;
+    /* rounding-error bounds (units of u): position of the current vertex and
+       the strength's first factor 2 phi q(y_1) A_T / P_T (later steps multiply
+       by the exact factors +-m) */
+    double graze = INFINITY, P = 0.0, werr = 0.0;
     /* y_1 ~ p_0 */
     uint32_t r[4];
     draw(seed, path, ORC_FWD_POINT, problem, 0xffffu, 3u, 0u, r);
@@ -1157,6 +1340,8 @@ int orc_forward_paths(const orc_mesh* m, const orc_bc* bc, const double* start_w
     const double P_T = (double)cdf[T] - (T > 0 ? (double)cdf[T - 1] : 0.0);
     const double p0 = P_T / prim_area(m, T);
     double W = 2.0 * phi * orc_boundary_datum(m, bc, T, x) / p0;
+    P = norm_d(x, dim); /* drawn by its barycentrics */
+    werr = 4.0 * fabs(W) + emission_err(m, bc, T, x, 2.0 / p0, P);
     int64_t cur = T;
     for (int k = 0; k < M; ++k) {
       if (k > 0) {
@@ -1178,7 +1363,7 @@ int orc_forward_paths(const orc_mesh* m, const orc_bc* bc, const double* start_w
         }
         line_hits h;
         all_hits(m, normals, bc, 0, 1, x, d, cur, seed, path, ORC_FWD_POINT, problem,
-                 (uint32_t)(k - 1), &h);
+                 (uint32_t)(k - 1), P, &h);
         if (h.graze < graze) graze = h.graze;
         if (out->vtx_m) out->vtx_m[p * M + k] = h.m;
         if (h.m == 0) break;
@@ -1188,20 +1373,22 @@ int orc_forward_paths(const orc_mesh* m, const orc_bc* bc, const double* start_w
         const double pdf = line_pdf(x, h.sel_y, ny, h.m, dim);
         {
           double rr[3] = {h.sel_y[0] - x[0], h.sel_y[1] - x[1], dim == 3 ? h.sel_y[2] - x[2] : 0.0};
-          const double c = fabs(dot(rr, ny, dim)) / sqrt(dot(rr, rr, dim));
-          if (c < cond) cond = c;
+          const double rho = sqrt(dot(rr, rr, dim)), c = fabs(dot(rr, ny, dim)) / rho;
+          P = (P + norm_d(x, dim) + norm_d(h.sel_y, dim) + rho) / c;
         }
         W *= kern / pdf;
+        werr *= (double)h.m;
         memcpy(x, h.sel_y, sizeof(x));
         cur = h.sel;
       }
       if (out->vtx_w) out->vtx_w[p * M + k] = (k + 1 < M ? 1.0 : 0.5) * W;
+      if (out->vtx_perr) out->vtx_perr[p * M + k] = P;
+      if (out->vtx_werr) out->vtx_werr[p * M + k] = (k + 1 < M ? 1.0 : 0.5) * werr;
       if (out->vtx_prim) out->vtx_prim[p * M + k] = (int32_t)cur;
       if (pos)
         for (int c = 0; c < dim; ++c) pos[k * dim + c] = x[c];
     }
     if (out->graze) out->graze[p] = graze;
-    if (out->cond_cos) out->cond_cos[p] = cond;
   }
   free(normals);
   free(cdf);
@@ -1254,7 +1441,8 @@ int orc_forward_gather(int dim, int64_t n_paths, int walk_len, const double* vtx
 int orc_trace_grad(const orc_mesh* m, const double* points, int64_t n_points, const orc_bc* bc,
                    int walk_len, uint64_t seed, uint32_t problem, int64_t n_items,
                    const int64_t* item_point, const int64_t* item_path, double* value, double* grad,
-                   double* abs_sum, double* grad_abs, double* graze, double* cond_cos, int n_threads) {
+                   double* abs_sum, double* grad_abs, double* graze, double* err, double* grad_err,
+                   int n_threads) {
   if (check_args(m, bc, walk_len) || bc->density || !grad) return 1;
   const int form = orc_resolve_formulation(m, bc->formulation);
   double* normals = make_normals(m);
@@ -1275,7 +1463,8 @@ int orc_trace_grad(const orc_mesh* m, const double* points, int64_t n_points, co
     if (abs_sum) abs_sum[it] = r.abs_sum;
     if (grad_abs) grad_abs[it] = gabs;
     if (graze) graze[it] = r.graze;
-    if (cond_cos) cond_cos[it] = r.cond_cos;
+    if (err) err[it] = r.err;
+    if (grad_err) grad_err[it] = r.grad_err;
   }
   free(normals);
   free(at.cdf);
@@ -1357,7 +1546,7 @@ int orc_intersect_all(const orc_mesh* m, const double* orig, const double* dir,
       if (j == ex) continue;
       double t, y[3], margin, cosv;
       int hit = line_prim(m, j, x, d, &t, y, &margin, &cosv);
-      double g = fabs(margin) * cosv;
+      double g = decision_margin(m, j, x, margin, cosv);
       if (g < graze) graze = g;
       if (!hit) continue;
       if (cnt < max_hits) {
@@ -1374,7 +1563,7 @@ int orc_intersect_all(const orc_mesh* m, const double* orig, const double* dir,
         }
         hp[pos] = (int32_t)j;
         ht[pos] = t;
-        if (hm) hm[pos] = fabs(margin) * cosv;
+        if (hm) hm[pos] = g;
       }
       ++cnt;
     }
@@ -1557,17 +1746,23 @@ static int collect_hits(const orc_mesh* m, const double* x, const double* d, int
 
 #define CV_MAX_HITS 256
 
+/* Value of the corrected path; *abs_out and *err_out (may be NULL) receive its
+   magnitude sum and its first-order rounding-error bound in units of u (the
+   bookkeeping of one_path, extended to the all-hits sums). */
 static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc* bc,
                           const double* g, const double* g0, const double* x0, int64_t prim0,
-                          int M, uint64_t seed, uint32_t problem, uint32_t point, uint32_t path) {
+                          int M, uint64_t seed, uint32_t problem, uint32_t point, uint32_t path,
+                          double* abs_out, double* err_out) {
   const int dim = m->dim;
   const double phi = (double)bc->domain;
   double x[3] = {x0[0], x0[1], dim == 3 ? x0[2] : 0.0};
   int64_t cur = prim0;
   double W = 1.0, acc = 0.0;
+  double Wabs = 1.0, abs_sum = 0.0, P = 0.0, eW = 0.0, err = 0.0;
   hit_rec hits[CV_MAX_HITS];
   for (int i = 0; i < M; ++i) {
     const int on_gamma = cur >= 0, last = i == M - 1;
+    const double xn = norm_d(x, dim);
     uint32_t r0[4];
     draw(seed, path, point, problem, (uint32_t)i, 0u, 0u, r0);
     double d[3] = {0.0, 0.0, 0.0};
@@ -1587,66 +1782,114 @@ static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc
     const int use_self = mixture && (r0[2] >> 8) < bc->self_threshold;
     double y[3];
     int64_t next;
-    double Wn;
+    double Wn, Wnabs, eWn, Pn;
     if (use_self) {
       uint32_t r1[4];
       draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
-      const double gp = orc_self_panel(m, cur, x, uniform(r1[0]), uniform(r1[1]), y);
+      double R, sinb;
+      const double gp = self_panel_geo(m, cur, x, uniform(r1[0]), uniform(r1[1]), y, &R, &sinb);
       const double w = (i == 0 ? gp : -2.0 * phi * prim_alpha(m, cur) * gp) / bc->self_p;
+      const double dR = (P + xn + R) / sinb;
       Wn = W * w;
+      Wnabs = Wabs * fabs(w);
+      eWn = eW + dR / R;
+      Pn = P + dR + xn + R;
       next = cur;
-      if (i == 0 && !last) acc -= Wn * g0[cur];
-      acc += Wn * (last ? phi : 2.0 * phi) * orc_boundary_datum(m, bc, cur, y);
+      if (i == 0 && !last) {
+        acc -= Wn * g0[cur];
+        abs_sum += Wnabs * fabs(g0[cur]);
+        err += eWn * Wnabs * fabs(g0[cur]);
+      }
+      const double k = last ? phi : 2.0 * phi;
+      const double e = k * orc_boundary_datum(m, bc, cur, y);
+      acc += Wn * e;
+      abs_sum += Wnabs * fabs(e);
+      err += Wnabs * emission_err(m, bc, cur, y, k, Pn) + eWn * Wnabs * fabs(e);
     } else {
       const int mh = collect_hits(m, x, d, cur, hits, CV_MAX_HITS, seed, path, point, problem,
                                   (uint32_t)i);
       if (mh == 0) break;
       if (mh > CV_MAX_HITS) return NAN;
-      double a[CV_MAX_HITS];
+      double a[CV_MAX_HITS], aabs[CV_MAX_HITS], aeps[CV_MAX_HITS], ap[CV_MAX_HITS];
       int j = 0;
       for (int h = 0; h < mh; ++h) {
         const double* ny = normals + 3 * hits[h].prim;
-        double kern;
+        double kern, kabs;
+        double r[3] = {hits[h].y[0] - x[0], hits[h].y[1] - x[1], dim == 3 ? hits[h].y[2] - x[2] : 0.0};
+        const double rho = norm_d(r, dim), cy = fabs(dot(r, ny, dim)) / rho;
+        ap[h] = (P + xn + norm_d(hits[h].y, dim) + rho) / cy; /* the hit's position error */
         if (i == 0) {
           kern = G(x, hits[h].y, dim);
+          kabs = G_mag(x, hits[h].y, dim);
+          aeps[h] = ap[h] / rho + 1.0 / cy;
         } else {
           const double* nx = normals + 3 * cur;
-          kern = -2.0 * phi * (dG_dnx(x, hits[h].y, nx, dim) + prim_alpha(m, cur) * G(x, hits[h].y, dim));
+          const double al = fabs(prim_alpha(m, cur));
+          const double dn = dG_dnx(x, hits[h].y, nx, dim);
+          kern = -2.0 * phi * (dn + prim_alpha(m, cur) * G(x, hits[h].y, dim));
+          kabs = 2.0 * (fabs(dn) + al * G_mag(x, hits[h].y, dim));
+          const double cx = fabs(dot(r, nx, dim)) / rho;
+          aeps[h] = (1.0 + xn / rho + al * ap[h]) / (cx + al * rho) + 1.0 / cy;
         }
-        a[h] = kern / line_pdf(x, hits[h].y, ny, 1, dim) / (mixture ? 1.0 - bc->self_p : 1.0);
+        const double pa = line_pdf(x, hits[h].y, ny, 1, dim) * (mixture ? 1.0 - bc->self_p : 1.0);
+        a[h] = kern / pa;
+        aabs[h] = kabs / pa;
         if (hits[h].key < hits[j].key || (hits[h].key == hits[j].key && hits[h].prim < hits[j].prim))
           j = h;
       }
       if (last) {
-        for (int h = 0; h < mh; ++h)
-          acc += W * a[h] * phi * orc_boundary_datum(m, bc, hits[h].prim, hits[h].y);
+        for (int h = 0; h < mh; ++h) {
+          const double e = phi * orc_boundary_datum(m, bc, hits[h].prim, hits[h].y);
+          acc += W * a[h] * e;
+          abs_sum += Wabs * aabs[h] * fabs(e);
+          err += Wabs * aabs[h] * emission_err(m, bc, hits[h].prim, hits[h].y, phi, ap[h]) +
+                 (eW + aeps[h]) * Wabs * aabs[h] * fabs(e);
+        }
         break;
       }
       const double wj = a[j] * (double)mh;
       Wn = W * wj;
+      Wnabs = Wabs * aabs[j] * (double)mh;
+      eWn = eW + aeps[j];
+      Pn = ap[j];
       memcpy(y, hits[j].y, sizeof(y));
       next = hits[j].prim;
       const double ej = 2.0 * phi * orc_boundary_datum(m, bc, next, y);
       if (i == 0) {
         acc -= Wn * g0[next];
         acc += Wn * ej;
+        abs_sum += Wnabs * (fabs(g0[next]) + fabs(ej));
+        err += Wnabs * emission_err(m, bc, next, y, 2.0 * phi, Pn) + eWn * Wnabs * (fabs(g0[next]) + fabs(ej));
       } else {
-        for (int h = 0; h < mh; ++h)
-          acc += W * a[h] * (2.0 * phi * orc_boundary_datum(m, bc, hits[h].prim, hits[h].y) + g[hits[h].prim]);
+        for (int h = 0; h < mh; ++h) {
+          const double eh = 2.0 * phi * orc_boundary_datum(m, bc, hits[h].prim, hits[h].y);
+          acc += W * a[h] * (eh + g[hits[h].prim]);
+          abs_sum += Wabs * aabs[h] * (fabs(eh) + fabs(g[hits[h].prim]));
+          err += Wabs * aabs[h] * emission_err(m, bc, hits[h].prim, hits[h].y, 2.0 * phi, ap[h]) +
+                 (eW + aeps[h]) * Wabs * aabs[h] * (fabs(eh) + fabs(g[hits[h].prim]));
+        }
         acc -= Wn * g[next]; /* the picked hit's emission is kept as in the plain estimator */
+        abs_sum += Wnabs * fabs(g[next]);
+        err += eWn * Wnabs * fabs(g[next]);
       }
     }
     W = Wn;
+    Wabs = Wnabs;
+    eW = eWn;
+    P = Pn;
     memcpy(x, y, sizeof(x));
     cur = next;
   }
+  if (abs_out) *abs_out = abs_sum;
+  if (err_out) *err_out = err;
   return acc;
 }
 
 int orc_trace_cv(const orc_mesh* m, const double* points, const int32_t* point_prim,
                  int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed, uint32_t problem,
                  const double* g, const double* g0, int64_t n_items, const int64_t* item_point,
-                 const int64_t* item_path, double* value, int n_threads) {
+                 const int64_t* item_path, double* value, double* abs_sum, double* err,
+                 int n_threads) {
   if (check_args(m, bc, walk_len) || !g) return 1;
   if (!g0) g0 = g;
   if (orc_resolve_formulation(m, bc->formulation) != ORC_SINGLE_LAYER || bc->density) return 1;
@@ -1664,7 +1907,8 @@ int orc_trace_cv(const orc_mesh* m, const double* points, const int32_t* point_p
     for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
     const int64_t prim0 = point_prim ? point_prim[p] : -1;
     value[it] = one_path_cv(m, normals, bc, g, g0, x0, prim0, walk_len, seed, problem,
-                            (uint32_t)p, (uint32_t)item_path[it]);
+                            (uint32_t)p, (uint32_t)item_path[it], abs_sum ? abs_sum + it : NULL,
+                            err ? err + it : NULL);
   }
   free(normals);
   return 0;

@@ -80,9 +80,11 @@ typedef struct {
   double* value;           /* [n_items] per-path estimate u_hat */
   double* abs_sum;         /* [n_items] the path sum with every factor and summand replaced
                               by its magnitude (scale for relative tolerances) */
-  double* graze;           /* [n_items] min over lines of |barycentric margin|*|cos| */
-  double* cond_cos;        /* [n_items] smallest |cos theta_y| entering a 1/|cos| factor
-                              (direct source hits, single-layer weights); inf if none */
+  double* graze;           /* [n_items] min over the lines' primitives of the decision margin in
+                              units of its rounding scale (decision_margin, oracle.c) */
+  double* err;             /* [n_items] first-order rounding-error bound of the value in units
+                              of the unit roundoff u (see oracle.c): an evaluation of the same
+                              path with unit roundoff u differs by about u * err at most */
   int32_t* vtx_prim;       /* [n_items * L] selected primitive per line, -1 none, -2-p self-panel */
   int32_t* vtx_m;          /* [n_items * L] number of hits per line */
   double* vtx_pos;         /* [n_items * L * dim] vertex reached by each line */
@@ -115,7 +117,8 @@ int orc_solve(const orc_mesh* mesh, const double* points, const int32_t* point_p
 
 /* All hits of the lines orig + t*dir (t real), excluding primitive exclude[i].
  * n_hits[i] is the full count; at most max_hits (prim, t, margin) are stored,
- * in increasing (t, prim) order. margin = |barycentric margin| * |cos|. */
+ * in increasing (t, prim) order. margin: the decision margin in units of its rounding
+ * scale (decision_margin in oracle.c). */
 int orc_intersect_all(const orc_mesh* mesh, const double* orig, const double* dir,
                       const int32_t* exclude, int64_t n_lines, int max_hits,
                       int32_t* n_hits, int32_t* hit_prim, double* hit_t,
@@ -138,12 +141,13 @@ double orc_prim_potential(const orc_mesh* mesh, int64_t prim, const double* x);
  * corrected estimator for per-primitive tables g (lines 1.., the network's
  * prediction of the boundary unknown minus its emission) and g0 (line 0; NULL
  * means g0 = g).  The per-point add-back sum_T g0_T int_T G(x0, y) dA comes
- * from orc_cv_addback (zero when M = 1). */
+ * from orc_cv_addback (zero when M = 1).  abs_sum and err (may be NULL): the
+ * path's magnitude sum and rounding-error bound in units of u, as in orc_trace. */
 int orc_trace_cv(const orc_mesh* mesh, const double* points, const int32_t* point_prim,
                  int64_t n_points, const orc_bc* bc, int walk_len, uint64_t seed,
                  uint32_t problem, const double* g, const double* g0, int64_t n_items,
                  const int64_t* item_point, const int64_t* item_path, double* value,
-                 int n_threads);
+                 double* abs_sum, double* err, int n_threads);
 /* randomized = 0: sum_T g_T int_T G(x0, y) dA in closed form.  randomized = 1:
  * closed form only for triangles whose centroid lies within four bounding radii of
  * x0; every other triangle contributes g_T A_T G(x0, y_T) at one uniform point
@@ -153,23 +157,26 @@ int orc_trace_cv(const orc_mesh* mesh, const double* points, const int32_t* poin
 int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points, int64_t n_points,
                    uint32_t seed, int randomized, double* out, int n_threads);
 
-/* Gradient estimators (Sec. 4.4, gradient estimation with the same paths):
+/* Gradient estimators (Sec. 4.1.3, derivative estimators along the same paths):
  * the path of orc_trace with the kernel of its first step replaced by its
  * gradient in x0 (double layer: -grad dG/dn_y; direct BIE: -phi grad dG/dn_y
  * and phi grad G in the step-0 source; single layer: grad G), the rest of the
  * path unchanged.  Points must lie off the boundary (the gradient equations
  * hold inside the domain); no density mode.  grad: [n_items * dim];
- * grad_abs: the magnitude sum of the gradient terms (rounding scale). */
+ * grad_abs: the magnitude sum of the gradient terms (rounding scale); err,
+ * grad_err: rounding-error bounds of the value and of each gradient component
+ * in units of u (as orc_trace_out.err). */
 int orc_trace_grad(const orc_mesh* mesh, const double* points, int64_t n_points, const orc_bc* bc,
                    int walk_len, uint64_t seed, uint32_t problem, int64_t n_items,
                    const int64_t* item_point, const int64_t* item_path, double* value, double* grad,
-                   double* abs_sum, double* grad_abs, double* graze, double* cond_cos, int n_threads);
+                   double* abs_sum, double* grad_abs, double* graze, double* err, double* grad_err,
+                   int n_threads);
 int orc_solve_grad(const orc_mesh* mesh, const double* points, int64_t n_points, const orc_bc* bc,
                    int samples, int walk_len, uint64_t seed, uint32_t problem, double* mean_out,
                    double* var_out, double* grad_out, double* grad_var_out, int n_threads);
 
 /* Forward (adjoint) estimator of the single layer, all-Neumann boundary
- * (Sec. 4.4 "Forward estimator"; see oracle.c for the derivation and the
+ * (Sec. 4.4.3 "Forward estimator"; see oracle.c for the derivation and the
  * random-number layout).  orc_forward_paths writes, per path and vertex
  * k = 1..M, the vertex y_k, its primitive, the hits of the line that reached
  * it (0 for k = 1) and its source strength c_{k-1} W_k (0 and prim -1 once the
@@ -180,9 +187,10 @@ typedef struct {
   double* vtx_w;           /* [n_paths * M] */
   int32_t* vtx_prim;       /* [n_paths * M] */
   int32_t* vtx_m;          /* [n_paths * M] */
-  double* graze;           /* [n_paths] min over lines of |barycentric margin|*|cos| */
-  double* cond_cos;        /* [n_paths] smallest |cos theta| at a sampled hit (its sign sets
-                              the weight) */
+  double* graze;           /* [n_paths] min over the lines' primitives of the decision margin in
+                              units of its rounding scale (decision_margin, oracle.c) */
+  double* vtx_perr;        /* [n_paths * M] rounding-error bounds (units of u) of each vertex's */
+  double* vtx_werr;        /* position and strength (see oracle.c) */
 } orc_forward_out;
 int orc_forward_paths(const orc_mesh* mesh, const orc_bc* bc, const double* start_weight,
                       int64_t n_paths, int walk_len, uint64_t seed, uint32_t problem,

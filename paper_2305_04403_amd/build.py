@@ -6,6 +6,7 @@ hipcc compiles the kernels for gfx950 only.  Packed-FP32 instruction
 selection is disabled (-packed-fp32-ops): ordinary scalar FP32 code is
 emitted for every float operation.
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -25,21 +26,23 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in ("wob.hip", "batch.hip", "mlp.hip", "forward.hip", "probe.hip"):
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
-        cmd = [hipcc, "-c", *HIP_FLAGS, os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append([hipcc, "-c", *HIP_FLAGS, os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in ("bvh_build.cpp",):
         obj = os.path.join(obj_dir, src.replace(".cpp", ".o"))
-        cmd = ["g++", "-c", "-O2", "-std=c++17", "-fPIC", "-Wall", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append(["g++", "-c", "-O2", "-std=c++17", "-fPIC", "-Wall", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # the translation units are independent: compile them side by side
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for f in [pool.submit(subprocess.check_call, cmd) for cmd in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:

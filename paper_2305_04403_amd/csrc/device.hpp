@@ -208,18 +208,6 @@ __device__ __forceinline__ void load_normal(const SceneView<R, D>& s, int32_t id
   n[2] = D == 3 ? p[2] : (R)0;
 }
 
-// Orientation only: a vector along the outward normal, not normalised.
-template <typename R, int D>
-__device__ __forceinline__ void normal_dir(const PrimGeo<R>& g, R n[3]) {
-  if constexpr (D == 3) {
-    cross3(g.e1, g.e2, n);
-  } else {
-    n[0] = g.e1[1];
-    n[1] = -g.e1[0];
-    n[2] = 0;
-  }
-}
-
 // --------------------------------------------------------------------------
 // Harmonic program and boundary datum (eq. PoissonBC)
 // --------------------------------------------------------------------------
@@ -430,6 +418,29 @@ template <typename R>
 __device__ __forceinline__ void hit_point(const PrimGeo<R>& g, R u, R v, R y[3]) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) y[k] = g.v0[k] + u * g.e1[k] + v * g.e2[k];
+}
+
+// Line parameter and point where the line x + t d crosses the plane of a
+// primitive it hits (unit normal n, 2D: n[2] = 0): t = (v0 - x) . n / (d . n),
+// y = x + t d.  The barycentric solution of the hit test rounds with the
+// primitive's shape (its error grows like |e1| |e2| / (2 A) on slivers); this
+// form rounds by a few units of |x| + |t| over |d . n| whatever the shape.
+// The test accepted the hit with d . n != 0; should the rounded normal still
+// give 0, the barycentric solution is used.
+template <typename R, int D>
+__device__ __forceinline__ R plane_hit(const PrimGeo<R>& g, const R n[3], const R x[3], const R d[3], R y[3]) {
+  const R w[3] = {g.v0[0] - x[0], g.v0[1] - x[1], D == 3 ? g.v0[2] - x[2] : (R)0};
+  const R dn = dot3(d, n);
+  R t;
+  if (dn != (R)0) {
+    t = dot3(w, n) / dn;
+  } else {
+    R u, v;
+    hit_prim<R, D>(g, x, d, t, u, v);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) y[k] = x[k] + t * d[k];
+  return t;
 }
 
 // Slab test of a line against a box in the scene's box frame; inv = 1 / d

@@ -212,11 +212,15 @@ __global__ void __launch_bounds__(NT) mlp_grad_kernel(Net net, const float* y, c
   float e = 0.f;
   if (r0 + r < n) {
     float tv = target[r0 + r];
-    if (tm.on) {
-      tv = (tv - tm.shift) * tm.inv_scale;
-      if (tm.clip > 0.f) tv = fminf(fmaxf(tv, -tm.clip), tm.clip);
+    // a non-finite target (a boundary point whose every path was non-finite)
+    // has no weight in the loss: e = 0 (clamping would turn NaN into -clip)
+    if (isfinite(tv)) {
+      if (tm.on) {
+        tv = (tv - tm.shift) * tm.inv_scale;
+        if (tm.clip > 0.f) tv = fminf(fmaxf(tv, -tm.clip), tm.clip);
+      }
+      e = f - tv;
     }
-    e = f - tv;
   }
   if ((tid & 3) == 0) sm.g5[r] = 2.f * e * scale;
   sm.red[tid] = (tid & 3) == 0 ? e * e : 0.f;

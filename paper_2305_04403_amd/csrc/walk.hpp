@@ -501,12 +501,10 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
           s.h.idx = j;
         }
       }
-      R t = 0, u = 0, v = 0;
-      if constexpr (GEO) hit_prim<R, D>(g, s.x, s.d, t, u, v);
       if constexpr (FORM == F_DIRECT) {
         R y[3], n[3];
-        hit_point(g, u, v, y);
         load_normal<R, D>(sc, j, n);
+        const R t = plane_hit<R, D>(g, n, s.x, s.d, y);
         R uu, grad[3];
         program_eval<R, D>(a.prog, y, uu, grad);
         const R q = dot3(n, grad);
@@ -531,8 +529,8 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
         if (s.sum) {
           // a(h) F(y_h): the weight of hit h without the 1/m of the pick
           R y[3], n[3];
-          hit_point(g, u, v, y);
           load_normal<R, D>(sc, j, n);
+          const R t = plane_hit<R, D>(g, n, s.x, s.d, y);
           const R rho = fabs(t);
           const R acy = fabs(dot3(s.d, n));
           const R sgn_t = t > (R)0 ? (R)1 : (R)-1;
@@ -587,22 +585,15 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     return ST_DONE;
   }
   const PrimGeo<R> gy = load_prim<R, D>(a.scene, h.idx);
-  R y[3], w;
-  {
-    // the kept hit's line parameter and barycentrics (the same test that
-    // accepted it, on the same line)
-    R u, v;
-    hit_prim<R, D>(gy, s.x, s.d, h.t, u, v);
-    hit_point(gy, u, v, y);
-  }
+  R y[3], w, ny[3];
+  // the kept hit: where the line crosses its primitive's plane
+  load_normal<R, D>(a.scene, h.idx, ny);
+  h.t = plane_hit<R, D>(gy, ny, s.x, s.d, y);
   // y - x = t d: the unit direction to the hit is sign(t) d and rho = |t|
   const R sgn_t = h.t > (R)0 ? (R)1 : (R)-1;
   const R mm = (R)h.m;
-  R ny[3] = {0, 0, 0};
   if constexpr (FORM == F_DL || FORM == F_DIRECT || FORM == F_FWD) {
-    R nd[3];
-    normal_dir<R, D>(gy, nd);
-    const R sg = sgn_t * dot3(s.d, nd) > (R)0 ? (R)1 : (R)-1;  // sgn(cos theta_y)
+    const R sg = sgn_t * dot3(s.d, ny) > (R)0 ? (R)1 : (R)-1;  // sgn(cos theta_y)
     if constexpr (FORM == F_DL)
       w = (s.first && !s.on_gamma) ? (R)0.5 * mm * sg : -phi * mm * sg;
     else if constexpr (FORM == F_DIRECT)
@@ -610,7 +601,6 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     else  // the Neumann row's kernel with its arguments swapped, over the line density
       w = phi * mm * sg;
   } else {
-    load_normal<R, D>(a.scene, h.idx, ny);
     const R rho = fabs(h.t);
     const R acy = fabs(dot3(s.d, ny));
     if (s.gscale != (R)0) {
@@ -631,8 +621,8 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
       //   single layer  grad G / p           = m rhat / (2 |c|)
       //   double layer  -grad dG/dn_y / p    = -m (n_y - D c rhat) / (2 rho |c|)
       //   direct BIE    -phi grad dG/dn_y / p (the same times phi)
-      R n[3], wg[3];
-      load_normal<R, D>(a.scene, h.idx, n);
+      const R* n = ny;
+      R wg[3];
       const R c = sgn_t * dot3(s.d, n), ac = fabs(c), rho = fabs(h.t);
       if constexpr (is_sl(FORM)) {
         const R f = s.gscale * mm * sgn_t / ((R)2 * ac);
@@ -1194,7 +1184,12 @@ __global__ void __launch_bounds__(256) intersect_kernel(SceneView<R, D> s, const
       if (!hit_prim<R, D>(g, x, d, t, u, v)) continue;
       if (cnt < max_hits) {
         hit_ids[l * max_hits + cnt] = g.id;
-        if (hit_t) hit_t[l * max_hits + cnt] = t;
+        if (hit_t) {
+          // the line parameter as the walk takes it: from the primitive's plane
+          R n[3], y[3];
+          load_normal<R, D>(s, j, n);
+          hit_t[l * max_hits + cnt] = plane_hit<R, D>(g, n, x, d, y);
+        }
       }
       ++cnt;
     }

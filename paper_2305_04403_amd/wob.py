@@ -209,6 +209,40 @@ def _stream(stream=None) -> Optional[int]:
     return s.cuda_stream
 
 
+def _need(t, name: str, dtype, shape, device: Optional[int] = None, optional: bool = False):
+    """Raise WobError unless t is a tensor of `dtype` and `shape` (None entries
+    match any size) on the CUDA device `device`, contiguous.  Checked before any
+    call into the library: a kernel reads its arrays at the sizes the call
+    states, so a mismatched tensor would be read past its end."""
+    if t is None:
+        if optional:
+            return
+        raise WobError(f"{name}: a tensor is required")
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise WobError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise WobError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.dim() != len(shape) or any(e is not None and int(a) != int(e) for a, e in zip(t.shape, shape)):
+        want = "(" + ", ".join("*" if e is None else str(e) for e in shape) + ")"
+        raise WobError(f"{name}: shape {tuple(t.shape)}, expected {want}")
+    if not t.is_cuda:
+        raise WobError(f"{name}: expected a device tensor")
+    if device is not None and t.device.index != device:
+        raise WobError(f"{name}: on cuda:{t.device.index}, the scene lives on cuda:{device}")
+    if not t.is_contiguous():
+        raise WobError(f"{name}: expected a contiguous tensor")
+
+
+def _need_points(scene, points, name: str = "points") -> int:
+    """(P, dim) points of the scene's dtype on its device; returns P."""
+    torch = _torch()
+    if not isinstance(points, torch.Tensor):
+        raise WobError(f"{name}: expected a torch tensor")
+    _need(points, name, scene.dtype, (None, scene.dim), scene.device)
+    return int(points.shape[0])
+
+
 class Scene:
     """A boundary mesh uploaded to the current device with its line-query BVH."""
 
@@ -226,6 +260,8 @@ class Scene:
         self.handle = h
         self.dim = int(mesh.dim)
         self.precision = int(precision)
+        self.n_prims = int(prims.shape[0])
+        self.device = _torch().cuda.current_device()  # the library builds on the current device
 
     @property
     def dtype(self):
@@ -268,12 +304,15 @@ def solve(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int =
     """Per-point mean (and variance) of ``samples`` WoB paths.  ``points`` is a
     contiguous (P, dim) device tensor of the scene's dtype."""
     torch = _torch()
-    P = points.shape[0]
+    P = _need_points(scene, points)
+    _need(point_prim, "point_prim", torch.int32, (P,), scene.device, optional=True)
     if out is None:
         mean = torch.empty(P, dtype=scene.dtype, device=points.device)
         var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
     else:
         mean, var = out
+        _need(mean, "mean out", scene.dtype, (P,), scene.device)
+        _need(var, "var out", scene.dtype, (P,), scene.device, optional=True)
     b = bc.c()
     st = lib().wob_solve(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
                          int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(mean),
@@ -318,7 +357,9 @@ def forward_paths(scene: Scene, bc: BC, n_paths: int, walk_len: int, seed: int =
     (n_paths, walk_len, 4) records (y, strength), plus the vertices' primitives
     and line hit counts when ``want_vertices``."""
     torch = _torch()
-    dev = torch.device("cuda", torch.cuda.current_device())
+    dev = torch.device("cuda", scene.device)
+    if out is not None:
+        _need(out, "out", scene.dtype, (n_paths, walk_len, 4), scene.device)
     vtx = out if out is not None else torch.empty((n_paths, walk_len, 4), dtype=scene.dtype, device=dev)
     vp = torch.empty((n_paths, walk_len), dtype=torch.int32, device=dev) if want_vertices else None
     vm = torch.empty((n_paths, walk_len), dtype=torch.int32, device=dev) if want_vertices else None
@@ -334,12 +375,15 @@ def forward_gather(scene: Scene, vtx, points, want_var: bool = True, stream=None
     """Connect every point to every forward-path vertex (``wob_forward_gather``):
     per-point mean and variance over the paths of ``vtx`` (n_paths, walk_len, 4)."""
     torch = _torch()
-    P = points.shape[0]
+    P = _need_points(scene, points)
+    _need(vtx, "vtx", scene.dtype, (None, None, 4), scene.device)
     if out is None:
         mean = torch.empty(P, dtype=scene.dtype, device=points.device)
         var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
     else:
         mean, var = out
+        _need(mean, "mean out", scene.dtype, (P,), scene.device)
+        _need(var, "var out", scene.dtype, (P,), scene.device, optional=True)
     st = lib().wob_forward_gather(scene.handle, _dev_ptr(vtx), int(vtx.shape[0]), int(vtx.shape[1]),
                                   _dev_ptr(points), P, _dev_ptr(mean), _dev_ptr(var), _stream(stream))
     _check(st, "wob_forward_gather")
@@ -351,7 +395,7 @@ def solve_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
     """Per-point mean value and gradient (and variances) along the same paths
     (``wob_solve_grad``); points off the boundary."""
     torch = _torch()
-    P, D = points.shape[0], scene.dim
+    P, D = _need_points(scene, points), scene.dim
     mean = torch.empty(P, dtype=scene.dtype, device=points.device)
     grad = torch.empty((P, D), dtype=scene.dtype, device=points.device)
     var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
@@ -367,7 +411,7 @@ def solve_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
 def trace_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0, stream=None):
     """Per-path values (P, samples) and gradients (P, samples, dim) (``wob_trace_grad``)."""
     torch = _torch()
-    P, D = points.shape[0], scene.dim
+    P, D = _need_points(scene, points), scene.dim
     path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
     pg = torch.empty((P, samples, D), dtype=scene.dtype, device=points.device)
     b = bc.c()
@@ -382,8 +426,11 @@ def gather_probe(buf, lanes: int, reads: int, seed: int = 0, out=None, stream=No
     returns one float per lane (the sum of all eight floats of each record
     read)."""
     torch = _torch()
+    if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
+        raise WobError("buf: expected a contiguous device tensor")
     if out is None:
         out = torch.empty(lanes, dtype=torch.float32, device=buf.device)
+    _need(out, "out", torch.float32, (lanes,), buf.device.index)
     st = lib().wob_gather_probe(_dev_ptr(buf), buf.numel() * buf.element_size(), int(lanes), int(reads),
                                 C.c_uint32(seed), _dev_ptr(out), _stream(stream))
     _check(st, "wob_gather_probe")
@@ -396,7 +443,9 @@ def trace(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int =
     hit count of every line.  ``point_ids`` (uint32 stored in an int32 tensor)
     replaces the point index used in the random-number counter."""
     torch = _torch()
-    P = points.shape[0]
+    P = _need_points(scene, points)
+    _need(point_prim, "point_prim", torch.int32, (P,), scene.device, optional=True)
+    _need(point_ids, "point_ids", torch.int32, (P,), scene.device, optional=True)
     L = scene.lines_per_path(bc, walk_len)
     path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
     vp = torch.empty((P, samples, L), dtype=torch.int32, device=points.device) if want_vertices else None
@@ -412,6 +461,8 @@ def trace(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int =
 def count_work(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
                point_prim=None, stream=None):
     torch = _torch()
+    P = _need_points(scene, points)
+    _need(point_prim, "point_prim", torch.int32, (P,), scene.device, optional=True)
     c = torch.zeros(4, dtype=torch.int64, device=points.device)
     b = bc.c()
     st = lib().wob_count_work(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), points.shape[0],
@@ -424,7 +475,9 @@ def count_work(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
 
 def intersect_all(scene: Scene, orig, dirs, exclude=None, max_hits: int = 64, stream=None):
     torch = _torch()
-    n = orig.shape[0]
+    n = _need_points(scene, orig, "orig")
+    _need(dirs, "dirs", scene.dtype, (n, scene.dim), scene.device)
+    _need(exclude, "exclude", torch.int32, (n,), scene.device, optional=True)
     nh = torch.empty(n, dtype=torch.int32, device=orig.device)
     hp = torch.full((n, max_hits), -1, dtype=torch.int32, device=orig.device)
     ht = torch.zeros((n, max_hits), dtype=scene.dtype, device=orig.device)
@@ -449,7 +502,8 @@ class Batch:
         arr = (_Problem * len(problems))()
         for i, p in enumerate(problems):
             scene, pts = p["scene"], p["points"]
-            P = pts.shape[0]
+            P = _need_points(scene, pts, f"problem {i} points")
+            _need(p.get("point_prim"), f"problem {i} point_prim", torch.int32, (P,), scene.device, optional=True)
             mean = torch.empty(P, dtype=scene.dtype, device=pts.device)
             var = torch.empty(P, dtype=scene.dtype, device=pts.device) if p.get("want_var", True) else None
             pp = p.get("point_prim")
@@ -519,6 +573,11 @@ class MLP:
         self.n_params = n
         self.max_batch = max_batch
 
+    def _need_batch(self, y, target):
+        torch = _torch()
+        _need(y, "y", torch.float32, (None, self.dim))
+        _need(target, "target", torch.float32, (y.shape[0],), y.device.index)
+
     def params(self) -> np.ndarray:
         out = np.zeros(self.n_params, dtype=np.float32)
         _check(lib().wob_mlp_get_params(self.handle, out.ctypes.data), "wob_mlp_get_params")
@@ -530,8 +589,10 @@ class MLP:
 
     def forward(self, y, out=None, stream=None):
         torch = _torch()
+        _need(y, "y", torch.float32, (None, self.dim))
         if out is None:
             out = torch.empty(y.shape[0], dtype=torch.float32, device=y.device)
+        _need(out, "out", torch.float32, (y.shape[0],), y.device.index)
         _check(lib().wob_mlp_forward(self.handle, _dev_ptr(y), y.shape[0], _dev_ptr(out), _stream(stream)),
                "wob_mlp_forward")
         return out
@@ -539,6 +600,7 @@ class MLP:
     def backward(self, y, target, target_map=None, stream=None):
         """target_map: (shift, scale, clip) applied to the targets inside the loss."""
         torch = _torch()
+        self._need_batch(y, target)
         grad = torch.empty(self.n_params, dtype=torch.float32, device=y.device)
         loss = torch.empty(1, dtype=torch.float32, device=y.device)
         _check(lib().wob_mlp_backward(self.handle, _dev_ptr(y), _dev_ptr(target), _tmap(target_map),
@@ -547,10 +609,13 @@ class MLP:
         return loss, grad
 
     def adam_step(self, grad, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        _need(grad, "grad", _torch().float32, (self.n_params,))
         _check(lib().wob_mlp_adam_step(self.handle, _dev_ptr(grad), int(step), lr, b1, b2, eps,
                                        _stream(stream)), "wob_mlp_adam_step")
 
     def train_step(self, y, target, step: int, lr: float, loss=None, target_map=None, stream=None):
+        self._need_batch(y, target)
+        _need(loss, "loss", _torch().float32, (1,), y.device.index, optional=True)
         _check(lib().wob_mlp_train_step(self.handle, _dev_ptr(y), _dev_ptr(target), _tmap(target_map),
                                         y.shape[0], int(step), lr, _dev_ptr(loss), _stream(stream)),
                "wob_mlp_train_step")
@@ -572,8 +637,9 @@ class MLP:
 def sample_boundary(scene: Scene, n: int, seed: int = 0, stream=None):
     """n area-uniform boundary points and their primitive ids (device tensors)."""
     torch = _torch()
-    pts = torch.empty((n, scene.dim), dtype=scene.dtype, device="cuda")
-    prim = torch.empty(n, dtype=torch.int32, device="cuda")
+    dev = torch.device("cuda", scene.device)
+    pts = torch.empty((n, scene.dim), dtype=scene.dtype, device=dev)
+    prim = torch.empty(n, dtype=torch.int32, device=dev)
     _check(lib().wob_sample_boundary(scene.handle, int(n), C.c_uint64(seed), _dev_ptr(pts), _dev_ptr(prim),
                                      _stream(stream)), "wob_sample_boundary")
     return pts, prim
@@ -581,7 +647,7 @@ def sample_boundary(scene: Scene, n: int, seed: int = 0, stream=None):
 
 def cv_table(scene: Scene, net: "MLP", stream=None):
     torch = _torch()
-    g = torch.empty(scene.info()["n_prims"], dtype=torch.float32, device="cuda")
+    g = torch.empty(scene.n_prims, dtype=torch.float32, device=torch.device("cuda", scene.device))
     _check(lib().wob_cv_table(scene.handle, net.handle, _dev_ptr(g), _stream(stream)), "wob_cv_table")
     return g
 
@@ -589,7 +655,8 @@ def cv_table(scene: Scene, net: "MLP", stream=None):
 def cv_emission(scene: Scene, bc: BC, g=None, stream=None):
     """Line-0 table g0 = g + 2 phi s(centroid) (g None = 0)."""
     torch = _torch()
-    g0 = torch.empty(scene.info()["n_prims"], dtype=torch.float32, device="cuda")
+    _need(g, "g", torch.float32, (scene.n_prims,), scene.device, optional=True)
+    g0 = torch.empty(scene.n_prims, dtype=torch.float32, device=torch.device("cuda", scene.device))
     b = bc.c()
     _check(lib().wob_cv_emission(scene.handle, C.byref(b), _dev_ptr(g), _dev_ptr(g0), _stream(stream)),
            "wob_cv_emission")
@@ -599,12 +666,17 @@ def cv_emission(scene: Scene, bc: BC, g=None, stream=None):
 def solve_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed: int = 0,
              point_prim=None, want_var: bool = True, stream=None, out=None, g0=None):
     torch = _torch()
-    P = points.shape[0]
+    P = _need_points(scene, points)
+    _need(point_prim, "point_prim", torch.int32, (P,), scene.device, optional=True)
+    _need(g, "g", torch.float32, (scene.n_prims,), scene.device)
+    _need(g0, "g0", torch.float32, (scene.n_prims,), scene.device, optional=True)
     if out is None:
         mean = torch.empty(P, dtype=scene.dtype, device=points.device)
         var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
     else:
         mean, var = out
+        _need(mean, "mean out", scene.dtype, (P,), scene.device)
+        _need(var, "var out", scene.dtype, (P,), scene.device, optional=True)
     b = bc.c()
     _check(lib().wob_solve_cv(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
                               int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(g0),
@@ -615,7 +687,10 @@ def solve_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed:
 def trace_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed: int = 0,
              point_prim=None, stream=None, g0=None):
     torch = _torch()
-    P = points.shape[0]
+    P = _need_points(scene, points)
+    _need(point_prim, "point_prim", torch.int32, (P,), scene.device, optional=True)
+    _need(g, "g", torch.float32, (scene.n_prims,), scene.device)
+    _need(g0, "g0", torch.float32, (scene.n_prims,), scene.device, optional=True)
     path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
     b = bc.c()
     _check(lib().wob_trace_cv(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
@@ -626,7 +701,9 @@ def trace_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed:
 
 def cv_addback(scene: Scene, g, points, seed: int = 0, stream=None):
     torch = _torch()
-    out = torch.empty(points.shape[0], dtype=scene.dtype, device=points.device)
+    P = _need_points(scene, points)
+    _need(g, "g", torch.float32, (scene.n_prims,), scene.device)
+    out = torch.empty(P, dtype=scene.dtype, device=points.device)
     _check(lib().wob_cv_addback(scene.handle, _dev_ptr(g), _dev_ptr(points), points.shape[0],
                                 C.c_uint64(seed), _dev_ptr(out), _stream(stream)),
            "wob_cv_addback")

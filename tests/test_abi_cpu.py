@@ -77,3 +77,40 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(wob, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(wob.WobError):
         wob.lib()
+
+
+class _StandInScene:
+    """Attributes the binding validates against (no device scene behind it)."""
+    dim, n_prims, device, handle = 3, 10, 0, None
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32
+
+
+@pytest.mark.parametrize("case", ["float64 points", "2-column points", "1-D points", "int64 point_prim",
+                                  "short point_prim", "short mean out", "float64 table", "short table",
+                                  "host tensor"])
+def test_binding_rejects_mismatched_tensors_before_any_call(case):
+    """Every entry point checks dtype, shape and device of its tensors against
+    the scene before it calls into the library (a kernel would read a
+    mismatched array past its end): WobError, and no library call."""
+    torch = pytest.importorskip("torch")
+    sc = _StandInScene()
+    bc = wob.BC(1, wob.AUTO, wob.PROG_CONST, (1.0,))
+    P = 5
+    pts = torch.zeros((P, 3), dtype=torch.float32)
+    calls = {
+        "float64 points": lambda: wob.solve(sc, pts.double(), bc, 8, 2),
+        "2-column points": lambda: wob.trace(sc, pts[:, :2].contiguous(), bc, 8, 2),
+        "1-D points": lambda: wob.solve_grad(sc, pts.reshape(-1), bc, 8, 2),
+        "int64 point_prim": lambda: wob.solve(sc, pts, bc, 8, 2, point_prim=torch.zeros(P, dtype=torch.int64)),
+        "short point_prim": lambda: wob.count_work(sc, pts, bc, 8, 2, point_prim=torch.zeros(P - 1, dtype=torch.int32)),
+        "short mean out": lambda: wob.solve(sc, pts, bc, 8, 2, out=(torch.zeros(P - 1), None)),
+        "float64 table": lambda: wob.solve_cv(sc, pts, bc, 8, 2, g=torch.zeros(10, dtype=torch.float64)),
+        "short table": lambda: wob.cv_addback(sc, torch.zeros(9), pts),
+        "host tensor": lambda: wob.solve(sc, pts, bc, 8, 2),
+    }
+    with pytest.raises(wob.WobError):
+        calls[case]()

@@ -144,11 +144,14 @@ def test_batch_stream_id_follows_oracle(W):
     tr = oracle.trace(om, p["pts"], None, p["obc"], p["walk_len"], p["seed"],
                       np.repeat(np.arange(P), N), np.tile(np.arange(N), P), problem=7, want_pos=False)
     mo = tr["value"].reshape(P, N).mean(axis=1)
-    scale = tr["abs_sum"].reshape(P, N).mean(axis=1)
+    # the mean of N paths is within the mean of their bars (plus the binary32
+    # rounding of the mean itself)
+    tol = PT.tolerance(tr["abs_sum"], tr["err"], PT.RTOL_F32).reshape(P, N).mean(axis=1)
+    # points none of whose paths takes a grazing decision (a point holds N of them)
     ok = (tr["graze"].reshape(P, N) >= PT.GRAZE).all(axis=1)
-    assert ok.mean() > 0.97
+    assert ok.mean() > 0.9
     err = np.abs(m.cpu().double().numpy() - mo)
-    assert np.all(err[ok] <= 2e-5 * scale[ok] + 1e-7)
+    assert np.all(err[ok] <= tol[ok] + PT.U_F32 * np.abs(mo[ok]))
     # and it differs from stream 0
     m0, _ = W.solve(p["scene"], p["points"], p["bc"], p["samples"], p["walk_len"], p["seed"])
     assert not torch.equal(m, m0)
@@ -218,9 +221,9 @@ def test_full_size_batched_sampled(W):
         res = PT.compare_paths(orc, vv.reshape(-1), vprim.cpu().numpy().reshape(-1, L),
                                vm.cpu().numpy().reshape(-1, L), PT.RTOL_F32)
         print(w.name, res.summary(), flush=True)
-        assert res.n_graze <= 0.01 * res.n + 1
-        assert res.n_vertex_mismatch <= 0.002 * res.n_checked + 1
-        assert res.n_value_mismatch <= 0.002 * res.n_checked + 1
+        # meshes of up to 200k triangles: lines that cross many small, distant
+        # primitives take more ill-conditioned hit decisions
+        res.assert_exact(max_graze_frac=0.02)
         checked += res.n_checked
     assert checked > 1000
     b.close()

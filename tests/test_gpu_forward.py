@@ -1,4 +1,4 @@
-"""GPU parity of the forward (adjoint) single-layer estimator (Sec. 4.4,
+"""GPU parity of the forward (adjoint) single-layer estimator (Sec. 4.4.3,
 forward estimator) against the FP64 oracle, through the C ABI.
 
 Paths: every vertex's primitive and hit count must agree for non-grazing
@@ -36,31 +36,31 @@ def _neumann(mesh):
 
 
 def compare_forward(orc, vtx, vp, vm, precision):
-    """Per-path comparison; returns (n, n_graze, n_checked, n_mismatch, worst ratio)."""
+    """Per-path comparison; returns (n, n_graze, n_checked, n_mismatch, worst ratio).
+    Every vertex's primitive and line hit count identical; its position within
+    RTOL (1 + |y|) + KAPPA u P and its strength within RTOL |w| + KAPPA u E_w,
+    P and E_w the oracle's rounding-error bounds of the vertex (its position
+    error propagated along the path; the strength's first factor 2 phi q A / P
+    carries the rounding of q, the steps multiply by the exact +-m)."""
     rtol = PT.RTOL_F32 if precision == "f32" else PT.RTOL_F64
-    cos_ulp = PT.COS_ULP_F32 if precision == "f32" else PT.COS_ULP_F64
     n, M = orc["w"].shape
     dim = orc["pos"].shape[2]
     g_pos = vtx[:, :, :dim]
     g_w = vtx[:, :, 3]
-    graze = orc["graze"] < PT.GRAZE
+    graze = orc["graze"] < PT.graze_for(rtol)
     ok = ~graze
-    cond = np.maximum(orc["cond_cos"], 1e-300)
     vmis = np.any(orc["prim"] != vp, axis=1) | np.any(orc["m"] != vm, axis=1)
-    # strengths: W_1 carries the rounding of q(y_1), A_T and P_T; a flipped
-    # sign is allowed only where |cos| at a hit is within rounding of zero
-    wscale = np.abs(orc["w"]) + 0.05 * np.median(np.abs(orc["w"][orc["w"] != 0]))
     werr = np.abs(g_w - orc["w"])
-    wtol = wscale * (rtol + cos_ulp / cond[:, None])
+    wtol = np.maximum(PT.tolerance(np.abs(orc["w"]), orc["werr"], rtol), 1e-300)
     # positions of live vertices (an ended path's records sit at 1e18 on the GPU)
     perr = np.where(orc["prim"] >= 0, np.linalg.norm(g_pos - orc["pos"], axis=2), 0.0)
-    ptol = (1.0 + np.linalg.norm(orc["pos"], axis=2)) * (rtol + cos_ulp / cond[:, None])
+    ptol = PT.tolerance(1.0 + np.linalg.norm(orc["pos"], axis=2), orc["perr"], rtol)
     bad = vmis | np.any(werr > wtol, axis=1) | np.any(perr > ptol, axis=1)
     ratio = np.where(ok[:, None], np.maximum(werr / wtol, perr / ptol), 0.0)
     return n, int(graze.sum()), int(ok.sum()), int((bad & ok).sum()), float(ratio.max())
 
 
-def run_paths_parity(W, mesh, bc, n_paths, M, seed, precision, weights=None, max_mismatch_frac=0.002):
+def run_paths_parity(W, mesh, bc, n_paths, M, seed, precision, weights=None):
     scene = W.Scene(mesh, W.F32 if precision == "f32" else W.F64)
     starts = None if weights is None else W.Starts(scene, weights)
     wb = W.BC(bc["domain"], 3, bc["program"], tuple(bc["params"]))
@@ -72,7 +72,7 @@ def run_paths_parity(W, mesh, bc, n_paths, M, seed, precision, weights=None, max
                                            vm.cpu().numpy(), precision)
     print(f"paths={n} grazing={ng} checked={nc} mismatch={nm} worst err/tol={worst:.3f}", flush=True)
     assert ng <= 0.01 * n
-    assert nm <= max_mismatch_frac * nc
+    assert nm == 0
     if starts is not None:
         starts.close()
     scene.close()
@@ -109,14 +109,14 @@ def test_forward_paths_parity_2d_f64(W):
     ang = np.arctan2(c.verts[:, 1], c.verts[:, 0])
     mesh = _neumann(I.Mesh(2, c.verts * (1 + 0.1 * np.cos(3 * ang))[:, None], c.prims))
     bc = dict(domain=1, program=oracle.PROG_QUAD, params=())
-    run_paths_parity(W, mesh, bc, 1501, 4, 5, "f64", max_mismatch_frac=0.0)
+    run_paths_parity(W, mesh, bc, 1501, 4, 5, "f64")
 
 
 def test_forward_single_vertex_paths(W):
     """M = 1: no line at all; every record is the start with half its strength."""
     mesh = _neumann(PT.f32_mesh(I.icosphere(6)))
     bc = dict(domain=1, program=oracle.PROG_LINEAR, params=(0.0, 0.0, 1.0, 0.0))
-    orc, vtx = run_paths_parity(W, mesh, bc, 5, 1, 3, "f32", max_mismatch_frac=0.0)
+    orc, vtx = run_paths_parity(W, mesh, bc, 5, 1, 3, "f32")
     assert np.all(orc["m"] == 0)
 
 
@@ -257,7 +257,9 @@ def test_forward_full_size_sampled(W):
     orc = oracle.forward_paths(om, ob, K, M, 99, start_weight=wts)
     res = compare_forward(orc, vtx[:K].cpu().double().numpy(), vp[:K].cpu().numpy(), vm[:K].cpu().numpy(), "f32")
     print("full-size paths", res, flush=True)
-    assert res[1] <= 0.01 * K and res[3] <= 0.002 * res[2]
+    # 200,992 triangles: lines crossing many small, distant primitives take more
+    # ill-conditioned hit decisions (grazing up to 2 %)
+    assert res[1] <= 0.02 * K and res[3] == 0
     assert bool(torch.isfinite(vtx).all())
     # connection at full path count on synthetic records, 16 sampled points
     pos, w = I.forward_records(n_paths, M, 3, 5)

@@ -107,6 +107,26 @@ def test_mlp_gradient_matches_autograd_and_finite_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8, i
 
 
+def test_mlp_gradient_gives_nonfinite_targets_no_weight():
+    """A NaN or infinite target adds nothing to the loss or the gradient (the
+    normalisation stays 1 / n): equal to autograd on the finite rows only."""
+    params, B = rand_net(7)
+    rng = np.random.default_rng(8)
+    y = rng.uniform(-1.5, 1.5, (24, 3))
+    t = rng.standard_normal(24)
+    t[[3, 11]] = np.nan
+    t[17] = np.inf
+    loss, g = oracle.mlp_loss_grad(params, B, y, t, bf16=False)
+    assert np.isfinite(loss) and np.all(np.isfinite(g))
+    keep = np.isfinite(t)
+    p = torch.tensor(params, requires_grad=True)
+    f = torch_mlp(p, B, y[keep])
+    lt = torch.sum((f - torch.as_tensor(t[keep])) ** 2) / len(t)
+    lt.backward()
+    assert loss == pytest.approx(lt.item(), rel=1e-12)
+    np.testing.assert_allclose(g, p.grad.numpy(), rtol=1e-9, atol=1e-12)
+
+
 def test_adam_step_matches_torch():
     rng = np.random.default_rng(7)
     n = 1000

@@ -1,4 +1,4 @@
-"""Pins of the oracle's gradient estimators (Sec. 4.4: the gradient is
+"""Pins of the oracle's gradient estimators (Sec. 4.1.3: the gradient is
 estimated with the same paths, the kernel of the first step replaced by its
 gradient in the evaluation point) against closed forms.
 
