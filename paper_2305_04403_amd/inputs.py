@@ -309,6 +309,58 @@ def slice_grid_inside(res: int, extent: float, amp: float, k_theta: int, k_phi: 
     return p[keep]
 
 
+def slice_grid(res: int, extent: float) -> np.ndarray:
+    """Cell centres of a res x res grid on z = 0 over [-extent, extent]^2."""
+    c = -extent + (np.arange(res) + 0.5) * (2.0 * extent / res)
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), np.zeros(res * res)], axis=1)
+
+
+def inside_star_mesh(mesh: Mesh, pts: np.ndarray) -> np.ndarray:
+    """Exact containment in a closed, outward-oriented triangle mesh that is
+    star-shaped about the origin (every ray from the origin leaves through one
+    triangle, as for a radially perturbed sphere): p is inside when it lies
+    before the plane of the triangle whose cone of directions holds p, which
+    for such a mesh is its winding number.  The cone is found among the
+    triangles around the nearest vertex directions and tested by the signs of
+    det(v_a, v_b, p) over its edges."""
+    from scipy.spatial import cKDTree
+    V = mesh.verts
+    T = mesh.prims.astype(np.int64)
+    U = V / np.linalg.norm(V, axis=1, keepdims=True)
+    # triangles around each vertex, padded with -1
+    inc = [[] for _ in range(len(V))]
+    for t, (a, b, c) in enumerate(T):
+        inc[a].append(t)
+        inc[b].append(t)
+        inc[c].append(t)
+    val = max(len(x) for x in inc)
+    I = -np.ones((len(V), val), dtype=np.int64)
+    for v, x in enumerate(inc):
+        I[v, :len(x)] = x
+    rad = np.linalg.norm(pts, axis=1)
+    d = pts / np.maximum(rad, 1e-300)[:, None]
+    d[rad == 0] = np.array([0.0, 0.0, 1.0])
+    _, nv = cKDTree(U).query(d, k=3)
+    cand = I[nv].reshape(len(pts), -1)                       # (P, 3 * valence)
+    ok = cand >= 0
+    c = np.where(ok, cand, 0)
+    A, B, C = V[T[c, 0]], V[T[c, 1]], V[T[c, 2]]
+    dd = d[:, None, :]
+    s0 = np.einsum("pkd,pkd->pk", np.cross(A, B), dd)
+    s1 = np.einsum("pkd,pkd->pk", np.cross(B, C), dd)
+    s2 = np.einsum("pkd,pkd->pk", np.cross(C, A), dd)
+    inc_cone = ok & (s0 >= 0) & (s1 >= 0) & (s2 >= 0)
+    if not np.all(inc_cone.any(axis=1)):
+        raise ValueError("a direction is in no triangle's cone: the mesh is not star-shaped about 0")
+    k = np.argmax(inc_cone, axis=1)
+    t = c[np.arange(len(pts)), k]
+    n = np.cross(V[T[t, 1]] - V[T[t, 0]], V[T[t, 2]] - V[T[t, 0]])
+    # the ray x = s d meets the plane at s = (v0 . n) / (d . n)
+    s = np.einsum("pd,pd->p", V[T[t, 0]], n) / np.einsum("pd,pd->p", d, n)
+    return rad < s
+
+
 def mesh_surface_points(mesh: Mesh, n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
     """Area-uniform points on a triangle mesh; returns (points, primitive ids)."""
     rng = np.random.default_rng(seed)
@@ -380,12 +432,11 @@ def config_circle(n_points: int = 1024, samples: int = 64, walk_len: int = 4) ->
 def config_icosphere_slice(res: int = 512, samples: int = 256, walk_len: int = 6,
                            freq: int = 32) -> Workload:
     """3D interior Dirichlet on a 20 freq^2-triangle icosphere perturbed to
-    r = 1 + 0.1 sin(3 theta) sin(4 phi); g = 1/|x - x0|, x0 = (2, 0.5, 0); the
-    cell centres of a res x res grid on z = 0 over [-1.1, 1.1]^2 that lie at
-    least 0.01 inside the smooth surface; FP32."""
-    mesh = perturb_radial(icosphere(freq), 0.1, 3, 4)
-    pts = slice_grid_inside(res, 1.1, 0.1, 3, 4, 0.01)
-    mesh, pts = _round(mesh, pts, "f32")
+    r = 1 + 0.1 sin(3 theta) sin(4 phi); g = 1/|x - x0|, x0 = (2, 0.5, 0); every
+    cell centre of a res x res grid on z = 0 over [-1.1, 1.1]^2 inside the mesh
+    (exact containment in the binary32 mesh, ``inside_star_mesh``); FP32."""
+    mesh, pts = _round(perturb_radial(icosphere(freq), 0.1, 3, 4), slice_grid(res, 1.1), "f32")
+    pts = pts[inside_star_mesh(mesh, pts)]
     x0 = (2.0, 0.5, 0.0)
     exact = 1.0 / np.linalg.norm(pts - np.array(x0), axis=1)
     return Workload(f"icosphere{20 * freq * freq}-slice{res}-dirichlet-f32", mesh, pts, None,
