@@ -52,7 +52,8 @@ typedef enum {
   WOB_E_ALLOC = 2,       /* device or host allocation failed */
   WOB_E_DEVICE = 3,      /* HIP runtime error (no device, launch failure, copy failure) */
   WOB_E_MESH = 4,        /* index out of range, zero-length / zero-area primitive, non-finite vertex */
-  WOB_E_UNSUPPORTED = 5  /* a combination this library does not implement */
+  WOB_E_UNSUPPORTED = 5, /* a combination this library does not implement */
+  WOB_E_TOO_LARGE = 6    /* beyond the fixed capacity of an allocation-free entry point */
 } wob_status;
 
 /* Boundary-condition kind per primitive (eq. PoissonBC). */
@@ -405,6 +406,24 @@ void wob_batch_free(wob_batch batch);
 /* One-shot: create, launch, wait on `stream`, free. */
 wob_status wob_solve_batched(const wob_problem* problems, int32_t n_problems,
                              const wob_tune* tune, void* stream);
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): wob_solve_batched without any device
+ * allocation.  The problem table, the tile offsets and the tile counter live
+ * in a fixed, file-scope device array of the library (one per device, about
+ * WOB_STATIC_MAX_PROBLEMS * 0.5 KB, held until the process ends), so at most
+ * WOB_STATIC_MAX_PROBLEMS problems per call (more: WOB_E_TOO_LARGE, nothing
+ * launched).  Same problems, tune and results as wob_solve_batched (bitwise:
+ * the same kernel and launch shape; tune NULL = 256 lanes x 4 per CU, or the
+ * same fallback); no autotuning and no graph.  The table is copied from host
+ * memory the call owns, so the call waits for `stream` before it returns.
+ * Every call on a device shares that device's array and overwrites it (the
+ * counter is reset by a kernel each call): calls that overlap on one device,
+ * from several threads or on several streams, race and must be serialised by
+ * the caller.  Errors: as wob_batch_create, and WOB_E_TOO_LARGE. */
+#define WOB_STATIC_MAX_PROBLEMS 256
+wob_status wob_solve_batched_static(const wob_problem* problems, int32_t n_problems,
+                                    const wob_tune* tune, void* stream);
 
 /* ------------------------------------------------------------------------- */
 /* Learned control variate (not in the paper; an exact control variate for   */

@@ -314,6 +314,7 @@ const char* wob_status_string(wob_status s) {
     case WOB_E_DEVICE: return "HIP runtime error";
     case WOB_E_MESH: return "invalid mesh";
     case WOB_E_UNSUPPORTED: return "unsupported combination";
+    case WOB_E_TOO_LARGE: return "beyond the capacity of an allocation-free entry point";
   }
   return "unknown status";
 }

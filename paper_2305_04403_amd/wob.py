@@ -26,7 +26,8 @@ SAMPLE_LINE, SAMPLE_RIS = 0, 1
 EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_path", "wob_solve",
             "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string",
             "wob_batch_create", "wob_batch_launch", "wob_batch_autotune", "wob_batch_get_tune",
-            "wob_batch_free", "wob_solve_batched", "wob_mlp_n_params", "wob_mlp_create",
+            "wob_batch_free", "wob_solve_batched", "wob_solve_batched_static", "wob_mlp_n_params",
+            "wob_mlp_create",
             "wob_mlp_free", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
             "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
             "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary",
@@ -102,8 +103,9 @@ def lib():
     L.wob_batch_free.argtypes = [vp]
     L.wob_batch_free.restype = None
     L.wob_solve_batched.argtypes = [C.POINTER(_Problem), i32, C.POINTER(_Tune), vp]
+    L.wob_solve_batched_static.argtypes = [C.POINTER(_Problem), i32, C.POINTER(_Tune), vp]
     for name in ("wob_batch_create", "wob_batch_launch", "wob_batch_autotune",
-                 "wob_batch_get_tune", "wob_solve_batched"):
+                 "wob_batch_get_tune", "wob_solve_batched", "wob_solve_batched_static"):
         getattr(L, name).restype = C.c_int
     L.wob_mlp_n_params.argtypes = []
     L.wob_mlp_n_params.restype = i64
@@ -554,6 +556,59 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _problem_table(problems):
+    """ctypes problem array for the batched entry points (outputs: the dicts'
+    "mean_out" / "var_out" tensors, allocated here when absent)."""
+    torch = _torch()
+    arr = (_Problem * len(problems))()
+    outs, keep = [], []
+    for i, p in enumerate(problems):
+        scene, pts = p["scene"], p["points"]
+        P = _need_points(scene, pts, f"problem {i} points")
+        pp = p.get("point_prim")
+        _need(pp, f"problem {i} point_prim", torch.int32, (P,), scene.device, optional=True)
+        mean = p.get("mean_out")
+        var = p.get("var_out")
+        if mean is None:
+            mean = torch.empty(P, dtype=scene.dtype, device=pts.device)
+            if var is None and p.get("want_var", True):
+                var = torch.empty(P, dtype=scene.dtype, device=pts.device)
+        _need(mean, f"problem {i} mean_out", scene.dtype, (P,), scene.device)
+        _need(var, f"problem {i} var_out", scene.dtype, (P,), scene.device, optional=True)
+        keep += [scene, pts, pp, mean, var]
+        outs.append((mean, var))
+        arr[i].scene = scene.handle
+        arr[i].points = _dev_ptr(pts)
+        arr[i].point_prim = _dev_ptr(pp)
+        arr[i].n_points = P
+        arr[i].bc = p["bc"].c()
+        arr[i].samples = int(p["samples"])
+        arr[i].walk_len = int(p["walk_len"])
+        arr[i].seed = int(p.get("seed", 0))
+        arr[i].stream_id = int(p.get("stream_id", 0))
+        arr[i].reserved = 0
+        arr[i].mean_out = _dev_ptr(mean)
+        arr[i].var_out = _dev_ptr(var)
+    return arr, outs, keep
+
+
+def solve_batched(problems, tune=None, stream=None, no_alloc: bool = False):
+    """One-shot batched solve (``wob_solve_batched``), or with ``no_alloc``
+    ``wob_solve_batched_static``, which allocates no device memory (at most
+    ``STATIC_MAX_PROBLEMS`` problems).  Problems as for :class:`Batch`, plus
+    optional caller-owned "mean_out" / "var_out" tensors.  Returns the
+    per-problem (mean, var) outputs; waits for the stream."""
+    arr, outs, _keep = _problem_table(problems)
+    t = None if tune is None else C.byref(_Tune(*tune))
+    fn = lib().wob_solve_batched_static if no_alloc else lib().wob_solve_batched
+    _check(fn(arr, len(problems), t, _stream(stream)),
+           "wob_solve_batched_static" if no_alloc else "wob_solve_batched")
+    return outs
+
+
+STATIC_MAX_PROBLEMS = 256
 
 
 class MLP:
