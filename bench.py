@@ -1,9 +1,10 @@
 """Walk-on-boundary throughput on one MI355X.
 
-Workload: 3D interior Dirichlet problem on a 20,480-triangle icosphere radially
-perturbed to r = 1 + 0.1 sin(3 theta) sin(4 phi), data g = 1/|x - x0| with
-x0 = (2, 0.5, 0), evaluated at the cells of a 512 x 512 slice z = 0 that lie
-inside (167,604 points), 256 paths per point, path length 6, FP32.
+Headline workload (the largest single-GPU configuration): 3D exterior mixed
+Neumann / Robin problem (Robin coefficient 1) on the 200,992-triangle union of
+three tori (R = 1, r = 0.3, random rotations), data from a point source inside
+the tori; 1,000,000 evaluation points, 10 % of them on the boundary; 512 paths
+per point, path length 4; single-layer formulation with line sampling, FP32.
 
 One step = one wob_solve over every point (direction sampling, all-hits BVH
 traversal, hit selection, weights, emission and the per-point mean / variance
@@ -11,20 +12,24 @@ reduction, all in one kernel).  The scene (BVH) is built once before timing, as
 a model's weights would be; inputs are resident in device memory.
 
 Prints one JSON line: path samples/s (value), lines/s, the roofline record of
-the walk kernel and the FP64 oracle timed on a bounded sample on host cores.
-Two more legs are reported in the same line (each with its own timing):
+the walk kernel (vector-ALU and vector-memory roofs, HBM traffic) and the FP64
+oracle timed on a bounded sample on host cores.  More legs in the same line,
+each with its own timing and roofline record:
+  slice     - 3D interior Dirichlet, 20,480-triangle perturbed icosphere,
+              every cell of a 512 x 512 slice inside it, 256 paths, M = 6;
+  circle    - 2D interior Dirichlet, 256-segment circle, 1,024 points, 64
+              paths, M = 4, FP64;
   batched   - 64 problems of uneven size (2k-200k triangles, 1k-256k points,
               128-1024 paths, Dirichlet and exterior Neumann) in one persistent
               launch replayed from a hipGraph, launch shape autotuned;
-  cv        - exterior Neumann / Robin single layer on a 200,992-triangle
-              union of three tori, 1M points: RMSE against the analytic
-              solution at equal wall time, plain WoB with 512 paths against
-              the learned control variate (fit + corrected solve);
+  cv        - the headline workload: RMSE against the analytic solution at
+              equal wall time, plain WoB with 512 paths against the learned
+              control variate (fit + corrected solve) and RIS;
   forward   - exterior Neumann data concentrated near one spot of the same
               tori: the forward (adjoint) estimator with every point connected
               to every path vertex against the backward walks at equal wall
               time, and the throughput of its two kernels;
-  grad      - value and gradient along the same paths on the main workload:
+  grad      - value and gradient along the same paths on the slice workload:
               cost relative to the value alone, gradient error.
 """
 import argparse
@@ -38,10 +43,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published fp32 vector peak (256 CUs at 2.4 GHz; counts an FMA as two
-# operations and includes packed math, which this build does not use, so one
-# half of it is the attainable issue rate)
+# MI355X published vector peaks (256 CUs at 2.4 GHz; an FMA counts as two
+# operations; the fp32 figure includes packed math, which this build does not
+# use, so one half of it is the attainable issue rate)
 FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+CU_CLOCKS_PER_S = 256 * 2.4e9
 # algorithmic operations of the traversal: a visited interior node tests the
 # boxes of its two children, each slab test (near / far sides ordered by the
 # direction's signs, fixed per line) 6 FMA (12), 2 three-way max / min (4) and
@@ -53,25 +60,34 @@ NODE_FLOP, TRI_FLOP = 2 * 17, 43
 # values, 24 B) and entries (2 x 4 B); a tested triangle is v0, e1, e2
 # (9 x 4 B); a hit also reads id, kind and alpha (12 B)
 NODE_BYTES, TRI_BYTES, HIT_BYTES = 32, 36, 12
-
+# bytes the kernel loads through the vector memory path: an interior record is
+# 32 B (two 16-byte loads), a tested triangle 48 B of its 64-byte record (three
+# loads), and each line's path step re-reads the kept hit's triangle and normal
+# (48 + 16 B)
+NODE_LOAD_BYTES, TRI_LOAD_BYTES, STEP_LOAD_BYTES = 32, 48, 64
 
 KERNEL_SOURCES = ("paper_2305_04403_amd/csrc/device.hpp", "paper_2305_04403_amd/csrc/walk.hpp",
                   "paper_2305_04403_amd/csrc/internal.hpp", "paper_2305_04403_amd/csrc/wob.hip")
-TRAFFIC_PROFILE = "profiles/walk_kernel_icosphere20480_slice512_traffic.md"
+# counter summaries (FETCH_SIZE, WRITE_SIZE) of each leg's walk kernel
+TRAFFIC_PROFILES = {
+    "tori": "profiles/walk_kernel_tori200992_1M_points_traffic.md",
+    "slice": "profiles/walk_kernel_icosphere20480_slice512_traffic.md",
+}
 
 
-def measured_traffic():
+def measured_traffic(leg: str):
     """HBM bytes per launch (FETCH + WRITE, calibrated) from the committed
-    counter summary, or None when the kernel sources changed since it was taken."""
+    counter summary of a leg's walk kernel, or None when the kernel sources
+    changed since it was taken."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     try:
-        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as fh:
+        with open(os.path.join(ROOT, TRAFFIC_PROFILES[leg])) as fh:
             text = fh.read()
-    except OSError:
+    except (OSError, KeyError):
         return None
     rec = dict(line.strip().split(": ", 1) for line in text.splitlines()
                if line.strip().startswith(("source-sha256-prefix:", "traffic-bytes-per-launch:")))
@@ -82,15 +98,74 @@ def measured_traffic():
     return fetch + write
 
 
+def walk_roofline(cnt, kern_s, cal, fp64=False, traffic=None):
+    """Roofline record of one walk kernel from its work counters and average
+    launch time.  roofline: algorithmic vector-ALU operations per second
+    against the published vector peak (the traversal is not a contraction: no
+    MFMA).  vector_memory: the bytes the kernel loads per second (node and
+    triangle records, path-step re-reads) against the rate at which the CUs'
+    vector memory path serves random 32-byte records held in L1 (the library's
+    gather probe, 32 KiB working set, same run): the ceiling of record loads
+    whatever level holds the scene.  hbm: the measured HBM traffic (committed
+    counter summary) over the launch time, against 8 TB/s."""
+    lines, nodes, prims, hits = cnt["lines"], cnt["nodes"], cnt["prims"], cnt["hits"]
+    alg_flop = nodes * NODE_FLOP + prims * TRI_FLOP
+    alg_bytes = nodes * NODE_BYTES + prims * TRI_BYTES + hits * HIT_BYTES
+    peak = FP64_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS
+    achieved = alg_flop / kern_s / 1e12
+    loads = nodes * NODE_LOAD_BYTES + prims * TRI_LOAD_BYTES + lines * STEP_LOAD_BYTES
+    vm = loads / kern_s / 1e9
+    out = {
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic},
+        "vector_memory": {"achieved": vm, "peak": cal["32KiB"], "unit": "GB/s", "frac": vm / cal["32KiB"],
+                          "bytes_per_line": loads / lines,
+                          "records_per_clk_per_cu": (nodes + prims + lines) / kern_s / CU_CLOCKS_PER_S,
+                          "ceiling": "random 32-byte records from an L1-resident buffer (gather probe, 32 KiB)"},
+        "work_per_line": {"interior_nodes": nodes / lines, "box_tests": 2 * nodes / lines,
+                          "triangles": prims / lines, "hits": hits / lines},
+        "algorithmic_flop_per_launch": alg_flop,
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "algorithmic_GB/s": alg_bytes / kern_s / 1e9,
+    }
+    if traffic is not None:
+        out["hbm"] = {"achieved": traffic / kern_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                      "frac": traffic / kern_s / 8e12}
+    return out
+
+
+def time_solve(torch, wob, scene, pts, pp, bc, N, M, seed, steps, warmup):
+    """Warm-up, then `steps` solves bracketed by HIP events on the stream the
+    kernel runs on; returns (wall seconds per step, average kernel seconds,
+    mean, var)."""
+    P = pts.shape[0]
+    mean = torch.empty(P, dtype=scene.dtype, device="cuda")
+    var = torch.empty(P, dtype=scene.dtype, device="cuda")
+    for _ in range(warmup):
+        wob.solve(scene, pts, bc, N, M, seed, point_prim=pp, out=(mean, var))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[2 * k].record(stream)
+        wob.solve(scene, pts, bc, N, M, seed, point_prim=pp, out=(mean, var))
+        ev[2 * k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    kern = 1e-3 * float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps)]))
+    return wall, kern, mean, var
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--cpu-sample-points", type=int, default=640)
+    p.add_argument("--cpu-sample-points", type=int, default=16)
     p.add_argument("--skip-cpu-baseline", action="store_true")
-    p.add_argument("--legs", default="main,batched,cv,forward,grad",
-                   help="comma-separated subset of main, batched, cv, forward, grad")
+    p.add_argument("--legs", default="main,slice,circle,batched,cv,forward,grad",
+                   help="comma-separated subset of main, slice, circle, batched, cv, forward, grad")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device once (a kernel of known "
                         "traffic that calibrates hardware byte counters)")
@@ -102,18 +177,49 @@ def cpu_baseline(w, n_points):
     om = oracle.OracleMesh(w.mesh)
     bc = oracle.make_bc(w.bc["domain"], w.bc["formulation"], w.bc["program"], w.bc["params"])
     idx = np.linspace(0, w.points.shape[0] - 1, n_points).astype(np.int64)
+    pp = None if w.point_prim is None else w.point_prim[idx]
     threads = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    oracle.solve(om, w.points[idx], None, bc, w.samples, w.walk_len, w.seed, n_threads=threads)
+    oracle.solve(om, w.points[idx], pp, bc, w.samples, w.walk_len, w.seed, n_threads=threads)
     dt = time.perf_counter() - t0
     paths = n_points * w.samples
     return {"value": paths / dt, "unit": "path samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_points} evenly spaced points of the same workload x {w.samples} paths x "
-                      f"{w.walk_len} lines, brute force over all {w.mesh.n_prims} triangles, FP64; "
+            "sample": f"{n_points} evenly spaced points of the same workload ("
+                      f"{0 if pp is None else int((pp >= 0).sum())} on the boundary) x {w.samples} paths x "
+                      f"{w.walk_len} lines, brute force over all {w.mesh.n_prims} primitives, FP64; "
                       f"{dt:.1f} s"}
 
 
-def batched_leg(torch, wob, I, steps=2):
+def timed_leg(torch, wob, w, steps, warmup, cal, leg=None, fp64=False):
+    """A single-problem workload: solve timing, work counters of exactly the
+    timed paths, roofline record, RMSE against the analytic solution."""
+    scene = wob.Scene(w.mesh, wob.F64 if fp64 else wob.F32)
+    info = scene.info()
+    bc = wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"]))
+    dt = torch.float64 if fp64 else torch.float32
+    pts = torch.as_tensor(w.points, dtype=dt, device="cuda")
+    pp = None if w.point_prim is None else torch.as_tensor(w.point_prim, dtype=torch.int32, device="cuda")
+    P, N, M = pts.shape[0], w.samples, w.walk_len
+    cnt = wob.count_work(scene, pts, bc, N, M, w.seed, point_prim=pp)
+    wall, kern, mean, var = time_solve(torch, wob, scene, pts, pp, bc, N, M, w.seed, steps, warmup)
+    m = mean.double().cpu().numpy()
+    ok = np.isfinite(m)
+    out = {"workload": w.name, "points": P, "paths_per_point": N, "walk_len": M,
+           "primitives": w.mesh.n_prims, "value": P * N / wall, "unit": "path samples/s",
+           "ms_per_step": 1e3 * wall, "kernel_ms": 1e3 * kern, "steps": steps,
+           "lines_per_s": cnt["lines"] / wall,
+           "rmse_vs_analytic": float(np.sqrt(np.mean((m[ok] - w.exact[ok]) ** 2))),
+           "median_abs_err": float(np.median(np.abs(m[ok] - w.exact[ok]))),
+           "mean_se": float(np.mean(np.sqrt(var.double().cpu().numpy()[ok] / N))),
+           "nonfinite_points": int((~ok).sum()),
+           "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")}}
+    out.update(walk_roofline(cnt, kern, cal, fp64=fp64,
+                             traffic=measured_traffic(leg) if leg else None))
+    scene.close()
+    return out
+
+
+def batched_leg(torch, wob, I, cal, steps=2):
     from concurrent.futures import ThreadPoolExecutor
     ws = I.config_batched()
     t0 = time.perf_counter()
@@ -143,6 +249,16 @@ def batched_leg(torch, wob, I, steps=2):
         rel.append(float(np.sqrt(np.mean((mm - w.exact) ** 2)) / np.sqrt(np.mean(w.exact ** 2))))
     (blk, bpc), n_tiles = b.tune()
     b.close()
+    # work per line of every problem (its points with 8 paths each: the same
+    # line statistics), scaled to the problem's lines
+    cnt = {"lines": 0, "nodes": 0.0, "prims": 0.0, "hits": 0.0}
+    for w, p in zip(ws, probs):
+        c = wob.count_work(p["scene"], p["points"], p["bc"], 8, w.walk_len, w.seed)
+        n_lines = w.points.shape[0] * w.samples * (w.walk_len + (1 if w.bc["formulation"] == 2 else 0))
+        cnt["lines"] += n_lines
+        for k in ("nodes", "prims", "hits"):
+            cnt[k] += c[k] * n_lines / c["lines"]
+    roof = walk_roofline(cnt, dt, cal)
     for s in scenes:
         s.close()
     return {"workload": "64 perturbed spheres, 2k-200k triangles (sum %d), %d points, 128-1024 paths, M=4, "
@@ -151,7 +267,7 @@ def batched_leg(torch, wob, I, steps=2):
             "value": paths / dt, "unit": "path samples/s", "ms_per_launch": 1e3 * dt, "lines_per_s": lines / dt,
             "paths": paths, "tiles": n_tiles, "launch": "persistent, hipGraph replay",
             "autotuned": {"block": blk, "blocks_per_cu": bpc, "tune_s": t_tune},
-            "bvh_build_s": t_build, "median_relative_rmse_vs_analytic": float(np.median(rel))}
+            "bvh_build_s": t_build, "median_relative_rmse_vs_analytic": float(np.median(rel)), **roof}
 
 
 def cv_leg(torch, wob, I):
@@ -472,90 +588,55 @@ def main():
 
     torch.cuda.set_device(0)
     legs = set(args.legs.split(","))
+    cal = gather_calibration(torch, wob)
     extra = {}
-    for leg, key, fn in (("batched", "batched", batched_leg), ("cv", "cv_equal_time", cv_leg),
-                         ("forward", "forward_equal_time", forward_leg), ("grad", "gradient", grad_leg)):
-        if leg in legs:
+
+    def leg(name, key, fn):
+        if name in legs:
             t0 = time.perf_counter()
-            extra[key] = fn(torch, wob, I)
-            print(f"[bench] {leg} leg done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    w = I.config_icosphere_slice()
-    scene = wob.Scene(w.mesh, wob.F32)
-    info = scene.info()
-    bc = wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"]))
-    pts = torch.as_tensor(w.points, dtype=torch.float32, device="cuda")
-    P, N, M = pts.shape[0], w.samples, w.walk_len
-    mean = torch.empty(P, dtype=torch.float32, device="cuda")
-    var = torch.empty(P, dtype=torch.float32, device="cuda")
+            extra[key] = fn()
+            print(f"[bench] {name} leg done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
-    # work counters of exactly the timed solve (same seed, same paths)
-    cnt = wob.count_work(scene, pts, bc, N, M, w.seed)
+    leg("slice", "slice", lambda: timed_leg(torch, wob, I.config_icosphere_slice(), max(3, args.steps // 4), 1,
+                                            cal, leg="slice"))
+    leg("circle", "circle", lambda: timed_leg(torch, wob, I.config_circle(), 20, 3, cal, fp64=True))
+    leg("batched", "batched", lambda: batched_leg(torch, wob, I, cal))
+    leg("cv", "cv_equal_time", lambda: cv_leg(torch, wob, I))
+    leg("forward", "forward_equal_time", lambda: forward_leg(torch, wob, I))
+    leg("grad", "gradient", lambda: grad_leg(torch, wob, I))
 
-    for _ in range(args.warmup):
-        wob.solve(scene, pts, bc, N, M, w.seed, out=(mean, var))
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[2 * k].record(stream)
-        wob.solve(scene, pts, bc, N, M, w.seed, out=(mean, var))
-        ev[2 * k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]
-    ms_step = 1e3 * wall / args.steps
-    avg_kern_s = 1e-3 * float(np.mean(kern_ms))
-
-    paths = P * N
-    value = paths * args.steps / wall
-    lines = cnt["lines"]
-    alg_bytes = cnt["nodes"] * NODE_BYTES + cnt["prims"] * TRI_BYTES + cnt["hits"] * HIT_BYTES
-    alg_flop = cnt["nodes"] * NODE_FLOP + cnt["prims"] * TRI_FLOP
-    achieved = alg_flop / avg_kern_s / 1e12
-    m = mean.double().cpu().numpy()
-    se = np.sqrt(var.double().cpu().numpy() / N)
-    rmse = float(np.sqrt(np.mean((m - w.exact) ** 2)))
-
+    # the headline: the three-tori workload
+    w = I.config_tori()
+    main_rec = timed_leg(torch, wob, w, args.steps, args.warmup, cal, leg="tori") if "main" in legs else None
+    if main_rec is None:
+        print(json.dumps({"legs": extra, "gather_calibration_GB/s": cal}))
+        return
+    print(f"[bench] main done: {main_rec['value'] / 1e6:.1f} M path samples/s", file=sys.stderr, flush=True)
     rec = {
         "metric": "WoB path samples/s at 1 GPU",
-        "value": value,
+        "value": main_rec["value"],
         "unit": "path samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main_rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "points": P, "paths_per_point": N, "walk_len": M,
-                   "triangles": w.mesh.n_prims, "formulation": "double layer (interior Dirichlet)",
+        "config": {"workload": w.name, "points": main_rec["points"],
+                   "boundary_points": int((w.point_prim >= 0).sum()),
+                   "paths_per_point": w.samples, "walk_len": w.walk_len, "triangles": w.mesh.n_prims,
+                   "formulation": "single layer, line sampling (exterior Neumann / Robin)",
                    "parallelism": "none (1 GPU)"},
-        "lines_per_s": lines * args.steps / wall,
-        "work_per_line": {"interior_nodes": cnt["nodes"] / lines, "box_tests": 2 * cnt["nodes"] / lines,
-                          "triangles": cnt["prims"] / lines,
-                          "hits": cnt["hits"] / lines},
-        "kernel_ms": float(np.mean(kern_ms)),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic()},
-        "algorithmic_flop_per_launch": alg_flop,
-        "gather": {"bytes_per_launch": alg_bytes, "GB/s": alg_bytes / avg_kern_s / 1e9,
-                   "note": "node, triangle and hit records the traversal reads; served by L2 (scene 2.2 MB)"},
-        "rmse_vs_analytic": rmse,
-        "mean_se": float(np.mean(se)),
-        "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")},
     }
-    cal = gather_calibration(torch, wob)
-    rec["gather"]["calibrated_random_32B_GB/s"] = cal
-    # records the traversal reads per second (interior nodes, triangles, hits)
-    # against the rate of random 32-byte records from an L2-resident buffer;
-    # above 1: the upper tree levels, shared by all lanes, stay in the CU caches
-    recs = (cnt["nodes"] + cnt["prims"] + cnt["hits"]) / avg_kern_s
-    rec["gather"]["records_per_s"] = recs
-    rec["gather"]["ratio_to_random_2MiB_records"] = recs / (cal["2MiB"] * 1e9 / 32)
+    for k in ("lines_per_s", "kernel_ms", "roofline", "vector_memory", "hbm", "work_per_line",
+              "algorithmic_flop_per_launch", "algorithmic_bytes_per_launch", "algorithmic_GB/s",
+              "rmse_vs_analytic", "median_abs_err", "mean_se", "nonfinite_points", "scene"):
+        if k in main_rec:
+            rec[k] = main_rec[k]
+    rec["gather_calibration_GB/s"] = cal
     rec.update(extra)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -567,7 +648,6 @@ def main():
         rec["copy_probe_bytes"] = 4 * n
     if not args.skip_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_points)
-    scene.close()
     print(json.dumps(rec))
 
 
