@@ -49,22 +49,23 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 CU_CLOCKS_PER_S = 256 * 2.4e9
-# algorithmic operations of the traversal: a visited interior node tests the
-# boxes of its two children, each slab test (near / far sides ordered by the
-# direction's signs, fixed per line) 6 FMA (12), 2 three-way max / min (4) and
-# one compare = 17; a tested triangle (numerator form of Moller-Trumbore, a
-# miss) is two cross products (18), three dots (15), x - v0 (3), three sign
-# products and four compares = 43
-NODE_FLOP, TRI_FLOP = 2 * 17, 43
-# algorithmic bytes: an interior node is its children's boxes (12 binary16
-# values, 24 B) and entries (2 x 4 B); a tested triangle is v0, e1, e2
+# algorithmic operations of the traversal: a visited interior record tests the
+# boxes of its four children (4-wide records), each slab test (near / far sides
+# ordered by the direction's signs, fixed per line) 6 FMA (12), 2 three-way
+# max / min (4) and one compare = 17; a tested triangle (numerator form of
+# Moller-Trumbore, a miss) is two cross products (18), three dots (15), x - v0
+# (3), three sign products and four compares = 43
+BOX_TESTS_PER_NODE = 4
+NODE_FLOP, TRI_FLOP = BOX_TESTS_PER_NODE * 17, 43
+# algorithmic bytes: an interior record is its children's boxes (4 x 6 binary16
+# values, 48 B) and entries (4 x 4 B); a tested triangle is v0, e1, e2
 # (9 x 4 B); a hit also reads id, kind and alpha (12 B)
-NODE_BYTES, TRI_BYTES, HIT_BYTES = 32, 36, 12
+NODE_BYTES, TRI_BYTES, HIT_BYTES = 64, 36, 12
 # bytes the kernel loads through the vector memory path: an interior record is
-# 32 B (two 16-byte loads), a tested triangle 48 B of its 64-byte record (three
+# 64 B (four 16-byte loads), a tested triangle 48 B of its 64-byte record (three
 # loads), and each line's path step re-reads the kept hit's triangle and normal
 # (48 + 16 B)
-NODE_LOAD_BYTES, TRI_LOAD_BYTES, STEP_LOAD_BYTES = 32, 48, 64
+NODE_LOAD_BYTES, TRI_LOAD_BYTES, STEP_LOAD_BYTES = 64, 48, 64
 
 KERNEL_SOURCES = ("paper_2305_04403_amd/csrc/device.hpp", "paper_2305_04403_amd/csrc/walk.hpp",
                   "paper_2305_04403_amd/csrc/internal.hpp", "paper_2305_04403_amd/csrc/wob.hip")
@@ -122,7 +123,7 @@ def walk_roofline(cnt, kern_s, cal, fp64=False, traffic=None):
                           "bytes_per_line": loads / lines,
                           "records_per_clk_per_cu": (nodes + prims + lines) / kern_s / CU_CLOCKS_PER_S,
                           "ceiling": "random 32-byte records from an L1-resident buffer (gather probe, 32 KiB)"},
-        "work_per_line": {"interior_nodes": nodes / lines, "box_tests": 2 * nodes / lines,
+        "work_per_line": {"interior_records": nodes / lines, "box_tests": BOX_TESTS_PER_NODE * nodes / lines,
                           "triangles": prims / lines, "hits": hits / lines},
         "algorithmic_flop_per_launch": alg_flop,
         "algorithmic_bytes_per_launch": alg_bytes,

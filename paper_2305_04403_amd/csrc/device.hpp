@@ -23,32 +23,36 @@ enum Program { P_CONST = 0, P_LINEAR = 1, P_QUAD = 2, P_INVDIST = 3 };
 // Scene records.  Primitives are stored in BVH leaf order.  idkind packs the
 // caller's primitive id (bits 0..28) and its boundary kind (bits 29..30).
 // --------------------------------------------------------------------------
-// The BVH is stored as its interior nodes, each record holding the boxes of
-// both children and their entries: one record tests two boxes.  The traversal
-// is bound by the rate at which the CUs' vector memory path serves the lanes'
-// gathers, so records are kept to two 16-byte loads: in an FP32 scene the
-// boxes are binary16 in a normalised frame (scene centre c, power-of-two scale
-// k, y' = (y - c) k in [-1, 1]), rounded outward, and the slab test reads them
-// with mixed-precision FMAs.  A child entry is the index of an interior record
-// (>= 0) or a leaf, -1 - ((first << 3) | (count - 1)) with first the
-// leaf-order index of its first primitive (< 2^27).
-template <typename R> struct alignas(32) Inner3 { R lo0[3], hi0[3], lo1[3], hi1[3]; int32_t child[2]; };
-template <typename R> struct alignas(32) Inner2 { R lo0[2], hi0[2], lo1[2], hi1[2]; int32_t child[2]; };
+// The BVH is stored as 4-wide interior records: the host collapses the binary
+// SAH tree (a record takes its node's two children and opens the largest
+// interior ones until it holds four entries), so a line takes half the
+// dependent record fetches of a binary tree and one record is one 64-byte
+// line.  The traversal is bound by the rate at which the CUs' vector memory
+// path serves the lanes' gathers, so records are kept small: in an FP32 scene
+// the boxes are binary16 in a normalised frame (scene centre c, power-of-two
+// scale k, y' = (y - c) k in [-1, 1]), rounded outward, and the slab test
+// reads them with mixed-precision FMAs.  A child entry is the index of an
+// interior record (>= 0) or a leaf, -1 - ((first << 3) | (count - 1)) with
+// first the leaf-order index of its first primitive (< 2^27).  Unused slots
+// hold an empty box (lo > hi), which no line crosses.
+constexpr int kArity = 4;
+template <typename R> struct alignas(32) Wide { R lo[kArity][3], hi[kArity][3]; int32_t child[kArity]; };
 // FP32 scenes: one word per box and axis, binary16 lo in the low half and hi
 // in the high half.  A lane rotates each word by 16 bits when its direction is
 // negative on that axis, so the low half is the slab's near side and the high
-// half its far side without a min / max per axis.
-template <> struct alignas(32) Inner3<float> { uint32_t box0[3], box1[3]; int32_t child[2]; };
-template <> struct alignas(32) Inner2<float> { uint32_t box0[2], box1[2]; int32_t child[2]; };
+// half its far side without a min / max per axis.  (2D scenes leave the third
+// axis word unused.)
+template <> struct alignas(64) Wide<float> { uint32_t box[kArity][3]; int32_t child[kArity]; };
 // Traversal positions besides entries: take the next entry from the stack,
 // and the line's traversal is over.
 constexpr int32_t kPop = INT32_MIN;
 constexpr int32_t kDone = INT32_MAX;
-// Bound on the traversal stack (the builder's trees have at most 32 SAH
-// levels, then at most 26 halvings of fewer than 2^27 primitives, and the
-// stack holds at most one entry per level below the root): with the leaf
-// queue a lane's LDS stays within 64 entries, a 256-thread workgroup's within
-// 64 KB.
+// Bound on the traversal stack: a record pushes the crossed entries it does
+// not continue with (up to three), so a lane's stack never holds more than the
+// largest sum of (entries - 1) over the records on a root-to-leaf path, which
+// the scene upload computes (scenes above this bound are rejected); with the
+// leaf queue a lane's LDS stays within 64 entries, a 256-thread workgroup's
+// within 64 KB.
 constexpr int kMaxDepth = 60;
 // An FP32 triangle record is padded to 64 bytes so that it never straddles a
 // 64-byte block: the traversal is bound by the rate of L1-miss requests, and a
@@ -57,8 +61,8 @@ template <typename R> struct alignas(sizeof(R) == 4 ? 64 : 32) Prim3 { R v0[3]; 
 template <typename R> struct alignas(16) Prim2 { R v0[2]; R e[2]; R alpha; int32_t idkind; };
 
 template <typename R, int D> struct Rec;
-template <typename R> struct Rec<R, 3> { using Node = Inner3<R>; using Prim = Prim3<R>; };
-template <typename R> struct Rec<R, 2> { using Node = Inner2<R>; using Prim = Prim2<R>; };
+template <typename R> struct Rec<R, 3> { using Node = Wide<R>; using Prim = Prim3<R>; };
+template <typename R> struct Rec<R, 2> { using Node = Wide<R>; using Prim = Prim2<R>; };
 
 constexpr int kIdBits = 29;
 constexpr int32_t kIdMask = (1 << kIdBits) - 1;
@@ -444,24 +448,18 @@ __device__ __forceinline__ R plane_hit(const PrimGeo<R>& g, const R n[3], const 
 }
 
 // Slab test of a line against a box in the scene's box frame; inv = 1 / d
-// (finite), ox = -x' inv with x' the line's point in that frame.
+// (finite), ox = -x' inv with x' the line's point in that frame.  The near side
+// of each slab is lo where inv >= 0 and hi otherwise, so an empty box (lo above
+// hi, an unused record slot) is never crossed.
 template <typename R, int D>
 __device__ __forceinline__ bool line_box(const R lo[3], const R hi[3], const R inv[3], const R ox[3]) {
-  R tmin, tmax;
-  {
-    const R a = fma(lo[0], inv[0], ox[0]), b = fma(hi[0], inv[0], ox[0]);
-    tmin = fmin(a, b);
-    tmax = fmax(a, b);
-  }
-  {
-    const R a = fma(lo[1], inv[1], ox[1]), b = fma(hi[1], inv[1], ox[1]);
-    tmin = fmax(tmin, fmin(a, b));
-    tmax = fmin(tmax, fmax(a, b));
-  }
-  if constexpr (D == 3) {
-    const R a = fma(lo[2], inv[2], ox[2]), b = fma(hi[2], inv[2], ox[2]);
-    tmin = fmax(tmin, fmin(a, b));
-    tmax = fmin(tmax, fmax(a, b));
+  R tmin = (R)-INFINITY, tmax = (R)INFINITY;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const bool pos = inv[k] >= (R)0;
+    const R tn = fma(pos ? lo[k] : hi[k], inv[k], ox[k]), tf = fma(pos ? hi[k] : lo[k], inv[k], ox[k]);
+    tmin = fmax(tmin, tn);
+    tmax = fmin(tmax, tf);
   }
   return tmin <= tmax;
 }
@@ -506,17 +504,19 @@ __device__ __forceinline__ bool packed_box(const uint32_t b[3], const float inv[
   return tmin <= tmax;
 }
 
-// Which of an interior record's two child boxes the line crosses.
+// Which of an interior record's child boxes the line crosses: bit k for slot k.
 template <typename R, int D>
-__device__ __forceinline__ void child_hits(const typename Rec<R, D>::Node& n, const R inv[3], const R ox[3],
-                                           const uint32_t rot[3], bool& h0, bool& h1) {
-  if constexpr (sizeof(R) == 4) {
-    h0 = packed_box<D>(n.box0, inv, ox, rot);
-    h1 = packed_box<D>(n.box1, inv, ox, rot);
-  } else {
-    h0 = line_box<R, D>(n.lo0, n.hi0, inv, ox);
-    h1 = line_box<R, D>(n.lo1, n.hi1, inv, ox);
+__device__ __forceinline__ uint32_t child_mask(const typename Rec<R, D>::Node& n, const R inv[3], const R ox[3],
+                                               const uint32_t rot[3]) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < kArity; ++k) {
+    bool h;
+    if constexpr (sizeof(R) == 4) h = packed_box<D>(n.box[k], inv, ox, rot);
+    else h = line_box<R, D>(n.lo[k], n.hi[k], inv, ox);
+    m |= h ? (1u << k) : 0u;
   }
+  return m;
 }
 
 // Calls leaf(first, count) for every leaf whose box the line crosses, depth
@@ -533,10 +533,16 @@ __device__ __forceinline__ void for_each_leaf(const SceneView<R, D>& s, const R 
     if (e >= 0) {
       const typename Rec<R, D>::Node n = s.nodes[e];
       if (COUNT) wc.nodes += 1;
-      bool h0, h1;
-      child_hits<R, D>(n, inv, ox, rot, h0, h1);
-      if (h0 && h1 && sp < kMaxDepth) stk[sp++] = n.child[1];
-      e = h0 ? n.child[0] : (h1 ? n.child[1] : kPop);
+      uint32_t m = child_mask<R, D>(n, inv, ox, rot);
+      // continue with the first crossed entry, push the others
+      e = kPop;
+#pragma unroll
+      for (int k = 0; k < kArity; ++k) {
+        if (m & (1u << k)) {
+          if (e == kPop) e = n.child[k];
+          else if (sp < kMaxDepth) stk[sp++] = n.child[k];
+        }
+      }
     } else if (e != kPop) {
       const int32_t code = -1 - e;
       leaf(code >> 3, (code & 7) + 1);

@@ -809,9 +809,9 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       while (trav) {
         if (active - __popcll(__ballot(1)) >= want) break;
         // one step: take the position (or pop it), fetch an interior record by
-        // a 32-bit byte offset from the uniform base, test both child boxes;
-        // both crossed -> push the second; a leaf entry goes to the lane's
-        // leaf queue, and the fourth one parks the lane
+        // a 32-bit byte offset from the uniform base, test its child boxes,
+        // continue with one crossed entry and push the others; a leaf entry
+        // goes to the lane's leaf queue, and the fourth one parks the lane
         int32_t e = s.ni;
         if (e == kPop) e = sp > 0 ? stk[--sp * BLOCK] : kDone;
         if (e >= 0 && e != kDone) {
@@ -819,10 +819,16 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
           const Node node = *reinterpret_cast<const Node*>(reinterpret_cast<const char*>(a.scene.nodes) +
                                                            (uint32_t)e * (uint32_t)sizeof(Node));
           if (COUNT) wc.nodes += 1;
-          bool h0, h1;
-          child_hits<R, D>(node, s.inv, s.ox, s.rot, h0, h1);
-          if (h0 && h1 && sp < a.scene.stack_cap) stk[sp++ * BLOCK] = node.child[1];
-          e = h0 ? node.child[0] : (h1 ? node.child[1] : kPop);
+          const uint32_t m = child_mask<R, D>(node, s.inv, s.ox, s.rot);
+          // continue with the first crossed entry, push the others
+          e = kPop;
+#pragma unroll
+          for (int q = 0; q < kArity; ++q) {
+            if (m & (1u << q)) {
+              if (e == kPop) e = node.child[q];
+              else if (sp < a.scene.stack_cap) stk[sp++ * BLOCK] = node.child[q];
+            }
+          }
         }
         const bool at_leaf = e < 0 && e != kPop;
         if (at_leaf) leafq[nq++ * BLOCK] = -1 - e;

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <vector>
 
@@ -57,7 +58,8 @@ void box_frame(const wobhost::Box& root, int dim, double c[3], double& k) {
 
 // A box in the frame, padded so that the FMA slab test in R precision never
 // misses a primitive that the exact test would hit, stored rounded outward
-// (FP32 scenes: binary16 pairs, lo in the low half of each word).
+// into slot `which` (FP32 scenes: binary16 pairs, lo in the low half of each
+// word).
 template <typename R, int D, typename Node>
 void store_box(const wobhost::Box& b, const double c[3], double k, Node& n, int which) {
   double l[3], h[3], mag = 0.0;
@@ -73,12 +75,29 @@ void store_box(const wobhost::Box& b, const double c[3], double k, Node& n, int 
       uint16_t ul, uh;
       std::memcpy(&ul, &lo, 2);
       std::memcpy(&uh, &hi, 2);
-      (which == 0 ? n.box0 : n.box1)[a] = (uint32_t)ul | ((uint32_t)uh << 16);
+      n.box[which][a] = (uint32_t)ul | ((uint32_t)uh << 16);
     } else {
-      (which == 0 ? n.lo0 : n.lo1)[a] = (R)(l[a] - pad);
-      (which == 0 ? n.hi0 : n.hi1)[a] = (R)(h[a] + pad);
+      n.lo[which][a] = (R)(l[a] - pad);
+      n.hi[which][a] = (R)(h[a] + pad);
     }
   }
+}
+
+// An unused slot: an empty box (lo above hi on every axis), which no line
+// crosses, whatever the signs of its direction (both slab tests take the near
+// side by the direction's sign), and the entry kPop, so that even a crossed
+// empty slot would only pop the stack.
+template <typename R, typename Node>
+void store_empty(Node& n, int which) {
+  for (int a = 0; a < 3; ++a) {
+    if constexpr (sizeof(R) == 4) {
+      n.box[which][a] = 0x7bffu | (0xfbffu << 16);  // lo = +65504, hi = -65504 (binary16)
+    } else {
+      n.lo[which][a] = (R)1e300;
+      n.hi[which][a] = (R)-1e300;
+    }
+  }
+  n.child[which] = wob::kPop;
 }
 
 template <typename R, int D>
@@ -87,34 +106,90 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   using Node = typename wob::Rec<R, D>::Node;
   using Prim = typename wob::Rec<R, D>::Prim;
   const int64_t T = sc->n_prims;
-  // interior records in pre-order; the first child of interior node i is
-  // node i + 1, the second the first node after the first child's subtree
+  // 4-wide interior records, in pre-order (a record's first interior child is
+  // the next record).  A record takes its binary node's two children and
+  // opens the interior entry of largest box measure until it holds kArity
+  // entries; every interior entry it keeps becomes a record of its own.  In
+  // the builder's flat array the first child of node i is node i + 1, the
+  // second the first node after the first child's subtree.
   const auto& fn = bvh.nodes;
-  std::vector<int32_t> rec_of(fn.size(), -1);
-  int32_t n_inner = 0;
-  for (size_t i = 0; i < fn.size(); ++i)
-    if (fn[i].child >= 0) rec_of[i] = n_inner++;
-  // the traversal addresses records by a 32-bit byte offset
-  if ((uint64_t)n_inner * sizeof(Node) > 0xffffffffull) return WOB_E_ARG;
-  auto entry = [&](size_t i) { return fn[i].child >= 0 ? rec_of[i] : fn[i].child; };
+  const int dim = D;
   double fc[3], fk;
   box_frame<R>(fn[0].box, D, fc, fk);
-  std::vector<Node> nodes((size_t)n_inner);
-  for (size_t i = 0; i < fn.size(); ++i) {
-    if (fn[i].child < 0) continue;
-    Node& n = nodes[rec_of[i]];
-    std::memset(&n, 0, sizeof(Node));
-    const size_t c0 = (size_t)fn[i].child, c1 = (size_t)fn[c0].skip;
-    store_box<R, D>(fn[c0].box, fc, fk, n, 0);
-    store_box<R, D>(fn[c1].box, fc, fk, n, 1);
-    n.child[0] = entry(c0);
-    n.child[1] = entry(c1);
+  std::vector<Node> nodes;
+  int max_ent = wob::kArity;
+  // deepest stack a line can need below a record: its own pushes (entries - 1)
+  // plus the deepest of its interior children
+  std::function<int32_t(size_t, int32_t*)> emit = [&](size_t i, int32_t* need) -> int32_t {
+    std::vector<size_t> ent = {(size_t)fn[i].child, (size_t)fn[(size_t)fn[i].child].skip};
+    while ((int)ent.size() < max_ent) {
+      int best = -1;
+      double bm = -1.0;
+      for (int q = 0; q < (int)ent.size(); ++q)
+        if (fn[ent[q]].child >= 0) {
+          const double mq = wobhost::box_measure(fn[ent[q]].box, dim);
+          if (mq > bm) {
+            bm = mq;
+            best = q;
+          }
+        }
+      if (best < 0) break;
+      const size_t c = ent[best];
+      ent.erase(ent.begin() + best);
+      ent.insert(ent.begin() + best, {(size_t)fn[c].child, (size_t)fn[(size_t)fn[c].child].skip});
+    }
+    const int32_t r = (int32_t)nodes.size();
+    nodes.emplace_back();
+    std::memset(&nodes[r], 0, sizeof(Node));
+    int32_t deepest = 0;
+    int32_t child[wob::kArity];
+    for (int q = 0; q < (int)ent.size(); ++q) {
+      if (fn[ent[q]].child >= 0) {
+        int32_t sub = 0;
+        child[q] = emit(ent[q], &sub);
+        deepest = std::max(deepest, sub);
+      } else {
+        child[q] = fn[ent[q]].child;  // leaf code
+      }
+    }
+    Node& n = nodes[r];
+    for (int q = 0; q < wob::kArity; ++q) {
+      if (q < (int)ent.size()) {
+        store_box<R, D>(fn[ent[q]].box, fc, fk, n, q);
+        n.child[q] = child[q];
+      } else {
+        store_empty<R>(n, q);
+      }
+    }
+    *need = (int32_t)ent.size() - 1 + deepest;
+    return r;
+  };
+  int32_t need = 0;
+  int32_t root = fn[0].child >= 0 ? emit(0, &need) : fn[0].child;
+  if (need > wob::kMaxDepth) {
+    // a degenerate tree whose 4-wide records could push more than a lane's
+    // stack holds: two entries per record (the binary tree, whose stack needs
+    // at most its depth - 1 entries)
+    nodes.clear();
+    max_ent = 2;
+    need = 0;
+    root = emit(0, &need);
   }
+  const int32_t n_inner = (int32_t)nodes.size();
+  // every interior entry points to a later record (pre-order), so a traversal
+  // never returns to a record it left: the walk ends on every line
+  for (int32_t r = 0; r < n_inner; ++r)
+    for (int q = 0; q < wob::kArity; ++q) {
+      const int32_t c = nodes[r].child[q];
+      if (c >= 0 && (c <= r || c >= n_inner)) return WOB_E_MESH;
+    }
+  // the traversal addresses records by a 32-bit byte offset
+  if ((uint64_t)n_inner * sizeof(Node) > 0xffffffffull) return WOB_E_ARG;
   sc->n_inner = n_inner;
   for (int a = 0; a < 3; ++a) sc->frame_c[a] = fc[a];
   sc->frame_k = fk;
-  sc->root = entry(0);
-  sc->stack_cap = std::max(bvh.depth - 1, 1);
+  sc->root = root;
+  sc->stack_cap = std::max(need, 1);
   if (sc->stack_cap > wob::kMaxDepth) return WOB_E_MESH;
   std::vector<Prim> recs((size_t)T);
   std::vector<R> normals((size_t)T * 4, (R)0);
