@@ -369,8 +369,8 @@ typedef struct {
 
 /* Launch shape of the persistent kernel. */
 typedef struct {
-  int32_t block;            /* lanes per workgroup: 128, 256 or 512 */
-  int32_t blocks_per_cu;    /* persistent workgroups per compute unit, 1..16 */
+  int32_t block;            /* lanes per workgroup: 64, 128, 256 or 512 */
+  int32_t blocks_per_cu;    /* persistent workgroups per compute unit, 1..32 */
 } wob_tune;
 
 typedef struct wob_batch_s* wob_batch;

@@ -49,8 +49,8 @@ bool fits_lds_cap(int32_t stack_cap, int32_t max_lds, int block) {
 bool fits_lds(const wob_batch_s* b, int block) { return fits_lds_cap(b->stack_cap, b->max_lds, block); }
 
 bool valid_tune(const wob_tune& t) {
-  return (t.block == 128 || t.block == 256 || t.block == 512) && t.blocks_per_cu >= 1 &&
-         t.blocks_per_cu <= 16;
+  return (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) && t.blocks_per_cu >= 1 &&
+         t.blocks_per_cu <= 32;
 }
 
 // Problem table for one block size (lanes per point and tiles depend on it):
@@ -126,7 +126,8 @@ void launch_persistent_t(const LaunchBufs& lb, int bpc, int64_t stride, hipStrea
 
 template <typename R, int D>
 void launch_persistent_rd(const LaunchBufs& lb, const wob_tune& t, int64_t stride, hipStream_t st) {
-  if (t.block == 128) launch_persistent_t<R, D, 128>(lb, t.blocks_per_cu, stride, st);
+  if (t.block == 64) launch_persistent_t<R, D, 64>(lb, t.blocks_per_cu, stride, st);
+  else if (t.block == 128) launch_persistent_t<R, D, 128>(lb, t.blocks_per_cu, stride, st);
   else if (t.block == 256) launch_persistent_t<R, D, 256>(lb, t.blocks_per_cu, stride, st);
   else launch_persistent_t<R, D, 512>(lb, t.blocks_per_cu, stride, st);
 }
@@ -373,16 +374,18 @@ wob_status wob_batch_autotune(wob_batch b, int32_t sample_stride, const char* ca
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return WOB_E_DEVICE;
     float best_ms = 1e30f;
-    const int blocks[3] = {128, 256, 512};
-    const int bpcs[6] = {1, 2, 3, 4, 6, 8};
-    for (int bi = 0; bi < 3; ++bi) {
+    const int blocks[4] = {64, 128, 256, 512};
+    // resident wavefronts per CU to try (4 SIMDs)
+    const int waves[6] = {4, 8, 12, 16, 20, 24};
+    for (int bi = 0; bi < 4; ++bi) {
       // the table is rewritten synchronously: wait for the kernels that read it
       if (hipStreamSynchronize(st) != hipSuccess) return WOB_E_DEVICE;
       if (upload(b, blocks[bi]) != WOB_OK) return WOB_E_DEVICE;
       if (!fits_lds(b, blocks[bi])) continue;
       for (int ci = 0; ci < 6; ++ci) {
-        const wob_tune t{blocks[bi], bpcs[ci]};
-        if (t.blocks_per_cu * t.block / 64 > 24) continue;  // beyond what a CU can hold
+        const int per_block = blocks[bi] / 64;
+        if (waves[ci] % per_block != 0) continue;
+        const wob_tune t{blocks[bi], waves[ci] / per_block};
         launch_persistent(b, t, sample_stride, st);  // warm-up
         (void)hipEventRecord(e0, st);
         launch_persistent(b, t, sample_stride, st);
