@@ -30,7 +30,8 @@ class _BC(C.Structure):
     _fields_ = [("domain", C.c_int), ("formulation", C.c_int), ("program", C.c_int),
                 ("params", C.c_double * 8), ("self_threshold", C.c_uint32), ("self_p", C.c_double),
                 ("density", C.c_int), ("sampling", C.c_int), ("candidates", C.c_int),
-                ("mixed_k", C.c_double), ("mixed_threshold", C.c_uint32), ("mixed_p", C.c_double)]
+                ("mixed_k", C.c_double), ("mixed_threshold", C.c_uint32), ("mixed_p", C.c_double),
+                ("data_mode", C.c_int), ("vertex_data", C.c_void_p)]
 
 
 class _TraceOut(C.Structure):
@@ -142,8 +143,17 @@ SAMPLE_LINE, SAMPLE_RIS = 0, 1
 
 def make_bc(domain: int = 1, formulation: int = AUTO, program: int = PROG_CONST,
             params=(), self_p: float = 1.0 / 16.0, density: bool = False, sampling: int = SAMPLE_LINE,
-            candidates: int = 16, mixed_k: float = 4.0, mixed_p: float = 2.0 / 3.0) -> _BC:
+            candidates: int = 16, mixed_k: float = 4.0, mixed_p: float = 2.0 / 3.0,
+            vertex_data: Optional[np.ndarray] = None) -> _BC:
+    """Boundary data from the harmonic program, or, with vertex_data (one value
+    per mesh vertex), given per vertex and interpolated linearly on each
+    primitive (the returned structure keeps a reference to the array)."""
     b = _BC()
+    if vertex_data is not None:
+        vd = np.ascontiguousarray(vertex_data, dtype=np.float64)
+        b.data_mode = 1
+        b.vertex_data = vd.ctypes.data
+        b._vd = vd
     b.mixed_k = float(mixed_k)
     b.mixed_threshold = self_threshold(mixed_p)
     b.mixed_p = b.mixed_threshold / 2.0 ** 24

@@ -230,8 +230,44 @@ double orc_program_value(const orc_mesh* m, const orc_bc* bc, const double* y) {
   return u;
 }
 
-/* eq. PoissonBC: Dirichlet value u, Neumann flux du/dn, Robin du/dn + alpha u. */
+/* Barycentric coordinates of y on primitive prim (the least-squares point of
+   its plane): solve [e1.e1 e1.e2; e1.e2 e2.e2] (b1, b2) = (e1.w, e2.w), w = y - v0
+   (2D: b1 = e.w / e.e); b0 = 1 - b1 - b2. */
+static void prim_bary(const orc_mesh* m, int64_t prim, const double* y, double b[3]) {
+  double v0[3] = {0.0, 0.0, 0.0}, v1[3] = {0.0, 0.0, 0.0}, v2[3] = {0.0, 0.0, 0.0};
+  prim_vertex(m, prim, 0, v0);
+  prim_vertex(m, prim, 1, v1);
+  const int dim = m->dim;
+  double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], dim == 3 ? v1[2] - v0[2] : 0.0};
+  double w[3] = {y[0] - v0[0], y[1] - v0[1], dim == 3 ? y[2] - v0[2] : 0.0};
+  if (dim == 2) {
+    b[1] = dot(e1, w, 2) / dot(e1, e1, 2);
+    b[2] = 0.0;
+  } else {
+    prim_vertex(m, prim, 2, v2);
+    double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+    const double g11 = dot(e1, e1, 3), g12 = dot(e1, e2, 3), g22 = dot(e2, e2, 3);
+    const double r1 = dot(e1, w, 3), r2 = dot(e2, w, 3), det = g11 * g22 - g12 * g12;
+    b[1] = (r1 * g22 - r2 * g12) / det;
+    b[2] = (r2 * g11 - r1 * g12) / det;
+  }
+  b[0] = 1.0 - b[1] - b[2];
+}
+
+/* Per-vertex data interpolated linearly on primitive prim at y. */
+static double vertex_datum(const orc_mesh* m, const orc_bc* bc, int64_t prim, const double* y) {
+  double b[3];
+  prim_bary(m, prim, y, b);
+  double f = 0.0;
+  for (int c = 0; c < m->dim; ++c) f += b[c] * bc->vertex_data[m->prims[prim * m->dim + c]];
+  return f;
+}
+
+/* eq. PoissonBC: Dirichlet value u, Neumann flux du/dn, Robin du/dn + alpha u;
+   with per-vertex data, the interpolated value is the datum of the primitive's
+   own kind. */
 double orc_boundary_datum(const orc_mesh* m, const orc_bc* bc, int64_t prim, const double* y) {
+  if (bc->data_mode == 1) return vertex_datum(m, bc, prim, y);
   double u, g[3], n[3];
   program_eval(m, bc, y, &u, g);
   int kind = prim_kind(m, prim);
@@ -502,6 +538,25 @@ static void program_sens(const orc_mesh* m, const orc_bc* bc, const double* y, d
    n . grad u + alpha u), and the size of the coordinates the program
    subtracts from y's (its centre). */
 static double datum_sens(const orc_mesh* m, const orc_bc* bc, int64_t prim, const double* y) {
+  if (bc->data_mode == 1) {
+    /* the in-plane gradient of the linear interpolant: |f(y + h) - f(y)| <= |grad| |h|
+       for a displacement h in the primitive's plane */
+    double v0[3] = {0.0, 0.0, 0.0}, v1[3] = {0.0, 0.0, 0.0}, v2[3] = {0.0, 0.0, 0.0};
+    prim_vertex(m, prim, 0, v0);
+    prim_vertex(m, prim, 1, v1);
+    const int32_t* ix = m->prims + prim * m->dim;
+    const double f0 = bc->vertex_data[ix[0]], df1 = bc->vertex_data[ix[1]] - f0;
+    double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], m->dim == 3 ? v1[2] - v0[2] : 0.0};
+    if (m->dim == 2) return fabs(df1) / sqrt(dot(e1, e1, 2));
+    prim_vertex(m, prim, 2, v2);
+    const double df2 = bc->vertex_data[ix[2]] - f0;
+    double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+    const double g11 = dot(e1, e1, 3), g12 = dot(e1, e2, 3), g22 = dot(e2, e2, 3), det = g11 * g22 - g12 * g12;
+    const double a = (df1 * g22 - df2 * g12) / det, b = (df2 * g11 - df1 * g12) / det;
+    double gr[3];
+    for (int k = 0; k < 3; ++k) gr[k] = a * e1[k] + b * e2[k];
+    return sqrt(dot(gr, gr, 3));
+  }
   double g1, g2;
   program_sens(m, bc, y, &g1, &g2);
   const int kind = prim_kind(m, prim);
@@ -510,7 +565,7 @@ static double datum_sens(const orc_mesh* m, const orc_bc* bc, int64_t prim, cons
   return g2 + fabs(prim_alpha(m, prim)) * g1;
 }
 static double program_centre(const orc_mesh* m, const orc_bc* bc) {
-  return bc->program == ORC_PROG_INVDIST ? norm_d(bc->params, m->dim) : 0.0;
+  return bc->data_mode == 0 && bc->program == ORC_PROG_INVDIST ? norm_d(bc->params, m->dim) : 0.0;
 }
 
 /* Error of an emission k s(y) (units of u) from the position error P of y. */
@@ -1138,6 +1193,7 @@ static double* make_normals(const orc_mesh* m) {
 
 static int check_args(const orc_mesh* m, const orc_bc* bc, int walk_len) {
   if (!m || !bc) return 1;
+  if (bc->data_mode != 0 && (bc->data_mode != 1 || !bc->vertex_data)) return 1;
   if (m->dim != 2 && m->dim != 3) return 1;
   if (m->n_prims <= 0 || !m->verts || !m->prims) return 1;
   if (walk_len < 1) return 1;

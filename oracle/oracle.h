@@ -71,6 +71,12 @@ typedef struct {
   double mixed_k;
   uint32_t mixed_threshold; /* p_k as floor(p_k * 2^24) */
   double mixed_p;           /* floor(p_k * 2^24) / 2^24 */
+  /* boundary data: 0 = derived from the harmonic program (u, n . grad u,
+     n . grad u + alpha u by kind), 1 = given per mesh vertex and interpolated
+     linearly on each primitive (the datum of the primitive's own kind: g, q
+     or g_R; eq. PoissonBC) */
+  int data_mode;
+  const double* vertex_data; /* [n_verts] when data_mode == 1 */
 } orc_bc;
 
 enum { ORC_SAMPLE_LINE = 0, ORC_SAMPLE_RIS = 1 };
