@@ -108,7 +108,20 @@ typedef struct {
                            (eq. mixed_second_kind_ish); 0 selects 4 (the paper's Results) */
   double mixed_p;       /* its probability p_k of sampling the k G term (else the walk stays
                            at x), in (0, 1); 0 selects 2/3 */
+  int32_t data_mode;    /* WOB_DATA_PROGRAM: the data g, q, g_R derive from `program` (the
+                           traces of a harmonic u).  WOB_DATA_VERTEX: they are given, one
+                           value per mesh vertex in `vertex_data`, and interpolated linearly
+                           on each primitive; the value is the datum of the primitive's own
+                           kind (eq. PoissonBC: g on Dirichlet, q on Neumann, g_R on Robin
+                           parts) and `program` / `params` are ignored */
+  int32_t reserved;     /* must be 0 */
+  const void* vertex_data; /* WOB_DATA_VERTEX: DEVICE array of the scene's n_verts values, of
+                           the scene's element type, indexed like the vertices passed to
+                           wob_build_bvh; caller-owned, read by enqueued work */
 } wob_bc;
+
+/* Where the boundary data come from (wob_bc.data_mode). */
+enum { WOB_DATA_PROGRAM = 0, WOB_DATA_VERTEX = 1 };
 
 typedef struct {
   int32_t dim;          /* 2 or 3 */
@@ -124,6 +137,7 @@ typedef struct {
   int64_t node_bytes;   /* size of one interior-node record */
   int64_t prim_bytes;   /* size of one primitive record */
   int32_t n_dirichlet, n_neumann, n_robin, reserved;
+  int64_t n_verts;      /* vertices of the mesh (the length of per-vertex data) */
 } wob_scene_info;
 
 /* Build the line-query acceleration structure for a boundary mesh and upload it
@@ -144,6 +158,18 @@ typedef struct {
 wob_status wob_build_bvh(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
                          const int32_t* prims, int64_t n_prims, const uint8_t* kind,
                          const double* alpha, wob_scene* out);
+
+/* wob_build_bvh with the mesh arrays in host or device memory and its copies
+ * on `stream`.  inputs_on_device = 1: verts, prims, kind and alpha are DEVICE
+ * pointers (same layouts; kind and alpha may be NULL); they are copied to the
+ * host on `stream`, which the call waits for (the tree is built on the host),
+ * and the scene is uploaded on `stream`.  inputs_on_device = 0: as
+ * wob_build_bvh, with the upload on `stream`.  Synchronous.  Errors: as
+ * wob_build_bvh. */
+wob_status wob_build_bvh_ex(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
+                            const int32_t* prims, int64_t n_prims, const uint8_t* kind,
+                            const double* alpha, int32_t inputs_on_device, void* stream,
+                            wob_scene* out);
 
 /* Release a scene (waits for nothing: the caller must not free a scene that
  * enqueued work still uses).  NULL is ignored. */

@@ -17,7 +17,8 @@ namespace wob {
 enum Formulation { F_DL = 1, F_DIRECT = 2, F_SL = 3, F_SL_RIS = 4, F_FWD = 5 };
 __host__ __device__ constexpr bool is_sl(int f) { return f == F_SL || f == F_SL_RIS; }
 enum Kind { K_DIRICHLET = 0, K_NEUMANN = 1, K_ROBIN = 2 };
-enum Program { P_CONST = 0, P_LINEAR = 1, P_QUAD = 2, P_INVDIST = 3 };
+// P_VERTEX: data given per mesh vertex, interpolated linearly on each primitive
+enum Program { P_CONST = 0, P_LINEAR = 1, P_QUAD = 2, P_INVDIST = 3, P_VERTEX = 4 };
 
 // --------------------------------------------------------------------------
 // Scene records.  Primitives are stored in BVH leaf order.  idkind packs the
@@ -86,6 +87,11 @@ template <typename R>
 struct ProgramView {
   int32_t type;
   R p[8];
+  // P_VERTEX: the values (caller's vertex order), each primitive's vertex ids
+  // (caller-id order, D per primitive) and the scene's rounded vertices
+  const R* vdata;
+  const int32_t* vid;
+  const R* verts;
 };
 
 // --------------------------------------------------------------------------
@@ -253,9 +259,42 @@ __device__ __forceinline__ void program_eval(const ProgramView<R>& g, const R y[
   }
 }
 
+// Per-vertex data interpolated linearly on primitive g at y: the barycentric
+// coordinates of y from the primitive's exact (rounded-once) vertices, solved
+// in binary64 (the Gram system; a sliver's ill-conditioning stays at the
+// binary64 unit), then f0 + b1 (f1 - f0) + b2 (f2 - f0).
+template <typename R, int D>
+__device__ __forceinline__ R vertex_datum(const ProgramView<R>& prog, const PrimGeo<R>& g, const R y[3]) {
+  const int32_t* ix = prog.vid + (int64_t)g.id * D;
+  double v[3][3];
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[c][a] = a < D ? (double)prog.verts[(int64_t)ix[c] * D + a] : 0.0;
+  const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+  const double w[3] = {(double)y[0] - v[0][0], (double)y[1] - v[0][1], D == 3 ? (double)y[2] - v[0][2] : 0.0};
+  const double f0 = (double)prog.vdata[ix[0]], d1 = (double)prog.vdata[ix[1]] - f0;
+  if constexpr (D == 3) {
+    const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+    const double g11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+    const double g12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+    const double g22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+    const double r1 = e1[0] * w[0] + e1[1] * w[1] + e1[2] * w[2];
+    const double r2 = e2[0] * w[0] + e2[1] * w[1] + e2[2] * w[2];
+    const double det = g11 * g22 - g12 * g12;
+    const double b1 = (r1 * g22 - r2 * g12) / det, b2 = (r2 * g11 - r1 * g12) / det;
+    const double d2 = (double)prog.vdata[ix[2]] - f0;
+    return (R)(f0 + b1 * d1 + b2 * d2);
+  } else {
+    const double b1 = (e1[0] * w[0] + e1[1] * w[1]) / (e1[0] * e1[0] + e1[1] * e1[1]);
+    return (R)(f0 + b1 * d1);
+  }
+}
+
 template <typename R, int D>
 __device__ __forceinline__ R boundary_datum(const ProgramView<R>& prog, const PrimGeo<R>& g,
                                             const R n[3], const R y[3]) {
+  if (prog.type == P_VERTEX) return vertex_datum<R, D>(prog, g, y);
   R u, grad[3];
   program_eval<R, D>(prog, y, u, grad);
   if (g.kind == K_DIRICHLET) return u;

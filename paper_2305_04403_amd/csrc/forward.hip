@@ -163,9 +163,7 @@ __global__ void __launch_bounds__(256) data_weight_kernel(wob::SceneView<R, D> s
 
 template <typename R, int D>
 wob_status data_weights(const wob_scene_s* sc, const wob_bc* bc, double* d_out) {
-  wob::ProgramView<R> prog;
-  prog.type = bc->program;
-  for (int k = 0; k < 8; ++k) prog.p[k] = (R)bc->params[k];
+  const wob::ProgramView<R> prog = make_program<R>(sc, bc);
   const dim3 grid((unsigned)((sc->n_prims + 255) / 256)), block(256);
   hipLaunchKernelGGL((data_weight_kernel<R, D>), grid, block, 0, 0, view<R, D>(sc), prog, d_out);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
@@ -178,8 +176,7 @@ wob_status launch_paths(const wob_scene_s* sc, const wob_bc* bc, const float* cd
   wob::WalkArgs<R, D> a;
   std::memset(&a, 0, sizeof(a));
   a.scene = view<R, D>(sc);
-  a.prog.type = bc->program;
-  for (int k = 0; k < 8; ++k) a.prog.p[k] = (R)bc->params[k];
+  a.prog = make_program<R>(sc, bc);
   // one lane per group of kFwdPathsPerLane paths: forward paths are short
   // (M - 1 lines from the boundary), so fewer per lane keep enough waves in
   // flight (2^20 paths of 4 vertices: 2.7 ms with 4 per lane, 4.0 ms with 8)
@@ -266,7 +263,7 @@ wob_status wob_starts_from_data(wob_scene sc, const wob_bc* bc, double floor, wo
   if (!out) return WOB_E_ARG;
   *out = nullptr;
   if (!sc || !bc || !(floor >= 0.0) || !std::isfinite(floor)) return WOB_E_ARG;
-  if (bc->program < WOB_PROG_CONST || bc->program > WOB_PROG_INVDIST) return WOB_E_ARG;
+  if (check_data(bc) != WOB_OK) return WOB_E_ARG;
   if (!on_device(sc->device)) return WOB_E_DEVICE;
   const int64_t T = sc->n_prims;
   double* d_w = nullptr;
@@ -306,7 +303,7 @@ wob_status wob_forward_paths(wob_scene sc, const wob_bc* bc, wob_starts starts, 
                              int32_t* vtx_m, void* stream) {
   if (!sc || !bc) return WOB_E_ARG;
   if (bc->domain != 1 && bc->domain != -1) return WOB_E_ARG;
-  if (bc->program < WOB_PROG_CONST || bc->program > WOB_PROG_INVDIST) return WOB_E_ARG;
+  if (check_data(bc) != WOB_OK) return WOB_E_ARG;
   if (bc->formulation != WOB_F_AUTO && bc->formulation != WOB_F_SINGLE_LAYER) return WOB_E_UNSUPPORTED;
   if (bc->density != 0 || bc->sampling != WOB_SAMPLE_LINE) return WOB_E_UNSUPPORTED;
   if (sc->n_neumann != sc->n_prims) return WOB_E_UNSUPPORTED;  // Neumann data only

@@ -11,7 +11,7 @@
 
 struct wob_scene_s {
   int32_t dim = 0, precision = 0, device = 0;
-  int64_t n_prims = 0, n_nodes = 0, n_leaves = 0;
+  int64_t n_prims = 0, n_nodes = 0, n_leaves = 0, n_verts = 0;
   int32_t n_inner = 0;    // interior records on the device
   int32_t root = 0;       // root entry (record 0, or a leaf)
   int32_t stack_cap = 1;  // traversal stack entries per lane
@@ -21,6 +21,8 @@ struct wob_scene_s {
   void* d_prims = nullptr;
   void* d_normals = nullptr;
   int32_t* d_leaf_of_id = nullptr;
+  void* d_verts = nullptr;       // the rounded vertices (n_verts x dim, scene precision)
+  int32_t* d_vid = nullptr;      // each primitive's vertex ids, caller-id order (n_prims x dim)
   float* d_area_cdf = nullptr;  // caller-id order, cumulative area / total (last entry 1)
   unsigned long long* d_status = nullptr;  // non-finite path values excluded from solves (sticky)
   double area_total = 0.0;      // |Gamma|
@@ -94,11 +96,33 @@ struct Plan {
   double mixed_p, mixed_k;
 };
 
+// The data program of a solve: the analytic program, or the per-vertex data.
+template <typename R>
+wob::ProgramView<R> make_program(const wob_scene_s* sc, const wob_bc* bc) {
+  wob::ProgramView<R> g;
+  std::memset(&g, 0, sizeof(g));
+  g.type = bc->data_mode == WOB_DATA_VERTEX ? wob::P_VERTEX : bc->program;
+  for (int k = 0; k < 8; ++k) g.p[k] = (R)bc->params[k];
+  g.vdata = (const R*)bc->vertex_data;
+  g.vid = sc->d_vid;
+  g.verts = (const R*)sc->d_verts;
+  return g;
+}
+
+// Data mode and program of a wob_bc.
+inline wob_status check_data(const wob_bc* bc) {
+  if (bc->data_mode != WOB_DATA_PROGRAM && bc->data_mode != WOB_DATA_VERTEX) return WOB_E_ARG;
+  if (bc->reserved != 0) return WOB_E_ARG;
+  if (bc->data_mode == WOB_DATA_VERTEX) return bc->vertex_data ? WOB_OK : WOB_E_ARG;
+  if (bc->program < WOB_PROG_CONST || bc->program > WOB_PROG_INVDIST) return WOB_E_ARG;
+  return WOB_OK;
+}
+
 inline wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t samples, int32_t walk_len,
                      Plan* p) {
   if (!sc || !bc) return WOB_E_ARG;
+  if (check_data(bc) != WOB_OK) return WOB_E_ARG;
   if (bc->domain != 1 && bc->domain != -1) return WOB_E_ARG;
-  if (bc->program < WOB_PROG_CONST || bc->program > WOB_PROG_INVDIST) return WOB_E_ARG;
   if (bc->density != 0 && bc->density != 1) return WOB_E_ARG;
   if (samples < 1 || walk_len < 1 || walk_len >= 65535) return WOB_E_ARG;
   const int f = resolve_formulation(sc, bc->formulation);
@@ -137,8 +161,7 @@ wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void*
   wob::WalkArgs<R, D> a;
   std::memset(&a, 0, sizeof(a));
   a.scene = view<R, D>(sc);
-  a.prog.type = bc->program;
-  for (int k = 0; k < 8; ++k) a.prog.p[k] = (R)bc->params[k];
+  a.prog = make_program<R>(sc, bc);
   a.points = (const R*)points;
   a.point_prim = point_prim;
   a.n_points = n_points;

@@ -505,9 +505,7 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
         R y[3], n[3];
         load_normal<R, D>(sc, j, n);
         const R t = plane_hit<R, D>(g, n, s.x, s.d, y);
-        R uu, grad[3];
-        program_eval<R, D>(a.prog, y, uu, grad);
-        const R q = dot3(n, grad);
+        const R q = boundary_datum<R, D>(a.prog, g, n, y);  // Neumann data
         // y - x = t d: distance and cosine from the line itself, free of the
         // cancellation in y - x when the hit is close to x
         const R rho = fabs(t);

@@ -102,7 +102,8 @@ void store_empty(Node& n, int which) {
 
 template <typename R, int D>
 wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int32_t* prims,
-                        const uint8_t* kind, const double* alpha, const wobhost::Bvh& bvh) {
+                        const uint8_t* kind, const double* alpha, const wobhost::Bvh& bvh,
+                        hipStream_t st) {
   using Node = typename wob::Rec<R, D>::Node;
   using Prim = typename wob::Rec<R, D>::Prim;
   const int64_t T = sc->n_prims;
@@ -235,20 +236,6 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   }
   sc->node_bytes = sizeof(Node);
   sc->prim_bytes = sizeof(Prim);
-  const size_t nb = std::max(nodes.size(), (size_t)1) * sizeof(Node), pb = recs.size() * sizeof(Prim),
-               lb = leaf_of_id.size() * sizeof(int32_t), qb = normals.size() * sizeof(R);
-  if (hipMalloc(&sc->d_nodes, nb) != hipSuccess) return WOB_E_ALLOC;
-  if (hipMalloc(&sc->d_prims, pb) != hipSuccess) return WOB_E_ALLOC;
-  if (hipMalloc(&sc->d_normals, qb) != hipSuccess) return WOB_E_ALLOC;
-  if (hipMemcpy(sc->d_normals, normals.data(), qb, hipMemcpyHostToDevice) != hipSuccess)
-    return WOB_E_DEVICE;
-  if (hipMalloc((void**)&sc->d_leaf_of_id, lb) != hipSuccess) return WOB_E_ALLOC;
-  if (!nodes.empty() &&
-      hipMemcpy(sc->d_nodes, nodes.data(), nodes.size() * sizeof(Node), hipMemcpyHostToDevice) != hipSuccess)
-    return WOB_E_DEVICE;
-  if (hipMemcpy(sc->d_prims, recs.data(), pb, hipMemcpyHostToDevice) != hipSuccess) return WOB_E_DEVICE;
-  if (hipMemcpy(sc->d_leaf_of_id, leaf_of_id.data(), lb, hipMemcpyHostToDevice) != hipSuccess)
-    return WOB_E_DEVICE;
   // cumulative area fraction in caller-id order: summed in binary64, rounded
   // once to binary32 (an area-uniform pick compares a binary32 uniform with it)
   std::vector<float> cdf((size_t)T);
@@ -261,12 +248,35 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   }
   cdf[T - 1] = 1.0f;
   sc->area_total = tot;
-  if (hipMalloc((void**)&sc->d_area_cdf, sizeof(float) * T) != hipSuccess) return WOB_E_ALLOC;
-  if (hipMemcpy(sc->d_area_cdf, cdf.data(), sizeof(float) * T, hipMemcpyHostToDevice) != hipSuccess)
-    return WOB_E_DEVICE;
-  if (hipMalloc((void**)&sc->d_status, sizeof(unsigned long long)) != hipSuccess) return WOB_E_ALLOC;
-  if (hipMemset(sc->d_status, 0, sizeof(unsigned long long)) != hipSuccess) return WOB_E_DEVICE;
-  sc->device_bytes = (int64_t)(nb + pb + lb + qb + sizeof(float) * T + sizeof(unsigned long long));
+  // the vertices (already rounded to R) and each primitive's vertex ids, for
+  // per-vertex boundary data
+  std::vector<R> verts_r(v.size());
+  for (size_t i = 0; i < v.size(); ++i) verts_r[i] = (R)v[i];
+  const size_t nb = std::max(nodes.size(), (size_t)1) * sizeof(Node), pb = recs.size() * sizeof(Prim),
+               lb = leaf_of_id.size() * sizeof(int32_t), qb = normals.size() * sizeof(R),
+               cb = sizeof(float) * T, vb = verts_r.size() * sizeof(R),
+               ib = (size_t)T * D * sizeof(int32_t), sb = sizeof(unsigned long long);
+  if (hipMalloc(&sc->d_nodes, nb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc(&sc->d_prims, pb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc(&sc->d_normals, qb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc((void**)&sc->d_leaf_of_id, lb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc((void**)&sc->d_area_cdf, cb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc(&sc->d_verts, vb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc((void**)&sc->d_vid, ib) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc((void**)&sc->d_status, sb) != hipSuccess) return WOB_E_ALLOC;
+  // copies on the caller's stream, waited for before the host arrays go
+  const auto put = [st](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+  };
+  bool ok = put(sc->d_normals, normals.data(), qb) && put(sc->d_prims, recs.data(), pb) &&
+            put(sc->d_leaf_of_id, leaf_of_id.data(), lb) && put(sc->d_area_cdf, cdf.data(), cb) &&
+            put(sc->d_verts, verts_r.data(), vb) && put(sc->d_vid, prims, ib) &&
+            hipMemsetAsync(sc->d_status, 0, sb, st) == hipSuccess;
+  if (ok && !nodes.empty()) ok = put(sc->d_nodes, nodes.data(), nodes.size() * sizeof(Node));
+  // the copies must end before the host arrays are released, also on failure
+  if (hipStreamSynchronize(st) != hipSuccess || !ok) return WOB_E_DEVICE;
+  sc->n_verts = (int64_t)(v.size() / D);
+  sc->device_bytes = (int64_t)(nb + pb + lb + qb + cb + vb + ib + sb);
   return WOB_OK;
 }
 
@@ -394,15 +404,14 @@ const char* wob_status_string(wob_status s) {
   return "unknown status";
 }
 
-wob_status wob_build_bvh(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
-                         const int32_t* prims, int64_t n_prims, const uint8_t* kind,
-                         const double* alpha, wob_scene* out) {
-  if (!out) return WOB_E_ARG;
-  *out = nullptr;
-  if (dim != 2 && dim != 3) return WOB_E_ARG;
-  if (precision != WOB_F32 && precision != WOB_F64) return WOB_E_ARG;
-  if (!verts || !prims || n_verts <= 0 || n_prims <= 0) return WOB_E_ARG;
-  if (n_prims >= ((int64_t)1 << 27)) return WOB_E_ARG;  // leaf entries pack the first index in 27 bits
+}  // extern "C"
+
+namespace {
+
+// wob_build_bvh on host arrays, the scene's copies on `st`.
+wob_status build_scene(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
+                       const int32_t* prims, int64_t n_prims, const uint8_t* kind, const double* alpha,
+                       hipStream_t st, wob_scene* out) {
   // vertices rounded to the scene precision: both the walk and any external
   // checker then see the same geometry
   std::vector<double> v((size_t)(n_verts * dim));
@@ -467,17 +476,68 @@ wob_status wob_build_bvh(int32_t dim, int32_t precision, const double* verts, in
   sc->n_robin = nr;
   wob_status s;
   if (precision == WOB_F32)
-    s = dim == 3 ? upload_scene<float, 3>(sc, v, prims, kind, alpha, bvh)
-                 : upload_scene<float, 2>(sc, v, prims, kind, alpha, bvh);
+    s = dim == 3 ? upload_scene<float, 3>(sc, v, prims, kind, alpha, bvh, st)
+                 : upload_scene<float, 2>(sc, v, prims, kind, alpha, bvh, st);
   else
-    s = dim == 3 ? upload_scene<double, 3>(sc, v, prims, kind, alpha, bvh)
-                 : upload_scene<double, 2>(sc, v, prims, kind, alpha, bvh);
+    s = dim == 3 ? upload_scene<double, 3>(sc, v, prims, kind, alpha, bvh, st)
+                 : upload_scene<double, 2>(sc, v, prims, kind, alpha, bvh, st);
   if (s != WOB_OK) {
     wob_free(sc);
     return s;
   }
   *out = sc;
   return WOB_OK;
+}
+
+wob_status check_build_args(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
+                            const int32_t* prims, int64_t n_prims, wob_scene* out) {
+  if (!out) return WOB_E_ARG;
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return WOB_E_ARG;
+  if (precision != WOB_F32 && precision != WOB_F64) return WOB_E_ARG;
+  if (!verts || !prims || n_verts <= 0 || n_prims <= 0) return WOB_E_ARG;
+  if (n_prims >= ((int64_t)1 << 27)) return WOB_E_ARG;  // leaf entries pack the first index in 27 bits
+  if (n_verts > ((int64_t)1 << 31) - 1) return WOB_E_ARG;  // vertex ids are int32
+  return WOB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wob_status wob_build_bvh(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
+                         const int32_t* prims, int64_t n_prims, const uint8_t* kind,
+                         const double* alpha, wob_scene* out) {
+  const wob_status a = check_build_args(dim, precision, verts, n_verts, prims, n_prims, out);
+  if (a != WOB_OK) return a;
+  return build_scene(dim, precision, verts, n_verts, prims, n_prims, kind, alpha, nullptr, out);
+}
+
+wob_status wob_build_bvh_ex(int32_t dim, int32_t precision, const double* verts, int64_t n_verts,
+                            const int32_t* prims, int64_t n_prims, const uint8_t* kind,
+                            const double* alpha, int32_t inputs_on_device, void* stream,
+                            wob_scene* out) {
+  const wob_status a = check_build_args(dim, precision, verts, n_verts, prims, n_prims, out);
+  if (a != WOB_OK) return a;
+  if (inputs_on_device != 0 && inputs_on_device != 1) return WOB_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (!inputs_on_device)
+    return build_scene(dim, precision, verts, n_verts, prims, n_prims, kind, alpha, st, out);
+  // the tree is built on the host: bring the mesh over on the caller's stream
+  std::vector<double> hv((size_t)(n_verts * dim)), ha(alpha ? (size_t)n_prims : 0);
+  std::vector<int32_t> hp((size_t)(n_prims * dim));
+  std::vector<uint8_t> hk(kind ? (size_t)n_prims : 0);
+  const auto get = [st](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st) == hipSuccess;
+  };
+  bool ok = get(hv.data(), verts, hv.size() * sizeof(double)) &&
+            get(hp.data(), prims, hp.size() * sizeof(int32_t));
+  if (ok && kind) ok = get(hk.data(), kind, hk.size());
+  if (ok && alpha) ok = get(ha.data(), alpha, ha.size() * sizeof(double));
+  // wait also after a failed enqueue: the host arrays are released on return
+  if (hipStreamSynchronize(st) != hipSuccess || !ok) return WOB_E_DEVICE;
+  return build_scene(dim, precision, hv.data(), n_verts, hp.data(), n_prims, kind ? hk.data() : nullptr,
+                     alpha ? ha.data() : nullptr, st, out);
 }
 
 void wob_free(wob_scene sc) {
@@ -488,6 +548,8 @@ void wob_free(wob_scene sc) {
   if (sc->d_area_cdf) (void)hipFree(sc->d_area_cdf);
   if (sc->d_leaf_of_id) (void)hipFree(sc->d_leaf_of_id);
   if (sc->d_status) (void)hipFree(sc->d_status);
+  if (sc->d_verts) (void)hipFree(sc->d_verts);
+  if (sc->d_vid) (void)hipFree(sc->d_vid);
   delete sc;
 }
 
@@ -521,6 +583,7 @@ wob_status wob_get_scene_info(wob_scene sc, wob_scene_info* info) {
   info->n_dirichlet = sc->n_dirichlet;
   info->n_neumann = sc->n_neumann;
   info->n_robin = sc->n_robin;
+  info->n_verts = sc->n_verts;
   return WOB_OK;
 }
 

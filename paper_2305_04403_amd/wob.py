@@ -20,10 +20,11 @@ LIB_PATH = os.path.join(HERE, "libwob.so")
 F32, F64 = 0, 1
 AUTO, DOUBLE_LAYER, DIRECT, SINGLE_LAYER = 0, 1, 2, 3
 PROG_CONST, PROG_LINEAR, PROG_QUAD, PROG_INVDIST = 0, 1, 2, 3
+DATA_PROGRAM, DATA_VERTEX = 0, 1
 DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 SAMPLE_LINE, SAMPLE_RIS = 0, 1
 
-EXPORTED = ("wob_build_bvh", "wob_free", "wob_get_scene_info", "wob_lines_per_path", "wob_solve",
+EXPORTED = ("wob_build_bvh", "wob_build_bvh_ex", "wob_free", "wob_get_scene_info", "wob_lines_per_path", "wob_solve",
             "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string",
             "wob_batch_create", "wob_batch_launch", "wob_batch_autotune", "wob_batch_get_tune",
             "wob_batch_free", "wob_solve_batched", "wob_solve_batched_static", "wob_mlp_n_params",
@@ -44,7 +45,8 @@ class _BC(C.Structure):
     _fields_ = [("domain", C.c_int32), ("formulation", C.c_int32), ("program", C.c_int32),
                 ("density", C.c_int32), ("sampling", C.c_int32), ("candidates", C.c_int32),
                 ("params", C.c_double * 8), ("self_panel_p", C.c_double), ("mixed_k", C.c_double),
-                ("mixed_p", C.c_double)]
+                ("mixed_p", C.c_double), ("data_mode", C.c_int32), ("reserved", C.c_int32),
+                ("vertex_data", C.c_void_p)]
 
 
 class _SceneInfo(C.Structure):
@@ -52,7 +54,7 @@ class _SceneInfo(C.Structure):
                 ("n_nodes", C.c_int64), ("n_leaves", C.c_int64), ("depth", C.c_int32),
                 ("max_leaf", C.c_int32), ("device_bytes", C.c_int64), ("node_bytes", C.c_int64),
                 ("prim_bytes", C.c_int64), ("n_dirichlet", C.c_int32), ("n_neumann", C.c_int32),
-                ("n_robin", C.c_int32), ("reserved", C.c_int32)]
+                ("n_robin", C.c_int32), ("reserved", C.c_int32), ("n_verts", C.c_int64)]
 
 
 class _Problem(C.Structure):
@@ -87,6 +89,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
     L.wob_build_bvh.argtypes = [i32, i32, vp, i64, vp, i64, vp, vp, C.POINTER(vp)]
+    L.wob_build_bvh_ex.argtypes = [i32, i32, vp, i64, vp, i64, vp, vp, i32, vp, C.POINTER(vp)]
     L.wob_free.argtypes = [vp]
     L.wob_free.restype = None
     L.wob_get_scene_info.argtypes = [vp, C.POINTER(_SceneInfo)]
@@ -151,7 +154,7 @@ def lib():
     L.wob_forward_gather.restype = C.c_int
     L.wob_status_string.argtypes = [C.c_int]
     L.wob_status_string.restype = C.c_char_p
-    for name in ("wob_build_bvh", "wob_get_scene_info", "wob_solve", "wob_trace",
+    for name in ("wob_build_bvh", "wob_build_bvh_ex", "wob_get_scene_info", "wob_solve", "wob_trace",
                  "wob_count_work", "wob_intersect_all"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -177,9 +180,14 @@ class BC:
     candidates: int = 0           # RIS candidates (0 = 16)
     mixed_k: float = 0.0          # Dirichlet parts of the single layer: k (0 = 4)
     mixed_p: float = 0.0          # and p_k (0 = 2/3)
+    vertex_data: object = None    # per-vertex data (device tensor of the scene's dtype,
+                                  # one value per mesh vertex): replaces program/params
 
-    def c(self) -> _BC:
+    def c(self, scene: "Scene") -> _BC:
         b = _BC()
+        if self.vertex_data is not None:
+            _need(self.vertex_data, "vertex_data", scene.dtype, (scene.n_verts,), scene.device)
+            b.data_mode, b.vertex_data = DATA_VERTEX, self.vertex_data.data_ptr()
         b.domain, b.formulation, b.program = self.domain, self.formulation, self.program
         b.density = int(bool(self.density))
         b.sampling, b.candidates = int(self.sampling), int(self.candidates)
@@ -246,24 +254,57 @@ def _need_points(scene, points, name: str = "points") -> int:
 
 
 class Scene:
-    """A boundary mesh uploaded to the current device with its line-query BVH."""
+    """A boundary mesh uploaded to the current device with its line-query BVH
+    (``wob_build_bvh``; with ``stream``, ``wob_build_bvh_ex`` copying on it)."""
 
-    def __init__(self, mesh, precision: int = F32):
+    def __init__(self, mesh, precision: int = F32, stream=None):
         verts = np.ascontiguousarray(mesh.verts, dtype=np.float64)
         prims = np.ascontiguousarray(mesh.prims, dtype=np.int32)
         kind = None if mesh.kind is None else np.ascontiguousarray(mesh.kind, dtype=np.uint8)
         alpha = None if mesh.alpha is None else np.ascontiguousarray(mesh.alpha, dtype=np.float64)
+        if verts.ndim != 2 or verts.shape[1] != mesh.dim or prims.shape != (prims.shape[0], mesh.dim):
+            raise WobError("mesh: verts (V, dim) and prims (T, dim) expected")
+        for a, name in ((kind, "kind"), (alpha, "alpha")):
+            if a is not None and a.shape != (prims.shape[0],):
+                raise WobError(f"mesh.{name}: one entry per primitive expected")
         h = C.c_void_p()
-        st = lib().wob_build_bvh(int(mesh.dim), int(precision), verts.ctypes.data, verts.shape[0],
-                                 prims.ctypes.data, prims.shape[0],
-                                 None if kind is None else kind.ctypes.data,
-                                 None if alpha is None else alpha.ctypes.data, C.byref(h))
-        _check(st, "wob_build_bvh")
+        args = (int(mesh.dim), int(precision), verts.ctypes.data, verts.shape[0], prims.ctypes.data,
+                prims.shape[0], None if kind is None else kind.ctypes.data,
+                None if alpha is None else alpha.ctypes.data)
+        if stream is None:
+            _check(lib().wob_build_bvh(*args, C.byref(h)), "wob_build_bvh")
+        else:
+            _check(lib().wob_build_bvh_ex(*args, 0, _stream(stream), C.byref(h)), "wob_build_bvh_ex")
+        self._adopt(h, mesh.dim, precision, prims.shape[0], verts.shape[0])
+
+    def _adopt(self, h, dim, precision, n_prims, n_verts):
         self.handle = h
-        self.dim = int(mesh.dim)
+        self.dim = int(dim)
         self.precision = int(precision)
-        self.n_prims = int(prims.shape[0])
+        self.n_prims = int(n_prims)
+        self.n_verts = int(n_verts)
         self.device = _torch().cuda.current_device()  # the library builds on the current device
+
+    @classmethod
+    def from_device(cls, dim: int, verts, prims, kind=None, alpha=None, precision: int = F32, stream=None):
+        """A scene from device-resident mesh arrays (``wob_build_bvh_ex``):
+        verts (V, dim) float64, prims (T, dim) int32, kind (T,) uint8 or None,
+        alpha (T,) float64 or None, all on the current device.  Waits for
+        ``stream`` (the current stream if None)."""
+        dev = _torch().cuda.current_device()
+        _need(verts, "verts", _torch().float64, (None, dim), dev)
+        _need(prims, "prims", _torch().int32, (None, dim), dev)
+        T = int(prims.shape[0])
+        _need(kind, "kind", _torch().uint8, (T,), dev, optional=True)
+        _need(alpha, "alpha", _torch().float64, (T,), dev, optional=True)
+        h = C.c_void_p()
+        _check(lib().wob_build_bvh_ex(int(dim), int(precision), verts.data_ptr(), int(verts.shape[0]),
+                                      prims.data_ptr(), T, None if kind is None else kind.data_ptr(),
+                                      None if alpha is None else alpha.data_ptr(), 1, _stream(stream),
+                                      C.byref(h)), "wob_build_bvh_ex")
+        self = cls.__new__(cls)
+        self._adopt(h, dim, precision, T, int(verts.shape[0]))
+        return self
 
     @property
     def dtype(self):
@@ -283,7 +324,7 @@ class Scene:
         return int(v.value)
 
     def lines_per_path(self, bc: BC, walk_len: int) -> int:
-        b = bc.c()
+        b = bc.c(self)
         n = lib().wob_lines_per_path(self.handle, C.byref(b), int(walk_len))
         if n < 0:
             raise WobError("wob_lines_per_path: invalid arguments")
@@ -315,7 +356,7 @@ def solve(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int =
         mean, var = out
         _need(mean, "mean out", scene.dtype, (P,), scene.device)
         _need(var, "var out", scene.dtype, (P,), scene.device, optional=True)
-    b = bc.c()
+    b = bc.c(scene)
     st = lib().wob_solve(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
                          int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(mean),
                          _dev_ptr(var), _stream(stream))
@@ -332,7 +373,7 @@ class Starts:
     def __init__(self, scene: Scene, weight=None, data: Optional["BC"] = None, floor: float = 0.0):
         h = C.c_void_p()
         if data is not None:
-            b = data.c()
+            b = data.c(scene)
             _check(lib().wob_starts_from_data(scene.handle, C.byref(b), float(floor), C.byref(h)),
                    "wob_starts_from_data")
         else:
@@ -365,7 +406,7 @@ def forward_paths(scene: Scene, bc: BC, n_paths: int, walk_len: int, seed: int =
     vtx = out if out is not None else torch.empty((n_paths, walk_len, 4), dtype=scene.dtype, device=dev)
     vp = torch.empty((n_paths, walk_len), dtype=torch.int32, device=dev) if want_vertices else None
     vm = torch.empty((n_paths, walk_len), dtype=torch.int32, device=dev) if want_vertices else None
-    b = bc.c()
+    b = bc.c(scene)
     st = lib().wob_forward_paths(scene.handle, C.byref(b), None if starts is None else starts.handle,
                                  int(n_paths), int(walk_len), C.c_uint64(seed), _dev_ptr(vtx),
                                  _dev_ptr(vp), _dev_ptr(vm), _stream(stream))
@@ -402,7 +443,7 @@ def solve_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
     grad = torch.empty((P, D), dtype=scene.dtype, device=points.device)
     var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
     gvar = torch.empty((P, D), dtype=scene.dtype, device=points.device) if want_var else None
-    b = bc.c()
+    b = bc.c(scene)
     st = lib().wob_solve_grad(scene.handle, _dev_ptr(points), P, C.byref(b), int(samples), int(walk_len),
                               C.c_uint64(seed), _dev_ptr(mean), _dev_ptr(var), _dev_ptr(grad), _dev_ptr(gvar),
                               _stream(stream))
@@ -416,7 +457,7 @@ def trace_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
     P, D = _need_points(scene, points), scene.dim
     path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
     pg = torch.empty((P, samples, D), dtype=scene.dtype, device=points.device)
-    b = bc.c()
+    b = bc.c(scene)
     st = lib().wob_trace_grad(scene.handle, _dev_ptr(points), P, C.byref(b), int(samples), int(walk_len),
                               C.c_uint64(seed), _dev_ptr(path), _dev_ptr(pg), _stream(stream))
     _check(st, "wob_trace_grad")
@@ -452,7 +493,7 @@ def trace(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int =
     path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
     vp = torch.empty((P, samples, L), dtype=torch.int32, device=points.device) if want_vertices else None
     vm = torch.empty((P, samples, L), dtype=torch.int32, device=points.device) if want_vertices else None
-    b = bc.c()
+    b = bc.c(scene)
     st = lib().wob_trace(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
                          int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(point_ids),
                          _dev_ptr(path), _dev_ptr(vp), _dev_ptr(vm), _stream(stream))
@@ -466,7 +507,7 @@ def count_work(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
     P = _need_points(scene, points)
     _need(point_prim, "point_prim", torch.int32, (P,), scene.device, optional=True)
     c = torch.zeros(4, dtype=torch.int64, device=points.device)
-    b = bc.c()
+    b = bc.c(scene)
     st = lib().wob_count_work(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), points.shape[0],
                               C.byref(b), int(samples), int(walk_len), C.c_uint64(seed),
                               _dev_ptr(c), _stream(stream))
@@ -515,7 +556,7 @@ class Batch:
             arr[i].points = _dev_ptr(pts)
             arr[i].point_prim = _dev_ptr(pp)
             arr[i].n_points = P
-            arr[i].bc = p["bc"].c()
+            arr[i].bc = p["bc"].c(scene)
             arr[i].samples = int(p["samples"])
             arr[i].walk_len = int(p["walk_len"])
             arr[i].seed = int(p.get("seed", 0))
@@ -583,7 +624,7 @@ def _problem_table(problems):
         arr[i].points = _dev_ptr(pts)
         arr[i].point_prim = _dev_ptr(pp)
         arr[i].n_points = P
-        arr[i].bc = p["bc"].c()
+        arr[i].bc = p["bc"].c(scene)
         arr[i].samples = int(p["samples"])
         arr[i].walk_len = int(p["walk_len"])
         arr[i].seed = int(p.get("seed", 0))
@@ -712,7 +753,7 @@ def cv_emission(scene: Scene, bc: BC, g=None, stream=None):
     torch = _torch()
     _need(g, "g", torch.float32, (scene.n_prims,), scene.device, optional=True)
     g0 = torch.empty(scene.n_prims, dtype=torch.float32, device=torch.device("cuda", scene.device))
-    b = bc.c()
+    b = bc.c(scene)
     _check(lib().wob_cv_emission(scene.handle, C.byref(b), _dev_ptr(g), _dev_ptr(g0), _stream(stream)),
            "wob_cv_emission")
     return g0
@@ -732,7 +773,7 @@ def solve_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed:
         mean, var = out
         _need(mean, "mean out", scene.dtype, (P,), scene.device)
         _need(var, "var out", scene.dtype, (P,), scene.device, optional=True)
-    b = bc.c()
+    b = bc.c(scene)
     _check(lib().wob_solve_cv(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
                               int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(g0),
                               _dev_ptr(mean), _dev_ptr(var), _stream(stream)), "wob_solve_cv")
@@ -747,7 +788,7 @@ def trace_cv(scene: Scene, points, bc: BC, samples: int, walk_len: int, g, seed:
     _need(g, "g", torch.float32, (scene.n_prims,), scene.device)
     _need(g0, "g0", torch.float32, (scene.n_prims,), scene.device, optional=True)
     path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
-    b = bc.c()
+    b = bc.c(scene)
     _check(lib().wob_trace_cv(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
                               int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(g), _dev_ptr(g0),
                               _dev_ptr(path), _stream(stream)), "wob_trace_cv")

@@ -63,7 +63,7 @@ def test_build_rejects_bad_meshes_on_host():
 
 def test_entry_points_reject_null_scene():
     L = wob.lib()
-    bc = wob.BC().c()
+    bc = wob.BC().c(_StandInScene())
     assert L.wob_lines_per_path(None, C.byref(bc), 4) == -1
     assert L.wob_solve(None, None, None, 0, C.byref(bc), 4, 4, 0, None, None, None) == 1
     assert L.wob_trace(None, None, None, 0, C.byref(bc), 4, 4, 0, None, None, None, None, None) == 1
@@ -81,7 +81,7 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 
 class _StandInScene:
     """Attributes the binding validates against (no device scene behind it)."""
-    dim, n_prims, device, handle = 3, 10, 0, None
+    dim, n_prims, n_verts, device, handle = 3, 10, 7, 0, None
 
     @property
     def dtype(self):
@@ -114,3 +114,47 @@ def test_binding_rejects_mismatched_tensors_before_any_call(case):
     }
     with pytest.raises(wob.WobError):
         calls[case]()
+
+
+@pytest.mark.parametrize("case,match", [("float64", "dtype"), ("short", "shape"), ("2-D", "shape"),
+                                        ("host", "device tensor")])
+def test_vertex_data_is_checked_against_the_scene(case, match):
+    """Per-vertex data must be one value per scene vertex, of the scene's dtype,
+    on its device: the kernels index it by vertex id."""
+    import torch
+    vd = {"float64": torch.zeros(7, dtype=torch.float64), "short": torch.zeros(6),
+          "2-D": torch.zeros((7, 1)), "host": torch.zeros(7)}[case]
+    with pytest.raises(wob.WobError, match=match):
+        wob.BC(1, wob.AUTO, vertex_data=vd).c(_StandInScene())
+
+
+_STRUCTS = [("wob_bc", "_BC"), ("wob_scene_info", "_SceneInfo"), ("wob_problem", "_Problem"),
+            ("wob_tune", "_Tune"), ("wob_target_map", "_TargetMap")]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes mirror of a header struct has the C layout: each field's
+    offset and the total size, as a C compiler lays out include/wob.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "wob.h"', "int main(void) {"]
+    want = {}
+    for cname, pyname in _STRUCTS:
+        st = getattr(wob, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        want[f"{cname} size"] = C.sizeof(st)
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+            want[f"{cname} {f}"] = getattr(st, f).offset
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {ln.rsplit(" ", 1)[0]: int(ln.rsplit(" ", 1)[1]) for ln in out.splitlines()}
+    assert got == want
