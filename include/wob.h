@@ -284,6 +284,16 @@ wob_status wob_trace_grad(wob_scene scene, const void* points, int64_t n_points,
 wob_status wob_gather_probe(const void* buf, int64_t bytes, int64_t lanes, int32_t reads, uint32_t seed,
                             float* out, void* stream);
 
+/* Measurement helper (not part of the method): for each of n_tiles tiles,
+ * D = A B + C with the bfloat16 matrix instruction that wob_mlp_* use
+ * (binary32 accumulation).  a: DEVICE bfloat16, n_tiles x 16 x 32 row-major;
+ * b: DEVICE bfloat16, n_tiles x 32 x 16 row-major; c, d: DEVICE binary32,
+ * n_tiles x 16 x 16 row-major.  Compared with exact dot products it bounds
+ * the instruction's accumulation error, on which the network's parity bound
+ * rests.  Errors: WOB_E_ARG, WOB_E_DEVICE. */
+wob_status wob_mfma_probe(const void* a, const void* b, const float* c, float* d, int64_t n_tiles,
+                          void* stream);
+
 const char* wob_status_string(wob_status status);
 
 /* ------------------------------------------------------------------------- */

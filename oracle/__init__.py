@@ -96,6 +96,9 @@ def lib():
         _lib.orc_mlp_forward.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, vp,
                                          C.c_int, vp]
         _lib.orc_mlp_forward.restype = None
+        _lib.orc_mlp_forward_bound.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, vp,
+                                               vp, C.c_double, C.c_double, C.c_double, vp, vp, vp, vp]
+        _lib.orc_mlp_forward_bound.restype = None
         _lib.orc_mlp_loss_grad.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, vp,
                                            vp, C.c_int, vp]
         _lib.orc_mlp_loss_grad.restype = C.c_double
@@ -402,6 +405,28 @@ def mlp_forward(params, Bmat, y, bf16: bool, n_freq=16, hidden=128, layers=4) ->
     lib().orc_mlp_forward(P.ctypes.data, B.ctypes.data, n_freq, hidden, layers, Y.shape[1], Y.shape[0],
                           Y.ctypes.data, int(bf16), out.ctypes.data)
     return out
+
+
+def mlp_forward_bound(params, Bmat, y, acc, dy=None, n_freq=16, hidden=128, layers=4) -> dict:
+    """The bfloat16-rounded forward pass with, per row, the output layer's
+    magnitude sum ("scale"), the first-order bound of a device evaluation's
+    deviation ("bound": binary32 accumulation and bfloat16 rounding flips,
+    through the exact sensitivities) and the count of activations at risk of a
+    flip ("risk").  acc = (first hidden layer, other hidden layers, output):
+    each layer's accumulation error bound in units of u32 times the magnitude
+    sum of its terms.  dy: per row, the half-width of each input coordinate
+    (an input computed on the device to within dy), or None."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    B = np.ascontiguousarray(Bmat, dtype=np.float64)
+    Y = np.ascontiguousarray(y, dtype=np.float64)
+    n = Y.shape[0]
+    out, scale, bound = np.zeros(n), np.zeros(n), np.zeros(n)
+    risk = np.zeros(n, dtype=np.int32)
+    DY = None if dy is None else np.ascontiguousarray(np.broadcast_to(dy, (n,)), dtype=np.float64)
+    lib().orc_mlp_forward_bound(P.ctypes.data, B.ctypes.data, n_freq, hidden, layers, Y.shape[1], n,
+                                Y.ctypes.data, None if DY is None else DY.ctypes.data, float(acc[0]), float(acc[1]), float(acc[2]), out.ctypes.data,
+                                scale.ctypes.data, bound.ctypes.data, risk.ctypes.data)
+    return {"out": out, "scale": scale, "bound": bound, "risk": risk}
 
 
 def mlp_loss_grad(params, Bmat, y, target, bf16: bool, n_freq=16, hidden=128, layers=4):

@@ -96,6 +96,128 @@ void orc_mlp_forward(const double* params, const double* Bmat, int n_freq, int h
   free(s);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Error bound of a bfloat16 evaluation of the network.                      */
+/*                                                                          */
+/* A device evaluation that rounds to bfloat16 at the same points as the     */
+/* forward pass above, but sums each layer's products in binary32 in its own */
+/* order, differs from it in two ways, both propagated layer by layer as an  */
+/* interval half-width d per value:                                         */
+/* (i) accumulation: a pre-activation carries at most acc u32 times the      */
+/*     magnitude sum of its terms (bias included), `acc` given per layer     */
+/*     kind (first hidden layer, other hidden layers, output layer) by the   */
+/*     caller from the device's summation, on top of its inputs' own         */
+/*     half-widths through |W|;                                             */
+/* (ii) flips: an activation h whose distance to a boundary where its        */
+/*     rounding (to binary32, then bfloat16) changes is within its           */
+/*     half-width dh (|silu'| d_s to first order, plus d_s^2 / 2 with        */
+/*     |silu''| <= 1/2) may round to another bfloat16 value; its rounded     */
+/*     value then differs by at most dh plus one bfloat16 spacing.  Away     */
+/*     from a boundary both sides round alike and the half-width is 0.       */
+/* Flips that cascade (a flip widening a later pre-activation past a         */
+/* boundary) are included; the bound is therefore a worst case over every    */
+/* combination of flips, loose where many activations are near boundaries.  */
+/* Features are exact up to the row's input half-width dy (each coordinate   */
+/* of y may differ by dy; NULL: 0): they are sines and cosines of a binary64 */
+/* argument rounded like the activations, moved by at most 2 pi sum|B| dy.   */
+/* For each row: out = f, scale = sum |w_i a_i| + |b| of the output layer,   */
+/* bound = the output's half-width, risk = activations near a boundary.      */
+/* ------------------------------------------------------------------------ */
+
+#define MLP_U32 (1.0 / 16777216.0)
+
+/* distance from x to the nearest boundary at which its rounding to bfloat16
+   (via binary32, as to_bf16) changes, and the larger bfloat16 spacing there */
+static void bf16_margin(double x, double* dist, double* spacing) {
+  const double r = fabs(to_bf16(x));
+  float fr = (float)r, fu, fd;
+  uint32_t u;
+  memcpy(&u, &fr, 4);
+  const uint32_t uu = u + 0x10000u, ud = u >= 0x10000u ? u - 0x10000u : 0u;
+  memcpy(&fu, &uu, 4);
+  memcpy(&fd, &ud, 4);
+  const double up = 0.5 * (r + (double)fu), dn = 0.5 * (r + (double)fd);
+  const double ax = fabs(x);
+  *dist = fmin(fabs(ax - up), fabs(ax - dn));
+  *spacing = fmax((double)fu - r, r - (double)fd);
+}
+
+void orc_mlp_forward_bound(const double* P, const double* Bm, int n_freq, int hidden, int layers, int dim,
+                           int64_t n, const double* y, const double* dy, double acc_first, double acc_hidden,
+                           double acc_out, double* out, double* scale, double* bound, int32_t* risk) {
+  const int K = n_freq, H = hidden, L = layers, W0 = 2 * K;
+  const int stride = W0 > H ? W0 : H;
+  double* a = (double*)malloc(sizeof(double) * (size_t)2 * stride);
+  double* da = (double*)malloc(sizeof(double) * (size_t)2 * stride);
+  for (int64_t r = 0; r < n; ++r) {
+    const double* yr = y + r * dim;
+    int nrisk = 0;
+    double *cur = a, *dcur = da, *nxt = a + stride, *dnxt = da + stride;
+    for (int k = 0; k < K; ++k) {
+      double arg = 0.0, darg = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        arg += Bm[k * dim + d] * yr[d];
+        darg += fabs(Bm[k * dim + d]) * (dy ? dy[r] : 0.0);
+      }
+      const double f2[2] = {sin(2.0 * MLP_PI * arg), cos(2.0 * MLP_PI * arg)};
+      for (int q = 0; q < 2; ++q) {
+        const double df = 2.0 * MLP_PI * darg;
+        double dist, sp;
+        bf16_margin(f2[q], &dist, &sp);
+        cur[q * K + k] = to_bf16(f2[q]);
+        dcur[q * K + k] = (df > 0.0 && dist <= df + MLP_U32 * fabs(f2[q])) ? df + sp : 0.0;
+      }
+    }
+    const double* p = P;
+    int in = W0;
+    for (int l = 0; l < L; ++l) {
+      const double* W = p;
+      const double* b = p + (int64_t)H * in;
+      const double acc = l == 0 ? acc_first : acc_hidden;
+      for (int o = 0; o < H; ++o) {
+        double s = b[o], mag = fabs(b[o]), prop = 0.0;
+        for (int i = 0; i < in; ++i) {
+          const double w = to_bf16(W[o * in + i]);
+          s += w * cur[i];
+          mag += fabs(w) * (fabs(cur[i]) + dcur[i]);
+          prop += fabs(w) * dcur[i];
+        }
+        const double ds = prop + acc * MLP_U32 * mag;
+        const double sg = 1.0 / (1.0 + exp(-s));
+        const double h = s * sg;
+        const double dh = (fabs(sg * (1.0 + s * (1.0 - sg))) + 0.25 * ds) * ds;
+        double dist, sp;
+        bf16_margin(h, &dist, &sp);
+        nxt[o] = to_bf16(h);
+        if (dist <= dh + MLP_U32 * fabs(h)) {
+          ++nrisk;
+          dnxt[o] = dh + sp;
+        } else {
+          dnxt[o] = 0.0;
+        }
+      }
+      double* t = cur; cur = nxt; nxt = t;
+      t = dcur; dcur = dnxt; dnxt = t;
+      p = b + H;
+      in = H;
+    }
+    double f = p[H], mag = fabs(p[H]), mag_dev = fabs(p[H]), prop = 0.0;
+    for (int i = 0; i < H; ++i) {
+      const double w = to_bf16(p[i]);
+      f += w * cur[i];
+      mag += fabs(w * cur[i]);
+      mag_dev += fabs(w) * (fabs(cur[i]) + dcur[i]);
+      prop += fabs(w) * dcur[i];
+    }
+    out[r] = f;
+    scale[r] = mag;
+    bound[r] = prop + acc_out * MLP_U32 * mag_dev;
+    risk[r] = nrisk;
+  }
+  free(a);
+  free(da);
+}
+
 /* Mean squared error over the batch and its gradient w.r.t. every parameter. */
 double orc_mlp_loss_grad(const double* params, const double* Bmat, int n_freq, int hidden,
                          int layers, int dim, int64_t n, const double* y, const double* target,

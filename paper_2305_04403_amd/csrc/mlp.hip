@@ -50,7 +50,15 @@ struct Net {
 // SiLU with the hardware reciprocal (1 ulp; the result is rounded to bfloat16
 // or multiplies a bfloat16-rounded gradient, so an IEEE division buys nothing)
 __device__ __forceinline__ float sigmoid_(float s) { return __builtin_amdgcn_rcpf(1.f + __expf(-s)); }
-__device__ __forceinline__ float silu(float s) { return s * sigmoid_(s); }
+// The activation that is rounded to bfloat16 is evaluated in binary64 from the
+// binary32 pre-activation and rounded to binary32 and then to bfloat16: its
+// only departure from exact arithmetic is then the accumulation of s, so a
+// rounding of h flips (to the neighbouring bfloat16) only where h lies within
+// that accumulation error of a rounding boundary.
+__device__ __forceinline__ float silu_rounded(float s) {
+  const double d = (double)s;
+  return (float)(d / (1.0 + exp(-d)));
+}
 __device__ __forceinline__ float silu_grad(float s) {
   const float sg = sigmoid_(s);
   return sg * (1.f + s * (1.f - sg));
@@ -111,9 +119,17 @@ __device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n,
     const int64_t row = r0 + r;
     float sv = 0.f, cv = 0.f;
     if (row < n) {
-      float arg = 0.f;
-      for (int d = 0; d < net.dim; ++d) arg += net.fourier[k * net.dim + d] * y[row * net.dim + d];
-      sincospif(2.f * arg, &sv, &cv);
+      // B y in binary64 (each product of two binary32 values is exact), the
+      // period taken out exactly, sin and cos of 2 pi (B y) in binary64: the
+      // features are then the binary32 roundings of the exact values except
+      // within ~1e-16 of a rounding boundary
+      double arg = 0.0;
+      for (int d = 0; d < net.dim; ++d) arg += (double)net.fourier[k * net.dim + d] * (double)y[row * net.dim + d];
+      const double r = arg - rint(arg);  // exact (Sterbenz), in [-1/2, 1/2]
+      double sd, cd;
+      sincospi(2.0 * r, &sd, &cd);
+      sv = (float)sd;
+      cv = (float)cd;
     }
     a0[r * F0 + k] = (__bf16)sv;
     a0[r * F0 + KF + k] = (__bf16)cv;
@@ -157,7 +173,7 @@ __device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n,
         const int r = wave * 16 + 4 * (lane >> 4) + v;
         const float s = acc[cb][v] + b[col];
         if (sbuf) sbuf[(l * TR + r) * HD + col] = s;
-        O[r * HD + col] = (__bf16)silu(s);
+        O[r * HD + col] = (__bf16)silu_rounded(s);
       }
     }
     __syncthreads();

@@ -34,7 +34,7 @@ EXPORTED = ("wob_build_bvh", "wob_build_bvh_ex", "wob_free", "wob_get_scene_info
             "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary",
             "wob_starts_create", "wob_starts_from_data", "wob_starts_free", "wob_forward_paths",
             "wob_forward_gather", "wob_solve_grad", "wob_trace_grad", "wob_last_device_status",
-            "wob_gather_probe")
+            "wob_gather_probe", "wob_mfma_probe")
 
 
 class WobError(RuntimeError):
@@ -136,6 +136,8 @@ def lib():
         getattr(L, name).restype = C.c_int
     L.wob_gather_probe.argtypes = [vp, i64, i64, i32, C.c_uint32, vp, vp]
     L.wob_gather_probe.restype = C.c_int
+    L.wob_mfma_probe.argtypes = [vp, vp, vp, vp, i64, vp]
+    L.wob_mfma_probe.restype = C.c_int
     L.wob_last_device_status.argtypes = [vp, C.POINTER(C.c_uint64), vp]
     L.wob_last_device_status.restype = C.c_int
     L.wob_solve_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
@@ -462,6 +464,24 @@ def trace_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: 
                               C.c_uint64(seed), _dev_ptr(path), _dev_ptr(pg), _stream(stream))
     _check(st, "wob_trace_grad")
     return path, pg
+
+
+def mfma_probe(a, b, c, stream=None):
+    """D = A B + C per tile on the network's bfloat16 matrix instruction
+    (``wob_mfma_probe``): a (T, 16, 32) and b (T, 32, 16) bfloat16, c
+    (T, 16, 16) float32, all on one device; returns d like c."""
+    torch = _torch()
+    if not isinstance(a, torch.Tensor):
+        raise WobError("a: expected a torch tensor")
+    T = int(a.shape[0]) if a.dim() == 3 else -1
+    dev = a.device.index if a.is_cuda else None
+    _need(a, "a", torch.bfloat16, (T, 16, 32), dev)
+    _need(b, "b", torch.bfloat16, (T, 32, 16), dev)
+    _need(c, "c", torch.float32, (T, 16, 16), dev)
+    d = torch.empty_like(c)
+    _check(lib().wob_mfma_probe(a.data_ptr(), b.data_ptr(), c.data_ptr(), d.data_ptr(), T, _stream(stream)),
+           "wob_mfma_probe")
+    return d
 
 
 def gather_probe(buf, lanes: int, reads: int, seed: int = 0, out=None, stream=None):

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.test_oracle_cv_pins import rand_net
+from tests.test_oracle_cv_pins import MLP_ACC, rand_net
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +24,45 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
+# a 32-product bfloat16 matrix instruction's binary32 accumulation error, in
+# units of u32 times the magnitude sum of its terms (C included): at most 6
+# roundings on any path of a tree sum of 32 products and C (measured: 3.3);
+# the network bound's per-layer figures are built from it
+MFMA_ACC = 6.0
+
+
+@pytest.mark.parametrize("case", ["random", "random-with-C", "cancelling", "cancelling-with-C"])
+def test_mfma_accumulation_error_is_bounded(W, case):
+    """The matrix instruction the network uses, against exact dot products
+    (the products of bfloat16 values and their sums over a bounded exponent
+    range are exact in binary64): every result within MFMA_ACC u32 times
+    |C| + sum |a b|, and the per-layer figures of the bound follow from it."""
+    assert MLP_ACC[0] == MFMA_ACC + 1 and MLP_ACC[1] == 4 * MFMA_ACC + 1
+    rng = np.random.default_rng(["random", "random-with-C", "cancelling", "cancelling-with-C"].index(case))
+    T = 4096
+    a = rng.uniform(-1, 1, (T, 16, 32)) * np.exp2(rng.integers(-4, 4, (T, 16, 32)))
+    b = rng.uniform(-1, 1, (T, 32, 16))
+    ta = torch.as_tensor(a, dtype=torch.float32).to(torch.bfloat16)
+    tb = torch.as_tensor(b, dtype=torch.float32).to(torch.bfloat16)
+    if case.startswith("cancelling"):
+        # the second half of each row's products nearly cancels the first half
+        ta[:, :, 16:] = -ta[:, :, :16]
+        tb[:, 16:, :] = tb[:, :16, :] * (1 + torch.as_tensor(rng.integers(0, 2, (T, 16, 16)) * 2.0 ** -7,
+                                                              dtype=torch.bfloat16))
+    c = rng.uniform(-64, 64, (T, 16, 16)) if case.endswith("with-C") else np.zeros((T, 16, 16))
+    tc = torch.as_tensor(c, dtype=torch.float32)
+    d = W.mfma_probe(ta.cuda(), tb.cuda(), tc.cuda())
+    torch.cuda.synchronize()
+    A, Bm, Cm = ta.double().numpy(), tb.double().numpy(), tc.double().numpy()
+    exact = np.matmul(A, Bm) + Cm
+    mag = np.matmul(np.abs(A), np.abs(Bm)) + np.abs(Cm)
+    err = np.abs(d.cpu().double().numpy() - exact)
+    ratio = err / np.maximum(2.0 ** -24 * mag, 1e-300)
+    print(f"{case}: max err / (u sum|terms|) {ratio.max():.3f}, results not correctly rounded "
+          f"{np.mean(d.cpu().double().numpy() != exact.astype(np.float32)):.3f}")
+    assert np.all(ratio <= MFMA_ACC)
+
+
 def test_forward_matches_bf16_oracle(W):
     params, B = rand_net(11)
     params, B = f32(params), f32(B)
@@ -32,14 +71,16 @@ def test_forward_matches_bf16_oracle(W):
     out = net.forward(torch.as_tensor(y, dtype=torch.float32, device="cuda"))
     torch.cuda.synchronize()
     g = out.cpu().double().numpy()
-    o = oracle.mlp_forward(params, B, y, bf16=True)
-    rel = np.abs(g - o) / np.maximum(np.abs(o), 1e-3)
-    print(f"forward: median rel {np.median(rel):.2e}, 99% {np.quantile(rel, 0.99):.2e}, "
-          f"within 1e-5: {np.mean(rel <= 1e-5):.3f}, normwise {np.linalg.norm(g - o) / np.linalg.norm(o):.2e}")
-    # identical rounding points: most outputs agree to binary32 accumulation error;
-    # the rest differ by an occasional bfloat16 rounding flip
-    assert np.median(rel) < 1e-5
-    assert np.linalg.norm(g - o) <= 2e-3 * np.linalg.norm(o)
+    res = oracle.mlp_forward_bound(params, B, y, MLP_ACC)
+    o, S = res["out"], res["scale"]
+    d = np.abs(g - o)
+    print(f"forward: within 1e-5 S: {np.mean(d <= 1e-5 * S):.4f}, max d/S {np.max(d / S):.2e}, "
+          f"max d/bound {np.max(d / res['bound']):.3f}, rows with an activation at risk "
+          f"{np.mean(res['risk'] > 0):.3f}, normwise {np.linalg.norm(g - o) / np.linalg.norm(o):.2e}")
+    # the plain bar on all but the rows where an accumulation difference flipped
+    # a bfloat16 rounding; those (and every row) inside the derived bound
+    assert np.mean(d <= 1e-5 * S) >= 0.99
+    assert np.all(d <= res["bound"])
     net.close()
 
 
@@ -55,15 +96,16 @@ def test_gradient_matches_bf16_oracle(W):
     torch.cuda.synchronize()
     lo, go = oracle.mlp_loss_grad(params, B, y, t, bf16=True)
     gg = grad.cpu().double().numpy()
-    assert loss.item() == pytest.approx(lo, rel=2e-3)
+    assert loss.item() == pytest.approx(lo, rel=1e-5)
     err = np.linalg.norm(gg - go) / np.linalg.norm(go)
-    print(f"gradient normwise relative error {err:.2e}")
-    assert err <= 1e-2
+    print(f"gradient normwise relative error {err:.2e}, loss rel {abs(loss.item() - lo) / lo:.2e}")
+    assert err <= 1e-3
     # per layer block
     offs = [0, 4096, 4224, 20608, 20736, 37120, 37248, 53632, 53760, 53888, 53889]
     for a, b in zip(offs[:-1], offs[1:]):
         e = np.linalg.norm(gg[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-12)
-        assert e <= 2e-2, (a, b, e)
+        print(f"  block {a}:{b} normwise {e:.2e}")
+        assert e <= 1e-3, (a, b, e)
     net.close()
 
 
@@ -84,8 +126,8 @@ def test_target_map_is_applied_inside_the_loss(W):
     tm = np.clip((t.astype(np.float64) - shift) / scale, -clip, clip)
     assert np.sum(np.abs(tm) == clip) > 20  # the clamp is exercised
     lo, go = oracle.mlp_loss_grad(params, B, y, tm, bf16=True)
-    assert loss.item() == pytest.approx(lo, rel=2e-3)
-    assert np.linalg.norm(grad.cpu().double().numpy() - go) <= 1e-2 * np.linalg.norm(go)
+    assert loss.item() == pytest.approx(lo, rel=1e-5)
+    assert np.linalg.norm(grad.cpu().double().numpy() - go) <= 1e-3 * np.linalg.norm(go)
     with pytest.raises(W.WobError):
         net.backward(torch.as_tensor(y, dtype=torch.float32, device="cuda"),
                      torch.as_tensor(t, dtype=torch.float32, device="cuda"), target_map=(0.0, 0.0, 1.0))

@@ -82,6 +82,71 @@ def test_mlp_bf16_rounding_matches_torch():
         assert oracle.bf16_round(v) == torch.tensor(v, dtype=torch.float64).to(torch.bfloat16).item()
 
 
+# accumulation error bounds of the device's sums, in units of u32 times the
+# magnitude sum of the terms (bias included): a 32-product matrix instruction
+# taken as a binary tree of binary32 additions (5 levels) plus its
+# accumulator input (6 roundings on any path), + the bias add (first layer);
+# four chained instructions + the bias add (other hidden layers); a sequential
+# binary32 sum of 32 exact products, two shuffle adds and the bias (output)
+MLP_ACC = (7.0, 25.0, 35.0)
+
+
+def _perturbed_mlp(params, B, y, noise: float, seed: int, keep_weight_layer=None):
+    """The bfloat16 network evaluated another way: float64 sums with each
+    pre-activation (and the output) moved by a uniform fraction `noise` of its
+    accumulation bound (MLP_ACC u32 times its magnitude sum), the activation
+    evaluated from it and rounded like the device.  With `keep_weight_layer`,
+    that layer's weights are left unrounded (a planted mistake the bound must
+    not cover)."""
+    rng = np.random.default_rng(seed)
+    u = 2.0 ** -24
+    p = torch.as_tensor(params)
+    Y = torch.as_tensor(y)
+    q = lambda t: t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    arg = 2 * np.pi * (Y @ torch.as_tensor(B).T)
+    a = q(torch.cat([torch.sin(arg), torch.cos(arg)], dim=1))
+    o, n_in = 0, 2 * K
+    for l in range(L + 1):
+        n_out = 1 if l == L else H
+        W = p[o:o + n_out * n_in].reshape(n_out, n_in)
+        o += n_out * n_in
+        b = p[o:o + n_out]
+        o += n_out
+        Wq = W if keep_weight_layer == l else q(W)
+        s = a @ Wq.T + b
+        mag = a.abs() @ Wq.abs().T + b.abs()
+        acc = MLP_ACC[0] if l == 0 else MLP_ACC[2] if l == L else MLP_ACC[1]
+        s = s + torch.as_tensor(rng.uniform(-1, 1, s.shape)) * noise * acc * u * mag
+        if l == L:
+            return s[:, 0]
+        a = q(torch.nn.functional.silu(s))
+        n_in = H
+
+
+def test_mlp_forward_bound_covers_other_evaluations():
+    """The bound of a bfloat16 device evaluation: its output is the bfloat16
+    forward pass; it covers evaluations whose every pre-activation carries up
+    to the allowed accumulation error (which flip bfloat16 roundings, and
+    cascade); a planted mistake (one layer's weights left unrounded) leaves
+    most rows outside the plain 1e-5 bar and many outside the bound."""
+    params, B = rand_net(21)
+    y = np.random.default_rng(22).uniform(-1.5, 1.5, (3000, 3))
+    res = oracle.mlp_forward_bound(params, B, y, MLP_ACC)
+    np.testing.assert_array_equal(res["out"], oracle.mlp_forward(params, B, y, bf16=True))
+    assert np.all(res["bound"] > 0) and np.median(res["bound"] / res["scale"]) < 1e-2
+    for noise, seed in ((0.0, 1), (1.0, 2), (1.0, 3), (0.3, 4), (1.0, 6), (1.0, 7)):
+        f = _perturbed_mlp(params, B, y, noise, seed).numpy()
+        d = np.abs(f - res["out"])
+        assert np.all(d <= res["bound"]), (noise, float(np.max(d / res["bound"])))
+        if noise == 1.0:
+            assert np.mean(d > 1e-5 * res["scale"]) > 0.1  # flips happen, and are covered
+    for layer in (0, 2, 4):
+        f = _perturbed_mlp(params, B, y, 0.0, 5, keep_weight_layer=layer).numpy()
+        d = np.abs(f - res["out"])
+        assert np.mean(d <= 1e-5 * res["scale"]) < 0.1, layer
+        assert np.mean(d > res["bound"]) > 0.05, layer
+
+
 def test_mlp_gradient_matches_autograd_and_finite_differences():
     params, B = rand_net(5)
     rng = np.random.default_rng(6)
