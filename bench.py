@@ -166,7 +166,8 @@ def parse():
     p.add_argument("--cpu-sample-points", type=int, default=16)
     p.add_argument("--skip-cpu-baseline", action="store_true")
     p.add_argument("--legs", default="main,slice,circle,batched,cv,forward,grad",
-                   help="comma-separated subset of main, slice, circle, batched, cv, forward, grad")
+                   help="comma-separated subset of main, slice, circle, batched, cv, forward, grad, "
+                        "cv_decomposition (not in the default set)")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device once (a kernel of known "
                         "traffic that calibrates hardware byte counters)")
@@ -271,15 +272,43 @@ def batched_leg(torch, wob, I, cal, steps=2):
             "bvh_build_s": t_build, "median_relative_rmse_vs_analytic": float(np.median(rel)), **roof}
 
 
-def cv_leg(torch, wob, I):
+def _boot_ratio(mse_a, mse_b, med_a, med_b, reps=4000, seed=0):
+    """Paired bootstrap over seeds of sqrt(mean mse_a / mean mse_b) and of the
+    ratio of mean median errors: the point estimates and 95 % intervals."""
+    import math
+    mse_a, mse_b, med_a, med_b = (np.asarray(v, dtype=np.float64) for v in (mse_a, mse_b, med_a, med_b))
+    rng = np.random.default_rng(seed)
+    k = len(mse_a)
+    idx = rng.integers(0, k, (reps, k))
+    r = np.sqrt(mse_a[idx].mean(1) / mse_b[idx].mean(1))
+    q = med_a[idx].mean(1) / med_b[idx].mean(1)
+    return {"rmse_ratio": math.sqrt(mse_a.mean() / mse_b.mean()),
+            "rmse_ratio_95": [float(np.quantile(r, 0.025)), float(np.quantile(r, 0.975))],
+            "median_err_ratio": float(med_a.mean() / med_b.mean()),
+            "median_err_ratio_95": [float(np.quantile(q, 0.025)), float(np.quantile(q, 0.975))]}
+
+
+def _tail_shares(vals):
+    """Share of the sum of squared per-path deviations (from each point's mean)
+    carried by the most extreme 0.01 %, 0.1 % and 1 % of paths."""
+    v = vals.double().cpu().numpy()
+    sq = np.sort(((v - v.mean(axis=1, keepdims=True)) ** 2).ravel())[::-1]
+    tot = max(sq.sum(), 1e-300)
+    return {f"top_{q * 100:g}%": float(sq[: max(1, int(q * sq.size))].sum() / tot) for q in (1e-4, 1e-3, 1e-2)}
+
+
+def cv_leg(torch, wob, I, n_seeds=10):
     """Equal wall time on the 1M points: plain WoB at 512 paths against the
     corrected estimator with (a) g = g0 = 0 (hit-selection Rao-Blackwellisation
-    only), (b) g = 0, g0 = line-0 emission at the centroid, (c) the learned
-    network (fit included in its time) and (d) the same without the fit time;
-    and plain resampled importance sampling (4 and 16 area candidates) in place
-    of line sampling.  Every variant runs with 3 seeds and reports the RMSE
-    pooled over them (the single-layer weights are heavy-tailed, so one seed's
-    RMSE is noisy) and the median error."""
+    only), (b) the learned network (fit included in its time) and (c) the same
+    without the fit time; and plain resampled importance sampling (4 and 16
+    area candidates) in place of line sampling.  Every variant runs with
+    `n_seeds` seeds; RMSE ratios pool the per-seed squared errors and carry a
+    paired bootstrap 95 % interval over the seeds.  Also the per-point
+    variance of each variant (paired log ratio against (a) on the same seeds)
+    and the share of the squared path deviations that the most extreme paths
+    carry (2000 points x 512 paths)."""
+    import dataclasses
     import math
     from paper_2305_04403_amd import cv as CV
     w = I.config_tori()
@@ -290,42 +319,44 @@ def cv_leg(torch, wob, I):
     N, M = w.samples, w.walk_len
     sync = torch.cuda.synchronize
     ex = w.exact
-
-    def score(m):
-        a = m.double().cpu().numpy()
-        return math.sqrt(np.mean((a - ex) ** 2)), float(np.median(np.abs(a - ex)))
+    zero = torch.zeros(scene.n_prims, dtype=torch.float32, device="cuda")
 
     # first launches load code objects: warm every kernel of both pipelines on small inputs
     wob.solve(scene, pts[:4096].contiguous(), bc, 64, M, point_prim=pp[:4096].contiguous())
-    warm = CV.LearnedControlVariate(scene, bc, M, CV.CVConfig(n_train=32768, epochs=1))
+    warm = CV.LearnedControlVariate(scene, bc, M, CV.CVConfig(n_train=32768))
     warm.fit()
     warm.solve(pts[:4096].contiguous(), 64, point_prim=pp[:4096].contiguous())
     warm.close()
     sync()
 
-    seeds = (11, 12, 13)
+    seeds = tuple(range(11, 11 + n_seeds))
 
-    def pooled(runs):
-        """RMSE pooled over seeds (mean of the per-seed squared errors), median error, time."""
-        mse = [np.mean((m.double().cpu().numpy() - ex) ** 2) for m, _ in runs]
-        med = [np.median(np.abs(m.double().cpu().numpy() - ex)) for m, _ in runs]
-        return (math.sqrt(float(np.mean(mse))), float(np.mean(med)),
-                [math.sqrt(float(v)) for v in mse], float(np.mean([v.double().mean().item() for _, v in runs])))
+    def record(runs, times, extra_s=0.0):
+        a = [m.double().cpu().numpy() for m, _ in runs]
+        mse = [float(np.mean((x - ex) ** 2)) for x in a]
+        med = [float(np.median(np.abs(x - ex))) for x in a]
+        var = np.mean([v.double().cpu().numpy() for _, v in runs], axis=0)
+        return {"seconds": extra_s + float(np.mean(times)), "rmse": math.sqrt(float(np.mean(mse))),
+                "rmse_per_seed": [math.sqrt(x) for x in mse], "median_abs_err": float(np.mean(med)),
+                "mean_var": float(var.mean()), "median_var": float(np.median(var)),
+                "_mse": mse, "_med": med, "_var": var}
 
-    runs, times = [], []
-    for sd in seeds:
-        t0 = time.perf_counter()
-        runs.append(wob.solve(scene, pts, bc, N, M, seed=sd, point_prim=pp))
-        sync()
-        times.append(time.perf_counter() - t0)
-    t_plain = float(np.mean(times))
-    rp, ep, per_seed, mv = pooled(runs)
-    out = {"workload": w.name + ", 1M points (10% on the boundary), M=4",
-           "seeds": len(seeds),
-           "plain": {"paths": N, "seconds": t_plain, "rmse": rp, "rmse_per_seed": per_seed,
-                     "median_abs_err": ep, "mean_var": mv}}
+    def timed(fn):
+        runs, times = [], []
+        for sd in seeds:
+            t0 = time.perf_counter()
+            runs.append(fn(sd))
+            sync()
+            times.append(time.perf_counter() - t0)
+        return runs, times
 
-    lcv = CV.LearnedControlVariate(scene, bc, M, CV.CVConfig(epochs=1, target_paths=4))
+    out = {"workload": w.name + ", 1M points (10% on the boundary), M=4", "seeds": len(seeds)}
+    runs, times = timed(lambda sd: wob.solve(scene, pts, bc, N, M, seed=sd, point_prim=pp))
+    plain = record(runs, times)
+    plain["paths"] = N
+    t_plain = plain["seconds"]
+
+    lcv = CV.LearnedControlVariate(scene, bc, M, CV.CVConfig())
     fit = lcv.fit()
     # the network on the matrix cores: forward over 2^20 points (106,752 FLOP each)
     yq = torch.rand((1 << 20, 3), dtype=torch.float32, device="cuda") * 4.0 - 2.0
@@ -340,11 +371,6 @@ def cv_leg(torch, wob, I):
     sync()
     t_mlp = 1e-3 * q0.elapsed_time(q1) / 5
     mlp_tflops = (1 << 20) * 106752 / t_mlp / 1e12
-    zero = torch.zeros_like(lcv.g)
-    t0 = time.perf_counter()
-    e0 = wob.cv_emission(scene, bc)
-    sync()
-    t_e0 = time.perf_counter() - t0
     t0 = time.perf_counter()
     wob.cv_addback(scene, lcv.g0, pts)
     sync()
@@ -358,30 +384,22 @@ def cv_leg(torch, wob, I):
         tt.append(time.perf_counter() - t0)
     per_path = max((tt[1] - tt[0]) / 64, 1e-9)
     base = max(tt[0] - 64 * per_path, 0.0)   # add-back and launch overheads
+    variants = {"plain": plain}
 
-    def run(name, g, g0, fixed_s, seed0):
+    def run_cv(name, g, g0, fixed_s, seed0):
         n = int(max(16, (t_plain - fixed_s - base) / per_path // 16 * 16))
-        rr, tm = [], []
-        for j, sd in enumerate(seeds):
-            t0 = time.perf_counter()
-            rr.append(wob.solve_cv(scene, pts, bc, n, M, g, seed=sd + 100 * seed0, point_prim=pp, g0=g0))
-            sync()
-            tm.append(time.perf_counter() - t0)
-        r, e, ps, v = pooled(rr)
-        t = float(np.mean(tm))
-        out[name] = {"paths": n, "seconds": fixed_s + t, "solve_s": t, "rmse": r, "rmse_per_seed": ps,
-                     "median_abs_err": e, "mean_var": v, "rmse_ratio": rp / r, "median_err_ratio": ep / e}
+        runs, times = timed(lambda sd: wob.solve_cv(scene, pts, bc, n, M, g, seed=sd + 100 * seed0,
+                                                    point_prim=pp, g0=g0))
+        variants[name] = record(runs, times, fixed_s)
+        variants[name]["paths"] = n
 
-    run("rb_only", zero, zero, 0.0, 3)
-    run("emission_table", zero, e0, t_e0, 4)
-    run("learned", lcv.g, lcv.g0, fit["fit_s"], 5)
-    out["learned"].update({"fit_s": fit["fit_s"], "targets_s": fit["targets_s"], "train_s": fit["train_s"],
-                           "train_steps": fit["train_steps"]})
-    run("learned_inference_only", lcv.g, lcv.g0, 0.0, 6)
-
+    run_cv("rb_only", zero, zero, 0.0, 3)
+    run_cv("learned", lcv.g, lcv.g0, fit["fit_s"], 5)
+    variants["learned"].update({"fit_s": fit["fit_s"], "targets_s": fit["targets_s"], "train_s": fit["train_s"],
+                                "train_steps": fit["train_steps"]})
+    run_cv("learned_inference_only", lcv.g, lcv.g0, 0.0, 6)
     # the paper's sampling for Robin / mixed problems: RIS over area-uniform
     # candidates (16 in the paper; 4 is cheaper than a traced line)
-    import dataclasses
     for C in (4, 16):
         b = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=C)
         wob.solve(scene, pts[:4096].contiguous(), b, 64, M, point_prim=pp[:4096].contiguous())
@@ -393,23 +411,91 @@ def cv_leg(torch, wob, I):
             tt.append(time.perf_counter() - t0)
         pp_cost = max((tt[1] - tt[0]) / 64, 1e-9)
         n = int(max(16, (t_plain - max(tt[0] - 64 * pp_cost, 0.0)) / pp_cost // 16 * 16))
-        rr, tm = [], []
-        for sd in seeds:
-            t0 = time.perf_counter()
-            rr.append(wob.solve(scene, pts, b, n, M, seed=sd + 700 + C, point_prim=pp))
-            sync()
-            tm.append(time.perf_counter() - t0)
-        r, e, ps, v = pooled(rr)
-        out[f"ris_{C}"] = {"paths": n, "seconds": float(np.mean(tm)), "path_cost_vs_line": pp_cost / (t_plain / N),
-                           "rmse": r, "rmse_per_seed": ps, "median_abs_err": e, "mean_var": v,
-                           "rmse_ratio": rp / r, "median_err_ratio": ep / e}
+        runs, times = timed(lambda sd: wob.solve(scene, pts, b, n, M, seed=sd + 700 + C, point_prim=pp))
+        variants[f"ris_{C}"] = record(runs, times)
+        variants[f"ris_{C}"].update({"paths": n, "path_cost_vs_line": pp_cost / (t_plain / N)})
+
+    # the same-paths variance comparison (N paths, seed 11): every variant's
+    # per-point variance against the Rao-Blackwellised one, paired by point
+    v_rb = wob.solve_cv(scene, pts, bc, N, M, zero, seed=11, point_prim=pp, g0=zero)[1].double().cpu().numpy()
+    v_ln = wob.solve_cv(scene, pts, bc, N, M, lcv.g, seed=11, point_prim=pp, g0=lcv.g0)[1].double().cpu().numpy()
+    lr = np.log(np.maximum(v_ln, 1e-30) / np.maximum(v_rb, 1e-30))
+    lr = lr[np.isfinite(lr)]
+    out["learned_vs_rb_same_paths"] = {"mean_log_var_ratio": float(lr.mean()),
+                                       "se": float(lr.std() / math.sqrt(max(len(lr), 1))),
+                                       "median_log_var_ratio": float(np.median(lr))}
+    sub = slice(0, 2000)
+    ps, pps = pts[sub].contiguous(), pp[sub].contiguous()
+    out["tail_share_of_squared_deviation"] = {
+        "plain": _tail_shares(wob.trace(scene, ps, bc, N, M, seed=11, point_prim=pps)[0]),
+        "rb_only": _tail_shares(wob.trace_cv(scene, ps, bc, N, M, zero, seed=11, point_prim=pps, g0=zero)),
+        "ris_16": _tail_shares(wob.trace(scene, ps, dataclasses.replace(bc, sampling=wob.SAMPLE_RIS,
+                                                                         candidates=16),
+                                         N, M, seed=11, point_prim=pps)[0])}
+    for name, r in variants.items():
+        if name != "plain":
+            r.update(_boot_ratio(plain["_mse"], r["_mse"], plain["_med"], r["_med"]))
+    for name, r in variants.items():
+        for k in ("_mse", "_med", "_var"):
+            r.pop(k)
+        out[name] = r
     out["mlp_forward"] = {"points": 1 << 20, "ms": 1e3 * t_mlp, "TFLOP/s": mlp_tflops, "peak_bf16_TFLOP/s": 2500.0,
                           "frac": mlp_tflops / 2500.0}
     out["addback_s"] = t_add
     out["corrected_path_cost_vs_plain"] = per_path / (t_plain / N)
     out["rmse_ratio_equal_time"] = out["learned"]["rmse_ratio"]
+    out["rmse_ratio_equal_time_95"] = out["learned"]["rmse_ratio_95"]
     out["median_err_ratio_equal_time"] = out["learned"]["median_err_ratio"]
     lcv.close()
+    scene.close()
+    return out
+
+
+def cv_decomposition_leg(torch, wob, I):
+    """Why the density control variate cannot reach large gains on the
+    three-tori problem (not in the default legs; ~1 minute): per-triangle
+    density tables estimated at the centroids by the walk itself with 64,
+    1024 and 16384 paths each (two independent tables at 16384, their
+    correlation), used as the control variate's table on 100k of the points
+    against g = 0 on the same paths."""
+    import math
+    w = I.config_tori()
+    scene = wob.Scene(w.mesh, wob.F32)
+    bc = wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"]))
+    idx = np.random.default_rng(0).choice(len(w.points), 100_000, replace=False)
+    pts = torch.as_tensor(w.points[idx], dtype=torch.float32, device="cuda")
+    pp = torch.as_tensor(w.point_prim[idx], dtype=torch.int32, device="cuda")
+    ex = w.exact[idx]
+    N, M = w.samples, w.walk_len
+    sync = torch.cuda.synchronize
+    zero = torch.zeros(scene.n_prims, dtype=torch.float32, device="cuda")
+    v_rb = wob.solve_cv(scene, pts, bc, N, M, zero, seed=11, point_prim=pp, g0=zero)[1].double().cpu().numpy()
+    cen = torch.as_tensor(w.mesh.verts[w.mesh.prims].mean(axis=1), dtype=torch.float32, device="cuda")
+    ids = torch.arange(scene.n_prims, dtype=torch.int32, device="cuda")
+    dbc = wob.BC(bc.domain, bc.formulation, bc.program, bc.params, density=True)
+    out = {"workload": w.name + ", 100k of the points, 512 paths, M=4"}
+    tables = {}
+    for n_t, sd in ((64, 99), (1024, 99), (16384, 99), (16384, 100)):
+        t0 = time.perf_counter()
+        g, gv = wob.solve(scene, cen, dbc, n_t, M - 1, seed=sd, point_prim=ids)
+        sync()
+        key = f"table_{n_t}" + ("_b" if sd == 100 else "")
+        tables[key] = g.float().contiguous()
+        g0 = wob.cv_emission(scene, bc, tables[key])
+        add = wob.cv_addback(scene, g0, pts).double().cpu().numpy()
+        m, v = wob.solve_cv(scene, pts, bc, N, M, tables[key], seed=11, point_prim=pp, g0=g0)
+        sync()
+        v = v.double().cpu().numpy()
+        lr = np.log(np.maximum(v, 1e-30) / np.maximum(v_rb, 1e-30))
+        out[key] = {"paths_per_triangle": n_t, "seconds": time.perf_counter() - t0,
+                    "median_var_per_path": float(gv.median()), "median_abs_g": float(g.abs().median()),
+                    "mean_var_ratio_vs_rb": float(v.mean() / v_rb.mean()),
+                    "mean_log_var_ratio_vs_rb": float(lr.mean()),
+                    "rmse": float(np.sqrt(np.mean((m.double().cpu().numpy() + add - ex) ** 2)))}
+    a, b = tables["table_16384"].cpu().numpy(), tables["table_16384_b"].cpu().numpy()
+    out["independent_16384_tables"] = {"correlation": float(np.corrcoef(a, b)[0, 1]),
+                                       "median_abs_difference": float(np.median(np.abs(a - b))),
+                                       "median_abs_value": float(np.median(np.abs(a)))}
     scene.close()
     return out
 
@@ -603,6 +689,7 @@ def main():
     leg("circle", "circle", lambda: timed_leg(torch, wob, I.config_circle(), 20, 3, cal, fp64=True))
     leg("batched", "batched", lambda: batched_leg(torch, wob, I, cal))
     leg("cv", "cv_equal_time", lambda: cv_leg(torch, wob, I))
+    leg("cv_decomposition", "cv_decomposition", lambda: cv_decomposition_leg(torch, wob, I))
     leg("forward", "forward_equal_time", lambda: forward_leg(torch, wob, I))
     leg("grad", "gradient", lambda: grad_leg(torch, wob, I))
 

@@ -50,14 +50,24 @@ struct Net {
 // SiLU with the hardware reciprocal (1 ulp; the result is rounded to bfloat16
 // or multiplies a bfloat16-rounded gradient, so an IEEE division buys nothing)
 __device__ __forceinline__ float sigmoid_(float s) { return __builtin_amdgcn_rcpf(1.f + __expf(-s)); }
-// The activation that is rounded to bfloat16 is evaluated in binary64 from the
-// binary32 pre-activation and rounded to binary32 and then to bfloat16: its
-// only departure from exact arithmetic is then the accumulation of s, so a
-// rounding of h flips (to the neighbouring bfloat16) only where h lies within
-// that accumulation error of a rounding boundary.
+// The activation that is rounded to bfloat16: s / (1 + e^-s) correctly
+// rounded to binary32 wherever that decides the bfloat16 rounding.  The fast
+// binary32 evaluation (hardware exp2 of s log2 e, hardware reciprocal) is
+// within (|s| + 3) ulp of the exact value (the product s log2 e carries |s| u
+// of absolute error into the exponent); its bfloat16 rounding can differ from
+// that of the exact value only when it lies that close to a bfloat16 rounding
+// boundary (low half-word 0x8000), and there the value is recomputed in
+// binary64 and rounded once to binary32.  The rounded activation then departs
+// from exact arithmetic only through the accumulation of s.
 __device__ __forceinline__ float silu_rounded(float s) {
-  const double d = (double)s;
-  return (float)(d / (1.0 + exp(-d)));
+  const float h = s * sigmoid_(s);
+  const int lo = (int)(__float_as_uint(h) & 0xffffu);
+  const float win = 8.f + 2.f * fabsf(s);  // ulps, twice the error bound
+  if (fabsf((float)(lo - 0x8000)) <= win) {
+    const double d = (double)s;
+    return (float)(d / (1.0 + exp(-d)));
+  }
+  return h;
 }
 __device__ __forceinline__ float silu_grad(float s) {
   const float sg = sigmoid_(s);

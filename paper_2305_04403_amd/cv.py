@@ -36,8 +36,8 @@ N_FREQ, HIDDEN, LAYERS = 16, 128, 4
 @dataclasses.dataclass
 class CVConfig:
     n_train: int = 2_000_000   # boundary points with one target each
-    target_paths: int = 2      # WoB paths averaged per target
-    epochs: int = 3
+    target_paths: int = 4      # WoB paths averaged per target
+    epochs: int = 1
     batch: int = 16384
     lr: float = 2e-3
     sigma: float = 1.5         # scale of the Fourier frequencies
