@@ -167,7 +167,7 @@ def parse():
     p.add_argument("--skip-cpu-baseline", action="store_true")
     p.add_argument("--legs", default="main,slice,circle,batched,cv,forward,grad",
                    help="comma-separated subset of main, slice, circle, batched, cv, forward, grad, "
-                        "cv_decomposition (not in the default set)")
+                        "cv_decomposition, truncation (the last two not in the default set)")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device once (a kernel of known "
                         "traffic that calibrates hardware byte counters)")
@@ -500,6 +500,57 @@ def cv_decomposition_leg(torch, wob, I):
     return out
 
 
+def truncation_leg(torch, wob, I, grid_n=28, n_points=1000, launches=2, paths=1 << 18):
+    """Truncation bias of the single layer on the three-tori union at about 20k
+    triangles (not in the default legs): for M = 2..6 and three boundary
+    conditions (the benchmark's random Neumann / Robin triangles with Robin
+    coefficient 1; the same with 0.1; every triangle Neumann), the mean over
+    `launches` x `paths` paths at each of `n_points` points off the boundary,
+    the same seeds for every M, so that a path at M + 1 extends the path at M
+    (line i's random numbers depend on i only) and consecutive estimates are
+    paired.  Reports per M the signed error against the analytic solution
+    (median relative, mean with its standard error over the points), the
+    median per-point standard error, and the paired increment from M - 1."""
+    import dataclasses
+    import math
+    w = I.config_tori(grid_n=grid_n, n_points=n_points, boundary_frac=0.0)
+    xs = tuple(w.bc["params"])
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device="cuda")
+    ex = w.exact
+    out = {"workload": f"three tori, {w.mesh.n_prims} triangles, {n_points} points off the boundary, "
+                       f"{launches} x {paths} paths per point per M", "problems": {}}
+    kinds = w.mesh.kind
+    for label, kind, alpha in (("mixed_robin_alpha_1", None, 1.0), ("mixed_robin_alpha_0.1", None, 0.1),
+                               ("neumann", I.NEUMANN, 0.0)):
+        k = kinds if kind is None else np.full(w.mesh.n_prims, kind, np.uint8)
+        mesh = dataclasses.replace(w.mesh, kind=k, alpha=np.where(k == I.ROBIN, alpha, 0.0))
+        scene = wob.Scene(mesh, wob.F32)
+        bc = wob.BC(-1, wob.SINGLE_LAYER, wob.PROG_INVDIST, xs)
+        rows, prev = {}, None
+        for M in range(2, 7):
+            ms, vs = [], []
+            for j in range(launches):
+                m, v = wob.solve(scene, pts, bc, paths, M, seed=1000 + j)
+                ms.append(m.double().cpu().numpy())
+                vs.append(v.double().cpu().numpy())
+            mean = np.mean(ms, axis=0)
+            se = np.sqrt(np.mean(vs, axis=0) / (launches * paths))
+            e = mean - ex
+            rec = {"median_relative_error": float(np.median(e / ex)), "mean_error": float(e.mean()),
+                   "mean_error_se": float(e.std() / math.sqrt(len(e))), "median_point_se": float(np.median(se))}
+            if prev is not None:
+                d = mean - prev
+                rec["increment_mean"] = float(d.mean())
+                rec["increment_se"] = float(d.std() / math.sqrt(len(d)))
+            rows[str(M)] = rec
+            prev = mean
+            print(f"[bench] truncation {label} M={M}: median relative error {rec['median_relative_error']:+.4f}, "
+                  f"median point SE {rec['median_point_se']:.4f}", file=sys.stderr, flush=True)
+        out["problems"][label] = rows
+        scene.close()
+    return out
+
+
 # connection of a point to a forward-path vertex: 3 differences, 3 products and
 # 2 sums for rho^2, one reciprocal square root, one multiply-add = 11
 GATHER_PAIR_FLOP = 11
@@ -690,6 +741,7 @@ def main():
     leg("batched", "batched", lambda: batched_leg(torch, wob, I, cal))
     leg("cv", "cv_equal_time", lambda: cv_leg(torch, wob, I))
     leg("cv_decomposition", "cv_decomposition", lambda: cv_decomposition_leg(torch, wob, I))
+    leg("truncation", "truncation", lambda: truncation_leg(torch, wob, I))
     leg("forward", "forward_equal_time", lambda: forward_leg(torch, wob, I))
     leg("grad", "gradient", lambda: grad_leg(torch, wob, I))
 
