@@ -80,10 +80,10 @@ def lib():
                                       vp, C.c_int64, vp, vp, vp, vp, vp, C.c_int]
         _lib.orc_trace_cv.restype = C.c_int
         _lib.orc_trace_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_uint64, C.c_uint32, C.c_int64,
-                                        vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
+                                        vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
         _lib.orc_trace_grad.restype = C.c_int
         _lib.orc_solve_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
-                                        vp, vp, vp, vp, C.c_int]
+                                        vp, vp, vp, vp, vp, vp, C.c_int]
         _lib.orc_solve_grad.restype = C.c_int
         _lib.orc_forward_paths.argtypes = [vp, vp, vp, C.c_int64, C.c_int, C.c_uint64, C.c_uint32, vp,
                                            C.c_int]
@@ -228,19 +228,31 @@ def solve(mesh: OracleMesh, points: np.ndarray, point_prim: Optional[np.ndarray]
     return mean, var
 
 
+def _anchor_args(anchors, anchor_prim, n_points, dim):
+    if anchors is None and anchor_prim is None:
+        return None, None, None
+    A = np.ascontiguousarray(anchors, dtype=np.float64).reshape(n_points, dim)
+    AP = np.ascontiguousarray(anchor_prim, dtype=np.int32).reshape(n_points)
+    return A, AP, (A, AP)
+
+
 def trace_grad(mesh: OracleMesh, points: np.ndarray, bc: _BC, walk_len: int, seed: int,
-               item_point: np.ndarray, item_path: np.ndarray, problem: int = 0, n_threads: int = 0) -> dict:
+               item_point: np.ndarray, item_path: np.ndarray, problem: int = 0, n_threads: int = 0,
+               anchors=None, anchor_prim=None) -> dict:
     """Per-path value and gradient in x0 (points off the boundary), with the
     magnitude sums, grazing margin and rounding-error bounds (units of u) of
-    each path."""
+    each path.  anchors / anchor_prim (double layer): per point a boundary
+    point and its primitive for the boundary split of the gradient."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     ip = np.ascontiguousarray(item_point, dtype=np.int64)
     ik = np.ascontiguousarray(item_path, dtype=np.int64)
+    A, AP, _keep = _anchor_args(anchors, anchor_prim, pts.shape[0], mesh.dim)
     n = ip.shape[0]
     out = {"value": np.zeros(n), "grad": np.zeros((n, mesh.dim)), "abs_sum": np.zeros(n),
            "grad_abs": np.zeros(n), "graze": np.zeros(n), "err": np.zeros(n), "grad_err": np.zeros(n)}
     rc = lib().orc_trace_grad(mesh.ref, _ptr(pts), C.c_int64(pts.shape[0]), C.byref(bc), C.c_int(walk_len),
                               C.c_uint64(seed), C.c_uint32(problem), C.c_int64(n), _ptr(ip), _ptr(ik),
+                              None if A is None else _ptr(A), None if AP is None else _ptr(AP),
                               _ptr(out["value"]), _ptr(out["grad"]), _ptr(out["abs_sum"]),
                               _ptr(out["grad_abs"]), _ptr(out["graze"]), _ptr(out["err"]),
                               _ptr(out["grad_err"]), C.c_int(n_threads))
@@ -250,15 +262,17 @@ def trace_grad(mesh: OracleMesh, points: np.ndarray, bc: _BC, walk_len: int, see
 
 
 def solve_grad(mesh: OracleMesh, points: np.ndarray, bc: _BC, samples: int, walk_len: int, seed: int,
-               problem: int = 0, n_threads: int = 0):
+               problem: int = 0, n_threads: int = 0, anchors=None, anchor_prim=None):
     """Mean and variance of the value and of the gradient (P, dim) over paths."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     P = pts.shape[0]
+    A, AP, _keep = _anchor_args(anchors, anchor_prim, P, mesh.dim)
     mean, var = np.zeros(P), np.zeros(P)
     g, gv = np.zeros((P, mesh.dim)), np.zeros((P, mesh.dim))
     rc = lib().orc_solve_grad(mesh.ref, _ptr(pts), C.c_int64(P), C.byref(bc), C.c_int(samples),
-                              C.c_int(walk_len), C.c_uint64(seed), C.c_uint32(problem), _ptr(mean), _ptr(var),
-                              _ptr(g), _ptr(gv), C.c_int(n_threads))
+                              C.c_int(walk_len), C.c_uint64(seed), C.c_uint32(problem),
+                              None if A is None else _ptr(A), None if AP is None else _ptr(AP),
+                              _ptr(mean), _ptr(var), _ptr(g), _ptr(gv), C.c_int(n_threads))
     if rc != 0:
         raise ValueError("orc_solve_grad rejected its arguments")
     return mean, var, g, gv

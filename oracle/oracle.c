@@ -729,17 +729,27 @@ typedef struct {
   double value, abs_sum, graze;
   double err;      /* first-order rounding-error bound of the value (units of u) */
   double grad_err; /* and of each gradient component (gradient walks) */
+  /* gradient walks: the derivative weight of step 0, w' = grad_x kernel / p
+     (0 when line 0 found no hit), its magnitude sum and its relative
+     rounding-error bound (units of u) */
+  double wg0[3], wg0_abs, wg0_eps;
 } path_result;
 
+/* i0 = 0: the path from x0 (an evaluation point, or a boundary point with
+   prim0 >= 0).  i0 > 0 (double layer only): the continuation of a path from
+   the boundary point x0 on prim0 taken as its vertex i0, with the random
+   numbers of lines i0, i0 + 1, ... of path (point, path): the emission at x0
+   and every later term, as the path itself carries them after reaching its
+   vertex i0 (the coupled walk of the gradient's boundary split). */
 static path_result one_path(const orc_mesh* m, const double* normals, const area_table* at,
                             const orc_bc* bc, int form, const double* x0, int64_t prim0, int M,
                             uint64_t seed, uint32_t problem, uint32_t point, uint32_t path,
                             int32_t* vprim, int32_t* vm, double* vpos, double* grad,
-                            double* grad_abs) {
+                            double* grad_abs, int i0) {
   const int dim = m->dim;
   const double phi = (double)bc->domain;
   const int L = form == ORC_DIRECT ? M + 1 : M;
-  path_result res = {0.0, 0.0, INFINITY, 0.0, 0.0};
+  path_result res = {0.0, 0.0, INFINITY, 0.0, 0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
   for (int i = 0; i < L; ++i) {
     if (vprim) vprim[i] = -1;
     if (vm) vm[i] = 0;
@@ -749,7 +759,7 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
 
   /* Table 1, Dirichlet: on the boundary the solution is the given value (also
      on the Dirichlet parts of a mixed problem) */
-  if (prim0 >= 0 && !bc->density &&
+  if (i0 == 0 && prim0 >= 0 && !bc->density &&
       (form == ORC_DOUBLE_LAYER || (form == ORC_SINGLE_LAYER && prim_kind(m, prim0) == ORC_DIRICHLET))) {
     res.value = orc_boundary_datum(m, bc, prim0, x0);
     res.abs_sum = fabs(res.value);
@@ -773,8 +783,16 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
      its own derivative; every emission e adds Wg e. */
   const int want_grad = grad != NULL;
   double Wg[3] = {0.0, 0.0, 0.0}, gacc[3] = {0.0, 0.0, 0.0}, Wgabs = 0.0, gabs = 0.0;
+  if (i0 > 0) {
+    /* the double layer's emission at vertex i0 = x0 (halved when it is x_M) */
+    const double k = i0 < M ? 2.0 : 1.0;
+    const double e = k * phi * orc_boundary_datum(m, bc, prim0, x);
+    acc = e;
+    abs_sum = fabs(e);
+    err = emission_err(m, bc, prim0, x, k, 0.0);
+  }
 
-  for (int i = 0; i < L; ++i) {
+  for (int i = i0; i < L; ++i) {
     const int on_gamma = cur >= 0;
     const double xn = norm_d(x, dim);
     uint32_t r0[4];
@@ -1132,6 +1150,9 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
            -m (n - D c rhat) / (2 rho c) (times phi): c rounded by one unit, rho
            moved by Pn, the D c rhat part by D units */
         eWg = form == ORC_SINGLE_LAYER ? 1.0 / cy + 2.0 : Pn / rho + (1.0 + dim) / cy + 2.0;
+        for (int a = 0; a < 3; ++a) res.wg0[a] = wg[a];
+        res.wg0_abs = wgabs;
+        res.wg0_eps = eWg;
       } else {
         for (int a = 0; a < 3; ++a) Wg[a] *= w;
         Wgabs *= wabs;
@@ -1234,7 +1255,7 @@ int orc_trace(const orc_mesh* m, const double* points, const int32_t* point_prim
                              (uint32_t)p, (uint32_t)item_path[it],
                              out->vtx_prim ? out->vtx_prim + it * L : NULL,
                              out->vtx_m ? out->vtx_m + it * L : NULL,
-                             out->vtx_pos ? out->vtx_pos + it * L * m->dim : NULL, NULL, NULL);
+                             out->vtx_pos ? out->vtx_pos + it * L * m->dim : NULL, NULL, NULL, 0);
     if (out->value) out->value[it] = r.value;
     if (out->abs_sum) out->abs_sum[it] = r.abs_sum;
     if (out->graze) out->graze[it] = r.graze;
@@ -1267,7 +1288,7 @@ int orc_solve(const orc_mesh* m, const double* points, const int32_t* point_prim
     int n = 0;
     for (int k = 0; k < samples; ++k) {
       const double val = one_path(m, normals, &at, bc, form, x0, prim0, walk_len, seed, problem,
-                                  (uint32_t)p, (uint32_t)k, NULL, NULL, NULL, NULL, NULL)
+                                  (uint32_t)p, (uint32_t)k, NULL, NULL, NULL, NULL, NULL, 0)
                              .value;
       if (!isfinite(val)) continue;
       v[n++] = val;
@@ -1494,12 +1515,49 @@ int orc_forward_gather(int dim, int64_t n_paths, int walk_len, const double* vtx
 
 /* Per-path values and gradients in x0 for (point, path) items; every point
  * off the boundary (the gradient equations hold inside the domain only). */
+/* The boundary split of the double layer's gradient (Sec. 4.1.3: near the
+ * boundary the first step's kernel grad_x dG/dn_y is hypersingular; split at
+ * the boundary point nearest to x0).  The kernel integrates to zero over the
+ * closed boundary for x0 off it (the double-layer potential of a constant
+ * density is constant on each side), so w' times any quantity independent of
+ * line 0 has mean zero: each path's gradient w' nu^(y_1) becomes
+ * w' (nu^(y_1) - nu^(x*)), nu^(x*) the path's coupled walk from the anchor
+ * x* (on primitive prim*) with the random numbers of its own lines 1, 2, ...
+ * Near x* the two walks start close together and take the same directions,
+ * so the difference, not the hypersingular kernel, sets the noise. */
+static void anchor_split(const orc_mesh* m, const double* normals, const area_table* at, const orc_bc* bc,
+                         int form, const double* anchors, const int32_t* anchor_prim, int64_t p, int walk_len,
+                         uint64_t seed, uint32_t problem, uint32_t path, path_result* r, double* grad,
+                         double* gabs) {
+  /* no anchor for this point, or line 0 found no hit: nothing to subtract */
+  if (anchor_prim[p] < 0 || r->wg0_abs == 0.0) return;
+  double xa[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < m->dim; ++a) xa[a] = anchors[p * m->dim + a];
+  const path_result c = one_path(m, normals, at, bc, form, xa, anchor_prim[p], walk_len, seed, problem,
+                                 (uint32_t)p, path, NULL, NULL, NULL, NULL, NULL, 1);
+  for (int a = 0; a < m->dim; ++a) grad[a] -= r->wg0[a] * c.value;
+  *gabs += r->wg0_abs * c.abs_sum;
+  r->grad_err += r->wg0_abs * c.err + r->wg0_eps * r->wg0_abs * c.abs_sum;
+  if (c.graze < r->graze) r->graze = c.graze;
+}
+
+static int check_anchors(const orc_mesh* m, const orc_bc* bc, const double* anchors,
+                         const int32_t* anchor_prim, int64_t n_points) {
+  if (!anchors && !anchor_prim) return 0;
+  if (!anchors || !anchor_prim) return 1;
+  if (orc_resolve_formulation(m, bc->formulation) != ORC_DOUBLE_LAYER) return 1;
+  for (int64_t p = 0; p < n_points; ++p)
+    if (anchor_prim[p] < -1 || anchor_prim[p] >= m->n_prims) return 1;
+  return 0;
+}
+
 int orc_trace_grad(const orc_mesh* m, const double* points, int64_t n_points, const orc_bc* bc,
                    int walk_len, uint64_t seed, uint32_t problem, int64_t n_items,
-                   const int64_t* item_point, const int64_t* item_path, double* value, double* grad,
-                   double* abs_sum, double* grad_abs, double* graze, double* err, double* grad_err,
-                   int n_threads) {
+                   const int64_t* item_point, const int64_t* item_path, const double* anchors,
+                   const int32_t* anchor_prim, double* value, double* grad, double* abs_sum, double* grad_abs,
+                   double* graze, double* err, double* grad_err, int n_threads) {
   if (check_args(m, bc, walk_len) || bc->density || !grad) return 1;
+  if (check_anchors(m, bc, anchors, anchor_prim, n_points)) return 1;
   const int form = orc_resolve_formulation(m, bc->formulation);
   double* normals = make_normals(m);
   area_table at = make_area_table(m);
@@ -1514,7 +1572,10 @@ int orc_trace_grad(const orc_mesh* m, const double* points, int64_t n_points, co
     for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
     double gabs = 0.0;
     path_result r = one_path(m, normals, &at, bc, form, x0, -1, walk_len, seed, problem, (uint32_t)p,
-                             (uint32_t)item_path[it], NULL, NULL, NULL, grad + it * m->dim, &gabs);
+                             (uint32_t)item_path[it], NULL, NULL, NULL, grad + it * m->dim, &gabs, 0);
+    if (anchors)
+      anchor_split(m, normals, &at, bc, form, anchors, anchor_prim, p, walk_len, seed, problem,
+                   (uint32_t)item_path[it], &r, grad + it * m->dim, &gabs);
     if (value) value[it] = r.value;
     if (abs_sum) abs_sum[it] = r.abs_sum;
     if (grad_abs) grad_abs[it] = gabs;
@@ -1530,9 +1591,11 @@ int orc_trace_grad(const orc_mesh* m, const double* points, int64_t n_points, co
 /* Mean and unbiased variance over paths 0..N-1 of the value and of each
  * gradient component (two-pass), every point off the boundary. */
 int orc_solve_grad(const orc_mesh* m, const double* points, int64_t n_points, const orc_bc* bc,
-                   int samples, int walk_len, uint64_t seed, uint32_t problem, double* mean_out,
-                   double* var_out, double* grad_out, double* grad_var_out, int n_threads) {
+                   int samples, int walk_len, uint64_t seed, uint32_t problem, const double* anchors,
+                   const int32_t* anchor_prim, double* mean_out, double* var_out, double* grad_out,
+                   double* grad_var_out, int n_threads) {
   if (check_args(m, bc, walk_len) || bc->density || samples < 1) return 1;
+  if (check_anchors(m, bc, anchors, anchor_prim, n_points)) return 1;
   const int form = orc_resolve_formulation(m, bc->formulation);
   const int dim = m->dim;
   double* normals = make_normals(m);
@@ -1549,9 +1612,14 @@ int orc_solve_grad(const orc_mesh* m, const double* points, int64_t n_points, co
     double* g = v + samples;
     int n = 0;
     for (int k = 0; k < samples; ++k) {
-      v[n] = one_path(m, normals, &at, bc, form, x0, -1, walk_len, seed, problem, (uint32_t)p, (uint32_t)k,
-                      NULL, NULL, NULL, g + (size_t)n * dim, NULL)
-                 .value;
+      path_result r = one_path(m, normals, &at, bc, form, x0, -1, walk_len, seed, problem, (uint32_t)p,
+                               (uint32_t)k, NULL, NULL, NULL, g + (size_t)n * dim, NULL, 0);
+      if (anchors) {
+        double gabs = 0.0;
+        anchor_split(m, normals, &at, bc, form, anchors, anchor_prim, p, walk_len, seed, problem, (uint32_t)k,
+                     &r, g + (size_t)n * dim, &gabs);
+      }
+      v[n] = r.value;
       int finite = isfinite(v[n]);
       for (int c = 0; c < dim; ++c) finite = finite && isfinite(g[(size_t)n * dim + c]);
       if (finite) ++n;

@@ -171,15 +171,22 @@ int orc_cv_addback(const orc_mesh* mesh, const double* g, const double* points, 
  * hold inside the domain); no density mode.  grad: [n_items * dim];
  * grad_abs: the magnitude sum of the gradient terms (rounding scale); err,
  * grad_err: rounding-error bounds of the value and of each gradient component
- * in units of u (as orc_trace_out.err). */
+ * in units of u (as orc_trace_out.err).
+ * anchors, anchor_prim (double layer only; both NULL or both given): per point
+ * a boundary point x* and its primitive (-1: no split at that point).  Each path's gradient w' nu^(y_1)
+ * (w' the step-0 derivative weight, nu^ the rest of the path) becomes
+ * w' (nu^(y_1) - nu^(x*)), nu^(x*) the coupled walk from x* with the path's
+ * own random numbers of lines 1, 2, ... (the boundary split of Sec. 4.1.3;
+ * unbiased because w' has mean zero for x0 off the closed boundary). */
 int orc_trace_grad(const orc_mesh* mesh, const double* points, int64_t n_points, const orc_bc* bc,
                    int walk_len, uint64_t seed, uint32_t problem, int64_t n_items,
-                   const int64_t* item_point, const int64_t* item_path, double* value, double* grad,
-                   double* abs_sum, double* grad_abs, double* graze, double* err, double* grad_err,
-                   int n_threads);
+                   const int64_t* item_point, const int64_t* item_path, const double* anchors,
+                   const int32_t* anchor_prim, double* value, double* grad, double* abs_sum, double* grad_abs,
+                   double* graze, double* err, double* grad_err, int n_threads);
 int orc_solve_grad(const orc_mesh* mesh, const double* points, int64_t n_points, const orc_bc* bc,
-                   int samples, int walk_len, uint64_t seed, uint32_t problem, double* mean_out,
-                   double* var_out, double* grad_out, double* grad_var_out, int n_threads);
+                   int samples, int walk_len, uint64_t seed, uint32_t problem, const double* anchors,
+                   const int32_t* anchor_prim, double* mean_out, double* var_out, double* grad_out,
+                   double* grad_var_out, int n_threads);
 
 /* Forward (adjoint) estimator of the single layer, all-Neumann boundary
  * (Sec. 4.4.3 "Forward estimator"; see oracle.c for the derivation and the

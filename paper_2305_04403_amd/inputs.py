@@ -376,6 +376,65 @@ def mesh_surface_points(mesh: Mesh, n: int, seed: int) -> Tuple[np.ndarray, np.n
     return pts, prim.astype(np.int32)
 
 
+def _closest_on_triangles(p: np.ndarray, a: np.ndarray, b: np.ndarray, c: np.ndarray) -> np.ndarray:
+    """Closest point to p on triangle (a, b, c), row by row: the point of the
+    plane when its barycentric coordinates are all >= 0, else the closest of
+    the three edge projections (each clamped to its segment)."""
+    ab, ac = b - a, c - a
+    n = np.cross(ab, ac)
+    nn = np.einsum("ij,ij->i", n, n)
+    ap = p - a
+    q = p - (np.einsum("ij,ij->i", ap, n) / nn)[:, None] * n     # projection on the plane
+    aq = q - a
+    d00, d01, d11 = (np.einsum("ij,ij->i", ab, ab), np.einsum("ij,ij->i", ab, ac), np.einsum("ij,ij->i", ac, ac))
+    d20, d21 = np.einsum("ij,ij->i", aq, ab), np.einsum("ij,ij->i", aq, ac)
+    den = d00 * d11 - d01 * d01
+    v = (d11 * d20 - d01 * d21) / den
+    w = (d00 * d21 - d01 * d20) / den
+    inside = (v >= 0) & (w >= 0) & (v + w <= 1)
+    best = q.copy()
+    bd = np.full(len(p), np.inf)
+    for s0, s1 in ((a, b), (b, c), (c, a)):
+        e = s1 - s0
+        t = np.clip(np.einsum("ij,ij->i", p - s0, e) / np.einsum("ij,ij->i", e, e), 0.0, 1.0)
+        r = s0 + t[:, None] * e
+        dd = np.einsum("ij,ij->i", p - r, p - r)
+        take = (~inside) & (dd < bd)
+        best[take] = r[take]
+        bd = np.where(take, dd, bd)
+    return best
+
+
+def nearest_boundary_points(mesh: Mesh, pts: np.ndarray, k: int = 16) -> Tuple[np.ndarray, np.ndarray]:
+    """For each point, the closest boundary point among the k primitives with
+    the nearest centroids, and that primitive's id (the exact nearest point
+    of the mesh whenever it lies on one of those k)."""
+    from scipy.spatial import cKDTree
+    v, t = mesh.verts, mesh.prims
+    cen = v[t].mean(axis=1)
+    k = min(k, len(t))
+    _, cand = cKDTree(cen).query(pts, k=k)
+    cand = np.asarray(cand).reshape(len(pts), k)
+    best = np.zeros_like(pts)
+    bd = np.full(len(pts), np.inf)
+    bp = np.zeros(len(pts), np.int32)
+    for j in range(k):
+        ids = cand[:, j]
+        if mesh.dim == 3:
+            q = _closest_on_triangles(pts, v[t[ids, 0]], v[t[ids, 1]], v[t[ids, 2]])
+        else:
+            a, b = v[t[ids, 0]], v[t[ids, 1]]
+            e = b - a
+            tt = np.clip(np.einsum("ij,ij->i", pts - a, e) / np.einsum("ij,ij->i", e, e), 0.0, 1.0)
+            q = a + tt[:, None] * e
+        dd = np.einsum("ij,ij->i", pts - q, pts - q)
+        take = dd < bd
+        best[take] = q[take]
+        bd[take] = dd[take]
+        bp[take] = ids[take]
+    return best, bp
+
+
 def box_points_outside(n: int, lo: float, hi: float, sdf, margin: float, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     out = []
