@@ -680,38 +680,78 @@ def forward_leg(torch, wob, I):
     return out
 
 
-def grad_leg(torch, wob, I):
+def grad_leg(torch, wob, I, near=0.05):
     """Value and gradient along the same paths on the benchmark workload
-    (icosphere slice, 167,604 points x 256 paths x 6 lines): the time of
+    (icosphere slice, every inside cell x 256 paths x 6 lines): the time of
     wob_solve_grad against wob_solve, and the gradient error against the
-    analytic gradient of g = 1/|x - x0|."""
+    analytic gradient of g = 1/|x - x0|; then the boundary split of the
+    gradient (anchors at the nearest boundary point for the points closer
+    than `near` to the boundary) at equal time, with the error split into the
+    component along the normal at the nearest boundary point and the
+    tangential rest, near the boundary and away from it."""
+    import math
     w = I.config_icosphere_slice()
     scene = wob.Scene(w.mesh, wob.F32)
     bc = wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"]))
     pts = torch.as_tensor(w.points, dtype=torch.float32, device="cuda")
     N, M = w.samples, w.walk_len
+    A, AP = I.nearest_boundary_points(w.mesh, w.points, inset=1e-3)
+    dist = np.linalg.norm(w.points - A, axis=1)
+    is_near = dist < near
+    AP_on = np.where(is_near, AP, -1).astype(np.int32)
+    ta = torch.as_tensor(A, dtype=torch.float32, device="cuda")
+    tp = torch.as_tensor(AP_on, dtype=torch.int32, device="cuda")
+    v, t = w.mesh.verts, w.mesh.prims[AP]
+    nrm = np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
     wob.solve_grad(scene, pts[:4096].contiguous(), bc, 16, M)
+    wob.solve_grad(scene, pts[:4096].contiguous(), bc, 16, M, anchors=ta[:4096].contiguous(),
+                   anchor_prim=tp[:4096].contiguous())
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record(st)
-    m0, _ = wob.solve(scene, pts, bc, N, M, w.seed)
-    ev[1].record(st)
-    mean, var, g, gv = wob.solve_grad(scene, pts, bc, N, M, w.seed)
-    ev[2].record(st)
-    torch.cuda.synchronize()
-    t_val = ev[0].elapsed_time(ev[1])
-    t_grad = ev[1].elapsed_time(ev[2])
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        out = fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1)
+
+    (m0, _), t_val = timed(lambda: wob.solve(scene, pts, bc, N, M, w.seed))
+    (mean, var, g, gv), t_grad = timed(lambda: wob.solve_grad(scene, pts, bc, N, M, w.seed))
     x0 = np.array(w.bc["params"])
     r = w.points - x0
     exact = -r / np.linalg.norm(r, axis=1)[:, None] ** 3
-    gn = g.double().cpu().numpy()
-    err = np.linalg.norm(gn - exact, axis=1)
+
+    def errors(gr):
+        e = gr.double().cpu().numpy() - exact
+        en = np.einsum("ij,ij->i", e, nrm)
+        et = np.linalg.norm(e - en[:, None] * nrm, axis=1)
+        tot = np.linalg.norm(e, axis=1)
+        rm = lambda x, msk: float(np.sqrt(np.mean(x[msk] ** 2))) if msk.any() else None
+        every = np.ones(len(e), bool)
+        return {"rmse": rm(tot, every), "median_err": float(np.median(tot)),
+                "rmse_near": rm(tot, is_near), "rmse_far": rm(tot, ~is_near),
+                "rmse_normal_near": rm(en, is_near), "rmse_tangential_near": rm(et, is_near),
+                "rmse_normal_far": rm(en, ~is_near), "rmse_tangential_far": rm(et, ~is_near)}
+
+    plain = errors(g)
+    # the split at about the same time: scale the paths by the measured cost
+    _, t_probe = timed(lambda: wob.solve_grad(scene, pts, bc, N, M, w.seed, anchors=ta, anchor_prim=tp))
+    n_split = max(8, int(N * t_grad / t_probe) // 8 * 8)
+    (_, _, gs, _), t_split = timed(lambda: wob.solve_grad(scene, pts, bc, n_split, M, w.seed, anchors=ta,
+                                                          anchor_prim=tp))
+    split = errors(gs)
     scene.close()
     return {"workload": w.name, "solve_ms": t_val, "solve_grad_ms": t_grad, "cost_ratio": t_grad / t_val,
-            "grad_rmse": float(np.sqrt(np.mean(err ** 2))), "grad_median_err": float(np.median(err)),
+            "grad_rmse": plain["rmse"], "grad_median_err": plain["median_err"],
             "grad_rms_exact": float(np.sqrt(np.mean(np.sum(exact ** 2, axis=1)))),
-            "value_rmse": float(np.sqrt(np.mean((mean.double().cpu().numpy() - w.exact) ** 2)))}
+            "value_rmse": float(np.sqrt(np.mean((mean.double().cpu().numpy() - w.exact) ** 2))),
+            "plain": dict(plain, paths=N, ms=t_grad),
+            "boundary_split": dict(split, paths=n_split, ms=t_split, near_distance=near,
+                                   points_near=int(is_near.sum()),
+                                   rmse_ratio_equal_time=plain["rmse"] / split["rmse"])}
 
 
 def main():

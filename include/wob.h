@@ -259,20 +259,35 @@ wob_status wob_count_work(wob_scene scene, const void* points, const int32_t* po
  * The double-layer and direct kernels are hypersingular (1 / |c|): noisier
  * near the boundary, as the paper observes.  Every point must lie off the
  * boundary (no point_prim argument); no density mode.
+ * Boundary split (double layer; Sec. 4.1.3 splits the gradient at the
+ * boundary point nearest to x0): with an anchor x* on the boundary, each
+ * path's gradient W' nu becomes W' (nu - nu*), nu the path's sum after its
+ * step 0 and nu* that of a coupled walk which takes x* as its vertex 1 and
+ * then the path's own random numbers of lines 1, 2, ...  Unbiased for any
+ * anchor (W' has mean zero for x0 off the closed boundary); near the boundary
+ * the two walks start close together and take the same directions, which
+ * removes the hypersingular growth of the variance.  A path costs up to two
+ * walks where the split is on.
  *   points        DEVICE, n_points * dim
+ *   anchor_points DEVICE, n_points * dim (scene element type): x* per point, or NULL
+ *   anchor_prim   DEVICE, n_points int32: the primitive (caller id) x* lies on,
+ *                 -1 for no split at that point; NULL with anchor_points NULL.
+ *                 An id outside [-1, n_prims) makes that point's gradient NaN.
  *   mean_out, var_out   as wob_solve (var_out may be NULL)
  *   grad_out      DEVICE, n_points * dim: mean gradient, point-major
  *   grad_var_out  DEVICE, n_points * dim: variance of each component, or NULL
- * Errors: WOB_E_ARG, WOB_E_UNSUPPORTED, WOB_E_DEVICE. */
+ * Errors: WOB_E_ARG, WOB_E_UNSUPPORTED (anchors for another formulation),
+ * WOB_E_DEVICE. */
 wob_status wob_solve_grad(wob_scene scene, const void* points, int64_t n_points, const wob_bc* bc,
-                          int32_t samples, int32_t walk_len, uint64_t seed, void* mean_out, void* var_out,
-                          void* grad_out, void* grad_var_out, void* stream);
+                          int32_t samples, int32_t walk_len, uint64_t seed, const void* anchor_points,
+                          const int32_t* anchor_prim, void* mean_out, void* var_out, void* grad_out,
+                          void* grad_var_out, void* stream);
 
 /* Per-path values (n_points * samples) and gradients (n_points * samples * dim)
- * of the estimator of wob_solve_grad (the same paths). */
+ * of the estimator of wob_solve_grad (the same paths, the same anchors). */
 wob_status wob_trace_grad(wob_scene scene, const void* points, int64_t n_points, const wob_bc* bc,
-                          int32_t samples, int32_t walk_len, uint64_t seed, void* path_out,
-                          void* path_grad_out, void* stream);
+                          int32_t samples, int32_t walk_len, uint64_t seed, const void* anchor_points,
+                          const int32_t* anchor_prim, void* path_out, void* path_grad_out, void* stream);
 
 /* Measurement helper (not part of the method): `lanes` lanes each read
  * `reads` 32-byte records (two 16-byte loads) at independent pseudo-random

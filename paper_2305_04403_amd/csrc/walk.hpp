@@ -46,6 +46,8 @@ struct WalkArgs {
   R* grad_out;                // gradient walk: per point, D components of the mean gradient
   R* grad_var_out;            // and their variances (or null)
   R* path_grad_out;           // gradient walk, trace mode: per path, D components
+  const R* anchor_pts;        // gradient walk, double layer: per point a boundary point (D values) and
+  const int32_t* anchor_prim; // its caller primitive id (-1: no boundary split), or both null
   int32_t* vtx_prim;
   int32_t* vtx_m;
   unsigned long long* counters;
@@ -117,6 +119,9 @@ struct PathState {
   HitAcc<R> h;
   int32_t ni;            // traversal position: an entry, kPop or kDone
   R Wg[3], gacc[3];      // gradient walk: d W / d x0 and the gradient sum
+  R Wg0[3];              // gradient walk: the step-0 derivative weight w'
+  R acc_main;            // boundary split: the path's value while its coupled walk runs
+  bool coupled;          // boundary split: the coupled walk from the anchor is running
 };
 
 // Forward walk: vertex k of the current path, (y_k, c_{k-1} W_k) with
@@ -368,6 +373,11 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
                                           int64_t item, WorkCount& wc) {
   constexpr bool GRAD = EXT == X_GRAD;
   s.path = path;
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.Wg0[k] = 0;
+    s.coupled = false;
+  }
   if constexpr (FORM == F_FWD) {
     // y_1 on the boundary: primitive T from the start table (Philox
     // (id, 0xfffffffe, (problem << 24) | 0xffff03, 0): word 0 against the
@@ -441,6 +451,43 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
 #pragma unroll
     for (int k = 0; k < 3; ++k) s.Wg[k] = s.gacc[k] = 0;
   }
+  return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
+}
+
+// Boundary split of the double layer's gradient (Sec. 4.1.3: the first
+// step's derivative kernel is hypersingular near the boundary; split at a
+// boundary point x* near x0).  The derivative weight w' of step 0 has mean
+// zero for x0 off the closed boundary (the double-layer potential of a
+// constant density is constant on each side), so the path may subtract w'
+// times anything independent of its line 0: w' times the coupled walk from
+// x*, which takes x* as its vertex 1 and then the path's own random numbers of
+// lines 1, 2, ...  Near x* the two walks start close together and take the
+// same directions, so their difference, not the kernel, sets the noise.  This
+// starts that walk (the path's value is kept aside); walk_block subtracts
+// w' times its value when it ends.
+template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
+__device__ __forceinline__ int start_coupled(const WalkArgs<R, D>& a, PathState<R, D>& s, int64_t point,
+                                             int32_t anchor, WorkCount& wc) {
+  s.acc_main = s.acc;
+  s.coupled = true;
+  if (anchor >= a.scene.n_prims) {  // a caller error: the gradient is NaN
+    s.acc = (R)NAN;
+    return ST_DONE;
+  }
+  if (TRACE) s.vp = s.vm = nullptr;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    s.x[k] = k < D ? a.anchor_pts[point * D + k] : (R)0;
+    s.Wg[k] = 0;
+  }
+  s.cur_idx = a.scene.leaf_of_id[anchor];
+  s.W = 1;
+  s.i = 1;
+  // the double layer's emission at vertex 1 (halved when it is x_M)
+  const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
+  R n[3];
+  load_normal<R, D>(a.scene, s.cur_idx, n);
+  s.acc = ((1 < a.M) ? (R)2 * a.phi : a.phi) * boundary_datum<R, D>(a.prog, g, n, s.x);
   return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
@@ -632,7 +679,10 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
         for (int k = 0; k < 3; ++k) wg[k] = f * (n[k] - (R)D * c * sgn_t * s.d[k]);
       }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) s.Wg[k] = s.Wg[k] * w + s.W * wg[k];
+      for (int k = 0; k < 3; ++k) {
+        s.Wg[k] = s.Wg[k] * w + s.W * wg[k];
+        s.Wg0[k] = wg[k];
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < 3; ++k) s.Wg[k] *= w;
@@ -759,6 +809,22 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     for (;;) {
       // finished paths: record, start the lane's next one
       while (st == ST_DONE) {
+        if constexpr (GRAD && FORM == F_DL) {
+          if (s.coupled) {
+            // the coupled walk ended: subtract w' times its value
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s.gacc[c] -= s.Wg0[c] * s.acc;
+            s.acc = s.acc_main;
+            s.coupled = false;
+          } else if (a.anchor_prim) {
+            const int32_t anchor = a.anchor_prim[point];
+            if (anchor >= 0 && (s.Wg0[0] != (R)0 || s.Wg0[1] != (R)0 || s.Wg0[2] != (R)0)) {
+              st = start_coupled<R, D, FORM, TRACE, COUNT, KEXT>(a, s, point, anchor, wc);
+              continue;
+            }
+            if (anchor < -1) s.gacc[0] = (R)NAN;  // a caller error: the gradient is NaN
+          }
+        }
         const R v = s.acc;
         if (TRACE) a.path_out[point * (int64_t)a.N + k] = v;
         bool finite = isfinite(v);

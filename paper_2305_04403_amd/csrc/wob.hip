@@ -329,7 +329,8 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
                     const uint32_t* point_ids, void* mean_out, void* var_out, void* path_out,
                     int32_t* vtx_prim, int32_t* vtx_m, uint64_t* counters, int mode,
                     void* stream, const float* cv_g = nullptr, const float* cv_g0 = nullptr,
-                    void* grad_out = nullptr, void* grad_var_out = nullptr, void* path_grad_out = nullptr) {
+                    void* grad_out = nullptr, void* grad_var_out = nullptr, void* path_grad_out = nullptr,
+                    const void* anchor_pts = nullptr, const int32_t* anchor_prim = nullptr) {
   Plan pl;
   wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
   if (s != WOB_OK) return s;
@@ -339,6 +340,9 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
   const bool grad = grad_out || path_grad_out;
   // gradients: evaluation points inside the domain, no density mode, no control variate
   if (grad && (point_prim || bc->density || cv_g)) return WOB_E_UNSUPPORTED;
+  // the boundary split: both arrays or neither, gradients of the double layer only
+  if ((anchor_pts != nullptr) != (anchor_prim != nullptr)) return WOB_E_ARG;
+  if (anchor_prim && (!grad || pl.form != WOB_F_DOUBLE_LAYER)) return WOB_E_UNSUPPORTED;
   if (grad && mode == MODE_SOLVE && n_points > 0 && !grad_out) return WOB_E_ARG;
   if (mode == MODE_SOLVE && grad_var_out && samples < 2) return WOB_E_ARG;
   if (n_points < 0 || (n_points > 0 && !points)) return WOB_E_ARG;
@@ -358,6 +362,8 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
       a.point_ids = point_ids;
       a.cv_g = cv_g;
       a.cv_g0 = cv_g0 ? cv_g0 : cv_g;
+      a.anchor_pts = (const float*)anchor_pts;
+      a.anchor_prim = anchor_prim;
       launch_walk<float, 3>(a, mode, st);
     } else {
       auto a = make_args<float, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
@@ -365,6 +371,8 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
       a.grad_out = (float*)grad_out; a.grad_var_out = (float*)grad_var_out; a.path_grad_out = (float*)path_grad_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
+      a.anchor_pts = (const float*)anchor_pts;
+      a.anchor_prim = anchor_prim;
       launch_walk<float, 2>(a, mode, st);
     }
   } else {
@@ -374,6 +382,8 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
       a.grad_out = (double*)grad_out; a.grad_var_out = (double*)grad_var_out; a.path_grad_out = (double*)path_grad_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
+      a.anchor_pts = (const double*)anchor_pts;
+      a.anchor_prim = anchor_prim;
       launch_walk<double, 3>(a, mode, st);
     } else {
       auto a = make_args<double, 2>(sc, pl, points, point_prim, n_points, bc, samples, walk_len, seed);
@@ -381,6 +391,8 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
       a.grad_out = (double*)grad_out; a.grad_var_out = (double*)grad_var_out; a.path_grad_out = (double*)path_grad_out;
       a.vtx_prim = vtx_prim; a.vtx_m = vtx_m; a.counters = (unsigned long long*)counters;
       a.point_ids = point_ids;
+      a.anchor_pts = (const double*)anchor_pts;
+      a.anchor_prim = anchor_prim;
       launch_walk<double, 2>(a, mode, st);
     }
   }
@@ -609,21 +621,22 @@ wob_status wob_trace(wob_scene sc, const void* points, const int32_t* point_prim
 }
 
 wob_status wob_solve_grad(wob_scene sc, const void* points, int64_t n_points, const wob_bc* bc,
-                          int32_t samples, int32_t walk_len, uint64_t seed, void* mean_out, void* var_out,
-                          void* grad_out, void* grad_var_out, void* stream) {
+                          int32_t samples, int32_t walk_len, uint64_t seed, const void* anchor_points,
+                          const int32_t* anchor_prim, void* mean_out, void* var_out, void* grad_out,
+                          void* grad_var_out, void* stream) {
   if (n_points > 0 && !grad_out) return WOB_E_ARG;
   return run_walk(sc, points, nullptr, n_points, bc, samples, walk_len, seed, nullptr, mean_out, var_out,
                   nullptr, nullptr, nullptr, nullptr, MODE_SOLVE, stream, nullptr, nullptr,
-                  n_points > 0 ? grad_out : nullptr, grad_var_out, nullptr);
+                  n_points > 0 ? grad_out : nullptr, grad_var_out, nullptr, anchor_points, anchor_prim);
 }
 
 wob_status wob_trace_grad(wob_scene sc, const void* points, int64_t n_points, const wob_bc* bc,
-                          int32_t samples, int32_t walk_len, uint64_t seed, void* path_out,
-                          void* path_grad_out, void* stream) {
+                          int32_t samples, int32_t walk_len, uint64_t seed, const void* anchor_points,
+                          const int32_t* anchor_prim, void* path_out, void* path_grad_out, void* stream) {
   if (n_points > 0 && (!path_out || !path_grad_out)) return WOB_E_ARG;
   return run_walk(sc, points, nullptr, n_points, bc, samples, walk_len, seed, nullptr, nullptr, nullptr,
                   path_out, nullptr, nullptr, nullptr, MODE_TRACE, stream, nullptr, nullptr, nullptr, nullptr,
-                  n_points > 0 ? path_grad_out : nullptr);
+                  n_points > 0 ? path_grad_out : nullptr, anchor_points, anchor_prim);
 }
 
 wob_status wob_count_work(wob_scene sc, const void* points, const int32_t* point_prim,

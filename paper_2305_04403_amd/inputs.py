@@ -405,10 +405,13 @@ def _closest_on_triangles(p: np.ndarray, a: np.ndarray, b: np.ndarray, c: np.nda
     return best
 
 
-def nearest_boundary_points(mesh: Mesh, pts: np.ndarray, k: int = 16) -> Tuple[np.ndarray, np.ndarray]:
+def nearest_boundary_points(mesh: Mesh, pts: np.ndarray, k: int = 16,
+                            inset: float = 0.0) -> Tuple[np.ndarray, np.ndarray]:
     """For each point, the closest boundary point among the k primitives with
     the nearest centroids, and that primitive's id (the exact nearest point
-    of the mesh whenever it lies on one of those k)."""
+    of the mesh whenever it lies on one of those k).  With inset > 0 each
+    point moves that fraction of the way to its primitive's centroid, off the
+    primitive's edges and vertices (where a nearest point often lies)."""
     from scipy.spatial import cKDTree
     v, t = mesh.verts, mesh.prims
     cen = v[t].mean(axis=1)
@@ -432,6 +435,8 @@ def nearest_boundary_points(mesh: Mesh, pts: np.ndarray, k: int = 16) -> Tuple[n
         best[take] = q[take]
         bd[take] = dd[take]
         bp[take] = ids[take]
+    if inset > 0.0:
+        best = best + inset * (cen[bp] - best)
     return best, bp
 
 

@@ -140,9 +140,9 @@ def lib():
     L.wob_mfma_probe.restype = C.c_int
     L.wob_last_device_status.argtypes = [vp, C.POINTER(C.c_uint64), vp]
     L.wob_last_device_status.restype = C.c_int
-    L.wob_solve_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
+    L.wob_solve_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp, vp, vp]
     L.wob_solve_grad.restype = C.c_int
-    L.wob_trace_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
+    L.wob_trace_grad.argtypes = [vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
     L.wob_trace_grad.restype = C.c_int
     L.wob_starts_create.argtypes = [vp, vp, C.POINTER(vp)]
     L.wob_starts_create.restype = C.c_int
@@ -435,33 +435,49 @@ def forward_gather(scene: Scene, vtx, points, want_var: bool = True, stream=None
     return mean, var
 
 
+def _need_anchors(scene, P, anchors, anchor_prim):
+    """Boundary-split anchors: both or neither; (P, dim) of the scene's dtype
+    and (P,) int32 on its device."""
+    torch = _torch()
+    if (anchors is None) != (anchor_prim is None):
+        raise WobError("anchors and anchor_prim go together")
+    _need(anchors, "anchors", scene.dtype, (P, scene.dim), scene.device, optional=True)
+    _need(anchor_prim, "anchor_prim", torch.int32, (P,), scene.device, optional=True)
+
+
 def solve_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
-               want_var: bool = True, stream=None):
+               want_var: bool = True, stream=None, anchors=None, anchor_prim=None):
     """Per-point mean value and gradient (and variances) along the same paths
-    (``wob_solve_grad``); points off the boundary."""
+    (``wob_solve_grad``); points off the boundary.  anchors / anchor_prim
+    (double layer): per point a boundary point and its primitive id (-1: none)
+    for the boundary split of the gradient."""
     torch = _torch()
     P, D = _need_points(scene, points), scene.dim
+    _need_anchors(scene, P, anchors, anchor_prim)
     mean = torch.empty(P, dtype=scene.dtype, device=points.device)
     grad = torch.empty((P, D), dtype=scene.dtype, device=points.device)
     var = torch.empty(P, dtype=scene.dtype, device=points.device) if want_var else None
     gvar = torch.empty((P, D), dtype=scene.dtype, device=points.device) if want_var else None
     b = bc.c(scene)
     st = lib().wob_solve_grad(scene.handle, _dev_ptr(points), P, C.byref(b), int(samples), int(walk_len),
-                              C.c_uint64(seed), _dev_ptr(mean), _dev_ptr(var), _dev_ptr(grad), _dev_ptr(gvar),
-                              _stream(stream))
+                              C.c_uint64(seed), _dev_ptr(anchors), _dev_ptr(anchor_prim), _dev_ptr(mean),
+                              _dev_ptr(var), _dev_ptr(grad), _dev_ptr(gvar), _stream(stream))
     _check(st, "wob_solve_grad")
     return mean, var, grad, gvar
 
 
-def trace_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0, stream=None):
+def trace_grad(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0, stream=None,
+               anchors=None, anchor_prim=None):
     """Per-path values (P, samples) and gradients (P, samples, dim) (``wob_trace_grad``)."""
     torch = _torch()
     P, D = _need_points(scene, points), scene.dim
+    _need_anchors(scene, P, anchors, anchor_prim)
     path = torch.empty((P, samples), dtype=scene.dtype, device=points.device)
     pg = torch.empty((P, samples, D), dtype=scene.dtype, device=points.device)
     b = bc.c(scene)
     st = lib().wob_trace_grad(scene.handle, _dev_ptr(points), P, C.byref(b), int(samples), int(walk_len),
-                              C.c_uint64(seed), _dev_ptr(path), _dev_ptr(pg), _stream(stream))
+                              C.c_uint64(seed), _dev_ptr(anchors), _dev_ptr(anchor_prim), _dev_ptr(path),
+                              _dev_ptr(pg), _stream(stream))
     _check(st, "wob_trace_grad")
     return path, pg
 

@@ -28,22 +28,28 @@ def dev(a, dtype):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
-def run_grad_parity(W, mesh, pts, bc, N, M, seed, precision):
+def run_grad_parity(W, mesh, pts, bc, N, M, seed, precision, anchors=None, anchor_prim=None):
     """Per-path value and gradient on every non-grazing path: the value within
     RTOL * S + KAPPA * u * E, every gradient component within the same bar of
-    the gradient (its magnitude sum and the oracle's bound of its rounding)."""
+    the gradient (its magnitude sum and the oracle's bound of its rounding).
+    With anchors: the boundary split at those points (the same anchors, in
+    the scene's precision, on both sides)."""
     scene = W.Scene(mesh, W.F32 if precision == "f32" else W.F64)
     dt = torch.float32 if precision == "f32" else torch.float64
     wb = W.BC(bc["domain"], bc["formulation"], bc["program"], tuple(bc["params"]),
               sampling=bc.get("sampling", 0), candidates=bc.get("candidates", 0))
-    val, g = W.trace_grad(scene, dev(pts, dt), wb, N, M, seed)
+    kw = {}
+    if anchors is not None:
+        kw = dict(anchors=dev(anchors, dt), anchor_prim=dev(anchor_prim, torch.int32))
+    val, g = W.trace_grad(scene, dev(pts, dt), wb, N, M, seed, **kw)
     torch.cuda.synchronize()
     ob = oracle.make_bc(bc["domain"], bc["formulation"], bc["program"], bc["params"],
                         sampling=bc.get("sampling", 0), candidates=bc.get("candidates", 0) or 16)
     P = pts.shape[0]
     ip = np.repeat(np.arange(P), N)
     ik = np.tile(np.arange(N), P)
-    orc = oracle.trace_grad(oracle.OracleMesh(mesh), pts, ob, M, seed, ip, ik)
+    orc = oracle.trace_grad(oracle.OracleMesh(mesh), pts, ob, M, seed, ip, ik, anchors=anchors,
+                            anchor_prim=anchor_prim)
     rtol = PT.RTOL_F32 if precision == "f32" else PT.RTOL_F64
     ok = orc["graze"] >= PT.graze_for(rtol)
     gv = val.cpu().double().numpy().reshape(-1)
@@ -181,4 +187,85 @@ def test_grad_full_size_sampled(W):
     tol = PT.tolerance(orc["grad_abs"], orc["grad_err"], PT.RTOL_F32)[:, None]
     bad = np.any(np.abs(gg - orc["grad"]) > tol, axis=1) & ok
     assert bad.sum() == 0, bad.sum()
+    scene.close()
+
+
+def _inward(mesh, n, depths, seed):
+    on, prim = I.mesh_surface_points(mesh, n, seed)
+    v, t = mesh.verts, mesh.prims[prim]
+    nrm = np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    return on - np.asarray(depths)[:, None] * nrm
+
+
+def test_grad_split_parity_3d_f32(W):
+    """Boundary split of the double-layer gradient (coupled walk from the
+    nearest boundary point): per-path value and gradient parity at points
+    0.002 to 0.05 inside a perturbed sphere and in its interior, some points
+    without an anchor (-1), M = 1 and 4."""
+    mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(10), 0.1, 3, 4))
+    pts = PT.f32(np.concatenate([_inward(mesh, 30, np.geomspace(0.002, 0.05, 30), 3),
+                                 I.ball_points(10, 0.6, 4)]))
+    A, AP = I.nearest_boundary_points(mesh, pts, inset=1e-3)
+    A = PT.f32(A)
+    AP[::7] = -1
+    bc = dict(domain=1, formulation=1, program=oracle.PROG_INVDIST, params=(2.0, 0.5, 0.0))
+    for M in (1, 4):
+        run_grad_parity(W, mesh, pts, bc, 64, M, 21 + M, "f32", anchors=A, anchor_prim=AP)
+
+
+def test_grad_split_parity_2d_f64(W):
+    """The same on the 128-gon in FP64 (x^2 - y^2), points near the boundary."""
+    c = I.circle_polygon(128)
+    ang = np.random.default_rng(6).uniform(0, 2 * np.pi, 30)
+    r = 1.0 - np.geomspace(0.002, 0.1, 30)
+    pts = np.stack([r * np.cos(ang), r * np.sin(ang)], axis=1)
+    A, AP = I.nearest_boundary_points(c, pts, inset=1e-3)
+    bc = dict(domain=1, formulation=1, program=oracle.PROG_QUAD, params=())
+    run_grad_parity(W, c, pts, bc, 64, 3, 23, "f64", anchors=A, anchor_prim=AP)
+
+
+def test_grad_split_arguments(W):
+    """Anchors go with the double layer only; both arrays or neither; an
+    invalid anchor id gives that point's gradient as NaN, the others as
+    usual."""
+    mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(6), 0.1, 3, 4))
+    scene = W.Scene(mesh, W.F32)
+    pts_np = PT.f32(I.ball_points(6, 0.8, 1))
+    A, AP = I.nearest_boundary_points(mesh, pts_np, inset=1e-3)
+    pts, ta, tp = dev(pts_np, torch.float32), dev(PT.f32(A), torch.float32), dev(AP, torch.int32)
+    sl = W.BC(-1, W.SINGLE_LAYER, W.PROG_INVDIST, (0.1, 0.2, 0.0))
+    with pytest.raises(W.WobError):
+        W.trace_grad(scene, pts, sl, 8, 3, 1, anchors=ta, anchor_prim=tp)
+    dl = W.BC(1, 1, W.PROG_INVDIST, (2.0, 0.5, 0.0))
+    with pytest.raises(W.WobError):
+        W.trace_grad(scene, pts, dl, 8, 3, 1, anchors=ta)
+    bad = tp.clone()
+    bad[2] = mesh.n_prims + 5
+    v, g = W.trace_grad(scene, pts, dl, 8, 3, 1, anchors=ta, anchor_prim=bad)
+    v0, g0 = W.trace_grad(scene, pts, dl, 8, 3, 1, anchors=ta, anchor_prim=tp)
+    torch.cuda.synchronize()
+    assert torch.isnan(g[2]).any(dim=-1).all()
+    keep = [0, 1, 3, 4, 5]
+    assert torch.equal(g[keep], g0[keep]) and torch.equal(v, v0)
+    scene.close()
+
+
+def test_grad_split_statistics(W):
+    """wob_solve_grad with anchors: its mean and variance are those of
+    wob_trace_grad's split paths; the value is unchanged."""
+    mesh = PT.f32_mesh(I.perturb_radial(I.icosphere(8), 0.1, 3, 4))
+    scene = W.Scene(mesh, W.F32)
+    pts_np = PT.f32(_inward(mesh, 37, np.full(37, 0.01), 5))
+    A, AP = I.nearest_boundary_points(mesh, pts_np, inset=1e-3)
+    pts, ta, tp = dev(pts_np, torch.float32), dev(PT.f32(A), torch.float32), dev(AP, torch.int32)
+    bc = W.BC(1, 1, W.PROG_INVDIST, (2.0, 0.5, 0.0))
+    mean, var, g, gv = W.solve_grad(scene, pts, bc, 130, 3, 8, anchors=ta, anchor_prim=tp)
+    pv, pg = W.trace_grad(scene, pts, bc, 130, 3, 8, anchors=ta, anchor_prim=tp)
+    m0, v0 = W.solve(scene, pts, bc, 130, 3, 8)
+    torch.cuda.synchronize()
+    pg64 = pg.double()
+    assert torch.allclose(g.double(), pg64.mean(dim=1), rtol=1e-5, atol=1e-6)
+    assert torch.allclose(gv.double(), pg64.var(dim=1), rtol=1e-4, atol=1e-8)
+    assert torch.allclose(mean, m0, rtol=1e-6, atol=1e-7)
     scene.close()

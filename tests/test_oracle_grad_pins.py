@@ -148,7 +148,7 @@ def test_boundary_split_is_exact_for_constant_data_on_a_convex_body():
     s = I.icosphere(6)
     om = oracle.OracleMesh(s)
     pts = np.concatenate([_inward_points(s, 12, 0.01, 1), I.ball_points(8, 0.5, 2)])
-    A, AP = I.nearest_boundary_points(s, pts)
+    A, AP = I.nearest_boundary_points(s, pts, inset=1e-3)
     bc = oracle.make_bc(1, oracle.DOUBLE_LAYER, oracle.PROG_CONST, (1.3,))
     N = 32
     ip, ik = np.repeat(np.arange(len(pts)), N), np.tile(np.arange(N), len(pts))
@@ -169,7 +169,7 @@ def test_boundary_split_is_unbiased(anchor_kind):
     om = oracle.OracleMesh(s)
     pts = np.concatenate([_inward_points(s, 10, 0.05, 3), I.ball_points(6, 0.5, 4)])
     if anchor_kind == "nearest":
-        A, AP = I.nearest_boundary_points(s, pts)
+        A, AP = I.nearest_boundary_points(s, pts, inset=1e-3)
     else:
         A, AP = I.mesh_surface_points(s, len(pts), 5)
     AP = AP.astype(np.int32)
@@ -193,7 +193,7 @@ def test_boundary_split_lowers_the_variance_near_the_boundary():
     m = I.perturb_radial(I.icosphere(10), 0.1, 3, 4)
     om = oracle.OracleMesh(m)
     pts = _inward_points(m, 16, 0.003, 7)
-    A, AP = I.nearest_boundary_points(m, pts)
+    A, AP = I.nearest_boundary_points(m, pts, inset=1e-3)
     bc = oracle.make_bc(1, oracle.DOUBLE_LAYER, oracle.PROG_INVDIST, (2.0, 0.5, 0.0))
     _, _, g0, gv0 = oracle.solve_grad(om, pts, bc, 1000, 4, 9)
     _, _, g1, gv1 = oracle.solve_grad(om, pts, bc, 1000, 4, 9, anchors=A, anchor_prim=AP)
