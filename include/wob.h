@@ -93,7 +93,8 @@ typedef struct {
   int32_t density;      /* 0: the solution u at the points.  1: the boundary unknown (double
                            layer nu, single layer mu) at points ON the boundary, without its
                            own emission 2 phi s (the targets of the learned control variate);
-                           not with the direct BIE */
+                           not with the direct BIE; a point with point_prim -1 (or no
+                           point_prim) has no boundary unknown and gets NaN paths */
   int32_t sampling;     /* single layer only: WOB_SAMPLE_LINE (line sampling of Sec. 4.4.1,
                            all hits, uniform pick, self-panel mixture) or WOB_SAMPLE_RIS
                            (resampled importance sampling over area-uniform boundary

@@ -14,7 +14,8 @@ import numpy as np
 from . import build as _build
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB selects another build of the same sources (the sanitized one)
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 AUTO, DOUBLE_LAYER, DIRECT, SINGLE_LAYER = 0, 1, 2, 3
 PROG_CONST, PROG_LINEAR, PROG_QUAD, PROG_INVDIST = 0, 1, 2, 3

@@ -9,15 +9,21 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
+# the same sources under AddressSanitizer and UndefinedBehaviorSanitizer
+# (any finding aborts); loaded by a process that preloads the two runtimes
+LIB_SANITIZED = os.path.join(HERE, "liboracle_sanitized.so")
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", LIB, os.path.join(HERE, "oracle.c"), os.path.join(HERE, "mlp.c"), "-lm"]
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    out = LIB_SANITIZED if sanitize else LIB
+    flags = ["-O1"] + SANITIZE_FLAGS if sanitize else ["-O2"]
+    cmd = ["gcc", "-std=c11", *flags, "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", out, os.path.join(HERE, "oracle.c"), os.path.join(HERE, "mlp.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

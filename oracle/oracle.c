@@ -757,6 +757,13 @@ static path_result one_path(const orc_mesh* m, const double* normals, const area
       for (int a = 0; a < dim; ++a) vpos[i * dim + a] = NAN;
   }
 
+  /* density mode estimates the boundary unknown at boundary points: a point
+     off the boundary has none (a caller error, as in the library: NaN) */
+  if (bc->density && prim0 < 0) {
+    res.value = NAN;
+    res.abs_sum = NAN;
+    return res;
+  }
   /* Table 1, Dirichlet: on the boundary the solution is the given value (also
      on the Dirichlet parts of a mixed problem) */
   if (i0 == 0 && prim0 >= 0 && !bc->density &&

@@ -113,15 +113,29 @@ struct LaunchBufs {
   const int64_t* tile_off;
   unsigned long long* counter;
   int32_t n_probs, stack_cap, n_cu;
+  bool vdata;  // some problem gives its boundary data per vertex
 };
+
+// Whether any problem gives its boundary data per vertex (then the batch runs
+// the kernel instantiated for it).
+inline bool any_vertex_data(const wob_problem* p, int32_t n) {
+  for (int32_t i = 0; i < n; ++i)
+    if (p[i].bc.data_mode == WOB_DATA_VERTEX) return true;
+  return false;
+}
 
 template <typename R, int D, int BLOCK>
 void launch_persistent_t(const LaunchBufs& lb, int bpc, int64_t stride, hipStream_t st) {
   hipLaunchKernelGGL(zero_counter, dim3(1), dim3(64), 0, st, lb.counter);
   const dim3 grid((unsigned)(lb.n_cu * bpc)), block(BLOCK);
-  hipLaunchKernelGGL((wob::batch_kernel<R, D, BLOCK>), grid, block,
-                     wob::walk_lds_bytes(lb.stack_cap, BLOCK), st,
-                     (const wob::WalkArgs<R, D>*)lb.args, lb.tile_off, lb.n_probs, stride, lb.counter);
+  const size_t lds = wob::walk_lds_bytes(lb.stack_cap, BLOCK);
+  const auto* args = (const wob::WalkArgs<R, D>*)lb.args;
+  if (lb.vdata)
+    hipLaunchKernelGGL((wob::batch_kernel<R, D, BLOCK, wob::X_VDATA>), grid, block, lds, st, args, lb.tile_off,
+                       lb.n_probs, stride, lb.counter);
+  else
+    hipLaunchKernelGGL((wob::batch_kernel<R, D, BLOCK>), grid, block, lds, st, args, lb.tile_off, lb.n_probs,
+                       stride, lb.counter);
 }
 
 template <typename R, int D>
@@ -144,7 +158,8 @@ void launch_persistent_buf(int precision, int dim, const LaunchBufs& lb, const w
 }
 
 void launch_persistent(wob_batch_s* b, const wob_tune& t, int64_t stride, hipStream_t st) {
-  const LaunchBufs lb{b->d_args, b->d_tile_off, b->d_counter, (int32_t)b->probs.size(), b->stack_cap, b->n_cu};
+  const LaunchBufs lb{b->d_args, b->d_tile_off, b->d_counter, (int32_t)b->probs.size(), b->stack_cap, b->n_cu,
+                      any_vertex_data(b->probs.data(), (int32_t)b->probs.size())};
   launch_persistent_buf(b->precision, b->dim, lb, t, stride, st);
 }
 
@@ -264,7 +279,7 @@ wob_status solve_static(const wob_problem* problems, int32_t n, const int32_t* o
   if (hipMemcpyAsync(base, args, sizeof(wob::WalkArgs<R, D>) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(d_off, off, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
     return WOB_E_DEVICE;
-  const LaunchBufs lb{base, d_off, d_counter, n, stack_cap, n_cu};
+  const LaunchBufs lb{base, d_off, d_counter, n, stack_cap, n_cu, any_vertex_data(problems, n)};
   launch_persistent_buf(sizeof(R) == 4 ? WOB_F32 : WOB_F64, D, lb, tune, 1, st);
   if (hipGetLastError() != hipSuccess) return WOB_E_DEVICE;
   return hipStreamSynchronize(st) == hipSuccess ? WOB_OK : WOB_E_DEVICE;

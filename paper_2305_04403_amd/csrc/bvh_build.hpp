@@ -3,10 +3,10 @@
 // The paper only asks for an "all-hits" ray query over the boundary
 // (Sec. 4.4.1); the acceleration structure is this library's own design: a
 // binary BVH built with the binned surface-area heuristic and laid out in
-// pre-order with a skip ("escape") index per node.  Because a line query
-// visits every box it meets and needs no front-to-back order, a lane can walk
-// the array without a stack: on a box hit go to the first child (or test the
-// leaf), otherwise jump to the skip index.
+// pre-order with a skip ("escape") index per node.  The device records are
+// derived from it (wob.hip: 4-wide interior records with binary16 boxes,
+// walked with a short per-lane stack; a line query visits every box it
+// meets and needs no front-to-back order).
 #pragma once
 
 #include <cstdint>

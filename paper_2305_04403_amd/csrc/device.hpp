@@ -291,10 +291,15 @@ __device__ __forceinline__ R vertex_datum(const ProgramView<R>& prog, const Prim
   }
 }
 
-template <typename R, int D>
+// VD: whether per-vertex data can occur (the walk kernels are instantiated
+// with and without it: the binary64 interpolation costs registers, and so
+// occupancy, even where it is never taken).
+template <typename R, int D, bool VD = true>
 __device__ __forceinline__ R boundary_datum(const ProgramView<R>& prog, const PrimGeo<R>& g,
                                             const R n[3], const R y[3]) {
-  if (prog.type == P_VERTEX) return vertex_datum<R, D>(prog, g, y);
+  if constexpr (VD) {
+    if (prog.type == P_VERTEX) return vertex_datum<R, D>(prog, g, y);
+  }
   R u, grad[3];
   program_eval<R, D>(prog, y, u, grad);
   if (g.kind == K_DIRICHLET) return u;

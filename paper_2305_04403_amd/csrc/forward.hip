@@ -197,8 +197,12 @@ wob_status launch_paths(const wob_scene_s* sc, const wob_bc* bc, const float* cd
   a.vtx_m = vtx_m;
   constexpr int B = kSolveBlock;
   const dim3 grid((unsigned)((a.n_points + B - 1) / B)), block(B);
-  hipLaunchKernelGGL((wob::walk_kernel<R, D, wob::F_FWD, false, false, B>), grid, block,
-                     wob::walk_lds_bytes(a.scene.stack_cap, B), st, a);
+  if (a.prog.type == wob::P_VERTEX)
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, wob::F_FWD, false, false, B, wob::X_VDATA>), grid, block,
+                       wob::walk_lds_bytes(a.scene.stack_cap, B), st, a);
+  else
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, wob::F_FWD, false, false, B>), grid, block,
+                       wob::walk_lds_bytes(a.scene.stack_cap, B), st, a);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }
 

@@ -86,15 +86,20 @@ enum { ST_NONE = 0, ST_LINE = 1, ST_DONE = 2 };
 
 // Extensions of the walk: the corrected walk of the control variate, and the
 // gradient in the evaluation point carried along the same paths.
-enum Ext { X_NONE = 0, X_CV = 1, X_GRAD = 2 };
+// X_VDATA is a flag on top of either: the boundary data may be given per
+// vertex (a separate instantiation, so the program-data kernels do not carry
+// the interpolation's registers).
+enum Ext { X_NONE = 0, X_CV = 1, X_GRAD = 2, X_VDATA = 4 };
+constexpr int ext_kind(int ext) { return ext & 3; }
+constexpr bool ext_vdata(int ext) { return (ext & X_VDATA) != 0; }
 
 // Single-layer emission at vertex y on primitive g, before the running
 // weight: 2 phi s(y) on Neumann / Robin parts (Table 1), k u_D(y) on Dirichlet
 // parts (eq. mixed_second_kind_ish); half of it at the last vertex x_M.
-template <typename R, int D>
+template <typename R, int D, bool VD>
 __device__ __forceinline__ R sl_emission(const WalkArgs<R, D>& a, const PrimGeo<R>& g, const R n[3],
                                          const R y[3], bool last_vertex) {
-  const R sv = boundary_datum<R, D>(a.prog, g, n, y);
+  const R sv = boundary_datum<R, D, VD>(a.prog, g, n, y);
   const R e = g.kind == K_DIRICHLET ? a.mixed_k * sv : (R)2 * a.phi * sv;
   return last_vertex ? (R)0.5 * e : e;
 }
@@ -162,7 +167,7 @@ __device__ __forceinline__ void fwd_end(const WalkArgs<R, D>& a, const PathState
 // candidate j when u_j S_j < |k_j|; weight sign(k) S |Gamma| / C.  Moves the
 // path to the kept point and adds its emission; returns false when no
 // candidate carries kernel mass (the path ends).
-template <typename R, int D, bool TRACE, bool GRAD>
+template <typename R, int D, bool TRACE, bool GRAD, bool VD>
 __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D>& s) {
   const SceneView<R, D>& sc = a.scene;
   const R phi = a.phi;
@@ -246,7 +251,7 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
   R nn[3];
   load_normal<R, D>(sc, lpick, nn);
   if (TRACE && s.vp) s.vp[s.i] = gn.id;
-  const R e = sl_emission<R, D>(a, gn, nn, s.x, s.i + 1 >= a.M);
+  const R e = sl_emission<R, D, VD>(a, gn, nn, s.x, s.i + 1 >= a.M);
   s.acc += s.W * e;
   if constexpr (GRAD) {
 #pragma unroll
@@ -257,7 +262,7 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
 
 template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
 __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, D>& s, WorkCount& wc) {
-  constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
+  constexpr bool CV = ext_kind(EXT) == X_CV, GRAD = ext_kind(EXT) == X_GRAD, VD = ext_vdata(EXT);
   const R phi = a.phi;
   for (;;) {
     if (s.i >= a.L) return ST_DONE;
@@ -276,7 +281,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
       // a second load there costs the single-layer kernel ~35 registers)
       if (s.first && s.on_gamma && s.gc.kind == K_DIRICHLET) {
         const R nz[3] = {0, 0, 0};
-        s.acc = boundary_datum<R, D>(a.prog, s.gc, nz, s.x);
+        s.acc = boundary_datum<R, D, VD>(a.prog, s.gc, nz, s.x);
         return ST_DONE;
       }
     }
@@ -297,7 +302,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
           const R ws = (R)1 / ((R)1 - a.mixed_p);
           s.W *= ws;
           if (TRACE && s.vp) s.vp[s.i] = -2 - s.gc.id;
-          const R e = sl_emission<R, D>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
+          const R e = sl_emission<R, D, VD>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
           s.acc += s.W * e;
           if constexpr (GRAD) {
 #pragma unroll
@@ -312,7 +317,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
         s.gscale = -a.mixed_k / a.mixed_p;
       }
       if constexpr (FORM == F_SL_RIS) {
-        if (!ris_step<R, D, TRACE, GRAD>(a, s)) return ST_DONE;
+        if (!ris_step<R, D, TRACE, GRAD, VD>(a, s)) return ST_DONE;
         ++s.i;
         continue;
       }
@@ -338,7 +343,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
       s.x[1] = y[1];
       s.x[2] = y[2];
       // emission at the new vertex (same primitive)
-      const R e = sl_emission<R, D>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
+      const R e = sl_emission<R, D, VD>(a, s.gc, s.nc, s.x, s.i + 1 >= a.M);
       s.acc += s.W * e;
       if constexpr (GRAD) {  // a vertex on the boundary: never the first step
 #pragma unroll
@@ -371,7 +376,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
 template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
 __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, D>& s, uint32_t path,
                                           int64_t item, WorkCount& wc) {
-  constexpr bool GRAD = EXT == X_GRAD;
+  constexpr bool GRAD = ext_kind(EXT) == X_GRAD, VD = ext_vdata(EXT);
   s.path = path;
   if constexpr (GRAD) {
 #pragma unroll
@@ -413,7 +418,7 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
       area = sqrt(g.e1[0] * g.e1[0] + g.e1[1] * g.e1[1]);
     }
     const R pt = (R)a.fwd_cdf[lo] - (lo > 0 ? (R)a.fwd_cdf[lo - 1] : (R)0);
-    s.W = (R)2 * a.phi * boundary_datum<R, D>(a.prog, g, n, s.x) * area / pt;
+    s.W = (R)2 * a.phi * boundary_datum<R, D, VD>(a.prog, g, n, s.x) * area / pt;
     s.acc = 0;
     s.i = 0;
     s.cur_idx = leaf;
@@ -428,8 +433,9 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
       if (s.vm) s.vm[i] = 0;
     }
   }
-  // a primitive id outside [-1, n_prims) is a caller error: the path is NaN
-  if (s.prim0 < -1 || s.prim0 >= a.scene.n_prims) {
+  // a primitive id outside [-1, n_prims) is a caller error: the path is NaN;
+  // so is a density-mode point off the boundary (it has no boundary unknown)
+  if (s.prim0 < -1 || s.prim0 >= a.scene.n_prims || (a.density && s.prim0 < 0)) {
     s.acc = (R)NAN;
     return ST_DONE;
   }
@@ -441,7 +447,7 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
     // Table 1: on the boundary the Dirichlet solution is the given value
     const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
     const R nz[3] = {0, 0, 0};
-    s.acc = boundary_datum<R, D>(a.prog, g, nz, s.x);
+    s.acc = boundary_datum<R, D, VD>(a.prog, g, nz, s.x);
     return ST_DONE;
   }
   s.W = 1;
@@ -468,6 +474,7 @@ __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, 
 template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
 __device__ __forceinline__ int start_coupled(const WalkArgs<R, D>& a, PathState<R, D>& s, int64_t point,
                                              int32_t anchor, WorkCount& wc) {
+  constexpr bool VD = ext_vdata(EXT);
   s.acc_main = s.acc;
   s.coupled = true;
   if (anchor >= a.scene.n_prims) {  // a caller error: the gradient is NaN
@@ -487,7 +494,7 @@ __device__ __forceinline__ int start_coupled(const WalkArgs<R, D>& a, PathState<
   const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
   R n[3];
   load_normal<R, D>(a.scene, s.cur_idx, n);
-  s.acc = ((1 < a.M) ? (R)2 * a.phi : a.phi) * boundary_datum<R, D>(a.prog, g, n, s.x);
+  s.acc = ((1 < a.M) ? (R)2 * a.phi : a.phi) * boundary_datum<R, D, VD>(a.prog, g, n, s.x);
   return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
@@ -505,7 +512,7 @@ template <typename R, int D, int FORM, bool COUNT, int EXT>
 __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, D>& s, int32_t code,
                                           int32_t code2, int32_t code3, int32_t code4, WorkCount& wc) {
   static_assert(kLeafSlots == 4, "leaf_work takes four leaf codes");
-  constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
+  constexpr bool CV = ext_kind(EXT) == X_CV, GRAD = ext_kind(EXT) == X_GRAD, VD = ext_vdata(EXT);
   const SceneView<R, D>& sc = a.scene;
   {
     // one to four leaves (codes -1 = none after the first): primitive b of the
@@ -552,7 +559,7 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
         R y[3], n[3];
         load_normal<R, D>(sc, j, n);
         const R t = plane_hit<R, D>(g, n, s.x, s.d, y);
-        const R q = boundary_datum<R, D>(a.prog, g, n, y);  // Neumann data
+        const R q = boundary_datum<R, D, VD>(a.prog, g, n, y);  // Neumann data
         // y - x = t d: distance and cosine from the line itself, free of the
         // cancellation in y - x when the hit is close to x
         const R rho = fabs(t);
@@ -582,7 +589,7 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
           R ah = s.first ? rho / ((R)2 * acy)
                          : -a.phi * (sgn_t * dot3(s.d, s.nc) + s.gc.alpha * rho) / acy;
           if (s.mixture) ah /= ((R)1 - a.self_p);
-          const R sh = boundary_datum<R, D>(a.prog, g, n, y);
+          const R sh = boundary_datum<R, D, VD>(a.prog, g, n, y);
           const R F = s.last ? a.phi * sh : (R)2 * a.phi * sh + a.cv_g[g.id];
           s.h.src += ah * F;
         }
@@ -593,7 +600,7 @@ __device__ __forceinline__ void leaf_work(const WalkArgs<R, D>& a, PathState<R, 
 
 template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
 __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>& s, WorkCount& wc) {
-  constexpr bool CV = EXT == X_CV, GRAD = EXT == X_GRAD;
+  constexpr bool CV = ext_kind(EXT) == X_CV, GRAD = ext_kind(EXT) == X_GRAD, VD = ext_vdata(EXT);
   const R phi = a.phi;
   HitAcc<R>& h = s.h;
   if (TRACE) {
@@ -606,7 +613,7 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
       const U4 r1 = philox(s.path, s.point, s.z | 1u, 0u, a.k0, a.k1);
       R ys[3];
       const R gp = self_panel<R, D>(s.gc, s.nc, s.x, unit<R>(r1.x), unit<R>(r1.y), ys);
-      S = (R)2 * phi * (h.src + gp * boundary_datum<R, D>(a.prog, s.gc, s.nc, ys));
+      S = (R)2 * phi * (h.src + gp * boundary_datum<R, D, VD>(a.prog, s.gc, s.nc, ys));
     } else {
       S = phi * h.src;
     }
@@ -698,19 +705,19 @@ __device__ __forceinline__ int end_step(const WalkArgs<R, D>& a, PathState<R, D>
     // exact mean the add-back restores; the emission of line 0 stays as is)
     if (s.i == 0) {
       s.acc -= s.W * a.cv_g0[gy.id];
-      s.acc += s.W * (R)2 * phi * boundary_datum<R, D>(a.prog, gy, ny, s.x);
+      s.acc += s.W * (R)2 * phi * boundary_datum<R, D, VD>(a.prog, gy, ny, s.x);
     } else {
       s.acc -= s.W * a.cv_g[gy.id];
     }
   } else if constexpr (is_sl(FORM)) {
-    const R e = sl_emission<R, D>(a, gy, ny, s.x, s.i + 1 >= a.M);
+    const R e = sl_emission<R, D, VD>(a, gy, ny, s.x, s.i + 1 >= a.M);
     s.acc += s.W * e;
     if constexpr (GRAD) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) s.gacc[k] += s.Wg[k] * e;
     }
   } else if constexpr (FORM == F_DL) {
-    const R e = ((s.i + 1 < a.M) ? (R)2 * phi : phi) * boundary_datum<R, D>(a.prog, gy, ny, s.x);
+    const R e = ((s.i + 1 < a.M) ? (R)2 * phi : phi) * boundary_datum<R, D, VD>(a.prog, gy, ny, s.x);
     s.acc += s.W * e;
     if constexpr (GRAD) {
 #pragma unroll
@@ -757,7 +764,7 @@ __device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, 
 // paths k, k + lpp, ...).  `red` is BLOCK / 64 x red_stride<EXT, D>() doubles
 // of LDS.
 template <int EXT, int D>
-constexpr int red_stride() { return EXT == X_GRAD ? 3 + 2 * D : 3; }
+constexpr int red_stride() { return ext_kind(EXT) == X_GRAD ? 3 + 2 * D : 3; }
 
 template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK, int EXT = X_NONE>
 __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t block_index, double* red) {
@@ -766,14 +773,14 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   const int64_t point = block_index * (BLOCK >> a.lpp_shift) + (tid >> a.lpp_shift);
   const int lane_in_point = tid & (lpp - 1);
   double n = 0.0, mean = 0.0, m2 = 0.0;
-  constexpr bool GRAD = EXT == X_GRAD;
+  constexpr bool GRAD = ext_kind(EXT) == X_GRAD;
   constexpr int GD = GRAD ? D : 1;  // gradient statistics per component (unused otherwise)
   double gmean[GD], gm2[GD];
 #pragma unroll
   for (int c = 0; c < GD; ++c) gmean[c] = gm2[c] = 0.0;
   WorkCount wc = {0, 0, 0, 0};
   // the corrected walk exists for the 3D single layer only
-  constexpr int KEXT = EXT == X_CV ? ((D == 3 && FORM == F_SL) ? X_CV : X_NONE) : EXT;
+  constexpr int KEXT = (ext_kind(EXT) == X_CV && !(D == 3 && FORM == F_SL)) ? (EXT & X_VDATA) : EXT;
   {
     // Paths k = lane_in_point, + lpp, ... of this lane, run as one state
     // machine.  Lanes step through BVH nodes; a lane that has reached four
@@ -1195,7 +1202,8 @@ __global__ void centroid_kernel(SceneView<R, 3> s, float* out) {
 // from a device counter until none is left.  Tiles of one problem are
 // contiguous; tile_off (n_probs + 1 entries) is the prefix sum of tiles per
 // problem.  With stride > 1 only every stride-th tile runs (autotuner timing).
-template <typename R, int D, int BLOCK>
+// VX: X_VDATA when some problem gives its data per vertex.
+template <typename R, int D, int BLOCK, int VX = X_NONE>
 __global__ void __launch_bounds__(BLOCK) batch_kernel(const WalkArgs<R, D>* __restrict__ probs,
                                                       const int64_t* __restrict__ tile_off,
                                                       int32_t n_probs, int64_t stride,
@@ -1219,10 +1227,10 @@ __global__ void __launch_bounds__(BLOCK) batch_kernel(const WalkArgs<R, D>* __re
     const WalkArgs<R, D>& a = probs[b];
     const int64_t local = tile - tile_off[b];
     const int form = __builtin_amdgcn_readfirstlane(a.form);
-    if (form == F_DL) walk_block<R, D, F_DL, false, false, BLOCK>(a, local, red);
-    else if (form == F_DIRECT) walk_block<R, D, F_DIRECT, false, false, BLOCK>(a, local, red);
-    else if (form == F_SL_RIS) walk_block<R, D, F_SL_RIS, false, false, BLOCK>(a, local, red);
-    else walk_block<R, D, F_SL, false, false, BLOCK>(a, local, red);
+    if (form == F_DL) walk_block<R, D, F_DL, false, false, BLOCK, VX>(a, local, red);
+    else if (form == F_DIRECT) walk_block<R, D, F_DIRECT, false, false, BLOCK, VX>(a, local, red);
+    else if (form == F_SL_RIS) walk_block<R, D, F_SL_RIS, false, false, BLOCK, VX>(a, local, red);
+    else walk_block<R, D, F_SL, false, false, BLOCK, VX>(a, local, red);
   }
 }
 

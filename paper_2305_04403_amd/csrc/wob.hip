@@ -282,7 +282,8 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
 
 enum Mode { MODE_SOLVE = 0, MODE_TRACE = 1, MODE_COUNT = 2 };
 
-template <typename R, int D, int FORM>
+// VX: X_VDATA for per-vertex data (its own instantiation of each kernel)
+template <typename R, int D, int FORM, int VX>
 void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
   constexpr int B = kSolveBlock;
   const int ppb = B >> a.lpp_shift;
@@ -291,37 +292,46 @@ void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
   if constexpr (FORM != wob::F_FWD) {
     if (a.grad_out || a.path_grad_out) {  // value and gradient along the same paths
       if (mode == MODE_TRACE)
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_GRAD>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_GRAD | VX>), grid, block, lds, st,
+                           a);
       else
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_GRAD>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_GRAD | VX>), grid, block, lds,
+                           st, a);
       return;
     }
   }
   if constexpr (D == 3 && FORM == wob::F_SL) {
     if (a.cv_g) {
       if (mode == MODE_SOLVE)
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_CV>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_CV | VX>), grid, block, lds, st,
+                           a);
       else if (mode == MODE_TRACE)
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_CV>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, wob::X_CV | VX>), grid, block, lds, st, a);
       else
-        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B, wob::X_CV>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B, wob::X_CV | VX>), grid, block, lds, st, a);
       return;
     }
   }
   if (mode == MODE_SOLVE)
-    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, VX>), grid, block, lds, st, a);
   else if (mode == MODE_TRACE)
-    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, true, false, B, VX>), grid, block, lds, st, a);
   else
-    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, true, B, VX>), grid, block, lds, st, a);
+}
+
+template <typename R, int D, int VX>
+void launch_walk_vx(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
+  if (a.form == wob::F_DL) launch_form<R, D, wob::F_DL, VX>(a, mode, st);
+  else if (a.form == wob::F_DIRECT) launch_form<R, D, wob::F_DIRECT, VX>(a, mode, st);
+  else if (a.form == wob::F_SL_RIS) launch_form<R, D, wob::F_SL_RIS, VX>(a, mode, st);
+  else launch_form<R, D, wob::F_SL, VX>(a, mode, st);
 }
 
 template <typename R, int D>
 void launch_walk(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
-  if (a.form == wob::F_DL) launch_form<R, D, wob::F_DL>(a, mode, st);
-  else if (a.form == wob::F_DIRECT) launch_form<R, D, wob::F_DIRECT>(a, mode, st);
-  else if (a.form == wob::F_SL_RIS) launch_form<R, D, wob::F_SL_RIS>(a, mode, st);
-  else launch_form<R, D, wob::F_SL>(a, mode, st);
+  if (a.prog.type == wob::P_VERTEX) launch_walk_vx<R, D, wob::X_VDATA>(a, mode, st);
+  else launch_walk_vx<R, D, wob::X_NONE>(a, mode, st);
 }
 
 wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim, int64_t n_points,

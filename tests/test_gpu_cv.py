@@ -207,3 +207,21 @@ def test_trained_table_lowers_variance_against_g0(W, kinds):
     assert lr.mean() < -0.15 and lr.mean() < -10 * se
     lcv.close()
     scene.close()
+
+
+def test_density_mode_off_the_boundary_is_nan(W, tori):
+    """Density mode at points off the boundary (no boundary unknown there): the
+    paths are NaN, on both sides, and counted by the scene's status."""
+    scene = W.Scene(tori.mesh, W.F32)
+    dbc, od = bcs(W, tori, density=True)
+    pts = PT.f32(I.ball_points(5, 0.2, 1) + np.array([3.0, 0.0, 0.0]))
+    scene.nonfinite_paths()
+    v = W.trace(scene, dev(pts), dbc, 8, 3, 1)[0]
+    m, _ = W.solve(scene, dev(pts), dbc, 8, 3, 1)
+    torch.cuda.synchronize()
+    assert torch.isnan(v).all()
+    assert scene.nonfinite_paths() == 5 * 8
+    o = oracle.trace(oracle.OracleMesh(tori.mesh), pts, None, od, 3, 1, np.repeat(np.arange(5), 2),
+                     np.tile(np.arange(2), 5), want_pos=False)
+    assert np.isnan(o["value"]).all()
+    scene.close()

@@ -351,3 +351,21 @@ def test_line0_emission_table_keeps_mean_and_lowers_variance():
     se = np.sqrt(plain.var(axis=1, ddof=1) / N + cv.var(axis=1, ddof=1) / N)
     assert np.max(np.abs(plain.mean(axis=1) - cv.mean(axis=1)) / se) < 4.5
     assert np.mean(cv.var(axis=1)) < 0.6 * np.mean(plain.var(axis=1))
+
+
+def test_density_mode_off_the_boundary_is_nan():
+    """Density mode estimates the boundary unknown at boundary points; a point
+    off the boundary has none and its paths are NaN (the library does the
+    same)."""
+    s = I.icosphere(4)
+    mesh = I.Mesh(3, s.verts, s.prims, np.full(s.n_prims, 1, np.uint8), None)
+    om = oracle.OracleMesh(mesh)
+    bc = oracle.make_bc(-1, oracle.SINGLE_LAYER, oracle.PROG_CONST, (1.0,), density=True)
+    pts = I.ball_points(3, 2.0, 1, r_min=1.5)
+    o = oracle.trace(om, pts, None, bc, 3, 1, np.repeat(np.arange(3), 2), np.tile(np.arange(2), 3),
+                     want_pos=False)
+    assert np.isnan(o["value"]).all()
+    on, onp = I.mesh_surface_points(mesh, 3, 2)
+    o = oracle.trace(om, on, onp, bc, 3, 1, np.repeat(np.arange(3), 2), np.tile(np.arange(2), 3),
+                     want_pos=False)
+    assert np.isfinite(o["value"]).all()
