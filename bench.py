@@ -69,37 +69,46 @@ NODE_LOAD_BYTES, TRI_LOAD_BYTES, STEP_LOAD_BYTES = 64, 48, 64
 
 KERNEL_SOURCES = ("paper_2305_04403_amd/csrc/device.hpp", "paper_2305_04403_amd/csrc/walk.hpp",
                   "paper_2305_04403_amd/csrc/internal.hpp", "paper_2305_04403_amd/csrc/wob.hip")
-# counter summaries (FETCH_SIZE, WRITE_SIZE) of each leg's walk kernel
-TRAFFIC_PROFILES = {
-    "tori": "profiles/walk_kernel_tori200992_1M_points_traffic.md",
-    "slice": "profiles/walk_kernel_icosphere20480_slice512_traffic.md",
+# committed counter summaries of each leg's kernel and the sources they were
+# taken from: their figures are reported only while those sources are unchanged
+PROFILES = {
+    "tori": ("profiles/walk_kernel_tori200992_1M_points.md", KERNEL_SOURCES),
+    "slice": ("profiles/walk_kernel_icosphere20480_slice512_dirichlet.md", KERNEL_SOURCES),
+    "batched": ("profiles/batch_kernel_64_problems.md",
+                KERNEL_SOURCES + ("paper_2305_04403_amd/csrc/batch.hip",)),
 }
 
 
-def measured_traffic(leg: str):
-    """HBM bytes per launch (FETCH + WRITE, calibrated) from the committed
-    counter summary of a leg's walk kernel, or None when the kernel sources
-    changed since it was taken."""
+def measured_profile(leg: str):
+    """From the committed counter summary of a leg's kernel: HBM bytes per
+    launch (FETCH + WRITE, calibrated), and where present the per-level
+    memory fractions and the VALU busy / utilization figures; None when the
+    kernel sources changed since the counters were taken."""
     import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
     try:
-        with open(os.path.join(ROOT, TRAFFIC_PROFILES[leg])) as fh:
+        path, sources = PROFILES[leg]
+        with open(os.path.join(ROOT, path)) as fh:
             text = fh.read()
     except (OSError, KeyError):
         return None
-    rec = dict(line.strip().split(": ", 1) for line in text.splitlines()
-               if line.strip().startswith(("source-sha256-prefix:", "traffic-bytes-per-launch:")))
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    keys = ("source-sha256-prefix:", "traffic-bytes-per-launch:", "memory-levels:", "valu:")
+    rec = dict(line.strip().split(": ", 1) for line in text.splitlines() if line.strip().startswith(keys))
     prefix = rec.get("source-sha256-prefix", "")
     if not prefix or not h.hexdigest().startswith(prefix):
         return None
     fetch, write = (int(v) for v in rec["traffic-bytes-per-launch"].split())
-    return fetch + write
+    out = {"traffic": fetch + write, "profile": path}
+    for k in ("memory-levels", "valu"):
+        if k in rec:
+            out[k] = {a: float(b) for a, b in (kv.split("=") for kv in rec[k].split())}
+    return out
 
 
-def walk_roofline(cnt, kern_s, cal, fp64=False, traffic=None):
+def walk_roofline(cnt, kern_s, cal, fp64=False, prof=None):
     """Roofline record of one walk kernel from its work counters and average
     launch time.  roofline: algorithmic vector-ALU operations per second
     against the published vector peak (the traversal is not a contraction: no
@@ -108,7 +117,11 @@ def walk_roofline(cnt, kern_s, cal, fp64=False, traffic=None):
     vector memory path serves random 32-byte records held in L1 (the library's
     gather probe, 32 KiB working set, same run): the ceiling of record loads
     whatever level holds the scene.  hbm: the measured HBM traffic (committed
-    counter summary) over the launch time, against 8 TB/s."""
+    counter summary) over the launch time, against 8 TB/s.  memory_roof: the
+    per-level request rates of the same summary, each over the gather probe's
+    rate into that level (L1: 32 KiB set, L2: 2 MiB, L2 misses: 20 MiB), the
+    largest being the roof."""
+    traffic = prof["traffic"] if prof else None
     lines, nodes, prims, hits = cnt["lines"], cnt["nodes"], cnt["prims"], cnt["hits"]
     alg_flop = nodes * NODE_FLOP + prims * TRI_FLOP
     alg_bytes = nodes * NODE_BYTES + prims * TRI_BYTES + hits * HIT_BYTES
@@ -132,6 +145,12 @@ def walk_roofline(cnt, kern_s, cal, fp64=False, traffic=None):
     if traffic is not None:
         out["hbm"] = {"achieved": traffic / kern_s / 1e9, "peak": 8000.0, "unit": "GB/s",
                       "frac": traffic / kern_s / 8e12}
+    if prof and "memory-levels" in prof:
+        lv = prof["memory-levels"]
+        top = max(lv, key=lv.get)
+        out["memory_roof"] = {"levels": lv, "frac": lv[top], "level": top, "source": prof["profile"]}
+    if prof and "valu" in prof:
+        out["valu"] = dict(prof["valu"], source=prof["profile"])
     return out
 
 
@@ -216,7 +235,7 @@ def timed_leg(torch, wob, w, steps, warmup, cal, leg=None, fp64=False):
            "nonfinite_points": int((~ok).sum()),
            "scene": {k: info[k] for k in ("n_nodes", "n_leaves", "depth", "device_bytes")}}
     out.update(walk_roofline(cnt, kern, cal, fp64=fp64,
-                             traffic=measured_traffic(leg) if leg else None))
+                             prof=measured_profile(leg) if leg else None))
     scene.close()
     return out
 
@@ -260,7 +279,7 @@ def batched_leg(torch, wob, I, cal, steps=2):
         cnt["lines"] += n_lines
         for k in ("nodes", "prims", "hits"):
             cnt[k] += c[k] * n_lines / c["lines"]
-    roof = walk_roofline(cnt, dt, cal)
+    roof = walk_roofline(cnt, dt, cal, prof=measured_profile("batched"))
     for s in scenes:
         s.close()
     return {"workload": "64 perturbed spheres, 2k-200k triangles (sum %d), %d points, 128-1024 paths, M=4, "
@@ -811,7 +830,7 @@ def main():
                    "formulation": "single layer, line sampling (exterior Neumann / Robin)",
                    "parallelism": "none (1 GPU)"},
     }
-    for k in ("lines_per_s", "kernel_ms", "roofline", "vector_memory", "hbm", "work_per_line",
+    for k in ("lines_per_s", "kernel_ms", "roofline", "vector_memory", "hbm", "memory_roof", "valu", "work_per_line",
               "algorithmic_flop_per_launch", "algorithmic_bytes_per_launch", "algorithmic_GB/s",
               "rmse_vs_analytic", "median_abs_err", "mean_se", "nonfinite_points", "scene"):
         if k in main_rec:
