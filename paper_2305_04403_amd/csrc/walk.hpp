@@ -373,130 +373,125 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
   }
 }
 
+// couple >= 0 (gradient walks of the double layer): instead of path `path`'s
+// walk from its evaluation point, start the coupled walk of the boundary split
+// from the anchor on primitive `couple` (see walk_block); the path's value is
+// kept aside.  Both starts end in the same begin_step call, so that its code
+// is inlined once.
 template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
 __device__ __forceinline__ int start_path(const WalkArgs<R, D>& a, PathState<R, D>& s, uint32_t path,
-                                          int64_t item, WorkCount& wc) {
+                                          int64_t item, WorkCount& wc, int32_t couple = -1,
+                                          int64_t point = 0) {
   constexpr bool GRAD = ext_kind(EXT) == X_GRAD, VD = ext_vdata(EXT);
   s.path = path;
-  if constexpr (GRAD) {
+  bool coupled_start = false;
+  if constexpr (GRAD && FORM == F_DL) coupled_start = couple >= 0;
+  if (coupled_start) {
+    // the coupled walk: x* as vertex 1, then the path's own lines 1, 2, ...
+    s.acc_main = s.acc;
+    s.coupled = true;
+    if (couple >= a.scene.n_prims) {  // a caller error: the gradient is NaN
+      s.acc = (R)NAN;
+      return ST_DONE;
+    }
+    if (TRACE) s.vp = s.vm = nullptr;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s.Wg0[k] = 0;
-    s.coupled = false;
-  }
-  if constexpr (FORM == F_FWD) {
-    // y_1 on the boundary: primitive T from the start table (Philox
-    // (id, 0xfffffffe, (problem << 24) | 0xffff03, 0): word 0 against the
-    // binary32 table, words 1, 2 the point, reflected into the triangle), with
-    // density p_0 = P_T / A_T; W_1 = 2 phi q(y_1) / p_0
-    if (item >= a.fwd_paths) return ST_NONE;
-    s.path = (uint32_t)item;
-    const SceneView<R, D>& sc = a.scene;
-    const U4 r = philox(s.path, s.point, (a.problem << 24) | 0xffff03u, 0u, a.k0, a.k1);
-    const float u = unit<float>(r.x);
-    int32_t lo = 0, hi = sc.n_prims - 1;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (a.fwd_cdf[mid] > u) hi = mid;
-      else lo = mid + 1;
+    for (int k = 0; k < 3; ++k) {
+      s.x[k] = k < D ? a.anchor_pts[point * D + k] : (R)0;
+      s.Wg[k] = 0;
     }
-    const int32_t leaf = sc.leaf_of_id[lo];
-    const PrimGeo<R> g = load_prim<R, D>(sc, leaf);
-    R bu = unit<R>(r.y), bv = D == 3 ? unit<R>(r.z) : (R)0;
-    if (bu + bv > (R)1) {
-      bu = (R)1 - bu;
-      bv = (R)1 - bv;
-    }
-    hit_point(g, bu, bv, s.x);
+    s.cur_idx = a.scene.leaf_of_id[couple];
+    s.W = 1;
+    s.i = 1;
+    // the double layer's emission at vertex 1 (halved when it is x_M)
+    const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
     R n[3];
-    load_normal<R, D>(sc, leaf, n);
-    R area;
-    if constexpr (D == 3) {
-      R c[3];
-      cross3(g.e1, g.e2, c);
-      area = (R)0.5 * sqrt(dot3(c, c));
-    } else {
-      area = sqrt(g.e1[0] * g.e1[0] + g.e1[1] * g.e1[1]);
+    load_normal<R, D>(a.scene, s.cur_idx, n);
+    s.acc = ((1 < a.M) ? (R)2 * a.phi : a.phi) * boundary_datum<R, D, VD>(a.prog, g, n, s.x);
+  } else {
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s.Wg0[k] = 0;
+      s.coupled = false;
     }
-    const R pt = (R)a.fwd_cdf[lo] - (lo > 0 ? (R)a.fwd_cdf[lo - 1] : (R)0);
-    s.W = (R)2 * a.phi * boundary_datum<R, D, VD>(a.prog, g, n, s.x) * area / pt;
+    if constexpr (FORM == F_FWD) {
+      // y_1 on the boundary: primitive T from the start table (Philox
+      // (id, 0xfffffffe, (problem << 24) | 0xffff03, 0): word 0 against the
+      // binary32 table, words 1, 2 the point, reflected into the triangle), with
+      // density p_0 = P_T / A_T; W_1 = 2 phi q(y_1) / p_0
+      if (item >= a.fwd_paths) return ST_NONE;
+      s.path = (uint32_t)item;
+      const SceneView<R, D>& sc = a.scene;
+      const U4 r = philox(s.path, s.point, (a.problem << 24) | 0xffff03u, 0u, a.k0, a.k1);
+      const float u = unit<float>(r.x);
+      int32_t lo = 0, hi = sc.n_prims - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a.fwd_cdf[mid] > u) hi = mid;
+        else lo = mid + 1;
+      }
+      const int32_t leaf = sc.leaf_of_id[lo];
+      const PrimGeo<R> g = load_prim<R, D>(sc, leaf);
+      R bu = unit<R>(r.y), bv = D == 3 ? unit<R>(r.z) : (R)0;
+      if (bu + bv > (R)1) {
+        bu = (R)1 - bu;
+        bv = (R)1 - bv;
+      }
+      hit_point(g, bu, bv, s.x);
+      R n[3];
+      load_normal<R, D>(sc, leaf, n);
+      R area;
+      if constexpr (D == 3) {
+        R c[3];
+        cross3(g.e1, g.e2, c);
+        area = (R)0.5 * sqrt(dot3(c, c));
+      } else {
+        area = sqrt(g.e1[0] * g.e1[0] + g.e1[1] * g.e1[1]);
+      }
+      const R pt = (R)a.fwd_cdf[lo] - (lo > 0 ? (R)a.fwd_cdf[lo - 1] : (R)0);
+      s.W = (R)2 * a.phi * boundary_datum<R, D, VD>(a.prog, g, n, s.x) * area / pt;
+      s.acc = 0;
+      s.i = 0;
+      s.cur_idx = leaf;
+      fwd_record<R, D>(a, s, 0, g.id, 0);
+      return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
+    }
+    if (TRACE) {
+      s.vp = a.vtx_prim ? a.vtx_prim + item * a.L : nullptr;
+      s.vm = a.vtx_m ? a.vtx_m + item * a.L : nullptr;
+      for (int i = 0; i < a.L; ++i) {
+        if (s.vp) s.vp[i] = -1;
+        if (s.vm) s.vm[i] = 0;
+      }
+    }
+    // a primitive id outside [-1, n_prims) is a caller error: the path is NaN;
+    // so is a density-mode point off the boundary (it has no boundary unknown)
+    if (s.prim0 < -1 || s.prim0 >= a.scene.n_prims || (a.density && s.prim0 < 0)) {
+      s.acc = (R)NAN;
+      return ST_DONE;
+    }
+    s.cur_idx = s.prim0 >= 0 ? a.scene.leaf_of_id[s.prim0] : -1;
+    s.x[0] = s.x0[0];
+    s.x[1] = s.x0[1];
+    s.x[2] = s.x0[2];
+    if (FORM == F_DL && s.cur_idx >= 0 && !a.density) {
+      // Table 1: on the boundary the Dirichlet solution is the given value
+      const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
+      const R nz[3] = {0, 0, 0};
+      s.acc = boundary_datum<R, D, VD>(a.prog, g, nz, s.x);
+      return ST_DONE;
+    }
+    s.W = 1;
     s.acc = 0;
     s.i = 0;
-    s.cur_idx = leaf;
-    fwd_record<R, D>(a, s, 0, g.id, 0);
-    return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
-  }
-  if (TRACE) {
-    s.vp = a.vtx_prim ? a.vtx_prim + item * a.L : nullptr;
-    s.vm = a.vtx_m ? a.vtx_m + item * a.L : nullptr;
-    for (int i = 0; i < a.L; ++i) {
-      if (s.vp) s.vp[i] = -1;
-      if (s.vm) s.vm[i] = 0;
+    if constexpr (GRAD) {
+  #pragma unroll
+      for (int k = 0; k < 3; ++k) s.Wg[k] = s.gacc[k] = 0;
     }
-  }
-  // a primitive id outside [-1, n_prims) is a caller error: the path is NaN;
-  // so is a density-mode point off the boundary (it has no boundary unknown)
-  if (s.prim0 < -1 || s.prim0 >= a.scene.n_prims || (a.density && s.prim0 < 0)) {
-    s.acc = (R)NAN;
-    return ST_DONE;
-  }
-  s.cur_idx = s.prim0 >= 0 ? a.scene.leaf_of_id[s.prim0] : -1;
-  s.x[0] = s.x0[0];
-  s.x[1] = s.x0[1];
-  s.x[2] = s.x0[2];
-  if (FORM == F_DL && s.cur_idx >= 0 && !a.density) {
-    // Table 1: on the boundary the Dirichlet solution is the given value
-    const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
-    const R nz[3] = {0, 0, 0};
-    s.acc = boundary_datum<R, D, VD>(a.prog, g, nz, s.x);
-    return ST_DONE;
-  }
-  s.W = 1;
-  s.acc = 0;
-  s.i = 0;
-  if constexpr (GRAD) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) s.Wg[k] = s.gacc[k] = 0;
   }
   return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
 }
 
-// Boundary split of the double layer's gradient (Sec. 4.1.3: the first
-// step's derivative kernel is hypersingular near the boundary; split at a
-// boundary point x* near x0).  The derivative weight w' of step 0 has mean
-// zero for x0 off the closed boundary (the double-layer potential of a
-// constant density is constant on each side), so the path may subtract w'
-// times anything independent of its line 0: w' times the coupled walk from
-// x*, which takes x* as its vertex 1 and then the path's own random numbers of
-// lines 1, 2, ...  Near x* the two walks start close together and take the
-// same directions, so their difference, not the kernel, sets the noise.  This
-// starts that walk (the path's value is kept aside); walk_block subtracts
-// w' times its value when it ends.
-template <typename R, int D, int FORM, bool TRACE, bool COUNT, int EXT>
-__device__ __forceinline__ int start_coupled(const WalkArgs<R, D>& a, PathState<R, D>& s, int64_t point,
-                                             int32_t anchor, WorkCount& wc) {
-  constexpr bool VD = ext_vdata(EXT);
-  s.acc_main = s.acc;
-  s.coupled = true;
-  if (anchor >= a.scene.n_prims) {  // a caller error: the gradient is NaN
-    s.acc = (R)NAN;
-    return ST_DONE;
-  }
-  if (TRACE) s.vp = s.vm = nullptr;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    s.x[k] = k < D ? a.anchor_pts[point * D + k] : (R)0;
-    s.Wg[k] = 0;
-  }
-  s.cur_idx = a.scene.leaf_of_id[anchor];
-  s.W = 1;
-  s.i = 1;
-  // the double layer's emission at vertex 1 (halved when it is x_M)
-  const PrimGeo<R> g = load_prim<R, D>(a.scene, s.cur_idx);
-  R n[3];
-  load_normal<R, D>(a.scene, s.cur_idx, n);
-  s.acc = ((1 < a.M) ? (R)2 * a.phi : a.phi) * boundary_datum<R, D, VD>(a.prog, g, n, s.x);
-  return begin_step<R, D, FORM, TRACE, COUNT, EXT>(a, s, wc);
-}
 
 // The primitives of the crossed leaves a lane holds (one to four) on the
 // current line.  The primitive loop
@@ -816,53 +811,57 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     for (;;) {
       // finished paths: record, start the lane's next one
       while (st == ST_DONE) {
+        // boundary split (gradient walks of the double layer): a path whose
+        // point has an anchor and whose line 0 met the boundary runs the
+        // coupled walk from the anchor next, then subtracts w' times its value
+        int32_t couple = -1;
         if constexpr (GRAD && FORM == F_DL) {
           if (s.coupled) {
-            // the coupled walk ended: subtract w' times its value
 #pragma unroll
             for (int c = 0; c < 3; ++c) s.gacc[c] -= s.Wg0[c] * s.acc;
             s.acc = s.acc_main;
             s.coupled = false;
           } else if (a.anchor_prim) {
             const int32_t anchor = a.anchor_prim[point];
-            if (anchor >= 0 && (s.Wg0[0] != (R)0 || s.Wg0[1] != (R)0 || s.Wg0[2] != (R)0)) {
-              st = start_coupled<R, D, FORM, TRACE, COUNT, KEXT>(a, s, point, anchor, wc);
-              continue;
-            }
-            if (anchor < -1) s.gacc[0] = (R)NAN;  // a caller error: the gradient is NaN
+            if (anchor >= 0 && (s.Wg0[0] != (R)0 || s.Wg0[1] != (R)0 || s.Wg0[2] != (R)0)) couple = anchor;
+            else if (anchor < -1) s.gacc[0] = (R)NAN;  // a caller error: the gradient is NaN
           }
         }
-        const R v = s.acc;
-        if (TRACE) a.path_out[point * (int64_t)a.N + k] = v;
-        bool finite = isfinite(v);
-        if constexpr (GRAD) {
-#pragma unroll
-          for (int c = 0; c < GD; ++c) {
-            if (TRACE) a.path_grad_out[(point * (int64_t)a.N + k) * D + c] = s.gacc[c];
-            finite = finite && isfinite(s.gacc[c]);
-          }
-        }
-        if (finite) {
-          n += 1.0;
-          const double dv = (double)v - mean;
-          mean += dv / n;
-          m2 += dv * ((double)v - mean);
+        if (couple < 0) {
+          const R v = s.acc;
+          if (TRACE) a.path_out[point * (int64_t)a.N + k] = v;
+          bool finite = isfinite(v);
           if constexpr (GRAD) {
 #pragma unroll
             for (int c = 0; c < GD; ++c) {
-              const double dg = (double)s.gacc[c] - gmean[c];
-              gmean[c] += dg / n;
-              gm2[c] += dg * ((double)s.gacc[c] - gmean[c]);
+              if (TRACE) a.path_grad_out[(point * (int64_t)a.N + k) * D + c] = s.gacc[c];
+              finite = finite && isfinite(s.gacc[c]);
             }
           }
-        } else if (!TRACE && !COUNT && FORM != F_FWD && a.status) {
-          // a non-finite path (degenerate geometry, an invalid primitive id, data
-          // singular on the boundary) is counted and left out of the statistics
-          atomicAdd(a.status, 1ull);
+          if (finite) {
+            n += 1.0;
+            const double dv = (double)v - mean;
+            mean += dv / n;
+            m2 += dv * ((double)v - mean);
+            if constexpr (GRAD) {
+#pragma unroll
+              for (int c = 0; c < GD; ++c) {
+                const double dg = (double)s.gacc[c] - gmean[c];
+                gmean[c] += dg / n;
+                gm2[c] += dg * ((double)s.gacc[c] - gmean[c]);
+              }
+            }
+          } else if (!TRACE && !COUNT && FORM != F_FWD && a.status) {
+            // a non-finite path (degenerate geometry, an invalid primitive id, data
+            // singular on the boundary) is counted and left out of the statistics
+            atomicAdd(a.status, 1ull);
+          }
+          k += lpp;
         }
-        k += lpp;
-        st = k < a.N ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc)
-                     : ST_NONE;
+        st = (couple >= 0 || k < a.N)
+                 ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc,
+                                                              couple, point)
+                 : ST_NONE;
       }
       const int idle = __popcll(__ballot(st == ST_NONE));
       if (idle == 64) break;
