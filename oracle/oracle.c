@@ -1880,10 +1880,10 @@ static int collect_hits(const orc_mesh* m, const double* x, const double* d, int
 /* Value of the corrected path; *abs_out and *err_out (may be NULL) receive its
    magnitude sum and its first-order rounding-error bound in units of u (the
    bookkeeping of one_path, extended to the all-hits sums). */
-static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc* bc,
-                          const double* g, const double* g0, const double* x0, int64_t prim0,
-                          int M, uint64_t seed, uint32_t problem, uint32_t point, uint32_t path,
-                          double* abs_out, double* err_out) {
+static double one_path_cv(const orc_mesh* m, const double* normals, const area_table* at,
+                          const orc_bc* bc, const double* g, const double* g0, const double* x0,
+                          int64_t prim0, int M, uint64_t seed, uint32_t problem, uint32_t point,
+                          uint32_t path, double* abs_out, double* err_out) {
   const int dim = m->dim;
   const double phi = (double)bc->domain;
   double x[3] = {x0[0], x0[1], dim == 3 ? x0[2] : 0.0};
@@ -1909,11 +1909,119 @@ static double one_path_cv(const orc_mesh* m, const double* normals, const orc_bc
       d[0] = cos(th);
       d[1] = sin(th);
     }
-    const int mixture = on_gamma && (i == 0 || prim_kind(m, cur) == ORC_ROBIN);
-    const int use_self = mixture && (r0[2] >> 8) < bc->self_threshold;
     double y[3];
     int64_t next;
     double Wn, Wnabs, eWn, Pn;
+    if (bc->sampling == ORC_SAMPLE_RIS) {
+      /* RIS vertex (candidates and pick as in one_path): given the C
+         candidates, the pick's expected contribution w F(y_pick) is
+         (|Gamma| / C) sum_j k(y_j) F(y_j); the corrected walk adds that sum
+         and subtracts w F(y_pick), with F as for line sampling (line 0: the
+         table g0, its mean restored by the add-back; lines 1..M-2:
+         2 phi s + g; the last line, line 0 included when M = 1: phi s, with
+         no pick). */
+      const int C = bc->candidates;
+      const double* nx = on_gamma ? normals + 3 * cur : NULL;
+      const double ax = on_gamma ? prim_alpha(m, cur) : 0.0;
+      const double cw = at->total / (double)C;
+      double S = 0.0, Smag = 0.0, dS = 0.0, kpick = 0.0, csum = 0.0, cabs = 0.0, cerr = 0.0;
+      int64_t jpick = -1;
+      for (int jc = 0; jc < C; ++jc) {
+        uint32_t rj[4];
+        draw(seed, path, point, problem, (uint32_t)i, 3u, (uint32_t)jc, rj);
+        const int64_t pj = area_pick(at, m->n_prims, (float)uniform(rj[0]));
+        double ca = uniform(rj[1]), cb = dim == 3 ? uniform(rj[2]) : 0.0;
+        if (ca + cb > 1.0) {
+          ca = 1.0 - ca;
+          cb = 1.0 - cb;
+        }
+        double v0[3], v1[3], v2[3] = {0.0, 0.0, 0.0}, yc[3] = {0.0, 0.0, 0.0};
+        prim_vertex(m, pj, 0, v0);
+        prim_vertex(m, pj, 1, v1);
+        if (dim == 3) prim_vertex(m, pj, 2, v2);
+        for (int c = 0; c < dim; ++c) yc[c] = v0[c] + ca * (v1[c] - v0[c]) + cb * (v2[c] - v0[c]);
+        double r[3] = {yc[0] - x[0], yc[1] - x[1], dim == 3 ? yc[2] - x[2] : 0.0};
+        const double rr = dot(r, r, dim);
+        double k = 0.0, kmag = 0.0, dk = 0.0;
+        if (rr > 0.0) {
+          const double rho = sqrt(rr), drho = P + xn + norm_d(yc, dim);
+          if (i == 0) {
+            k = G(x, yc, dim);
+            kmag = G_mag(x, yc, dim);
+            dk = (dim == 3 ? 1.0 / (4.0 * ORC_PI * rr) : 1.0 / (2.0 * ORC_PI * rho)) * drho;
+          } else {
+            /* (y - x) . n_x from the candidate's vertex and edges (zero on the
+               own primitive), as in one_path */
+            double rn = 0.0;
+            if (pj != cur) {
+              double w0[3];
+              prim_vertex(m, cur, 0, w0);
+              double dv[3] = {v0[0] - w0[0], v0[1] - w0[1], dim == 3 ? v0[2] - w0[2] : 0.0};
+              double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], dim == 3 ? v1[2] - v0[2] : 0.0};
+              double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], dim == 3 ? v2[2] - v0[2] : 0.0};
+              rn = dot(dv, nx, dim) + ca * dot(e1, nx, dim) + (dim == 3 ? cb * dot(e2, nx, dim) : 0.0);
+            }
+            const double dgdn = dim == 3 ? rn / (4.0 * ORC_PI * rr * rho) : rn / (2.0 * ORC_PI * rr);
+            k = -2.0 * phi * (dgdn + ax * G(x, yc, dim));
+            const double dn2 = fabs(2.0 * dgdn);
+            kmag = dn2 + 2.0 * fabs(ax) * G_mag(x, yc, dim);
+            const double sd = dim == 3 ? 4.0 * ORC_PI * rr * rho : 2.0 * ORC_PI * rr;
+            dk = dn2 * (double)dim * drho / rho + 2.0 * (xn + norm_d(yc, dim)) / sd +
+                 2.0 * fabs(ax) * (dim == 3 ? 1.0 / (4.0 * ORC_PI * rr) : 1.0 / (2.0 * ORC_PI * rho)) * drho;
+          }
+        }
+        const double pk = fabs(k);
+        S += pk;
+        Smag += kmag;
+        dS += dk;
+        const double u = uniform(rj[3]);
+        if (u * S < pk) {
+          jpick = pj;
+          kpick = k;
+          memcpy(y, yc, sizeof(y));
+        }
+        if (i > 0 || last) { /* the candidate's term of the all-candidates sum */
+          const double kf = last ? phi : 2.0 * phi;
+          const double e = kf * orc_boundary_datum(m, bc, pj, yc);
+          const double F = e + (last ? 0.0 : g[pj]);
+          csum += cw * k * F;
+          cabs += cw * kmag * (fabs(e) + (last ? 0.0 : fabs(g[pj])));
+          cerr += cw * (kmag * emission_err(m, bc, pj, yc, kf, norm_d(yc, dim)) +
+                        (eW * kmag + dk) * (fabs(e) + (last ? 0.0 : fabs(g[pj]))));
+        }
+      }
+      if (i > 0 || last) {
+        acc += W * csum;
+        abs_sum += Wabs * cabs;
+        err += Wabs * cerr;
+      }
+      if (last || jpick < 0 || !(S > 0.0)) break;
+      const double w = (kpick > 0.0 ? 1.0 : -1.0) * S * cw;
+      Wn = W * w;
+      Wnabs = Wabs * Smag * cw;
+      eWn = eW + dS / Smag;
+      Pn = norm_d(y, dim); /* a point drawn by its barycentrics */
+      next = jpick;
+      if (i == 0) {
+        const double ej = 2.0 * phi * orc_boundary_datum(m, bc, next, y);
+        acc += Wn * (ej - g0[next]);
+        abs_sum += Wnabs * (fabs(g0[next]) + fabs(ej));
+        err += Wnabs * emission_err(m, bc, next, y, 2.0 * phi, Pn) + eWn * Wnabs * (fabs(g0[next]) + fabs(ej));
+      } else {
+        acc -= Wn * g[next]; /* the picked candidate's emission is inside the sum */
+        abs_sum += Wnabs * fabs(g[next]);
+        err += eWn * Wnabs * fabs(g[next]);
+      }
+      W = Wn;
+      Wabs = Wnabs;
+      eW = eWn;
+      P = Pn;
+      memcpy(x, y, sizeof(x));
+      cur = next;
+      continue;
+    }
+    const int mixture = on_gamma && (i == 0 || prim_kind(m, cur) == ORC_ROBIN);
+    const int use_self = mixture && (r0[2] >> 8) < bc->self_threshold;
     if (use_self) {
       uint32_t r1[4];
       draw(seed, path, point, problem, (uint32_t)i, 1u, 0u, r1);
@@ -2027,6 +2135,7 @@ int orc_trace_cv(const orc_mesh* m, const double* points, const int32_t* point_p
   for (int64_t j = 0; j < m->n_prims; ++j)
     if (prim_kind(m, j) == ORC_DIRICHLET) return 1; /* the corrected walk has no Dirichlet rows */
   double* normals = make_normals(m);
+  area_table at = make_area_table(m);
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -2037,10 +2146,11 @@ int orc_trace_cv(const orc_mesh* m, const double* points, const int32_t* point_p
     double x0[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < m->dim; ++a) x0[a] = points[p * m->dim + a];
     const int64_t prim0 = point_prim ? point_prim[p] : -1;
-    value[it] = one_path_cv(m, normals, bc, g, g0, x0, prim0, walk_len, seed, problem,
+    value[it] = one_path_cv(m, normals, &at, bc, g, g0, x0, prim0, walk_len, seed, problem,
                             (uint32_t)p, (uint32_t)item_path[it], abs_sum ? abs_sum + it : NULL,
                             err ? err + it : NULL);
   }
   free(normals);
+  free(at.cdf);
   return 0;
 }

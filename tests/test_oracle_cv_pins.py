@@ -255,12 +255,15 @@ def _tori_problem(grid_n=14):
     return w
 
 
-def test_control_variate_is_unbiased_for_any_table():
+@pytest.mark.parametrize("sampling", [oracle.SAMPLE_LINE, oracle.SAMPLE_RIS])
+def test_control_variate_is_unbiased_for_any_table(sampling):
     """For an arbitrary (even adversarial) table g, mean(CV path) + add-back equals
-    the plain mean: every correction has zero conditional mean."""
+    the plain mean: every correction has zero conditional mean (line sampling:
+    given the line; RIS: given the candidates)."""
     w = _tori_problem()
     om = oracle.OracleMesh(w.mesh)
-    bc = oracle.make_bc(**{k: w.bc[k] for k in ("domain", "formulation", "program", "params")})
+    bc = oracle.make_bc(**{k: w.bc[k] for k in ("domain", "formulation", "program", "params")},
+                        sampling=sampling, candidates=8)
     rng = np.random.default_rng(3)
     g = rng.standard_normal(w.mesh.n_prims) * 3.0 + 1.0
     g0 = rng.standard_normal(w.mesh.n_prims) * 2.0 - 1.0   # a different line-0 table
@@ -281,12 +284,15 @@ def test_control_variate_is_unbiased_for_any_table():
     assert np.max(np.abs(z0)) < 4.5
 
 
-def test_control_variate_with_one_line_is_all_hits_average():
-    """M = 1: the corrected path is sum_h a(h) phi s(y_h), the conditional mean of
-    the plain one given the line."""
+@pytest.mark.parametrize("sampling", [oracle.SAMPLE_LINE, oracle.SAMPLE_RIS])
+def test_control_variate_with_one_line_is_all_hits_average(sampling):
+    """M = 1: the corrected path is sum_h a(h) phi s(y_h) (RIS: the
+    all-candidates average (|Gamma| / C) sum_j k_j phi s(y_j)), the conditional
+    mean of the plain one given the line (the candidates)."""
     w = _tori_problem()
     om = oracle.OracleMesh(w.mesh)
-    bc = oracle.make_bc(**{k: w.bc[k] for k in ("domain", "formulation", "program", "params")})
+    bc = oracle.make_bc(**{k: w.bc[k] for k in ("domain", "formulation", "program", "params")},
+                        sampling=sampling, candidates=8)
     P, N = w.points.shape[0], 2000
     ip, ik = np.repeat(np.arange(P), N), np.tile(np.arange(N), P)
     plain = oracle.trace(om, w.points, w.point_prim, bc, 1, 2, ip, ik, want_pos=False)["value"].reshape(P, N)
