@@ -303,6 +303,9 @@ def _boot_ratio(mse_a, mse_b, med_a, med_b, reps=4000, seed=0):
     q = med_a[idx].mean(1) / med_b[idx].mean(1)
     return {"rmse_ratio": math.sqrt(mse_a.mean() / mse_b.mean()),
             "rmse_ratio_95": [float(np.quantile(r, 0.025)), float(np.quantile(r, 0.975))],
+            # the median seed's RMSE ratio: what a typical run sees, where the
+            # pooled ratio is set by the rare seed that draws an extreme path
+            "rmse_ratio_median_seed": math.sqrt(float(np.median(mse_a)) / float(np.median(mse_b))),
             "median_err_ratio": float(med_a.mean() / med_b.mean()),
             "median_err_ratio_95": [float(np.quantile(q, 0.025)), float(np.quantile(q, 0.975))]}
 
@@ -321,7 +324,8 @@ def cv_leg(torch, wob, I, n_seeds=10):
     corrected estimator with (a) g = g0 = 0 (hit-selection Rao-Blackwellisation
     only), (b) the learned network (fit included in its time) and (c) the same
     without the fit time; and plain resampled importance sampling (4 and 16
-    area candidates) in place of line sampling.  Every variant runs with
+    area candidates) in place of line sampling, and the corrected walk on
+    RIS-16 (g = g0 = 0, and learned).  Every variant runs with
     `n_seeds` seeds; RMSE ratios pool the per-seed squared errors and carry a
     paired bootstrap 95 % interval over the seeds.  Also the per-point
     variance of each variant (paired log ratio against (a) on the same seeds)
@@ -349,6 +353,25 @@ def cv_leg(torch, wob, I, n_seeds=10):
     sync()
 
     seeds = tuple(range(11, 11 + n_seeds))
+
+    def slope(fn, lo=64, hi=320):
+        """Cost per path and the fixed rest (add-back, launch overheads): the
+        slope between `lo` and `hi` paths on the full point set, fastest of two
+        runs each, after a full-size warm-up (a one-off stall in a probe would
+        otherwise skew the slope)."""
+        fn(lo)
+        sync()
+        tt = []
+        for n_probe in (lo, hi):
+            best = float("inf")
+            for _ in range(2):
+                t0 = time.perf_counter()
+                fn(n_probe)
+                sync()
+                best = min(best, time.perf_counter() - t0)
+            tt.append(best)
+        per = max((tt[1] - tt[0]) / (hi - lo), 1e-9)
+        return per, max(tt[0] - lo * per, 0.0)
 
     def record(runs, times, extra_s=0.0):
         a = [m.double().cpu().numpy() for m, _ in runs]
@@ -394,23 +417,22 @@ def cv_leg(torch, wob, I, n_seeds=10):
     wob.cv_addback(scene, lcv.g0, pts)
     sync()
     t_add = time.perf_counter() - t0
-    # cost per corrected path: slope between 64 and 128 paths (fixed costs cancel)
-    tt = []
-    for n_probe in (64, 128):
-        t0 = time.perf_counter()
-        wob.solve_cv(scene, pts, bc, n_probe, M, lcv.g, seed=2, point_prim=pp, g0=lcv.g0)
-        sync()
-        tt.append(time.perf_counter() - t0)
-    per_path = max((tt[1] - tt[0]) / 64, 1e-9)
-    base = max(tt[0] - 64 * per_path, 0.0)   # add-back and launch overheads
+    ris16 = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=16)
+
+    def cost(b):
+        return slope(lambda n: wob.solve_cv(scene, pts, b, n, M, lcv.g, seed=2, point_prim=pp, g0=lcv.g0))
+
+    costs = {id(bc): cost(bc), id(ris16): cost(ris16)}
     variants = {"plain": plain}
 
-    def run_cv(name, g, g0, fixed_s, seed0):
+    def run_cv(name, g, g0, fixed_s, seed0, b=bc):
+        per_path, base = costs[id(b)]
         n = int(max(16, (t_plain - fixed_s - base) / per_path // 16 * 16))
-        runs, times = timed(lambda sd: wob.solve_cv(scene, pts, bc, n, M, g, seed=sd + 100 * seed0,
+        runs, times = timed(lambda sd: wob.solve_cv(scene, pts, b, n, M, g, seed=sd + 100 * seed0,
                                                     point_prim=pp, g0=g0))
         variants[name] = record(runs, times, fixed_s)
         variants[name]["paths"] = n
+        variants[name]["path_cost_vs_line"] = per_path / (t_plain / N)
 
     run_cv("rb_only", zero, zero, 0.0, 3)
     run_cv("learned", lcv.g, lcv.g0, fit["fit_s"], 5)
@@ -421,28 +443,32 @@ def cv_leg(torch, wob, I, n_seeds=10):
     # candidates (16 in the paper; 4 is cheaper than a traced line)
     for C in (4, 16):
         b = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=C)
-        wob.solve(scene, pts[:4096].contiguous(), b, 64, M, point_prim=pp[:4096].contiguous())
-        tt = []
-        for n_probe in (64, 128):
-            t0 = time.perf_counter()
-            wob.solve(scene, pts, b, n_probe, M, seed=2, point_prim=pp)
-            sync()
-            tt.append(time.perf_counter() - t0)
-        pp_cost = max((tt[1] - tt[0]) / 64, 1e-9)
-        n = int(max(16, (t_plain - max(tt[0] - 64 * pp_cost, 0.0)) / pp_cost // 16 * 16))
+        pp_cost, rest = slope(lambda n: wob.solve(scene, pts, b, n, M, seed=2, point_prim=pp))
+        n = int(max(16, (t_plain - rest) / pp_cost // 16 * 16))
         runs, times = timed(lambda sd: wob.solve(scene, pts, b, n, M, seed=sd + 700 + C, point_prim=pp))
         variants[f"ris_{C}"] = record(runs, times)
         variants[f"ris_{C}"].update({"paths": n, "path_cost_vs_line": pp_cost / (t_plain / N)})
+    # the corrected walk on RIS (16 candidates): the pick's mean over the
+    # candidates replaces the pick, with g = g0 = 0 and with the learned tables
+    run_cv("ris_16_rb_only", zero, zero, 0.0, 8, b=ris16)
+    run_cv("ris_16_learned", lcv.g, lcv.g0, fit["fit_s"], 9, b=ris16)
 
     # the same-paths variance comparison (N paths, seed 11): every variant's
     # per-point variance against the Rao-Blackwellised one, paired by point
     v_rb = wob.solve_cv(scene, pts, bc, N, M, zero, seed=11, point_prim=pp, g0=zero)[1].double().cpu().numpy()
     v_ln = wob.solve_cv(scene, pts, bc, N, M, lcv.g, seed=11, point_prim=pp, g0=lcv.g0)[1].double().cpu().numpy()
-    lr = np.log(np.maximum(v_ln, 1e-30) / np.maximum(v_rb, 1e-30))
-    lr = lr[np.isfinite(lr)]
-    out["learned_vs_rb_same_paths"] = {"mean_log_var_ratio": float(lr.mean()),
-                                       "se": float(lr.std() / math.sqrt(max(len(lr), 1))),
-                                       "median_log_var_ratio": float(np.median(lr))}
+    v_rr = wob.solve_cv(scene, pts, ris16, N, M, zero, seed=11, point_prim=pp, g0=zero)[1].double().cpu().numpy()
+    v_rl = wob.solve_cv(scene, pts, ris16, N, M, lcv.g, seed=11, point_prim=pp,
+                        g0=lcv.g0)[1].double().cpu().numpy()
+
+    def paired(a, b):
+        lr = np.log(np.maximum(a, 1e-30) / np.maximum(b, 1e-30))
+        lr = lr[np.isfinite(lr)]
+        return {"mean_log_var_ratio": float(lr.mean()), "se": float(lr.std() / math.sqrt(max(len(lr), 1))),
+                "median_log_var_ratio": float(np.median(lr))}
+
+    out["learned_vs_rb_same_paths"] = paired(v_ln, v_rb)
+    out["ris_16_learned_vs_ris_16_rb_same_paths"] = paired(v_rl, v_rr)
     sub = slice(0, 2000)
     ps, pps = pts[sub].contiguous(), pp[sub].contiguous()
     out["tail_share_of_squared_deviation"] = {
@@ -450,7 +476,9 @@ def cv_leg(torch, wob, I, n_seeds=10):
         "rb_only": _tail_shares(wob.trace_cv(scene, ps, bc, N, M, zero, seed=11, point_prim=pps, g0=zero)),
         "ris_16": _tail_shares(wob.trace(scene, ps, dataclasses.replace(bc, sampling=wob.SAMPLE_RIS,
                                                                          candidates=16),
-                                         N, M, seed=11, point_prim=pps)[0])}
+                                         N, M, seed=11, point_prim=pps)[0]),
+        "ris_16_rb_only": _tail_shares(wob.trace_cv(scene, ps, ris16, N, M, zero, seed=11, point_prim=pps,
+                                                    g0=zero))}
     for name, r in variants.items():
         if name != "plain":
             r.update(_boot_ratio(plain["_mse"], r["_mse"], plain["_med"], r["_med"]))
@@ -461,7 +489,7 @@ def cv_leg(torch, wob, I, n_seeds=10):
     out["mlp_forward"] = {"points": 1 << 20, "ms": 1e3 * t_mlp, "TFLOP/s": mlp_tflops, "peak_bf16_TFLOP/s": 2500.0,
                           "frac": mlp_tflops / 2500.0}
     out["addback_s"] = t_add
-    out["corrected_path_cost_vs_plain"] = per_path / (t_plain / N)
+    out["corrected_path_cost_vs_plain"] = costs[id(bc)][0] / (t_plain / N)
     out["rmse_ratio_equal_time"] = out["learned"]["rmse_ratio"]
     out["rmse_ratio_equal_time_95"] = out["learned"]["rmse_ratio_95"]
     out["median_err_ratio_equal_time"] = out["learned"]["median_err_ratio"]

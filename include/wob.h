@@ -544,7 +544,9 @@ wob_status wob_cv_table(wob_scene scene, wob_mlp net, float* g_out, void* stream
 /* Exact control variate for the single-layer estimator (3D, binary32 scenes;
  * the control variate is not part of the paper).  Same paths and picks as
  * wob_solve; every line adds a term whose mean given the line is zero because
- * the pick is uniform over the m hits:
+ * the pick is uniform over the m hits (with RIS sampling: given the C
+ * candidates, the pick's mean is (|Gamma| / C) sum_j k(y_j) F(y_j), and the
+ * sums below run over the candidates):
  *   line 0:     the subtraction w(j) g0(T_j), whose mean sum_T g0_T int_T G(x0, y) dA
  *               is added per point (wob_cv_addback, with the solve's seed);
  *   lines 1..M-2: the all-hits sum of a(h) [2 phi s(y_h) + g(T_h)] minus the

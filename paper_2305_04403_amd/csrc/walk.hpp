@@ -167,13 +167,21 @@ __device__ __forceinline__ void fwd_end(const WalkArgs<R, D>& a, const PathState
 // candidate j when u_j S_j < |k_j|; weight sign(k) S |Gamma| / C.  Moves the
 // path to the kept point and adds its emission; returns false when no
 // candidate carries kernel mass (the path ends).
-template <typename R, int D, bool TRACE, bool GRAD, bool VD>
+// CV (corrected walk, 3D single layer): given the candidates, the pick's
+// expected contribution w F(y_pick) is (|Gamma| / C) sum_j k(y_j) F(y_j); the
+// step adds that sum and subtracts w F(y_pick), with F as for line sampling
+// (line 0: the table g0, restored by the add-back; lines 1..M-2: 2 phi s + g;
+// the last line: phi s, with no pick).
+template <typename R, int D, bool TRACE, bool GRAD, bool VD, bool CV>
 __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D>& s) {
   const SceneView<R, D>& sc = a.scene;
   const R phi = a.phi;
   const R inv4pi = (R)(0.25 / 3.14159265358979323846), inv2pi = (R)(0.5 / 3.14159265358979323846);
   R S = 0, kpick = 0, ypick[3] = {0, 0, 0};
   int32_t lpick = -1;
+  const bool last = s.i == a.L - 1;
+  const bool sum = CV && (s.i > 0 || last);
+  R csum = 0;
   for (int j = 0; j < a.ris_c; ++j) {
     const U4 rj = philox(s.path, s.point, s.z | 3u, (uint32_t)j, a.k0, a.k1);
     const float u = unit<float>(rj.x);
@@ -224,6 +232,18 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
       ypick[1] = y[1];
       ypick[2] = y[2];
     }
+    if constexpr (CV) {
+      if (sum) {  // the candidate's term of the all-candidates sum
+        R cn[3];
+        load_normal<R, D>(sc, leaf, cn);
+        const R e = sl_emission<R, D, VD>(a, g, cn, y, s.i + 1 >= a.M);
+        csum += k * (last ? e : e + a.cv_g[g.id]);
+      }
+    }
+  }
+  if constexpr (CV) {
+    if (sum) s.acc += s.W * csum * sc.area_total / (R)a.ris_c;
+    if (last) return false;  // the last line needs no pick
   }
   if (lpick < 0 || !(S > (R)0)) return false;
   const R w = (kpick > (R)0 ? (R)1 : (R)-1) * S * sc.area_total / (R)a.ris_c;
@@ -251,6 +271,14 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
   R nn[3];
   load_normal<R, D>(sc, lpick, nn);
   if (TRACE && s.vp) s.vp[s.i] = gn.id;
+  if constexpr (CV) {
+    if (s.i == 0) {  // the line-0 table subtracted, the emission kept
+      s.acc += s.W * (sl_emission<R, D, VD>(a, gn, nn, s.x, false) - a.cv_g0[gn.id]);
+    } else {  // the picked emission is inside the sum
+      s.acc -= s.W * a.cv_g[gn.id];
+    }
+    return true;
+  }
   const R e = sl_emission<R, D, VD>(a, gn, nn, s.x, s.i + 1 >= a.M);
   s.acc += s.W * e;
   if constexpr (GRAD) {
@@ -317,7 +345,7 @@ __device__ __forceinline__ int begin_step(const WalkArgs<R, D>& a, PathState<R, 
         s.gscale = -a.mixed_k / a.mixed_p;
       }
       if constexpr (FORM == F_SL_RIS) {
-        if (!ris_step<R, D, TRACE, GRAD, VD>(a, s)) return ST_DONE;
+        if (!ris_step<R, D, TRACE, GRAD, VD, CV>(a, s)) return ST_DONE;
         ++s.i;
         continue;
       }
@@ -774,8 +802,9 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
 #pragma unroll
   for (int c = 0; c < GD; ++c) gmean[c] = gm2[c] = 0.0;
   WorkCount wc = {0, 0, 0, 0};
-  // the corrected walk exists for the 3D single layer only
-  constexpr int KEXT = (ext_kind(EXT) == X_CV && !(D == 3 && FORM == F_SL)) ? (EXT & X_VDATA) : EXT;
+  // the corrected walk exists for the 3D single layer only (lines and RIS)
+  constexpr int KEXT =
+      (ext_kind(EXT) == X_CV && !(D == 3 && (FORM == F_SL || FORM == F_SL_RIS))) ? (EXT & X_VDATA) : EXT;
   {
     // Paths k = lane_in_point, + lpp, ... of this lane, run as one state
     // machine.  Lanes step through BVH nodes; a lane that has reached four

@@ -300,7 +300,7 @@ void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
       return;
     }
   }
-  if constexpr (D == 3 && FORM == wob::F_SL) {
+  if constexpr (D == 3 && (FORM == wob::F_SL || FORM == wob::F_SL_RIS)) {
     if (a.cv_g) {
       if (mode == MODE_SOLVE)
         hipLaunchKernelGGL((wob::walk_kernel<R, D, FORM, false, false, B, wob::X_CV | VX>), grid, block, lds, st,
@@ -345,7 +345,7 @@ wob_status run_walk(wob_scene sc, const void* points, const int32_t* point_prim,
   wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
   if (s != WOB_OK) return s;
   if (cv_g && (sc->dim != 3 || sc->precision != WOB_F32 || pl.form != WOB_F_SINGLE_LAYER ||
-               bc->density || pl.ris_c > 0 || sc->n_dirichlet > 0))
+               bc->density || sc->n_dirichlet > 0))
     return WOB_E_UNSUPPORTED;
   const bool grad = grad_out || path_grad_out;
   // gradients: evaluation points inside the domain, no density mode, no control variate

@@ -55,13 +55,15 @@ def test_addback_matches_oracle(W, tori):
     scene.close()
 
 
-@pytest.mark.parametrize("separate_g0", [False, True])
-def test_trace_cv_matches_oracle(W, tori, separate_g0):
+@pytest.mark.parametrize("separate_g0,sampling", [(False, 0), (True, 0), (True, 1)])
+def test_trace_cv_matches_oracle(W, tori, separate_g0, sampling):
+    """Per-path corrected values against the oracle; with RIS (sampling 1, 16
+    candidates) the correction sums over the candidates."""
     rng = np.random.default_rng(2)
     g = PT.f32(rng.standard_normal(tori.mesh.n_prims))
     g0 = PT.f32(rng.standard_normal(tori.mesh.n_prims) * 2.0 + 1.0) if separate_g0 else None
     scene = W.Scene(tori.mesh, W.F32)
-    wb, ob = bcs(W, tori)
+    wb, ob = bcs(W, tori, sampling=sampling, candidates=16)
     P, N, M = tori.points.shape[0], 64, 4
     val = W.trace_cv(scene, dev(tori.points), wb, N, M, g=dev(g), seed=3,
                      point_prim=dev(tori.point_prim, torch.int32), g0=None if g0 is None else dev(g0))
@@ -144,13 +146,15 @@ def test_emission_table_matches_oracle(W, tori):
     scene.close()
 
 
-def test_solve_cv_is_unbiased_on_gpu(W, tori):
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_solve_cv_is_unbiased_on_gpu(W, tori, sampling):
     """Corrected and plain solves on the same points: the per-point difference of
-    the means is within 4.5 standard errors of zero, for an arbitrary table."""
+    the means is within 4.5 standard errors of zero, for an arbitrary table
+    (lines and RIS)."""
     rng = np.random.default_rng(5)
     g = PT.f32(rng.standard_normal(tori.mesh.n_prims) * 2.0)
     scene = W.Scene(tori.mesh, W.F32)
-    wb, _ = bcs(W, tori)
+    wb, _ = bcs(W, tori, sampling=sampling, candidates=16)
     pts = dev(tori.points)
     pp = dev(tori.point_prim, torch.int32)
     N = 16384
