@@ -39,10 +39,10 @@ namespace wobi {
 // 256 / 128 / 64 lanes 723 / 621 / 522 ms; icosphere slice 58.9 / 58.8 / 58.7).
 constexpr int kSolveBlock = 64;
 
-// Paths each lane runs back to back: a lane's work is then the sum of many
-// lines, whose spread across the lanes of a wavefront is smaller than that of
-// single lines (measured on the 20,480-triangle icosphere benchmark with 2, 4,
-// 8, 16 paths per lane: 708, 732, 738, 728 M path samples/s).
+// Paths per lane, on average (the lanes of a point share its paths and take
+// the next one as theirs end): fixes the lanes per point.  Measured with 4, 8
+// and 16: three-tori workload (512 paths) 1,301 / 1,300 / 1,110 M path
+// samples/s, icosphere slice (256 paths) 747 / 767 / 769 M.
 constexpr int kPathsPerLane = 8;
 
 // log2 of the lanes that share one point: the smallest power of two >=

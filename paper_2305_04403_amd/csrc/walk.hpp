@@ -7,12 +7,12 @@
 namespace wob {
 
 // Dynamic LDS of the path kernels: the lanes' traversal stacks and held
-// leaves, stack_cap + kLeafSlots entries of 4 bytes per thread of the block
-// (sized at launch).
+// leaves, stack_cap + kLeafSlots entries of 4 bytes per thread of the block,
+// then one more row (the path counters of the lane groups; sized at launch).
 extern __shared__ int32_t wob_stack[];
 constexpr int kLeafSlots = 4;
 inline size_t walk_lds_bytes(int stack_cap, int block) {
-  return (size_t)(stack_cap + kLeafSlots) * (size_t)block * sizeof(int32_t);
+  return (size_t)(stack_cap + kLeafSlots + 1) * (size_t)block * sizeof(int32_t);
 }
 
 template <typename R, int D>
@@ -783,9 +783,13 @@ __device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, 
 }
 
 // One block's share of a solve: BLOCK lanes cover BLOCK >> lpp_shift points,
-// the N paths of a point on 1 << lpp_shift consecutive lanes (a lane loops over
-// paths k, k + lpp, ...).  `red` is BLOCK / 64 x red_stride<EXT, D>() doubles
-// of LDS.
+// the N paths of a point on lpp = 1 << lpp_shift consecutive lanes.  The lanes
+// of a point inside one wavefront (G = min(lpp, 64) of them, the first at
+// L0 within the point) share the paths L0 + (c mod G) + (c / G) lpp, c = 0,
+// 1, ...: each takes the next free c when its path ends, so the wavefront's
+// lanes finish together instead of waiting for the lane whose share of paths
+// ran longest.  A path's value depends on its index only, not on the lane.
+// `red` is BLOCK / 64 x red_stride<EXT, D>() doubles of LDS.
 template <int EXT, int D>
 constexpr int red_stride() { return ext_kind(EXT) == X_GRAD ? 3 + 2 * D : 3; }
 
@@ -795,6 +799,15 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   const int lpp = 1 << a.lpp_shift;
   const int64_t point = block_index * (BLOCK >> a.lpp_shift) + (tid >> a.lpp_shift);
   const int lane_in_point = tid & (lpp - 1);
+  {
+    // the group's next free counter, in LDS after the stacks and held leaves
+    // (the first G counters start at once); only this wavefront reads and
+    // writes it
+    const int G = 1 << (a.lpp_shift < 6 ? a.lpp_shift : 6);
+    if ((tid & (G - 1)) == 0)
+      __hip_atomic_store(wob_stack + (a.scene.stack_cap + kLeafSlots) * BLOCK + tid, G, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
   double n = 0.0, mean = 0.0, m2 = 0.0;
   constexpr bool GRAD = ext_kind(EXT) == X_GRAD;
   constexpr int GD = GRAD ? D : 1;  // gradient statistics per component (unused otherwise)
@@ -806,8 +819,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   constexpr int KEXT =
       (ext_kind(EXT) == X_CV && !(D == 3 && (FORM == F_SL || FORM == F_SL_RIS))) ? (EXT & X_VDATA) : EXT;
   {
-    // Paths k = lane_in_point, + lpp, ... of this lane, run as one state
-    // machine.  Lanes step through BVH nodes; a lane that has reached four
+    // The lane's paths (its first k = lane_in_point, then the group's next
+    // free ones) run as one state machine.  Lanes step through BVH nodes; a lane that has reached four
     // crossed leaves parks until half of the stepping lanes have parked, and
     // the lanes holding leaves then test them together; a lane at the end of its line
     // parks until a quarter of the working lanes have, and those lanes then
@@ -844,48 +857,71 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         // point has an anchor and whose line 0 met the boundary runs the
         // coupled walk from the anchor next, then subtracts w' times its value
         int32_t couple = -1;
-        if constexpr (GRAD && FORM == F_DL) {
-          if (s.coupled) {
+        bool take = false;
+        {
+          if constexpr (GRAD && FORM == F_DL) {
+            if (s.coupled) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) s.gacc[c] -= s.Wg0[c] * s.acc;
-            s.acc = s.acc_main;
-            s.coupled = false;
-          } else if (a.anchor_prim) {
-            const int32_t anchor = a.anchor_prim[point];
-            if (anchor >= 0 && (s.Wg0[0] != (R)0 || s.Wg0[1] != (R)0 || s.Wg0[2] != (R)0)) couple = anchor;
-            else if (anchor < -1) s.gacc[0] = (R)NAN;  // a caller error: the gradient is NaN
-          }
-        }
-        if (couple < 0) {
-          const R v = s.acc;
-          if (TRACE) a.path_out[point * (int64_t)a.N + k] = v;
-          bool finite = isfinite(v);
-          if constexpr (GRAD) {
-#pragma unroll
-            for (int c = 0; c < GD; ++c) {
-              if (TRACE) a.path_grad_out[(point * (int64_t)a.N + k) * D + c] = s.gacc[c];
-              finite = finite && isfinite(s.gacc[c]);
+              for (int c = 0; c < 3; ++c) s.gacc[c] -= s.Wg0[c] * s.acc;
+              s.acc = s.acc_main;
+              s.coupled = false;
+            } else if (a.anchor_prim) {
+              const int32_t anchor = a.anchor_prim[point];
+              if (anchor >= 0 && (s.Wg0[0] != (R)0 || s.Wg0[1] != (R)0 || s.Wg0[2] != (R)0)) couple = anchor;
+              else if (anchor < -1) s.gacc[0] = (R)NAN;  // a caller error: the gradient is NaN
             }
           }
-          if (finite) {
-            n += 1.0;
-            const double dv = (double)v - mean;
-            mean += dv / n;
-            m2 += dv * ((double)v - mean);
+          if (couple < 0) {
+            const R v = s.acc;
+            if (TRACE) a.path_out[point * (int64_t)a.N + k] = v;
+            bool finite = isfinite(v);
             if constexpr (GRAD) {
 #pragma unroll
               for (int c = 0; c < GD; ++c) {
-                const double dg = (double)s.gacc[c] - gmean[c];
-                gmean[c] += dg / n;
-                gm2[c] += dg * ((double)s.gacc[c] - gmean[c]);
+                if (TRACE) a.path_grad_out[(point * (int64_t)a.N + k) * D + c] = s.gacc[c];
+                finite = finite && isfinite(s.gacc[c]);
               }
             }
-          } else if (!TRACE && !COUNT && FORM != F_FWD && a.status) {
-            // a non-finite path (degenerate geometry, an invalid primitive id, data
-            // singular on the boundary) is counted and left out of the statistics
-            atomicAdd(a.status, 1ull);
+            if (finite) {
+              n += 1.0;
+              const double dv = (double)v - mean;
+              mean += dv / n;
+              m2 += dv * ((double)v - mean);
+              if constexpr (GRAD) {
+#pragma unroll
+                for (int c = 0; c < GD; ++c) {
+                  const double dg = (double)s.gacc[c] - gmean[c];
+                  gmean[c] += dg / n;
+                  gm2[c] += dg * ((double)s.gacc[c] - gmean[c]);
+                }
+              }
+            } else if (!TRACE && !COUNT && FORM != F_FWD && a.status) {
+              // a non-finite path (degenerate geometry, an invalid primitive id, data
+              // singular on the boundary) is counted and left out of the statistics
+              atomicAdd(a.status, 1ull);
+            }
+            take = true;
           }
-          k += lpp;
+        }
+        // the lanes of the group that take a path here get its next counters in
+        // lane order (every lane reads the counter before the first one of
+        // them writes it back)
+        const uint64_t grab = __ballot(take);
+        if (take) {
+          // the point's lanes in this wavefront: G of them, a power of two,
+          // aligned; the first at L0 within the point
+          const int gshift = a.lpp_shift < 6 ? a.lpp_shift : 6;
+          const int G = 1 << gshift, lane = tid & 63;
+          const uint64_t mine = G == 64 ? grab : grab & (((1ull << G) - 1) << (lane & ~(G - 1)));
+          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mine >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mine, 0u));
+          // atomic loads and stores: other lanes write the counter, and a plain
+          // load may be hoisted out of this loop and kept in a register that
+          // only the writing lane updates (stale counters, repeated paths)
+          int32_t* const gnext = wob_stack + (a.scene.stack_cap + kLeafSlots) * BLOCK + (tid & ~(G - 1));
+          const int c = __hip_atomic_load(gnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) + rank;
+          if (rank == 0) __hip_atomic_store(gnext, c + __popcll(mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          k = (lane_in_point & ~(G - 1)) + (c & (G - 1)) + (c >> gshift) * lpp;  // increasing in c
         }
         st = (couple >= 0 || k < a.N)
                  ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc,
@@ -902,7 +938,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       // holds fewer (measured on the icosphere benchmark: parking at the
       // first / second / third / fourth leaf 622 / 694 / 725 / 733 M path
       // samples/s; with two, a wait for 3/8, 1/2, 5/8 of the lanes: 678, 688,
-      // 677)
+      // 677; with four and the shared paths, 3/8, 1/2, 5/8 on the three-tori
+      // workload: 1,284, 1,303, 1,287)
       const int want = (active * 4 + 7) >> 3;
       bool trav = st == ST_LINE && nq == 0 && s.ni != kDone;
       while (trav) {
@@ -943,7 +980,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
       }
       // path steps run once a quarter of the working lanes stand at the end of
       // their line, or when no lane steps (measured: 557, 574, 566 M path
-      // samples/s for 1/8, 1/4, 3/8)
+      // samples/s for 1/8, 1/4, 3/8; with the shared paths on the three-tori
+      // workload 1,279, 1,303, 1,280)
       const bool at_end = st == ST_LINE && s.ni == kDone;
       const int n_end = __popcll(__ballot(at_end));
       const int stepping = __popcll(__ballot(st == ST_LINE && s.ni != kDone));

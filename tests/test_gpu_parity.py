@@ -317,10 +317,15 @@ def test_ris_arguments(W):
                                   candidates=c), 8, 2)
     with pytest.raises(W.WobError):
         W.solve(s2, pts, W.BC(-1, W.SINGLE_LAYER, W.PROG_CONST, (1.0,), sampling=2), 8, 2)
-    # the corrected (control-variate) walk is built for line sampling only
+    # the corrected (control-variate) walk takes RIS sampling too, but not an
+    # invalid candidate count
     g = torch.zeros(mesh.n_prims, dtype=torch.float32, device="cuda")
+    m, _ = W.solve_cv(s2, pts, W.BC(-1, W.SINGLE_LAYER, W.PROG_CONST, (1.0,), sampling=W.SAMPLE_RIS), 8, 2, g)
+    torch.cuda.synchronize()
+    assert torch.isfinite(m).all()
     with pytest.raises(W.WobError):
-        W.solve_cv(s2, pts, W.BC(-1, W.SINGLE_LAYER, W.PROG_CONST, (1.0,), sampling=W.SAMPLE_RIS), 8, 2, g)
+        W.solve_cv(s2, pts, W.BC(-1, W.SINGLE_LAYER, W.PROG_CONST, (1.0,), sampling=W.SAMPLE_RIS, candidates=65),
+                   8, 2, g)
     s2.close()
     scene.close()
 
@@ -352,6 +357,41 @@ def test_solve_mean_var_equal_trace_statistics(W):
         np.testing.assert_allclose(mean.cpu().numpy(), v.mean(axis=1), rtol=2e-6, atol=2e-6)
         if N > 1:
             np.testing.assert_allclose(var.cpu().numpy(), v.var(axis=1, ddof=1), rtol=2e-5, atol=1e-6)
+    scene.close()
+
+
+def test_solve_and_batch_statistics_equal_trace_with_paths_ending_at_start(W):
+    """The lanes of a point take the next free path index as their paths end
+    (a counter per lane group in LDS).  RIS paths on a mixed Robin / Neumann /
+    Dirichlet tori scene end inside their first step more often than not, so
+    a lane takes several indices in one pass; the solve's and the batch's
+    per-point mean and variance must still be those of the traced paths (each
+    path once), also with a point spread over several wavefronts (batch with
+    256-lane blocks, N = 700: 128 lanes per point)."""
+    w = I.config_tori(grid_n=12, n_points=90, boundary_frac=0.25, samples=64, walk_len=4)
+    kind = np.random.default_rng(3).integers(0, 3, w.mesh.n_prims).astype(np.uint8)
+    mixed = PT.f32_mesh(I.Mesh(3, w.mesh.verts, w.mesh.prims, kind, np.full(w.mesh.n_prims, 1.0)))
+    scene = W.Scene(mixed, W.F32)
+    pts = dev(PT.f32(w.points), torch.float32)
+    pp = dev(w.point_prim, torch.int32)
+    for sampling in (W.SAMPLE_RIS, W.SAMPLE_LINE):
+        bc = W.BC(-1, 0, W.PROG_INVDIST, (0.2, -0.1, 0.05), sampling=sampling, candidates=8)
+        for N in (1, 37, 96, 100, 700):
+            print(f"sampling {sampling} N {N}", flush=True)
+            val = W.trace(scene, pts, bc, N, 3, 21, point_prim=pp, want_vertices=False)[0]
+            mean, var = W.solve(scene, pts, bc, N, 3, 21, point_prim=pp, want_var=N > 1)
+            b = W.Batch([dict(scene=scene, points=pts, point_prim=pp, bc=bc, samples=N, walk_len=3, seed=21,
+                              want_var=N > 1)], tune=(256, 1))
+            bm, bv = b.launch()[0]
+            torch.cuda.synchronize()
+            v = val.cpu().double().numpy()
+            scale = np.abs(v).mean(axis=1) + 1e-30
+            for m, s2 in ((mean, var), (bm, bv)):
+                np.testing.assert_array_less(np.abs(m.cpu().double().numpy() - v.mean(axis=1)), 2e-6 * scale)
+                if N > 1:
+                    ref = v.var(axis=1, ddof=1)
+                    np.testing.assert_array_less(np.abs(s2.cpu().double().numpy() - ref), 2e-5 * ref + 1e-30)
+            b.close()
     scene.close()
 
 
