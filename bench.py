@@ -427,7 +427,7 @@ def cv_leg(torch, wob, I, n_seeds=10):
 
     def run_cv(name, g, g0, fixed_s, seed0, b=bc):
         per_path, base = costs[id(b)]
-        n = int(max(16, (t_plain - fixed_s - base) / per_path // 16 * 16))
+        n = int(max(8, (t_plain - fixed_s - base) / per_path // 8 * 8))  # lanes take paths one by one: any N
         runs, times = timed(lambda sd: wob.solve_cv(scene, pts, b, n, M, g, seed=sd + 100 * seed0,
                                                     point_prim=pp, g0=g0))
         variants[name] = record(runs, times, fixed_s)
@@ -444,7 +444,7 @@ def cv_leg(torch, wob, I, n_seeds=10):
     for C in (4, 16):
         b = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=C)
         pp_cost, rest = slope(lambda n: wob.solve(scene, pts, b, n, M, seed=2, point_prim=pp))
-        n = int(max(16, (t_plain - rest) / pp_cost // 16 * 16))
+        n = int(max(8, (t_plain - rest) / pp_cost // 8 * 8))
         runs, times = timed(lambda sd: wob.solve(scene, pts, b, n, M, seed=sd + 700 + C, point_prim=pp))
         variants[f"ris_{C}"] = record(runs, times)
         variants[f"ris_{C}"].update({"paths": n, "path_cost_vs_line": pp_cost / (t_plain / N)})
