@@ -53,6 +53,14 @@ bool valid_tune(const wob_tune& t) {
          t.blocks_per_cu <= 32;
 }
 
+// Whether any problem gives its boundary data per vertex (then the batch runs
+// the kernel instantiated for it).
+inline bool any_vertex_data(const wob_problem* p, int32_t n) {
+  for (int32_t i = 0; i < n; ++i)
+    if (p[i].bc.data_mode == WOB_DATA_VERTEX) return true;
+  return false;
+}
+
 // Problem table for one block size (lanes per point and tiles depend on it):
 // the walk arguments of problem order[i] at args[i], tile offsets off[0..n],
 // and the deepest traversal stack of the problems' scenes.
@@ -61,6 +69,7 @@ wob_status fill_table(const wob_problem* probs, const int32_t* order, int n, int
                       wob::WalkArgs<R, D>* args, int64_t* off, int32_t* stack_cap) {
   off[0] = 0;
   *stack_cap = 1;
+  const bool vdata = any_vertex_data(probs, n);
   for (int i = 0; i < n; ++i) {
     const wob_problem& p = probs[order[i]];
     Plan pl;
@@ -69,7 +78,11 @@ wob_status fill_table(const wob_problem* probs, const int32_t* order, int n, int
     auto a = make_args<R, D>(p.scene, pl, p.points, p.point_prim, p.n_points, &p.bc, p.samples,
                              p.walk_len, p.seed);
     a.problem = p.stream_id;
-    a.lpp_shift = lpp_shift_for(p.samples, block);
+    // the kernel runs the X_VDATA instantiation for every problem when one
+    // gives its data per vertex; the plain single-layer forms pool two points
+    // per lane group in the other (the same rule as the kernel's)
+    a.lpp_shift = lpp_shift_for(p.samples, block,
+                                wob::pools_points(a.form, vdata ? wob::X_VDATA : wob::X_NONE, false, false));
     a.mean_out = (R*)p.mean_out;
     a.var_out = (R*)p.var_out;
     args[i] = a;
@@ -116,13 +129,6 @@ struct LaunchBufs {
   bool vdata;  // some problem gives its boundary data per vertex
 };
 
-// Whether any problem gives its boundary data per vertex (then the batch runs
-// the kernel instantiated for it).
-inline bool any_vertex_data(const wob_problem* p, int32_t n) {
-  for (int32_t i = 0; i < n; ++i)
-    if (p[i].bc.data_mode == WOB_DATA_VERTEX) return true;
-  return false;
-}
 
 template <typename R, int D, int BLOCK>
 void launch_persistent_t(const LaunchBufs& lb, int bpc, int64_t stride, hipStream_t st) {

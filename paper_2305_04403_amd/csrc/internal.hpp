@@ -47,11 +47,13 @@ constexpr int kPathsPerLane = 8;
 
 // log2 of the lanes that share one point: the smallest power of two >=
 // ceil(N / kPathsPerLane), at most the block (a wavefront holds several points
-// when that is below 64)
-inline int lpp_shift_for(int32_t samples, int block) {
+// when that is below 64), and at most 32 for solves whose lane groups pool
+// two points (wob::pools_points: a group of 2 x 32 lanes is one wavefront)
+inline int lpp_shift_for(int32_t samples, int block, bool pooled = false) {
   const int32_t lanes = (samples + kPathsPerLane - 1) / kPathsPerLane;
+  const int cap = pooled ? (block < 32 ? block : 32) : block;
   int s = 0;
-  while ((1 << s) < lanes && (1 << s) < block) ++s;
+  while ((1 << s) < lanes && (1 << s) < cap) ++s;
   return s;
 }
 

@@ -93,6 +93,13 @@ enum Ext { X_NONE = 0, X_CV = 1, X_GRAD = 2, X_VDATA = 4 };
 constexpr int ext_kind(int ext) { return ext & 3; }
 constexpr bool ext_vdata(int ext) { return (ext & X_VDATA) != 0; }
 
+// Solves whose lane groups pool the paths of two points (the plain
+// single-layer walks, lines and RIS: the second point's statistics fit their
+// register budget); the host gives them at most 32 lanes per point.
+constexpr bool pools_points(int form, int ext, bool trace, bool count) {
+  return (form == F_SL || form == F_SL_RIS) && ext == X_NONE && !trace && !count;
+}
+
 // Single-layer emission at vertex y on primitive g, before the running
 // weight: 2 phi s(y) on Neumann / Robin parts (Table 1), k u_D(y) on Dirichlet
 // parts (eq. mixed_second_kind_ish); half of it at the last vertex x_M.
@@ -788,7 +795,10 @@ __device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, 
 // L0 within the point) share the paths L0 + (c mod G) + (c / G) lpp, c = 0,
 // 1, ...: each takes the next free c when its path ends, so the wavefront's
 // lanes finish together instead of waiting for the lane whose share of paths
-// ran longest.  A path's value depends on its index only, not on the lane.
+// ran longest.  Pooled solves (pools_points) share across two points: the
+// 2 lpp lanes of points 2j, 2j + 1 take c = 0 .. 2N - 1 as (point c >= N,
+// path c mod N), which halves the time the lanes wait for the group's last
+// paths.  A path's value depends on its index only, not on the lane.
 // `red` is BLOCK / 64 x red_stride<EXT, D>() doubles of LDS.
 template <int EXT, int D>
 constexpr int red_stride() { return ext_kind(EXT) == X_GRAD ? 3 + 2 * D : 3; }
@@ -797,18 +807,37 @@ template <typename R, int D, int FORM, bool TRACE, bool COUNT, int BLOCK, int EX
 __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t block_index, double* red) {
   const int tid = threadIdx.x;
   const int lpp = 1 << a.lpp_shift;
-  const int64_t point = block_index * (BLOCK >> a.lpp_shift) + (tid >> a.lpp_shift);
+  constexpr bool POOL = pools_points(FORM, EXT, TRACE, COUNT);
+  // the lane group that shares a pool of paths: G lanes, a power of two,
+  // aligned; its first point point0
+  const int gshift = POOL ? a.lpp_shift + 1 : (a.lpp_shift < 6 ? a.lpp_shift : 6);
+  const int G = 1 << gshift;
+  const int64_t point0 =
+      block_index * (BLOCK >> a.lpp_shift) + (POOL ? ((tid >> a.lpp_shift) & ~1) : (tid >> a.lpp_shift));
   const int lane_in_point = tid & (lpp - 1);
-  {
-    // the group's next free counter, in LDS after the stacks and held leaves
-    // (the first G counters start at once); only this wavefront reads and
-    // writes it
-    const int G = 1 << (a.lpp_shift < 6 ? a.lpp_shift : 6);
-    if ((tid & (G - 1)) == 0)
-      __hip_atomic_store(wob_stack + (a.scene.stack_cap + kLeafSlots) * BLOCK + tid, G, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_WAVEFRONT);
-  }
+  // the group's next free counter, in LDS after the stacks and held leaves
+  // (the first G counters start at once); only this wavefront reads and
+  // writes it
+  if ((tid & (G - 1)) == 0)
+    __hip_atomic_store(wob_stack + (a.scene.stack_cap + kLeafSlots) * BLOCK + tid, G, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+  // counter c of the group -> the path's point (0 or 1 within the pool) and
+  // index; false past the group's last path (c is taken in increasing order,
+  // and so are the paths it names)
+  auto path_of = [&](int c, int& pl_, int& k_) -> bool {
+    if constexpr (POOL) {
+      pl_ = c >= a.N ? 1 : 0;
+      k_ = c - pl_ * a.N;
+      return c < 2 * a.N && point0 + pl_ < a.n_points;
+    } else {
+      pl_ = 0;
+      k_ = (lane_in_point & ~(G - 1)) + (c & (G - 1)) + (c >> gshift) * lpp;
+      return k_ < a.N && point0 < a.n_points;
+    }
+  };
   double n = 0.0, mean = 0.0, m2 = 0.0;
+  // pooled: the statistics of the pool's second point
+  double n1 = 0.0, mean1 = 0.0, m21 = 0.0;
   constexpr bool GRAD = ext_kind(EXT) == X_GRAD;
   constexpr int GD = GRAD ? D : 1;  // gradient statistics per component (unused otherwise)
   double gmean[GD], gm2[GD];
@@ -828,7 +857,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     // once instead of on the one or two lanes that stand at a leaf or a line
     // end in a given node step.
     PathState<R, D> s;
-    int k = lane_in_point;
+    int k = 0, pl = 0;
+    int64_t point = point0;  // the point of the lane's path
     int st = ST_NONE;
     // the lane's traversal stack: LDS, entry k at wob_stack[k * BLOCK + tid]
     // (consecutive lanes in consecutive banks); empty between lines.  After
@@ -838,7 +868,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     int32_t* const stk = wob_stack + tid;
     int32_t* const leafq = stk + a.scene.stack_cap * BLOCK;
     int sp = 0, nq = 0;
-    if (point < a.n_points) {
+    auto load_point = [&]() {
       if constexpr (FORM == F_FWD) {
         s.point = 0xfffffffeu;  // forward paths: no evaluation point
       } else {
@@ -848,7 +878,11 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         s.prim0 = a.point_prim ? a.point_prim[point] : -1;
         s.point = a.point_ids ? a.point_ids[point] : (uint32_t)point;
       }
-      if (k < a.N) st = start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc);
+    };
+    if (path_of(tid & (G - 1), pl, k)) {
+      point = point0 + pl;
+      load_point();
+      st = start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc);
     }
     for (;;) {
       // finished paths: record, start the lane's next one
@@ -882,7 +916,12 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
                 finite = finite && isfinite(s.gacc[c]);
               }
             }
-            if (finite) {
+            if (POOL && finite && pl) {
+              n1 += 1.0;
+              const double dv = (double)v - mean1;
+              mean1 += dv / n1;
+              m21 += dv * ((double)v - mean1);
+            } else if (finite) {
               n += 1.0;
               const double dv = (double)v - mean;
               mean += dv / n;
@@ -907,11 +946,9 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         // lane order (every lane reads the counter before the first one of
         // them writes it back)
         const uint64_t grab = __ballot(take);
+        bool go = couple >= 0;
         if (take) {
-          // the point's lanes in this wavefront: G of them, a power of two,
-          // aligned; the first at L0 within the point
-          const int gshift = a.lpp_shift < 6 ? a.lpp_shift : 6;
-          const int G = 1 << gshift, lane = tid & 63;
+          const int lane = tid & 63;
           const uint64_t mine = G == 64 ? grab : grab & (((1ull << G) - 1) << (lane & ~(G - 1)));
           const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mine >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mine, 0u));
@@ -921,12 +958,17 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
           int32_t* const gnext = wob_stack + (a.scene.stack_cap + kLeafSlots) * BLOCK + (tid & ~(G - 1));
           const int c = __hip_atomic_load(gnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) + rank;
           if (rank == 0) __hip_atomic_store(gnext, c + __popcll(mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-          k = (lane_in_point & ~(G - 1)) + (c & (G - 1)) + (c >> gshift) * lpp;  // increasing in c
+          int pn;
+          go = path_of(c, pn, k);
+          if (POOL && go && pn != pl) {  // the pool's second point: its data
+            pl = pn;
+            point = point0 + pl;
+            load_point();
+          }
         }
-        st = (couple >= 0 || k < a.N)
-                 ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc,
-                                                              couple, point)
-                 : ST_NONE;
+        st = go ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc,
+                                                             couple, point)
+                : ST_NONE;
       }
       const int idle = __popcll(__ballot(st == ST_NONE));
       if (idle == 64) break;
@@ -1001,8 +1043,36 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   }
   if (TRACE || FORM == F_FWD) return;
 
-  // per-point reduction: within the point's lanes of the wavefront, then across
-  // the point's wavefronts
+  if constexpr (POOL) {
+    // each of the pool's two points: merged over the group's lanes
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      double tn = slot ? n1 : n, tm = slot ? mean1 : mean, ts = slot ? m21 : m2;
+      for (int off = G >> 1; off > 0; off >>= 1) {
+        const double nb = __shfl_xor(tn, off, 64);
+        const double mb = __shfl_xor(tm, off, 64);
+        const double sb = __shfl_xor(ts, off, 64);
+        if (((tid & 63) & off) == 0) {
+          chan_merge(tn, tm, ts, nb, mb, sb);
+        } else {
+          double n2 = nb, mean2 = mb, m22 = sb;
+          chan_merge(n2, mean2, m22, tn, tm, ts);
+          tn = n2;
+          tm = mean2;
+          ts = m22;
+        }
+      }
+      const int64_t pt = point0 + slot;
+      if ((tid & (G - 1)) == 0 && pt < a.n_points) {
+        a.mean_out[pt] = tn > 0.0 ? (R)tm : (R)NAN;
+        if (a.var_out) a.var_out[pt] = (R)(tn > 1.0 ? ts / (tn - 1.0) : 0.0);
+      }
+    }
+    return;
+  }
+
+  // per-point0 reduction: within the point0's lanes of the wavefront, then across
+  // the point0's wavefronts
   // (the gradient components merge with the same counts, in the same order)
   for (int off = (lpp < 64 ? lpp : 64) >> 1; off > 0; off >>= 1) {
     const double nb = __shfl_xor(n, off, 64);
@@ -1036,14 +1106,14 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     }
   }
   if (lpp <= 64) {
-    if (lane_in_point == 0 && point < a.n_points) {
-      a.mean_out[point] = n > 0.0 ? (R)mean : (R)NAN;
-      if (a.var_out) a.var_out[point] = (R)(n > 1.0 ? m2 / (n - 1.0) : 0.0);
+    if (lane_in_point == 0 && point0 < a.n_points) {
+      a.mean_out[point0] = n > 0.0 ? (R)mean : (R)NAN;
+      if (a.var_out) a.var_out[point0] = (R)(n > 1.0 ? m2 / (n - 1.0) : 0.0);
       if constexpr (GRAD) {
 #pragma unroll
         for (int c = 0; c < GD; ++c) {
-          a.grad_out[point * D + c] = n > 0.0 ? (R)gmean[c] : (R)NAN;
-          if (a.grad_var_out) a.grad_var_out[point * D + c] = (R)(n > 1.0 ? gm2[c] / (n - 1.0) : 0.0);
+          a.grad_out[point0 * D + c] = n > 0.0 ? (R)gmean[c] : (R)NAN;
+          if (a.grad_var_out) a.grad_var_out[point0 * D + c] = (R)(n > 1.0 ? gm2[c] / (n - 1.0) : 0.0);
         }
       }
     }
@@ -1064,7 +1134,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     }
   }
   __syncthreads();
-  if (lane_in_point == 0 && point < a.n_points) {
+  if (lane_in_point == 0 && point0 < a.n_points) {
     const int waves = lpp >> 6;
     double tn = red[wave * RS + 0], tm = red[wave * RS + 1], ts = red[wave * RS + 2];
     if constexpr (GRAD) {
@@ -1074,14 +1144,14 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
         for (int w = 1; w < waves; ++w)
           chan_merge(gn, gm, gs, red[(wave + w) * RS + 0], red[(wave + w) * RS + 3 + 2 * c],
                      red[(wave + w) * RS + 4 + 2 * c]);
-        a.grad_out[point * D + c] = gn > 0.0 ? (R)gm : (R)NAN;
-        if (a.grad_var_out) a.grad_var_out[point * D + c] = (R)(gn > 1.0 ? gs / (gn - 1.0) : 0.0);
+        a.grad_out[point0 * D + c] = gn > 0.0 ? (R)gm : (R)NAN;
+        if (a.grad_var_out) a.grad_var_out[point0 * D + c] = (R)(gn > 1.0 ? gs / (gn - 1.0) : 0.0);
       }
     }
     for (int w = 1; w < waves; ++w)
       chan_merge(tn, tm, ts, red[(wave + w) * RS + 0], red[(wave + w) * RS + 1], red[(wave + w) * RS + 2]);
-    a.mean_out[point] = tn > 0.0 ? (R)tm : (R)NAN;
-    if (a.var_out) a.var_out[point] = (R)(tn > 1.0 ? ts / (tn - 1.0) : 0.0);
+    a.mean_out[point0] = tn > 0.0 ? (R)tm : (R)NAN;
+    if (a.var_out) a.var_out[point0] = (R)(tn > 1.0 ? ts / (tn - 1.0) : 0.0);
   }
 }
 

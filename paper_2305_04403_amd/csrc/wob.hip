@@ -284,8 +284,14 @@ enum Mode { MODE_SOLVE = 0, MODE_TRACE = 1, MODE_COUNT = 2 };
 
 // VX: X_VDATA for per-vertex data (its own instantiation of each kernel)
 template <typename R, int D, int FORM, int VX>
-void launch_form(const wob::WalkArgs<R, D>& a, int mode, hipStream_t st) {
+void launch_form(const wob::WalkArgs<R, D>& a0, int mode, hipStream_t st) {
   constexpr int B = kSolveBlock;
+  // plain single-layer solves pool two points per lane group: at most 32
+  // lanes per point (the kernel instantiation decides, by the same rule)
+  const bool pooled = mode == MODE_SOLVE && !(a0.grad_out || a0.path_grad_out) && !a0.cv_g &&
+                      wob::pools_points(FORM, VX, false, false);
+  wob::WalkArgs<R, D> a = a0;
+  a.lpp_shift = lpp_shift_for(a0.N, B, pooled);
   const int ppb = B >> a.lpp_shift;
   const dim3 grid((unsigned)((a.n_points + ppb - 1) / ppb)), block(B);
   const size_t lds = wob::walk_lds_bytes(a.scene.stack_cap, B);  // traversal stacks, held leaves

@@ -15,7 +15,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # (source, mangled-name prefix, description, VGPR bound, waves per SIMD)
 BUDGETS = [
-    ("wob.hip", "_ZN3wob11walk_kernelIfLi3ELi3ELb0ELb0ELi64ELi0EE", "single layer, 3D FP32 solve", 120, 4),
+    ("wob.hip", "_ZN3wob11walk_kernelIfLi3ELi3ELb0ELb0ELi64ELi0EE", "single layer, 3D FP32 solve (two points pooled per lane group)", 128, 4),
     ("wob.hip", "_ZN3wob11walk_kernelIfLi3ELi1ELb0ELb0ELi64ELi0EE", "double layer, 3D FP32 solve", 96, 5),
     ("wob.hip", "_ZN3wob11walk_kernelIfLi3ELi1ELb0ELb0ELi64ELi2EE", "double layer gradient (with the split)", 128, 4),
     ("wob.hip", "_ZN3wob11walk_kernelIfLi3ELi3ELb0ELb0ELi64ELi1EE", "single layer, control variate", 128, 4),
