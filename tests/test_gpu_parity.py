@@ -366,9 +366,10 @@ def test_solve_and_batch_statistics_equal_trace_with_paths_ending_at_start(W):
     Dirichlet tori scene end inside their first step more often than not, so
     a lane takes several indices in one pass; the solve's and the batch's
     per-point mean and variance must still be those of the traced paths (each
-    path once), also with a point spread over several wavefronts (batch with
-    256-lane blocks, N = 700: 128 lanes per point)."""
-    w = I.config_tori(grid_n=12, n_points=90, boundary_frac=0.25, samples=64, walk_len=4)
+    path once), also where plain single-layer solves pool two points per lane
+    group: an odd point count leaves the last group one point, and N = 700
+    gives 22 paths per lane."""
+    w = I.config_tori(grid_n=12, n_points=91, boundary_frac=0.25, samples=64, walk_len=4)
     kind = np.random.default_rng(3).integers(0, 3, w.mesh.n_prims).astype(np.uint8)
     mixed = PT.f32_mesh(I.Mesh(3, w.mesh.verts, w.mesh.prims, kind, np.full(w.mesh.n_prims, 1.0)))
     scene = W.Scene(mixed, W.F32)
