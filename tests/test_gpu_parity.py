@@ -445,6 +445,44 @@ def test_full_size_icosphere_slice_sampled(W):
     scene.close()
 
 
+def test_full_size_tori_sampled(W):
+    """The headline workload at full size (three tori, 200,992 triangles, 1M
+    points with 10 % on the boundary, 512 paths, M = 4, single layer: two
+    points pooled per lane group) in the benchmark's launch configuration; at
+    8 sampled points (6 off and 2 on the boundary) the paths are re-traced
+    with their original random-number indices and compared path by path with
+    the oracle, and the solve's mean and variance there must equal the traced
+    paths' (each of the 512 paths counted once)."""
+    w = I.config_tori()
+    scene = W.Scene(w.mesh, W.F32)
+    tp = dev(w.points, torch.float32)
+    pp = dev(w.point_prim, torch.int32)
+    mean, var = W.solve(scene, tp, wbc(W, w.bc), w.samples, w.walk_len, w.seed, point_prim=pp)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    on = np.flatnonzero(w.point_prim >= 0)
+    off = np.flatnonzero(w.point_prim < 0)
+    ids = np.sort(np.concatenate([rng.choice(off, 6, replace=False), rng.choice(on, 2, replace=False)]))
+    sub, subp = w.points[ids], w.point_prim[ids]
+    print(f"sampled points {ids.tolist()}", flush=True)
+    val, vprim, vm = W.trace(scene, dev(sub, torch.float32), wbc(W, w.bc), w.samples, w.walk_len, w.seed,
+                             point_prim=dev(subp, torch.int32), point_ids=dev(ids.astype(np.int32), torch.int32))
+    torch.cuda.synchronize()
+    v = val.cpu().double().numpy()
+    scale = np.abs(v).mean(axis=1) + 1e-30
+    np.testing.assert_array_less(np.abs(mean.cpu().double().numpy()[ids] - v.mean(axis=1)), 2e-6 * scale)
+    ref_var = v.var(axis=1, ddof=1)
+    np.testing.assert_array_less(np.abs(var.cpu().double().numpy()[ids] - ref_var), 2e-5 * ref_var + 1e-30)
+    om = oracle.OracleMesh(w.mesh)
+    orc = PT.oracle_all_paths(om, sub, subp, obc(w.bc), w.samples, w.walk_len, w.seed, point_ids=ids)
+    L = orc["vtx_prim"].shape[1]
+    res = PT.compare_paths(orc, v.reshape(-1), vprim.cpu().numpy().reshape(-1, L),
+                           vm.cpu().numpy().reshape(-1, L), PT.RTOL_F32)
+    print(res.summary(), flush=True)
+    res.assert_exact()
+    scene.close()
+
+
 # ------------------------------------------------------------------- edge cases
 
 def test_edge_cases(W):
