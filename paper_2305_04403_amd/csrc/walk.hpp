@@ -94,10 +94,12 @@ constexpr int ext_kind(int ext) { return ext & 3; }
 constexpr bool ext_vdata(int ext) { return (ext & X_VDATA) != 0; }
 
 // Solves whose lane groups pool the paths of two points (the plain
-// single-layer walks, lines and RIS: the second point's statistics fit their
-// register budget); the host gives them at most 32 lanes per point.
+// single-layer walks, lines and RIS, and the direct BIE: the second point's
+// statistics fit their register budget of four waves per SIMD; the double
+// layer's five would not hold them); the host gives them at most 32 lanes per
+// point.
 constexpr bool pools_points(int form, int ext, bool trace, bool count) {
-  return (form == F_SL || form == F_SL_RIS) && ext == X_NONE && !trace && !count;
+  return (form == F_SL || form == F_SL_RIS || form == F_DIRECT) && ext == X_NONE && !trace && !count;
 }
 
 // Single-layer emission at vertex y on primitive g, before the running

@@ -366,9 +366,9 @@ def test_solve_and_batch_statistics_equal_trace_with_paths_ending_at_start(W):
     Dirichlet tori scene end inside their first step more often than not, so
     a lane takes several indices in one pass; the solve's and the batch's
     per-point mean and variance must still be those of the traced paths (each
-    path once), also where plain single-layer solves pool two points per lane
-    group: an odd point count leaves the last group one point, and N = 700
-    gives 22 paths per lane."""
+    path once), also where plain single-layer and direct-BIE solves pool two
+    points per lane group: an odd point count leaves the last group one point,
+    and N = 700 gives 22 paths per lane."""
     w = I.config_tori(grid_n=12, n_points=91, boundary_frac=0.25, samples=64, walk_len=4)
     kind = np.random.default_rng(3).integers(0, 3, w.mesh.n_prims).astype(np.uint8)
     mixed = PT.f32_mesh(I.Mesh(3, w.mesh.verts, w.mesh.prims, kind, np.full(w.mesh.n_prims, 1.0)))
@@ -393,6 +393,27 @@ def test_solve_and_batch_statistics_equal_trace_with_paths_ending_at_start(W):
                     ref = v.var(axis=1, ddof=1)
                     np.testing.assert_array_less(np.abs(s2.cpu().double().numpy() - ref), 2e-5 * ref + 1e-30)
             b.close()
+    scene.close()
+    # the direct BIE pools two points too: exterior Neumann on a sphere, points
+    # off and on the boundary
+    sph = I.icosphere(8)
+    neu = PT.f32_mesh(I.Mesh(3, sph.verts, sph.prims, np.full(sph.n_prims, 1, np.uint8), None))
+    scene = W.Scene(neu, W.F32)
+    on, onp = I.mesh_surface_points(neu, 20, 4)
+    pts = dev(PT.f32(np.concatenate([I.ball_points(71, 2.5, 3, r_min=1.2), on])), torch.float32)
+    pp = dev(np.concatenate([np.full(71, -1), onp]).astype(np.int32), torch.int32)
+    bc = W.BC(-1, W.DIRECT, W.PROG_INVDIST, (0.2, -0.1, 0.05))
+    for N in (1, 37, 100, 700):
+        print(f"direct N {N}", flush=True)
+        val = W.trace(scene, pts, bc, N, 3, 23, point_prim=pp, want_vertices=False)[0]
+        mean, var = W.solve(scene, pts, bc, N, 3, 23, point_prim=pp, want_var=N > 1)
+        torch.cuda.synchronize()
+        v = val.cpu().double().numpy()
+        scale = np.abs(v).mean(axis=1) + 1e-30
+        np.testing.assert_array_less(np.abs(mean.cpu().double().numpy() - v.mean(axis=1)), 2e-6 * scale)
+        if N > 1:
+            ref = v.var(axis=1, ddof=1)
+            np.testing.assert_array_less(np.abs(var.cpu().double().numpy() - ref), 2e-5 * ref + 1e-30)
     scene.close()
 
 
