@@ -75,6 +75,10 @@ struct SceneView {
   const R* normals;           // 4 per primitive (leaf order): unit outward normal, 0
   const int32_t* leaf_of_id;  // caller id -> leaf-order index
   const float* area_cdf;      // caller-id order, cumulative area / |Gamma| (binary32, last 1)
+  // guide[b] = the first index whose area_cdf exceeds b / 2^guide_shift
+  // (b = 0 .. 2^guide_shift; the last entry n_prims - 1)
+  const int32_t* area_guide;
+  int32_t guide_shift;
   R area_total;               // |Gamma|
   int32_t n_nodes;            // interior records
   int32_t n_prims;

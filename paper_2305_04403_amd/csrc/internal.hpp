@@ -24,6 +24,8 @@ struct wob_scene_s {
   void* d_verts = nullptr;       // the rounded vertices (n_verts x dim, scene precision)
   int32_t* d_vid = nullptr;      // each primitive's vertex ids, caller-id order (n_prims x dim)
   float* d_area_cdf = nullptr;  // caller-id order, cumulative area / total (last entry 1)
+  int32_t* d_area_guide = nullptr;  // 2^guide_shift + 1 entries: the search range of each bucket
+  int32_t guide_shift = 0;
   unsigned long long* d_status = nullptr;  // non-finite path values excluded from solves (sticky)
   double area_total = 0.0;      // |Gamma|
   int64_t node_bytes = 0, prim_bytes = 0, device_bytes = 0;
@@ -65,6 +67,8 @@ wob::SceneView<R, D> view(const wob_scene_s* sc) {
   s.normals = (const R*)sc->d_normals;
   s.leaf_of_id = sc->d_leaf_of_id;
   s.area_cdf = sc->d_area_cdf;
+  s.area_guide = sc->d_area_guide;
+  s.guide_shift = sc->guide_shift;
   s.area_total = (R)sc->area_total;
   s.n_nodes = sc->n_inner;
   s.n_prims = (int32_t)sc->n_prims;

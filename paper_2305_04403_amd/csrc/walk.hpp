@@ -194,7 +194,9 @@ __device__ __forceinline__ bool ris_step(const WalkArgs<R, D>& a, PathState<R, D
   for (int j = 0; j < a.ris_c; ++j) {
     const U4 rj = philox(s.path, s.point, s.z | 3u, (uint32_t)j, a.k0, a.k1);
     const float u = unit<float>(rj.x);
-    int32_t lo = 0, hi = sc.n_prims - 1;
+    // the first caller id whose cdf exceeds u, searched in its guide bucket
+    const uint32_t bkt = (uint32_t)(u * (float)(1u << sc.guide_shift));
+    int32_t lo = sc.area_guide[bkt], hi = sc.area_guide[bkt + 1];
     while (lo < hi) {
       const int32_t mid = (lo + hi) >> 1;
       if (sc.area_cdf[mid] > u) hi = mid;

@@ -248,6 +248,24 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   }
   cdf[T - 1] = 1.0f;
   sc->area_total = tot;
+  // a guide to the area CDF: with K = 2^shift >= T buckets (at most 2^24),
+  // guide[b] is the first index whose cdf exceeds b / K, so the first index
+  // whose cdf exceeds a binary32 uniform u lies in [guide[b], guide[b + 1]]
+  // for b = floor(u K) (exact: K is a power of two); the area-uniform pick
+  // searches there and finds the same index as a search of the whole CDF
+  int shift = 0;
+  while ((int64_t)1 << shift < T && shift < 24) ++shift;
+  const int64_t K = (int64_t)1 << shift;
+  std::vector<int32_t> guide((size_t)K + 1);
+  {
+    int64_t i = 0;
+    for (int64_t b = 0; b <= K; ++b) {
+      const double t = (double)b / (double)K;
+      while (i < T - 1 && !((double)cdf[i] > t)) ++i;
+      guide[b] = (int32_t)i;
+    }
+  }
+  sc->guide_shift = shift;
   // the vertices (already rounded to R) and each primitive's vertex ids, for
   // per-vertex boundary data
   std::vector<R> verts_r(v.size());
@@ -255,12 +273,14 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   const size_t nb = std::max(nodes.size(), (size_t)1) * sizeof(Node), pb = recs.size() * sizeof(Prim),
                lb = leaf_of_id.size() * sizeof(int32_t), qb = normals.size() * sizeof(R),
                cb = sizeof(float) * T, vb = verts_r.size() * sizeof(R),
-               ib = (size_t)T * D * sizeof(int32_t), sb = sizeof(unsigned long long);
+               ib = (size_t)T * D * sizeof(int32_t), sb = sizeof(unsigned long long),
+               gb = guide.size() * sizeof(int32_t);
   if (hipMalloc(&sc->d_nodes, nb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc(&sc->d_prims, pb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc(&sc->d_normals, qb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc((void**)&sc->d_leaf_of_id, lb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc((void**)&sc->d_area_cdf, cb) != hipSuccess) return WOB_E_ALLOC;
+  if (hipMalloc((void**)&sc->d_area_guide, gb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc(&sc->d_verts, vb) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc((void**)&sc->d_vid, ib) != hipSuccess) return WOB_E_ALLOC;
   if (hipMalloc((void**)&sc->d_status, sb) != hipSuccess) return WOB_E_ALLOC;
@@ -270,13 +290,14 @@ wob_status upload_scene(wob_scene_s* sc, const std::vector<double>& v, const int
   };
   bool ok = put(sc->d_normals, normals.data(), qb) && put(sc->d_prims, recs.data(), pb) &&
             put(sc->d_leaf_of_id, leaf_of_id.data(), lb) && put(sc->d_area_cdf, cdf.data(), cb) &&
+            put(sc->d_area_guide, guide.data(), gb) &&
             put(sc->d_verts, verts_r.data(), vb) && put(sc->d_vid, prims, ib) &&
             hipMemsetAsync(sc->d_status, 0, sb, st) == hipSuccess;
   if (ok && !nodes.empty()) ok = put(sc->d_nodes, nodes.data(), nodes.size() * sizeof(Node));
   // the copies must end before the host arrays are released, also on failure
   if (hipStreamSynchronize(st) != hipSuccess || !ok) return WOB_E_DEVICE;
   sc->n_verts = (int64_t)(v.size() / D);
-  sc->device_bytes = (int64_t)(nb + pb + lb + qb + cb + vb + ib + sb);
+  sc->device_bytes = (int64_t)(nb + pb + lb + qb + cb + vb + ib + sb + gb);
   return WOB_OK;
 }
 
@@ -574,6 +595,7 @@ void wob_free(wob_scene sc) {
   if (sc->d_prims) (void)hipFree(sc->d_prims);
   if (sc->d_normals) (void)hipFree(sc->d_normals);
   if (sc->d_area_cdf) (void)hipFree(sc->d_area_cdf);
+  if (sc->d_area_guide) (void)hipFree(sc->d_area_guide);
   if (sc->d_leaf_of_id) (void)hipFree(sc->d_leaf_of_id);
   if (sc->d_status) (void)hipFree(sc->d_status);
   if (sc->d_verts) (void)hipFree(sc->d_verts);
