@@ -279,6 +279,30 @@ def test_trace_parity_single_layer_ris_2d_f64(W):
     run_trace_parity(W, mesh, pts, None, bc, 64, 3, 2, "f64")
 
 
+@pytest.mark.parametrize("shape", ["tetrahedron-f32", "square-f64"])
+def test_trace_parity_ris_equal_areas(W, shape):
+    """RIS picks through the area-CDF guide table where every bucket edge b / K
+    falls on a CDF value (primitives of equal area: a regular tetrahedron,
+    K = 4, CDF 1/4, 1/2, 3/4, 1; a square in 2D), so the strict comparison at
+    the bucket edges decides; exterior Robin single layer, against the
+    oracle path by path."""
+    if shape == "tetrahedron-f32":
+        v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], np.float64)
+        f = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]], np.int32)  # outward
+        mesh = PT.f32_mesh(I.Mesh(3, v, f, np.full(4, 2, np.uint8), np.full(4, 0.5)))
+        pts = PT.f32(I.ball_points(30, 4.0, 3, r_min=2.0))
+        prec, M = "f32", 4
+    else:
+        v = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], np.float64)
+        f = np.array([[0, 1], [1, 2], [2, 3], [3, 0]], np.int32)
+        mesh = I.Mesh(2, v, f, np.full(4, 2, np.uint8), np.full(4, 0.5))
+        pts = I.disk_points(30, 4.0, 3)
+        pts = pts[np.abs(pts).max(axis=1) > 1.2]
+        prec, M = "f64", 3
+    bc = dict(domain=-1, formulation=3, program=3, params=(0.1, 0.2, 0.05), sampling=1, candidates=16)
+    run_trace_parity(W, mesh, pts, None, bc, 64, M, 7, prec)
+
+
 @pytest.mark.parametrize("sampling", [0, 1])
 def test_trace_parity_mixed_tori(W, sampling):
     """Mixed problem on the tori union: every triangle Dirichlet, Neumann or
