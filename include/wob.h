@@ -115,7 +115,14 @@ typedef struct {
                            on each primitive; the value is the datum of the primitive's own
                            kind (eq. PoissonBC: g on Dirichlet, q on Neumann, g_R on Robin
                            parts) and `program` / `params` are ignored */
-  int32_t reserved;     /* must be 0 */
+  int32_t path_offset;  /* >= 0: path k of every point draws the random numbers of path
+                           path_offset + k (0 for a plain solve; path_offset + samples <=
+                           2^31 - 1).  Solves of disjoint path ranges of the same points
+                           and seed hold disjoint paths of one estimator: their per-point
+                           (n, mean, M2 = (n - 1) var) merge into the solve of the union by
+                           Chan's formula, n = n1 + n2, d = mean2 - mean1, mean = mean1 +
+                           d n2 / n, M2 = M2_1 + M2_2 + d^2 n1 n2 / n (resume a solve, or
+                           share its paths among devices).  Not with wob_forward_paths */
   const void* vertex_data; /* WOB_DATA_VERTEX: DEVICE array of the scene's n_verts values, of
                            the scene's element type, indexed like the vertices passed to
                            wob_build_bvh; caller-owned, read by enqueued work */

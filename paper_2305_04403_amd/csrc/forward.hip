@@ -310,6 +310,7 @@ wob_status wob_forward_paths(wob_scene sc, const wob_bc* bc, wob_starts starts, 
   if (check_data(bc) != WOB_OK) return WOB_E_ARG;
   if (bc->formulation != WOB_F_AUTO && bc->formulation != WOB_F_SINGLE_LAYER) return WOB_E_UNSUPPORTED;
   if (bc->density != 0 || bc->sampling != WOB_SAMPLE_LINE) return WOB_E_UNSUPPORTED;
+  if (bc->path_offset != 0) return WOB_E_UNSUPPORTED;  // forward paths have ids of their own
   if (sc->n_neumann != sc->n_prims) return WOB_E_UNSUPPORTED;  // Neumann data only
   if (walk_len < 1 || walk_len >= 65535) return WOB_E_ARG;
   if (n_paths < 0 || n_paths >= ((int64_t)1 << 32)) return WOB_E_ARG;  // path id is a 32-bit counter word

@@ -118,7 +118,7 @@ wob::ProgramView<R> make_program(const wob_scene_s* sc, const wob_bc* bc) {
 // Data mode and program of a wob_bc.
 inline wob_status check_data(const wob_bc* bc) {
   if (bc->data_mode != WOB_DATA_PROGRAM && bc->data_mode != WOB_DATA_VERTEX) return WOB_E_ARG;
-  if (bc->reserved != 0) return WOB_E_ARG;
+  if (bc->path_offset < 0) return WOB_E_ARG;
   if (bc->data_mode == WOB_DATA_VERTEX) return bc->vertex_data ? WOB_OK : WOB_E_ARG;
   if (bc->program < WOB_PROG_CONST || bc->program > WOB_PROG_INVDIST) return WOB_E_ARG;
   return WOB_OK;
@@ -131,6 +131,7 @@ inline wob_status plan_walk(const wob_scene_s* sc, const wob_bc* bc, int32_t sam
   if (bc->domain != 1 && bc->domain != -1) return WOB_E_ARG;
   if (bc->density != 0 && bc->density != 1) return WOB_E_ARG;
   if (samples < 1 || walk_len < 1 || walk_len >= 65535) return WOB_E_ARG;
+  if ((int64_t)bc->path_offset + samples > INT32_MAX) return WOB_E_ARG;
   const int f = resolve_formulation(sc, bc->formulation);
   if (f == -2) return WOB_E_ARG;
   if (f < 0) return WOB_E_UNSUPPORTED;
@@ -180,6 +181,7 @@ wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void*
   a.k0 = (uint32_t)(seed & 0xffffffffu);
   a.k1 = (uint32_t)(seed >> 32);
   a.problem = 0;
+  a.path_offset = bc->path_offset;
   a.lpp_shift = lpp_shift_for(samples, kSolveBlock);
   a.density = bc->density;
   a.status = sc->d_status;

@@ -30,6 +30,7 @@ struct WalkArgs {
   uint32_t k0, k1;            // Philox key
   uint32_t problem;           // problem index (counter word 2, bits 24..31)
   int32_t lpp_shift;          // log2 of lanes per point (0 .. log2 of the block size)
+  int32_t path_offset;        // path k of a point draws the random numbers of path path_offset + k
   int32_t form;               // F_DL / F_DIRECT / F_SL / F_SL_RIS (read by the batched kernel)
   int32_t density;            // estimate the boundary unknown at boundary points (no own emission)
   int32_t ris_c;              // single layer: RIS candidates per vertex, 0 = line sampling
@@ -886,7 +887,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     if (path_of(tid & (G - 1), pl, k)) {
       point = point0 + pl;
       load_point();
-      st = start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc);
+      st = start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)(a.path_offset + k), point * (int64_t)a.N + k,
+                                                      wc);
     }
     for (;;) {
       // finished paths: record, start the lane's next one
@@ -970,7 +972,8 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
             load_point();
           }
         }
-        st = go ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)k, point * (int64_t)a.N + k, wc,
+        st = go ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)(a.path_offset + k),
+                                                             point * (int64_t)a.N + k, wc,
                                                              couple, point)
                 : ST_NONE;
       }

@@ -45,7 +45,7 @@ class _BC(C.Structure):
     _fields_ = [("domain", C.c_int32), ("formulation", C.c_int32), ("program", C.c_int32),
                 ("density", C.c_int32), ("sampling", C.c_int32), ("candidates", C.c_int32),
                 ("params", C.c_double * 8), ("self_panel_p", C.c_double), ("mixed_k", C.c_double),
-                ("mixed_p", C.c_double), ("data_mode", C.c_int32), ("reserved", C.c_int32),
+                ("mixed_p", C.c_double), ("data_mode", C.c_int32), ("path_offset", C.c_int32),
                 ("vertex_data", C.c_void_p)]
 
 
@@ -184,6 +184,7 @@ class BC:
     mixed_p: float = 0.0          # and p_k (0 = 2/3)
     vertex_data: object = None    # per-vertex data (device tensor of the scene's dtype,
                                   # one value per mesh vertex): replaces program/params
+    path_offset: int = 0          # path k draws the random numbers of path path_offset + k
 
     def c(self, scene: "Scene") -> _BC:
         b = _BC()
@@ -194,6 +195,7 @@ class BC:
         b.density = int(bool(self.density))
         b.sampling, b.candidates = int(self.sampling), int(self.candidates)
         b.mixed_k, b.mixed_p = float(self.mixed_k), float(self.mixed_p)
+        b.path_offset = int(self.path_offset)
         for i, v in enumerate(self.params):
             b.params[i] = float(v)
         b.self_panel_p = float(self.self_panel_p)
