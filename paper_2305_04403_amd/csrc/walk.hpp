@@ -8,11 +8,12 @@ namespace wob {
 
 // Dynamic LDS of the path kernels: the lanes' traversal stacks and held
 // leaves, stack_cap + kLeafSlots entries of 4 bytes per thread of the block,
-// then one more row (the path counters of the lane groups; sized at launch).
+// then one more row (the path counters of the lane groups) and one word (the
+// path offset; sized at launch).
 extern __shared__ int32_t wob_stack[];
 constexpr int kLeafSlots = 4;
 inline size_t walk_lds_bytes(int stack_cap, int block) {
-  return (size_t)(stack_cap + kLeafSlots + 1) * (size_t)block * sizeof(int32_t);
+  return ((size_t)(stack_cap + kLeafSlots + 1) * (size_t)block + 1) * sizeof(int32_t);
 }
 
 template <typename R, int D>
@@ -826,6 +827,12 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   if ((tid & (G - 1)) == 0)
     __hip_atomic_store(wob_stack + (a.scene.stack_cap + kLeafSlots) * BLOCK + tid, G, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_WAVEFRONT);
+  // the path offset, read back at each path's start: kept in LDS rather than
+  // in a scalar register across the loops (the kernel's scalar registers are
+  // all in use; one more spills others into the hot loops).  Every wavefront
+  // writes the same value before it reads it.
+  int32_t* const offset_word = wob_stack + (a.scene.stack_cap + kLeafSlots + 1) * BLOCK;
+  if ((tid & 63) == 0) *offset_word = a.path_offset;
   // counter c of the group -> the path's point (0 or 1 within the pool) and
   // index; false past the group's last path (c is taken in increasing order,
   // and so are the paths it names)
@@ -887,7 +894,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
     if (path_of(tid & (G - 1), pl, k)) {
       point = point0 + pl;
       load_point();
-      st = start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)(a.path_offset + k), point * (int64_t)a.N + k,
+      st = start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)(*offset_word + k), point * (int64_t)a.N + k,
                                                       wc);
     }
     for (;;) {
@@ -972,7 +979,7 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
             load_point();
           }
         }
-        st = go ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)(a.path_offset + k),
+        st = go ? start_path<R, D, FORM, TRACE, COUNT, KEXT>(a, s, (uint32_t)(*offset_word + k),
                                                              point * (int64_t)a.N + k, wc,
                                                              couple, point)
                 : ST_NONE;
