@@ -323,9 +323,9 @@ def cv_leg(torch, wob, I, n_seeds=10):
     """Equal wall time on the 1M points: plain WoB at 512 paths against the
     corrected estimator with (a) g = g0 = 0 (hit-selection Rao-Blackwellisation
     only), (b) the learned network (fit included in its time) and (c) the same
-    without the fit time; and plain resampled importance sampling (4 and 16
-    area candidates) in place of line sampling, and the corrected walk on
-    RIS-16 (g = g0 = 0, and learned).  Every variant runs with
+    without the fit time; and plain resampled importance sampling (4, 16 and
+    32 area candidates) in place of line sampling, and the corrected walk on
+    RIS-16 and RIS-32 (g = g0 = 0, and learned).  Every variant runs with
     `n_seeds` seeds; RMSE ratios pool the per-seed squared errors and carry a
     paired bootstrap 95 % interval over the seeds.  Also the per-point
     variance of each variant (paired log ratio against (a) on the same seeds)
@@ -418,11 +418,12 @@ def cv_leg(torch, wob, I, n_seeds=10):
     sync()
     t_add = time.perf_counter() - t0
     ris16 = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=16)
+    ris32 = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=32)
 
     def cost(b):
         return slope(lambda n: wob.solve_cv(scene, pts, b, n, M, lcv.g, seed=2, point_prim=pp, g0=lcv.g0))
 
-    costs = {id(bc): cost(bc), id(ris16): cost(ris16)}
+    costs = {id(bc): cost(bc), id(ris16): cost(ris16), id(ris32): cost(ris32)}
     variants = {"plain": plain}
 
     def run_cv(name, g, g0, fixed_s, seed0, b=bc):
@@ -441,7 +442,7 @@ def cv_leg(torch, wob, I, n_seeds=10):
     run_cv("learned_inference_only", lcv.g, lcv.g0, 0.0, 6)
     # the paper's sampling for Robin / mixed problems: RIS over area-uniform
     # candidates (16 in the paper; 4 is cheaper than a traced line)
-    for C in (4, 16):
+    for C in (4, 16, 32):
         b = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=C)
         pp_cost, rest = slope(lambda n: wob.solve(scene, pts, b, n, M, seed=2, point_prim=pp))
         n = int(max(8, (t_plain - rest) / pp_cost // 8 * 8))
@@ -452,6 +453,10 @@ def cv_leg(torch, wob, I, n_seeds=10):
     # candidates replaces the pick, with g = g0 = 0 and with the learned tables
     run_cv("ris_16_rb_only", zero, zero, 0.0, 8, b=ris16)
     run_cv("ris_16_learned", lcv.g, lcv.g0, fit["fit_s"], 9, b=ris16)
+    # 32 candidates (the paper takes 16): the cheaper pick made more candidates
+    # affordable, and they thin the tail further
+    run_cv("ris_32_rb_only", zero, zero, 0.0, 10, b=ris32)
+    run_cv("ris_32_learned", lcv.g, lcv.g0, fit["fit_s"], 11, b=ris32)
 
     # the same-paths variance comparison (N paths, seed 11): every variant's
     # per-point variance against the Rao-Blackwellised one, paired by point
