@@ -79,26 +79,38 @@ PROFILES = {
 }
 
 
+def kernel_source_hash(sources) -> str:
+    """SHA-256 of the kernel sources' code: the files concatenated in order,
+    each with its comments removed and its whitespace runs collapsed to one
+    space (a change of comments or layout leaves the kernels, and so the
+    counters taken from them, as they were)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def measured_profile(leg: str):
     """From the committed counter summary of a leg's kernel: HBM bytes per
     launch (FETCH + WRITE, calibrated), and where present the per-level
     memory fractions and the VALU busy / utilization figures; None when the
-    kernel sources changed since the counters were taken."""
-    import hashlib
+    kernel code changed since the counters were taken."""
     try:
         path, sources = PROFILES[leg]
         with open(os.path.join(ROOT, path)) as fh:
             text = fh.read()
     except (OSError, KeyError):
         return None
-    h = hashlib.sha256()
-    for f in sources:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
     keys = ("source-sha256-prefix:", "traffic-bytes-per-launch:", "memory-levels:", "valu:")
     rec = dict(line.strip().split(": ", 1) for line in text.splitlines() if line.strip().startswith(keys))
     prefix = rec.get("source-sha256-prefix", "")
-    if not prefix or not h.hexdigest().startswith(prefix):
+    if not prefix or not kernel_source_hash(sources).startswith(prefix):
         return None
     fetch, write = (int(v) for v in rec["traffic-bytes-per-launch"].split())
     out = {"traffic": fetch + write, "profile": path}

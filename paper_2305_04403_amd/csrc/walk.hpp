@@ -860,12 +860,13 @@ __device__ __forceinline__ void walk_block(const WalkArgs<R, D>& a, int64_t bloc
   constexpr int KEXT =
       (ext_kind(EXT) == X_CV && !(D == 3 && (FORM == F_SL || FORM == F_SL_RIS))) ? (EXT & X_VDATA) : EXT;
   {
-    // The lane's paths (its first k = lane_in_point, then the group's next
-    // free ones) run as one state machine.  Lanes step through BVH nodes; a lane that has reached four
-    // crossed leaves parks until half of the stepping lanes have parked, and
-    // the lanes holding leaves then test them together; a lane at the end of its line
-    // parks until a quarter of the working lanes have, and those lanes then
-    // take their path steps together.  That code thus runs on many lanes at
+    // The lane's paths (first the one of counter c = its place in the group,
+    // then the group's next free ones) run as one state machine.  Lanes step
+    // through BVH nodes; a lane that has reached four crossed leaves parks
+    // until half of the stepping lanes have parked, and the lanes holding
+    // leaves then test them together; a lane at the end of its line parks
+    // until a quarter of the working lanes have, and those lanes then take
+    // their path steps together.  That code thus runs on many lanes at
     // once instead of on the one or two lanes that stand at a leaf or a line
     // end in a given node step.
     PathState<R, D> s;
