@@ -18,11 +18,20 @@ SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "
 def build(verbose: bool = False, sanitize: bool = False) -> str:
     out = LIB_SANITIZED if sanitize else LIB
     flags = ["-O1"] + SANITIZE_FLAGS if sanitize else ["-O2"]
+    # written under a name of this process and renamed into place, so that a
+    # process loading the library (parallel test workers) never sees it half
+    # written
+    tmp = f"{out}.{os.getpid()}.tmp"
     cmd = ["gcc", "-std=c11", *flags, "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", out, os.path.join(HERE, "oracle.c"), os.path.join(HERE, "mlp.c"), "-lm"]
+           "-o", tmp, os.path.join(HERE, "oracle.c"), os.path.join(HERE, "mlp.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
-    subprocess.check_call(cmd)
+    try:
+        subprocess.check_call(cmd)
+        os.replace(tmp, out)
+    finally:
+        if os.path.exists(tmp):
+            os.remove(tmp)
     return out
 
 
