@@ -508,6 +508,14 @@ void wob_mlp_free(wob_mlp net);
 /* HOST copies of the binary32 parameters (set also resets the Adam moments). */
 wob_status wob_mlp_get_params(wob_mlp net, float* params);
 wob_status wob_mlp_set_params(wob_mlp net, const float* params);
+/* HOST copies of the Adam moments (first and second, wob_mlp_n_params() values
+ * each; binary32).  With the parameters they are the whole training state (the
+ * step count is the caller's, passed to each Adam step): a fit checkpointed by
+ * get_params + get_moments and restored by set_params then set_moments goes on
+ * exactly as without the break.  Synchronous with the null stream: wait for
+ * work enqueued on other streams first.  Errors: WOB_E_ARG, WOB_E_DEVICE. */
+wob_status wob_mlp_get_moments(wob_mlp net, float* m, float* v);
+wob_status wob_mlp_set_moments(wob_mlp net, const float* m, const float* v);
 
 /* out[i] = f(y_i); y DEVICE n x dim, out DEVICE n. */
 wob_status wob_mlp_forward(wob_mlp net, const float* y, int64_t n, float* out, void* stream);

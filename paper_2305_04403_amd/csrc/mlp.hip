@@ -494,6 +494,22 @@ wob_status wob_mlp_set_params(wob_mlp h, const float* params) {
   return WOB_OK;
 }
 
+wob_status wob_mlp_get_moments(wob_mlp h, float* m, float* v) {
+  if (!h || !m || !v) return WOB_E_ARG;
+  return hipMemcpy(m, h->net.m, NP * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+                 hipMemcpy(v, h->net.v, NP * 4, hipMemcpyDeviceToHost) == hipSuccess
+             ? WOB_OK
+             : WOB_E_DEVICE;
+}
+
+wob_status wob_mlp_set_moments(wob_mlp h, const float* m, const float* v) {
+  if (!h || !m || !v) return WOB_E_ARG;
+  if (hipMemcpy(h->net.m, m, NP * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->net.v, v, NP * 4, hipMemcpyHostToDevice) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return WOB_E_DEVICE;
+  return WOB_OK;
+}
+
 wob_status wob_mlp_forward(wob_mlp h, const float* y, int64_t n, float* out, void* stream) {
   if (!h || n < 0 || (n > 0 && (!y || !out))) return WOB_E_ARG;
   if (n == 0) return WOB_OK;
@@ -527,8 +543,8 @@ wob_status wob_mlp_backward(wob_mlp h, const float* y, const float* target,
 
 wob_status wob_mlp_adam_step(wob_mlp h, const float* grad, int64_t step, float lr, float b1, float b2,
                              float eps, void* stream) {
-  if (!h || !grad || step < 1 || !(lr > 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) ||
-      !(eps > 0.f))
+  if (!h || !grad || step < 1 || !(lr > 0.f) || !std::isfinite(lr) || !(b1 >= 0.f && b1 < 1.f) ||
+      !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
     return WOB_E_ARG;
   const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
   hipLaunchKernelGGL(adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, (hipStream_t)stream, h->net,

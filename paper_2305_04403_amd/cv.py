@@ -18,6 +18,9 @@ Steps, each a call into libwob.so (this module only sequences them):
   4. the output layer is rescaled to the raw targets, ``wob_cv_table``
      evaluates the network at every centroid (g) and ``wob_cv_emission`` adds
      the line-0 emission at the centroid (g0 = g + 2 phi s).
+If training leaves non-finite parameters, or the tables hold non-finite
+values, the control variate is switched off (``disabled`` names why) and
+``solve`` runs plain WoB, which needs no table.
 """
 from __future__ import annotations
 
@@ -71,6 +74,7 @@ class LearnedControlVariate:
         self.g0 = None
         self.timings = {}
         self.history = []
+        self.disabled = None  # why the control variate is off, if it is
 
     def fit(self, stream=None) -> dict:
         import torch
@@ -106,20 +110,31 @@ class LearnedControlVariate:
         t2 = time.perf_counter()
         # back to raw targets: f = scale * f_n + median
         p = self.net.params()
-        o = p.shape[0] - HIDDEN - 1
-        p[o:o + HIDDEN] *= scale
-        p[-1] = p[-1] * scale + med
-        self.net.set_params(p)
-        self.g = wob.cv_table(self.scene, self.net, stream=stream)
-        self.g0 = wob.cv_emission(self.scene, self.bc, self.g, stream=stream)
+        self.disabled = None
+        if not np.isfinite(p).all():
+            self.disabled = "the trained network's parameters are not finite"
+            self.g = self.g0 = None
+        else:
+            o = p.shape[0] - HIDDEN - 1
+            p[o:o + HIDDEN] *= scale
+            p[-1] = p[-1] * scale + med
+            self.net.set_params(p)
+            self.g = wob.cv_table(self.scene, self.net, stream=stream)
+            self.g0 = wob.cv_emission(self.scene, self.bc, self.g, stream=stream)
+            if not (np.isfinite(self.g.cpu().numpy()).all() and np.isfinite(self.g0.cpu().numpy()).all()):
+                self.disabled = "the network's tables are not finite"
+                self.g = self.g0 = None
         sync()
         t3 = time.perf_counter()
         self.timings = {"targets_s": t1 - t0, "train_s": t2 - t1, "table_s": t3 - t2, "fit_s": t3 - t0,
                         "train_steps": total, "final_loss": self.history[-1] if self.history else None,
-                        "target_median": med, "target_scale": scale}
+                        "target_median": med, "target_scale": scale, "cv_disabled": self.disabled}
         return self.timings
 
     def solve(self, points, samples: int, seed: int = 0, point_prim=None, want_var=True, stream=None):
+        if self.disabled:  # plain WoB: the same estimator without the control variate
+            return wob.solve(self.scene, points, self.bc, samples, self.walk_len, seed=seed,
+                             point_prim=point_prim, want_var=want_var, stream=stream)
         if self.g is None:
             raise wob.WobError("fit() first")
         return wob.solve_cv(self.scene, points, self.bc, samples, self.walk_len, self.g, seed=seed,

@@ -29,7 +29,8 @@ EXPORTED = ("wob_build_bvh", "wob_build_bvh_ex", "wob_free", "wob_get_scene_info
             "wob_batch_create", "wob_batch_launch", "wob_batch_autotune", "wob_batch_get_tune",
             "wob_batch_free", "wob_solve_batched", "wob_solve_batched_static", "wob_mlp_n_params",
             "wob_mlp_create",
-            "wob_mlp_free", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
+            "wob_mlp_free", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_get_moments",
+            "wob_mlp_set_moments", "wob_mlp_forward",
             "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
             "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_cv_emission", "wob_sample_boundary",
             "wob_starts_create", "wob_starts_from_data", "wob_starts_free", "wob_forward_paths",
@@ -117,11 +118,14 @@ def lib():
     L.wob_mlp_free.restype = None
     L.wob_mlp_get_params.argtypes = [vp, vp]
     L.wob_mlp_set_params.argtypes = [vp, vp]
+    L.wob_mlp_get_moments.argtypes = [vp, vp, vp]
+    L.wob_mlp_set_moments.argtypes = [vp, vp, vp]
     L.wob_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
     L.wob_mlp_backward.argtypes = [vp, vp, vp, C.POINTER(_TargetMap), i64, vp, vp, vp]
     L.wob_mlp_adam_step.argtypes = [vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.wob_mlp_train_step.argtypes = [vp, vp, vp, C.POINTER(_TargetMap), i64, i64, C.c_float, vp, vp]
-    for name in ("wob_mlp_create", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_forward",
+    for name in ("wob_mlp_create", "wob_mlp_get_params", "wob_mlp_set_params", "wob_mlp_get_moments",
+                 "wob_mlp_set_moments", "wob_mlp_forward",
                  "wob_mlp_backward", "wob_mlp_adam_step", "wob_mlp_train_step", "wob_cv_table",
             "wob_solve_cv", "wob_trace_cv", "wob_cv_addback", "wob_sample_boundary"):
         getattr(L, name).restype = C.c_int
@@ -720,6 +724,20 @@ class MLP:
     def set_params(self, params: np.ndarray):
         p = np.ascontiguousarray(params, dtype=np.float32)
         _check(lib().wob_mlp_set_params(self.handle, p.ctypes.data), "wob_mlp_set_params")
+
+    def moments(self):
+        """The Adam moments (m, v): with params() the training state."""
+        m = np.zeros(self.n_params, dtype=np.float32)
+        v = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().wob_mlp_get_moments(self.handle, m.ctypes.data, v.ctypes.data), "wob_mlp_get_moments")
+        return m, v
+
+    def set_moments(self, m: np.ndarray, v: np.ndarray):
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        if m.shape != (self.n_params,) or v.shape != (self.n_params,):
+            raise WobError("MLP: wrong moment shape")
+        _check(lib().wob_mlp_set_moments(self.handle, m.ctypes.data, v.ctypes.data), "wob_mlp_set_moments")
 
     def forward(self, y, out=None, stream=None):
         torch = _torch()

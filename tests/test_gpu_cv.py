@@ -229,3 +229,60 @@ def test_density_mode_off_the_boundary_is_nan(W, tori):
                      np.tile(np.arange(2), 5), want_pos=False)
     assert np.isnan(o["value"]).all()
     scene.close()
+
+
+def test_non_finite_network_switches_the_control_variate_off(W, tori):
+    """A fit that diverges (a learning rate of 1e38, forced from the host: the
+    parameters overflow) leaves non-finite parameters: the control variate is
+    switched off, says why, and solve() runs plain WoB (the same values as
+    wob.solve with the same seed).  Non-finite learning rates and parameters
+    are argument errors of the library itself."""
+    from paper_2305_04403_amd import cv as CV
+    scene = W.Scene(tori.mesh, W.F32)
+    wb, _ = bcs(W, tori)
+    for bad in (float("nan"), float("inf")):
+        with pytest.raises(W.WobError):
+            CV.LearnedControlVariate(scene, wb, 4, CV.CVConfig(n_train=32768, lr=bad)).fit()
+    lcv = CV.LearnedControlVariate(scene, wb, 4, CV.CVConfig(n_train=32768, lr=1e38))
+    info = lcv.fit()
+    assert lcv.disabled and info["cv_disabled"] == lcv.disabled
+    pts, pp = dev(tori.points), dev(tori.point_prim, torch.int32)
+    m, v = lcv.solve(pts, 64, seed=3, point_prim=pp)
+    m0, v0 = W.solve(scene, pts, wb, 64, 4, seed=3, point_prim=pp)
+    torch.cuda.synchronize()
+    assert torch.isfinite(m).all()
+    assert torch.equal(m, m0) and torch.equal(v, v0)
+    lcv.close()
+    scene.close()
+
+
+def test_training_state_checkpoint_and_resume(W):
+    """Parameters and Adam moments saved after 5 training steps and restored
+    into a new network: 3 more steps there give the parameters of 3 more
+    steps of the uninterrupted network, bit for bit."""
+    from tests.test_oracle_cv_pins import rand_net
+    params, B = rand_net(21)
+    params, B = PT.f32(params), PT.f32(B)
+    rng = np.random.default_rng(4)
+    y = dev(PT.f32(rng.uniform(-1.2, 1.2, (1024, 3))))
+    t = dev(PT.f32(rng.standard_normal(1024)))
+    a = W.MLP(3, B, params, max_batch=1024)
+    for step in range(1, 6):
+        a.train_step(y, t, step, 2e-3)
+    torch.cuda.synchronize()
+    p5, (m5, v5) = a.params(), a.moments()
+    assert np.abs(m5).max() > 0 and np.abs(v5).max() > 0
+    b = W.MLP(3, B, params, max_batch=1024)
+    b.set_params(p5)
+    b.set_moments(m5, v5)
+    for step in range(6, 9):
+        a.train_step(y, t, step, 2e-3)
+        b.train_step(y, t, step, 2e-3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.params(), b.params())
+    ma, va = a.moments()
+    mb, vb = b.moments()
+    np.testing.assert_array_equal(ma, mb)
+    np.testing.assert_array_equal(va, vb)
+    a.close()
+    b.close()
