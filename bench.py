@@ -72,7 +72,10 @@ KERNEL_SOURCES = ("paper_2305_04403_amd/csrc/device.hpp", "paper_2305_04403_amd/
 # committed counter summaries of each leg's kernel and the sources they were
 # taken from: their figures are reported only while those sources are unchanged
 PROFILES = {
-    "tori": ("profiles/walk_kernel_tori200992_1M_points.md", KERNEL_SOURCES),
+    # the headline solve walks its points in Morton order: the ordering code
+    # shapes the walk kernel's counters too
+    "tori": ("profiles/walk_kernel_tori200992_1M_points.md",
+             KERNEL_SOURCES + ("paper_2305_04403_amd/csrc/order.hip",)),
     "slice": ("profiles/walk_kernel_icosphere20480_slice512_dirichlet.md", KERNEL_SOURCES),
     "batched": ("profiles/batch_kernel_64_problems.md",
                 KERNEL_SOURCES + ("paper_2305_04403_amd/csrc/batch.hip",)),
@@ -166,22 +169,28 @@ def walk_roofline(cnt, kern_s, cal, fp64=False, prof=None):
     return out
 
 
-def time_solve(torch, wob, scene, pts, pp, bc, N, M, seed, steps, warmup):
+def time_solve(torch, wob, scene, pts, pp, bc, N, M, seed, steps, warmup, ordered=False):
     """Warm-up, then `steps` solves bracketed by HIP events on the stream the
     kernel runs on; returns (wall seconds per step, average kernel seconds,
-    mean, var)."""
+    mean, var).  ``ordered``: the ordered solve (Morton order of the points,
+    sort and write-back inside the timed call), its workspace allocated once
+    beforehand like the outputs."""
     P = pts.shape[0]
     mean = torch.empty(P, dtype=scene.dtype, device="cuda")
     var = torch.empty(P, dtype=scene.dtype, device="cuda")
+    kw = {}
+    if ordered:
+        kw = dict(ordered=True, workspace=torch.empty(wob.ordered_workspace_bytes(scene, P), dtype=torch.uint8,
+                                                      device="cuda"))
     for _ in range(warmup):
-        wob.solve(scene, pts, bc, N, M, seed, point_prim=pp, out=(mean, var))
+        wob.solve(scene, pts, bc, N, M, seed, point_prim=pp, out=(mean, var), **kw)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
     t0 = time.perf_counter()
     for k in range(steps):
         ev[2 * k].record(stream)
-        wob.solve(scene, pts, bc, N, M, seed, point_prim=pp, out=(mean, var))
+        wob.solve(scene, pts, bc, N, M, seed, point_prim=pp, out=(mean, var), **kw)
         ev[2 * k + 1].record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
@@ -223,9 +232,10 @@ def cpu_baseline(w, n_points):
                       f"{dt:.1f} s"}
 
 
-def timed_leg(torch, wob, w, steps, warmup, cal, leg=None, fp64=False):
-    """A single-problem workload: solve timing, work counters of exactly the
-    timed paths, roofline record, RMSE against the analytic solution."""
+def timed_leg(torch, wob, w, steps, warmup, cal, leg=None, fp64=False, ordered=False):
+    """A single-problem workload: solve timing (``ordered``: the ordered
+    solve), work counters of exactly the timed paths (the order of the points
+    changes no path), roofline record, RMSE against the analytic solution."""
     scene = wob.Scene(w.mesh, wob.F64 if fp64 else wob.F32)
     info = scene.info()
     bc = wob.BC(w.bc["domain"], w.bc["formulation"], w.bc["program"], tuple(w.bc["params"]))
@@ -234,11 +244,12 @@ def timed_leg(torch, wob, w, steps, warmup, cal, leg=None, fp64=False):
     pp = None if w.point_prim is None else torch.as_tensor(w.point_prim, dtype=torch.int32, device="cuda")
     P, N, M = pts.shape[0], w.samples, w.walk_len
     cnt = wob.count_work(scene, pts, bc, N, M, w.seed, point_prim=pp)
-    wall, kern, mean, var = time_solve(torch, wob, scene, pts, pp, bc, N, M, w.seed, steps, warmup)
+    wall, kern, mean, var = time_solve(torch, wob, scene, pts, pp, bc, N, M, w.seed, steps, warmup, ordered)
     m = mean.double().cpu().numpy()
     ok = np.isfinite(m)
     out = {"workload": w.name, "points": P, "paths_per_point": N, "walk_len": M,
            "primitives": w.mesh.n_prims, "value": P * N / wall, "unit": "path samples/s",
+           "point_order": "Morton order, sorted inside the timed call" if ordered else "as given",
            "ms_per_step": 1e3 * wall, "kernel_ms": 1e3 * kern, "steps": steps,
            "lines_per_s": cnt["lines"] / wall,
            "rmse_vs_analytic": float(np.sqrt(np.mean((m[ok] - w.exact[ok]) ** 2))),
@@ -851,7 +862,8 @@ def main():
 
     # the headline: the three-tori workload
     w = I.config_tori()
-    main_rec = timed_leg(torch, wob, w, args.steps, args.warmup, cal, leg="tori") if "main" in legs else None
+    main_rec = (timed_leg(torch, wob, w, args.steps, args.warmup, cal, leg="tori", ordered=True)
+                if "main" in legs else None)
     if main_rec is None:
         print(json.dumps({"legs": extra, "gather_calibration_GB/s": cal}))
         return
@@ -873,6 +885,7 @@ def main():
                    "boundary_points": int((w.point_prim >= 0).sum()),
                    "paths_per_point": w.samples, "walk_len": w.walk_len, "triangles": w.mesh.n_prims,
                    "formulation": "single layer, line sampling (exterior Neumann / Robin)",
+                   "point_order": main_rec["point_order"],
                    "parallelism": "none (1 GPU)"},
     }
     for k in ("lines_per_s", "kernel_ms", "roofline", "vector_memory", "hbm", "memory_roof", "valu", "work_per_line",

@@ -38,6 +38,7 @@
 #ifndef WOB_H
 #define WOB_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -219,6 +220,35 @@ int32_t wob_lines_per_path(wob_scene scene, const wob_bc* bc, int32_t walk_len);
 wob_status wob_solve(wob_scene scene, const void* points, const int32_t* point_prim,
                      int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
                      uint64_t seed, void* mean_out, void* var_out, void* stream);
+
+/* wob_solve with the evaluation points walked in a locality order: the same
+ * estimate (Algorithm 1's EstimateSolution under Table 1's estimators) and the
+ * same paths, scheduled so that points lying close together run side by side
+ * and share cached BVH nodes and triangles.  On the device, on `stream`: Morton
+ * keys of the points (2^10 cells per axis in 3D, 2^15 in 2D, over the points'
+ * bounding box), a stable radix sort of (key, index), the points and their
+ * primitive ids gathered into that order, the walk (point i of the sorted order
+ * keeps the random-number point index of its caller position), and the results
+ * written back to the caller's order.  Every point's path values equal
+ * wob_solve's; mean_out and var_out equal wob_solve's up to the order in which
+ * a point's path values are summed (binary32 / binary64 rounding).  The result
+ * does not depend on anything but the inputs: equal calls give equal bits.
+ *   points ... var_out   as for wob_solve; n_points <= INT32_MAX
+ *   workspace        DEVICE, 256-byte aligned, at least the size that
+ *                    wob_solve_ordered_workspace gives for n_points; owned by
+ *                    the caller, contents undefined after the call.  Calls that
+ *                    share a workspace must be ordered on one stream.
+ * Errors: WOB_E_ARG (also: workspace NULL, misaligned or too small),
+ * WOB_E_UNSUPPORTED, WOB_E_DEVICE. */
+wob_status wob_solve_ordered(wob_scene scene, const void* points, const int32_t* point_prim,
+                             int64_t n_points, const wob_bc* bc, int32_t samples, int32_t walk_len,
+                             uint64_t seed, void* mean_out, void* var_out, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/* Device workspace bytes of wob_solve_ordered for n_points points of this
+ * scene (its dimension and precision).  Errors: WOB_E_ARG (n_points < 0 or
+ * above INT32_MAX, NULL scene or bytes). */
+wob_status wob_solve_ordered_workspace(wob_scene scene, int64_t n_points, size_t* bytes);
 
 /* Per-path values (parity and debugging); the same paths as wob_solve.
  *   point_ids  DEVICE, n_points uint32 point indices used in the random-number

@@ -27,7 +27,7 @@ def build(verbose: bool = False) -> str:
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     cmds, objs = [], []
-    for src in ("wob.hip", "batch.hip", "mlp.hip", "forward.hip", "probe.hip"):
+    for src in ("wob.hip", "order.hip", "batch.hip", "mlp.hip", "forward.hip", "probe.hip"):
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
         cmds.append([hipcc, "-c", *HIP_FLAGS, os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

@@ -197,4 +197,28 @@ wob::WalkArgs<R, D> make_args(const wob_scene_s* sc, const Plan& pl, const void*
 }
 
 
+// Workspace of the ordered solve (byte offsets, each 256-aligned): partial
+// bounding boxes, Morton keys (in, sorted), indices (in, sorted = the order),
+// the sorted points and primitive ids, the sorted-order results, the radix
+// sort's temporary storage.
+struct OrderLayout {
+  size_t part, keys, keys_s, idx, order, pts, prim, mean, var, temp, temp_bytes, total;
+};
+// The walk's inputs in locality order: order[i] is the caller's index of
+// sorted point i (also its random-number point index).
+struct OrderBuffers {
+  const uint32_t* order;
+  const void* points;
+  const int32_t* point_prim;
+  void* mean;
+  void* var;
+};
+OrderLayout order_layout(int dim, int precision, int64_t n);
+// Enqueues the Morton keys, the stable sort and the gather on `stream`.
+wob_status order_points(int dim, int precision, const OrderLayout& L, void* workspace, const void* points,
+                        const int32_t* point_prim, int64_t n, void* stream, OrderBuffers* out);
+// Enqueues mean_out[order[i]] = mean[i] (and var) on `stream`.
+wob_status scatter_results(int precision, const OrderBuffers& b, int64_t n, void* mean_out, void* var_out,
+                           void* stream);
+
 }  // namespace wobi

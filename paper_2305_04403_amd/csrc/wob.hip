@@ -650,6 +650,34 @@ wob_status wob_solve(wob_scene sc, const void* points, const int32_t* point_prim
                   var_out, nullptr, nullptr, nullptr, nullptr, MODE_SOLVE, stream);
 }
 
+wob_status wob_solve_ordered_workspace(wob_scene sc, int64_t n_points, size_t* bytes) {
+  if (!sc || !bytes || n_points < 0 || n_points > INT32_MAX) return WOB_E_ARG;
+  *bytes = order_layout(sc->dim, sc->precision, n_points).total;
+  return WOB_OK;
+}
+
+wob_status wob_solve_ordered(wob_scene sc, const void* points, const int32_t* point_prim, int64_t n_points,
+                             const wob_bc* bc, int32_t samples, int32_t walk_len, uint64_t seed,
+                             void* mean_out, void* var_out, void* workspace, size_t workspace_bytes,
+                             void* stream) {
+  Plan pl;
+  wob_status s = plan_walk(sc, bc, samples, walk_len, &pl);
+  if (s != WOB_OK) return s;
+  if (n_points < 0 || n_points > INT32_MAX || (n_points > 0 && (!points || !mean_out))) return WOB_E_ARG;
+  if (var_out && samples < 2) return WOB_E_ARG;
+  if (n_points == 0) return WOB_OK;
+  const OrderLayout L = order_layout(sc->dim, sc->precision, n_points);
+  if (!workspace || (uintptr_t)workspace % 256 != 0 || workspace_bytes < L.total) return WOB_E_ARG;
+  OrderBuffers b;
+  s = order_points(sc->dim, sc->precision, L, workspace, points, point_prim, n_points, stream, &b);
+  if (s != WOB_OK) return s;
+  // the walk in locality order; each point keeps its own random-number index
+  s = run_walk(sc, b.points, b.point_prim, n_points, bc, samples, walk_len, seed, b.order, b.mean,
+               var_out ? b.var : nullptr, nullptr, nullptr, nullptr, nullptr, MODE_SOLVE, stream);
+  if (s != WOB_OK) return s;
+  return scatter_results(sc->precision, b, n_points, mean_out, var_out, stream);
+}
+
 wob_status wob_trace(wob_scene sc, const void* points, const int32_t* point_prim, int64_t n_points,
                      const wob_bc* bc, int32_t samples, int32_t walk_len, uint64_t seed,
                      const uint32_t* point_ids, void* path_out, int32_t* vtx_prim, int32_t* vtx_m,

@@ -25,7 +25,7 @@ DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 SAMPLE_LINE, SAMPLE_RIS = 0, 1
 
 EXPORTED = ("wob_build_bvh", "wob_build_bvh_ex", "wob_free", "wob_get_scene_info", "wob_lines_per_path", "wob_solve",
-            "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string",
+            "wob_solve_ordered", "wob_solve_ordered_workspace", "wob_trace", "wob_intersect_all", "wob_count_work", "wob_status_string",
             "wob_batch_create", "wob_batch_launch", "wob_batch_autotune", "wob_batch_get_tune",
             "wob_batch_free", "wob_solve_batched", "wob_solve_batched_static", "wob_mlp_n_params",
             "wob_mlp_create",
@@ -97,6 +97,8 @@ def lib():
     L.wob_lines_per_path.argtypes = [vp, C.POINTER(_BC), i32]
     L.wob_lines_per_path.restype = i32
     L.wob_solve.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp]
+    L.wob_solve_ordered.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, C.c_size_t, vp]
+    L.wob_solve_ordered_workspace.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
     L.wob_trace.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp, vp, vp, vp]
     L.wob_count_work.argtypes = [vp, vp, vp, i64, C.POINTER(_BC), i32, i32, u64, vp, vp]
     L.wob_intersect_all.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
@@ -160,7 +162,8 @@ def lib():
     L.wob_forward_gather.restype = C.c_int
     L.wob_status_string.argtypes = [C.c_int]
     L.wob_status_string.restype = C.c_char_p
-    for name in ("wob_build_bvh", "wob_build_bvh_ex", "wob_get_scene_info", "wob_solve", "wob_trace",
+    for name in ("wob_build_bvh", "wob_build_bvh_ex", "wob_get_scene_info", "wob_solve", "wob_solve_ordered",
+                 "wob_solve_ordered_workspace", "wob_trace",
                  "wob_count_work", "wob_intersect_all"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -351,9 +354,14 @@ class Scene:
 
 
 def solve(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int = 0,
-          point_prim=None, want_var: bool = True, stream=None, out=None):
+          point_prim=None, want_var: bool = True, stream=None, out=None, ordered: bool = False,
+          workspace=None):
     """Per-point mean (and variance) of ``samples`` WoB paths.  ``points`` is a
-    contiguous (P, dim) device tensor of the scene's dtype."""
+    contiguous (P, dim) device tensor of the scene's dtype.  ``ordered``: walk
+    the points in a locality order (``wob_solve_ordered``; the same paths, the
+    statistics equal to the summation's rounding), in ``workspace`` (a uint8
+    device tensor of at least ``ordered_workspace_bytes`` bytes) or in one
+    allocated here."""
     torch = _torch()
     P = _need_points(scene, points)
     _need(point_prim, "point_prim", torch.int32, (P,), scene.device, optional=True)
@@ -365,11 +373,30 @@ def solve(scene: Scene, points, bc: BC, samples: int, walk_len: int, seed: int =
         _need(mean, "mean out", scene.dtype, (P,), scene.device)
         _need(var, "var out", scene.dtype, (P,), scene.device, optional=True)
     b = bc.c(scene)
+    if ordered:
+        need = ordered_workspace_bytes(scene, P)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=points.device)
+        _need(workspace, "workspace", torch.uint8, (None,), scene.device)
+        st = lib().wob_solve_ordered(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
+                                     int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(mean),
+                                     _dev_ptr(var), _dev_ptr(workspace), workspace.numel(), _stream(stream))
+        _check(st, "wob_solve_ordered")
+        return mean, var
     st = lib().wob_solve(scene.handle, _dev_ptr(points), _dev_ptr(point_prim), P, C.byref(b),
                          int(samples), int(walk_len), C.c_uint64(seed), _dev_ptr(mean),
                          _dev_ptr(var), _stream(stream))
     _check(st, "wob_solve")
     return mean, var
+
+
+def ordered_workspace_bytes(scene: Scene, n_points: int) -> int:
+    """Device workspace bytes of an ordered solve of ``n_points`` points
+    (``wob_solve_ordered_workspace``)."""
+    n = C.c_size_t(0)
+    _check(lib().wob_solve_ordered_workspace(scene.handle, int(n_points), C.byref(n)),
+           "wob_solve_ordered_workspace")
+    return int(n.value)
 
 
 class Starts:
