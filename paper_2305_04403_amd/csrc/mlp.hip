@@ -25,6 +25,7 @@ constexpr int HD = 128;       // hidden width
 constexpr int NL = 4;         // hidden layers
 constexpr int TR = 64;        // rows per workgroup
 constexpr int NT = 256;       // threads per workgroup (4 wavefronts)
+constexpr int kFwdGrid = 1024;  // forward-pass workgroups (256 CUs x 4)
 
 // parameter offsets (floats): W_l [out][in] then b_l, layers 0..NL (NL = output)
 constexpr int in_of(int l) { return l == 0 ? F0 : HD; }
@@ -104,27 +105,24 @@ struct Smem {
   float red[NT];
 };
 
-// The forward pass alone keeps two activation buffers (layer l writes buffer
-// l % 2): 36 KiB of LDS, four workgroups per CU instead of the backward pass's
-// one.
+// The forward pass alone: two activation buffers (layer l writes buffer l % 2)
+// whose rows are padded by 8 elements, so that the 16 rows of an operand
+// fragment start 16 bytes apart and spread over the LDS banks.  About 40 KiB.
+constexpr int LDA0 = F0 + 8, LDH = HD + 8;
 struct FwdSmem {
-  __bf16 a0[TR * F0];
-  __bf16 act[2][TR * HD];
-  __bf16 w[HD * (HD + 8)];  // the current layer's weights, rows padded by 8 (bank spread)
+  __bf16 a0[TR * LDA0];
+  __bf16 act[2][TR * LDH];
+  float w5[HD];  // the output layer's weights (their bfloat16 values)
 };
 
-// Features and the four hidden layers for rows r0 .. r0 + 63 into LDS: the
-// features to a0, layer l's activations to act + (ALL ? l : l % 2) TR HD (ALL:
-// every layer kept, for the backward pass).  Pre-activations go to `sbuf`
-// (4 x 64 x 128 floats) when it is not null.  With `wlds`, each layer's
-// weights are first staged in LDS (every wavefront reads all of them: staged,
-// they come from L2 once per workgroup instead of once per wavefront).
+// Features and the four hidden layers for rows r0 .. r0 + 63 into LDS (the
+// backward pass): the features to a0, layer l's activations to act + l TR HD.
+// Pre-activations go to `sbuf` (4 x 64 x 128 floats) when it is not null.
 // Returns the last layer's buffer.
-template <bool ALL>
-__device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n, int64_t r0,
-                                      __bf16* a0, __bf16* act, float* sbuf, __bf16* wlds = nullptr) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int idx = tid; idx < TR * KF; idx += NT) {
+// The Fourier features of rows r0 .. r0 + 63 into a0 (row stride lda; rows
+// past n are zero).
+__device__ void features_tile(const Net& net, const float* y, int64_t n, int64_t r0, __bf16* a0, int lda) {
+  for (int idx = threadIdx.x; idx < TR * KF; idx += NT) {
     const int r = idx / KF, k = idx % KF;
     const int64_t row = r0 + r;
     float sv = 0.f, cv = 0.f;
@@ -141,25 +139,23 @@ __device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n,
       sv = (float)sd;
       cv = (float)cd;
     }
-    a0[r * F0 + k] = (__bf16)sv;
-    a0[r * F0 + KF + k] = (__bf16)cv;
+    a0[r * lda + k] = (__bf16)sv;
+    a0[r * lda + KF + k] = (__bf16)cv;
   }
+}
+
+template <bool ALL>
+__device__ const __bf16* forward_tile(const Net& net, const float* y, int64_t n, int64_t r0,
+                                      __bf16* a0, __bf16* act, float* sbuf) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  features_tile(net, y, n, r0, a0, F0);
   __syncthreads();
   for (int l = 0; l < NL; ++l) {
     const int K = in_of(l);
     const __bf16* A = l == 0 ? a0 : act + (ALL ? l - 1 : (l - 1) & 1) * TR * HD;
     __bf16* O = act + (ALL ? l : l & 1) * TR * HD;
     const __bf16* W = net.wq + offW(l);
-    int ldw = K;
-    if (wlds) {
-      for (int idx = tid * 8; idx < HD * K; idx += NT * 8) {
-        const int o = idx / K, k = idx - o * K;
-        *(bf16x8*)(wlds + o * (K + 8) + k) = *(const bf16x8*)(W + idx);
-      }
-      __syncthreads();
-      W = wlds;
-      ldw = K + 8;
-    }
+    const int ldw = K;
     const float* b = net.p + offB(l);
     floatx4 acc[8];
 #pragma unroll
@@ -204,14 +200,87 @@ __device__ float output_row(const Net& net, const __bf16* h4, int& r_out) {
   return acc + net.p[offB(NL)];
 }
 
-__global__ void __launch_bounds__(NT) mlp_forward_kernel(Net net, const float* y, int64_t n, float* out) {
+// Forward pass, weight-stationary: wavefront w computes output columns
+// 32 w .. 32 w + 31 of every hidden layer, and holds those columns of every
+// layer's bfloat16 weights in registers as MFMA operand fragments (26
+// fragments, 104 registers), loaded once per workgroup; the workgroups then
+// take 64-row tiles in turn.  Per layer and tile a wavefront reads the four
+// row blocks' activation fragments from LDS and issues 4 x 2 MFMAs per 32-wide
+// k step.  The accumulation order of each output (k ascending in steps of 32),
+// the bias, the activation and its rounding are those of the backward pass's
+// forward tile.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) mlp_forward_kernel(Net net, const float* y,
+                                                                                        int64_t n, float* out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   FwdSmem& sm = *reinterpret_cast<FwdSmem*>(smem_raw);
-  const int64_t r0 = (int64_t)blockIdx.x * TR;
-  const __bf16* h4 = forward_tile<false>(net, y, n, r0, sm.a0, sm.act[0], nullptr, sm.w);
-  int r;
-  const float f = output_row(net, h4, r);
-  if ((threadIdx.x & 3) == 0 && r0 + r < n) out[r0 + r] = f;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kq = 8 * (lane >> 4);  // the lane's eight k values within a 32-wide step
+  // weight fragments: B[k][o] = W[o][k], o = 32 wave + 16 cb + lane % 16
+  bf16x8 w0[2], wh[NL - 1][2][HD / 32];
+  float bias[NL][2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int o = 32 * wave + 16 * cb + (lane & 15);
+    w0[cb] = *(const bf16x8*)(net.wq + offW(0) + o * F0 + kq);
+#pragma unroll
+    for (int l = 1; l < NL; ++l)
+#pragma unroll
+      for (int ks = 0; ks < HD / 32; ++ks) wh[l - 1][cb][ks] = *(const bf16x8*)(net.wq + offW(l) + o * HD + 32 * ks + kq);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) bias[l][cb] = net.p[offB(l) + o];
+  }
+  if (tid < HD) sm.w5[tid] = (float)net.wq[offW(NL) + tid];
+  const float b5 = net.p[offB(NL)];
+  const int64_t n_tiles = (n + TR - 1) / TR;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t r0 = t * TR;
+    features_tile(net, y, n, r0, sm.a0, LDA0);
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const __bf16* A = l == 0 ? sm.a0 : sm.act[(l - 1) & 1];
+      const int lda = l == 0 ? LDA0 : LDH;
+      __bf16* O = sm.act[l & 1];
+      floatx4 acc[4][2];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < in_of(l) / 32; ++ks) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          const bf16x8 af = *(const bf16x8*)(A + (16 * rb + (lane & 15)) * lda + 32 * ks + kq);
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma(af, l == 0 ? w0[cb] : wh[l - 1][cb][ks], acc[rb][cb]);
+        }
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const int col = 32 * wave + 16 * cb + (lane & 15);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * rb + 4 * (lane >> 4) + v;
+            O[r * LDH + col] = (__bf16)silu_rounded(acc[rb][cb][v] + bias[l][cb]);
+          }
+        }
+      __syncthreads();
+    }
+    // output layer, as output_row computes it (4 lanes per row, 32 terms each
+    // in order, then two butterfly steps), with the weights from LDS
+    {
+      const int r = tid >> 2, part = tid & 3;
+      const __bf16* h4 = sm.act[(NL - 1) & 1] + r * LDH;
+      float acc = 0.f;
+      for (int i = part * 32; i < part * 32 + 32; ++i) acc += sm.w5[i] * (float)h4[i];
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (part == 0 && r0 + r < n) out[r0 + r] = acc + b5;
+    }
+    __syncthreads();  // the next tile's features and layers overwrite a0 and act
+  }
 }
 
 // Target transform t -> (t - shift) inv_scale, clamped to [-clip, clip] when clip > 0.
@@ -435,7 +504,7 @@ wob_status wob_mlp_create(int32_t dim, const float* fourier, const float* params
     if (!std::isfinite(fourier[i])) return WOB_E_ARG;
   for (int i = 0; i < NP; ++i)
     if (!std::isfinite(params[i])) return WOB_E_ARG;
-  // the workgroups keep every activation of their 64 rows in LDS (> 64 KiB)
+  // the backward pass keeps every activation of its 64 rows in LDS (> 64 KiB)
   if (hipFuncSetAttribute((const void*)mlp_forward_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, sizeof(FwdSmem)) != hipSuccess ||
       hipFuncSetAttribute((const void*)mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -514,8 +583,9 @@ wob_status wob_mlp_forward(wob_mlp h, const float* y, int64_t n, float* out, voi
   if (!h || n < 0 || (n > 0 && (!y || !out))) return WOB_E_ARG;
   if (n == 0) return WOB_OK;
   const int64_t tiles = (n + TR - 1) / TR;
-  if (tiles > 0x7fffffff) return WOB_E_ARG;
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)tiles), dim3(NT), sizeof(FwdSmem),
+  // persistent workgroups (their weight fragments loaded once): up to four per CU
+  const int64_t grid = tiles < kFwdGrid ? tiles : kFwdGrid;
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)grid), dim3(NT), sizeof(FwdSmem),
                      (hipStream_t)stream, h->net, y, n, out);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;
 }

@@ -84,6 +84,28 @@ def test_forward_matches_bf16_oracle(W):
     net.close()
 
 
+def test_forward_many_tiles_per_workgroup(W):
+    """200,003 rows: 3,126 tiles of 64 over at most 1,024 persistent
+    workgroups, the last tile ragged.  Each row's output does not depend on
+    the batch it comes in (equal bits for the first 1,000 rows and the last
+    777 evaluated alone), and sampled rows are within the oracle's bound."""
+    params, B = rand_net(13)
+    params, B = f32(params), f32(B)
+    y = f32(np.random.default_rng(4).uniform(-1.5, 1.5, (200003, 3)))
+    net = W.MLP(3, B, params)
+    ty = torch.as_tensor(y, dtype=torch.float32, device="cuda")
+    out = net.forward(ty)
+    head = net.forward(ty[:1000].contiguous())
+    tail = net.forward(ty[-777:].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(out[:1000], head) and torch.equal(out[-777:], tail)
+    idx = np.sort(np.random.default_rng(5).choice(len(y), 500, replace=False))
+    res = oracle.mlp_forward_bound(params, B, y[idx], MLP_ACC)
+    d = np.abs(out.cpu().double().numpy()[idx] - res["out"])
+    assert np.all(d <= res["bound"])
+    net.close()
+
+
 def test_gradient_matches_bf16_oracle(W):
     params, B = rand_net(12)
     params, B = f32(params), f32(B)
