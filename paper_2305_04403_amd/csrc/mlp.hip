@@ -407,13 +407,28 @@ __global__ void __launch_bounds__(NT) mlp_grad_kernel(Net net, const float* y, c
   }
 }
 
-// grad[p] = sum over tiles of part[t][p] (fixed order), loss = sum part_loss * scale.
+// The tiles' partial gradients are summed in slices of kSlice tiles (tiles
+// s kSlice .. s kSlice + kSlice - 1 in order, the sum written over the
+// slice's first tile), then the slice sums in order: a fixed order, so the
+// gradient is deterministic, with kSlice times more threads at work than one
+// sum per parameter.
+constexpr int kSlice = 32;
+__global__ void slice_grad_kernel(float* part, int n_tiles) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t0 = blockIdx.y * kSlice, t1 = t0 + kSlice < n_tiles ? t0 + kSlice : n_tiles;
+  if (p >= NP) return;
+  float acc = 0.f;
+  for (int t = t0; t < t1; ++t) acc += part[(int64_t)t * NP + p];
+  part[(int64_t)t0 * NP + p] = acc;
+}
+
+// grad[p] = sum over slices of the slice sums (fixed order), loss = sum part_loss * scale.
 __global__ void reduce_grad_kernel(const float* part, int n_tiles, float* grad, const float* part_loss,
                                    float* loss, float scale) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < NP) {
     float acc = 0.f;
-    for (int t = 0; t < n_tiles; ++t) acc += part[(int64_t)t * NP + p];
+    for (int t = 0; t < n_tiles; t += kSlice) acc += part[(int64_t)t * NP + p];
     grad[p] = acc;
   }
   if (p == 0 && loss) {
@@ -583,7 +598,7 @@ wob_status wob_mlp_forward(wob_mlp h, const float* y, int64_t n, float* out, voi
   if (!h || n < 0 || (n > 0 && (!y || !out))) return WOB_E_ARG;
   if (n == 0) return WOB_OK;
   const int64_t tiles = (n + TR - 1) / TR;
-  // persistent workgroups (their weight fragments loaded once): up to four per CU
+  // persistent workgroups, their weight fragments loaded once (two resident per CU)
   const int64_t grid = tiles < kFwdGrid ? tiles : kFwdGrid;
   hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)grid), dim3(NT), sizeof(FwdSmem),
                      (hipStream_t)stream, h->net, y, n, out);
@@ -606,6 +621,8 @@ wob_status wob_mlp_backward(wob_mlp h, const float* y, const float* target,
   const float scale = 1.f / (float)n;
   hipLaunchKernelGGL(mlp_grad_kernel, dim3(tiles), dim3(NT), sizeof(Smem), st, h->net, y, target, tm,
                      n, scale, h->part, h->part_loss, h->sbuf);
+  hipLaunchKernelGGL(slice_grad_kernel, dim3((NP + 255) / 256, (unsigned)((tiles + kSlice - 1) / kSlice)), dim3(256),
+                     0, st, h->part, (int)tiles);
   hipLaunchKernelGGL(reduce_grad_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, h->part, tiles,
                      grad, h->part_loss, loss, scale);
   return hipGetLastError() == hipSuccess ? WOB_OK : WOB_E_DEVICE;

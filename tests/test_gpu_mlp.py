@@ -106,6 +106,30 @@ def test_forward_many_tiles_per_workgroup(W):
     net.close()
 
 
+def test_gradient_over_several_reduction_slices(W):
+    """5,000 rows: 79 tiles, whose partial gradients are summed in slices of
+    32 tiles (the last ragged) and then across slices.  Against the oracle at
+    the bar of the single-slice test; two calls give equal bits."""
+    params, B = rand_net(14)
+    params, B = f32(params), f32(B)
+    rng = np.random.default_rng(6)
+    y = f32(rng.uniform(-1.5, 1.5, (5000, 3)))
+    t = f32(rng.standard_normal(5000))
+    net = W.MLP(3, B, params, max_batch=5000)
+    ty = torch.as_tensor(y, dtype=torch.float32, device="cuda")
+    tt = torch.as_tensor(t, dtype=torch.float32, device="cuda")
+    loss, grad = net.backward(ty, tt)
+    loss2, grad2 = net.backward(ty, tt)
+    torch.cuda.synchronize()
+    assert torch.equal(grad, grad2) and torch.equal(loss, loss2)
+    lo, go = oracle.mlp_loss_grad(params, B, y, t, bf16=True)
+    assert loss.item() == pytest.approx(lo, rel=1e-5)
+    err = np.linalg.norm(grad.cpu().double().numpy() - go) / np.linalg.norm(go)
+    print(f"gradient normwise relative error {err:.2e}")
+    assert err <= 1e-3
+    net.close()
+
+
 def test_gradient_matches_bf16_oracle(W):
     params, B = rand_net(12)
     params, B = f32(params), f32(B)
