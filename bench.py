@@ -443,14 +443,20 @@ def cv_leg(torch, wob, I, n_seeds=10):
     ris16 = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=16)
     ris32 = dataclasses.replace(bc, sampling=wob.SAMPLE_RIS, candidates=32)
 
-    def cost(b):
-        return slope(lambda n: wob.solve_cv(scene, pts, b, n, M, lcv.g, seed=2, point_prim=pp, g0=lcv.g0))
+    # cost per path and fixed cost of each corrected walk with its own tables
+    # (the add-back skips the triangles with g0 = 0: all of them for g0 = 0)
+    costs = {}
 
-    costs = {id(bc): cost(bc), id(ris16): cost(ris16), id(ris32): cost(ris32)}
+    def cost(b, g, g0):
+        key = (id(b), g is zero)
+        if key not in costs:
+            costs[key] = slope(lambda n: wob.solve_cv(scene, pts, b, n, M, g, seed=2, point_prim=pp, g0=g0))
+        return costs[key]
+
     variants = {"plain": plain}
 
     def run_cv(name, g, g0, fixed_s, seed0, b=bc):
-        per_path, base = costs[id(b)]
+        per_path, base = cost(b, g, g0)
         n = int(max(8, (t_plain - fixed_s - base) / per_path // 8 * 8))  # lanes take paths one by one: any N
         runs, times = timed(lambda sd: wob.solve_cv(scene, pts, b, n, M, g, seed=sd + 100 * seed0,
                                                     point_prim=pp, g0=g0))
@@ -517,7 +523,8 @@ def cv_leg(torch, wob, I, n_seeds=10):
     out["mlp_forward"] = {"points": 1 << 20, "ms": 1e3 * t_mlp, "TFLOP/s": mlp_tflops, "peak_bf16_TFLOP/s": 2500.0,
                           "frac": mlp_tflops / 2500.0}
     out["addback_s"] = t_add
-    out["corrected_path_cost_vs_plain"] = costs[id(bc)][0] / (t_plain / N)
+    out["corrected_path_cost_vs_plain"] = costs[(id(bc), False)][0] / (t_plain / N)
+    out["fixed_cost_s"] = {"learned_tables": costs[(id(bc), False)][1], "zero_tables": costs[(id(bc), True)][1]}
     out["rmse_ratio_equal_time"] = out["learned"]["rmse_ratio"]
     out["rmse_ratio_equal_time_95"] = out["learned"]["rmse_ratio_95"]
     out["median_err_ratio_equal_time"] = out["learned"]["median_err_ratio"]

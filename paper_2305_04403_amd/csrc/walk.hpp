@@ -1188,12 +1188,14 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs<R, D> a) {
 //   reflected into the triangle when u0 + u1 > 1, y_T = v0 + u0 e1 + u1 e2.
 // Every workgroup streams the triangles through LDS in tiles of 256; a far pair
 // costs one distance test and one reciprocal square root.  Each lane keeps 4
-// points in registers.
+// points in registers.  A tile whose triangles all have g_T = 0 adds exactly
+// zero: its pairs are skipped (the whole sum, for g = 0).
 template <typename R>
 __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, const R* __restrict__ g_by_id,
                                                          const R* __restrict__ points, int64_t n,
                                                          uint32_t seed, R* out, int accumulate) {
   // per triangle: [c (3), (4 r)^2] [y_T (3), g A / (4 pi)] [v (9), t (9), u (9), n (3), g, pad]
+  // (the pad words of the first four records carry the wavefronts' votes)
   constexpr int TILE = 256, PPT = 4, NF = 40;
   __shared__ __align__(16) R tile[TILE * NF];
   const int tid = threadIdx.x;
@@ -1212,6 +1214,7 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
     __syncthreads();
     const int32_t j = t0 + tid;
     R* T = tile + tid * NF;
+    bool nonzero = false;
     if (j < s.n_prims) {
       const PrimGeo<R> g = load_prim<R, 3>(s, j);
       R nn[3];
@@ -1241,6 +1244,7 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
       R cr[3];
       cross3(g.e1, g.e2, cr);
       const R gT = g_by_id[g.id];
+      nonzero = gT != (R)0;
       const uint32_t h = hash32((uint32_t)g.id + 0x9e3779b9u * (seed + 1u));
       R a = unit<R>(hash32(h ^ 0x68e31da4u)), b = unit<R>(hash32(h ^ 0xb5297a4du));
       if (a + b > (R)1) {
@@ -1257,9 +1261,14 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
       T[36] = nn[1];
       T[37] = nn[2];
       T[38] = gT;
-      T[39] = (R)0;
     }
+    // whether any g_T of the tile is non-zero: each wavefront's vote in the
+    // pad word of one of the first four records (no LDS beyond the tile's
+    // 40 KiB, which lets four workgroups share a CU)
+    if ((tid & 63) == 0) tile[(tid >> 6) * NF + 39] = __ballot(nonzero) != 0 ? (R)1 : (R)0;
     __syncthreads();
+    if (tile[39] == (R)0 && tile[NF + 39] == (R)0 && tile[2 * NF + 39] == (R)0 && tile[3 * NF + 39] == (R)0)
+      continue;  // the same decision in every lane
     const int cnt = s.n_prims - t0 < TILE ? s.n_prims - t0 : TILE;
     for (int q = 0; q < cnt; ++q) {
       const R* P = tile + q * NF;
