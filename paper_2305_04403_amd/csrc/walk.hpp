@@ -1265,7 +1265,8 @@ __global__ void __launch_bounds__(256) cv_addback_kernel(SceneView<R, 3> s, cons
     // whether any g_T of the tile is non-zero: each wavefront's vote in the
     // pad word of one of the first four records (no LDS beyond the tile's
     // 40 KiB, which lets four workgroups share a CU)
-    if ((tid & 63) == 0) tile[(tid >> 6) * NF + 39] = __ballot(nonzero) != 0 ? (R)1 : (R)0;
+    const bool wave_nonzero = __ballot(nonzero) != 0;  // every lane of the wavefront votes
+    if ((tid & 63) == 0) tile[(tid >> 6) * NF + 39] = wave_nonzero ? (R)1 : (R)0;
     __syncthreads();
     if (tile[39] == (R)0 && tile[NF + 39] == (R)0 && tile[2 * NF + 39] == (R)0 && tile[3 * NF + 39] == (R)0)
       continue;  // the same decision in every lane

@@ -55,6 +55,28 @@ def test_addback_matches_oracle(W, tori):
     scene.close()
 
 
+def test_addback_zero_and_sparse_tables(W, tori):
+    """The add-back skips the tiles of 256 triangles whose g values are all
+    zero: a zero table gives exact zeros, and a table with three non-zero
+    triangles (6,552 triangles in 26 tiles: at least 23 tiles skipped) matches
+    the oracle at the dense table's bar."""
+    scene = W.Scene(tori.mesh, W.F32)
+    pts = dev(tori.points)
+    zero = W.cv_addback(scene, dev(np.zeros(tori.mesh.n_prims, np.float32)), pts, seed=9)
+    g = np.zeros(tori.mesh.n_prims, np.float32)
+    g[np.random.default_rng(3).choice(tori.mesh.n_prims, 3, replace=False)] = (1.5, -0.75, 2.0)
+    out = W.cv_addback(scene, dev(g), pts, seed=9)
+    torch.cuda.synchronize()
+    assert bool((zero == 0).all())
+    om = oracle.OracleMesh(tori.mesh)
+    ref = oracle.cv_addback(om, g, tori.points, seed=9, randomized=True)
+    scale = oracle.cv_addback(om, np.abs(g), tori.points)
+    err = np.abs(out.cpu().double().numpy() - ref) / scale
+    print(f"sparse table: max error / sum |g| potential {err.max():.2e}")
+    assert err.max() < 2e-5
+    scene.close()
+
+
 @pytest.mark.parametrize("separate_g0,sampling", [(False, 0), (True, 0), (True, 1)])
 def test_trace_cv_matches_oracle(W, tori, separate_g0, sampling):
     """Per-path corrected values against the oracle; with RIS (sampling 1, 16
